@@ -1,0 +1,148 @@
+// Device-side access to fields in the library's internal (site-fastest) layout.
+//
+//   spinor FP64 : [12][V] double2       component k = 3*spin + colour
+//   spinor FP32 : [6][V]  float4        chunk c holds components 2c and 2c+1
+//   links       : [4][9][V] of double2 / float2 / __half2, element 3*a + b of U_nu(x)
+//
+// Consecutive lanes read consecutive sites of the same component, so every
+// wavefront-wide load is one contiguous 512 B .. 1 KiB segment.
+#pragma once
+
+#include "sgn_internal.h"
+
+namespace sgn {
+
+template <typename R> struct SpinorStore;
+template <> struct SpinorStore<double> { using type = double2; static constexpr int chunks = 12; };
+template <> struct SpinorStore<float> { using type = float4; static constexpr int chunks = 6; };
+
+// Load/store with a wavefront-uniform base (kept in SGPRs) plus a 32-bit
+// per-lane byte offset: lets the compiler use the SGPR-base addressing mode
+// instead of one 64-bit VGPR address per component (which costs ~2 VGPRs per
+// load in flight and made the stencil spill).
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *__restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_off(T *__restrict__ base, uint32_t byte_off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
+__device__ __forceinline__ void load_spinor(const double2 *__restrict__ p, int V, int s, cpx<double> v[12])
+{
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        double2 t = ld_off(p + (size_t)c * V, off);
+        v[c] = {t.x, t.y};
+    }
+}
+
+__device__ __forceinline__ void load_spinor(const float4 *__restrict__ p, int V, int s, cpx<float> v[12])
+{
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        float4 t = ld_off(p + (size_t)c * V, off);
+        v[2 * c] = {t.x, t.y};
+        v[2 * c + 1] = {t.z, t.w};
+    }
+}
+
+__device__ __forceinline__ void store_spinor(double2 *__restrict__ p, int V, int s, const cpx<double> v[12])
+{
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st_off(p + (size_t)c * V, off, make_double2(v[c].r, v[c].i));
+}
+
+__device__ __forceinline__ void store_spinor(float4 *__restrict__ p, int V, int s, const cpx<float> v[12])
+{
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        st_off(p + (size_t)c * V, off, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i));
+}
+
+template <typename R>
+__device__ __forceinline__ void load_link(const double2 *__restrict__ U, int V, int nu, int s, cpx<R> u[9])
+{
+    const double2 *b = U + (size_t)nu * 9 * V;
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        double2 t = ld_off(b + (size_t)e * V, off);
+        u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_link(const float2 *__restrict__ U, int V, int nu, int s, cpx<R> u[9])
+{
+    const float2 *b = U + (size_t)nu * 9 * V;
+    const uint32_t off = (uint32_t)s * 8u;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        float2 t = ld_off(b + (size_t)e * V, off);
+        u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_link(const __half2 *__restrict__ U, int V, int nu, int s, cpx<R> u[9])
+{
+    const __half2 *b = U + (size_t)nu * 9 * V;
+    const uint32_t off = (uint32_t)s * 4u;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        float2 t = __half22float2(ld_off(b + (size_t)e * V, off));
+        u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
+    }
+}
+
+// XCD-aware block order: consecutive hardware block ids are dealt round-robin
+// to the 8 XCDs, so hardware block i is mapped to a logical block such that
+// each XCD walks one contiguous slab of the lattice (t-neighbours then mostly
+// hit its own L2).  Bijective on [0, nblk).
+__device__ __forceinline__ int xcd_block(int i, int nblk)
+{
+    constexpr int kXcd = 8;
+    int per = nblk / kXcd, rem = nblk % kXcd;
+    int k = i % kXcd, j = i / kXcd;
+    return k * per + (k < rem ? k : rem) + j;
+}
+
+// FP64 sum over a 256-thread block (4 wavefronts of 64); result valid in thread 0.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [4*NV] */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += lds[w * NV + k];
+            v[k] = s;
+        }
+    }
+}
+
+}  // namespace sgn

@@ -1,0 +1,271 @@
+// Context, lattice objects, layout conversion and status strings.
+#include "field_io.h"
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+namespace sgn {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void *Context::ensure_partials(size_t bytes)
+{
+    if (bytes > partials_bytes) {
+        if (partials) SGN_HIP(hipFree(partials));
+        partials = nullptr;
+        partials_bytes = 0;
+        if (hipMalloc(&partials, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "partials buffer"};
+        partials_bytes = bytes;
+    }
+    return partials;
+}
+
+void *Context::ensure_scalars(size_t bytes)
+{
+    if (bytes > scalars_bytes) {
+        if (scalars) SGN_HIP(hipFree(scalars));
+        scalars = nullptr;
+        scalars_bytes = 0;
+        if (hipMalloc(&scalars, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "scalar buffer"};
+        scalars_bytes = bytes;
+    }
+    return scalars;
+}
+
+void Lattice::ensure_stage(size_t bytes)
+{
+    if (bytes <= stage_bytes) return;
+    if (stage_in) SGN_HIP(hipFree(stage_in));
+    if (stage_out) SGN_HIP(hipFree(stage_out));
+    stage_in = stage_out = nullptr;
+    stage_bytes = 0;
+    if (hipMalloc(&stage_in, bytes) != hipSuccess || hipMalloc(&stage_out, bytes) != hipSuccess)
+        throw Failure{SGN_ERR_NOMEM, "staging buffers"};
+    stage_bytes = bytes;
+}
+
+namespace {
+
+// canonical [site][nu][3][3] complex128  ->  [nu][9][V] of LT
+template <typename LT> __device__ inline LT to_link(double2 v);
+template <> __device__ inline double2 to_link<double2>(double2 v) { return v; }
+template <> __device__ inline float2 to_link<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ inline __half2 to_link<__half2>(double2 v)
+{
+    return __floats2half2_rn((float)v.x, (float)v.y);
+}
+
+template <typename LT>
+__global__ void pack_links_kernel(const double2 *__restrict__ canon, LT *__restrict__ out, int V)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * V) return;
+    const int s = t / 4, nu = t % 4;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) out[((size_t)nu * 9 + e) * V + s] = to_link<LT>(canon[(size_t)t * 9 + e]);
+}
+
+__global__ void pack64(const double2 *__restrict__ c, double2 *__restrict__ o, int V)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[(size_t)k * V + s] = c[(size_t)s * 12 + k];
+}
+
+__global__ void unpack64(const double2 *__restrict__ o, double2 *__restrict__ c, int V)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[(size_t)s * 12 + k] = o[(size_t)k * V + s];
+}
+
+__global__ void pack32(const float2 *__restrict__ c, float4 *__restrict__ o, int V)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float2 a = c[(size_t)s * 12 + 2 * k], b = c[(size_t)s * 12 + 2 * k + 1];
+        o[(size_t)k * V + s] = make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
+__global__ void unpack32(const float4 *__restrict__ o, float2 *__restrict__ c, int V)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float4 t = o[(size_t)k * V + s];
+        c[(size_t)s * 12 + 2 * k] = make_float2(t.x, t.y);
+        c[(size_t)s * 12 + 2 * k + 1] = make_float2(t.z, t.w);
+    }
+}
+
+}  // namespace
+
+void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s)
+{
+    const int V = (int)lat.V;
+    dim3 g((V + 255) / 256), b(256);
+    if (p == SGN_PREC_F64)
+        hipLaunchKernelGGL(pack64, g, b, 0, s, (const double2 *)canon, (double2 *)internal, V);
+    else
+        hipLaunchKernelGGL(pack32, g, b, 0, s, (const float2 *)canon, (float4 *)internal, V);
+    SGN_HIP(hipGetLastError());
+}
+
+void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_prec p, hipStream_t s)
+{
+    const int V = (int)lat.V;
+    dim3 g((V + 255) / 256), b(256);
+    if (p == SGN_PREC_F64)
+        hipLaunchKernelGGL(unpack64, g, b, 0, s, (const double2 *)internal, (double2 *)canon, V);
+    else
+        hipLaunchKernelGGL(unpack32, g, b, 0, s, (const float4 *)internal, (float2 *)canon, V);
+    SGN_HIP(hipGetLastError());
+}
+
+}  // namespace sgn
+
+using namespace sgn;
+
+extern "C" const char *sgn_status_string(sgn_status s)
+{
+    switch (s) {
+    case SGN_OK: return "ok";
+    case SGN_ERR_INVALID: return "invalid argument";
+    case SGN_ERR_HIP: return "HIP runtime error";
+    case SGN_ERR_NOMEM: return "out of device memory";
+    case SGN_ERR_BREAKDOWN: return "Krylov breakdown";
+    case SGN_ERR_NOT_CONVERGED: return "not converged";
+    case SGN_ERR_IMAG_AXIS: return "eigenvalue on the imaginary axis";
+    case SGN_ERR_UNSUPPORTED: return "unsupported option";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *sgn_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" sgn_status sgn_init(sgn_handle *h, int device)
+{
+    return guard([&] {
+        SGN_REQUIRE(h != nullptr, "sgn_init: null handle pointer");
+        int n = 0;
+        SGN_HIP(hipGetDeviceCount(&n));
+        SGN_REQUIRE(device >= 0 && device < n, "sgn_init: no such device");
+        SGN_HIP(hipSetDevice(device));
+        auto *c = new Context();
+        c->device = device;
+        hipDeviceProp_t prop;
+        SGN_HIP(hipGetDeviceProperties(&prop, device));
+        c->num_cu = prop.multiProcessorCount;
+        *h = reinterpret_cast<sgn_handle>(c);
+    });
+}
+
+extern "C" sgn_status sgn_finalize(sgn_handle h)
+{
+    return guard([&] {
+        if (!h) return;
+        auto *c = reinterpret_cast<Context *>(h);
+        SGN_HIP(hipSetDevice(c->device));
+        if (c->partials) SGN_HIP(hipFree(c->partials));
+        if (c->scalars) SGN_HIP(hipFree(c->scalars));
+        delete c;
+    });
+}
+
+extern "C" sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d, const void *links,
+                                         unsigned prec_mask, void *stream, sgn_lattice *out)
+{
+    Lattice *lat = nullptr;
+    sgn_status st = guard([&] {
+        SGN_REQUIRE(h && d && links && out, "sgn_lattice_create: null argument");
+        auto *ctx = reinterpret_cast<Context *>(h);
+        int64_t V = 1;
+        for (int i = 0; i < 4; ++i) {
+            SGN_REQUIRE(d->dims[i] >= 2, "sgn_lattice_create: every extent must be >= 2");
+            SGN_REQUIRE(d->bc[i] == 1 || d->bc[i] == -1, "sgn_lattice_create: bc must be +1 or -1");
+            V *= d->dims[i];
+        }
+        SGN_REQUIRE(V <= (int64_t)(1 << 26), "sgn_lattice_create: volume above 2^26 sites");
+        SGN_REQUIRE(std::isfinite(d->kappa), "sgn_lattice_create: kappa not finite");
+        SGN_HIP(hipSetDevice(ctx->device));
+        lat = new Lattice();
+        lat->ctx = ctx;
+        for (int i = 0; i < 4; ++i) {
+            lat->L[i] = d->dims[i];
+            lat->bc[i] = d->bc[i];
+        }
+        lat->kappa = d->kappa;
+        lat->V = V;
+        const unsigned mask = prec_mask ? prec_mask : 7u;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int nthr = (int)(4 * V);
+        dim3 g((nthr + 255) / 256), b(256);
+        if (mask & (1u << SGN_PREC_F64)) {
+            if (hipMalloc(&lat->links64, (size_t)V * 36 * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links64"};
+            hipLaunchKernelGGL(pack_links_kernel<double2>, g, b, 0, s, (const double2 *)links,
+                               (double2 *)lat->links64, (int)V);
+        }
+        if (mask & (1u << SGN_PREC_F32)) {
+            if (hipMalloc(&lat->links32, (size_t)V * 36 * 8) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links32"};
+            hipLaunchKernelGGL(pack_links_kernel<float2>, g, b, 0, s, (const double2 *)links,
+                               (float2 *)lat->links32, (int)V);
+        }
+        if (mask & (1u << SGN_PREC_F32_H16)) {
+            if (hipMalloc(&lat->links16, (size_t)V * 36 * 4) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links16"};
+            hipLaunchKernelGGL(pack_links_kernel<__half2>, g, b, 0, s, (const double2 *)links,
+                               (__half2 *)lat->links16, (int)V);
+        }
+        SGN_HIP(hipGetLastError());
+        SGN_HIP(hipStreamSynchronize(s));
+        *out = reinterpret_cast<sgn_lattice>(lat);
+    });
+    if (st != SGN_OK && lat) sgn_lattice_destroy(reinterpret_cast<sgn_lattice>(lat));
+    return st;
+}
+
+extern "C" sgn_status sgn_lattice_destroy(sgn_lattice l)
+{
+    return guard([&] {
+        if (!l) return;
+        Lattice *lat = as_lattice(l);
+        SGN_HIP(hipSetDevice(lat->ctx->device));
+        for (void *p : {lat->links64, lat->links32, lat->links16, lat->stage_in, lat->stage_out})
+            if (p) SGN_HIP(hipFree(p));
+        delete lat;
+    });
+}
+
+extern "C" int64_t sgn_lattice_volume(sgn_lattice l) { return l ? as_lattice(l)->V : 0; }
+
+extern "C" size_t sgn_spinor_bytes(sgn_lattice l, sgn_prec p) { return l ? spinor_bytes(as_lattice(l)->V, p) : 0; }
+
+extern "C" sgn_status sgn_spinor_pack(sgn_lattice l, const void *canon, void *internal, sgn_prec p, void *stream)
+{
+    return guard([&] {
+        SGN_REQUIRE(l && canon && internal, "sgn_spinor_pack: null argument");
+        Lattice &lat = *as_lattice(l);
+        SGN_HIP(hipSetDevice(lat.ctx->device));
+        pack_spinor(lat, canon, internal, p, static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" sgn_status sgn_spinor_unpack(sgn_lattice l, const void *internal, void *canon, sgn_prec p, void *stream)
+{
+    return guard([&] {
+        SGN_REQUIRE(l && canon && internal, "sgn_spinor_unpack: null argument");
+        Lattice &lat = *as_lattice(l);
+        SGN_HIP(hipSetDevice(lat.ctx->device));
+        unpack_spinor(lat, internal, canon, p, static_cast<hipStream_t>(stream));
+    });
+}

@@ -1,0 +1,148 @@
+// Internal declarations of libsgn (gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/sgn.h"
+
+namespace sgn {
+
+// ----------------------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+
+struct Failure {
+    sgn_status st;
+    std::string msg;
+};
+
+#define SGN_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw ::sgn::Failure{SGN_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define SGN_REQUIRE(cond, msg)                                                              \
+    do {                                                                                    \
+        if (!(cond)) throw ::sgn::Failure{SGN_ERR_INVALID, (msg)};                          \
+    } while (0)
+
+// Run `body`, translating Failure / std::exception into a status code.
+template <typename F>
+sgn_status guard(F &&body)
+{
+    try {
+        body();
+        return SGN_OK;
+    } catch (const Failure &f) {
+        set_error(f.msg);
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SGN_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return SGN_ERR_INVALID;
+    }
+}
+
+// ----------------------------------------------------------------------------- complex
+template <typename R>
+struct cpx {
+    R r, i;
+};
+
+template <typename R> __host__ __device__ inline cpx<R> mk(R r, R i) { return cpx<R>{r, i}; }
+template <typename R> __host__ __device__ inline cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename R> __host__ __device__ inline cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename R> __host__ __device__ inline cpx<R> operator-(cpx<R> a) { return {-a.r, -a.i}; }
+template <typename R> __host__ __device__ inline cpx<R> operator*(cpx<R> a, cpx<R> b)
+{
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename R> __host__ __device__ inline cpx<R> operator*(R s, cpx<R> a) { return {s * a.r, s * a.i}; }
+template <typename R> __host__ __device__ inline cpx<R> conj(cpx<R> a) { return {a.r, -a.i}; }
+// conj(a) * b
+template <typename R> __host__ __device__ inline cpx<R> cmulc(cpx<R> a, cpx<R> b)
+{
+    return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+template <typename R> __host__ __device__ inline cpx<R> times_i(cpx<R> a) { return {-a.i, a.r}; }
+template <typename R> __host__ __device__ inline cpx<R> times_mi(cpx<R> a) { return {a.i, -a.r}; }
+template <typename R> __host__ __device__ inline R norm2(cpx<R> a) { return a.r * a.r + a.i * a.i; }
+template <typename A, typename B> __host__ __device__ inline cpx<A> cast(cpx<B> b)
+{
+    return {static_cast<A>(b.r), static_cast<A>(b.i)};
+}
+
+using z64 = cpx<double>;
+
+// ----------------------------------------------------------------------------- objects
+struct Context {
+    int device = 0;
+    int num_cu = 0;
+    // scratch device buffers owned by the context, grown on demand
+    void *partials = nullptr;
+    size_t partials_bytes = 0;
+    void *scalars = nullptr;  // device scalars of the solvers
+    size_t scalars_bytes = 0;
+    void *ensure_partials(size_t bytes);
+    void *ensure_scalars(size_t bytes);
+};
+
+struct Lattice {
+    Context *ctx = nullptr;
+    int L[4] = {0, 0, 0, 0};
+    int bc[4] = {1, 1, 1, -1};
+    double kappa = 0.0;
+    int64_t V = 0;
+    void *links64 = nullptr;  // [4][9][V] double2
+    void *links32 = nullptr;  // [4][9][V] float2
+    void *links16 = nullptr;  // [4][9][V] __half2
+    // canonical <-> internal staging for wilson_apply in canonical layout
+    void *stage_in = nullptr, *stage_out = nullptr;
+    size_t stage_bytes = 0;
+    void ensure_stage(size_t bytes);
+};
+
+inline size_t spinor_bytes(int64_t V, sgn_prec p) { return (size_t)V * 12 * (p == SGN_PREC_F64 ? 16 : 8); }
+
+// ----------------------------------------------------------------------------- launches
+// Operator selection for one stencil application.
+struct OpSpec {
+    double mu = 0.0;     // chemical potential actually used (the adjoint passes -mu)
+    bool g5_out = true;  // multiply the result by gamma5
+    bool g5_in = false;  // multiply the input by gamma5 first
+};
+
+// Epilogue of a stencil application:  out = a * Op(in) + b * z   (z optional),
+// optionally accumulating per-block partial sums of  conj(w) . out  (FP64).
+struct Epilogue {
+    double a = 1.0;
+    z64 b = {0.0, 0.0};
+    const z64 *b_dev = nullptr;   // if set, b is read from device memory (times b)
+    const void *z = nullptr;      // same precision/layout as out
+    const void *w = nullptr;      // dot partner, same precision/layout as out
+    z64 *partials = nullptr;      // one z64 per block when w != nullptr
+    const z64 *in_scale = nullptr;  // if set: Op(in) is multiplied by *in_scale (device)
+};
+
+// Launch the stencil on internal-layout fields.  Returns the number of blocks
+// (= number of partials written when ep.w is set).
+int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,
+                  const Epilogue &ep, hipStream_t s);
+int dslash_blocks(const Lattice &lat);
+
+void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s);
+void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_prec p, hipStream_t s);
+
+inline Lattice *as_lattice(sgn_lattice l) { return reinterpret_cast<Lattice *>(l); }
+
+}  // namespace sgn

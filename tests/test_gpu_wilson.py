@@ -1,0 +1,128 @@
+"""Parity of the HIP Wilson stencil (wilson_apply / wilson_apply_dag) with the oracle.
+
+Tolerances (relative 2-norm): FP64 1e-13, FP32 1e-6; FP16 links are reported
+and bounded by 5e-3 (half precision has a 2^-11 relative step).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import WilsonRef
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_0910_1048_amd as sgn  # noqa: E402
+from gpu_util import dev, host, lattice  # noqa: E402
+
+TOL = {sgn.F64: 1e-13, sgn.F32: 1e-6, sgn.F32_H16: 5e-3}
+CDT = {sgn.F64: np.complex128, sgn.F32: np.complex64, sgn.F32_H16: np.complex64}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _run(lat, mu, b, prec, dag=False, flags=0):
+    x = dev(b.astype(CDT[prec]))
+    y = torch.empty_like(x)
+    (sgn.wilson_apply_dag if dag else sgn.wilson_apply)(lat, mu, x, y, prec, flags)
+    return host(y).astype(np.complex128)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 8, 10), (3, 5, 2, 7), (8, 8, 8, 16)])
+@pytest.mark.parametrize("mu", [0.0, 0.3, -0.2])
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+def test_wilson_apply_matches_oracle(dims, mu, prec):
+    print(f"case dims={dims} mu={mu} prec={prec}", flush=True)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 1)
+    ref = WilsonRef(U, dims, 0.2)
+    lat = lattice(U, dims)
+    err = _rel(_run(lat, mu, b, prec), ref.apply(b, mu))
+    errd = _rel(_run(lat, mu, b, prec, dag=True), ref.apply_adj(b, mu))
+    print(f"  H err {err:.2e}  H^dag err {errd:.2e}", flush=True)
+    assert err < TOL[prec] and errd < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32])
+def test_no_gamma5_flag(prec):
+    dims = (4, 4, 6, 4)
+    U = synth.gauge_field(dims, 0.5, 2)
+    b = synth.gaussian_source(dims, 3)
+    ref = WilsonRef(U, dims, 0.2)
+    lat = lattice(U, dims)
+    assert _rel(_run(lat, 0.3, b, prec, flags=sgn.NO_GAMMA5), ref.apply(b, 0.3, g5=False)) < TOL[prec]
+    assert _rel(_run(lat, 0.3, b, prec, dag=True, flags=sgn.NO_GAMMA5), ref.apply_adj(b, 0.3, g5=False)) < TOL[prec]
+
+
+def test_boundary_conditions_and_kappa():
+    dims = (4, 4, 4, 6)
+    U = synth.gauge_field(dims, 0.5, 4)
+    b = synth.gaussian_source(dims, 5)
+    for bc, kappa in (((1, 1, 1, 1), 0.15), ((-1, 1, -1, -1), 0.25)):
+        ref = WilsonRef(U, dims, kappa, bc=bc)
+        lat = lattice(U, dims, kappa, bc)
+        assert _rel(_run(lat, 0.3, b, sgn.F64), ref.apply(b, 0.3)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+def test_internal_layout_roundtrip(prec):
+    dims = (4, 6, 4, 8)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).astype(CDT[prec])
+    lat = lattice(U, dims)
+    x = dev(b)
+    nbytes = lat.spinor_bytes(prec)
+    xi = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    yi = torch.empty_like(xi)
+    y = torch.empty_like(x)
+    back = torch.empty_like(x)
+    sgn.sgn_spinor_pack(lat, x, xi, prec)
+    sgn.sgn_spinor_unpack(lat, xi, back, prec)
+    assert np.array_equal(host(back), b)
+    sgn.wilson_apply(lat, 0.3, xi, yi, prec, sgn.INTERNAL_LAYOUT)
+    sgn.sgn_spinor_unpack(lat, yi, y, prec)
+    sgn.wilson_apply(lat, 0.3, x, back, prec)
+    assert np.array_equal(host(y), host(back))
+
+
+def test_deterministic_rerun():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0)
+    lat = lattice(U, dims)
+    a1 = _run(lat, 0.2, b, sgn.F32)
+    a2 = _run(lat, 0.2, b, sgn.F32)
+    assert np.array_equal(a1, a2)
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+def test_full_size_sampled_sites(prec):
+    """24^3 x 48 (the largest configuration): GPU on the whole lattice, oracle at
+    sampled sites including every kind of boundary site."""
+    dims = (24, 24, 24, 48)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0)
+    lat = lattice(U, dims)
+    got = _run(lat, 0.2, b, prec).reshape(-1, 4, 3)
+    rng = np.random.default_rng(7)
+    V = 24 ** 3 * 48
+    corners = [0, 23, 24 * 23, 24 ** 2 * 23, 24 ** 3 * 47, V - 1, 24 ** 3 * 47 + 5]
+    sites = np.unique(np.concatenate([rng.integers(0, V, 3000), corners]))
+    want = WilsonRef(U, dims, 0.2).apply_sites(b, 0.2, sites)
+    err = _rel(got[sites], want)
+    print(f"24^3x48 prec={prec} sampled err {err:.2e}", flush=True)
+    assert err < TOL[prec]
+
+
+def test_invalid_arguments_are_rejected():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    lat = lattice(U, dims)
+    x = dev(synth.gaussian_source(dims, 0))
+    with pytest.raises(sgn.SgnError) as e:
+        sgn.wilson_apply(lat, 0.3, x, x, sgn.F64)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError):
+        sgn.wilson_apply(lat, float("nan"), x, torch.empty_like(x), sgn.F64)
