@@ -108,6 +108,117 @@ sgn_status wilson_apply(sgn_lattice lat, double mu, const void *in, void *out, s
 sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *in, void *out, sgn_prec p,
                             unsigned flags, void *stream);
 
+/* ------------------------------------------------------------------ deflation and statistics */
+/* LR deflation set (section "Deflation", oblique projector P = R L^H):
+ * m right eigenvectors R and left eigenvectors L of H_W(mu) for its m
+ * critical eigenvalues lambda, normalised so that L^H R = I_m.  L and R
+ * (device) hold m canonical complex128 vectors back to back (vector i at
+ * offset i*n); lambda (host) holds m complex128 values.  m = 0 or a NULL
+ * pointer to the struct means no deflation.  The caller owns all arrays.
+ * Used for x_P = R sign(Lambda) L^H b (Eq. exact_proj) and r = (I - P) b. */
+typedef struct {
+    int m;
+    const void *L;
+    const void *R;
+    const double *lambda;
+} sgn_deflation;
+
+#define SGN_MAX_POLES 128
+
+/* Per-call statistics (any pointer may be NULL). */
+typedef struct {
+    int iterations;          /* Krylov steps (Lanczos), Arnoldi steps (FOM), BiCG iterations */
+    int matvecs;             /* applications of H_W or H_W^H */
+    int restarts;            /* FOM restart cycles */
+    int reliable_updates;    /* FP64 true-residual recomputations (mixed precision) */
+    int refine_iterations;   /* iterations spent in the per-shift FP64 refinement */
+    int nshift;
+    double shift_residual[SGN_MAX_POLES]; /* final relative residual of each shifted system */
+    double residual;         /* largest final relative residual (rational methods) */
+    double min_abs_re;       /* smallest |Re| of the small matrix's eigenvalues (direct Lanczos) */
+    double krylov_ms;        /* time in the Krylov iteration (host clock, includes device waits) */
+    double small_ms;         /* time in the small dense sign / Hessenberg solves */
+    double total_ms;
+} sgn_stats;
+
+/* ------------------------------------------------------------------ direct two-sided Lanczos */
+typedef struct {
+    int k;              /* maximal Krylov dimension, fixed a priori (>= 1) */
+    sgn_prec prec;      /* SGN_PREC_F64: FP64 throughout.  SGN_PREC_F32 / _H16: the two stencils
+                           per step run in FP32 (FP16 links), the recurrence stays FP64 */
+    double tol;         /* > 0: stop early once the lift coefficients y = sign(T_j) e_1 change by
+                           less than tol (relative) between checks */
+    int check_every;    /* steps between such checks (used when tol > 0) */
+} sgn_lanczos_opts;
+
+/* Direct two-sided Lanczos-LR(m, k) (section "Direct application of the
+ * two-sided Lanczos approach", recurrences (2sided1)-(2sided2)):
+ *   x_P = R sign(Lambda) L^H b,  r = b - R L^H b,  shadow r~ = b - L R^H b,
+ *   v_1 = r/||r||, w_1 = r~ scaled to v_1^H w_1 = 1, k steps of two-sided
+ *   Lanczos with A = H_W(mu), A^H = H_W(-mu), T_k tridiagonal,
+ *   x = x_P + ||r|| V_k sign(T_k) e_1.
+ * b, x: device, canonical complex128.  The small sign is evaluated on the host
+ * in FP64 (complex Schur form); the call synchronises `stream`.
+ * Returns SGN_ERR_BREAKDOWN if |w^H v| < 1e-14 ||w|| ||v|| at some step,
+ * SGN_ERR_IMAG_AXIS if a deflated eigenvalue or an eigenvalue of T_k has
+ * |Re| <= 1e-12 of the norm. */
+sgn_status sign_lanczos_2sided(sgn_lattice lat, double mu, const void *b, void *x, const sgn_deflation *defl,
+                               const sgn_lanczos_opts *opts, sgn_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ rational approximation */
+/* sign(t) ~ g_s(c t) = c t sum_i omega_i / (c^2 t^2 - sigma_i)   (Eqs. (neuberger_mit_c), (pfe_s)):
+ * the shifted systems of the rational methods are (c^2 H_W^2 - sigma_i) x_i = c H_W r. */
+typedef struct {
+    int s;                          /* number of poles, 1 <= s <= SGN_MAX_POLES */
+    double c;                       /* scale c > 0 */
+    double alpha, beta;             /* spectral bounds the coefficients were built for (informational) */
+    double omega[SGN_MAX_POLES];    /* weights omega_i > 0 */
+    double sigma[SGN_MAX_POLES];    /* shifts sigma_i < 0 */
+} sgn_rational;
+
+/* Neuberger coefficients of Eq. (pfe_s) with the scale of the spectral-circle
+ * heuristic: circle through alpha and beta (0 < alpha < beta), m = (alpha+beta)/2,
+ * r = (beta-alpha)/2, c = ((m+r)(m-r))^{-1/2}  (section on the choice of the
+ * rational function and the numerical-results section).  Host only. */
+sgn_status sgn_rational_neuberger(int s, double alpha, double beta, sgn_rational *out);
+/* Smallest s satisfying Eq. (no_of_poles) for accuracy eps on the circles
+ * through alpha and beta (circle theorem).  Host only. */
+sgn_status sgn_poles_needed(double alpha, double beta, double eps, int *s);
+
+/* ------------------------------------------------------------------ multishift BiCG */
+typedef struct {
+    sgn_lattice lat;
+    double mu;
+    const void *b;              /* device, canonical complex128 */
+    void *x;                    /* device, canonical complex128: x_P + sum_i omega_i x_i */
+    const sgn_deflation *defl;  /* may be NULL */
+    void *const *x_shift;       /* NULL, or s device pointers receiving the x_i (canonical complex128) */
+} sgn_problem;
+
+typedef struct {
+    double tol;         /* every shifted system: ||c H r - (c^2 H^2 - sigma_i) x_i|| <= tol ||c H r|| */
+    int maxiter;        /* BiCG iterations */
+    sgn_prec prec;      /* SGN_PREC_F64: FP64 throughout.  SGN_PREC_F32: FP64 while the seed residual is
+                           above theta32, then FP32 vectors and stencil with FP64 reliable updates.
+                           SGN_PREC_F32_H16: as F32, and FP16 links once below theta16 */
+    double theta32;     /* relative seed residual at which FP32 takes over (default 1e-3 if <= 0) */
+    double theta16;     /* relative seed residual at which FP16 links take over (default 1e-6 if <= 0) */
+    double delta;       /* reliable update when the seed residual drops by this factor (default 0.1) */
+    int poll;           /* iterations between host checks of the device flags (0: automatic) */
+    int verify;         /* nonzero: recompute every shifted residual in FP64 at the end (stats) */
+} sgn_ms_opts;
+
+/* BiCG-LR(m) (section "Two-sided Lanczos with rational functions"): for each
+ * problem, x_P = R sign(Lambda) L^H b, r = (I - P) b, y = c H_W(mu) r, and the
+ * BiCG iterates of all shifted systems (c^2 H_W^2 - sigma_i) x_i = y from one
+ * two-sided Lanczos sequence (seed: the shift of smallest modulus; the others
+ * by the collinearity of their residuals), x = x_P + sum_i omega_i x_i.
+ * Problems may live on different lattices.  stats: nprob entries or NULL.
+ * Synchronises `stream`.  Returns SGN_ERR_NOT_CONVERGED (x holds the last
+ * iterate) if maxiter is reached, SGN_ERR_BREAKDOWN on a BiCG breakdown. */
+sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
+                            sgn_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

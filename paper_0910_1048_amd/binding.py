@@ -154,3 +154,124 @@ def wilson_apply(lat, mu, x, out, prec=F64, flags=0, stream=None):
 def wilson_apply_dag(lat, mu, x, out, prec=F64, flags=0, stream=None):
     check(lib.wilson_apply_dag(lat.h, float(mu), _ptr(x), _ptr(out), int(prec), C.c_uint(flags),
                                _stream(stream)), "wilson_apply_dag")
+
+
+# ----------------------------------------------------------------------------- solvers
+MAX_POLES = 128
+
+
+class _Deflation(C.Structure):
+    _fields_ = [("m", C.c_int), ("L", _vp), ("R", _vp), ("lam", C.POINTER(C.c_double))]
+
+
+class LanczosOpts(C.Structure):
+    _fields_ = [("k", C.c_int), ("prec", C.c_int), ("tol", C.c_double), ("check_every", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("matvecs", C.c_int), ("restarts", C.c_int),
+                ("reliable_updates", C.c_int), ("refine_iterations", C.c_int), ("nshift", C.c_int),
+                ("shift_residual", C.c_double * MAX_POLES), ("residual", C.c_double),
+                ("min_abs_re", C.c_double), ("krylov_ms", C.c_double), ("small_ms", C.c_double),
+                ("total_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "shift_residual"}
+        d["shift_residual"] = list(self.shift_residual[: self.nshift])
+        return d
+
+
+class Deflation:
+    """LR deflation set: L, R device tensors of shape (m, n) complex128 (canonical
+    vectors back to back), lam host complex eigenvalues (m,)."""
+
+    def __init__(self, L, R, lam):
+        import numpy as np
+        self.L, self.R = L, R
+        self._lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128)).view(np.float64)
+        self.m = int(np.asarray(lam).size)
+        self.struct = _Deflation(self.m, C.c_void_p(L.data_ptr()), C.c_void_p(R.data_ptr()),
+                                 self._lam.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def _defl_ptr(defl):
+    return None if defl is None else C.byref(defl.struct)
+
+
+lib.sign_lanczos_2sided.argtypes = [_vp, C.c_double, _vp, _vp, _vp, C.POINTER(LanczosOpts),
+                                    C.POINTER(Stats), _vp]
+
+
+def sign_lanczos_2sided(lat, mu, b, x, defl=None, k=200, prec=F64, tol=0.0, check_every=0, stream=None):
+    """x = sign(H_W(mu)) b by the direct two-sided Lanczos-LR method; returns the stats dict."""
+    o = LanczosOpts(int(k), int(prec), float(tol), int(check_every))
+    st = Stats()
+    check(lib.sign_lanczos_2sided(lat.h, float(mu), _ptr(b), _ptr(x), _defl_ptr(defl), C.byref(o), C.byref(st),
+                                  _stream(stream)), "sign_lanczos_2sided")
+    return st.as_dict()
+
+
+class Rational(C.Structure):
+    _fields_ = [("s", C.c_int), ("c", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
+                ("omega", C.c_double * MAX_POLES), ("sigma", C.c_double * MAX_POLES)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("lat", _vp), ("mu", C.c_double), ("b", _vp), ("x", _vp), ("defl", C.POINTER(_Deflation)),
+                ("x_shift", C.POINTER(_vp))]
+
+
+class MsOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("prec", C.c_int), ("theta32", C.c_double),
+                ("theta16", C.c_double), ("delta", C.c_double), ("poll", C.c_int), ("verify", C.c_int)]
+
+
+lib.sgn_rational_neuberger.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(Rational)]
+lib.sgn_poles_needed.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]
+lib.multishift_solve.argtypes = [C.POINTER(_Problem), C.c_int, C.POINTER(Rational), C.POINTER(MsOpts),
+                                 C.POINTER(Stats), _vp]
+
+
+def sgn_rational_neuberger(s, alpha, beta):
+    r = Rational()
+    check(lib.sgn_rational_neuberger(int(s), float(alpha), float(beta), C.byref(r)), "sgn_rational_neuberger")
+    return r
+
+
+def sgn_poles_needed(alpha, beta, eps):
+    s = C.c_int()
+    check(lib.sgn_poles_needed(float(alpha), float(beta), float(eps), C.byref(s)), "sgn_poles_needed")
+    return s.value
+
+
+class Problem:
+    """One right-hand side of multishift_solve.  x_shift: optional list of s device tensors."""
+
+    def __init__(self, lat, mu, b, x, defl=None, x_shift=None):
+        self.lat, self.mu, self.b, self.x, self.defl, self.x_shift = lat, mu, b, x, defl, x_shift
+
+
+def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
+                     delta=0.0, poll=0, verify=False, stream=None):
+    """Multishift BiCG-LR for every problem; returns one stats dict per problem."""
+    if isinstance(problems, Problem):
+        problems = [problems]
+    n = len(problems)
+    arr = (_Problem * n)()
+    keep = []
+    for i, p in enumerate(problems):
+        arr[i].lat = p.lat.h
+        arr[i].mu = float(p.mu)
+        arr[i].b = C.c_void_p(p.b.data_ptr())
+        arr[i].x = C.c_void_p(p.x.data_ptr())
+        if p.defl is not None:
+            arr[i].defl = C.pointer(p.defl.struct)
+        if p.x_shift is not None:
+            xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
+            keep.append(xs)
+            arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
+    o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll),
+               int(bool(verify)))
+    st = (Stats * max(n, 1))()
+    check(lib.multishift_solve(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_solve")
+    return [st[i].as_dict() for i in range(n)]

@@ -1,0 +1,393 @@
+// Direct two-sided Lanczos-LR(m, k): sign(H_W) b = x_P + ||r|| V_k sign(T_k) e_1
+// (section "Direct application of the two-sided Lanczos approach"; the
+// recurrences (2sided1), (2sided2) with A = H_W(mu), A^H = H_W(-mu)).
+//
+// Basis vectors are kept unnormalised: v_j = s_j vh_j, w_j = t_j wh_j, with the
+// real scale s_j and complex scale t_j in device memory.  No separate scaling
+// pass is needed: every kernel that reads a basis vector folds its scale into
+// its coefficients, and the lift folds s_j into the coefficients of V_k.
+//
+// Per step j (all coefficients FP64, computed on the device):
+//   stencil  u  = A vh_j,    partials of wh_j^H u       (epilogue-fused dot)
+//   finalize alpha_j = conj(t_j) s_j wh_j^H u          (= w_j^H A v_j)
+//   stencil  z  = A^H wh_j
+//   update   vh_{j+1} = s_j u - alpha_j s_j vh_j - h_{j-1,j} s_{j-1} vh_{j-1}
+//            wh_{j+1} = t_j z - conj(alpha_j) t_j wh_j - conj(h_{j,j-1}) t_{j-1} wh_{j-1}
+//            partials of ||vh||^2, wh^H vh, ||wh||^2
+//   finalize h_{j+1,j} = ||vh_{j+1}||, s_{j+1} = 1/h_{j+1,j},
+//            h_{j,j+1} = wh_{j+1}^H v_{j+1},  t_{j+1} = 1/conj(h_{j,j+1})
+#include <chrono>
+#include <complex>
+#include <vector>
+
+#include "field_io.h"
+#include "small_sign.h"
+#include "vec.h"
+
+namespace sgn {
+
+namespace {
+
+// device scalar block of one solve
+struct LzScalars {
+    z64 *alpha;  // [k]   h_{jj}
+    z64 *hsub;   // [k]   h_{j+1,j} (real, stored complex)
+    z64 *hsup;   // [k]   h_{j,j+1}
+    z64 *sv;     // [k+1] s_j
+    z64 *tw;     // [k+1] t_j
+    int *flag;   // [k]   breakdown flags
+};
+
+__global__ void lz_alpha_kernel(const z64 *partials, int nblk, LzScalars S, int j)
+{
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        re += partials[i].r;
+        im += partials[i].i;
+    }
+    __shared__ double lds[8];
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const z64 d = {v[0], v[1]};
+        S.alpha[j] = S.sv[j].r * cmulc(S.tw[j], d);  // conj(t_j) s_j (wh^H u)
+    }
+}
+
+__global__ void lz_step_kernel(const z64 *partials, int nblk, LzScalars S, int j, double tol)
+{
+    double a = 0.0, br = 0.0, bi = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        a += partials[2 * i].r;
+        br += partials[2 * i].i;
+        bi += partials[2 * i + 1].r;
+        c += partials[2 * i + 1].i;
+    }
+    __shared__ double lds[16];
+    double v[4] = {a, br, bi, c};
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0) {
+        const double vv = v[0], ww = v[3];
+        const z64 wv = {v[1], v[2]};
+        const double delta = sqrt(vv);
+        const double sn = delta > 0.0 ? 1.0 / delta : 0.0;
+        const z64 hsup = sn * wv;
+        S.hsub[j] = {delta, 0.0};
+        S.hsup[j] = hsup;
+        S.sv[j + 1] = {sn, 0.0};
+        const double m2 = norm2(hsup);
+        S.tw[j + 1] = m2 > 0.0 ? z64{hsup.r / m2, hsup.i / m2} : z64{0.0, 0.0};  // 1/conj(h)
+        S.flag[j] = (!(delta > 0.0) || !(sqrt(norm2(wv)) > tol * sqrt(vv * ww))) ? 1 : 0;
+    }
+}
+
+__device__ __forceinline__ z64 ld2(const double2 *p, int64_t i)
+{
+    double2 t = p[i];
+    return {t.x, t.y};
+}
+
+// One thread per pair of complex entries (e0 = 2*c2*V + s, e1 = e0 + V) so that
+// the FP32 stencil outputs ([6][V] float4) and FP64 vectors line up.
+template <bool F32>
+__global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const void *z_, const double2 *vj,
+                                                        const double2 *vjm, const double2 *wj, const double2 *wjm,
+                                                        double2 *vn, double2 *wn, float4 *vn32, float4 *wn32,
+                                                        LzScalars S, int j, int V, z64 *partials)
+{
+    // coefficients of the two three-term recurrences
+    const double s0 = S.sv[j].r;
+    const z64 al = S.alpha[j], t0 = S.tw[j];
+    const z64 cu = {s0, 0.0};
+    const z64 cv0 = -(s0 * al);
+    const z64 cz = t0;
+    const z64 cw0 = -(conj(al) * t0);
+    z64 cv1 = {0.0, 0.0}, cw1 = {0.0, 0.0};
+    if (j > 0) {
+        cv1 = -(S.sv[j - 1].r * S.hsup[j - 1]);       // h_{j-1,j} s_{j-1}
+        cw1 = -(conj(S.hsub[j - 1]) * S.tw[j - 1]);   // conj(h_{j,j-1}) t_{j-1}
+    }
+    const int64_t npair = (int64_t)6 * V;
+    double a = 0.0, br = 0.0, bi = 0.0, c = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npair; p += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(p / V), s = (int)(p - (int64_t)c2 * V);
+        const int64_t e0 = (int64_t)(2 * c2) * V + s, e1 = e0 + V;
+        z64 u0, u1, z0, z1;
+        if constexpr (F32) {
+            float4 uu = static_cast<const float4 *>(u_)[p], zz = static_cast<const float4 *>(z_)[p];
+            u0 = {uu.x, uu.y};
+            u1 = {uu.z, uu.w};
+            z0 = {zz.x, zz.y};
+            z1 = {zz.z, zz.w};
+        } else {
+            u0 = ld2(static_cast<const double2 *>(u_), e0);
+            u1 = ld2(static_cast<const double2 *>(u_), e1);
+            z0 = ld2(static_cast<const double2 *>(z_), e0);
+            z1 = ld2(static_cast<const double2 *>(z_), e1);
+        }
+        z64 v0 = cu * u0 + cv0 * ld2(vj, e0), v1 = cu * u1 + cv0 * ld2(vj, e1);
+        z64 w0 = cz * z0 + cw0 * ld2(wj, e0), w1 = cz * z1 + cw0 * ld2(wj, e1);
+        if (j > 0) {
+            v0 = v0 + cv1 * ld2(vjm, e0);
+            v1 = v1 + cv1 * ld2(vjm, e1);
+            w0 = w0 + cw1 * ld2(wjm, e0);
+            w1 = w1 + cw1 * ld2(wjm, e1);
+        }
+        vn[e0] = make_double2(v0.r, v0.i);
+        vn[e1] = make_double2(v1.r, v1.i);
+        wn[e0] = make_double2(w0.r, w0.i);
+        wn[e1] = make_double2(w1.r, w1.i);
+        if constexpr (F32) {
+            vn32[p] = make_float4((float)v0.r, (float)v0.i, (float)v1.r, (float)v1.i);
+            wn32[p] = make_float4((float)w0.r, (float)w0.i, (float)w1.r, (float)w1.i);
+        }
+        a += norm2(v0) + norm2(v1);
+        const z64 d = cmulc(w0, v0) + cmulc(w1, v1);
+        br += d.r;
+        bi += d.i;
+        c += norm2(w0) + norm2(w1);
+    }
+    __shared__ double lds[16];
+    double v[4] = {a, br, bi, c};
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = {v[0], v[1]};
+        partials[2 * blockIdx.x + 1] = {v[2], v[3]};
+    }
+}
+
+// x[e] = sum_j c_j V_j[e]
+__global__ void __launch_bounds__(256) lift_kernel(const double2 *basis, int64_t n, int k, const z64 *c, double2 *x)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 acc = {0.0, 0.0};
+        for (int jj = 0; jj < k; ++jj) acc = acc + c[jj] * ld2(basis, (int64_t)jj * n + e);
+        x[e] = make_double2(acc.r, acc.i);
+    }
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    explicit DevBuf(size_t bytes)
+    {
+        if (bytes && hipMalloc(&p, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "device workspace"};
+    }
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+void deflation_prologue(Context &ctx, const sgn_deflation *defl, int64_t n, const void *b, void *x, void *r,
+                        void *rt, hipStream_t s)
+{
+    const size_t bytes = (size_t)n * 16;
+    const int m = (defl && defl->m > 0) ? defl->m : 0;
+    if (r) SGN_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, s));
+    if (rt) SGN_HIP(hipMemcpyAsync(rt, b, bytes, hipMemcpyDeviceToDevice, s));
+    if (m == 0) {
+        if (x) SGN_HIP(hipMemsetAsync(x, 0, bytes, s));
+        return;
+    }
+    SGN_REQUIRE(defl->L && defl->R && defl->lambda, "deflation: null L, R or lambda");
+    double lmax = 0.0;
+    for (int i = 0; i < m; ++i) lmax = std::max(lmax, std::hypot(defl->lambda[2 * i], defl->lambda[2 * i + 1]));
+    std::vector<z64> sg(m);
+    for (int i = 0; i < m; ++i) {
+        const double re = defl->lambda[2 * i];
+        if (!(std::abs(re) > 1e-12 * lmax)) throw Failure{SGN_ERR_IMAG_AXIS, "deflated eigenvalue on the imaginary axis"};
+        sg[i] = {re > 0 ? 1.0 : -1.0, 0.0};
+    }
+    DevBuf c(sizeof(z64) * (2 * m)), d(sizeof(z64) * m);
+    SGN_HIP(hipMemcpyAsync(d.p, sg.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s));
+    deflate_dots(defl->L, m, b, n, c.as<z64>(), ctx, s);  // L^H b
+    if (x) deflate_combine(x, {0.0, 0.0}, {1.0, 0.0}, defl->R, m, c.as<z64>(), d.as<z64>(), n, s);
+    if (r) deflate_combine(r, {1.0, 0.0}, {-1.0, 0.0}, defl->R, m, c.as<z64>(), nullptr, n, s);
+    if (rt) {
+        deflate_dots(defl->R, m, b, n, c.as<z64>() + m, ctx, s);  // R^H b
+        deflate_combine(rt, {1.0, 0.0}, {-1.0, 0.0}, defl->L, m, c.as<z64>() + m, nullptr, n, s);
+    }
+    SGN_HIP(hipStreamSynchronize(s));  // c, d are freed on return
+}
+
+}  // namespace sgn
+
+using namespace sgn;
+
+extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *b, void *x,
+                                          const sgn_deflation *defl, const sgn_lanczos_opts *opts,
+                                          sgn_stats *stats, void *stream)
+{
+    return guard([&] {
+        const auto t_start = std::chrono::steady_clock::now();
+        SGN_REQUIRE(l && b && x && opts, "sign_lanczos_2sided: null argument");
+        SGN_REQUIRE(opts->k >= 1, "sign_lanczos_2sided: k must be >= 1");
+        SGN_REQUIRE(std::isfinite(mu), "sign_lanczos_2sided: mu not finite");
+        Lattice &lat = *as_lattice(l);
+        Context &ctx = *lat.ctx;
+        SGN_HIP(hipSetDevice(ctx.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int k = opts->k;
+        const int64_t V = lat.V, n = 12 * V;
+        const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8;
+        const bool f32 = opts->prec != SGN_PREC_F64;
+        const sgn_prec sp = opts->prec;
+        if (stats) *stats = sgn_stats{};
+
+        // canonical residual and shadow; x <- x_P
+        DevBuf r(b64), rt(b64);
+        deflation_prologue(ctx, defl, n, b, x, r.p, rt.p, s);
+        const double beta = norm_sync(ctx, r.p, n, false, s);
+        SGN_REQUIRE(std::isfinite(beta), "sign_lanczos_2sided: b contains NaN or Inf");
+        // (I - P) b at rounding level: the deflated part x_P is the whole answer
+        if (beta <= 1e-13 * norm_sync(ctx, b, n, false, s)) return;
+        const z64 g = dot_sync(ctx, r.p, rt.p, n, false, s);   // r^H r~
+        if (!(std::sqrt(norm2(g)) > 1e-14 * beta * norm_sync(ctx, rt.p, n, false, s)))
+            throw Failure{SGN_ERR_BREAKDOWN, "shadow vector orthogonal to the residual"};
+
+        // workspace: basis V (k vectors), 3 W vectors, u, z (FP64 internal) + FP32 copies
+        DevBuf Vb((size_t)k * b64), Wb(3 * b64), u(b64), z(b64);
+        DevBuf v32(f32 ? b32 : 0), w32(f32 ? b32 : 0), u32(f32 ? b32 : 0), z32(f32 ? b32 : 0);
+        DevBuf scal(sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k);
+        LzScalars S;
+        S.alpha = scal.as<z64>();
+        S.hsub = S.alpha + k;
+        S.hsup = S.hsub + k;
+        S.sv = S.hsup + k;
+        S.tw = S.sv + (k + 1);
+        S.flag = reinterpret_cast<int *>(S.tw + (k + 1));
+        SGN_HIP(hipMemsetAsync(scal.p, 0, sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k, s));
+        const double s1 = 1.0 / beta;
+        const z64 v1rt = {s1 * g.r, s1 * g.i};  // v_1^H r~
+        const double m2 = norm2(v1rt);
+        const z64 t1 = {v1rt.r / m2, -v1rt.i / m2};  // 1 / (v_1^H r~)
+        const z64 sv0 = {s1, 0.0};
+        SGN_HIP(hipMemcpyAsync(S.sv, &sv0, sizeof(z64), hipMemcpyHostToDevice, s));
+        SGN_HIP(hipMemcpyAsync(S.tw, &t1, sizeof(z64), hipMemcpyHostToDevice, s));
+        auto Vj = [&](int j) { return static_cast<char *>(Vb.p) + (size_t)j * b64; };
+        auto Wj = [&](int j) { return static_cast<char *>(Wb.p) + (size_t)(j % 3) * b64; };
+        pack_spinor(lat, r.p, Vj(0), SGN_PREC_F64, s);
+        pack_spinor(lat, rt.p, Wj(0), SGN_PREC_F64, s);
+        if (f32) {
+            convert_64_to_32(Vj(0), v32.p, V, s);
+            convert_64_to_32(Wj(0), w32.p, V, s);
+        }
+
+        const int nst = dslash_blocks(lat);
+        const int nvb = vec_blocks(6 * V);
+        z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nst, 2 * nvb)));
+        OpSpec opA, opAh;
+        opA.mu = mu;
+        opAh.mu = -mu;
+
+        std::vector<z64> halpha(k), hsub(k), hsup(k), hsv(k + 1), ycur, yprev;
+        std::vector<int> hflag(k);
+        auto download = [&](int kk) {
+            SGN_HIP(hipMemcpyAsync(halpha.data(), S.alpha, sizeof(z64) * kk, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipMemcpyAsync(hsub.data(), S.hsub, sizeof(z64) * kk, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipMemcpyAsync(hsup.data(), S.hsup, sizeof(z64) * kk, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipMemcpyAsync(hsv.data(), S.sv, sizeof(z64) * kk, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipMemcpyAsync(hflag.data(), S.flag, sizeof(int) * kk, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j + 1 < kk; ++j)
+                if (hflag[j]) throw Failure{SGN_ERR_BREAKDOWN, "two-sided Lanczos breakdown at step " + std::to_string(j + 1)};
+        };
+        double small_ms = 0.0, minre = 0.0;
+        auto small_sign = [&](int kk, std::vector<z64> &y) {
+            const auto t0 = std::chrono::steady_clock::now();
+            std::vector<std::complex<double>> d(kk), sb(kk), sp(kk), yy(kk);
+            for (int j = 0; j < kk; ++j) {
+                d[j] = {halpha[j].r, halpha[j].i};
+                sb[j] = {hsub[j].r, hsub[j].i};
+                sp[j] = {hsup[j].r, hsup[j].i};
+            }
+            SmallSignInfo info;
+            const int rc = small_sign_e1(kk, d.data(), sb.data(), sp.data(), yy.data(), &info);
+            small_ms += ms_since(t0);
+            minre = info.min_abs_re;
+            if (rc == 3) throw Failure{SGN_ERR_IMAG_AXIS, "eigenvalue of T_k on the imaginary axis"};
+            if (rc != 0) throw Failure{SGN_ERR_INVALID, "small sign: QR iteration failed"};
+            y.resize(kk);
+            for (int j = 0; j < kk; ++j) y[j] = {yy[j].real(), yy[j].imag()};
+        };
+
+        const auto t_kry = std::chrono::steady_clock::now();
+        int kused = k;
+        for (int j = 0; j < k; ++j) {
+            // u = A vh_j with partials of wh_j^H u
+            Epilogue ep;
+            ep.w = f32 ? w32.p : Wj(j);
+            ep.partials = part;
+            const int nb1 = dslash_launch(lat, sp, opA, f32 ? v32.p : Vj(j), f32 ? u32.p : u.p, ep, s);
+            hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S, j);
+            if (j + 1 == k) break;
+            dslash_launch(lat, sp, opAh, f32 ? w32.p : Wj(j), f32 ? z32.p : z.p, Epilogue{}, s);
+            void *vn = Vj(j + 1);
+            const double2 *vjm = j > 0 ? reinterpret_cast<const double2 *>(Vj(j - 1)) : nullptr;
+            const double2 *wjm = j > 0 ? reinterpret_cast<const double2 *>(Wj(j - 1)) : nullptr;
+            if (f32)
+                hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb), dim3(256), 0, s, u32.p, z32.p,
+                                   (const double2 *)Vj(j), vjm, (const double2 *)Wj(j), wjm, (double2 *)vn,
+                                   (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, S, j, (int)V, part);
+            else
+                hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb), dim3(256), 0, s, u.p, z.p,
+                                   (const double2 *)Vj(j), vjm, (const double2 *)Wj(j), wjm, (double2 *)vn,
+                                   (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)V, part);
+            hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(256), 0, s, part, nvb, S, j, 1e-14);
+            SGN_HIP(hipGetLastError());
+            if (opts->tol > 0 && opts->check_every > 0 && (j + 1) % opts->check_every == 0 && j + 1 < k) {
+                const int kk = j + 1;
+                download(kk);
+                small_sign(kk, ycur);
+                if (!yprev.empty()) {
+                    double num = 0.0, den = 0.0;
+                    for (int i = 0; i < kk; ++i) {
+                        z64 d = ycur[i];
+                        if (i < (int)yprev.size()) d = d - yprev[i];
+                        num += norm2(d);
+                        den += norm2(ycur[i]);
+                    }
+                    if (std::sqrt(num) <= opts->tol * std::sqrt(den)) {
+                        kused = kk;
+                        break;
+                    }
+                }
+                yprev = ycur;
+            }
+        }
+        SGN_HIP(hipGetLastError());
+        download(kused);
+        const double kry_ms = ms_since(t_kry);
+        std::vector<z64> y;
+        small_sign(kused, y);
+        // x = x_P + beta * sum_j y_j s_j vh_j
+        std::vector<z64> c(kused);
+        for (int j = 0; j < kused; ++j) c[j] = (beta * hsv[j].r) * y[j];
+        DevBuf cd(sizeof(z64) * kused);
+        SGN_HIP(hipMemcpyAsync(cd.p, c.data(), sizeof(z64) * kused, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(lift_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, (const double2 *)Vb.p, n, kused,
+                           cd.as<z64>(), (double2 *)u.p);
+        unpack_spinor(lat, u.p, r.p, SGN_PREC_F64, s);
+        axpby64({1.0, 0.0}, r.p, {1.0, 0.0}, x, n, s);
+        SGN_HIP(hipStreamSynchronize(s));
+        if (stats) {
+            stats->iterations = kused;
+            stats->matvecs = 2 * kused - 1;
+            stats->min_abs_re = minre;
+            stats->krylov_ms = kry_ms;
+            stats->small_ms = small_ms;
+            stats->total_ms = ms_since(t_start);
+        }
+    });
+}

@@ -16,6 +16,7 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 void *Context::ensure_partials(size_t bytes)
 {
     if (bytes > partials_bytes) {
+        SGN_HIP(hipDeviceSynchronize());  // kernels of earlier calls may still use the old buffer
         if (partials) SGN_HIP(hipFree(partials));
         partials = nullptr;
         partials_bytes = 0;
@@ -28,6 +29,7 @@ void *Context::ensure_partials(size_t bytes)
 void *Context::ensure_scalars(size_t bytes)
 {
     if (bytes > scalars_bytes) {
+        SGN_HIP(hipDeviceSynchronize());
         if (scalars) SGN_HIP(hipFree(scalars));
         scalars = nullptr;
         scalars_bytes = 0;
@@ -40,6 +42,7 @@ void *Context::ensure_scalars(size_t bytes)
 void Lattice::ensure_stage(size_t bytes)
 {
     if (bytes <= stage_bytes) return;
+    SGN_HIP(hipDeviceSynchronize());
     if (stage_in) SGN_HIP(hipFree(stage_in));
     if (stage_out) SGN_HIP(hipFree(stage_out));
     stage_in = stage_out = nullptr;

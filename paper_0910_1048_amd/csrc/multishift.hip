@@ -1,0 +1,658 @@
+// Multishift BiCG for the shifted systems of the Neuberger rational function,
+// BiCG-LR(m) of the section "Two-sided Lanczos with rational functions".
+//
+// Systems: (A' - sigma_i) x_i = y,  A' = c^2 H_W(mu)^2,  y = c H_W (I - P) b.
+// Seed: the shift of smallest modulus, M = A' - sigma_1, BiCG with shadow
+// r~_0 = r_0.  The other shifts, M + tau_i (tau_i = sigma_1 - sigma_i), keep
+// residuals collinear with the seed's, r^i_k = zeta^i_k r_k, with zeta from the
+// three-term recurrence of the seed's residual polynomial.  Converged shifts
+// are frozen (no more memory traffic).
+//
+// Precision schedule (mixed mode): while the seed residual is above theta32
+// ||y|| everything is FP64; below it the vectors p_i, r, r~, p~ and the stencil
+// drop to FP32 and the solutions accumulate in FP32 increments that are folded
+// into FP64 x_i at every reliable update (true seed residual in FP64).  Below
+// theta16 the stencil may also switch to FP16 links.  Rounding injected at a
+// given iteration is proportional to the residual size at that point, so the
+// shifted systems -- which get no reliable update -- keep residuals at the
+// 1e-10 level without a separate refinement phase.
+//
+// Per iteration (all scalars on the device, host polls flags every few iterations):
+//   tmp = A p;  q = c^2 A tmp - sigma_1 p   (+ partials of p~^H q)
+//   tmp~ = A^H p~;  q~ = c^2 A^H tmp~ - sigma_1 p~
+//   alpha = rho / p~^H q;  zeta^i_{k+1}, alpha_i          (1 block)
+//   r -= alpha q;  r~ -= conj(alpha) q~   (+ partials of r~^H r, ||r||^2)
+//   beta = rho'/rho;  beta_i = beta (zeta_{k+1}/zeta_k)^2; convergence flags (1 block)
+//   x_i += alpha_i p_i;  p_i = zeta_{k+1} r + beta_i p_i;  p~ = r~ + conj(beta) p~
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "field_io.h"
+#include "vec.h"
+
+namespace sgn {
+
+namespace {
+
+constexpr int kS = SGN_MAX_POLES;
+
+struct MsHead {
+    z64 rho, alpha, beta, alpha_prev, beta_prev;
+    double rnorm, rmax, ynorm, tol, delta, theta32, theta16;
+    int done, reliable, want_phase, breakdown, iter, maxiter, nshift, seed, phase, pad;
+};
+
+struct MsState {
+    MsHead h;
+    z64 zeta[kS], zeta_prev[kS], zeta_next[kS], alpha_i[kS], beta_i[kS];
+    double tau[kS];
+    double res[kS];
+    int act[kS], act_next[kS];
+};
+
+__device__ __forceinline__ z64 cdiv(z64 a, z64 b)
+{
+    const double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+__device__ __forceinline__ bool finite(z64 a) { return isfinite(a.r) && isfinite(a.i); }
+
+__global__ void __launch_bounds__(256) ms_alpha_kernel(const z64 *partials, int nb, MsState *S)
+{
+    if (S->h.done) return;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        re += partials[i].r;
+        im += partials[i].i;
+    }
+    __shared__ double lds[8];
+    __shared__ z64 alpha_sh;
+    __shared__ int bad_sh;
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const z64 den = {v[0], v[1]};
+        z64 a = cdiv(S->h.rho, den);
+        bad_sh = 0;
+        if (!(norm2(den) > 0.0) || !finite(a)) {
+            S->h.breakdown = 1;
+            S->h.done = 1;
+            a = {0.0, 0.0};
+            bad_sh = 1;
+        }
+        S->h.alpha = a;
+        alpha_sh = a;
+    }
+    __syncthreads();
+    if (bad_sh) return;
+    const z64 al = alpha_sh, ap = S->h.alpha_prev, bp = S->h.beta_prev;
+    for (int i = threadIdx.x; i < S->h.nshift; i += blockDim.x) {
+        const int a = S->act_next[i];
+        S->act[i] = a;
+        if (!a) continue;
+        const z64 z = S->zeta[i], zp = S->zeta_prev[i];
+        const z64 one_tau = {1.0 + S->tau[i] * al.r, S->tau[i] * al.i};
+        const z64 denom = ap * one_tau * zp + al * bp * (zp - z);
+        const z64 zn = cdiv(z * zp * ap, denom);
+        S->zeta_next[i] = zn;
+        S->alpha_i[i] = cdiv(al * zn, z);
+    }
+}
+
+__global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int nb, MsState *S)
+{
+    if (S->h.done) return;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += partials[2 * i].r;
+        b += partials[2 * i].i;
+        c += partials[2 * i + 1].r;
+    }
+    __shared__ double lds[12];
+    __shared__ z64 beta_sh;
+    __shared__ double rn_sh;
+    __shared__ int any_sh, bad_sh;
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        const z64 rho_new = {v[0], v[1]};
+        z64 beta = cdiv(rho_new, S->h.rho);
+        const double rn = sqrt(v[2]);
+        bad_sh = 0;
+        if (!(norm2(S->h.rho) > 0.0) || !finite(beta) || !isfinite(rn)) {
+            S->h.breakdown = 1;
+            S->h.done = 1;
+            beta = {0.0, 0.0};
+            bad_sh = 1;
+        }
+        S->h.beta = beta;
+        S->h.rho = rho_new;
+        S->h.rnorm = rn;
+        S->h.rmax = fmax(S->h.rmax, rn);
+        S->h.alpha_prev = S->h.alpha;
+        S->h.beta_prev = beta;
+        S->h.iter += 1;
+        if (S->h.phase >= 1 && rn < S->h.delta * S->h.rmax) S->h.reliable = 1;
+        if (S->h.phase == 0 && rn < S->h.theta32 * S->h.ynorm) S->h.want_phase = 1;
+        if (S->h.phase == 1 && rn < S->h.theta16 * S->h.ynorm) S->h.want_phase = 2;
+        beta_sh = beta;
+        rn_sh = rn;
+        any_sh = 0;
+    }
+    __syncthreads();
+    if (bad_sh) return;
+    const z64 beta = beta_sh;
+    const double rn = rn_sh;
+    const double lim = S->h.tol * S->h.ynorm;
+    for (int i = threadIdx.x; i < S->h.nshift; i += blockDim.x) {
+        if (!S->act[i]) continue;
+        const z64 zn = S->zeta_next[i], z = S->zeta[i];
+        const z64 q = cdiv(zn, z);
+        S->beta_i[i] = beta * (q * q);
+        S->zeta_prev[i] = z;
+        S->zeta[i] = zn;
+        const double ri = sqrt(norm2(zn)) * rn;
+        S->res[i] = ri;
+        const int an = ri > lim ? 1 : 0;
+        S->act_next[i] = an;
+        if (an) atomicOr(&any_sh, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (!any_sh) {
+            S->h.done = 1;
+        } else {
+            S->act_next[S->h.seed] = 1;  // the seed drives the recurrence
+        }
+        if (S->h.iter >= S->h.maxiter) S->h.done = 1;
+    }
+}
+
+template <typename R> struct VecT;
+template <> struct VecT<double> { using t = double2; };
+template <> struct VecT<float> { using t = float2; };
+
+template <typename T> __device__ __forceinline__ z64 ldz(const T *p, int64_t i)
+{
+    T v = p[i];
+    return {(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void stz(double2 *p, int64_t i, z64 v) { p[i] = make_double2(v.r, v.i); }
+__device__ __forceinline__ void stz(float2 *p, int64_t i, z64 v) { p[i] = make_float2((float)v.r, (float)v.i); }
+
+template <typename R>
+__global__ void __launch_bounds__(256) ms_seed_update(typename VecT<R>::t *r, typename VecT<R>::t *rt,
+                                                      const typename VecT<R>::t *q, const typename VecT<R>::t *qt,
+                                                      int64_t n, const MsState *S, z64 *partials)
+{
+    if (S->h.done) return;
+    const z64 al = S->h.alpha, alc = conj(al);
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 rv = ldz(r, e) - al * ldz(q, e);
+        z64 tv = ldz(rt, e) - alc * ldz(qt, e);
+        stz(r, e, rv);
+        stz(rt, e, tv);
+        if constexpr (sizeof(R) == 4) {  // reduce what is stored
+            rv = ldz(r, e);
+            tv = ldz(rt, e);
+        }
+        const z64 d = cmulc(tv, rv);
+        a += d.r;
+        b += d.i;
+        c += norm2(rv);
+    }
+    __shared__ double lds[12];
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = {v[0], v[1]};
+        partials[2 * blockIdx.x + 1] = {v[2], 0.0};
+    }
+}
+
+// x_i += alpha_i p_i ; p_i = zeta_i r + beta_i p_i (active shifts) ; p~ = r~ + conj(beta) p~
+template <typename R, typename XT>
+__global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, XT *X, const typename VecT<R>::t *r,
+                                                       const typename VecT<R>::t *rt, typename VecT<R>::t *pt,
+                                                       int64_t n, const MsState *S, int expect)
+{
+    // apply only if this iteration's beta step ran (it may have just declared convergence;
+    // later launches of a polling chunk after convergence must not repeat the update)
+    if (S->h.breakdown || S->h.iter != expect) return;
+    __shared__ z64 al_s[kS], be_s[kS], ze_s[kS];
+    __shared__ int act_s[kS];
+    __shared__ int ns;
+    const int nsh = S->h.nshift;
+    for (int i = threadIdx.x; i < nsh; i += blockDim.x) {
+        act_s[i] = S->act[i];
+        al_s[i] = S->alpha_i[i];
+        be_s[i] = S->beta_i[i];
+        ze_s[i] = S->zeta[i];
+    }
+    if (threadIdx.x == 0) ns = nsh;
+    __syncthreads();
+    const z64 bc = conj(S->h.beta);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const z64 rv = ldz(r, e);
+        for (int i = 0; i < ns; ++i) {
+            if (!act_s[i]) continue;
+            typename VecT<R>::t *Pi = P + (int64_t)i * n;
+            XT *Xi = X + (int64_t)i * n;
+            const z64 p = ldz(Pi, e);
+            stz(Xi, e, ldz(Xi, e) + al_s[i] * p);
+            stz(Pi, e, ze_s[i] * rv + be_s[i] * p);
+        }
+        stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
+    }
+}
+
+// x_hi_i += x_lo_i ; x_lo_i = 0   (FP32 layout -> FP64 layout, pair mapping)
+__global__ void ms_flush_kernel(double2 *Xhi, float4 *Xlo, int s, int V)
+{
+    const int64_t np = (int64_t)6 * V;
+    const int64_t n = (int64_t)12 * V;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(p / V), st = (int)(p - (int64_t)c2 * V);
+        const int64_t e0 = (int64_t)(2 * c2) * V + st, e1 = e0 + V;
+        for (int i = 0; i < s; ++i) {
+            float4 l = Xlo[(int64_t)i * np + p];
+            double2 *h = Xhi + (int64_t)i * n;
+            double2 a = h[e0], b = h[e1];
+            h[e0] = make_double2(a.x + l.x, a.y + l.y);
+            h[e1] = make_double2(b.x + l.z, b.y + l.w);
+            Xlo[(int64_t)i * np + p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+// r32 = f32(y + t) (pair mapping) with partials of rt32^H r32 and ||r32||^2
+__global__ void __launch_bounds__(256) ms_reliable_kernel(const double2 *y, const double2 *t, float4 *r32,
+                                                          const float4 *rt32, int V, z64 *partials)
+{
+    const int64_t np = (int64_t)6 * V;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(p / V), st = (int)(p - (int64_t)c2 * V);
+        const int64_t e0 = (int64_t)(2 * c2) * V + st, e1 = e0 + V;
+        const double2 y0 = y[e0], y1 = y[e1], t0 = t[e0], t1 = t[e1];
+        const float4 rv = make_float4((float)(y0.x + t0.x), (float)(y0.y + t0.y), (float)(y1.x + t1.x),
+                                      (float)(y1.y + t1.y));
+        r32[p] = rv;
+        const float4 tv = rt32[p];
+        a += (double)tv.x * rv.x + (double)tv.y * rv.y + (double)tv.z * rv.z + (double)tv.w * rv.w;
+        b += (double)tv.x * rv.y - (double)tv.y * rv.x + (double)tv.z * rv.w - (double)tv.w * rv.z;
+        c += (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z + (double)rv.w * rv.w;
+    }
+    __shared__ double lds[12];
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = {v[0], v[1]};
+        partials[2 * blockIdx.x + 1] = {v[2], 0.0};
+    }
+}
+
+__global__ void __launch_bounds__(256) ms_reliable_coef(const z64 *partials, int nb, MsState *S)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += partials[2 * i].r;
+        b += partials[2 * i].i;
+        c += partials[2 * i + 1].r;
+    }
+    __shared__ double lds[12];
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        S->h.rho = {v[0], v[1]};
+        const double rn = sqrt(v[2]);
+        S->h.rnorm = rn;
+        S->h.rmax = rn;
+        S->h.reliable = 0;
+        const int seed = S->h.seed;
+        S->res[seed] = rn;
+        if (rn > S->h.tol * S->h.ynorm && S->h.iter < S->h.maxiter) {
+            S->act_next[seed] = 1;
+            S->h.done = 0;
+        }
+    }
+}
+
+// x = sum_i w_i X_i (FP64)
+__global__ void ms_combine_kernel(const double2 *X, const double *w, int s, int64_t n, double2 *x)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < s; ++i) {
+            const double2 v = X[(int64_t)i * n + e];
+            re += w[i] * v.x;
+            im += w[i] * v.y;
+        }
+        x[e] = make_double2(re, im);
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T *p, T v, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
+}
+
+__global__ void copy_rep_kernel(const double2 *src, double2 *dst, int s, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = src[e];
+        for (int i = 0; i < s; ++i) dst[(int64_t)i * n + e] = v;
+    }
+}
+
+struct DevMem {
+    void *p = nullptr;
+    explicit DevMem(size_t bytes)
+    {
+        if (bytes && hipMalloc(&p, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "multishift workspace"};
+    }
+    ~DevMem()
+    {
+        if (p) (void)hipFree(p);
+    }
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// One problem of multishift_solve.
+sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, sgn_stats *st,
+                     hipStream_t s)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    Lattice &lat = *as_lattice(pb.lat);
+    Context &ctx = *lat.ctx;
+    SGN_HIP(hipSetDevice(ctx.device));
+    const int64_t V = lat.V, n = 12 * V;
+    const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8;
+    const int ns = rf.s;
+    const bool mixed = o.prec != SGN_PREC_F64;
+    const double c2 = rf.c * rf.c;
+    int seed = 0;
+    for (int i = 1; i < ns; ++i)
+        if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed])) seed = i;
+    const double s1 = rf.sigma[seed];
+
+    // x <- x_P, r = (I - P) b (canonical)
+    DevMem rcan(b64);
+    deflation_prologue(ctx, pb.defl, n, pb.b, pb.x, rcan.p, nullptr, s);
+
+    // FP64 workspace
+    DevMem y(b64), r(b64), rt(b64), pt(b64), q(b64), qt(b64), tmp(b64), tmpt(b64);
+    DevMem X((size_t)ns * b64), P((size_t)ns * b64);
+    // FP32 workspace (mixed)
+    DevMem r32(mixed ? b32 : 0), rt32(mixed ? b32 : 0), pt32(mixed ? b32 : 0), q32(mixed ? b32 : 0),
+        qt32(mixed ? b32 : 0), tmp32(mixed ? b32 : 0), tmpt32(mixed ? b32 : 0);
+    DevMem P32(mixed ? (size_t)ns * b32 : 0), Xlo(mixed ? (size_t)ns * b32 : 0);
+    DevMem Sd(sizeof(MsState));
+    MsState *S = Sd.as<MsState>();
+
+    OpSpec opA, opAh;
+    opA.mu = pb.mu;
+    opAh.mu = -pb.mu;
+    // y = c A r
+    pack_spinor(lat, rcan.p, tmp.p, SGN_PREC_F64, s);
+    {
+        Epilogue ep;
+        ep.a = rf.c;
+        dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, y.p, ep, s);
+    }
+    const double ynorm = norm_sync(ctx, y.p, n, false, s);
+    SGN_REQUIRE(std::isfinite(ynorm), "multishift_solve: b contains NaN or Inf");
+    if (st) {
+        *st = sgn_stats{};
+        st->nshift = ns;
+    }
+    if (ynorm == 0.0) return SGN_OK;  // x = x_P
+
+    const int nvb = vec_blocks(n);
+    const int nst = dslash_blocks(lat);
+    const int nvbp = vec_blocks(6 * V);
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max({nst, 2 * nvb, 2 * nvbp})));
+
+    // initial state
+    MsState h0{};
+    h0.h.rho = {ynorm * ynorm, 0.0};
+    h0.h.alpha_prev = {1.0, 0.0};
+    h0.h.beta_prev = {0.0, 0.0};
+    h0.h.rnorm = h0.h.rmax = h0.h.ynorm = ynorm;
+    h0.h.tol = o.tol;
+    h0.h.delta = o.delta > 0 ? o.delta : 0.1;
+    h0.h.theta32 = mixed ? (o.theta32 > 0 ? o.theta32 : 1e-3) : 0.0;
+    h0.h.theta16 = (o.prec == SGN_PREC_F32_H16) ? (o.theta16 > 0 ? o.theta16 : 1e-6) : 0.0;
+    h0.h.maxiter = o.maxiter > 0 ? o.maxiter : 10000;
+    h0.h.nshift = ns;
+    h0.h.seed = seed;
+    for (int i = 0; i < ns; ++i) {
+        h0.zeta[i] = h0.zeta_prev[i] = {1.0, 0.0};
+        h0.tau[i] = s1 - rf.sigma[i];
+        h0.act_next[i] = 1;
+        h0.res[i] = ynorm;
+    }
+    SGN_HIP(hipMemcpyAsync(S, &h0, sizeof(MsState), hipMemcpyHostToDevice, s));
+    SGN_HIP(hipMemcpyAsync(r.p, y.p, b64, hipMemcpyDeviceToDevice, s));
+    SGN_HIP(hipMemcpyAsync(rt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
+    SGN_HIP(hipMemcpyAsync(pt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s, y.as<double2>(), P.as<double2>(), ns, n);
+    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s, X.as<double2>(), make_double2(0, 0),
+                       (int64_t)ns * n);
+    SGN_HIP(hipGetLastError());
+
+    int phase = 0;
+    int poll = o.poll > 0 ? o.poll : (int)std::min<int64_t>(16, std::max<int64_t>(1, (200000 + V - 1) / V));
+    int reliable_updates = 0;
+    const double sigma_seed = s1;
+
+    int launched = 0;  // iteration number of the next launch minus one (synced with the device at polls)
+    auto iterate = [&](int count) {
+        for (int it = 0; it < count; ++it) {
+            ++launched;
+            const bool lo = phase >= 1;
+            const sgn_prec sp = phase == 0 ? SGN_PREC_F64 : (phase == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16);
+            void *pseed = lo ? (void *)(P32.as<char>() + (size_t)seed * b32) : (void *)(P.as<char>() + (size_t)seed * b64);
+            void *vr = lo ? r32.p : r.p, *vrt = lo ? rt32.p : rt.p, *vpt = lo ? pt32.p : pt.p;
+            void *vq = lo ? q32.p : q.p, *vqt = lo ? qt32.p : qt.p, *vtmp = lo ? tmp32.p : tmp.p,
+                 *vtmpt = lo ? tmpt32.p : tmpt.p;
+            dslash_launch(lat, sp, opA, pseed, vtmp, Epilogue{}, s);
+            Epilogue e1;
+            e1.a = c2;
+            e1.z = pseed;
+            e1.b = {-sigma_seed, 0.0};
+            e1.w = vpt;
+            e1.partials = part;
+            const int nb1 = dslash_launch(lat, sp, opA, vtmp, vq, e1, s);
+            dslash_launch(lat, sp, opAh, vpt, vtmpt, Epilogue{}, s);
+            Epilogue e2;
+            e2.a = c2;
+            e2.z = vpt;
+            e2.b = {-sigma_seed, 0.0};
+            dslash_launch(lat, sp, opAh, vtmpt, vqt, e2, s);
+            hipLaunchKernelGGL(ms_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S);
+            if (lo) {
+                hipLaunchKernelGGL(ms_seed_update<float>, dim3(nvb), dim3(256), 0, s, (float2 *)vr, (float2 *)vrt,
+                                   (const float2 *)vq, (const float2 *)vqt, n, S, part);
+                hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
+                hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(nvb), dim3(256), 0, s, P32.as<float2>(),
+                                   Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt, (float2 *)vpt, n, S,
+                                   launched);
+            } else {
+                hipLaunchKernelGGL(ms_seed_update<double>, dim3(nvb), dim3(256), 0, s, (double2 *)vr,
+                                   (double2 *)vrt, (const double2 *)vq, (const double2 *)vqt, n, S, part);
+                hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
+                hipLaunchKernelGGL((ms_shift_update<double, double2>), dim3(nvb), dim3(256), 0, s, P.as<double2>(),
+                                   X.as<double2>(), (const double2 *)vr, (const double2 *)vrt, (double2 *)vpt, n, S,
+                                   launched);
+            }
+        }
+        SGN_HIP(hipGetLastError());
+    };
+
+    auto flush = [&]() {
+        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), ns, (int)V);
+    };
+
+    auto reliable_update = [&]() {
+        flush();
+        double2 *xs = X.as<double2>() + (size_t)seed * n;
+        dslash_launch(lat, SGN_PREC_F64, opA, xs, tmp.p, Epilogue{}, s);
+        Epilogue ep;
+        ep.a = -c2;
+        ep.z = xs;
+        ep.b = {sigma_seed, 0.0};
+        dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, q.p, ep, s);  // q = -c^2 A A x + sigma x
+        hipLaunchKernelGGL(ms_reliable_kernel, dim3(nvbp), dim3(256), 0, s, y.as<double2>(), q.as<double2>(),
+                           r32.as<float4>(), rt32.as<float4>(), (int)V, part);
+        hipLaunchKernelGGL(ms_reliable_coef, dim3(1), dim3(256), 0, s, part, nvbp, S);
+        SGN_HIP(hipGetLastError());
+        ++reliable_updates;
+    };
+
+    auto switch_to_f32 = [&]() {
+        convert_64_to_32(r.p, r32.p, V, s);
+        convert_64_to_32(rt.p, rt32.p, V, s);
+        convert_64_to_32(pt.p, pt32.p, V, s);
+        for (int i = 0; i < ns; ++i)
+            convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, V, s);
+        hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
+                           (int64_t)ns * n);
+        SGN_HIP(hipGetLastError());
+    };
+
+    MsHead hh{};
+    auto read_head = [&]() {
+        SGN_HIP(hipMemcpyAsync(&hh, &S->h, sizeof(MsHead), hipMemcpyDeviceToHost, s));
+        SGN_HIP(hipStreamSynchronize(s));
+        launched = hh.iter;
+    };
+    auto put = [&](void *dst, const void *src, size_t bytes) {
+        SGN_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        SGN_HIP(hipStreamSynchronize(s));
+    };
+    auto set_phase = [&](int ph) {
+        phase = ph;
+        const int zero = 0;
+        put(&S->h.phase, &ph, sizeof(int));
+        put(&S->h.want_phase, &zero, sizeof(int));
+    };
+
+    const auto t_kry = std::chrono::steady_clock::now();
+    sgn_status result = SGN_OK;
+    for (;;) {
+        iterate(poll);
+        read_head();
+        if (hh.breakdown) throw Failure{SGN_ERR_BREAKDOWN, "multishift BiCG breakdown at iteration " + std::to_string(hh.iter)};
+        if (hh.done) {
+            if (phase >= 1) {
+                reliable_update();
+                read_head();
+                if (!hh.done) continue;
+            }
+            if (hh.iter >= h0.h.maxiter && hh.rnorm > o.tol * ynorm) result = SGN_ERR_NOT_CONVERGED;
+            break;
+        }
+        if (mixed && hh.want_phase > phase) {
+            if (phase == 0) {
+                switch_to_f32();
+                set_phase(1);
+                const double rm = hh.rnorm;
+                put(&S->h.rmax, &rm, sizeof(double));
+            } else if (phase == 1 && o.prec == SGN_PREC_F32_H16) {
+                set_phase(2);
+            }
+            continue;
+        }
+        if (phase >= 1 && hh.reliable) reliable_update();
+    }
+    if (phase >= 1) flush();
+    const double kry_ms = ms_since(t_kry);
+
+    // x += sum_i omega_i x_i
+    {
+        DevMem w(sizeof(double) * ns);
+        SGN_HIP(hipMemcpyAsync(w.p, rf.omega, sizeof(double) * ns, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), ns, n,
+                           tmp.as<double2>());
+        unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
+        axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, n, s);
+        if (pb.x_shift)
+            for (int i = 0; i < ns; ++i)
+                if (pb.x_shift[i]) unpack_spinor(lat, X.as<char>() + (size_t)i * b64, pb.x_shift[i], SGN_PREC_F64, s);
+        SGN_HIP(hipStreamSynchronize(s));
+    }
+    if (st) {
+        MsState hs;
+        SGN_HIP(hipMemcpy(&hs, S, sizeof(MsState), hipMemcpyDeviceToHost));
+        st->iterations = hs.h.iter;
+        st->matvecs = 4 * hs.h.iter + 1 + 2 * reliable_updates;
+        st->reliable_updates = reliable_updates;
+        double mx = 0.0;
+        for (int i = 0; i < ns; ++i) {
+            st->shift_residual[i] = hs.res[i] / ynorm;
+            mx = std::max(mx, st->shift_residual[i]);
+        }
+        if (o.verify) {  // FP64 true residuals of every shifted system
+            mx = 0.0;
+            for (int i = 0; i < ns; ++i) {
+                double2 *xi = X.as<double2>() + (size_t)i * n;
+                dslash_launch(lat, SGN_PREC_F64, opA, xi, tmp.p, Epilogue{}, s);
+                Epilogue ep;
+                ep.a = -c2;
+                ep.z = xi;
+                ep.b = {rf.sigma[i], 0.0};
+                dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, q.p, ep, s);
+                axpby64({1.0, 0.0}, y.p, {1.0, 0.0}, q.p, n, s);
+                st->shift_residual[i] = norm_sync(ctx, q.p, n, false, s) / ynorm;
+                mx = std::max(mx, st->shift_residual[i]);
+            }
+            st->matvecs += 2 * ns;
+        }
+        st->residual = mx;
+        st->krylov_ms = kry_ms;
+        st->total_ms = ms_since(t_start);
+    }
+    return result;
+}
+
+}  // namespace
+
+}  // namespace sgn
+
+using namespace sgn;
+
+extern "C" sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *rf,
+                                       const sgn_ms_opts *o, sgn_stats *stats, void *stream)
+{
+    sgn_status worst = SGN_OK;
+    sgn_status st = guard([&] {
+        SGN_REQUIRE(pb && rf && o && nprob >= 0, "multishift_solve: null argument");
+        SGN_REQUIRE(rf->s >= 1 && rf->s <= SGN_MAX_POLES, "multishift_solve: bad number of poles");
+        SGN_REQUIRE(rf->c > 0 && std::isfinite(rf->c), "multishift_solve: bad scale c");
+        for (int i = 0; i < rf->s; ++i)
+            SGN_REQUIRE(rf->sigma[i] < 0 && std::isfinite(rf->omega[i]), "multishift_solve: shifts must be negative");
+        SGN_REQUIRE(o->tol > 0 && o->tol < 1, "multishift_solve: tol must be in (0, 1)");
+        for (int p = 0; p < nprob; ++p) {
+            SGN_REQUIRE(pb[p].lat && pb[p].b && pb[p].x, "multishift_solve: null problem field");
+            SGN_REQUIRE(std::isfinite(pb[p].mu), "multishift_solve: mu not finite");
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        for (int p = 0; p < nprob; ++p) {
+            const sgn_status r = solve_one(pb[p], *rf, *o, stats ? &stats[p] : nullptr, s);
+            if (r != SGN_OK && worst == SGN_OK) worst = r;
+        }
+    });
+    return st != SGN_OK ? st : worst;
+}

@@ -1,0 +1,210 @@
+// sign(T) e_1 for the small projected matrix of the direct two-sided Lanczos
+// method (section "Short recurrences": f(H_k) of the k x k projected matrix,
+// computed here through its eigendecomposition; cost O(k^3), the last term of
+// the cost proposition of the direct method).
+//
+// Route: complex Schur form T = Z S Z^H by the implicit single-shift QR
+// algorithm on the (tridiagonal, hence Hessenberg) input; eigenvectors of the
+// triangular S by back substitution; then
+//   sign(T) e_1 = Z X sign(Lambda) X^{-1} Z^H e_1,
+// where X (unit upper triangular) holds the eigenvectors of S.  Only O(k^2)
+// work besides the QR sweeps and the eigenvector back substitution.
+#include "small_sign.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <limits>
+#include <vector>
+
+namespace sgn {
+
+using zc = std::complex<double>;
+
+namespace {
+
+struct Mat {
+    int n;
+    std::vector<zc> a;  // row-major
+    explicit Mat(int n_) : n(n_), a((size_t)n_ * n_, zc(0, 0)) {}
+    zc &operator()(int i, int j) { return a[(size_t)i * n + j]; }
+    zc operator()(int i, int j) const { return a[(size_t)i * n + j]; }
+};
+
+inline double cabs1(zc z) { return std::abs(z.real()) + std::abs(z.imag()); }
+
+// Givens (c real, s complex) with G [x; y] = [r; 0], G = [[c, s], [-conj(s), c]].
+inline void givens(zc x, zc y, double &c, zc &s)
+{
+    const double ax = std::abs(x), ay = std::abs(y);
+    if (ay == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        return;
+    }
+    if (ax == 0.0) {
+        c = 0.0;
+        s = std::conj(y) / ay;
+        return;
+    }
+    const double nrm = std::hypot(ax, ay);
+    c = ax / nrm;
+    s = (x / ax) * std::conj(y) / nrm;
+}
+
+// Complex Schur decomposition of upper Hessenberg H (overwritten by S); Z accumulates.
+// Returns false if the iteration did not converge.
+bool hessenberg_schur(Mat &H, Mat &Z)
+{
+    const int n = H.n;
+    const double ulp = std::numeric_limits<double>::epsilon();
+    const double smallnum = std::numeric_limits<double>::min() * (n / ulp);
+    int ihi = n - 1;
+    int its = 0, total = 0;
+    const int max_total = 60 * std::max(n, 10);
+    while (ihi >= 0) {
+        // look for a negligible subdiagonal entry
+        int l = ihi;
+        for (; l > 0; --l) {
+            const double tst = cabs1(H(l - 1, l - 1)) + cabs1(H(l, l));
+            if (cabs1(H(l, l - 1)) <= std::max(ulp * tst, smallnum)) {
+                H(l, l - 1) = 0.0;
+                break;
+            }
+        }
+        if (l == ihi) {  // 1x1 block converged
+            --ihi;
+            its = 0;
+            continue;
+        }
+        if (++total > max_total) return false;
+        ++its;
+        // shift
+        zc sigma;
+        if (its % 11 == 10) {  // exceptional shift
+            sigma = H(ihi, ihi) + 0.75 * std::abs(H(ihi, ihi - 1).real());
+        } else {
+            const zc a = H(ihi - 1, ihi - 1), b = H(ihi - 1, ihi), c = H(ihi, ihi - 1), d = H(ihi, ihi);
+            const zc tr2 = 0.5 * (a + d);
+            const zc disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+            const zc e1 = tr2 + disc, e2 = tr2 - disc;
+            sigma = (std::abs(e1 - d) <= std::abs(e2 - d)) ? e1 : e2;
+        }
+        // implicit single-shift QR sweep on rows/columns l..ihi
+        for (int m = l; m < ihi; ++m) {
+            zc x, y;
+            if (m == l) {
+                x = H(l, l) - sigma;
+                y = H(l + 1, l);
+            } else {
+                x = H(m, m - 1);
+                y = H(m + 1, m - 1);
+            }
+            double c;
+            zc s;
+            givens(x, y, c, s);
+            // rows m, m+1  (all columns from the bulge column to the end: full Schur form)
+            for (int j = (m == l ? l : m - 1); j < n; ++j) {
+                const zc t1 = H(m, j), t2 = H(m + 1, j);
+                H(m, j) = c * t1 + s * t2;
+                H(m + 1, j) = -std::conj(s) * t1 + c * t2;
+            }
+            if (m > l) H(m + 1, m - 1) = 0.0;
+            // columns m, m+1
+            const int imax = std::min(m + 2, ihi);
+            for (int i = 0; i <= imax; ++i) {
+                const zc t1 = H(i, m), t2 = H(i, m + 1);
+                H(i, m) = t1 * c + t2 * std::conj(s);
+                H(i, m + 1) = -t1 * s + t2 * c;
+            }
+            for (int i = 0; i < n; ++i) {
+                const zc t1 = Z(i, m), t2 = Z(i, m + 1);
+                Z(i, m) = t1 * c + t2 * std::conj(s);
+                Z(i, m + 1) = -t1 * s + t2 * c;
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) H(i, j) = 0.0;
+    return true;
+}
+
+}  // namespace
+
+int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<double> *sub,
+                  const std::complex<double> *sup, std::complex<double> *y, SmallSignInfo *info)
+{
+    if (k <= 0) return 1;
+    Mat S(k), Z(k);
+    double tnorm = 0.0;
+    for (int i = 0; i < k; ++i) {
+        S(i, i) = diag[i];
+        if (i + 1 < k) {
+            S(i + 1, i) = sub[i];
+            S(i, i + 1) = sup[i];
+        }
+        Z(i, i) = 1.0;
+    }
+    for (int i = 0; i < k; ++i) {
+        double row = std::abs(diag[i]);
+        if (i + 1 < k) row += std::abs(sup[i]);
+        if (i > 0) row += std::abs(sub[i - 1]);
+        tnorm = std::max(tnorm, row);
+    }
+    if (!hessenberg_schur(S, Z)) return 2;
+    // eigenvalues and the imaginary-axis check
+    double minre = std::numeric_limits<double>::infinity();
+    std::vector<double> sgn(k);
+    for (int i = 0; i < k; ++i) {
+        const double re = S(i, i).real();
+        minre = std::min(minre, std::abs(re));
+        sgn[i] = re > 0 ? 1.0 : -1.0;
+    }
+    if (info) {
+        info->min_abs_re = minre;
+        info->norm = tnorm;
+    }
+    if (!(minre > 1e-12 * tnorm)) return 3;
+    // eigenvectors of S: X(:, i) with X(i, i) = 1, X(j > i, i) = 0
+    const double ulp = std::numeric_limits<double>::epsilon();
+    const double smin = std::max(ulp * tnorm, std::numeric_limits<double>::min());
+    Mat X(k);
+    double cond_est = 1.0;
+    for (int i = 0; i < k; ++i) {
+        X(i, i) = 1.0;
+        const zc lam = S(i, i);
+        for (int j = i - 1; j >= 0; --j) {
+            zc acc = 0.0;
+            for (int l = j + 1; l <= i; ++l) acc += S(j, l) * X(l, i);
+            zc den = S(j, j) - lam;
+            if (std::abs(den) < smin) den = smin;
+            X(j, i) = -acc / den;
+        }
+        double cn = 0.0;
+        for (int j = 0; j <= i; ++j) cn += std::norm(X(j, i));
+        cond_est = std::max(cond_est, std::sqrt(cn));
+    }
+    if (info) info->eigvec_growth = cond_est;
+    // q = Z^H e_1;  c = X^{-1} q (unit upper triangular back substitution)
+    std::vector<zc> c(k);
+    for (int i = 0; i < k; ++i) c[i] = std::conj(Z(0, i));
+    for (int i = k - 1; i >= 0; --i) {
+        zc acc = c[i];
+        for (int j = i + 1; j < k; ++j) acc -= X(i, j) * c[j];
+        c[i] = acc;
+    }
+    // u = X sign(Lambda) c ; y = Z u
+    std::vector<zc> u(k, zc(0, 0));
+    for (int j = 0; j < k; ++j) {
+        const zc cj = sgn[j] * c[j];
+        for (int i = 0; i <= j; ++i) u[i] += X(i, j) * cj;
+    }
+    for (int i = 0; i < k; ++i) {
+        zc acc = 0.0;
+        for (int j = 0; j < k; ++j) acc += Z(i, j) * u[j];
+        y[i] = acc;
+    }
+    return 0;
+}
+
+}  // namespace sgn

@@ -1,0 +1,53 @@
+// Level-1 vector kernels with deterministic FP64 reductions.
+//
+// Vectors are flat arrays of complex numbers (the internal spinor layouts are
+// flat complex arrays of length 12 V as far as element-wise work is
+// concerned).  A reduction is two launches: a producer that writes one
+// partial sum per block (grid-stride, at most kMaxBlocks blocks) and a 1-block
+// finalize that adds them in block order -- the same result on every run.
+#pragma once
+
+#include "sgn_internal.h"
+
+namespace sgn {
+
+constexpr int kVecThreads = 256;
+constexpr int kMaxBlocks = 1024;
+
+int vec_blocks(int64_t n);
+
+// partials[b] = sum over the block's elements of conj(x) * y (complex128 / complex64 inputs)
+int dot_partials(const void *x, const void *y, int64_t n, bool f32, z64 *partials, hipStream_t s);
+// partials[b] = sum |x|^2 (stored in .r)
+int norm2_partials(const void *x, int64_t n, bool f32, z64 *partials, hipStream_t s);
+// out[0] = sum_b partials[b]   (device)
+void finalize_sum(const z64 *partials, int nblk, z64 *out, hipStream_t s);
+// blocking FP64 dot (host result) -- setup paths only
+z64 dot_sync(Context &ctx, const void *x, const void *y, int64_t n, bool f32, hipStream_t s);
+double norm_sync(Context &ctx, const void *x, int64_t n, bool f32, hipStream_t s);
+
+// y = a * x + b * y  (complex128, host scalars)
+void axpby64(z64 a, const void *x, z64 b, void *y, int64_t n, hipStream_t s);
+// y = a * x  (complex128)
+void scale64(z64 a, const void *x, void *y, int64_t n, hipStream_t s);
+
+// precision conversion between the internal FP64 ([12][V] double2) and FP32 ([6][V] float4) spinor layouts
+void convert_64_to_32(const void *x64, void *x32, int64_t V, hipStream_t s);
+void convert_32_to_64(const void *x32, void *x64, int64_t V, hipStream_t s);
+
+// LR deflation on canonical complex128 vectors of length n, with m vectors
+// stored back to back (X + i*n):
+//   c[i] = X_i^H y                              (deflate_dots, c on device)
+//   y = alpha * y + beta * sum_i X_i (d_i c[i])  (deflate_combine; d on device or null = 1)
+void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s);
+void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
+                     int64_t n, hipStream_t s);
+
+// LR-deflation prologue shared by the solvers (canonical complex128 vectors):
+// x = x_P = R sign(Lambda) L^H b, r = (I - R L^H) b and, if rt != nullptr, the
+// modified shadow vector rt = (I - L R^H) b.  Null x / r skip that output.
+// Synchronises the stream.
+void deflation_prologue(Context &ctx, const sgn_deflation *defl, int64_t n, const void *b, void *x, void *r,
+                        void *rt, hipStream_t s);
+
+}  // namespace sgn

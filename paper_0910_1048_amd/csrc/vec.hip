@@ -1,0 +1,260 @@
+// Level-1 vector kernels, deterministic FP64 reductions, precision conversion
+// and the LR-deflation projections.  All of these are HBM-bound streaming
+// kernels: grid-stride loops over at most kMaxBlocks blocks of 256 threads.
+#include "vec.h"
+
+#include "field_io.h"
+
+namespace sgn {
+
+int vec_blocks(int64_t n)
+{
+    int64_t b = (n + kVecThreads - 1) / kVecThreads;
+    if (b < 1) b = 1;
+    return (int)(b < kMaxBlocks ? b : kMaxBlocks);
+}
+
+namespace {
+
+__device__ __forceinline__ z64 ld64(const void *p, int64_t i)
+{
+    double2 t = static_cast<const double2 *>(p)[i];
+    return {t.x, t.y};
+}
+
+__device__ __forceinline__ z64 ld32(const void *p, int64_t i)
+{
+    float2 t = static_cast<const float2 *>(p)[i];
+    return {(double)t.x, (double)t.y};
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(256) dot_kernel(const void *x, const void *y, int64_t n, z64 *partials)
+{
+    double re = 0.0, im = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        z64 a = F32 ? ld32(x, i) : ld64(x, i);
+        z64 b = F32 ? ld32(y, i) : ld64(y, i);
+        re += a.r * b.r + a.i * b.i;
+        im += a.r * b.i - a.i * b.r;
+    }
+    __shared__ double lds[8];
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = {v[0], v[1]};
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(256) norm2_kernel(const void *x, int64_t n, z64 *partials)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        z64 a = F32 ? ld32(x, i) : ld64(x, i);
+        acc += a.r * a.r + a.i * a.i;
+    }
+    __shared__ double lds[4];
+    double v[1] = {acc};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = {v[0], 0.0};
+}
+
+// sum partials in block order (one block; threads take strided slices, then a fixed-order combine)
+__global__ void __launch_bounds__(256) finalize_kernel(const z64 *partials, int nblk, z64 *out)
+{
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        re += partials[i].r;
+        im += partials[i].i;
+    }
+    __shared__ double lds[8];
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) *out = {v[0], v[1]};
+}
+
+__global__ void axpby64_kernel(z64 a, const double2 *x, z64 b, double2 *y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 xv = x[i], yv = y[i];
+        z64 r = a * z64{xv.x, xv.y} + b * z64{yv.x, yv.y};
+        y[i] = make_double2(r.r, r.i);
+    }
+}
+
+__global__ void scale64_kernel(z64 a, const double2 *x, double2 *y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 xv = x[i];
+        z64 r = a * z64{xv.x, xv.y};
+        y[i] = make_double2(r.r, r.i);
+    }
+}
+
+__global__ void cvt64to32(const double2 *__restrict__ x, float4 *__restrict__ y, int V)
+{
+    const int64_t n = (int64_t)6 * V;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(p / V), s = (int)(p - (int64_t)c2 * V);
+        double2 a = x[(int64_t)(2 * c2) * V + s], b = x[(int64_t)(2 * c2 + 1) * V + s];
+        y[p] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+    }
+}
+
+__global__ void cvt32to64(const float4 *__restrict__ x, double2 *__restrict__ y, int V)
+{
+    const int64_t n = (int64_t)6 * V;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(p / V), s = (int)(p - (int64_t)c2 * V);
+        float4 t = x[p];
+        y[(int64_t)(2 * c2) * V + s] = make_double2(t.x, t.y);
+        y[(int64_t)(2 * c2 + 1) * V + s] = make_double2(t.z, t.w);
+    }
+}
+
+// grid (nbx, m): partials[i * nbx + bx] = sum conj(X_i) y over the block's slice
+__global__ void __launch_bounds__(256) mdot_kernel(const double2 *X, const double2 *y, int64_t n, z64 *partials)
+{
+    const int i = blockIdx.y;
+    const double2 *xi = X + (int64_t)i * n;
+    double re = 0.0, im = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 a = xi[e], b = y[e];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    __shared__ double lds[8];
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = {v[0], v[1]};
+}
+
+__global__ void __launch_bounds__(256) mfinalize_kernel(const z64 *partials, int nbx, z64 *out)
+{
+    const int i = blockIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int b = threadIdx.x; b < nbx; b += blockDim.x) {
+        re += partials[(int64_t)i * nbx + b].r;
+        im += partials[(int64_t)i * nbx + b].i;
+    }
+    __shared__ double lds[8];
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) out[i] = {v[0], v[1]};
+}
+
+__global__ void mcombine_kernel(double2 *y, z64 alpha, z64 beta, const double2 *X, int m, const z64 *c,
+                                const z64 *d, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 acc = {0.0, 0.0};
+        for (int i = 0; i < m; ++i) {
+            z64 ci = c[i];
+            if (d) ci = d[i] * ci;
+            double2 xv = X[(int64_t)i * n + e];
+            acc = acc + z64{xv.x, xv.y} * ci;
+        }
+        double2 yv = y[e];
+        z64 r = alpha * z64{yv.x, yv.y} + beta * acc;
+        y[e] = make_double2(r.r, r.i);
+    }
+}
+
+}  // namespace
+
+int dot_partials(const void *x, const void *y, int64_t n, bool f32, z64 *partials, hipStream_t s)
+{
+    const int nb = vec_blocks(n);
+    if (f32)
+        hipLaunchKernelGGL(dot_kernel<true>, dim3(nb), dim3(256), 0, s, x, y, n, partials);
+    else
+        hipLaunchKernelGGL(dot_kernel<false>, dim3(nb), dim3(256), 0, s, x, y, n, partials);
+    SGN_HIP(hipGetLastError());
+    return nb;
+}
+
+int norm2_partials(const void *x, int64_t n, bool f32, z64 *partials, hipStream_t s)
+{
+    const int nb = vec_blocks(n);
+    if (f32)
+        hipLaunchKernelGGL(norm2_kernel<true>, dim3(nb), dim3(256), 0, s, x, n, partials);
+    else
+        hipLaunchKernelGGL(norm2_kernel<false>, dim3(nb), dim3(256), 0, s, x, n, partials);
+    SGN_HIP(hipGetLastError());
+    return nb;
+}
+
+void finalize_sum(const z64 *partials, int nblk, z64 *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nblk, out);
+    SGN_HIP(hipGetLastError());
+}
+
+z64 dot_sync(Context &ctx, const void *x, const void *y, int64_t n, bool f32, hipStream_t s)
+{
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials((kMaxBlocks + 1) * sizeof(z64)));
+    const int nb = dot_partials(x, y, n, f32, part, s);
+    finalize_sum(part, nb, part + kMaxBlocks, s);
+    z64 h;
+    SGN_HIP(hipMemcpyAsync(&h, part + kMaxBlocks, sizeof(z64), hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+double norm_sync(Context &ctx, const void *x, int64_t n, bool f32, hipStream_t s)
+{
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials((kMaxBlocks + 1) * sizeof(z64)));
+    const int nb = norm2_partials(x, n, f32, part, s);
+    finalize_sum(part, nb, part + kMaxBlocks, s);
+    z64 h;
+    SGN_HIP(hipMemcpyAsync(&h, part + kMaxBlocks, sizeof(z64), hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    return std::sqrt(h.r);
+}
+
+void axpby64(z64 a, const void *x, z64 b, void *y, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(axpby64_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, a, (const double2 *)x, b,
+                       (double2 *)y, n);
+    SGN_HIP(hipGetLastError());
+}
+
+void scale64(z64 a, const void *x, void *y, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(scale64_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, a, (const double2 *)x,
+                       (double2 *)y, n);
+    SGN_HIP(hipGetLastError());
+}
+
+void convert_64_to_32(const void *x64, void *x32, int64_t V, hipStream_t s)
+{
+    hipLaunchKernelGGL(cvt64to32, dim3(vec_blocks(6 * V)), dim3(256), 0, s, (const double2 *)x64, (float4 *)x32,
+                       (int)V);
+    SGN_HIP(hipGetLastError());
+}
+
+void convert_32_to_64(const void *x32, void *x64, int64_t V, hipStream_t s)
+{
+    hipLaunchKernelGGL(cvt32to64, dim3(vec_blocks(6 * V)), dim3(256), 0, s, (const float4 *)x32, (double2 *)x64,
+                       (int)V);
+    SGN_HIP(hipGetLastError());
+}
+
+void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s)
+{
+    if (m <= 0) return;
+    const int nbx = std::max(1, std::min(64, vec_blocks(n)));
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)m * nbx * sizeof(z64)));
+    hipLaunchKernelGGL(mdot_kernel, dim3(nbx, m), dim3(256), 0, s, (const double2 *)X, (const double2 *)y, n, part);
+    hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, c_dev);
+    SGN_HIP(hipGetLastError());
+}
+
+void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
+                     int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(mcombine_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, (double2 *)y, alpha, beta,
+                       (const double2 *)X, m, c_dev, d_dev, n);
+    SGN_HIP(hipGetLastError());
+}
+
+}  // namespace sgn

@@ -1,0 +1,46 @@
+"""Write the stored expected values under tests/golden/ (calls only oracle/ and synth/).
+
+    python tests/golden/make_golden.py
+
+c1_dense.npz -- the 4^4 configuration (links eps = 0.5, seed 0; kappa = 0.2,
+    mu = 0.3; Gaussian source of seed 0):
+      sign_b   sign(H_W) b from the eigendecomposition of the dense H_W
+               (definition f(A) = R f(Lambda) R^{-1}, sign z = sign Re z;
+               introduction, Eqs. (1), (matfun_action))
+      g16_b    g_16(cA) b, the 16-pole Neuberger approximation (Eq. (pfe_s))
+               with c from the spectral-circle heuristic through the smallest
+               and largest eigenvalue moduli (numerical-results section)
+      alpha, beta  smallest / largest |lambda| of H_W
+      evals    all eigenvalues of H_W
+Dense n = 3072 eigendecomposition: about a minute on 8 cores.
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import WilsonRef, dense, rational  # noqa: E402
+
+
+def c1():
+    dims, eps, seed, kappa, mu = (4, 4, 4, 4), 0.5, 0, 0.2, 0.3
+    U = synth.gauge_field(dims, eps, seed)
+    b = synth.gaussian_source(dims, seed).ravel()
+    H = WilsonRef(U, dims, kappa).dense(mu)
+    evals = np.linalg.eigvals(H)
+    alpha, beta = float(np.abs(evals).min()), float(np.abs(evals).max())
+    sign_b = dense.sign_eig(H, b)
+    om, sg, c = rational.coefficients(16, alpha, beta)
+    g16_b = dense.rational_dense(H, b, om, sg, c)
+    np.savez_compressed(os.path.join(HERE, "c1_dense.npz"), sign_b=sign_b, g16_b=g16_b, alpha=alpha,
+                        beta=beta, evals=evals)
+    print("c1: alpha", alpha, "beta", beta, "|g16 - sign| / |sign|",
+          np.linalg.norm(g16_b - sign_b) / np.linalg.norm(sign_b))
+
+
+if __name__ == "__main__":
+    c1()

@@ -30,3 +30,22 @@ def test_library_is_gfx950_code_object():
     # the offload bundle inside the host library names the target
     data = open(sgn.LIB_PATH, "rb").read()
     assert b"gfx950" in data
+
+
+def test_rational_coefficients_match_oracle():
+    """Host-only library calls (no GPU): Eq. (pfe_s) coefficients, the scale c of
+    the spectral-circle heuristic and the pole count of Eq. (no_of_poles)."""
+    from oracle import rational
+    for s, a, b in ((16, 0.185, 2.385), (8, 0.3, 1.0), (70, 0.01, 2.6)):
+        r = sgn.sgn_rational_neuberger(s, a, b)
+        om, sg, c = rational.coefficients(s, a, b)
+        assert abs(r.c - c) <= 1e-15 * c
+        assert max(abs(r.omega[i] - om[i]) / om[i] for i in range(s)) < 1e-14
+        assert max(abs(r.sigma[i] - sg[i]) / abs(sg[i]) for i in range(s)) < 1e-13
+    for a, b, eps in ((0.185, 2.385, 1e-8), (0.05, 2.6, 1e-10), (0.3, 0.6, 1e-4)):
+        assert sgn.sgn_poles_needed(a, b, eps) == rational.poles_needed(a, b, eps)
+    import pytest
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_rational_neuberger(0, 0.1, 1.0)
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_rational_neuberger(8, 1.0, 0.5)
