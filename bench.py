@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark: sign(H_W) b on one MI355X.
+
+One step = one evaluation of sign(H_W(mu)) b for H_W = gamma5 D_W(mu) on a
+24^3 x 48 lattice through the 16-pole Neuberger rational function, by the
+multishift BiCG-LR solver with the mixed-precision schedule (FP64 -> FP32 ->
+FP16 links, FP64 reliable updates): libsgn's multishift_solve.  Inputs (gauge
+links, source, coefficients) are resident in HBM before the timed region.
+
+Reported beside it on the same GPU: the plain FP64 single-RHS form of the same
+solve (solves/s), the error of the mixed result against an FP64 solve to
+tolerance 1e-12, the live per-kernel timing of the solver's own launches (HIP
+events on the launch stream) as HBM roofline fractions, and the CPU oracle
+timed on this host's cores on a bounded sample of the same solve.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.4, seed=0, kappa=0.2, mu=0.2, poles=16,
+                alpha=0.12, beta=2.6, tol=1e-9)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the solver path is single-GPU "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_0910_1048_amd as sgn
+
+    W = WORKLOAD
+    dims = W["dims"]
+    log(f"[bench] generating 24^3x48 links (eps={W['eps']}, seed={W['seed']}) and source")
+    U = synth.gauge_field(dims, W["eps"], W["seed"])
+    b = synth.gaussian_source(dims, W["seed"])
+    ctx = sgn.Context(0)
+    lat = sgn.Lattice(ctx, torch.from_numpy(U).cuda(), dims, W["kappa"])
+    bd = torch.from_numpy(b).cuda()
+    x = torch.empty_like(bd)
+    rf = sgn.sgn_rational_neuberger(W["poles"], W["alpha"], W["beta"])
+    prob = sgn.Problem(lat, W["mu"], bd, x)
+
+    def solve(prec, tol, p=prob):
+        return sgn.multishift_solve(p, rf, tol=tol, prec=prec)[0]
+
+    # FP64 reference solution (untimed) for the accuracy of every timed result
+    log("[bench] FP64 reference solve (tol 1e-12)")
+    xref_t = torch.empty_like(bd)
+    st_ref = solve(sgn.F64, 1e-12, sgn.Problem(lat, W["mu"], bd, xref_t))
+    xref = xref_t.cpu().numpy()
+
+    # ---- headline: mixed precision
+    for _ in range(args.warmup):
+        solve(sgn.F32_H16, W["tol"])
+    torch.cuda.synchronize()
+    sgn.sgn_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        stats.append(solve(sgn.F32_H16, W["tol"]))
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    prof = sgn.sgn_profile_read(ctx)
+    sgn.sgn_profile_enable(ctx, False)
+    err_mixed = float(np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref))
+    value = args.steps / t_mixed
+    log(f"[bench] mixed: {t_mixed / args.steps * 1e3:.1f} ms/solve, {stats[-1]['iterations']} iterations, "
+        f"{stats[-1]['reliable_updates']} reliable updates, err vs FP64 {err_mixed:.2e}")
+
+    # ---- plain FP64 single-RHS form of the same solve
+    solve(sgn.F64, W["tol"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st64 = None
+    for _ in range(args.fp64_steps):
+        st64 = solve(sgn.F64, W["tol"])
+    torch.cuda.synchronize()
+    t64 = (time.perf_counter() - t0) / args.fp64_steps
+    err64 = float(np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref))
+    log(f"[bench] fp64: {t64 * 1e3:.1f} ms/solve, {st64['iterations']} iterations, err {err64:.2e}")
+
+    # ---- roofline: dominant kernel by time, and the stencil (Dslash) itself
+    def roof(name):
+        p = prof[name]
+        ach = p["bytes"] / (p["total_ms"] * 1e-3) / 1e9 if p["total_ms"] > 0 else 0.0
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "launches": p["launches"], "avg_launch_us": round(p["total_ms"] * 1e3 / max(p["launches"], 1), 2),
+                "bytes_per_launch": p["bytes"] / max(p["launches"], 1)}
+    dominant = max(prof, key=lambda k: prof[k]["total_ms"])
+    roofline = roof(dominant)
+    stencils = {k: roof(k) for k in ("stencil_f64", "stencil_f32", "stencil_h16") if prof[k]["launches"]}
+    time_share = {k: round(v["total_ms"] / (t_mixed * 1e3), 4) for k, v in prof.items() if v["launches"]}
+
+    # ---- CPU oracle on this host, bounded sample of the same solve
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import WilsonRef, krylov, rational, wilson
+        Wr = WilsonRef(U, dims, W["kappa"])
+        om, sg, c = rational.coefficients(W["poles"], W["alpha"], W["beta"])
+        A = lambda v: Wr.apply(v, W["mu"])
+        Ah = lambda v: Wr.apply_adj(v, W["mu"])
+        bf = b.ravel()
+        ts = []
+        for it in (1, 3):
+            t0 = time.perf_counter()
+            krylov.multishift_bicg(A, Ah, bf, om, sg, c, tol=1e-30, maxiter=it)
+            ts.append(time.perf_counter() - t0)
+        per_it = (ts[1] - ts[0]) / 2
+        est = ts[0] + (st64["iterations"] - 1) * per_it
+        cpu = {"value": round(1.0 / est, 6), "unit": "solves/s", "cores": wilson.get_threads(), "kind": "oracle",
+               "sample": f"oracle multishift BiCG (FP64, 16 poles) on the same 24^3x48 problem, run for 1 and 3 "
+                         f"iterations ({ts[0]:.1f} s, {ts[1]:.1f} s); per-iteration cost extrapolated to the "
+                         f"{st64['iterations']} iterations of the FP64 GPU solve"}
+        log(f"[bench] cpu oracle: {per_it:.2f} s/iteration -> {est:.0f} s/solve")
+
+    out = {
+        "metric": "Dslash HBM GB/s (%peak); sign(H_W)b solves/s at 1e-8 rel err, mixed vs FP64",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_mixed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sign(H_W)b, 24^3x48, 16-pole Neuberger rational via multishift BiCG-LR, "
+                               "mixed FP64->FP32->FP16-link schedule with FP64 reliable updates",
+                   "lattice": list(dims), "kappa": W["kappa"], "mu": W["mu"], "link_eps": W["eps"],
+                   "poles": W["poles"], "alpha": W["alpha"], "beta": W["beta"], "tol": W["tol"],
+                   "deflation_m": 0, "rhs": 1},
+        "err_vs_fp64_ref": err_mixed,
+        "iterations": stats[-1]["iterations"],
+        "reliable_updates": stats[-1]["reliable_updates"],
+        "fp64_solves_per_s": round(1.0 / t64, 4),
+        "fp64_err_vs_ref": err64,
+        "speedup_vs_fp64": round(value * t64, 3),
+        "roofline": roofline,
+        "stencil_roofline": stencils,
+        "kernel_time_share": time_share,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

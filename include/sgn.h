@@ -219,6 +219,33 @@ typedef struct {
 sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                             sgn_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------ profiling */
+/* Per-kernel-class timing of the library's own launches, measured with HIP
+ * events recorded on the launch stream around each launch, together with the
+ * algorithmic HBM bytes (every input read once, every output written once)
+ * and flops of each launch.  Meant for roofline reporting; adds one event
+ * pair per profiled launch. */
+typedef enum {
+    SGN_K_STENCIL_F64 = 0,
+    SGN_K_STENCIL_F32 = 1,
+    SGN_K_STENCIL_H16 = 2,
+    SGN_K_SHIFT_UPDATE = 3,   /* multishift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i */
+    SGN_K_SEED_UPDATE = 4,    /* multishift: r, r~ updates with their inner products */
+    SGN_K_COUNT = 5
+} sgn_kernel_class;
+
+typedef struct {
+    long long launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} sgn_kernel_profile;
+
+/* enable != 0 starts (and resets) profiling on this context; 0 stops it. */
+sgn_status sgn_profile_enable(sgn_handle h, int enable);
+/* Waits for the recorded launches and fills out[SGN_K_COUNT]. */
+sgn_status sgn_profile_read(sgn_handle h, sgn_kernel_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

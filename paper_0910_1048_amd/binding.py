@@ -275,3 +275,27 @@ def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, the
     st = (Stats * max(n, 1))()
     check(lib.multishift_solve(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_solve")
     return [st[i].as_dict() for i in range(n)]
+
+
+K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_H16, K_SHIFT_UPDATE, K_SEED_UPDATE, K_COUNT = range(6)
+KERNEL_NAMES = ["stencil_f64", "stencil_f32", "stencil_h16", "shift_update", "seed_update"]
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+lib.sgn_profile_enable.argtypes = [_vp, C.c_int]
+lib.sgn_profile_read.argtypes = [_vp, C.POINTER(KernelProfile)]
+
+
+def sgn_profile_enable(ctx, enable=True):
+    check(lib.sgn_profile_enable(ctx.h, int(bool(enable))), "sgn_profile_enable")
+
+
+def sgn_profile_read(ctx):
+    """{kernel class name: {launches, total_ms, bytes, flops}} of the launches since enable."""
+    arr = (KernelProfile * K_COUNT)()
+    check(lib.sgn_profile_read(ctx.h, arr), "sgn_profile_read")
+    return {KERNEL_NAMES[i]: {"launches": arr[i].launches, "total_ms": arr[i].total_ms, "bytes": arr[i].bytes,
+                              "flops": arr[i].flops} for i in range(K_COUNT)}

@@ -284,6 +284,13 @@ int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *
     const bool epi = dot || ep.z != nullptr || ep.a != 1.0 || ep.in_scale != nullptr;
     if (dot && !ep.partials) throw Failure{SGN_ERR_INVALID, "stencil dot without partial buffer"};
     const int nblk = dslash_blocks(lat);
+    // algorithmic bytes: in and out spinors once, the 4 links of each site once,
+    // plus the epilogue operands; 1368 flop per site for the stencil itself
+    const double sb = (p == SGN_PREC_F64) ? 192.0 : 96.0;
+    const double lb = (p == SGN_PREC_F64) ? 144.0 : (p == SGN_PREC_F32 ? 72.0 : 36.0);
+    const double site_bytes = 2 * sb + 4 * lb + (ep.z ? sb : 0.0) + (dot ? sb : 0.0);
+    const double site_flops = 1368.0 + (epi ? 24.0 : 0.0) + (ep.z ? 96.0 : 0.0) + (dot ? 96.0 : 0.0);
+    const int prof = lat.ctx->prof_start(s);
     switch (p) {
     case SGN_PREC_F64:
         if (!lat.links64) throw Failure{SGN_ERR_INVALID, "lattice has no FP64 links"};
@@ -304,6 +311,8 @@ int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *
         throw Failure{SGN_ERR_INVALID, "unknown precision"};
     }
     SGN_HIP(hipGetLastError());
+    lat.ctx->prof_stop(prof, s, p == SGN_PREC_F64 ? SGN_K_STENCIL_F64 : (p == SGN_PREC_F32 ? SGN_K_STENCIL_F32 : SGN_K_STENCIL_H16),
+                       site_bytes * lat.V, site_flops * lat.V);
     return nblk;
 }
 

@@ -39,6 +39,19 @@ void *Context::ensure_scalars(size_t bytes)
     return scalars;
 }
 
+void *Context::ensure_arena(size_t bytes)
+{
+    if (bytes > arena_bytes) {
+        SGN_HIP(hipDeviceSynchronize());
+        if (arena) SGN_HIP(hipFree(arena));
+        arena = nullptr;
+        arena_bytes = 0;
+        if (hipMalloc(&arena, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "solver workspace"};
+        arena_bytes = bytes;
+    }
+    return arena;
+}
+
 void Lattice::ensure_stage(size_t bytes)
 {
     if (bytes <= stage_bytes) return;
@@ -182,6 +195,13 @@ extern "C" sgn_status sgn_finalize(sgn_handle h)
         SGN_HIP(hipSetDevice(c->device));
         if (c->partials) SGN_HIP(hipFree(c->partials));
         if (c->scalars) SGN_HIP(hipFree(c->scalars));
+        if (c->arena) SGN_HIP(hipFree(c->arena));
+        if (c->byte_counter) SGN_HIP(hipFree(c->byte_counter));
+        for (auto &r : c->prof_recs) {
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+        for (auto e : c->event_pool) (void)hipEventDestroy(e);
         delete c;
     });
 }
@@ -270,5 +290,99 @@ extern "C" sgn_status sgn_spinor_unpack(sgn_lattice l, const void *internal, voi
         Lattice &lat = *as_lattice(l);
         SGN_HIP(hipSetDevice(lat.ctx->device));
         unpack_spinor(lat, internal, canon, p, static_cast<hipStream_t>(stream));
+    });
+}
+
+// ----------------------------------------------------------------------------- profiling
+namespace sgn {
+
+int Context::prof_start(hipStream_t s)
+{
+    if (!prof) return -1;
+    ProfRec r{};
+    for (hipEvent_t *e : {&r.start, &r.stop}) {
+        if (!event_pool.empty()) {
+            *e = event_pool.back();
+            event_pool.pop_back();
+        } else {
+            SGN_HIP(hipEventCreate(e));
+        }
+    }
+    SGN_HIP(hipEventRecord(r.start, s));
+    prof_recs.push_back(r);
+    return (int)prof_recs.size() - 1;
+}
+
+void Context::prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes)
+{
+    if (rec < 0) return;
+    ProfRec &r = prof_recs[rec];
+    r.cls = cls;
+    r.bytes = bytes;
+    r.flops = flops;
+    r.device_bytes = device_bytes;
+    SGN_HIP(hipEventRecord(r.stop, s));
+}
+
+void Context::prof_collect()
+{
+    for (ProfRec &r : prof_recs) {
+        SGN_HIP(hipEventSynchronize(r.stop));
+        float ms = 0.f;
+        SGN_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        acc_ms[r.cls] += ms;
+        acc_bytes[r.cls] += r.bytes;
+        acc_flops[r.cls] += r.flops;
+        acc_launches[r.cls] += 1;
+        event_pool.push_back(r.start);
+        event_pool.push_back(r.stop);
+    }
+    prof_recs.clear();
+    if (byte_counter) {
+        unsigned long long b = 0;
+        SGN_HIP(hipMemcpy(&b, byte_counter, sizeof(b), hipMemcpyDeviceToHost));
+        acc_bytes[SGN_K_SHIFT_UPDATE] += (double)b;
+        const unsigned long long z = 0;
+        SGN_HIP(hipMemcpy(byte_counter, &z, sizeof(z), hipMemcpyHostToDevice));
+    }
+}
+
+}  // namespace sgn
+
+extern "C" sgn_status sgn_profile_enable(sgn_handle h, int enable)
+{
+    return guard([&] {
+        SGN_REQUIRE(h != nullptr, "sgn_profile_enable: null handle");
+        auto *c = reinterpret_cast<Context *>(h);
+        SGN_HIP(hipSetDevice(c->device));
+        SGN_HIP(hipDeviceSynchronize());
+        c->prof_collect();
+        for (int k = 0; k < SGN_K_COUNT; ++k) {
+            c->acc_ms[k] = c->acc_bytes[k] = c->acc_flops[k] = 0.0;
+            c->acc_launches[k] = 0;
+        }
+        if (enable && !c->byte_counter) {
+            if (hipMalloc(&c->byte_counter, sizeof(unsigned long long)) != hipSuccess)
+                throw Failure{SGN_ERR_NOMEM, "profiling counter"};
+            const unsigned long long z = 0;
+            SGN_HIP(hipMemcpy(c->byte_counter, &z, sizeof(z), hipMemcpyHostToDevice));
+        }
+        c->prof = enable != 0;
+    });
+}
+
+extern "C" sgn_status sgn_profile_read(sgn_handle h, sgn_kernel_profile *out)
+{
+    return guard([&] {
+        SGN_REQUIRE(h != nullptr && out != nullptr, "sgn_profile_read: null argument");
+        auto *c = reinterpret_cast<Context *>(h);
+        SGN_HIP(hipSetDevice(c->device));
+        c->prof_collect();
+        for (int k = 0; k < SGN_K_COUNT; ++k) {
+            out[k].launches = c->acc_launches[k];
+            out[k].total_ms = c->acc_ms[k];
+            out[k].bytes = c->acc_bytes[k];
+            out[k].flops = c->acc_flops[k];
+        }
     });
 }

@@ -217,7 +217,8 @@ __global__ void __launch_bounds__(256) ms_seed_update(typename VecT<R>::t *r, ty
 template <typename R, typename XT>
 __global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, XT *X, const typename VecT<R>::t *r,
                                                        const typename VecT<R>::t *rt, typename VecT<R>::t *pt,
-                                                       int64_t n, const MsState *S, int expect)
+                                                       int64_t n, const MsState *S, int expect,
+                                                       unsigned long long *byte_counter)
 {
     // apply only if this iteration's beta step ran (it may have just declared convergence;
     // later launches of a polling chunk after convergence must not repeat the update)
@@ -232,7 +233,15 @@ __global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, X
         be_s[i] = S->beta_i[i];
         ze_s[i] = S->zeta[i];
     }
-    if (threadIdx.x == 0) ns = nsh;
+    if (threadIdx.x == 0) {
+        ns = nsh;
+        if (byte_counter && blockIdx.x == 0) {  // algorithmic bytes of this launch (profiling)
+            int na = 0;
+            for (int i = 0; i < nsh; ++i) na += S->act[i] ? 1 : 0;
+            const unsigned long long eb = sizeof(typename VecT<R>::t), xb = sizeof(XT);
+            atomicAdd(byte_counter, (unsigned long long)n * (4ull * eb + (unsigned long long)na * (2ull * eb + 2ull * xb)));
+        }
+    }
     __syncthreads();
     const z64 bc = conj(S->h.beta);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -364,6 +373,11 @@ struct DevMem {
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+struct Span {
+    void *p;
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
 double ms_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -387,19 +401,26 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed])) seed = i;
     const double s1 = rf.sigma[seed];
 
-    // x <- x_P, r = (I - P) b (canonical)
-    DevMem rcan(b64);
-    deflation_prologue(ctx, pb.defl, n, pb.b, pb.x, rcan.p, nullptr, s);
+    // workspace carved from the context's arena (kept between calls)
+    const size_t a64 = (9 + 2 * (size_t)ns) * b64, a32 = mixed ? (7 + 2 * (size_t)ns) * b32 : 0;
+    char *arena = static_cast<char *>(ctx.ensure_arena(a64 + a32 + sizeof(MsState)));
+    auto carve = [&](size_t bytes) {
+        Span sp{arena};
+        arena += bytes;
+        return sp;
+    };
+    Span y = carve(b64), r = carve(b64), rt = carve(b64), pt = carve(b64), q = carve(b64), qt = carve(b64),
+         tmp = carve(b64), tmpt = carve(b64);
+    Span X = carve((size_t)ns * b64), P = carve((size_t)ns * b64);
+    Span r32 = carve(mixed ? b32 : 0), rt32 = carve(mixed ? b32 : 0), pt32 = carve(mixed ? b32 : 0),
+         q32 = carve(mixed ? b32 : 0), qt32 = carve(mixed ? b32 : 0), tmp32 = carve(mixed ? b32 : 0),
+         tmpt32 = carve(mixed ? b32 : 0);
+    Span P32 = carve(mixed ? (size_t)ns * b32 : 0), Xlo = carve(mixed ? (size_t)ns * b32 : 0);
+    MsState *S = carve(sizeof(MsState)).as<MsState>();
+    Span rcan = carve(b64);
 
-    // FP64 workspace
-    DevMem y(b64), r(b64), rt(b64), pt(b64), q(b64), qt(b64), tmp(b64), tmpt(b64);
-    DevMem X((size_t)ns * b64), P((size_t)ns * b64);
-    // FP32 workspace (mixed)
-    DevMem r32(mixed ? b32 : 0), rt32(mixed ? b32 : 0), pt32(mixed ? b32 : 0), q32(mixed ? b32 : 0),
-        qt32(mixed ? b32 : 0), tmp32(mixed ? b32 : 0), tmpt32(mixed ? b32 : 0);
-    DevMem P32(mixed ? (size_t)ns * b32 : 0), Xlo(mixed ? (size_t)ns * b32 : 0);
-    DevMem Sd(sizeof(MsState));
-    MsState *S = Sd.as<MsState>();
+    // x <- x_P, r = (I - P) b (canonical)
+    deflation_prologue(ctx, pb.defl, n, pb.b, pb.x, rcan.p, nullptr, s);
 
     OpSpec opA, opAh;
     opA.mu = pb.mu;
@@ -482,21 +503,27 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
             e2.b = {-sigma_seed, 0.0};
             dslash_launch(lat, sp, opAh, vtmpt, vqt, e2, s);
             hipLaunchKernelGGL(ms_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S);
-            if (lo) {
+            unsigned long long *bc = ctx.prof ? ctx.byte_counter : nullptr;
+            const double eb = lo ? 8.0 : 16.0;
+            int pr = ctx.prof_start(s);
+            if (lo)
                 hipLaunchKernelGGL(ms_seed_update<float>, dim3(nvb), dim3(256), 0, s, (float2 *)vr, (float2 *)vrt,
                                    (const float2 *)vq, (const float2 *)vqt, n, S, part);
-                hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
-                hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(nvb), dim3(256), 0, s, P32.as<float2>(),
-                                   Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt, (float2 *)vpt, n, S,
-                                   launched);
-            } else {
+            else
                 hipLaunchKernelGGL(ms_seed_update<double>, dim3(nvb), dim3(256), 0, s, (double2 *)vr,
                                    (double2 *)vrt, (const double2 *)vq, (const double2 *)vqt, n, S, part);
-                hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
+            ctx.prof_stop(pr, s, SGN_K_SEED_UPDATE, 6.0 * eb * n, 40.0 * n);
+            hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
+            pr = ctx.prof_start(s);
+            if (lo)
+                hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(nvb), dim3(256), 0, s, P32.as<float2>(),
+                                   Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt, (float2 *)vpt, n, S,
+                                   launched, bc);
+            else
                 hipLaunchKernelGGL((ms_shift_update<double, double2>), dim3(nvb), dim3(256), 0, s, P.as<double2>(),
                                    X.as<double2>(), (const double2 *)vr, (const double2 *)vrt, (double2 *)vpt, n, S,
-                                   launched);
-            }
+                                   launched, bc);
+            ctx.prof_stop(pr, s, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
         }
         SGN_HIP(hipGetLastError());
     };

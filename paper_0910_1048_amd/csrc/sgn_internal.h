@@ -85,9 +85,29 @@ template <typename A, typename B> __host__ __device__ inline cpx<A> cast(cpx<B> 
 using z64 = cpx<double>;
 
 // ----------------------------------------------------------------------------- objects
+struct ProfRec {
+    int cls;
+    hipEvent_t start, stop;
+    double bytes, flops;
+    bool device_bytes;  // bytes accumulated by the kernel itself into byte_counter
+};
+
 struct Context {
     int device = 0;
     int num_cu = 0;
+    // profiling of the library's own launches (sgn_profile_enable)
+    bool prof = false;
+    std::vector<ProfRec> prof_recs;
+    std::vector<hipEvent_t> event_pool;
+    unsigned long long *byte_counter = nullptr;  // device, bytes reported by kernels
+    double acc_ms[SGN_K_COUNT] = {};
+    double acc_bytes[SGN_K_COUNT] = {};
+    double acc_flops[SGN_K_COUNT] = {};
+    long long acc_launches[SGN_K_COUNT] = {};
+    // returns -1 when profiling is off
+    int prof_start(hipStream_t s);
+    void prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes = false);
+    void prof_collect();
     // scratch device buffers owned by the context, grown on demand
     void *partials = nullptr;
     size_t partials_bytes = 0;
@@ -95,6 +115,10 @@ struct Context {
     size_t scalars_bytes = 0;
     void *ensure_partials(size_t bytes);
     void *ensure_scalars(size_t bytes);
+    // solver workspace arena, grown on demand and kept between calls
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    void *ensure_arena(size_t bytes);
 };
 
 struct Lattice {
