@@ -108,6 +108,14 @@ sgn_status wilson_apply(sgn_lattice lat, double mu, const void *in, void *out, s
 sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *in, void *out, sgn_prec p,
                             unsigned flags, void *stream);
 
+/* out[i] = H_W(mu[i]) in[i] for i < nrhs on one gauge field (flags: SGN_NO_GAMMA5
+ * as above; SGN_INTERNAL_LAYOUT is required).  Right-hand sides are processed in
+ * groups that share every link load (multi-RHS stencil), so a group costs less
+ * HBM traffic than separate calls.  mu (host) holds nrhs values; in/out (host
+ * arrays of device pointers) must not alias each other. */
+sgn_status wilson_apply_multi(sgn_lattice lat, int nrhs, const double *mu, const void *const *in,
+                              void *const *out, sgn_prec p, unsigned flags, void *stream);
+
 /* ------------------------------------------------------------------ deflation and statistics */
 /* LR deflation set (section "Deflation", oblique projector P = R L^H):
  * m right eigenvectors R and left eigenvectors L of H_W(mu) for its m

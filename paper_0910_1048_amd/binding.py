@@ -12,7 +12,7 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsgn.so")
+LIB_PATH = os.environ.get("SGN_LIBRARY") or os.path.join(_HERE, "libsgn.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "sgn.h")
 
 F64, F32, F32_H16 = 0, 1, 2
@@ -35,7 +35,7 @@ class LatticeDesc(C.Structure):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_0910_1048_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built: run `python paper_0910_1048_amd/build.py`")
 
 lib = C.CDLL(LIB_PATH)
 _vp, _i64 = C.c_void_p, C.c_int64
@@ -299,3 +299,17 @@ def sgn_profile_read(ctx):
     check(lib.sgn_profile_read(ctx.h, arr), "sgn_profile_read")
     return {KERNEL_NAMES[i]: {"launches": arr[i].launches, "total_ms": arr[i].total_ms, "bytes": arr[i].bytes,
                               "flops": arr[i].flops} for i in range(K_COUNT)}
+
+
+lib.wilson_apply_multi.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(_vp), C.POINTER(_vp), C.c_int,
+                                   C.c_uint, _vp]
+
+
+def wilson_apply_multi(lat, mus, xs, outs, prec=F64, flags=INTERNAL_LAYOUT, stream=None):
+    """outs[i] = H_W(mus[i]) xs[i], right-hand sides sharing link loads (internal layout)."""
+    n = len(xs)
+    mu = (C.c_double * n)(*[float(m) for m in mus])
+    pin = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in xs])
+    pout = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in outs])
+    check(lib.wilson_apply_multi(lat.h, n, mu, pin, pout, int(prec), C.c_uint(flags), _stream(stream)),
+          "wilson_apply_multi")

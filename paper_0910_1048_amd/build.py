@@ -1,6 +1,8 @@
 """Build libsgn.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_0910_1048_amd.build [-j N] [-v]
+    python paper_0910_1048_amd/build.py [-j N] [-v]
+
+(run as a script: importing the package needs the library this builds)
 
 Every .hip / .cpp under csrc/ is compiled to an object under _build/ and
 linked into paper_0910_1048_amd/libsgn.so.  Objects are rebuilt when the
@@ -18,13 +20,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OBJ = os.path.join(ROOT, "_build", "sgn")
-LIB = os.path.join(HERE, "libsgn.so")
+OBJ = os.environ.get("SGN_OBJ_DIR") or os.path.join(ROOT, "_build", "sgn")
+LIB = os.environ.get("SGN_LIB_OUT") or os.path.join(HERE, "libsgn.so")
 ARCH = os.environ.get("SGN_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-          "-I" + os.path.join(ROOT, "include")]
+          "-I" + os.path.join(ROOT, "include")] + os.environ.get("SGN_EXTRA_FLAGS", "").split()
 # hipcc flags for device code: gfx950 only, no packed-FP32 instructions.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]

@@ -13,24 +13,37 @@
 #ifndef SGN_STENCIL_WAVES
 #define SGN_STENCIL_WAVES 1
 #endif
+#ifndef SGN_STENCIL_THREADS
+#define SGN_STENCIL_THREADS 256
+#endif
+#ifndef SGN_XCD_REMAP
+#define SGN_XCD_REMAP 1
+#endif
+#ifndef SGN_T_MINOR
+#define SGN_T_MINOR 1   // t-fastest block order inside each XCD's t-slab when the shape allows
+#endif
+#ifndef SGN_STENCIL_LDS_PAD
+#define SGN_STENCIL_LDS_PAD 0
+#endif
+#ifndef SGN_PIN_PAIR
+#define SGN_PIN_PAIR 0   // 1: both hops of a direction in flight together
+#endif
 
 namespace sgn {
 
 namespace {
 
-struct StencilParams {
+}  // namespace
+constexpr int kMaxRhs = 2;
+namespace {
+
+struct RhsParams {
     const void *in;
     void *out;
-    const void *links;
-    int V;
-    int L[4];
-    int stride[4];
-    float bcf[4];       // boundary factor per direction (hops that wrap)
-    double kappa;
-    double wf_t, wb_t;  // time-hop weights e^{-mu}, e^{+mu}
+    double wf_t, wb_t;  // time-hop weights e^{-mu}, e^{+mu} of this right-hand side
     float s5_in;        // -1: apply gamma5 to the input first
     float s5_out;       // -1: apply gamma5 to the result
-    // epilogue
+    // epilogue  out = a * in_scale * Op(in) + b * z ;  partials of conj(w) . out
     double a;
     z64 b;
     const z64 *b_dev;
@@ -38,6 +51,19 @@ struct StencilParams {
     const void *w;
     z64 *partials;
     const z64 *in_scale;
+};
+
+struct StencilParams {
+    const void *links;
+    int V;
+    int L[4];
+    int stride[4];
+    float bcf[4];  // boundary factor per direction (hops that wrap)
+    double kappa;
+    // block schedule: when sched_T > 0, XCD k owns the t-slab [k*T, (k+1)*T) and
+    // walks it region by region with t fastest (sched_R spatial regions per slice)
+    int sched_T, sched_R;
+    RhsParams rhs[kMaxRhs];
 };
 
 // Half-spinor projection (1 - gamma_nu) for FWD, (1 + gamma_nu) otherwise:
@@ -127,56 +153,77 @@ __device__ __forceinline__ void pin(cpx<R> acc[12])
     for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(acc[k].r), "+v"(acc[k].i)::"memory");
 }
 
-template <int NU, typename R, typename LT>
-__device__ __forceinline__ void hop_pair(cpx<R> acc[12], const StencilParams &P, int s, int coord, R s5)
+template <int NU, int NR, typename R, typename LT>
+__device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilParams &P, int s, int coord)
 {
-    const SpT<R> *in = static_cast<const SpT<R> *>(P.in);
     const LT *U = static_cast<const LT *>(P.links);
     const int L = P.L[NU], st = P.stride[NU];
     const R kap = static_cast<R>(P.kappa);
-    R wf = 1, wb = 1;
-    if constexpr (NU == 3) {
-        wf = static_cast<R>(P.wf_t);
-        wb = static_cast<R>(P.wb_t);
-    }
-    cpx<R> p[12], h[6], chi[6], u[9];
-    // forward hop: (1 - gamma) U_nu(x) psi(x + nu)
+    cpx<R> u[9];
+    // forward hop: (1 - gamma) U_nu(x) psi(x + nu), the link shared by all right-hand sides
     {
         const bool wrap = coord == L - 1;
         const int n = wrap ? s - (L - 1) * st : s + st;
-        load_spinor(in, P.V, n, p);
-#pragma unroll
-        for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
-        project<NU, true>(p, h);
+        const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         load_link<R>(U, P.V, NU, s, u);
-        link_mul<false>(u, h, chi);
-        const R coef = -kap * wf * (wrap ? static_cast<R>(P.bcf[NU]) : R(1));
-        accumulate<NU, true>(acc, chi, coef);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            cpx<R> p[12], h[6], chi[6];
+            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.V, n, p);
+            const R s5 = static_cast<R>(P.rhs[r].s5_in);
+#pragma unroll
+            for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
+            project<NU, true>(p, h);
+            link_mul<false>(u, h, chi);
+            const R w = NU == 3 ? static_cast<R>(P.rhs[r].wf_t) : R(1);
+            accumulate<NU, true>(acc[r], chi, -kap * w * bcf);
+        }
     }
-    pin(acc);
+    if (!SGN_PIN_PAIR) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pin(acc[r]);
+    }
     // backward hop: (1 + gamma) U_nu(x - nu)^H psi(x - nu)
     {
         const bool wrap = coord == 0;
         const int n = wrap ? s + (L - 1) * st : s - st;
-        load_spinor(in, P.V, n, p);
-#pragma unroll
-        for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
-        project<NU, false>(p, h);
+        const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         load_link<R>(U, P.V, NU, n, u);
-        link_mul<true>(u, h, chi);
-        const R coef = -kap * wb * (wrap ? static_cast<R>(P.bcf[NU]) : R(1));
-        accumulate<NU, false>(acc, chi, coef);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            cpx<R> p[12], h[6], chi[6];
+            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.V, n, p);
+            const R s5 = static_cast<R>(P.rhs[r].s5_in);
+#pragma unroll
+            for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
+            project<NU, false>(p, h);
+            link_mul<true>(u, h, chi);
+            const R w = NU == 3 ? static_cast<R>(P.rhs[r].wb_t) : R(1);
+            accumulate<NU, false>(acc[r], chi, -kap * w * bcb);
+        }
     }
-    pin(acc);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) pin(acc[r]);
 }
 
-template <typename R, typename LT, bool kEpi, bool kDot>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SGN_STENCIL_WAVES))) stencil_kernel(StencilParams P)
+template <typename R, typename LT, int NR, bool kEpi, bool kDot>
+__global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(SGN_STENCIL_WAVES))) stencil_kernel(StencilParams P)
 {
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s = blk * 256 + threadIdx.x;
+    int blk;
+    if (P.sched_T > 0) {
+        // t-minor order inside each XCD's slab: the t-neighbours of a block are the
+        // blocks just before and after it
+        const int k = blockIdx.x % 8, j = blockIdx.x / 8;
+        const int tl = j % P.sched_T, r = j / P.sched_T;
+        blk = (k * P.sched_T + tl) * P.sched_R + r;
+    } else {
+        blk = SGN_XCD_REMAP ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    }
+    const int s = blk * SGN_STENCIL_THREADS + threadIdx.x;
     const bool valid = s < P.V;
-    double dr = 0.0, di = 0.0;
+    double dr[NR], di[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dr[r] = di[r] = 0.0;
     if (valid) {
         int c0 = s % P.L[0];
         int q = s / P.L[0];
@@ -184,81 +231,104 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SGN_ST
         q /= P.L[1];
         int c2 = q % P.L[2];
         int c3 = q / P.L[2];
-        const R s5 = static_cast<R>(P.s5_in);
-        cpx<R> acc[12];
-        load_spinor(static_cast<const SpT<R> *>(P.in), P.V, s, acc);
+        cpx<R> acc[NR][12];
 #pragma unroll
-        for (int k = 6; k < 12; ++k) acc[k] = s5 * acc[k];
-        hop_pair<0, R, LT>(acc, P, s, c0, s5);
-        hop_pair<1, R, LT>(acc, P, s, c1, s5);
-        hop_pair<2, R, LT>(acc, P, s, c2, s5);
-        hop_pair<3, R, LT>(acc, P, s, c3, s5);
-        const R s5o = static_cast<R>(P.s5_out);
+        for (int r = 0; r < NR; ++r) {
+            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.V, s, acc[r]);
+            const R s5 = static_cast<R>(P.rhs[r].s5_in);
 #pragma unroll
-        for (int k = 6; k < 12; ++k) acc[k] = s5o * acc[k];
-        if constexpr (kEpi) {
-            cpx<R> sc = {static_cast<R>(P.a), R(0)};
-            if (P.in_scale) {
-                z64 t = *P.in_scale;
-                sc = {static_cast<R>(P.a * t.r), static_cast<R>(P.a * t.i)};
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
-            if (P.z) {
-                z64 bb = P.b;
-                if (P.b_dev) {
-                    z64 t = *P.b_dev;
-                    bb = {bb.r * t.r - bb.i * t.i, bb.r * t.i + bb.i * t.r};
-                }
-                cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
-                cpx<R> zz[12];
-                load_spinor(static_cast<const SpT<R> *>(P.z), P.V, s, zz);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) acc[k] = acc[k] + b * zz[k];
-            }
+            for (int k = 6; k < 12; ++k) acc[r][k] = s5 * acc[r][k];
         }
-        store_spinor(static_cast<SpT<R> *>(P.out), P.V, s, acc);
-        if constexpr (kDot) {
-            cpx<R> ww[12];
-            load_spinor(static_cast<const SpT<R> *>(P.w), P.V, s, ww);
+        hop_pair<0, NR, R, LT>(acc, P, s, c0);
+        hop_pair<1, NR, R, LT>(acc, P, s, c1);
+        hop_pair<2, NR, R, LT>(acc, P, s, c2);
+        hop_pair<3, NR, R, LT>(acc, P, s, c3);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                z64 a = cast<double>(ww[k]), o = cast<double>(acc[k]);
-                dr += a.r * o.r + a.i * o.i;
-                di += a.r * o.i - a.i * o.r;
+        for (int r = 0; r < NR; ++r) {
+            const RhsParams &Q = P.rhs[r];
+            const R s5o = static_cast<R>(Q.s5_out);
+#pragma unroll
+            for (int k = 6; k < 12; ++k) acc[r][k] = s5o * acc[r][k];
+            if constexpr (kEpi) {
+                cpx<R> sc = {static_cast<R>(Q.a), R(0)};
+                if (Q.in_scale) {
+                    z64 t = *Q.in_scale;
+                    sc = {static_cast<R>(Q.a * t.r), static_cast<R>(Q.a * t.i)};
+                }
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[r][k] = sc * acc[r][k];
+                if (Q.z) {
+                    z64 bb = Q.b;
+                    if (Q.b_dev) {
+                        z64 t = *Q.b_dev;
+                        bb = {bb.r * t.r - bb.i * t.i, bb.r * t.i + bb.i * t.r};
+                    }
+                    cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
+                    cpx<R> zz[12];
+                    load_spinor(static_cast<const SpT<R> *>(Q.z), P.V, s, zz);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) acc[r][k] = acc[r][k] + b * zz[k];
+                }
+            }
+            store_spinor(static_cast<SpT<R> *>(Q.out), P.V, s, acc[r]);
+            if constexpr (kDot) {
+                if (Q.w) {
+                    cpx<R> ww[12];
+                    load_spinor(static_cast<const SpT<R> *>(Q.w), P.V, s, ww);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        z64 a = cast<double>(ww[k]), o = cast<double>(acc[r][k]);
+                        dr[r] += a.r * o.r + a.i * o.i;
+                        di[r] += a.r * o.i - a.i * o.r;
+                    }
+                }
             }
         }
     }
     if constexpr (kDot) {
-        __shared__ double lds[8];
-        double v[2] = {dr, di};
-        block_sum<2>(v, lds);
-        if (threadIdx.x == 0) P.partials[blockIdx.x] = {v[0], v[1]};
+        __shared__ double lds[2 * (SGN_STENCIL_THREADS / 64)];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!P.rhs[r].w) continue;  // uniform
+            double v[2] = {dr[r], di[r]};
+            block_sum<2>(v, lds);
+            if (threadIdx.x == 0) P.rhs[r].partials[blockIdx.x] = {v[0], v[1]};
+            __syncthreads();
+        }
     }
 }
 
-template <typename R, typename LT>
+template <typename R, typename LT, int NR>
 void launch_typed(const StencilParams &P, int nblk, bool epi, bool dot, hipStream_t s)
 {
-    dim3 g(nblk), b(256);
+    dim3 g(nblk), b(SGN_STENCIL_THREADS);
     if (dot)
-        hipLaunchKernelGGL((stencil_kernel<R, LT, true, true>), g, b, 0, s, P);
+        hipLaunchKernelGGL((stencil_kernel<R, LT, NR, true, true>), g, b, 0, s, P);
     else if (epi)
-        hipLaunchKernelGGL((stencil_kernel<R, LT, true, false>), g, b, 0, s, P);
+        hipLaunchKernelGGL((stencil_kernel<R, LT, NR, true, false>), g, b, 0, s, P);
     else
-        hipLaunchKernelGGL((stencil_kernel<R, LT, false, false>), g, b, 0, s, P);
+        hipLaunchKernelGGL((stencil_kernel<R, LT, NR, false, false>), g, b, 0, s, P);
+}
+
+template <typename R, typename LT>
+void launch_nr(const StencilParams &P, int nr, int nblk, bool epi, bool dot, hipStream_t s)
+{
+    switch (nr) {
+    case 1: launch_typed<R, LT, 1>(P, nblk, epi, dot, s); break;
+    case 2: launch_typed<R, LT, 2>(P, nblk, epi, dot, s); break;
+    default: throw Failure{SGN_ERR_INVALID, "stencil: unsupported number of right-hand sides"};
+    }
 }
 
 }  // namespace
 
-int dslash_blocks(const Lattice &lat) { return (int)((lat.V + 255) / 256); }
+int dslash_blocks(const Lattice &lat) { return (int)((lat.V + SGN_STENCIL_THREADS - 1) / SGN_STENCIL_THREADS); }
 
-int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,
-                  const Epilogue &ep, hipStream_t s)
+int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
+                        void *const *out, const Epilogue *ep, hipStream_t s)
 {
+    if (nr < 1 || nr > kMaxRhs) throw Failure{SGN_ERR_INVALID, "stencil: 1..2 right-hand sides per launch"};
     StencilParams P{};
-    P.in = in;
-    P.out = out;
     P.V = (int)lat.V;
     for (int d = 0; d < 4; ++d) {
         P.L[d] = lat.L[d];
@@ -269,43 +339,62 @@ int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *
     P.stride[2] = lat.L[0] * lat.L[1];
     P.stride[3] = lat.L[0] * lat.L[1] * lat.L[2];
     P.kappa = lat.kappa;
-    P.wf_t = std::exp(-op.mu);
-    P.wb_t = std::exp(op.mu);
-    P.s5_in = op.g5_in ? -1.f : 1.f;
-    P.s5_out = op.g5_out ? -1.f : 1.f;
-    P.a = ep.a;
-    P.b = ep.b;
-    P.b_dev = ep.b_dev;
-    P.z = ep.z;
-    P.w = ep.w;
-    P.partials = ep.partials;
-    P.in_scale = ep.in_scale;
-    const bool dot = ep.w != nullptr;
-    const bool epi = dot || ep.z != nullptr || ep.a != 1.0 || ep.in_scale != nullptr;
-    if (dot && !ep.partials) throw Failure{SGN_ERR_INVALID, "stencil dot without partial buffer"};
-    const int nblk = dslash_blocks(lat);
-    // algorithmic bytes: in and out spinors once, the 4 links of each site once,
-    // plus the epilogue operands; 1368 flop per site for the stencil itself
+    bool dot = false, epi = false;
+    double extra_bytes = 0.0, extra_flops = 0.0;
     const double sb = (p == SGN_PREC_F64) ? 192.0 : 96.0;
+    for (int r = 0; r < nr; ++r) {
+        RhsParams &Q = P.rhs[r];
+        Q.in = in[r];
+        Q.out = out[r];
+        Q.wf_t = std::exp(-op[r].mu);
+        Q.wb_t = std::exp(op[r].mu);
+        Q.s5_in = op[r].g5_in ? -1.f : 1.f;
+        Q.s5_out = op[r].g5_out ? -1.f : 1.f;
+        Q.a = ep[r].a;
+        Q.b = ep[r].b;
+        Q.b_dev = ep[r].b_dev;
+        Q.z = ep[r].z;
+        Q.w = ep[r].w;
+        Q.partials = ep[r].partials;
+        Q.in_scale = ep[r].in_scale;
+        if (ep[r].w && !ep[r].partials) throw Failure{SGN_ERR_INVALID, "stencil dot without partial buffer"};
+        dot = dot || ep[r].w != nullptr;
+        epi = epi || ep[r].w != nullptr || ep[r].z != nullptr || ep[r].a != 1.0 || ep[r].in_scale != nullptr;
+        extra_bytes += (ep[r].z ? sb : 0.0) + (ep[r].w ? sb : 0.0);
+        extra_flops += (ep[r].z ? 96.0 : 0.0) + (ep[r].w ? 96.0 : 0.0) + 24.0;
+    }
+    const int nblk = dslash_blocks(lat);
+    {
+        const int64_t vxyz = (int64_t)lat.L[0] * lat.L[1] * lat.L[2];
+        P.sched_T = P.sched_R = 0;
+        if (SGN_T_MINOR && vxyz % SGN_STENCIL_THREADS == 0 && lat.L[3] % 8 == 0) {
+            P.sched_T = lat.L[3] / 8;
+            P.sched_R = (int)(vxyz / SGN_STENCIL_THREADS);
+            if ((int64_t)8 * P.sched_T * P.sched_R != nblk) P.sched_T = P.sched_R = 0;
+        }
+    }
+    // algorithmic bytes: every input and output spinor once, the 4 links of each
+    // site once (shared by the right-hand sides), plus the epilogue operands;
+    // 1368 flop per site and right-hand side for the stencil itself
     const double lb = (p == SGN_PREC_F64) ? 144.0 : (p == SGN_PREC_F32 ? 72.0 : 36.0);
-    const double site_bytes = 2 * sb + 4 * lb + (ep.z ? sb : 0.0) + (dot ? sb : 0.0);
-    const double site_flops = 1368.0 + (epi ? 24.0 : 0.0) + (ep.z ? 96.0 : 0.0) + (dot ? 96.0 : 0.0);
+    const double site_bytes = 2 * sb * nr + 4 * lb + extra_bytes;
+    const double site_flops = 1368.0 * nr + extra_flops;
     const int prof = lat.ctx->prof_start(s);
     switch (p) {
     case SGN_PREC_F64:
         if (!lat.links64) throw Failure{SGN_ERR_INVALID, "lattice has no FP64 links"};
         P.links = lat.links64;
-        launch_typed<double, double2>(P, nblk, epi, dot, s);
+        launch_nr<double, double2>(P, nr, nblk, epi, dot, s);
         break;
     case SGN_PREC_F32:
         if (!lat.links32) throw Failure{SGN_ERR_INVALID, "lattice has no FP32 links"};
         P.links = lat.links32;
-        launch_typed<float, float2>(P, nblk, epi, dot, s);
+        launch_nr<float, float2>(P, nr, nblk, epi, dot, s);
         break;
     case SGN_PREC_F32_H16:
         if (!lat.links16) throw Failure{SGN_ERR_INVALID, "lattice has no FP16 links"};
         P.links = lat.links16;
-        launch_typed<float, __half2>(P, nblk, epi, dot, s);
+        launch_nr<float, __half2>(P, nr, nblk, epi, dot, s);
         break;
     default:
         throw Failure{SGN_ERR_INVALID, "unknown precision"};
@@ -314,6 +403,12 @@ int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *
     lat.ctx->prof_stop(prof, s, p == SGN_PREC_F64 ? SGN_K_STENCIL_F64 : (p == SGN_PREC_F32 ? SGN_K_STENCIL_F32 : SGN_K_STENCIL_H16),
                        site_bytes * lat.V, site_flops * lat.V);
     return nblk;
+}
+
+int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,
+                  const Epilogue &ep, hipStream_t s)
+{
+    return dslash_launch_multi(lat, p, 1, &op, &in, &out, &ep, s);
 }
 
 }  // namespace sgn
@@ -369,4 +464,32 @@ extern "C" sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *i
                                        unsigned flags, void *stream)
 {
     return apply_common(lat, mu, in, out, p, flags, stream, true);
+}
+
+extern "C" sgn_status wilson_apply_multi(sgn_lattice l, int nrhs, const double *mu, const void *const *in,
+                                         void *const *out, sgn_prec p, unsigned flags, void *stream)
+{
+    return guard([&] {
+        SGN_REQUIRE(l != nullptr && mu != nullptr && in != nullptr && out != nullptr && nrhs >= 0,
+                    "wilson_apply_multi: null argument");
+        SGN_REQUIRE(flags & SGN_INTERNAL_LAYOUT, "wilson_apply_multi: fields must be in the internal layout");
+        Lattice &lat = *as_lattice(l);
+        SGN_HIP(hipSetDevice(lat.ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        for (int i = 0; i < nrhs; ++i) {
+            SGN_REQUIRE(in[i] && out[i] && std::isfinite(mu[i]), "wilson_apply_multi: bad right-hand side");
+            for (int j = 0; j < nrhs; ++j)
+                SGN_REQUIRE(in[i] != out[j], "wilson_apply_multi: inputs and outputs must not alias");
+        }
+        for (int i0 = 0; i0 < nrhs; i0 += kMaxRhs) {
+            const int nr = std::min(kMaxRhs, nrhs - i0);
+            OpSpec op[kMaxRhs];
+            Epilogue ep[kMaxRhs];
+            for (int r = 0; r < nr; ++r) {
+                op[r].mu = mu[i0 + r];
+                op[r].g5_out = !(flags & SGN_NO_GAMMA5);
+            }
+            dslash_launch_multi(lat, p, nr, op, in + i0, out + i0, ep, s);
+        }
+    });
 }

@@ -125,7 +125,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [4*NV] */)
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [(blockDim/64)*NV] */)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll

@@ -45,8 +45,8 @@ struct MsHead {
 
 struct MsState {
     MsHead h;
-    z64 zeta[kS], zeta_prev[kS], zeta_next[kS], alpha_i[kS], beta_i[kS];
-    double tau[kS];
+    z64 zeta[kS], zeta_prev[kS], zeta_next[kS], alpha_i[kS], beta_i[kS];    double tau[kS];
+    double omega[kS];
     double res[kS];
     int act[kS], act_next[kS];
 };
@@ -213,8 +213,13 @@ __global__ void __launch_bounds__(256) ms_seed_update(typename VecT<R>::t *r, ty
     }
 }
 
-// x_i += alpha_i p_i ; p_i = zeta_i r + beta_i p_i (active shifts) ; p~ = r~ + conj(beta) p~
-template <typename R, typename XT>
+// p_i = zeta_i r + beta_i p_i for the active shifts, p~ = r~ + conj(beta) p~, and the
+// solution updates with the old p_i:
+//   KEEP:  x_i += alpha_i p_i for every active shift (X holds s vectors)
+//   else:  x_seed += alpha_seed p_seed and x_rest += sum_{i != seed} omega_i alpha_i p_i
+//          (X holds 2 vectors) -- only the omega-weighted sum of the non-seed
+//          solutions is ever needed, which halves the per-shift memory traffic.
+template <typename R, typename XT, bool KEEP>
 __global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, XT *X, const typename VecT<R>::t *r,
                                                        const typename VecT<R>::t *rt, typename VecT<R>::t *pt,
                                                        int64_t n, const MsState *S, int expect,
@@ -225,35 +230,49 @@ __global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, X
     if (S->h.breakdown || S->h.iter != expect) return;
     __shared__ z64 al_s[kS], be_s[kS], ze_s[kS];
     __shared__ int act_s[kS];
-    __shared__ int ns;
-    const int nsh = S->h.nshift;
+    __shared__ int ns, any_rest;
+    const int nsh = S->h.nshift, seed = S->h.seed;
+    if (threadIdx.x == 0) any_rest = 0;
+    __syncthreads();
     for (int i = threadIdx.x; i < nsh; i += blockDim.x) {
-        act_s[i] = S->act[i];
-        al_s[i] = S->alpha_i[i];
+        const int a = S->act[i];
+        act_s[i] = a;
+        al_s[i] = (KEEP || i == seed) ? S->alpha_i[i] : S->omega[i] * S->alpha_i[i];
         be_s[i] = S->beta_i[i];
         ze_s[i] = S->zeta[i];
+        if (a && i != seed) any_rest = 1;  // every writer stores the same value
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         ns = nsh;
         if (byte_counter && blockIdx.x == 0) {  // algorithmic bytes of this launch (profiling)
-            int na = 0;
-            for (int i = 0; i < nsh; ++i) na += S->act[i] ? 1 : 0;
+            unsigned long long na = 0;
+            for (int i = 0; i < nsh; ++i) na += act_s[i] ? 1 : 0;
             const unsigned long long eb = sizeof(typename VecT<R>::t), xb = sizeof(XT);
-            atomicAdd(byte_counter, (unsigned long long)n * (4ull * eb + (unsigned long long)na * (2ull * eb + 2ull * xb)));
+            const unsigned long long nxv = KEEP ? na : (1ull + (any_rest ? 1ull : 0ull));
+            atomicAdd(byte_counter, (unsigned long long)n * (4ull * eb + na * 2ull * eb + nxv * 2ull * xb));
         }
     }
     __syncthreads();
     const z64 bc = conj(S->h.beta);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 rv = ldz(r, e);
+        z64 rest = {0.0, 0.0};
         for (int i = 0; i < ns; ++i) {
             if (!act_s[i]) continue;
             typename VecT<R>::t *Pi = P + (int64_t)i * n;
-            XT *Xi = X + (int64_t)i * n;
             const z64 p = ldz(Pi, e);
-            stz(Xi, e, ldz(Xi, e) + al_s[i] * p);
+            if (KEEP) {
+                XT *Xi = X + (int64_t)i * n;
+                stz(Xi, e, ldz(Xi, e) + al_s[i] * p);
+            } else if (i == seed) {
+                stz(X, e, ldz(X, e) + al_s[i] * p);
+            } else {
+                rest = rest + al_s[i] * p;
+            }
             stz(Pi, e, ze_s[i] * rv + be_s[i] * p);
         }
+        if (!KEEP && any_rest) stz(X + n, e, ldz(X + n, e) + rest);
         stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
     }
 }
@@ -401,8 +420,10 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed])) seed = i;
     const double s1 = rf.sigma[seed];
 
-    // workspace carved from the context's arena (kept between calls)
-    const size_t a64 = (9 + 2 * (size_t)ns) * b64, a32 = mixed ? (7 + 2 * (size_t)ns) * b32 : 0;
+    // workspace carved from the context's arena (kept between calls)    // per-shift solutions are kept only when the caller asks for them
+    const bool keep = pb.x_shift != nullptr || o.verify;
+    const int nx = keep ? ns : 2;
+    const size_t a64 = (9 + (size_t)ns + nx) * b64, a32 = mixed ? (7 + (size_t)ns + nx) * b32 : 0;
     char *arena = static_cast<char *>(ctx.ensure_arena(a64 + a32 + sizeof(MsState)));
     auto carve = [&](size_t bytes) {
         Span sp{arena};
@@ -410,12 +431,10 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         return sp;
     };
     Span y = carve(b64), r = carve(b64), rt = carve(b64), pt = carve(b64), q = carve(b64), qt = carve(b64),
-         tmp = carve(b64), tmpt = carve(b64);
-    Span X = carve((size_t)ns * b64), P = carve((size_t)ns * b64);
+         tmp = carve(b64), tmpt = carve(b64);    Span X = carve((size_t)nx * b64), P = carve((size_t)ns * b64);
     Span r32 = carve(mixed ? b32 : 0), rt32 = carve(mixed ? b32 : 0), pt32 = carve(mixed ? b32 : 0),
          q32 = carve(mixed ? b32 : 0), qt32 = carve(mixed ? b32 : 0), tmp32 = carve(mixed ? b32 : 0),
-         tmpt32 = carve(mixed ? b32 : 0);
-    Span P32 = carve(mixed ? (size_t)ns * b32 : 0), Xlo = carve(mixed ? (size_t)ns * b32 : 0);
+         tmpt32 = carve(mixed ? b32 : 0);    Span P32 = carve(mixed ? (size_t)ns * b32 : 0), Xlo = carve(mixed ? (size_t)nx * b32 : 0);
     MsState *S = carve(sizeof(MsState)).as<MsState>();
     Span rcan = carve(b64);
 
@@ -459,8 +478,8 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     h0.h.nshift = ns;
     h0.h.seed = seed;
     for (int i = 0; i < ns; ++i) {
-        h0.zeta[i] = h0.zeta_prev[i] = {1.0, 0.0};
-        h0.tau[i] = s1 - rf.sigma[i];
+        h0.zeta[i] = h0.zeta_prev[i] = {1.0, 0.0};        h0.tau[i] = s1 - rf.sigma[i];
+        h0.omega[i] = rf.omega[i];
         h0.act_next[i] = 1;
         h0.res[i] = ynorm;
     }
@@ -468,9 +487,8 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     SGN_HIP(hipMemcpyAsync(r.p, y.p, b64, hipMemcpyDeviceToDevice, s));
     SGN_HIP(hipMemcpyAsync(rt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
     SGN_HIP(hipMemcpyAsync(pt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s, y.as<double2>(), P.as<double2>(), ns, n);
-    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s, X.as<double2>(), make_double2(0, 0),
-                       (int64_t)ns * n);
+    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s, y.as<double2>(), P.as<double2>(), ns, n);    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s, X.as<double2>(), make_double2(0, 0),
+                       (int64_t)nx * n);
     SGN_HIP(hipGetLastError());
 
     int phase = 0;
@@ -514,27 +532,32 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
                                    (double2 *)vrt, (const double2 *)vq, (const double2 *)vqt, n, S, part);
             ctx.prof_stop(pr, s, SGN_K_SEED_UPDATE, 6.0 * eb * n, 40.0 * n);
             hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
-            pr = ctx.prof_start(s);
-            if (lo)
-                hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(nvb), dim3(256), 0, s, P32.as<float2>(),
+            pr = ctx.prof_start(s);            if (lo && keep)
+                hipLaunchKernelGGL((ms_shift_update<float, float2, true>), dim3(nvb), dim3(256), 0, s, P32.as<float2>(),
                                    Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt, (float2 *)vpt, n, S,
                                    launched, bc);
+            else if (lo)
+                hipLaunchKernelGGL((ms_shift_update<float, float2, false>), dim3(nvb), dim3(256), 0, s,
+                                   P32.as<float2>(), Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt,
+                                   (float2 *)vpt, n, S, launched, bc);
+            else if (keep)
+                hipLaunchKernelGGL((ms_shift_update<double, double2, true>), dim3(nvb), dim3(256), 0, s,
+                                   P.as<double2>(), X.as<double2>(), (const double2 *)vr, (const double2 *)vrt,
+                                   (double2 *)vpt, n, S, launched, bc);
             else
-                hipLaunchKernelGGL((ms_shift_update<double, double2>), dim3(nvb), dim3(256), 0, s, P.as<double2>(),
-                                   X.as<double2>(), (const double2 *)vr, (const double2 *)vrt, (double2 *)vpt, n, S,
-                                   launched, bc);
+                hipLaunchKernelGGL((ms_shift_update<double, double2, false>), dim3(nvb), dim3(256), 0, s,
+                                   P.as<double2>(), X.as<double2>(), (const double2 *)vr, (const double2 *)vrt,
+                                   (double2 *)vpt, n, S, launched, bc);
             ctx.prof_stop(pr, s, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
         }
         SGN_HIP(hipGetLastError());
     };
 
-    auto flush = [&]() {
-        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), ns, (int)V);
+    auto flush = [&]() {        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), nx, (int)V);
     };
 
     auto reliable_update = [&]() {
-        flush();
-        double2 *xs = X.as<double2>() + (size_t)seed * n;
+        flush();        double2 *xs = X.as<double2>() + (keep ? (size_t)seed * n : 0);
         dslash_launch(lat, SGN_PREC_F64, opA, xs, tmp.p, Epilogue{}, s);
         Epilogue ep;
         ep.a = -c2;
@@ -553,9 +576,8 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         convert_64_to_32(rt.p, rt32.p, V, s);
         convert_64_to_32(pt.p, pt32.p, V, s);
         for (int i = 0; i < ns; ++i)
-            convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, V, s);
-        hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
-                           (int64_t)ns * n);
+            convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, V, s);        hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
+                           (int64_t)nx * n);
         SGN_HIP(hipGetLastError());
     };
 
@@ -608,10 +630,10 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     const double kry_ms = ms_since(t_kry);
 
     // x += sum_i omega_i x_i
-    {
-        DevMem w(sizeof(double) * ns);
-        SGN_HIP(hipMemcpyAsync(w.p, rf.omega, sizeof(double) * ns, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), ns, n,
+    {        DevMem w(sizeof(double) * ns);
+        const double wh[2] = {rf.omega[seed], 1.0};
+        SGN_HIP(hipMemcpyAsync(w.p, keep ? rf.omega : wh, sizeof(double) * nx, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), nx, n,
                            tmp.as<double2>());
         unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
         axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, n, s);

@@ -160,6 +160,10 @@ struct Epilogue {
 
 // Launch the stencil on internal-layout fields.  Returns the number of blocks
 // (= number of partials written when ep.w is set).
+// nr (1 or 2) right-hand sides in one launch sharing every link load; each has
+// its own operator (mu, gamma5 flags), input, output and epilogue.
+int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
+                        void *const *out, const Epilogue *ep, hipStream_t s);
 int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,
                   const Epilogue &ep, hipStream_t s);
 int dslash_blocks(const Lattice &lat);

@@ -126,3 +126,25 @@ def test_invalid_arguments_are_rejected():
     assert e.value.status == 1
     with pytest.raises(sgn.SgnError):
         sgn.wilson_apply(lat, float("nan"), x, torch.empty_like(x), sgn.F64)
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+@pytest.mark.parametrize("nrhs", [1, 2, 3])
+def test_multi_rhs_stencil(prec, nrhs):
+    """wilson_apply_multi: right-hand sides with their own mu sharing link loads."""
+    dims = (4, 6, 4, 8)
+    U = synth.gauge_field(dims, 0.5, 1)
+    ref = WilsonRef(U, dims, 0.2)
+    lat = lattice(U, dims)
+    mus = [0.3, -0.3, 0.1][:nrhs]
+    srcs = [synth.gaussian_source(dims, 20 + i) for i in range(nrhs)]
+    nbytes = lat.spinor_bytes(prec)
+    xi = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nrhs)]
+    yi = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(nrhs)]
+    for b, t in zip(srcs, xi):
+        sgn.sgn_spinor_pack(lat, dev(b.astype(CDT[prec])), t, prec)
+    sgn.wilson_apply_multi(lat, mus, xi, yi, prec)
+    for mu, b, t in zip(mus, srcs, yi):
+        out = torch.empty(b.size, dtype=torch.complex128 if prec == sgn.F64 else torch.complex64, device="cuda")
+        sgn.sgn_spinor_unpack(lat, t, out, prec)
+        assert _rel(host(out).astype(np.complex128).reshape(b.shape), ref.apply(b, mu)) < TOL[prec]
