@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 512 MiB device-to-device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the solver path is single-GPU "
@@ -52,6 +54,13 @@ def main():
 
     import synth
     import paper_0910_1048_amd as sgn
+
+    if args.calibrate_copy:
+        a = torch.zeros(1 << 27, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
 
     W = WORKLOAD
     dims = W["dims"]

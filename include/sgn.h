@@ -193,6 +193,26 @@ sgn_status sgn_rational_neuberger(int s, double alpha, double beta, sgn_rational
  * through alpha and beta (circle theorem).  Host only. */
 sgn_status sgn_poles_needed(double alpha, double beta, double eps, int *s);
 
+/* ------------------------------------------------------------------ restarted FOM (Arnoldi) */
+typedef struct {
+    int kmax;           /* Arnoldi steps per restart cycle (k_max) */
+    double tol;         /* every shifted residual |rho_i| ||r|| <= tol ||c H (I-P) b|| */
+    int max_restarts;   /* cycles (0: 1000) */
+    sgn_prec prec;      /* SGN_PREC_F64 (the only form implemented; others return SGN_ERR_INVALID) */
+} sgn_arnoldi_opts;
+
+/* Restarted FOM-LR(m, k) (section "Restarted Arnoldi with rational functions"):
+ * x = x_P + sum_i omega_i x_i with (c^2 H_W^2 - sigma_i) x_i = c H_W (I-P) b, all
+ * shifts from one restarted Arnoldi process (classical Gram-Schmidt twice) on
+ * c^2 H_W^2; the collinear restart of Eq. (collinearity); the projection step
+ * r = (I-P) v_{k+1} after every cycle.  b, x: device canonical complex128.
+ * The shifted Hessenberg systems are solved on the host each cycle; the call
+ * synchronises `stream`.  SGN_ERR_NOT_CONVERGED after max_restarts cycles
+ * (x holds the last iterate). */
+sgn_status sign_arnoldi_rational(sgn_lattice lat, double mu, const void *b, void *x, const sgn_rational *r,
+                                 const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *stats,
+                                 void *stream);
+
 /* ------------------------------------------------------------------ multishift BiCG */
 typedef struct {
     sgn_lattice lat;

@@ -34,6 +34,15 @@ class LatticeDesc(C.Structure):
     _fields_ = [("dims", C.c_int * 4), ("bc", C.c_int * 4), ("kappa", C.c_double)]
 
 
+# torch ships its own libamdhip64 and loads it by file name, so a library that
+# brought in the system copy first would leave two HIP runtimes in the process
+# and the second finds no device.  Importing torch first makes libsgn bind to
+# the runtime torch already holds (same soname).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run `python paper_0910_1048_amd/build.py`")
 
@@ -313,3 +322,22 @@ def wilson_apply_multi(lat, mus, xs, outs, prec=F64, flags=INTERNAL_LAYOUT, stre
     pout = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in outs])
     check(lib.wilson_apply_multi(lat.h, n, mu, pin, pout, int(prec), C.c_uint(flags), _stream(stream)),
           "wilson_apply_multi")
+
+
+class ArnoldiOpts(C.Structure):
+    _fields_ = [("kmax", C.c_int), ("tol", C.c_double), ("max_restarts", C.c_int), ("prec", C.c_int)]
+
+
+lib.sign_arnoldi_rational.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(Rational), C.POINTER(_Deflation),
+                                      C.POINTER(ArnoldiOpts), C.POINTER(Stats), _vp]
+
+
+def sign_arnoldi_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10, max_restarts=0, prec=F64,
+                          stream=None):
+    """x = x_P + g_s(c H_W)(I-P) b by restarted FOM-LR; returns the stats dict."""
+    o = ArnoldiOpts(int(kmax), float(tol), int(max_restarts), int(prec))
+    st = Stats()
+    d = C.pointer(defl.struct) if defl is not None else None
+    check(lib.sign_arnoldi_rational(lat.h, float(mu), _ptr(b), _ptr(x), C.byref(rational), d, C.byref(o),
+                                    C.byref(st), _stream(stream)), "sign_arnoldi_rational")
+    return st.as_dict()

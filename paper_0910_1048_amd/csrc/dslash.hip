@@ -55,7 +55,8 @@ struct RhsParams {
 
 struct StencilParams {
     const void *links;
-    int V;
+    int V;  // sites
+    int S;  // component stride
     int L[4];
     int stride[4];
     float bcf[4];  // boundary factor per direction (hops that wrap)
@@ -63,6 +64,7 @@ struct StencilParams {
     // block schedule: when sched_T > 0, XCD k owns the t-slab [k*T, (k+1)*T) and
     // walks it region by region with t fastest (sched_R spatial regions per slice)
     int sched_T, sched_R;
+    int nblk_sites;  // blocks covering the V sites; later blocks zero the padding sites [V, S)
     RhsParams rhs[kMaxRhs];
 };
 
@@ -165,11 +167,11 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
         const bool wrap = coord == L - 1;
         const int n = wrap ? s - (L - 1) * st : s + st;
         const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
-        load_link<R>(U, P.V, NU, s, u);
+        load_link<R>(U, P.S, NU, s, u);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             cpx<R> p[12], h[6], chi[6];
-            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.V, n, p);
+            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.S, n, p);
             const R s5 = static_cast<R>(P.rhs[r].s5_in);
 #pragma unroll
             for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
@@ -188,11 +190,11 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
         const bool wrap = coord == 0;
         const int n = wrap ? s + (L - 1) * st : s - st;
         const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
-        load_link<R>(U, P.V, NU, n, u);
+        load_link<R>(U, P.S, NU, n, u);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             cpx<R> p[12], h[6], chi[6];
-            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.V, n, p);
+            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.S, n, p);
             const R s5 = static_cast<R>(P.rhs[r].s5_in);
 #pragma unroll
             for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
@@ -209,6 +211,22 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
 template <typename R, typename LT, int NR, bool kEpi, bool kDot>
 __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(SGN_STENCIL_WAVES))) stencil_kernel(StencilParams P)
 {
+    if ((int)blockIdx.x >= P.nblk_sites) {  // padding of the component arrays: keep it zero
+        const int s = P.V + ((int)blockIdx.x - P.nblk_sites) * SGN_STENCIL_THREADS + threadIdx.x;
+        if (s < P.S) {
+            cpx<R> zero[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) zero[k] = {R(0), R(0)};
+#pragma unroll
+            for (int r = 0; r < NR; ++r) store_spinor(static_cast<SpT<R> *>(P.rhs[r].out), P.S, s, zero);
+        }
+        if constexpr (kDot) {
+            if (threadIdx.x == 0)
+                for (int r = 0; r < NR; ++r)
+                    if (P.rhs[r].w) P.rhs[r].partials[blockIdx.x] = {0.0, 0.0};
+        }
+        return;
+    }
     int blk;
     if (P.sched_T > 0) {
         // t-minor order inside each XCD's slab: the t-neighbours of a block are the
@@ -234,7 +252,7 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
         cpx<R> acc[NR][12];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.V, s, acc[r]);
+            load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.S, s, acc[r]);
             const R s5 = static_cast<R>(P.rhs[r].s5_in);
 #pragma unroll
             for (int k = 6; k < 12; ++k) acc[r][k] = s5 * acc[r][k];
@@ -265,16 +283,16 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
                     }
                     cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
                     cpx<R> zz[12];
-                    load_spinor(static_cast<const SpT<R> *>(Q.z), P.V, s, zz);
+                    load_spinor(static_cast<const SpT<R> *>(Q.z), P.S, s, zz);
 #pragma unroll
                     for (int k = 0; k < 12; ++k) acc[r][k] = acc[r][k] + b * zz[k];
                 }
             }
-            store_spinor(static_cast<SpT<R> *>(Q.out), P.V, s, acc[r]);
+            store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, acc[r]);
             if constexpr (kDot) {
                 if (Q.w) {
                     cpx<R> ww[12];
-                    load_spinor(static_cast<const SpT<R> *>(Q.w), P.V, s, ww);
+                    load_spinor(static_cast<const SpT<R> *>(Q.w), P.S, s, ww);
 #pragma unroll
                     for (int k = 0; k < 12; ++k) {
                         z64 a = cast<double>(ww[k]), o = cast<double>(acc[r][k]);
@@ -322,7 +340,13 @@ void launch_nr(const StencilParams &P, int nr, int nblk, bool epi, bool dot, hip
 
 }  // namespace
 
-int dslash_blocks(const Lattice &lat) { return (int)((lat.V + SGN_STENCIL_THREADS - 1) / SGN_STENCIL_THREADS); }
+int dslash_blocks(const Lattice &lat)
+{
+    const int64_t t = SGN_STENCIL_THREADS;
+    const int64_t valid = (lat.V + t - 1) / t;
+    const int64_t pad = lat.S > lat.V ? (lat.S - lat.V + t - 1) / t : 0;  // padding sites [V, S)
+    return (int)(valid + pad);
+}
 
 int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
                         void *const *out, const Epilogue *ep, hipStream_t s)
@@ -330,6 +354,7 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
     if (nr < 1 || nr > kMaxRhs) throw Failure{SGN_ERR_INVALID, "stencil: 1..2 right-hand sides per launch"};
     StencilParams P{};
     P.V = (int)lat.V;
+    P.S = (int)lat.S;
     for (int d = 0; d < 4; ++d) {
         P.L[d] = lat.L[d];
         P.bcf[d] = (float)lat.bc[d];
@@ -364,13 +389,14 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
         extra_flops += (ep[r].z ? 96.0 : 0.0) + (ep[r].w ? 96.0 : 0.0) + 24.0;
     }
     const int nblk = dslash_blocks(lat);
+    P.nblk_sites = (int)((lat.V + SGN_STENCIL_THREADS - 1) / SGN_STENCIL_THREADS);
     {
         const int64_t vxyz = (int64_t)lat.L[0] * lat.L[1] * lat.L[2];
         P.sched_T = P.sched_R = 0;
         if (SGN_T_MINOR && vxyz % SGN_STENCIL_THREADS == 0 && lat.L[3] % 8 == 0) {
             P.sched_T = lat.L[3] / 8;
             P.sched_R = (int)(vxyz / SGN_STENCIL_THREADS);
-            if ((int64_t)8 * P.sched_T * P.sched_R != nblk) P.sched_T = P.sched_R = 0;
+            if ((int64_t)8 * P.sched_T * P.sched_R != P.nblk_sites) P.sched_T = P.sched_R = 0;
         }
     }
     // algorithmic bytes: every input and output spinor once, the 4 links of each
@@ -445,7 +471,7 @@ static sgn_status apply_common(sgn_lattice l, double mu, const void *in, void *o
         if (flags & SGN_INTERNAL_LAYOUT) {
             dslash_launch(lat, p, op, in, out, ep, s);
         } else {
-            const size_t bytes = spinor_bytes(lat.V, p);
+            const size_t bytes = spinor_bytes(lat.S, p);
             lat.ensure_stage(bytes);
             pack_spinor(lat, in, lat.stage_in, p, s);
             dslash_launch(lat, p, op, lat.stage_in, lat.stage_out, ep, s);

@@ -1,8 +1,9 @@
 // Device-side access to fields in the library's internal (site-fastest) layout.
 //
-//   spinor FP64 : [12][V] double2       component k = 3*spin + colour
-//   spinor FP32 : [6][V]  float4        chunk c holds components 2c and 2c+1
-//   links       : [4][9][V] of double2 / float2 / __half2, element 3*a + b of U_nu(x)
+//   spinor FP64 : [12][S] double2       component k = 3*spin + colour
+//   spinor FP32 : [6][S]  float4        chunk c holds components 2c and 2c+1
+//   links       : [4][9][S] of double2 / float2 / __half2, element 3*a + b of U_nu(x)
+// S >= V is the lattice's padded component stride; entries s >= V are zero.
 //
 // Consecutive lanes read consecutive sites of the same component, so every
 // wavefront-wide load is one contiguous 512 B .. 1 KiB segment.
@@ -32,74 +33,74 @@ __device__ __forceinline__ void st_off(T *__restrict__ base, uint32_t byte_off, 
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
-__device__ __forceinline__ void load_spinor(const double2 *__restrict__ p, int V, int s, cpx<double> v[12])
+__device__ __forceinline__ void load_spinor(const double2 *__restrict__ p, int S, int s, cpx<double> v[12])
 {
     const uint32_t off = (uint32_t)s * 16u;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        double2 t = ld_off(p + (size_t)c * V, off);
+        double2 t = ld_off(p + (size_t)c * S, off);
         v[c] = {t.x, t.y};
     }
 }
 
-__device__ __forceinline__ void load_spinor(const float4 *__restrict__ p, int V, int s, cpx<float> v[12])
+__device__ __forceinline__ void load_spinor(const float4 *__restrict__ p, int S, int s, cpx<float> v[12])
 {
     const uint32_t off = (uint32_t)s * 16u;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        float4 t = ld_off(p + (size_t)c * V, off);
+        float4 t = ld_off(p + (size_t)c * S, off);
         v[2 * c] = {t.x, t.y};
         v[2 * c + 1] = {t.z, t.w};
     }
 }
 
-__device__ __forceinline__ void store_spinor(double2 *__restrict__ p, int V, int s, const cpx<double> v[12])
+__device__ __forceinline__ void store_spinor(double2 *__restrict__ p, int S, int s, const cpx<double> v[12])
 {
     const uint32_t off = (uint32_t)s * 16u;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) st_off(p + (size_t)c * V, off, make_double2(v[c].r, v[c].i));
+    for (int c = 0; c < 12; ++c) st_off(p + (size_t)c * S, off, make_double2(v[c].r, v[c].i));
 }
 
-__device__ __forceinline__ void store_spinor(float4 *__restrict__ p, int V, int s, const cpx<float> v[12])
+__device__ __forceinline__ void store_spinor(float4 *__restrict__ p, int S, int s, const cpx<float> v[12])
 {
     const uint32_t off = (uint32_t)s * 16u;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-        st_off(p + (size_t)c * V, off, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i));
+        st_off(p + (size_t)c * S, off, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i));
 }
 
 template <typename R>
-__device__ __forceinline__ void load_link(const double2 *__restrict__ U, int V, int nu, int s, cpx<R> u[9])
+__device__ __forceinline__ void load_link(const double2 *__restrict__ U, int S, int nu, int s, cpx<R> u[9])
 {
-    const double2 *b = U + (size_t)nu * 9 * V;
+    const double2 *b = U + (size_t)nu * 9 * S;
     const uint32_t off = (uint32_t)s * 16u;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        double2 t = ld_off(b + (size_t)e * V, off);
+        double2 t = ld_off(b + (size_t)e * S, off);
         u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
     }
 }
 
 template <typename R>
-__device__ __forceinline__ void load_link(const float2 *__restrict__ U, int V, int nu, int s, cpx<R> u[9])
+__device__ __forceinline__ void load_link(const float2 *__restrict__ U, int S, int nu, int s, cpx<R> u[9])
 {
-    const float2 *b = U + (size_t)nu * 9 * V;
+    const float2 *b = U + (size_t)nu * 9 * S;
     const uint32_t off = (uint32_t)s * 8u;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        float2 t = ld_off(b + (size_t)e * V, off);
+        float2 t = ld_off(b + (size_t)e * S, off);
         u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
     }
 }
 
 template <typename R>
-__device__ __forceinline__ void load_link(const __half2 *__restrict__ U, int V, int nu, int s, cpx<R> u[9])
+__device__ __forceinline__ void load_link(const __half2 *__restrict__ U, int S, int nu, int s, cpx<R> u[9])
 {
-    const __half2 *b = U + (size_t)nu * 9 * V;
+    const __half2 *b = U + (size_t)nu * 9 * S;
     const uint32_t off = (uint32_t)s * 4u;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        float2 t = __half22float2(ld_off(b + (size_t)e * V, off));
+        float2 t = __half22float2(ld_off(b + (size_t)e * S, off));
         u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
     }
 }

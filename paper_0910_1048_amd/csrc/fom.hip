@@ -1,0 +1,259 @@
+// Restarted FOM-LR(m, k) for the Neuberger rational function (the algorithm of
+// the section "Restarted Arnoldi with rational functions", with the collinear
+// restart of Eq. (collinearity)).
+//
+// Shifted systems (A' - sigma_i) x_i = y with A' = c^2 H_W(mu)^2, y = c H_W (I-P) b.
+// One cycle: k Arnoldi steps on A' from v_1 = r/||r|| (classical Gram-Schmidt
+// applied twice; the Hessenberg columns stay on the device), then on the host
+// y_i = beta rho_i (H_k - sigma_i)^{-1} e_1 for every shift (Hessenberg LU,
+// O(k^2) each), x += V_k sum_i omega_i y_i on the device, the new collinearity
+// factors rho_i = -h_{k+1,k} e_k^T y_i, and the projection step r = (I-P) v_{k+1}.
+// Converged when every shifted residual |rho_i| ||r|| <= tol ||y||.
+#include <chrono>
+#include <complex>
+#include <vector>
+
+#include "field_io.h"
+#include "vec.h"
+
+namespace sgn {
+
+namespace {
+
+using zc = std::complex<double>;
+
+// H[:, j] = a + b (device, j+1 entries); then hsub = ||w|| and its inverse for the scaling
+__global__ void fom_hcol_kernel(const z64 *a, const z64 *b, int nj, z64 *hcol)
+{
+    for (int i = threadIdx.x; i < nj; i += blockDim.x) hcol[i] = a[i] + b[i];
+}
+
+__global__ void fom_norm_kernel(const z64 *partials, int nb, z64 *hsub, z64 *inv)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[i].r;
+    __shared__ double lds[4];
+    double v[1] = {acc};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) {
+        const double h = sqrt(v[0]);
+        *hsub = {h, 0.0};
+        *inv = {h > 0.0 ? 1.0 / h : 0.0, 0.0};
+    }
+}
+
+__global__ void fom_scale_kernel(const double2 *w, const z64 *inv, double2 *v, int64_t n)
+{
+    const double s = inv->r;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 t = w[e];
+        v[e] = make_double2(s * t.x, s * t.y);
+    }
+}
+
+// x[e] += sum_j c_j V_j[e]
+__global__ void fom_lift_kernel(const double2 *basis, int64_t n, int k, const z64 *c, double2 *x)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 xv = x[e];
+        z64 acc = {xv.x, xv.y};
+        for (int j = 0; j < k; ++j) {
+            const double2 v = basis[(int64_t)j * n + e];
+            acc = acc + c[j] * z64{v.x, v.y};
+        }
+        x[e] = make_double2(acc.r, acc.i);
+    }
+}
+
+// Solve (H - sigma I) y = rhs e_1 for a k x k upper Hessenberg H (column-major
+// hc[j*(kmax+1) + i] = H(i,j)), Gaussian elimination with partial pivoting.
+bool hessenberg_solve(const std::vector<zc> &hc, int ld, int k, double sigma, zc rhs, std::vector<zc> &y)
+{
+    std::vector<zc> A((size_t)k * k);
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < k; ++i) A[(size_t)i * k + j] = (i <= j + 1) ? hc[(size_t)j * ld + i] : zc(0, 0);
+    for (int i = 0; i < k; ++i) A[(size_t)i * k + i] -= sigma;
+    std::vector<zc> b(k, zc(0, 0));
+    b[0] = rhs;
+    for (int i = 0; i + 1 < k; ++i) {  // eliminate the subdiagonal entry of column i
+        zc *ri = &A[(size_t)i * k], *rn = &A[(size_t)(i + 1) * k];
+        if (std::abs(rn[i]) > std::abs(ri[i])) {
+            for (int j = i; j < k; ++j) std::swap(ri[j], rn[j]);
+            std::swap(b[i], b[i + 1]);
+        }
+        if (ri[i] == zc(0, 0)) return false;
+        const zc f = rn[i] / ri[i];
+        for (int j = i; j < k; ++j) rn[j] -= f * ri[j];
+        b[i + 1] -= f * b[i];
+    }
+    y.assign(k, zc(0, 0));
+    for (int i = k - 1; i >= 0; --i) {
+        zc acc = b[i];
+        for (int j = i + 1; j < k; ++j) acc -= A[(size_t)i * k + j] * y[j];
+        if (A[(size_t)i * k + i] == zc(0, 0)) return false;
+        y[i] = acc / A[(size_t)i * k + i];
+    }
+    return true;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+}  // namespace sgn
+
+using namespace sgn;
+
+extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void *b, void *x, const sgn_rational *rf,
+                                           const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *st,
+                                           void *stream)
+{
+    sgn_status result = SGN_OK;
+    sgn_status g = guard([&] {
+        const auto t_start = std::chrono::steady_clock::now();
+        SGN_REQUIRE(l && b && x && rf && o, "sign_arnoldi_rational: null argument");
+        SGN_REQUIRE(o->kmax >= 1, "sign_arnoldi_rational: kmax must be >= 1");
+        SGN_REQUIRE(o->tol > 0 && o->tol < 1, "sign_arnoldi_rational: tol must be in (0, 1)");
+        SGN_REQUIRE(rf->s >= 1 && rf->s <= SGN_MAX_POLES && rf->c > 0, "sign_arnoldi_rational: bad rational function");
+        SGN_REQUIRE(o->prec == SGN_PREC_F64, "sign_arnoldi_rational: only the FP64 form is implemented");
+        SGN_REQUIRE(std::isfinite(mu), "sign_arnoldi_rational: mu not finite");
+        Lattice &lat = *as_lattice(l);
+        Context &ctx = *lat.ctx;
+        SGN_HIP(hipSetDevice(ctx.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int k = o->kmax, ns = rf->s;
+        // internal vectors: n = 12 S entries (padded stride); canonical: nc = 12 V
+        const int64_t V = lat.V, n = 12 * lat.S, nc = 12 * V;
+        const size_t b64 = (size_t)n * 16, c64 = (size_t)nc * 16;
+        const int ld = k + 1;
+        const double c2 = rf->c * rf->c;
+        if (st) {
+            *st = sgn_stats{};
+            st->nshift = ns;
+        }
+        // workspace: basis V_{k+1}, w, t, x_int, canonical r (from the arena)
+        const size_t hbytes = sizeof(z64) * ((size_t)ld * k + 4 * (size_t)ld + 4);
+        char *arena = static_cast<char *>(ctx.ensure_arena((size_t)(k + 1) * b64 + 3 * b64 + c64 + hbytes));
+        char *Vb = arena;
+        char *w = Vb + (size_t)(k + 1) * b64, *t = w + b64, *xi = t + b64, *rcan = xi + b64;
+        z64 *Hd = reinterpret_cast<z64 *>(rcan + c64);  // column-major (k+1) x k
+        z64 *h1 = Hd + (size_t)ld * k, *h2 = h1 + ld, *cd = h2 + ld, *scal = cd + ld;  // scal: hsub, inv
+        auto Vj = [&](int j) { return Vb + (size_t)j * b64; };
+
+        deflation_prologue(ctx, defl, nc, b, x, rcan, nullptr, s);
+        OpSpec opA;
+        opA.mu = mu;
+        // y = c A r  -> V_0 (unnormalised for now)
+        pack_spinor(lat, rcan, t, SGN_PREC_F64, s);
+        {
+            Epilogue ep;
+            ep.a = rf->c;
+            dslash_launch(lat, SGN_PREC_F64, opA, t, Vj(0), ep, s);
+        }
+        const double ynorm = norm_sync(ctx, Vj(0), n, false, s);
+        SGN_REQUIRE(std::isfinite(ynorm), "sign_arnoldi_rational: b contains NaN or Inf");
+        if (ynorm == 0.0) return;
+        SGN_HIP(hipMemsetAsync(xi, 0, b64, s));
+        double beta = ynorm;
+        scale64({1.0 / beta, 0.0}, Vj(0), Vj(0), n, s);
+        std::vector<zc> rho(ns, zc(1, 0));
+        std::vector<zc> Hh((size_t)ld * k), y, comb(k);
+        const int nvb = vec_blocks(n);
+        z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nvb, 1)));
+        const int max_cycles = o->max_restarts > 0 ? o->max_restarts : 1000;
+        int cycles = 0, matvecs = 1, steps = 0;
+        double small_ms = 0.0;
+        const auto t_kry = std::chrono::steady_clock::now();
+        bool converged = false;
+        for (;;) {
+            int kk = k;
+            for (int j = 0; j < k; ++j) {
+                // w = A' v_j
+                dslash_launch(lat, SGN_PREC_F64, opA, Vj(j), t, Epilogue{}, s);
+                Epilogue ep;
+                ep.a = c2;
+                dslash_launch(lat, SGN_PREC_F64, opA, t, w, ep, s);
+                matvecs += 2;
+                // classical Gram-Schmidt, twice
+                deflate_dots(Vb, j + 1, w, n, h1, ctx, s);
+                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h1, nullptr, n, s);
+                deflate_dots(Vb, j + 1, w, n, h2, ctx, s);
+                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h2, nullptr, n, s);
+                hipLaunchKernelGGL(fom_hcol_kernel, dim3(1), dim3(256), 0, s, h1, h2, j + 1, Hd + (size_t)j * ld);
+                part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nvb, 1)));
+                const int nb = norm2_partials(w, n, false, part, s);
+                hipLaunchKernelGGL(fom_norm_kernel, dim3(1), dim3(256), 0, s, part, nb, Hd + (size_t)j * ld + j + 1,
+                                   scal + 1);
+                hipLaunchKernelGGL(fom_scale_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)w, scal + 1,
+                                   (double2 *)Vj(j + 1), n);
+                SGN_HIP(hipGetLastError());
+                ++steps;
+            }
+            // host: shifted Hessenberg systems of this cycle
+            SGN_HIP(hipMemcpyAsync(Hh.data(), Hd, sizeof(z64) * (size_t)ld * k, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j + 1 < k; ++j)
+                if (std::abs(Hh[(size_t)j * ld + j + 1]) == 0.0) {  // invariant subspace: exact solution in K_{j+1}
+                    kk = j + 1;
+                    break;
+                }
+            const auto t0 = std::chrono::steady_clock::now();
+            std::fill(comb.begin(), comb.end(), zc(0, 0));
+            const zc hnext = Hh[(size_t)(kk - 1) * ld + kk];
+            for (int i = 0; i < ns; ++i) {
+                if (!hessenberg_solve(Hh, ld, kk, rf->sigma[i], beta * rho[i], y))
+                    throw Failure{SGN_ERR_BREAKDOWN, "singular shifted Hessenberg system"};
+                for (int j = 0; j < kk; ++j) comb[j] += rf->omega[i] * y[j];
+                rho[i] = (kk < k) ? zc(0, 0) : -hnext * y[kk - 1];
+            }
+            small_ms += ms_since(t0);
+            SGN_HIP(hipMemcpyAsync(cd, comb.data(), sizeof(z64) * kk, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(fom_lift_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)Vb, n, kk, cd,
+                               (double2 *)xi);
+            ++cycles;
+            // r = (I - P) v_{k+1}  (canonical round trip for the deflation projection)
+            double rnorm = 1.0;
+            if (defl && defl->m > 0 && kk == k) {
+                unpack_spinor(lat, Vj(k), rcan, SGN_PREC_F64, s);
+                deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s);  // t = (I - P) v (canonical)
+                pack_spinor(lat, t, Vj(0), SGN_PREC_F64, s);
+                rnorm = norm_sync(ctx, Vj(0), n, false, s);
+            } else if (kk == k) {
+                SGN_HIP(hipMemcpyAsync(Vj(0), Vj(k), b64, hipMemcpyDeviceToDevice, s));
+            }
+            double worst = 0.0;
+            for (int i = 0; i < ns; ++i) {
+                const double ri = std::abs(rho[i]) * rnorm / ynorm;
+                worst = std::max(worst, ri);
+                if (st) st->shift_residual[i] = ri;
+            }
+            if (worst <= o->tol || kk < k) {
+                converged = true;
+                break;
+            }
+            if (cycles >= max_cycles) break;
+            beta = rnorm;
+            if (rnorm != 1.0) scale64({1.0 / rnorm, 0.0}, Vj(0), Vj(0), n, s);
+        }
+        // x = x_P + x_int
+        unpack_spinor(lat, xi, rcan, SGN_PREC_F64, s);
+        axpby64({1.0, 0.0}, rcan, {1.0, 0.0}, x, nc, s);
+        SGN_HIP(hipStreamSynchronize(s));
+        if (!converged) result = SGN_ERR_NOT_CONVERGED;
+        if (st) {
+            st->iterations = steps;
+            st->restarts = cycles;
+            st->matvecs = matvecs;
+            double worst = 0.0;
+            for (int i = 0; i < ns; ++i) worst = std::max(worst, st->shift_residual[i]);
+            st->residual = worst;
+            st->small_ms = small_ms;
+            st->krylov_ms = ms_since(t_kry);
+            st->total_ms = ms_since(t_start);
+        }
+    });
+    return g != SGN_OK ? g : result;
+}

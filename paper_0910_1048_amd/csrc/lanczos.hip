@@ -93,7 +93,8 @@ template <bool F32>
 __global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const void *z_, const double2 *vj,
                                                         const double2 *vjm, const double2 *wj, const double2 *wjm,
                                                         double2 *vn, double2 *wn, float4 *vn32, float4 *wn32,
-                                                        LzScalars S, int j, int V, z64 *partials)
+                                                        LzScalars S, int j, int V /* component stride */,
+                                                        z64 *partials)
 {
     // coefficients of the two three-term recurrences
     const double s0 = S.sv[j].r;
@@ -239,8 +240,9 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         SGN_HIP(hipSetDevice(ctx.device));
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int k = opts->k;
-        const int64_t V = lat.V, n = 12 * V;
-        const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8;
+        // canonical vectors have n = 12 V entries, internal ones ni = 12 S (padded stride)
+        const int64_t V = lat.V, Sst = lat.S, n = 12 * V, ni = 12 * Sst;
+        const size_t b64 = (size_t)n * 16, i64 = (size_t)ni * 16, b32 = (size_t)ni * 8;
         const bool f32 = opts->prec != SGN_PREC_F64;
         const sgn_prec sp = opts->prec;
         if (stats) *stats = sgn_stats{};
@@ -257,7 +259,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
             throw Failure{SGN_ERR_BREAKDOWN, "shadow vector orthogonal to the residual"};
 
         // workspace: basis V (k vectors), 3 W vectors, u, z (FP64 internal) + FP32 copies
-        DevBuf Vb((size_t)k * b64), Wb(3 * b64), u(b64), z(b64);
+        DevBuf Vb((size_t)k * i64), Wb(3 * i64), u(i64), z(i64);
         DevBuf v32(f32 ? b32 : 0), w32(f32 ? b32 : 0), u32(f32 ? b32 : 0), z32(f32 ? b32 : 0);
         DevBuf scal(sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k);
         LzScalars S;
@@ -275,17 +277,17 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         const z64 sv0 = {s1, 0.0};
         SGN_HIP(hipMemcpyAsync(S.sv, &sv0, sizeof(z64), hipMemcpyHostToDevice, s));
         SGN_HIP(hipMemcpyAsync(S.tw, &t1, sizeof(z64), hipMemcpyHostToDevice, s));
-        auto Vj = [&](int j) { return static_cast<char *>(Vb.p) + (size_t)j * b64; };
-        auto Wj = [&](int j) { return static_cast<char *>(Wb.p) + (size_t)(j % 3) * b64; };
+        auto Vj = [&](int j) { return static_cast<char *>(Vb.p) + (size_t)j * i64; };
+        auto Wj = [&](int j) { return static_cast<char *>(Wb.p) + (size_t)(j % 3) * i64; };
         pack_spinor(lat, r.p, Vj(0), SGN_PREC_F64, s);
         pack_spinor(lat, rt.p, Wj(0), SGN_PREC_F64, s);
         if (f32) {
-            convert_64_to_32(Vj(0), v32.p, V, s);
-            convert_64_to_32(Wj(0), w32.p, V, s);
+            convert_64_to_32(Vj(0), v32.p, Sst, s);
+            convert_64_to_32(Wj(0), w32.p, Sst, s);
         }
 
         const int nst = dslash_blocks(lat);
-        const int nvb = vec_blocks(6 * V);
+        const int nvb = vec_blocks(6 * Sst);
         z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nst, 2 * nvb)));
         OpSpec opA, opAh;
         opA.mu = mu;
@@ -339,11 +341,11 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
             if (f32)
                 hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb), dim3(256), 0, s, u32.p, z32.p,
                                    (const double2 *)Vj(j), vjm, (const double2 *)Wj(j), wjm, (double2 *)vn,
-                                   (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, S, j, (int)V, part);
+                                   (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, S, j, (int)Sst, part);
             else
                 hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb), dim3(256), 0, s, u.p, z.p,
                                    (const double2 *)Vj(j), vjm, (const double2 *)Wj(j), wjm, (double2 *)vn,
-                                   (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)V, part);
+                                   (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)Sst, part);
             hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(256), 0, s, part, nvb, S, j, 1e-14);
             SGN_HIP(hipGetLastError());
             if (opts->tol > 0 && opts->check_every > 0 && (j + 1) % opts->check_every == 0 && j + 1 < k) {
@@ -376,7 +378,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         for (int j = 0; j < kused; ++j) c[j] = (beta * hsv[j].r) * y[j];
         DevBuf cd(sizeof(z64) * kused);
         SGN_HIP(hipMemcpyAsync(cd.p, c.data(), sizeof(z64) * kused, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(lift_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, (const double2 *)Vb.p, n, kused,
+        hipLaunchKernelGGL(lift_kernel, dim3(vec_blocks(ni)), dim3(256), 0, s, (const double2 *)Vb.p, ni, kused,
                            cd.as<z64>(), (double2 *)u.p);
         unpack_spinor(lat, u.p, r.p, SGN_PREC_F64, s);
         axpby64({1.0, 0.0}, r.p, {1.0, 0.0}, x, n, s);

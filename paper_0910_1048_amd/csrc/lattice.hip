@@ -47,6 +47,9 @@ void *Context::ensure_arena(size_t bytes)
         arena = nullptr;
         arena_bytes = 0;
         if (hipMalloc(&arena, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "solver workspace"};
+        // padding entries of internal fields must read as zero in every reduction;
+        // kernels never write non-zero values there, so clearing once suffices
+        SGN_HIP(hipMemset(arena, 0, bytes));
         arena_bytes = bytes;
     }
     return arena;
@@ -77,49 +80,54 @@ template <> __device__ inline __half2 to_link<__half2>(double2 v)
 }
 
 template <typename LT>
-__global__ void pack_links_kernel(const double2 *__restrict__ canon, LT *__restrict__ out, int V)
+__global__ void pack_links_kernel(const double2 *__restrict__ canon, LT *__restrict__ out, int V, int S)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 4 * V) return;
     const int s = t / 4, nu = t % 4;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) out[((size_t)nu * 9 + e) * V + s] = to_link<LT>(canon[(size_t)t * 9 + e]);
+    for (int e = 0; e < 9; ++e) out[((size_t)nu * 9 + e) * S + s] = to_link<LT>(canon[(size_t)t * 9 + e]);
 }
 
-__global__ void pack64(const double2 *__restrict__ c, double2 *__restrict__ o, int V)
+// internal layouts: padding sites (V <= s < S) are written as zeros
+__global__ void pack64(const double2 *__restrict__ c, double2 *__restrict__ o, int V, int S)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[(size_t)k * S + s] = s < V ? c[(size_t)s * 12 + k] : make_double2(0.0, 0.0);
+}
+
+__global__ void unpack64(const double2 *__restrict__ o, double2 *__restrict__ c, int V, int S)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) o[(size_t)k * V + s] = c[(size_t)s * 12 + k];
+    for (int k = 0; k < 12; ++k) c[(size_t)s * 12 + k] = o[(size_t)k * S + s];
 }
 
-__global__ void unpack64(const double2 *__restrict__ o, double2 *__restrict__ c, int V)
+__global__ void pack32(const float2 *__restrict__ c, float4 *__restrict__ o, int V, int S)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) c[(size_t)s * 12 + k] = o[(size_t)k * V + s];
-}
-
-__global__ void pack32(const float2 *__restrict__ c, float4 *__restrict__ o, int V)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
+    if (s >= S) return;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
+        if (s >= V) {
+            o[(size_t)k * S + s] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
         float2 a = c[(size_t)s * 12 + 2 * k], b = c[(size_t)s * 12 + 2 * k + 1];
-        o[(size_t)k * V + s] = make_float4(a.x, a.y, b.x, b.y);
+        o[(size_t)k * S + s] = make_float4(a.x, a.y, b.x, b.y);
     }
 }
 
-__global__ void unpack32(const float4 *__restrict__ o, float2 *__restrict__ c, int V)
+__global__ void unpack32(const float4 *__restrict__ o, float2 *__restrict__ c, int V, int S)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float4 t = o[(size_t)k * V + s];
+        float4 t = o[(size_t)k * S + s];
         c[(size_t)s * 12 + 2 * k] = make_float2(t.x, t.y);
         c[(size_t)s * 12 + 2 * k + 1] = make_float2(t.z, t.w);
     }
@@ -129,23 +137,23 @@ __global__ void unpack32(const float4 *__restrict__ o, float2 *__restrict__ c, i
 
 void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s)
 {
-    const int V = (int)lat.V;
-    dim3 g((V + 255) / 256), b(256);
+    const int V = (int)lat.V, S = (int)lat.S;
+    dim3 g((S + 255) / 256), b(256);
     if (p == SGN_PREC_F64)
-        hipLaunchKernelGGL(pack64, g, b, 0, s, (const double2 *)canon, (double2 *)internal, V);
+        hipLaunchKernelGGL(pack64, g, b, 0, s, (const double2 *)canon, (double2 *)internal, V, S);
     else
-        hipLaunchKernelGGL(pack32, g, b, 0, s, (const float2 *)canon, (float4 *)internal, V);
+        hipLaunchKernelGGL(pack32, g, b, 0, s, (const float2 *)canon, (float4 *)internal, V, S);
     SGN_HIP(hipGetLastError());
 }
 
 void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_prec p, hipStream_t s)
 {
-    const int V = (int)lat.V;
+    const int V = (int)lat.V, S = (int)lat.S;
     dim3 g((V + 255) / 256), b(256);
     if (p == SGN_PREC_F64)
-        hipLaunchKernelGGL(unpack64, g, b, 0, s, (const double2 *)internal, (double2 *)canon, V);
+        hipLaunchKernelGGL(unpack64, g, b, 0, s, (const double2 *)internal, (double2 *)canon, V, S);
     else
-        hipLaunchKernelGGL(unpack32, g, b, 0, s, (const float4 *)internal, (float2 *)canon, V);
+        hipLaunchKernelGGL(unpack32, g, b, 0, s, (const float4 *)internal, (float2 *)canon, V, S);
     SGN_HIP(hipGetLastError());
 }
 
@@ -230,24 +238,29 @@ extern "C" sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d
         }
         lat->kappa = d->kappa;
         lat->V = V;
+        lat->S = component_stride(V);
+        const int64_t S = lat->S;
         const unsigned mask = prec_mask ? prec_mask : 7u;
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int nthr = (int)(4 * V);
         dim3 g((nthr + 255) / 256), b(256);
         if (mask & (1u << SGN_PREC_F64)) {
-            if (hipMalloc(&lat->links64, (size_t)V * 36 * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links64"};
+            if (hipMalloc(&lat->links64, (size_t)S * 36 * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links64"};
+            SGN_HIP(hipMemsetAsync(lat->links64, 0, (size_t)S * 36 * 16, s));
             hipLaunchKernelGGL(pack_links_kernel<double2>, g, b, 0, s, (const double2 *)links,
-                               (double2 *)lat->links64, (int)V);
+                               (double2 *)lat->links64, (int)V, (int)S);
         }
         if (mask & (1u << SGN_PREC_F32)) {
-            if (hipMalloc(&lat->links32, (size_t)V * 36 * 8) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links32"};
+            if (hipMalloc(&lat->links32, (size_t)S * 36 * 8) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links32"};
+            SGN_HIP(hipMemsetAsync(lat->links32, 0, (size_t)S * 36 * 8, s));
             hipLaunchKernelGGL(pack_links_kernel<float2>, g, b, 0, s, (const double2 *)links,
-                               (float2 *)lat->links32, (int)V);
+                               (float2 *)lat->links32, (int)V, (int)S);
         }
         if (mask & (1u << SGN_PREC_F32_H16)) {
-            if (hipMalloc(&lat->links16, (size_t)V * 36 * 4) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links16"};
+            if (hipMalloc(&lat->links16, (size_t)S * 36 * 4) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links16"};
+            SGN_HIP(hipMemsetAsync(lat->links16, 0, (size_t)S * 36 * 4, s));
             hipLaunchKernelGGL(pack_links_kernel<__half2>, g, b, 0, s, (const double2 *)links,
-                               (__half2 *)lat->links16, (int)V);
+                               (__half2 *)lat->links16, (int)V, (int)S);
         }
         SGN_HIP(hipGetLastError());
         SGN_HIP(hipStreamSynchronize(s));
@@ -271,7 +284,7 @@ extern "C" sgn_status sgn_lattice_destroy(sgn_lattice l)
 
 extern "C" int64_t sgn_lattice_volume(sgn_lattice l) { return l ? as_lattice(l)->V : 0; }
 
-extern "C" size_t sgn_spinor_bytes(sgn_lattice l, sgn_prec p) { return l ? spinor_bytes(as_lattice(l)->V, p) : 0; }
+extern "C" size_t sgn_spinor_bytes(sgn_lattice l, sgn_prec p) { return l ? spinor_bytes(as_lattice(l)->S, p) : 0; }
 
 extern "C" sgn_status sgn_spinor_pack(sgn_lattice l, const void *canon, void *internal, sgn_prec p, void *stream)
 {

@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, X
 }
 
 // x_hi_i += x_lo_i ; x_lo_i = 0   (FP32 layout -> FP64 layout, pair mapping)
-__global__ void ms_flush_kernel(double2 *Xhi, float4 *Xlo, int s, int V)
+__global__ void ms_flush_kernel(double2 *Xhi, float4 *Xlo, int s, int V /* component stride */)
 {
     const int64_t np = (int64_t)6 * V;
     const int64_t n = (int64_t)12 * V;
@@ -298,7 +298,8 @@ __global__ void ms_flush_kernel(double2 *Xhi, float4 *Xlo, int s, int V)
 
 // r32 = f32(y + t) (pair mapping) with partials of rt32^H r32 and ||r32||^2
 __global__ void __launch_bounds__(256) ms_reliable_kernel(const double2 *y, const double2 *t, float4 *r32,
-                                                          const float4 *rt32, int V, z64 *partials)
+                                                          const float4 *rt32, int V /* component stride */,
+                                                          z64 *partials)
 {
     const int64_t np = (int64_t)6 * V;
     double a = 0.0, b = 0.0, c = 0.0;
@@ -410,8 +411,9 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     Lattice &lat = *as_lattice(pb.lat);
     Context &ctx = *lat.ctx;
     SGN_HIP(hipSetDevice(ctx.device));
-    const int64_t V = lat.V, n = 12 * V;
-    const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8;
+    // internal vectors have n = 12 S entries (padded component stride), canonical ones nc = 12 V
+    const int64_t V = lat.V, Sst = lat.S, n = 12 * Sst, nc = 12 * V;
+    const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8, c64 = (size_t)nc * 16;
     const int ns = rf.s;
     const bool mixed = o.prec != SGN_PREC_F64;
     const double c2 = rf.c * rf.c;
@@ -423,7 +425,7 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     // workspace carved from the context's arena (kept between calls)    // per-shift solutions are kept only when the caller asks for them
     const bool keep = pb.x_shift != nullptr || o.verify;
     const int nx = keep ? ns : 2;
-    const size_t a64 = (9 + (size_t)ns + nx) * b64, a32 = mixed ? (7 + (size_t)ns + nx) * b32 : 0;
+    const size_t a64 = (8 + (size_t)ns + nx) * b64 + c64, a32 = mixed ? (7 + (size_t)ns + nx) * b32 : 0;
     char *arena = static_cast<char *>(ctx.ensure_arena(a64 + a32 + sizeof(MsState)));
     auto carve = [&](size_t bytes) {
         Span sp{arena};
@@ -436,10 +438,10 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
          q32 = carve(mixed ? b32 : 0), qt32 = carve(mixed ? b32 : 0), tmp32 = carve(mixed ? b32 : 0),
          tmpt32 = carve(mixed ? b32 : 0);    Span P32 = carve(mixed ? (size_t)ns * b32 : 0), Xlo = carve(mixed ? (size_t)nx * b32 : 0);
     MsState *S = carve(sizeof(MsState)).as<MsState>();
-    Span rcan = carve(b64);
+    Span rcan = carve(c64);
 
     // x <- x_P, r = (I - P) b (canonical)
-    deflation_prologue(ctx, pb.defl, n, pb.b, pb.x, rcan.p, nullptr, s);
+    deflation_prologue(ctx, pb.defl, nc, pb.b, pb.x, rcan.p, nullptr, s);
 
     OpSpec opA, opAh;
     opA.mu = pb.mu;
@@ -461,7 +463,7 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
 
     const int nvb = vec_blocks(n);
     const int nst = dslash_blocks(lat);
-    const int nvbp = vec_blocks(6 * V);
+    const int nvbp = vec_blocks(6 * Sst);
     z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max({nst, 2 * nvb, 2 * nvbp})));
 
     // initial state
@@ -553,7 +555,8 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         SGN_HIP(hipGetLastError());
     };
 
-    auto flush = [&]() {        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), nx, (int)V);
+    auto flush = [&]() {
+        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), nx, (int)Sst);
     };
 
     auto reliable_update = [&]() {
@@ -565,18 +568,19 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         ep.b = {sigma_seed, 0.0};
         dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, q.p, ep, s);  // q = -c^2 A A x + sigma x
         hipLaunchKernelGGL(ms_reliable_kernel, dim3(nvbp), dim3(256), 0, s, y.as<double2>(), q.as<double2>(),
-                           r32.as<float4>(), rt32.as<float4>(), (int)V, part);
+                           r32.as<float4>(), rt32.as<float4>(), (int)Sst, part);
         hipLaunchKernelGGL(ms_reliable_coef, dim3(1), dim3(256), 0, s, part, nvbp, S);
         SGN_HIP(hipGetLastError());
         ++reliable_updates;
     };
 
     auto switch_to_f32 = [&]() {
-        convert_64_to_32(r.p, r32.p, V, s);
-        convert_64_to_32(rt.p, rt32.p, V, s);
-        convert_64_to_32(pt.p, pt32.p, V, s);
+        convert_64_to_32(r.p, r32.p, Sst, s);
+        convert_64_to_32(rt.p, rt32.p, Sst, s);
+        convert_64_to_32(pt.p, pt32.p, Sst, s);
         for (int i = 0; i < ns; ++i)
-            convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, V, s);        hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
+            convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, Sst, s);
+        hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
                            (int64_t)nx * n);
         SGN_HIP(hipGetLastError());
     };
@@ -636,7 +640,7 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
         hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), nx, n,
                            tmp.as<double2>());
         unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
-        axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, n, s);
+        axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, nc, s);
         if (pb.x_shift)
             for (int i = 0; i < ns; ++i)
                 if (pb.x_shift[i]) unpack_spinor(lat, X.as<char>() + (size_t)i * b64, pb.x_shift[i], SGN_PREC_F64, s);

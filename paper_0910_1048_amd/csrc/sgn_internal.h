@@ -127,7 +127,11 @@ struct Lattice {
     int bc[4] = {1, 1, 1, -1};
     double kappa = 0.0;
     int64_t V = 0;
-    void *links64 = nullptr;  // [4][9][V] double2
+    // component stride of every internal field array, >= V (padded so that the
+    // 12 spinor and 36 link component arrays of one site do not fall into the
+    // same L2 set)
+    int64_t S = 0;
+    void *links64 = nullptr;  // [4][9][S] double2
     void *links32 = nullptr;  // [4][9][V] float2
     void *links16 = nullptr;  // [4][9][V] __half2
     // canonical <-> internal staging for wilson_apply in canonical layout
@@ -136,7 +140,16 @@ struct Lattice {
     void ensure_stage(size_t bytes);
 };
 
-inline size_t spinor_bytes(int64_t V, sgn_prec p) { return (size_t)V * 12 * (p == SGN_PREC_F64 ? 16 : 8); }
+inline size_t spinor_bytes(int64_t S, sgn_prec p) { return (size_t)S * 12 * (p == SGN_PREC_F64 ? 16 : 8); }
+
+// component stride for a lattice of V sites (a multiple of 64 sites, offset by an odd
+// multiple of 64 sites from a multiple of 128 sites for volumes where aliasing matters)
+inline int64_t component_stride(int64_t V)
+{
+    if (V < 4096) return V;
+    const int64_t r = (V + 63) / 64 * 64;
+    return r + ((r / 64) % 2 == 0 ? 320 : 256);
+}
 
 // ----------------------------------------------------------------------------- launches
 // Operator selection for one stencil application.

@@ -31,9 +31,10 @@ void axpby64(z64 a, const void *x, z64 b, void *y, int64_t n, hipStream_t s);
 // y = a * x  (complex128)
 void scale64(z64 a, const void *x, void *y, int64_t n, hipStream_t s);
 
-// precision conversion between the internal FP64 ([12][V] double2) and FP32 ([6][V] float4) spinor layouts
-void convert_64_to_32(const void *x64, void *x32, int64_t V, hipStream_t s);
-void convert_32_to_64(const void *x32, void *x64, int64_t V, hipStream_t s);
+// precision conversion between the internal FP64 ([12][S] double2) and FP32 ([6][S] float4) spinor
+// layouts (S: the lattice's component stride)
+void convert_64_to_32(const void *x64, void *x32, int64_t S, hipStream_t s);
+void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s);
 
 // LR deflation on canonical complex128 vectors of length n, with m vectors
 // stored back to back (X + i*n):

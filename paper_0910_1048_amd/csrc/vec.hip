@@ -90,24 +90,24 @@ __global__ void scale64_kernel(z64 a, const double2 *x, double2 *y, int64_t n)
     }
 }
 
-__global__ void cvt64to32(const double2 *__restrict__ x, float4 *__restrict__ y, int V)
+__global__ void cvt64to32(const double2 *__restrict__ x, float4 *__restrict__ y, int S)
 {
-    const int64_t n = (int64_t)6 * V;
+    const int64_t n = (int64_t)6 * S;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const int c2 = (int)(p / V), s = (int)(p - (int64_t)c2 * V);
-        double2 a = x[(int64_t)(2 * c2) * V + s], b = x[(int64_t)(2 * c2 + 1) * V + s];
+        const int c2 = (int)(p / S), s = (int)(p - (int64_t)c2 * S);
+        double2 a = x[(int64_t)(2 * c2) * S + s], b = x[(int64_t)(2 * c2 + 1) * S + s];
         y[p] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
     }
 }
 
-__global__ void cvt32to64(const float4 *__restrict__ x, double2 *__restrict__ y, int V)
+__global__ void cvt32to64(const float4 *__restrict__ x, double2 *__restrict__ y, int S)
 {
-    const int64_t n = (int64_t)6 * V;
+    const int64_t n = (int64_t)6 * S;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const int c2 = (int)(p / V), s = (int)(p - (int64_t)c2 * V);
+        const int c2 = (int)(p / S), s = (int)(p - (int64_t)c2 * S);
         float4 t = x[p];
-        y[(int64_t)(2 * c2) * V + s] = make_double2(t.x, t.y);
-        y[(int64_t)(2 * c2 + 1) * V + s] = make_double2(t.z, t.w);
+        y[(int64_t)(2 * c2) * S + s] = make_double2(t.x, t.y);
+        y[(int64_t)(2 * c2 + 1) * S + s] = make_double2(t.z, t.w);
     }
 }
 
@@ -225,17 +225,17 @@ void scale64(z64 a, const void *x, void *y, int64_t n, hipStream_t s)
     SGN_HIP(hipGetLastError());
 }
 
-void convert_64_to_32(const void *x64, void *x32, int64_t V, hipStream_t s)
+void convert_64_to_32(const void *x64, void *x32, int64_t S, hipStream_t s)
 {
-    hipLaunchKernelGGL(cvt64to32, dim3(vec_blocks(6 * V)), dim3(256), 0, s, (const double2 *)x64, (float4 *)x32,
-                       (int)V);
+    hipLaunchKernelGGL(cvt64to32, dim3(vec_blocks(6 * S)), dim3(256), 0, s, (const double2 *)x64, (float4 *)x32,
+                       (int)S);
     SGN_HIP(hipGetLastError());
 }
 
-void convert_32_to_64(const void *x32, void *x64, int64_t V, hipStream_t s)
+void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s)
 {
-    hipLaunchKernelGGL(cvt32to64, dim3(vec_blocks(6 * V)), dim3(256), 0, s, (const float4 *)x32, (double2 *)x64,
-                       (int)V);
+    hipLaunchKernelGGL(cvt32to64, dim3(vec_blocks(6 * S)), dim3(256), 0, s, (const float4 *)x32, (double2 *)x64,
+                       (int)S);
     SGN_HIP(hipGetLastError());
 }
 

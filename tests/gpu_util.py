@@ -10,6 +10,8 @@ _ctx = None
 def ctx():
     global _ctx
     if _ctx is None:
+        # torch owns the device memory of the tests: bring its HIP state up first
+        torch.cuda.init()
         _ctx = sgn.Context(0)
     return _ctx
 

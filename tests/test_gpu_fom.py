@@ -1,0 +1,92 @@
+"""Parity of the HIP restarted FOM-LR (sign_arnoldi_rational) with the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import WilsonRef, dense, krylov, rational
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_0910_1048_amd as sgn  # noqa: E402
+from gpu_util import dev, host, lattice  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_dense.npz")
+
+
+def _rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _fom(lat, mu, b, rf, **kw):
+    bd = dev(b)
+    x = torch.empty_like(bd)
+    st = sgn.sign_arnoldi_rational(lat, mu, bd, x, rf, **kw)
+    return host(x).ravel(), st
+
+
+@pytest.mark.parametrize("kmax", [10, 30, 60])
+def test_c1_fom_matches_dense_rational(kmax):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    x, st = _fom(lattice(U, dims), 0.3, b, rf, kmax=kmax, tol=1e-11)
+    e = _rel(x, g["g16_b"])
+    print(f"C1 FOM kmax={kmax}: vs dense g16 {e:.2e}, cycles {st['restarts']}, matvecs {st['matvecs']}, "
+          f"max res {st['residual']:.1e}", flush=True)
+    assert e < 1e-8
+
+
+def test_8x4_fom_against_oracle():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(16, 0.15, 2.6)
+    rf = sgn.sgn_rational_neuberger(16, 0.15, 2.6)
+    x, st = _fom(lattice(U, dims), 0.2, b, rf, kmax=40, tol=1e-11)
+    xo = krylov.fom_rational(lambda v: W.apply(v, 0.2), b, om, sg, c, 40, tol=1e-11)
+    e = _rel(x, xo)
+    print(f"8^4 FOM kmax=40: vs oracle {e:.2e}, cycles {st['restarts']}, {st['krylov_ms']:.1f} ms", flush=True)
+    assert e < 1e-8
+
+
+def test_deflated_fom_against_oracle():
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    H = W.dense(0.3)
+    lam, R = np.linalg.eig(H)
+    Linv = np.linalg.inv(R)
+    idx = np.argsort(np.abs(lam.real))[:8]
+    Lr, Rr, lm = Linv[idx].conj(), R[:, idx].T.copy(), lam[idx]
+    rest = np.delete(lam, idx)
+    alpha, beta = float(np.abs(rest).min()), float(np.abs(lam).max())
+    om, sg, c = rational.coefficients(12, alpha, beta)
+    rf = sgn.sgn_rational_neuberger(12, alpha, beta)
+    defl = sgn.Deflation(dev(Lr), dev(Rr), lm)
+    x, _ = _fom(lattice(U, dims), 0.3, b, rf, defl=defl, kmax=12, tol=1e-12)
+    target = krylov.deflation_xP(Lr.T, Rr.T, lm, b) + dense.rational_dense(H, krylov.project_out(Lr.T, Rr.T, b),
+                                                                             om, sg, c)
+    assert _rel(x, target) < 1e-9
+
+
+def test_fom_error_paths():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    lat = lattice(U, dims)
+    rf = sgn.sgn_rational_neuberger(8, 0.2, 2.4)
+    with pytest.raises(sgn.SgnError) as e:
+        _fom(lat, 0.3, b, rf, kmax=10, prec=sgn.F32)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _fom(lat, 0.3, b, rf, kmax=5, tol=1e-13, max_restarts=1)
+    assert e.value.status == 5
