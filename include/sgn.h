@@ -234,6 +234,9 @@ typedef struct {
     double delta;       /* reliable update when the seed residual drops by this factor (default 0.1) */
     int poll;           /* iterations between host checks of the device flags (0: automatic) */
     int verify;         /* nonzero: recompute every shifted residual in FP64 at the end (stats) */
+    int basis_slots;    /* Krylov-basis storage of the non-seed shifts (see multishift_solve):
+                           0: automatic (up to half of the device memory free at the start),
+                           > 0: at most this many stored residual vectors, < 0: never */
 } sgn_ms_opts;
 
 /* BiCG-LR(m) (section "Two-sided Lanczos with rational functions"): for each
@@ -242,10 +245,27 @@ typedef struct {
  * two-sided Lanczos sequence (seed: the shift of smallest modulus; the others
  * by the collinearity of their residuals), x = x_P + sum_i omega_i x_i.
  * Problems may live on different lattices.  stats: nprob entries or NULL.
+ * Unless per-shift solutions are requested (x_shift or verify), the non-seed
+ * shifts keep no vectors of their own: the seed residuals r_k are stored (they
+ * span the Krylov space every p_i and x_i lives in) and sum_{i != seed} omega_i x_i
+ * is formed once at the end from the scalar recurrences -- the same iterates,
+ * with one stored vector per iteration instead of a read-modify-write of every
+ * p_i.  If the stored basis would exceed basis_slots vectors the solver turns
+ * the basis into explicit p_i, x_i and continues with per-shift vectors.
  * Synchronises `stream`.  Returns SGN_ERR_NOT_CONVERGED (x holds the last
  * iterate) if maxiter is reached, SGN_ERR_BREAKDOWN on a BiCG breakdown. */
 sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                             sgn_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ accuracy measure */
+/* Accuracy of an approximate sign function S (numerical-results section): as
+ * sign(A)^2 = I, the value 1/2 ||S(S b) - b|| / ||b|| estimates the error of S
+ * without knowing sign(A) b.  The caller applies the same S twice (any of the
+ * three methods above, identical options) and passes b and ssb = S(S b), both
+ * device canonical complex128 on `lat` (12 V entries).  *acc (host) receives the
+ * value; both norms are FP64 sums in a fixed order (deterministic).
+ * Synchronises `stream`.  SGN_ERR_INVALID if ||b|| = 0 or a pointer is NULL. */
+sgn_status sgn_accuracy_measure(sgn_lattice lat, const void *b, const void *ssb, double *acc, void *stream);
 
 /* ------------------------------------------------------------------ profiling */
 /* Per-kernel-class timing of the library's own launches, measured with HIP
@@ -257,9 +277,11 @@ typedef enum {
     SGN_K_STENCIL_F64 = 0,
     SGN_K_STENCIL_F32 = 1,
     SGN_K_STENCIL_H16 = 2,
-    SGN_K_SHIFT_UPDATE = 3,   /* multishift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i */
+    SGN_K_SHIFT_UPDATE = 3,   /* multishift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i (seed only
+                                 when the basis is stored) */
     SGN_K_SEED_UPDATE = 4,    /* multishift: r, r~ updates with their inner products */
-    SGN_K_COUNT = 5
+    SGN_K_LIFT = 5,           /* multishift: sum of the stored residuals with their coefficients */
+    SGN_K_COUNT = 6
 } sgn_kernel_class;
 
 typedef struct {

@@ -232,7 +232,8 @@ class _Problem(C.Structure):
 
 class MsOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("prec", C.c_int), ("theta32", C.c_double),
-                ("theta16", C.c_double), ("delta", C.c_double), ("poll", C.c_int), ("verify", C.c_int)]
+                ("theta16", C.c_double), ("delta", C.c_double), ("poll", C.c_int), ("verify", C.c_int),
+                ("basis_slots", C.c_int)]
 
 
 lib.sgn_rational_neuberger.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(Rational)]
@@ -261,7 +262,7 @@ class Problem:
 
 
 def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
-                     delta=0.0, poll=0, verify=False, stream=None):
+                     delta=0.0, poll=0, verify=False, basis_slots=0, stream=None):
     """Multishift BiCG-LR for every problem; returns one stats dict per problem."""
     if isinstance(problems, Problem):
         problems = [problems]
@@ -280,14 +281,14 @@ def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, the
             keep.append(xs)
             arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
     o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll),
-               int(bool(verify)))
+               int(bool(verify)), int(basis_slots))
     st = (Stats * max(n, 1))()
     check(lib.multishift_solve(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_solve")
     return [st[i].as_dict() for i in range(n)]
 
 
-K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_H16, K_SHIFT_UPDATE, K_SEED_UPDATE, K_COUNT = range(6)
-KERNEL_NAMES = ["stencil_f64", "stencil_f32", "stencil_h16", "shift_update", "seed_update"]
+K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_H16, K_SHIFT_UPDATE, K_SEED_UPDATE, K_LIFT, K_COUNT = range(7)
+KERNEL_NAMES = ["stencil_f64", "stencil_f32", "stencil_h16", "shift_update", "seed_update", "basis_lift"]
 
 
 class KernelProfile(C.Structure):
@@ -341,3 +342,14 @@ def sign_arnoldi_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10
     check(lib.sign_arnoldi_rational(lat.h, float(mu), _ptr(b), _ptr(x), C.byref(rational), d, C.byref(o),
                                     C.byref(st), _stream(stream)), "sign_arnoldi_rational")
     return st.as_dict()
+
+
+lib.sgn_accuracy_measure.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_double), _vp]
+
+
+def sgn_accuracy_measure(lat, b, ssb, stream=None):
+    """1/2 ||S(S b) - b|| / ||b|| for ssb = S(S b) computed with one approximate sign S."""
+    acc = C.c_double()
+    check(lib.sgn_accuracy_measure(lat.h, _ptr(b), _ptr(ssb), C.byref(acc), _stream(stream)),
+          "sgn_accuracy_measure")
+    return acc.value

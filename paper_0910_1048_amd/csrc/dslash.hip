@@ -28,6 +28,15 @@
 #ifndef SGN_PIN_PAIR
 #define SGN_PIN_PAIR 0   // 1: both hops of a direction in flight together
 #endif
+#ifndef SGN_STENCIL_LDS
+#define SGN_STENCIL_LDS 1   // single-RHS stencil with the block's own spinors staged in LDS
+#endif
+#ifndef SGN_STAGED_STRIP
+#define SGN_STAGED_STRIP 1   // staged kernel block order: 0 = z-fastest XCD t-slabs, W > 0 = t-fastest strips of W blocks
+#endif
+#ifndef SGN_LDS_MAXBYTES
+#define SGN_LDS_MAXBYTES 64512   // dynamic LDS budget of one block of the staged stencil (64 KiB less the reduction scratch)
+#endif
 
 namespace sgn {
 
@@ -65,6 +74,7 @@ struct StencilParams {
     // walks it region by region with t fastest (sched_R spatial regions per slice)
     int sched_T, sched_R;
     int nblk_sites;  // blocks covering the V sites; later blocks zero the padding sites [V, S)
+    int blk_sites;   // staged kernel: sites per block (whole x-rows)
     RhsParams rhs[kMaxRhs];
 };
 
@@ -235,7 +245,7 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
         const int tl = j % P.sched_T, r = j / P.sched_T;
         blk = (k * P.sched_T + tl) * P.sched_R + r;
     } else {
-        blk = SGN_XCD_REMAP ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+        blk = SGN_XCD_REMAP ? xcd_block(blockIdx.x, P.nblk_sites) : (int)blockIdx.x;
     }
     const int s = blk * SGN_STENCIL_THREADS + threadIdx.x;
     const bool valid = s < P.V;
@@ -316,6 +326,226 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
     }
 }
 
+// ---------------------------------------------------------------------------- staged stencil
+// Single right-hand side.  A block owns B consecutive sites made of whole
+// x-rows (whole x-y planes when they fit), so the +-x neighbours of every site
+// and, for whole planes, the +-y neighbours too lie inside the block.  Each
+// thread loads its own spinor once (it is needed for the diagonal term anyway)
+// and stores it in LDS; a neighbour inside the block is then read from LDS and
+// only the others (+-z, +-t, block-edge rows) are gathered from memory.
+
+// largest block of the staged kernel: FP64 needs ~160 VGPRs, so at most 2 waves per SIMD
+template <typename R> constexpr int kStagedMaxThreads = sizeof(R) == 8 ? 512 : 1024;
+
+template <typename R>
+__device__ __forceinline__ void lds_store_spinor(SpT<R> *l, int B, int i, const cpx<R> v[12]);
+template <>
+__device__ __forceinline__ void lds_store_spinor<double>(double2 *l, int B, int i, const cpx<double> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) l[c * B + i] = make_double2(v[c].r, v[c].i);
+}
+template <>
+__device__ __forceinline__ void lds_store_spinor<float>(float4 *l, int B, int i, const cpx<float> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) l[c * B + i] = make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i);
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_load_spinor(const SpT<R> *l, int B, int i, cpx<R> v[12]);
+template <>
+__device__ __forceinline__ void lds_load_spinor<double>(const double2 *l, int B, int i, cpx<double> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        double2 t = l[c * B + i];
+        v[c] = {t.x, t.y};
+    }
+}
+template <>
+__device__ __forceinline__ void lds_load_spinor<float>(const float4 *l, int B, int i, cpx<float> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        float4 t = l[c * B + i];
+        v[2 * c] = {t.x, t.y};
+        v[2 * c + 1] = {t.z, t.w};
+    }
+}
+
+// neighbour spinor n: from LDS when it belongs to this block (stored already
+// multiplied by the input gamma5 sign), else from memory
+template <typename R>
+__device__ __forceinline__ void fetch_neighbour(const StencilParams &P, const SpT<R> *lds, int base, int n,
+                                                cpx<R> p[12])
+{
+    const int ln = n - base;
+    if ((unsigned)ln < (unsigned)P.blk_sites) {
+        lds_load_spinor<R>(lds, P.blk_sites, ln, p);
+    } else {
+        load_spinor(static_cast<const SpT<R> *>(P.rhs[0].in), P.S, n, p);
+        const R s5 = static_cast<R>(P.rhs[0].s5_in);
+#pragma unroll
+        for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
+    }
+}
+
+template <int NU, typename R, typename LT>
+__device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const StencilParams &P, const SpT<R> *lds,
+                                                int base, int s, int coord)
+{
+    const LT *U = static_cast<const LT *>(P.links);
+    const int L = P.L[NU], st = P.stride[NU];
+    const R kap = static_cast<R>(P.kappa);
+    cpx<R> u[9];
+    {
+        const bool wrap = coord == L - 1;
+        const int n = wrap ? s - (L - 1) * st : s + st;
+        const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
+        cpx<R> p[12], h[6], chi[6];
+        load_link<R>(U, P.S, NU, s, u);
+        fetch_neighbour<R>(P, lds, base, n, p);
+        project<NU, true>(p, h);
+        link_mul<false>(u, h, chi);
+        const R w = NU == 3 ? static_cast<R>(P.rhs[0].wf_t) : R(1);
+        accumulate<NU, true>(acc, chi, -kap * w * bcf);
+    }
+    pin(acc);
+    {
+        const bool wrap = coord == 0;
+        const int n = wrap ? s + (L - 1) * st : s - st;
+        const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
+        cpx<R> p[12], h[6], chi[6];
+        load_link<R>(U, P.S, NU, n, u);
+        fetch_neighbour<R>(P, lds, base, n, p);
+        project<NU, false>(p, h);
+        link_mul<true>(u, h, chi);
+        const R w = NU == 3 ? static_cast<R>(P.rhs[0].wb_t) : R(1);
+        accumulate<NU, false>(acc, chi, -kap * w * bcb);
+    }
+    pin(acc);
+}
+
+template <typename R, typename LT, bool kEpi, bool kDot>
+__global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(StencilParams P)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SpT<R> *lds = reinterpret_cast<SpT<R> *>(smem_raw);
+    const RhsParams &Q = P.rhs[0];
+    if ((int)blockIdx.x >= P.nblk_sites) {  // padding of the component arrays: keep it zero
+        const int s = P.V + ((int)blockIdx.x - P.nblk_sites) * (int)blockDim.x + (int)threadIdx.x;
+        if (s < P.S) {
+            cpx<R> zero[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) zero[k] = {R(0), R(0)};
+            store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, zero);
+        }
+        if constexpr (kDot) {
+            if (threadIdx.x == 0 && Q.w) Q.partials[blockIdx.x] = {0.0, 0.0};
+        }
+        return;
+    }
+    const int B = P.blk_sites;
+    int blk;
+    if (P.sched_T > 0) {
+        // XCD k owns the t-slab [k T, (k+1) T) of sched_R blocks per t-slice and
+        // walks it in strips of W consecutive blocks with t fastest, so the
+        // t-neighbours of a block run on the same XCD at about the same time
+        const int W = SGN_STAGED_STRIP;
+        const int k = blockIdx.x % 8, j = blockIdx.x / 8;
+        const int per_strip = P.sched_T * W;
+        const int strip = j / per_strip, rem = j - strip * per_strip;
+        const int tl = rem / W, wi = rem - tl * W;
+        blk = (k * P.sched_T + tl) * P.sched_R + strip * W + wi;
+    } else {
+        blk = SGN_XCD_REMAP ? xcd_block(blockIdx.x, P.nblk_sites) : (int)blockIdx.x;
+    }
+    const int base = blk * B;
+    const int i = threadIdx.x;
+    const int s = base + i;
+    const bool valid = i < B;  // blocks tile the V sites exactly
+    cpx<R> acc[12];
+    if (valid) {
+        load_spinor(static_cast<const SpT<R> *>(Q.in), P.S, s, acc);
+        const R s5 = static_cast<R>(Q.s5_in);
+#pragma unroll
+        for (int k = 6; k < 12; ++k) acc[k] = s5 * acc[k];
+        lds_store_spinor<R>(lds, B, i, acc);
+    }
+    __syncthreads();
+    double dr = 0.0, di = 0.0;
+    if (valid) {
+        int c0 = s % P.L[0];
+        int q = s / P.L[0];
+        int c1 = q % P.L[1];
+        q /= P.L[1];
+        int c2 = q % P.L[2];
+        int c3 = q / P.L[2];
+        hop_pair_staged<0, R, LT>(acc, P, lds, base, s, c0);
+        hop_pair_staged<1, R, LT>(acc, P, lds, base, s, c1);
+        hop_pair_staged<2, R, LT>(acc, P, lds, base, s, c2);
+        hop_pair_staged<3, R, LT>(acc, P, lds, base, s, c3);
+        const R s5o = static_cast<R>(Q.s5_out);
+#pragma unroll
+        for (int k = 6; k < 12; ++k) acc[k] = s5o * acc[k];
+        if constexpr (kEpi) {
+            cpx<R> sc = {static_cast<R>(Q.a), R(0)};
+            if (Q.in_scale) {
+                z64 t = *Q.in_scale;
+                sc = {static_cast<R>(Q.a * t.r), static_cast<R>(Q.a * t.i)};
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
+            if (Q.z) {
+                z64 bb = Q.b;
+                if (Q.b_dev) {
+                    z64 t = *Q.b_dev;
+                    bb = {bb.r * t.r - bb.i * t.i, bb.r * t.i + bb.i * t.r};
+                }
+                cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
+                cpx<R> zz[12];
+                load_spinor(static_cast<const SpT<R> *>(Q.z), P.S, s, zz);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = acc[k] + b * zz[k];
+            }
+        }
+        store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, acc);
+        if constexpr (kDot) {
+            if (Q.w) {
+                cpx<R> ww[12];
+                load_spinor(static_cast<const SpT<R> *>(Q.w), P.S, s, ww);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    z64 a = cast<double>(ww[k]), o = cast<double>(acc[k]);
+                    dr += a.r * o.r + a.i * o.i;
+                    di += a.r * o.i - a.i * o.r;
+                }
+            }
+        }
+    }
+    if constexpr (kDot) {
+        __shared__ double red[2 * 16];
+        if (Q.w) {  // uniform
+            double v[2] = {dr, di};
+            block_sum<2>(v, red);
+            if (threadIdx.x == 0) Q.partials[blockIdx.x] = {v[0], v[1]};
+        }
+    }
+}
+
+template <typename R, typename LT>
+void launch_staged(const StencilParams &P, int nblk, int threads, size_t lds, bool epi, bool dot, hipStream_t s)
+{
+    dim3 g(nblk), b(threads);
+    if (dot)
+        hipLaunchKernelGGL((stencil_staged_kernel<R, LT, true, true>), g, b, lds, s, P);
+    else if (epi)
+        hipLaunchKernelGGL((stencil_staged_kernel<R, LT, true, false>), g, b, lds, s, P);
+    else
+        hipLaunchKernelGGL((stencil_staged_kernel<R, LT, false, false>), g, b, lds, s, P);
+}
+
 template <typename R, typename LT, int NR>
 void launch_typed(const StencilParams &P, int nblk, bool epi, bool dot, hipStream_t s)
 {
@@ -340,12 +570,60 @@ void launch_nr(const StencilParams &P, int nr, int nblk, bool epi, bool dot, hip
 
 }  // namespace
 
+namespace {
+
+// Block shape of the staged kernel: B sites of whole x-rows (whole x-y planes
+// when they fit the LDS budget), B dividing V; not used when B < 64.
+struct StagedPlan {
+    bool ok = false;
+    int B = 0, threads = 0, nblk_sites = 0, nblk = 0;
+    size_t lds = 0;
+};
+
+StagedPlan staged_plan(const Lattice &lat, sgn_prec p)
+{
+    StagedPlan pl;
+    if (!SGN_STENCIL_LDS) return pl;
+    const int64_t site_bytes = p == SGN_PREC_F64 ? 192 : 96;
+    const int64_t bmax = std::min<int64_t>(p == SGN_PREC_F64 ? kStagedMaxThreads<double> : kStagedMaxThreads<float>,
+                                           SGN_LDS_MAXBYTES / site_bytes);
+    const int64_t Lx = lat.L[0], A = (int64_t)lat.L[0] * lat.L[1];
+    const int64_t nplane = (int64_t)lat.L[2] * lat.L[3];
+    int64_t B = 0;
+    if (A <= bmax) {
+        int64_t P = bmax / A;
+        while (nplane % P) --P;
+        B = P * A;
+    } else {
+        int64_t rows = bmax / Lx;
+        const int64_t nrows = (int64_t)lat.L[1] * nplane;
+        while (rows > 0 && nrows % rows) --rows;
+        B = rows * Lx;
+    }
+    if (B < 64) return pl;
+    pl.ok = true;
+    pl.B = (int)B;
+    pl.threads = (int)((B + 63) / 64 * 64);
+    pl.nblk_sites = (int)(lat.V / B);
+    const int64_t pad = lat.S > lat.V ? (lat.S - lat.V + pl.threads - 1) / pl.threads : 0;
+    pl.nblk = pl.nblk_sites + (int)pad;
+    pl.lds = (size_t)B * site_bytes;
+    return pl;
+}
+
+}  // namespace
+
 int dslash_blocks(const Lattice &lat)
 {
     const int64_t t = SGN_STENCIL_THREADS;
     const int64_t valid = (lat.V + t - 1) / t;
     const int64_t pad = lat.S > lat.V ? (lat.S - lat.V + t - 1) / t : 0;  // padding sites [V, S)
-    return (int)(valid + pad);
+    int n = (int)(valid + pad);
+    for (sgn_prec p : {SGN_PREC_F64, SGN_PREC_F32}) {
+        const StagedPlan pl = staged_plan(lat, p);
+        if (pl.ok) n = std::max(n, pl.nblk);
+    }
+    return n;
 }
 
 int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
@@ -405,22 +683,44 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
     const double lb = (p == SGN_PREC_F64) ? 144.0 : (p == SGN_PREC_F32 ? 72.0 : 36.0);
     const double site_bytes = 2 * sb * nr + 4 * lb + extra_bytes;
     const double site_flops = 1368.0 * nr + extra_flops;
+    const StagedPlan pl = nr == 1 ? staged_plan(lat, p) : StagedPlan{};
+    int nlaunch = nblk;
+    if (pl.ok) {
+        P.blk_sites = pl.B;
+        P.nblk_sites = pl.nblk_sites;
+        nlaunch = pl.nblk;
+        P.sched_T = P.sched_R = 0;
+        const int64_t v3 = (int64_t)lat.L[0] * lat.L[1] * lat.L[2];
+        if (SGN_STAGED_STRIP > 0 && v3 % pl.B == 0 && lat.L[3] % 8 == 0 && (v3 / pl.B) % SGN_STAGED_STRIP == 0) {
+            P.sched_T = lat.L[3] / 8;
+            P.sched_R = (int)(v3 / pl.B);
+        }
+    }
     const int prof = lat.ctx->prof_start(s);
     switch (p) {
     case SGN_PREC_F64:
         if (!lat.links64) throw Failure{SGN_ERR_INVALID, "lattice has no FP64 links"};
         P.links = lat.links64;
-        launch_nr<double, double2>(P, nr, nblk, epi, dot, s);
+        if (pl.ok)
+            launch_staged<double, double2>(P, nlaunch, pl.threads, pl.lds, epi, dot, s);
+        else
+            launch_nr<double, double2>(P, nr, nblk, epi, dot, s);
         break;
     case SGN_PREC_F32:
         if (!lat.links32) throw Failure{SGN_ERR_INVALID, "lattice has no FP32 links"};
         P.links = lat.links32;
-        launch_nr<float, float2>(P, nr, nblk, epi, dot, s);
+        if (pl.ok)
+            launch_staged<float, float2>(P, nlaunch, pl.threads, pl.lds, epi, dot, s);
+        else
+            launch_nr<float, float2>(P, nr, nblk, epi, dot, s);
         break;
     case SGN_PREC_F32_H16:
         if (!lat.links16) throw Failure{SGN_ERR_INVALID, "lattice has no FP16 links"};
         P.links = lat.links16;
-        launch_nr<float, __half2>(P, nr, nblk, epi, dot, s);
+        if (pl.ok)
+            launch_staged<float, __half2>(P, nlaunch, pl.threads, pl.lds, epi, dot, s);
+        else
+            launch_nr<float, __half2>(P, nr, nblk, epi, dot, s);
         break;
     default:
         throw Failure{SGN_ERR_INVALID, "unknown precision"};
@@ -428,7 +728,7 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
     SGN_HIP(hipGetLastError());
     lat.ctx->prof_stop(prof, s, p == SGN_PREC_F64 ? SGN_K_STENCIL_F64 : (p == SGN_PREC_F32 ? SGN_K_STENCIL_F32 : SGN_K_STENCIL_H16),
                        site_bytes * lat.V, site_flops * lat.V);
-    return nblk;
+    return nlaunch;
 }
 
 int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,

@@ -26,6 +26,7 @@
 //   x_i += alpha_i p_i;  p_i = zeta_{k+1} r + beta_i p_i;  p~ = r~ + conj(beta) p~
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <vector>
 
 #include "field_io.h"
@@ -49,6 +50,12 @@ struct MsState {
     double omega[kS];
     double res[kS];
     int act[kS], act_next[kS];
+};
+
+// Scalars of iteration k for shift i (zero when the shift was frozen): the
+// stored-basis form rebuilds p_i and x_i from them.
+struct MsHist {
+    z64 alpha, beta, zeta;  // alpha_i^(k), beta_i^(k), zeta_i^(k+1)
 };
 
 __device__ __forceinline__ z64 cdiv(z64 a, z64 b)
@@ -101,9 +108,11 @@ __global__ void __launch_bounds__(256) ms_alpha_kernel(const z64 *partials, int 
     }
 }
 
-__global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int nb, MsState *S)
+__global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int nb, MsState *S, MsHist *hist,
+                                                      int hist_cap)
 {
     if (S->h.done) return;
+    const int k = S->h.iter;  // this iteration (read before thread 0 advances it)
     double a = 0.0, b = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         a += partials[2 * i].r;
@@ -146,11 +155,16 @@ __global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int n
     const z64 beta = beta_sh;
     const double rn = rn_sh;
     const double lim = S->h.tol * S->h.ynorm;
+    MsHist *hk = (hist && k < hist_cap) ? hist + (int64_t)k * S->h.nshift : nullptr;
     for (int i = threadIdx.x; i < S->h.nshift; i += blockDim.x) {
-        if (!S->act[i]) continue;
+        if (!S->act[i]) {
+            if (hk) hk[i] = MsHist{{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+            continue;
+        }
         const z64 zn = S->zeta_next[i], z = S->zeta[i];
         const z64 q = cdiv(zn, z);
         S->beta_i[i] = beta * (q * q);
+        if (hk) hk[i] = MsHist{S->alpha_i[i], S->beta_i[i], zn};
         S->zeta_prev[i] = z;
         S->zeta[i] = zn;
         const double ri = sqrt(norm2(zn)) * rn;
@@ -182,21 +196,24 @@ template <typename T> __device__ __forceinline__ z64 ldz(const T *p, int64_t i)
 __device__ __forceinline__ void stz(double2 *p, int64_t i, z64 v) { p[i] = make_double2(v.r, v.i); }
 __device__ __forceinline__ void stz(float2 *p, int64_t i, z64 v) { p[i] = make_float2((float)v.r, (float)v.i); }
 
+// r_out = r_in - alpha q (r_out may be r_in, or the next stored-basis slot),
+// r~ -= conj(alpha) q~, with partials of r~^H r_out and ||r_out||^2
 template <typename R>
-__global__ void __launch_bounds__(256) ms_seed_update(typename VecT<R>::t *r, typename VecT<R>::t *rt,
-                                                      const typename VecT<R>::t *q, const typename VecT<R>::t *qt,
-                                                      int64_t n, const MsState *S, z64 *partials)
+__global__ void __launch_bounds__(256) ms_seed_update(const typename VecT<R>::t *r_in, typename VecT<R>::t *r_out,
+                                                      typename VecT<R>::t *rt, const typename VecT<R>::t *q,
+                                                      const typename VecT<R>::t *qt, int64_t n, const MsState *S,
+                                                      z64 *partials)
 {
     if (S->h.done) return;
     const z64 al = S->h.alpha, alc = conj(al);
     double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        z64 rv = ldz(r, e) - al * ldz(q, e);
+        z64 rv = ldz(r_in, e) - al * ldz(q, e);
         z64 tv = ldz(rt, e) - alc * ldz(qt, e);
-        stz(r, e, rv);
+        stz(r_out, e, rv);
         stz(rt, e, tv);
         if constexpr (sizeof(R) == 4) {  // reduce what is stored
-            rv = ldz(r, e);
+            rv = ldz(r_out, e);
             tv = ldz(rt, e);
         }
         const z64 d = cmulc(tv, rv);
@@ -274,6 +291,71 @@ __global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, X
         }
         if (!KEEP && any_rest) stz(X + n, e, ldz(X + n, e) + rest);
         stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
+    }
+}
+
+// Stored-basis form: only the seed keeps vectors,
+//   x_seed += alpha p_seed;  p_seed = r + beta p_seed;  p~ = r~ + conj(beta) p~
+// (zeta = 1 and alpha_i = alpha, beta_i = beta for the seed; the values are
+// taken from the shift arrays all the same).
+template <typename R, typename XT>
+__global__ void __launch_bounds__(256) ms_seed_xp_update(typename VecT<R>::t *P, XT *X, const typename VecT<R>::t *r,
+                                                         const typename VecT<R>::t *rt, typename VecT<R>::t *pt,
+                                                         int64_t n, const MsState *S, int expect,
+                                                         unsigned long long *byte_counter)
+{
+    if (S->h.breakdown || S->h.iter != expect) return;
+    const int seed = S->h.seed;
+    const z64 al = S->alpha_i[seed], be = S->beta_i[seed], ze = S->zeta[seed], bc = conj(S->h.beta);
+    if (byte_counter && blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long eb = sizeof(typename VecT<R>::t), xb = sizeof(XT);
+        atomicAdd(byte_counter, (unsigned long long)n * (6ull * eb + 2ull * xb));
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const z64 p = ldz(P, e);
+        stz(X, e, ldz(X, e) + al * p);
+        stz(P, e, ze * ldz(r, e) + be * p);
+        stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
+    }
+}
+
+// out (+)= sum_j coef_j v_j over up to kLiftChunk stored vectors, FP64 or FP32 each.
+// out and FP64 vectors use the [12][S] double2 layout; an FP32 vector is [6][S]
+// float4, i.e. component c of site st is float2 entry 2 ((c/2) S + st) + c%2.
+constexpr int kLiftChunk = 256;
+struct LiftSlot {
+    const void *p;
+    int f32;
+    int pad;
+};
+
+__global__ void __launch_bounds__(256) ms_lift_kernel(const LiftSlot *slots, const z64 *coef, int K, int Sst,
+                                                      double2 *out, int accumulate)
+{
+    __shared__ LiftSlot sl[kLiftChunk];
+    __shared__ z64 cf[kLiftChunk];
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        sl[j] = slots[j];
+        cf[j] = coef[j];
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)12 * Sst;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int comp = (int)(e / Sst), st = (int)(e - (int64_t)comp * Sst);
+        const int64_t e32 = 2 * ((int64_t)(comp >> 1) * Sst + st) + (comp & 1);
+        z64 acc = {0.0, 0.0};
+        if (accumulate) {
+            const double2 o = out[e];
+            acc = {o.x, o.y};
+        }
+        for (int j = 0; j < K; ++j) {
+            const z64 c = cf[j];
+            if (c.r == 0.0 && c.i == 0.0) continue;  // uniform
+            const z64 v = sl[j].f32 ? ldz(static_cast<const float2 *>(sl[j].p), e32)
+                                    : ldz(static_cast<const double2 *>(sl[j].p), e);
+            acc = acc + c * v;
+        }
+        out[e] = make_double2(acc.r, acc.i);
     }
 }
 
@@ -403,6 +485,35 @@ double ms_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Coefficients of the stored residuals r_0..r_k for shift i from the scalar
+// history (iterations 0..k-1):
+//   p_i^(k) = sum_{j<=k} a_j r_j,  a_j = zeta^(j) prod_{l=j}^{k-1} beta^(l)
+//   x_i^(k) = sum_{j<k}  c_j r_j,  c_j = zeta^(j) g^(j),  g^(j) = alpha^(j) + beta^(j) g^(j+1),  g^(k) = 0
+// where zeta^(0) = 1 and zeta^(j) is the zeta recorded at iteration j-1.
+void basis_coefficients(const std::vector<MsHist> &H, int ns, int k, int i, std::vector<z64> *c,
+                        std::vector<z64> *a)
+{
+    auto zeta = [&](int j) -> z64 { return j == 0 ? z64{1.0, 0.0} : H[(size_t)(j - 1) * ns + i].zeta; };
+    if (c) {
+        c->assign(k, z64{0.0, 0.0});
+        z64 g = {0.0, 0.0};
+        for (int j = k - 1; j >= 0; --j) {
+            const MsHist &h = H[(size_t)j * ns + i];
+            g = h.alpha + h.beta * g;
+            (*c)[j] = zeta(j) * g;
+        }
+    }
+    if (a) {
+        a->assign(k + 1, z64{0.0, 0.0});
+        (*a)[k] = zeta(k);
+        z64 prod = {1.0, 0.0};
+        for (int j = k - 1; j >= 0; --j) {
+            prod = prod * H[(size_t)j * ns + i].beta;
+            (*a)[j] = zeta(j) * prod;
+        }
+    }
+}
+
 // One problem of multishift_solve.
 sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, sgn_stats *st,
                      hipStream_t s)
@@ -421,24 +532,45 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     for (int i = 1; i < ns; ++i)
         if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed])) seed = i;
     const double s1 = rf.sigma[seed];
+    const int maxiter = o.maxiter > 0 ? o.maxiter : 10000;
 
-    // workspace carved from the context's arena (kept between calls)    // per-shift solutions are kept only when the caller asks for them
-    const bool keep = pb.x_shift != nullptr || o.verify;
-    const int nx = keep ? ns : 2;
-    const size_t a64 = (8 + (size_t)ns + nx) * b64 + c64, a32 = mixed ? (7 + (size_t)ns + nx) * b32 : 0;
-    char *arena = static_cast<char *>(ctx.ensure_arena(a64 + a32 + sizeof(MsState)));
+    // Stored-basis form unless per-shift solutions are wanted: slots 1..slot_cap
+    // may hold residuals r_j (slot 0 is y itself).
+    const bool want_shifts = pb.x_shift != nullptr || o.verify;
+    int slot_cap = 0;
+    if (!want_shifts && o.basis_slots >= 0) {
+        if (o.basis_slots > 0) {
+            slot_cap = o.basis_slots;
+        } else {
+            size_t fr = 0, tot = 0;
+            SGN_HIP(hipMemGetInfo(&fr, &tot));
+            slot_cap = (int)std::min<double>(1e9, 0.5 * (double)(fr + ctx.basis_bytes()) / (double)b64);
+        }
+        slot_cap = std::min(slot_cap, maxiter);
+    }
+    bool explicit_mode = slot_cap < 1;
+    const int np0 = explicit_mode ? ns : 1;  // p and x vectors held in the arena
+    const size_t hist_bytes = explicit_mode ? 0 : (size_t)slot_cap * ns * sizeof(MsHist);
+
+    // workspace carved from the context's arena (kept between calls)
+    const size_t a64 = (8 + 2 * (size_t)np0) * b64 + c64, a32 = mixed ? (7 + 2 * (size_t)np0) * b32 : 0;
+    char *arena = static_cast<char *>(ctx.ensure_arena(a64 + a32 + hist_bytes + sizeof(MsState)));
     auto carve = [&](size_t bytes) {
         Span sp{arena};
         arena += bytes;
         return sp;
     };
     Span y = carve(b64), r = carve(b64), rt = carve(b64), pt = carve(b64), q = carve(b64), qt = carve(b64),
-         tmp = carve(b64), tmpt = carve(b64);    Span X = carve((size_t)nx * b64), P = carve((size_t)ns * b64);
+         tmp = carve(b64), tmpt = carve(b64);
+    Span X = carve((size_t)np0 * b64), P = carve((size_t)np0 * b64);
     Span r32 = carve(mixed ? b32 : 0), rt32 = carve(mixed ? b32 : 0), pt32 = carve(mixed ? b32 : 0),
          q32 = carve(mixed ? b32 : 0), qt32 = carve(mixed ? b32 : 0), tmp32 = carve(mixed ? b32 : 0),
-         tmpt32 = carve(mixed ? b32 : 0);    Span P32 = carve(mixed ? (size_t)ns * b32 : 0), Xlo = carve(mixed ? (size_t)nx * b32 : 0);
+         tmpt32 = carve(mixed ? b32 : 0);
+    Span P32 = carve(mixed ? (size_t)np0 * b32 : 0), Xlo = carve(mixed ? (size_t)np0 * b32 : 0);
+    MsHist *hist = carve(hist_bytes).as<MsHist>();
     MsState *S = carve(sizeof(MsState)).as<MsState>();
     Span rcan = carve(c64);
+    std::unique_ptr<DevMem> xp64, xp32;  // per-shift vectors after a change to explicit form
 
     // x <- x_P, r = (I - P) b (canonical)
     deflation_prologue(ctx, pb.defl, nc, pb.b, pb.x, rcan.p, nullptr, s);
@@ -476,11 +608,12 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     h0.h.delta = o.delta > 0 ? o.delta : 0.1;
     h0.h.theta32 = mixed ? (o.theta32 > 0 ? o.theta32 : 1e-3) : 0.0;
     h0.h.theta16 = (o.prec == SGN_PREC_F32_H16) ? (o.theta16 > 0 ? o.theta16 : 1e-6) : 0.0;
-    h0.h.maxiter = o.maxiter > 0 ? o.maxiter : 10000;
+    h0.h.maxiter = maxiter;
     h0.h.nshift = ns;
     h0.h.seed = seed;
     for (int i = 0; i < ns; ++i) {
-        h0.zeta[i] = h0.zeta_prev[i] = {1.0, 0.0};        h0.tau[i] = s1 - rf.sigma[i];
+        h0.zeta[i] = h0.zeta_prev[i] = {1.0, 0.0};
+        h0.tau[i] = s1 - rf.sigma[i];
         h0.omega[i] = rf.omega[i];
         h0.act_next[i] = 1;
         h0.res[i] = ynorm;
@@ -489,8 +622,9 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     SGN_HIP(hipMemcpyAsync(r.p, y.p, b64, hipMemcpyDeviceToDevice, s));
     SGN_HIP(hipMemcpyAsync(rt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
     SGN_HIP(hipMemcpyAsync(pt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s, y.as<double2>(), P.as<double2>(), ns, n);    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s, X.as<double2>(), make_double2(0, 0),
-                       (int64_t)nx * n);
+    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s, y.as<double2>(), P.as<double2>(), np0, n);
+    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s, X.as<double2>(), make_double2(0, 0),
+                       (int64_t)np0 * n);
     SGN_HIP(hipGetLastError());
 
     int phase = 0;
@@ -498,16 +632,32 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     int reliable_updates = 0;
     const double sigma_seed = s1;
 
+    // stored basis: slot j holds the residual r_j written by iteration j-1
+    std::vector<char> slot_f32(1, 0);
+    auto slot_ptr = [&](int j) -> void * { return j == 0 ? y.p : ctx.basis[(size_t)j - 1]; };
+    void *cur = y.p;  // residual the next seed update starts from (basis form)
+
     int launched = 0;  // iteration number of the next launch minus one (synced with the device at polls)
     auto iterate = [&](int count) {
         for (int it = 0; it < count; ++it) {
             ++launched;
             const bool lo = phase >= 1;
             const sgn_prec sp = phase == 0 ? SGN_PREC_F64 : (phase == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16);
-            void *pseed = lo ? (void *)(P32.as<char>() + (size_t)seed * b32) : (void *)(P.as<char>() + (size_t)seed * b64);
-            void *vr = lo ? r32.p : r.p, *vrt = lo ? rt32.p : rt.p, *vpt = lo ? pt32.p : pt.p;
+            const size_t pso = explicit_mode ? (size_t)seed : 0;  // seed's index in P / X
+            void *pseed = lo ? (void *)(P32.as<char>() + pso * b32) : (void *)(P.as<char>() + pso * b64);
+            void *vrt = lo ? rt32.p : rt.p, *vpt = lo ? pt32.p : pt.p;
             void *vq = lo ? q32.p : q.p, *vqt = lo ? qt32.p : qt.p, *vtmp = lo ? tmp32.p : tmp.p,
                  *vtmpt = lo ? tmpt32.p : tmpt.p;
+            void *rin, *rout;
+            if (explicit_mode) {
+                rin = rout = lo ? r32.p : r.p;
+            } else {
+                rin = cur;
+                rout = slot_ptr(launched);
+                if ((int)slot_f32.size() <= launched) slot_f32.resize(launched + 1, 0);
+                slot_f32[launched] = lo ? 1 : 0;
+                cur = rout;
+            }
             dslash_launch(lat, sp, opA, pseed, vtmp, Epilogue{}, s);
             Epilogue e1;
             e1.a = c2;
@@ -527,40 +677,48 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
             const double eb = lo ? 8.0 : 16.0;
             int pr = ctx.prof_start(s);
             if (lo)
-                hipLaunchKernelGGL(ms_seed_update<float>, dim3(nvb), dim3(256), 0, s, (float2 *)vr, (float2 *)vrt,
-                                   (const float2 *)vq, (const float2 *)vqt, n, S, part);
+                hipLaunchKernelGGL(ms_seed_update<float>, dim3(nvb), dim3(256), 0, s, (const float2 *)rin,
+                                   (float2 *)rout, (float2 *)vrt, (const float2 *)vq, (const float2 *)vqt, n, S, part);
             else
-                hipLaunchKernelGGL(ms_seed_update<double>, dim3(nvb), dim3(256), 0, s, (double2 *)vr,
-                                   (double2 *)vrt, (const double2 *)vq, (const double2 *)vqt, n, S, part);
+                hipLaunchKernelGGL(ms_seed_update<double>, dim3(nvb), dim3(256), 0, s, (const double2 *)rin,
+                                   (double2 *)rout, (double2 *)vrt, (const double2 *)vq, (const double2 *)vqt, n, S,
+                                   part);
             ctx.prof_stop(pr, s, SGN_K_SEED_UPDATE, 6.0 * eb * n, 40.0 * n);
-            hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S);
-            pr = ctx.prof_start(s);            if (lo && keep)
-                hipLaunchKernelGGL((ms_shift_update<float, float2, true>), dim3(nvb), dim3(256), 0, s, P32.as<float2>(),
-                                   Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt, (float2 *)vpt, n, S,
-                                   launched, bc);
-            else if (lo)
-                hipLaunchKernelGGL((ms_shift_update<float, float2, false>), dim3(nvb), dim3(256), 0, s,
-                                   P32.as<float2>(), Xlo.as<float2>(), (const float2 *)vr, (const float2 *)vrt,
+            hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S,
+                               explicit_mode ? nullptr : hist, explicit_mode ? 0 : slot_cap);
+            pr = ctx.prof_start(s);
+            if (!explicit_mode) {
+                if (lo)
+                    hipLaunchKernelGGL((ms_seed_xp_update<float, float2>), dim3(nvb), dim3(256), 0, s,
+                                       P32.as<float2>(), Xlo.as<float2>(), (const float2 *)rout, (const float2 *)vrt,
+                                       (float2 *)vpt, n, S, launched, bc);
+                else
+                    hipLaunchKernelGGL((ms_seed_xp_update<double, double2>), dim3(nvb), dim3(256), 0, s,
+                                       P.as<double2>(), X.as<double2>(), (const double2 *)rout, (const double2 *)vrt,
+                                       (double2 *)vpt, n, S, launched, bc);
+            } else if (lo) {
+                hipLaunchKernelGGL((ms_shift_update<float, float2, true>), dim3(nvb), dim3(256), 0, s,
+                                   P32.as<float2>(), Xlo.as<float2>(), (const float2 *)rout, (const float2 *)vrt,
                                    (float2 *)vpt, n, S, launched, bc);
-            else if (keep)
+            } else {
                 hipLaunchKernelGGL((ms_shift_update<double, double2, true>), dim3(nvb), dim3(256), 0, s,
-                                   P.as<double2>(), X.as<double2>(), (const double2 *)vr, (const double2 *)vrt,
+                                   P.as<double2>(), X.as<double2>(), (const double2 *)rout, (const double2 *)vrt,
                                    (double2 *)vpt, n, S, launched, bc);
-            else
-                hipLaunchKernelGGL((ms_shift_update<double, double2, false>), dim3(nvb), dim3(256), 0, s,
-                                   P.as<double2>(), X.as<double2>(), (const double2 *)vr, (const double2 *)vrt,
-                                   (double2 *)vpt, n, S, launched, bc);
+            }
             ctx.prof_stop(pr, s, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
         }
         SGN_HIP(hipGetLastError());
     };
 
+    auto nxv = [&]() { return explicit_mode ? ns : 1; };
     auto flush = [&]() {
-        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), nx, (int)Sst);
+        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), nxv(),
+                           (int)Sst);
     };
 
     auto reliable_update = [&]() {
-        flush();        double2 *xs = X.as<double2>() + (keep ? (size_t)seed * n : 0);
+        flush();
+        double2 *xs = X.as<double2>() + (explicit_mode ? (size_t)seed * n : 0);
         dslash_launch(lat, SGN_PREC_F64, opA, xs, tmp.p, Epilogue{}, s);
         Epilogue ep;
         ep.a = -c2;
@@ -571,18 +729,94 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
                            r32.as<float4>(), rt32.as<float4>(), (int)Sst, part);
         hipLaunchKernelGGL(ms_reliable_coef, dim3(1), dim3(256), 0, s, part, nvbp, S);
         SGN_HIP(hipGetLastError());
+        if (!explicit_mode) cur = r32.p;
         ++reliable_updates;
     };
 
     auto switch_to_f32 = [&]() {
-        convert_64_to_32(r.p, r32.p, Sst, s);
+        convert_64_to_32(explicit_mode ? r.p : cur, r32.p, Sst, s);
+        if (!explicit_mode) cur = r32.p;
         convert_64_to_32(rt.p, rt32.p, Sst, s);
         convert_64_to_32(pt.p, pt32.p, Sst, s);
-        for (int i = 0; i < ns; ++i)
+        for (int i = 0; i < nxv(); ++i)
             convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, Sst, s);
         hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
-                           (int64_t)nx * n);
+                           (int64_t)nxv() * n);
         SGN_HIP(hipGetLastError());
+    };
+
+    // out (+)= sum_j coef[j] slot_j over slots 0..K-1
+    auto lift = [&](const std::vector<z64> &coef, void *out, bool accumulate) {
+        const int K = (int)coef.size();
+        std::vector<LiftSlot> hs(K);
+        double bytes = accumulate ? 2.0 * b64 : (double)b64;
+        for (int j = 0; j < K; ++j) {
+            hs[j] = LiftSlot{slot_ptr(j), slot_f32[j], 0};
+            bytes += (coef[j].r != 0.0 || coef[j].i != 0.0) ? (slot_f32[j] ? (double)b32 : (double)b64) : 0.0;
+        }
+        DevMem dsl(sizeof(LiftSlot) * std::max(K, 1)), dcf(sizeof(z64) * std::max(K, 1));
+        SGN_HIP(hipMemcpy(dsl.p, hs.data(), sizeof(LiftSlot) * K, hipMemcpyHostToDevice));
+        SGN_HIP(hipMemcpy(dcf.p, coef.data(), sizeof(z64) * K, hipMemcpyHostToDevice));
+        const int pr = ctx.prof_start(s);
+        bool acc = accumulate;
+        for (int j0 = 0; j0 < K || (j0 == 0 && !acc); j0 += kLiftChunk) {
+            const int kk = std::min(kLiftChunk, K - j0);
+            hipLaunchKernelGGL(ms_lift_kernel, dim3(nvb), dim3(256), 0, s, dsl.as<LiftSlot>() + j0,
+                               dcf.as<z64>() + j0, kk, (int)Sst, static_cast<double2 *>(out), acc ? 1 : 0);
+            acc = true;
+            if (K == 0) break;
+        }
+        SGN_HIP(hipGetLastError());
+        ctx.prof_stop(pr, s, SGN_K_LIFT, bytes, 8.0 * n * K);
+        SGN_HIP(hipStreamSynchronize(s));  // dsl, dcf go out of scope
+    };
+    auto history = [&](int k) {
+        std::vector<MsHist> H((size_t)k * ns);
+        if (k > 0) SGN_HIP(hipMemcpy(H.data(), hist, sizeof(MsHist) * H.size(), hipMemcpyDeviceToHost));
+        return H;
+    };
+
+    // Turn the stored basis into explicit p_i, x_i at iteration k = launched
+    // (all launched iterations have run) and continue with per-shift vectors.
+    auto to_explicit = [&]() {
+        const int k = launched;
+        const std::vector<MsHist> H = history(k);
+        xp64 = std::make_unique<DevMem>(2 * (size_t)ns * b64);
+        if (mixed) xp32 = std::make_unique<DevMem>(2 * (size_t)ns * b32);
+        Span Xn{xp64->p}, Pn{xp64->as<char>() + (size_t)ns * b64};
+        Span Xlon{mixed ? xp32->p : nullptr}, P32n{mixed ? xp32->as<char>() + (size_t)ns * b32 : nullptr};
+        if (phase >= 1) flush();
+        std::vector<z64> cj, aj;
+        for (int i = 0; i < ns; ++i) {
+            char *xi = Xn.as<char>() + (size_t)i * b64, *pi = Pn.as<char>() + (size_t)i * b64;
+            if (i == seed) {
+                SGN_HIP(hipMemcpyAsync(xi, X.p, b64, hipMemcpyDeviceToDevice, s));
+                if (phase >= 1)
+                    SGN_HIP(hipMemcpyAsync(P32n.as<char>() + (size_t)i * b32, P32.p, b32, hipMemcpyDeviceToDevice, s));
+                else
+                    SGN_HIP(hipMemcpyAsync(pi, P.p, b64, hipMemcpyDeviceToDevice, s));
+                continue;
+            }
+            basis_coefficients(H, ns, k, i, &cj, &aj);
+            lift(cj, xi, false);
+            lift(aj, pi, false);
+            if (phase >= 1) convert_64_to_32(pi, P32n.as<char>() + (size_t)i * b32, Sst, s);
+        }
+        if (mixed)
+            hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlon.as<float2>(), make_float2(0, 0),
+                               (int64_t)ns * n);
+        // the explicit form keeps the current residual in r (FP64) or r32
+        if (phase >= 1) {
+            if (cur != r32.p) SGN_HIP(hipMemcpyAsync(r32.p, cur, b32, hipMemcpyDeviceToDevice, s));
+        } else {
+            SGN_HIP(hipMemcpyAsync(r.p, cur, b64, hipMemcpyDeviceToDevice, s));
+        }
+        SGN_HIP(hipStreamSynchronize(s));
+        X = Xn;
+        P = Pn;
+        Xlo = Xlon;
+        P32 = P32n;
+        explicit_mode = true;
     };
 
     MsHead hh{};
@@ -605,8 +839,15 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     const auto t_kry = std::chrono::steady_clock::now();
     sgn_status result = SGN_OK;
     for (;;) {
+        if (!explicit_mode) {
+            // slots for the next chunk; past the budget the basis becomes explicit vectors
+            const int upto = launched + poll;
+            if (upto > slot_cap || !ctx.ensure_basis(upto - 1, b64)) to_explicit();
+        }
+        const int iter_before = launched;
         iterate(poll);
         read_head();
+        if (!explicit_mode && hh.iter > iter_before) cur = slot_ptr(hh.iter);
         if (hh.breakdown) throw Failure{SGN_ERR_BREAKDOWN, "multishift BiCG breakdown at iteration " + std::to_string(hh.iter)};
         if (hh.done) {
             if (phase >= 1) {
@@ -614,7 +855,7 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
                 read_head();
                 if (!hh.done) continue;
             }
-            if (hh.iter >= h0.h.maxiter && hh.rnorm > o.tol * ynorm) result = SGN_ERR_NOT_CONVERGED;
+            if (hh.iter >= maxiter && hh.rnorm > o.tol * ynorm) result = SGN_ERR_NOT_CONVERGED;
             break;
         }
         if (mixed && hh.want_phase > phase) {
@@ -634,11 +875,27 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     const double kry_ms = ms_since(t_kry);
 
     // x += sum_i omega_i x_i
-    {        DevMem w(sizeof(double) * ns);
-        const double wh[2] = {rf.omega[seed], 1.0};
-        SGN_HIP(hipMemcpyAsync(w.p, keep ? rf.omega : wh, sizeof(double) * nx, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), nx, n,
-                           tmp.as<double2>());
+    {
+        if (explicit_mode) {
+            DevMem w(sizeof(double) * ns);
+            SGN_HIP(hipMemcpy(w.p, rf.omega, sizeof(double) * ns, hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), ns, n,
+                               tmp.as<double2>());
+            SGN_HIP(hipGetLastError());
+            SGN_HIP(hipStreamSynchronize(s));
+        } else {
+            // omega_seed x_seed + sum_j d_j r_j,  d_j = sum_{i != seed} omega_i c_ij
+            const int K = launched;
+            const std::vector<MsHist> H = history(K);
+            std::vector<z64> d(K, z64{0.0, 0.0}), cj;
+            for (int i = 0; i < ns; ++i) {
+                if (i == seed) continue;
+                basis_coefficients(H, ns, K, i, &cj, nullptr);
+                for (int j = 0; j < K; ++j) d[j] = d[j] + rf.omega[i] * cj[j];
+            }
+            scale64({rf.omega[seed], 0.0}, X.p, tmp.p, n, s);
+            lift(d, tmp.p, true);
+        }
         unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
         axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, nc, s);
         if (pb.x_shift)

@@ -119,6 +119,12 @@ struct Context {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     void *ensure_arena(size_t bytes);
+    // stored Krylov vectors of the multishift solver (slot j >= 1), kept between calls;
+    // ensure_basis returns false when slot j cannot be allocated
+    std::vector<void *> basis;
+    size_t basis_slot_bytes = 0;
+    bool ensure_basis(int j, size_t bytes);
+    size_t basis_bytes() const { return basis.size() * basis_slot_bytes; }
 };
 
 struct Lattice {

@@ -159,6 +159,22 @@ __global__ void mcombine_kernel(double2 *y, z64 alpha, z64 beta, const double2 *
     }
 }
 
+// partials[block] = ( sum |y - x|^2 , sum |x|^2 ) over the block's slice
+__global__ void __launch_bounds__(256) diff_norm_kernel(const double2 *x, const double2 *y, int64_t n, z64 *partials)
+{
+    double d = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double2 a = x[i], c = y[i];
+        const double er = c.x - a.x, ei = c.y - a.y;
+        d += er * er + ei * ei;
+        b += a.x * a.x + a.y * a.y;
+    }
+    __shared__ double lds[8];
+    double v[2] = {d, b};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = {v[0], v[1]};
+}
+
 }  // namespace
 
 int dot_partials(const void *x, const void *y, int64_t n, bool f32, z64 *partials, hipStream_t s)
@@ -258,3 +274,26 @@ void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z
 }
 
 }  // namespace sgn
+
+extern "C" sgn_status sgn_accuracy_measure(sgn_lattice l, const void *b, const void *ssb, double *acc, void *stream)
+{
+    using namespace sgn;
+    return guard([&] {
+        SGN_REQUIRE(l && b && ssb && acc, "sgn_accuracy_measure: null argument");
+        Lattice &lat = *as_lattice(l);
+        SGN_HIP(hipSetDevice(lat.ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t n = 12 * lat.V;
+        z64 *part = static_cast<z64 *>(lat.ctx->ensure_partials((kMaxBlocks + 1) * sizeof(z64)));
+        const int nb = vec_blocks(n);
+        hipLaunchKernelGGL(diff_norm_kernel, dim3(nb), dim3(256), 0, s, (const double2 *)b, (const double2 *)ssb,
+                           n, part);
+        SGN_HIP(hipGetLastError());
+        finalize_sum(part, nb, part + kMaxBlocks, s);
+        z64 h;
+        SGN_HIP(hipMemcpyAsync(&h, part + kMaxBlocks, sizeof(z64), hipMemcpyDeviceToHost, s));
+        SGN_HIP(hipStreamSynchronize(s));
+        SGN_REQUIRE(h.i > 0.0, "sgn_accuracy_measure: b is zero");
+        *acc = 0.5 * std::sqrt(h.r / h.i);
+    });
+}

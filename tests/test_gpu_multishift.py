@@ -169,3 +169,40 @@ def test_error_paths():
     with pytest.raises(sgn.SgnError) as e:
         _solve(lat, 0.3, b, rf, tol=1e-12, maxiter=3)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32_H16])
+def test_stored_basis_equals_per_shift_vectors(prec):
+    """The stored-basis form and the per-shift-vector form are the same iteration."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    lat = lattice(U, dims)
+    xb, sb = _solve(lat, 0.3, b, rf, tol=1e-10, prec=prec)
+    xe, se = _solve(lat, 0.3, b, rf, tol=1e-10, prec=prec, basis_slots=-1)
+    print(f"prec={prec}: basis vs per-shift {_rel(xb, xe):.2e}; vs dense g16 {_rel(xb, g['g16_b']):.2e} / "
+          f"{_rel(xe, g['g16_b']):.2e}; iterations {sb['iterations']} / {se['iterations']}", flush=True)
+    # the update kernels round differently (FMA contraction), and BiCG turns ulp-level
+    # differences into a few iterations more or less; the results agree to tolerance
+    assert abs(sb["iterations"] - se["iterations"]) <= 0.1 * se["iterations"]
+    assert _rel(xb, xe) < 1e-9
+    assert _rel(xb, g["g16_b"]) < 1e-8 and _rel(xe, g["g16_b"]) < 1e-8
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+def test_basis_budget_fallback(prec):
+    """A basis budget smaller than the iteration count: the solver rebuilds p_i, x_i
+    from the stored residuals mid-solve and finishes with per-shift vectors."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    lat = lattice(U, dims)
+    for slots in (10, 37):
+        x, st = _solve(lat, 0.3, b, rf, tol=1e-10, prec=prec, basis_slots=slots, poll=4)
+        e = _rel(x, g["g16_b"])
+        print(f"prec={prec} basis_slots={slots}: vs dense g16 {e:.2e}, iterations {st['iterations']}", flush=True)
+        assert e < 1e-8

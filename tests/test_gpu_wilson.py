@@ -30,7 +30,10 @@ def _run(lat, mu, b, prec, dag=False, flags=0):
     return host(y).astype(np.complex128)
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 8, 10), (3, 5, 2, 7), (8, 8, 8, 16)])
+# shapes cover: whole-plane blocks of the staged kernel, partial planes (FP64 at
+# 32x16), blocks below one wavefront (generic kernel), padded component stride
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 8, 10), (3, 5, 2, 7), (8, 8, 8, 16), (12, 12, 12, 12),
+                                  (32, 16, 4, 4), (2, 2, 2, 4)])
 @pytest.mark.parametrize("mu", [0.0, 0.3, -0.2])
 @pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
 def test_wilson_apply_matches_oracle(dims, mu, prec):
@@ -130,9 +133,10 @@ def test_invalid_arguments_are_rejected():
 
 @pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
 @pytest.mark.parametrize("nrhs", [1, 2, 3])
-def test_multi_rhs_stencil(prec, nrhs):
+@pytest.mark.parametrize("dims", [(4, 6, 4, 8), (12, 12, 12, 12)])
+def test_multi_rhs_stencil(prec, nrhs, dims):
     """wilson_apply_multi: right-hand sides with their own mu sharing link loads."""
-    dims = (4, 6, 4, 8)
+    print(f"case multi dims={dims} nrhs={nrhs} prec={prec}", flush=True)
     U = synth.gauge_field(dims, 0.5, 1)
     ref = WilsonRef(U, dims, 0.2)
     lat = lattice(U, dims)

@@ -5,7 +5,7 @@ import os
 import numpy as np
 
 import synth
-from oracle import WilsonRef, krylov, rational
+from oracle import WilsonRef, dense, krylov, rational
 
 from conftest import rel
 
@@ -47,3 +47,20 @@ def test_unconverged_lanczos_amplifies_rounding():
     d320 = rel(krylov.lanczos_sign(A, Ah, bp, 320), krylov.lanczos_sign(A, Ah, b, 320))
     assert 1e-9 < d200 < 3e-7
     assert d320 < 1e-9
+
+
+def test_accuracy_measure_tracks_the_rational_error():
+    # g_16 is a rational function of A, so S = sign(A) + E with E commuting with
+    # sign(A) and S^2 - I = 2 sign(A) E + E^2: half the defect of S^2 b is the
+    # error of S b to first order (numerical-results section)
+    g = np.load(GOLD)
+    b = synth.gaussian_source((4, 4, 4, 4), 0).ravel()
+    err = np.linalg.norm(g["g16_b"] - g["sign_b"]) / np.linalg.norm(b)
+    acc = float(g["acc16"])
+    assert 0.5 < acc / err < 2.0
+    assert abs(0.5 * np.linalg.norm(g["g16_g16_b"] - b) / np.linalg.norm(b) - acc) < 1e-20
+    # the exact sign squares to the identity
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)) + 3 * np.diag(np.sign(rng.standard_normal(12)))
+    v = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    assert krylov.accuracy_measure(lambda w: dense.sign_eig(A, w), v) < 1e-12
