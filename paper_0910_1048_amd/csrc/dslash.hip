@@ -75,6 +75,7 @@ struct StencilParams {
     int sched_T, sched_R;
     int nblk_sites;  // blocks covering the V sites; later blocks zero the padding sites [V, S)
     int blk_sites;   // staged kernel: sites per block (whole x-rows)
+    int nblk_total;  // blocks of this application (sites + padding); batched launches skip the rest
     RhsParams rhs[kMaxRhs];
 };
 
@@ -428,13 +429,13 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
 }
 
 template <typename R, typename LT, bool kEpi, bool kDot>
-__global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(StencilParams P)
+__device__ __forceinline__ void staged_body(const StencilParams &P, const int bx)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SpT<R> *lds = reinterpret_cast<SpT<R> *>(smem_raw);
     const RhsParams &Q = P.rhs[0];
-    if ((int)blockIdx.x >= P.nblk_sites) {  // padding of the component arrays: keep it zero
-        const int s = P.V + ((int)blockIdx.x - P.nblk_sites) * (int)blockDim.x + (int)threadIdx.x;
+    if (bx >= P.nblk_sites) {  // padding of the component arrays: keep it zero
+        const int s = P.V + (bx - P.nblk_sites) * (int)blockDim.x + (int)threadIdx.x;
         if (s < P.S) {
             cpx<R> zero[12];
 #pragma unroll
@@ -442,7 +443,7 @@ __global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(St
             store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, zero);
         }
         if constexpr (kDot) {
-            if (threadIdx.x == 0 && Q.w) Q.partials[blockIdx.x] = {0.0, 0.0};
+            if (threadIdx.x == 0 && Q.w) Q.partials[bx] = {0.0, 0.0};
         }
         return;
     }
@@ -453,13 +454,13 @@ __global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(St
         // walks it in strips of W consecutive blocks with t fastest, so the
         // t-neighbours of a block run on the same XCD at about the same time
         const int W = SGN_STAGED_STRIP;
-        const int k = blockIdx.x % 8, j = blockIdx.x / 8;
+        const int k = bx % 8, j = bx / 8;
         const int per_strip = P.sched_T * W;
         const int strip = j / per_strip, rem = j - strip * per_strip;
         const int tl = rem / W, wi = rem - tl * W;
         blk = (k * P.sched_T + tl) * P.sched_R + strip * W + wi;
     } else {
-        blk = SGN_XCD_REMAP ? xcd_block(blockIdx.x, P.nblk_sites) : (int)blockIdx.x;
+        blk = SGN_XCD_REMAP ? xcd_block(bx, P.nblk_sites) : bx;
     }
     const int base = blk * B;
     const int i = threadIdx.x;
@@ -529,9 +530,27 @@ __global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(St
         if (Q.w) {  // uniform
             double v[2] = {dr, di};
             block_sum<2>(v, red);
-            if (threadIdx.x == 0) Q.partials[blockIdx.x] = {v[0], v[1]};
+            if (threadIdx.x == 0) Q.partials[bx] = {v[0], v[1]};
         }
     }
+}
+
+template <typename R, typename LT, bool kEpi, bool kDot>
+__global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(StencilParams P)
+{
+    staged_body<R, LT, kEpi, kDot>(P, (int)blockIdx.x);
+}
+
+// Batched form: blockIdx.y selects one of several independent applications
+// (own lattice, fields and epilogue) whose parameters live in device memory.
+// gridDim.x is a multiple of 8, so the XCD of block (x, y) is x mod 8 as in
+// the single form.
+template <typename R, typename LT, bool kEpi, bool kDot>
+__global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_batch(const StencilParams *__restrict__ plist)
+{
+    const StencilParams P = plist[blockIdx.y];
+    if ((int)blockIdx.x >= P.nblk_total) return;
+    staged_body<R, LT, kEpi, kDot>(P, (int)blockIdx.x);
 }
 
 template <typename R, typename LT>
@@ -626,11 +645,24 @@ int dslash_blocks(const Lattice &lat)
     return n;
 }
 
-int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
-                        void *const *out, const Epilogue *ep, hipStream_t s)
+namespace {
+
+// Everything about one stencil application except the launch itself.
+struct PreparedStencil {
+    StencilParams P{};
+    StagedPlan pl;
+    int nblk = 0;       // blocks of the launch (= partials written when dotting)
+    double bytes = 0.0;  // algorithmic bytes and flops
+    double flops = 0.0;
+    bool epi = false, dot = false;
+};
+
+PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
+                                void *const *out, const Epilogue *ep)
 {
     if (nr < 1 || nr > kMaxRhs) throw Failure{SGN_ERR_INVALID, "stencil: 1..2 right-hand sides per launch"};
-    StencilParams P{};
+    PreparedStencil ps;
+    StencilParams &P = ps.P;
     P.V = (int)lat.V;
     P.S = (int)lat.S;
     for (int d = 0; d < 4; ++d) {
@@ -642,7 +674,6 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
     P.stride[2] = lat.L[0] * lat.L[1];
     P.stride[3] = lat.L[0] * lat.L[1] * lat.L[2];
     P.kappa = lat.kappa;
-    bool dot = false, epi = false;
     double extra_bytes = 0.0, extra_flops = 0.0;
     const double sb = (p == SGN_PREC_F64) ? 192.0 : 96.0;
     for (int r = 0; r < nr; ++r) {
@@ -661,12 +692,15 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
         Q.partials = ep[r].partials;
         Q.in_scale = ep[r].in_scale;
         if (ep[r].w && !ep[r].partials) throw Failure{SGN_ERR_INVALID, "stencil dot without partial buffer"};
-        dot = dot || ep[r].w != nullptr;
-        epi = epi || ep[r].w != nullptr || ep[r].z != nullptr || ep[r].a != 1.0 || ep[r].in_scale != nullptr;
+        ps.dot = ps.dot || ep[r].w != nullptr;
+        ps.epi = ps.epi || ep[r].w != nullptr || ep[r].z != nullptr || ep[r].a != 1.0 || ep[r].in_scale != nullptr;
         extra_bytes += (ep[r].z ? sb : 0.0) + (ep[r].w ? sb : 0.0);
         extra_flops += (ep[r].z ? 96.0 : 0.0) + (ep[r].w ? 96.0 : 0.0) + 24.0;
     }
-    const int nblk = dslash_blocks(lat);
+    {
+        const int64_t t = SGN_STENCIL_THREADS;
+        ps.nblk = (int)((lat.V + t - 1) / t + (lat.S > lat.V ? (lat.S - lat.V + t - 1) / t : 0));
+    }
     P.nblk_sites = (int)((lat.V + SGN_STENCIL_THREADS - 1) / SGN_STENCIL_THREADS);
     {
         const int64_t vxyz = (int64_t)lat.L[0] * lat.L[1] * lat.L[2];
@@ -681,54 +715,145 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
     // site once (shared by the right-hand sides), plus the epilogue operands;
     // 1368 flop per site and right-hand side for the stencil itself
     const double lb = (p == SGN_PREC_F64) ? 144.0 : (p == SGN_PREC_F32 ? 72.0 : 36.0);
-    const double site_bytes = 2 * sb * nr + 4 * lb + extra_bytes;
-    const double site_flops = 1368.0 * nr + extra_flops;
-    const StagedPlan pl = nr == 1 ? staged_plan(lat, p) : StagedPlan{};
-    int nlaunch = nblk;
-    if (pl.ok) {
-        P.blk_sites = pl.B;
-        P.nblk_sites = pl.nblk_sites;
-        nlaunch = pl.nblk;
+    ps.bytes = (2 * sb * nr + 4 * lb + extra_bytes) * lat.V;
+    ps.flops = (1368.0 * nr + extra_flops) * lat.V;
+    ps.pl = nr == 1 ? staged_plan(lat, p) : StagedPlan{};
+    if (ps.pl.ok) {
+        P.blk_sites = ps.pl.B;
+        P.nblk_sites = ps.pl.nblk_sites;
+        ps.nblk = ps.pl.nblk;
         P.sched_T = P.sched_R = 0;
         const int64_t v3 = (int64_t)lat.L[0] * lat.L[1] * lat.L[2];
-        if (SGN_STAGED_STRIP > 0 && v3 % pl.B == 0 && lat.L[3] % 8 == 0 && (v3 / pl.B) % SGN_STAGED_STRIP == 0) {
+        if (SGN_STAGED_STRIP > 0 && v3 % ps.pl.B == 0 && lat.L[3] % 8 == 0 && (v3 / ps.pl.B) % SGN_STAGED_STRIP == 0) {
             P.sched_T = lat.L[3] / 8;
-            P.sched_R = (int)(v3 / pl.B);
+            P.sched_R = (int)(v3 / ps.pl.B);
         }
     }
+    P.nblk_total = ps.nblk;
+    switch (p) {
+    case SGN_PREC_F64: P.links = lat.links64; break;
+    case SGN_PREC_F32: P.links = lat.links32; break;
+    case SGN_PREC_F32_H16: P.links = lat.links16; break;
+    default: throw Failure{SGN_ERR_INVALID, "unknown precision"};
+    }
+    if (!P.links)
+        throw Failure{SGN_ERR_INVALID, p == SGN_PREC_F64 ? "lattice has no FP64 links"
+                                                         : (p == SGN_PREC_F32 ? "lattice has no FP32 links"
+                                                                              : "lattice has no FP16 links")};
+    return ps;
+}
+
+int kclass(sgn_prec p)
+{
+    return p == SGN_PREC_F64 ? SGN_K_STENCIL_F64 : (p == SGN_PREC_F32 ? SGN_K_STENCIL_F32 : SGN_K_STENCIL_H16);
+}
+
+template <typename R, typename LT>
+void launch_staged_batch(const StencilParams *dev, int count, int gx, int threads, size_t lds, bool epi, bool dot,
+                         hipStream_t s)
+{
+    dim3 g(gx, count), b(threads);
+    if (dot)
+        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, true>), g, b, lds, s, dev);
+    else if (epi)
+        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, false>), g, b, lds, s, dev);
+    else
+        hipLaunchKernelGGL((stencil_staged_batch<R, LT, false, false>), g, b, lds, s, dev);
+}
+
+}  // namespace
+
+int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
+                        void *const *out, const Epilogue *ep, hipStream_t s)
+{
+    const PreparedStencil ps = prepare_stencil(lat, p, nr, op, in, out, ep);
     const int prof = lat.ctx->prof_start(s);
     switch (p) {
     case SGN_PREC_F64:
-        if (!lat.links64) throw Failure{SGN_ERR_INVALID, "lattice has no FP64 links"};
-        P.links = lat.links64;
-        if (pl.ok)
-            launch_staged<double, double2>(P, nlaunch, pl.threads, pl.lds, epi, dot, s);
+        if (ps.pl.ok)
+            launch_staged<double, double2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s);
         else
-            launch_nr<double, double2>(P, nr, nblk, epi, dot, s);
+            launch_nr<double, double2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s);
         break;
     case SGN_PREC_F32:
-        if (!lat.links32) throw Failure{SGN_ERR_INVALID, "lattice has no FP32 links"};
-        P.links = lat.links32;
-        if (pl.ok)
-            launch_staged<float, float2>(P, nlaunch, pl.threads, pl.lds, epi, dot, s);
+        if (ps.pl.ok)
+            launch_staged<float, float2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s);
         else
-            launch_nr<float, float2>(P, nr, nblk, epi, dot, s);
-        break;
-    case SGN_PREC_F32_H16:
-        if (!lat.links16) throw Failure{SGN_ERR_INVALID, "lattice has no FP16 links"};
-        P.links = lat.links16;
-        if (pl.ok)
-            launch_staged<float, __half2>(P, nlaunch, pl.threads, pl.lds, epi, dot, s);
-        else
-            launch_nr<float, __half2>(P, nr, nblk, epi, dot, s);
+            launch_nr<float, float2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s);
         break;
     default:
-        throw Failure{SGN_ERR_INVALID, "unknown precision"};
+        if (ps.pl.ok)
+            launch_staged<float, __half2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s);
+        else
+            launch_nr<float, __half2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s);
+        break;
     }
     SGN_HIP(hipGetLastError());
-    lat.ctx->prof_stop(prof, s, p == SGN_PREC_F64 ? SGN_K_STENCIL_F64 : (p == SGN_PREC_F32 ? SGN_K_STENCIL_F32 : SGN_K_STENCIL_H16),
-                       site_bytes * lat.V, site_flops * lat.V);
-    return nlaunch;
+    lat.ctx->prof_stop(prof, s, kclass(p), ps.bytes, ps.flops);
+    return ps.nblk;
+}
+
+StencilBatch::~StencilBatch()
+{
+    if (dev_) (void)hipFree(dev_);
+}
+
+void StencilBatch::prepare(const std::vector<StencilJob> &jobs, sgn_prec p)
+{
+    jobs_ = jobs;
+    prec_ = p;
+    nblk_.assign(jobs.size(), 0);
+    batched_ = !jobs.empty();
+    epi_ = dot_ = false;
+    gx_ = threads_ = 0;
+    lds_ = 0;
+    bytes_ = flops_ = 0.0;
+    std::vector<StencilParams> host(jobs.size());
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        const StencilJob &j = jobs[k];
+        const PreparedStencil ps = prepare_stencil(*j.lat, p, 1, &j.op, &j.in, &j.out, &j.ep);
+        host[k] = ps.P;
+        nblk_[k] = ps.nblk;
+        batched_ = batched_ && ps.pl.ok;
+        epi_ = epi_ || ps.epi;
+        dot_ = dot_ || ps.dot;
+        gx_ = std::max(gx_, ps.nblk);
+        threads_ = std::max(threads_, ps.pl.threads);
+        lds_ = std::max(lds_, ps.pl.lds);
+        bytes_ += ps.bytes;
+        flops_ += ps.flops;
+    }
+    gx_ = (gx_ + 7) / 8 * 8;
+    if (!batched_) return;
+    const size_t need = sizeof(StencilParams) * host.size();
+    if (need > dev_bytes_) {
+        if (dev_) SGN_HIP(hipFree(dev_));
+        dev_ = nullptr;
+        dev_bytes_ = 0;
+        if (hipMalloc(&dev_, need) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "stencil batch parameters"};
+        dev_bytes_ = need;
+    }
+    SGN_HIP(hipMemcpy(dev_, host.data(), need, hipMemcpyHostToDevice));
+}
+
+void StencilBatch::launch(hipStream_t s) const
+{
+    if (jobs_.empty()) return;
+    if (!batched_) {  // some lattice has no staged block shape: one launch per application
+        for (const StencilJob &j : jobs_) dslash_launch(*j.lat, prec_, j.op, j.in, j.out, j.ep, s);
+        return;
+    }
+    Context *ctx = jobs_[0].lat->ctx;
+    const int prof = ctx->prof_start(s);
+    const StencilParams *d = static_cast<const StencilParams *>(dev_);
+    const int cnt = (int)jobs_.size();
+    switch (prec_) {
+    case SGN_PREC_F64: launch_staged_batch<double, double2>(d, cnt, gx_, threads_, lds_, epi_, dot_, s); break;
+    case SGN_PREC_F32: launch_staged_batch<float, float2>(d, cnt, gx_, threads_, lds_, epi_, dot_, s); break;
+    default: launch_staged_batch<float, __half2>(d, cnt, gx_, threads_, lds_, epi_, dot_, s); break;
+    }
+    SGN_HIP(hipGetLastError());
+    ctx->prof_stop(prof, s, kclass(prec_), bytes_, flops_);
 }
 
 int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,

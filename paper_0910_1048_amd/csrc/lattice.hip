@@ -55,25 +55,6 @@ void *Context::ensure_arena(size_t bytes)
     return arena;
 }
 
-bool Context::ensure_basis(int j, size_t bytes)
-{
-    if (bytes > basis_slot_bytes) {
-        SGN_HIP(hipDeviceSynchronize());
-        for (void *b : basis) SGN_HIP(hipFree(b));
-        basis.clear();
-        basis_slot_bytes = bytes;
-    }
-    while ((int)basis.size() <= j) {
-        void *b = nullptr;
-        if (hipMalloc(&b, basis_slot_bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        basis.push_back(b);
-    }
-    return true;
-}
-
 void Lattice::ensure_stage(size_t bytes)
 {
     if (bytes <= stage_bytes) return;
@@ -224,7 +205,8 @@ extern "C" sgn_status sgn_finalize(sgn_handle h)
         if (c->scalars) SGN_HIP(hipFree(c->scalars));
         if (c->arena) SGN_HIP(hipFree(c->arena));
         if (c->byte_counter) SGN_HIP(hipFree(c->byte_counter));
-        for (void *b : c->basis) SGN_HIP(hipFree(b));
+        for (auto &kv : c->basis_pools)
+            for (void *b : kv.second) SGN_HIP(hipFree(b));
         for (auto &r : c->prof_recs) {
             (void)hipEventDestroy(r.start);
             (void)hipEventDestroy(r.stop);

@@ -6,23 +6,36 @@
 // r~_0 = r_0.  The other shifts, M + tau_i (tau_i = sigma_1 - sigma_i), keep
 // residuals collinear with the seed's, r^i_k = zeta^i_k r_k, with zeta from the
 // three-term recurrence of the seed's residual polynomial.  Converged shifts
-// are frozen (no more memory traffic).
+// are frozen.
+//
+// Two forms of the same iteration:
+//  * stored basis (default when per-shift solutions are not requested): every
+//    seed residual r_k is kept in its own slot; p_i and x_i of the non-seed
+//    shifts are linear combinations of the r_k whose coefficients follow from
+//    the recorded scalars, so only the seed keeps p and x, and the
+//    omega-weighted sum of the other solutions is one lift at the end;
+//  * per-shift vectors: p_i and x_i of every shift are updated each iteration.
 //
 // Precision schedule (mixed mode): while the seed residual is above theta32
-// ||y|| everything is FP64; below it the vectors p_i, r, r~, p~ and the stencil
-// drop to FP32 and the solutions accumulate in FP32 increments that are folded
-// into FP64 x_i at every reliable update (true seed residual in FP64).  Below
-// theta16 the stencil may also switch to FP16 links.  Rounding injected at a
-// given iteration is proportional to the residual size at that point, so the
+// ||y|| everything is FP64; below it the vectors and the stencil drop to FP32
+// and the solutions accumulate in FP32 increments that are folded into FP64 at
+// every reliable update (true seed residual in FP64).  Below theta16 the
+// stencil may also switch to FP16 links.  Rounding injected at a given
+// iteration is proportional to the residual size at that point, so the
 // shifted systems -- which get no reliable update -- keep residuals at the
 // 1e-10 level without a separate refinement phase.
 //
-// Per iteration (all scalars on the device, host polls flags every few iterations):
+// Batching: all problems of one call iterate in lockstep.  Each step of an
+// iteration is one launch over every problem in the same precision phase
+// (blockIdx.y selects the problem, whose pointers sit in a device-side
+// descriptor); the host polls all of them every few iterations.
+//
+// Per iteration (all scalars on the device):
 //   tmp = A p;  q = c^2 A tmp - sigma_1 p   (+ partials of p~^H q)
 //   tmp~ = A^H p~;  q~ = c^2 A^H tmp~ - sigma_1 p~
-//   alpha = rho / p~^H q;  zeta^i_{k+1}, alpha_i          (1 block)
-//   r -= alpha q;  r~ -= conj(alpha) q~   (+ partials of r~^H r, ||r||^2)
-//   beta = rho'/rho;  beta_i = beta (zeta_{k+1}/zeta_k)^2; convergence flags (1 block)
+//   alpha = rho / p~^H q;  zeta^i_{k+1}, alpha_i          (1 block per problem)
+//   r_{k+1} = r_k - alpha q;  r~ -= conj(alpha) q~   (+ partials of r~^H r, ||r||^2)
+//   beta = rho'/rho;  beta_i = beta (zeta_{k+1}/zeta_k)^2; convergence flags
 //   x_i += alpha_i p_i;  p_i = zeta_{k+1} r + beta_i p_i;  p~ = r~ + conj(beta) p~
 #include <algorithm>
 #include <chrono>
@@ -37,16 +50,19 @@ namespace sgn {
 namespace {
 
 constexpr int kS = SGN_MAX_POLES;
+constexpr int kVecGrid = 1024;  // blocks of the batched vector kernels (grid-stride over each problem)
 
 struct MsHead {
     z64 rho, alpha, beta, alpha_prev, beta_prev;
     double rnorm, rmax, ynorm, tol, delta, theta32, theta16;
-    int done, reliable, want_phase, breakdown, iter, maxiter, nshift, seed, phase, pad;
+    int done, reliable, want_phase, breakdown, iter, maxiter, nshift, seed, phase;
+    int go;  // set by the beta step of an iteration: that iteration's solution/direction update may run
 };
 
 struct MsState {
     MsHead h;
-    z64 zeta[kS], zeta_prev[kS], zeta_next[kS], alpha_i[kS], beta_i[kS];    double tau[kS];
+    z64 zeta[kS], zeta_prev[kS], zeta_next[kS], alpha_i[kS], beta_i[kS];
+    double tau[kS];
     double omega[kS];
     double res[kS];
     int act[kS], act_next[kS];
@@ -58,6 +74,25 @@ struct MsHist {
     z64 alpha, beta, zeta;  // alpha_i^(k), beta_i^(k), zeta_i^(k+1)
 };
 
+// Device-side descriptor of one problem for the batched iteration kernels.
+// The vector pointers are those of the problem's current precision.
+struct MsVec {
+    MsState *S;
+    void *r;             // per-shift form: the residual (updated in place); stored-basis form: the
+                         // residual that replaces slot temp_iter as input (after a reliable update)
+    void *const *slots;  // stored-basis form: slot table, slot 0 = y; nullptr in per-shift form
+    int temp_iter;       // stored-basis form: iteration whose seed update starts from r
+    int nst_part;        // partials written by the dotting stencil
+    void *rt, *q, *qt, *pt;
+    void *P, *X;         // the seed's p and x (stored basis) or those of every shift
+    z64 *spart;          // partials of the dotting stencil
+    z64 *vpart;          // partials of the seed update (2 per block)
+    MsHist *hist;        // scalar history (stored-basis form), hist_cap iterations
+    int hist_cap;
+    int pad;
+    int64_t n;
+};
+
 __device__ __forceinline__ z64 cdiv(z64 a, z64 b)
 {
     const double d = b.r * b.r + b.i * b.i;
@@ -66,13 +101,16 @@ __device__ __forceinline__ z64 cdiv(z64 a, z64 b)
 
 __device__ __forceinline__ bool finite(z64 a) { return isfinite(a.r) && isfinite(a.i); }
 
-__global__ void __launch_bounds__(256) ms_alpha_kernel(const z64 *partials, int nb, MsState *S)
+// one block per problem
+__global__ void __launch_bounds__(256) ms_alpha_kernel(const MsVec *vl, const int *list)
 {
+    const MsVec &d = vl[list[blockIdx.x]];
+    MsState *S = d.S;
     if (S->h.done) return;
     double re = 0.0, im = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        re += partials[i].r;
-        im += partials[i].i;
+    for (int i = threadIdx.x; i < d.nst_part; i += blockDim.x) {
+        re += d.spart[i].r;
+        im += d.spart[i].i;
     }
     __shared__ double lds[8];
     __shared__ z64 alpha_sh;
@@ -108,16 +146,21 @@ __global__ void __launch_bounds__(256) ms_alpha_kernel(const z64 *partials, int 
     }
 }
 
-__global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int nb, MsState *S, MsHist *hist,
-                                                      int hist_cap)
+// one block per problem; nb = blocks of the seed update that wrote vpart
+__global__ void __launch_bounds__(256) ms_beta_kernel(const MsVec *vl, const int *list, int nb)
 {
-    if (S->h.done) return;
+    const MsVec &d = vl[list[blockIdx.x]];
+    MsState *S = d.S;
+    if (S->h.done) {
+        if (threadIdx.x == 0) S->h.go = 0;
+        return;
+    }
     const int k = S->h.iter;  // this iteration (read before thread 0 advances it)
     double a = 0.0, b = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        a += partials[2 * i].r;
-        b += partials[2 * i].i;
-        c += partials[2 * i + 1].r;
+        a += d.vpart[2 * i].r;
+        b += d.vpart[2 * i].i;
+        c += d.vpart[2 * i + 1].r;
     }
     __shared__ double lds[12];
     __shared__ z64 beta_sh;
@@ -136,6 +179,7 @@ __global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int n
             beta = {0.0, 0.0};
             bad_sh = 1;
         }
+        S->h.go = bad_sh ? 0 : 1;
         S->h.beta = beta;
         S->h.rho = rho_new;
         S->h.rnorm = rn;
@@ -155,7 +199,7 @@ __global__ void __launch_bounds__(256) ms_beta_kernel(const z64 *partials, int n
     const z64 beta = beta_sh;
     const double rn = rn_sh;
     const double lim = S->h.tol * S->h.ynorm;
-    MsHist *hk = (hist && k < hist_cap) ? hist + (int64_t)k * S->h.nshift : nullptr;
+    MsHist *hk = (d.hist && k < d.hist_cap) ? d.hist + (int64_t)k * S->h.nshift : nullptr;
     for (int i = threadIdx.x; i < S->h.nshift; i += blockDim.x) {
         if (!S->act[i]) {
             if (hk) hk[i] = MsHist{{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
@@ -196,15 +240,29 @@ template <typename T> __device__ __forceinline__ z64 ldz(const T *p, int64_t i)
 __device__ __forceinline__ void stz(double2 *p, int64_t i, z64 v) { p[i] = make_double2(v.r, v.i); }
 __device__ __forceinline__ void stz(float2 *p, int64_t i, z64 v) { p[i] = make_float2((float)v.r, (float)v.i); }
 
-// r_out = r_in - alpha q (r_out may be r_in, or the next stored-basis slot),
-// r~ -= conj(alpha) q~, with partials of r~^H r_out and ||r_out||^2
+// r_{k+1} = r_k - alpha q, r~ -= conj(alpha) q~, with partials of r~^H r_{k+1}
+// and ||r_{k+1}||^2.  Per-shift form: in place.  Stored-basis form: from slot k
+// (or the replacement residual) into slot k+1.
 template <typename R>
-__global__ void __launch_bounds__(256) ms_seed_update(const typename VecT<R>::t *r_in, typename VecT<R>::t *r_out,
-                                                      typename VecT<R>::t *rt, const typename VecT<R>::t *q,
-                                                      const typename VecT<R>::t *qt, int64_t n, const MsState *S,
-                                                      z64 *partials)
+__global__ void __launch_bounds__(256) ms_seed_update(const MsVec *vl, const int *list)
 {
+    using T = typename VecT<R>::t;
+    const MsVec &d = vl[list[blockIdx.y]];
+    const MsState *S = d.S;
     if (S->h.done) return;
+    const int k = S->h.iter;
+    const T *r_in;
+    T *r_out;
+    if (!d.slots) {
+        r_out = static_cast<T *>(d.r);
+        r_in = r_out;
+    } else {
+        r_in = static_cast<const T *>(k == d.temp_iter ? d.r : d.slots[k]);
+        r_out = static_cast<T *>(d.slots[k + 1]);
+    }
+    T *rt = static_cast<T *>(d.rt);
+    const T *q = static_cast<const T *>(d.q), *qt = static_cast<const T *>(d.qt);
+    const int64_t n = d.n;
     const z64 al = S->h.alpha, alc = conj(al);
     double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -216,101 +274,85 @@ __global__ void __launch_bounds__(256) ms_seed_update(const typename VecT<R>::t 
             rv = ldz(r_out, e);
             tv = ldz(rt, e);
         }
-        const z64 d = cmulc(tv, rv);
-        a += d.r;
-        b += d.i;
+        const z64 dd = cmulc(tv, rv);
+        a += dd.r;
+        b += dd.i;
         c += norm2(rv);
     }
     __shared__ double lds[12];
     double v[3] = {a, b, c};
     block_sum<3>(v, lds);
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = {v[0], v[1]};
-        partials[2 * blockIdx.x + 1] = {v[2], 0.0};
+        d.vpart[2 * blockIdx.x] = {v[0], v[1]};
+        d.vpart[2 * blockIdx.x + 1] = {v[2], 0.0};
     }
 }
 
-// p_i = zeta_i r + beta_i p_i for the active shifts, p~ = r~ + conj(beta) p~, and the
-// solution updates with the old p_i:
-//   KEEP:  x_i += alpha_i p_i for every active shift (X holds s vectors)
-//   else:  x_seed += alpha_seed p_seed and x_rest += sum_{i != seed} omega_i alpha_i p_i
-//          (X holds 2 vectors) -- only the omega-weighted sum of the non-seed
-//          solutions is ever needed, which halves the per-shift memory traffic.
-template <typename R, typename XT, bool KEEP>
-__global__ void __launch_bounds__(256) ms_shift_update(typename VecT<R>::t *P, XT *X, const typename VecT<R>::t *r,
-                                                       const typename VecT<R>::t *rt, typename VecT<R>::t *pt,
-                                                       int64_t n, const MsState *S, int expect,
+// Per-shift form: p_i = zeta_i r + beta_i p_i and x_i += alpha_i p_i (old p_i)
+// for every active shift; p~ = r~ + conj(beta) p~.
+template <typename R, typename XT>
+__global__ void __launch_bounds__(256) ms_shift_update(const MsVec *vl, const int *list,
                                                        unsigned long long *byte_counter)
 {
-    // apply only if this iteration's beta step ran (it may have just declared convergence;
-    // later launches of a polling chunk after convergence must not repeat the update)
-    if (S->h.breakdown || S->h.iter != expect) return;
+    using T = typename VecT<R>::t;
+    const MsVec &d = vl[list[blockIdx.y]];
+    const MsState *S = d.S;
+    if (S->h.breakdown || !S->h.go) return;
     __shared__ z64 al_s[kS], be_s[kS], ze_s[kS];
     __shared__ int act_s[kS];
-    __shared__ int ns, any_rest;
-    const int nsh = S->h.nshift, seed = S->h.seed;
-    if (threadIdx.x == 0) any_rest = 0;
-    __syncthreads();
+    const int nsh = S->h.nshift;
     for (int i = threadIdx.x; i < nsh; i += blockDim.x) {
-        const int a = S->act[i];
-        act_s[i] = a;
-        al_s[i] = (KEEP || i == seed) ? S->alpha_i[i] : S->omega[i] * S->alpha_i[i];
+        act_s[i] = S->act[i];
+        al_s[i] = S->alpha_i[i];
         be_s[i] = S->beta_i[i];
         ze_s[i] = S->zeta[i];
-        if (a && i != seed) any_rest = 1;  // every writer stores the same value
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        ns = nsh;
-        if (byte_counter && blockIdx.x == 0) {  // algorithmic bytes of this launch (profiling)
-            unsigned long long na = 0;
-            for (int i = 0; i < nsh; ++i) na += act_s[i] ? 1 : 0;
-            const unsigned long long eb = sizeof(typename VecT<R>::t), xb = sizeof(XT);
-            const unsigned long long nxv = KEEP ? na : (1ull + (any_rest ? 1ull : 0ull));
-            atomicAdd(byte_counter, (unsigned long long)n * (4ull * eb + na * 2ull * eb + nxv * 2ull * xb));
-        }
+    const int64_t n = d.n;
+    if (byte_counter && blockIdx.x == 0 && threadIdx.x == 0) {  // algorithmic bytes (profiling)
+        unsigned long long na = 0;
+        for (int i = 0; i < nsh; ++i) na += act_s[i] ? 1 : 0;
+        const unsigned long long eb = sizeof(T), xb = sizeof(XT);
+        atomicAdd(byte_counter, (unsigned long long)n * (4ull * eb + na * 2ull * eb + na * 2ull * xb));
     }
-    __syncthreads();
+    T *P = static_cast<T *>(d.P), *pt = static_cast<T *>(d.pt);
+    XT *X = static_cast<XT *>(d.X);
+    const T *r = static_cast<const T *>(d.r), *rt = static_cast<const T *>(d.rt);
     const z64 bc = conj(S->h.beta);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 rv = ldz(r, e);
-        z64 rest = {0.0, 0.0};
-        for (int i = 0; i < ns; ++i) {
+        for (int i = 0; i < nsh; ++i) {
             if (!act_s[i]) continue;
-            typename VecT<R>::t *Pi = P + (int64_t)i * n;
+            T *Pi = P + (int64_t)i * n;
+            XT *Xi = X + (int64_t)i * n;
             const z64 p = ldz(Pi, e);
-            if (KEEP) {
-                XT *Xi = X + (int64_t)i * n;
-                stz(Xi, e, ldz(Xi, e) + al_s[i] * p);
-            } else if (i == seed) {
-                stz(X, e, ldz(X, e) + al_s[i] * p);
-            } else {
-                rest = rest + al_s[i] * p;
-            }
+            stz(Xi, e, ldz(Xi, e) + al_s[i] * p);
             stz(Pi, e, ze_s[i] * rv + be_s[i] * p);
         }
-        if (!KEEP && any_rest) stz(X + n, e, ldz(X + n, e) + rest);
         stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
     }
 }
 
 // Stored-basis form: only the seed keeps vectors,
-//   x_seed += alpha p_seed;  p_seed = r + beta p_seed;  p~ = r~ + conj(beta) p~
+//   x_seed += alpha p_seed;  p_seed = r_{k+1} + beta p_seed;  p~ = r~ + conj(beta) p~
 // (zeta = 1 and alpha_i = alpha, beta_i = beta for the seed; the values are
 // taken from the shift arrays all the same).
 template <typename R, typename XT>
-__global__ void __launch_bounds__(256) ms_seed_xp_update(typename VecT<R>::t *P, XT *X, const typename VecT<R>::t *r,
-                                                         const typename VecT<R>::t *rt, typename VecT<R>::t *pt,
-                                                         int64_t n, const MsState *S, int expect,
+__global__ void __launch_bounds__(256) ms_seed_xp_update(const MsVec *vl, const int *list,
                                                          unsigned long long *byte_counter)
 {
-    if (S->h.breakdown || S->h.iter != expect) return;
+    using T = typename VecT<R>::t;
+    const MsVec &d = vl[list[blockIdx.y]];
+    const MsState *S = d.S;
+    if (S->h.breakdown || !S->h.go) return;
     const int seed = S->h.seed;
     const z64 al = S->alpha_i[seed], be = S->beta_i[seed], ze = S->zeta[seed], bc = conj(S->h.beta);
-    if (byte_counter && blockIdx.x == 0 && threadIdx.x == 0) {
-        const unsigned long long eb = sizeof(typename VecT<R>::t), xb = sizeof(XT);
-        atomicAdd(byte_counter, (unsigned long long)n * (6ull * eb + 2ull * xb));
-    }
+    const int64_t n = d.n;
+    if (byte_counter && blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(byte_counter, (unsigned long long)n * (6ull * sizeof(T) + 2ull * sizeof(XT)));
+    T *P = static_cast<T *>(d.P), *pt = static_cast<T *>(d.pt);
+    XT *X = static_cast<XT *>(d.X);
+    const T *r = static_cast<const T *>(d.slots[S->h.iter]), *rt = static_cast<const T *>(d.rt);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 p = ldz(P, e);
         stz(X, e, ldz(X, e) + al * p);
@@ -514,427 +556,672 @@ void basis_coefficients(const std::vector<MsHist> &H, int ns, int k, int i, std:
     }
 }
 
-// One problem of multishift_solve.
-sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, sgn_stats *st,
-                     hipStream_t s)
-{
-    const auto t_start = std::chrono::steady_clock::now();
-    Lattice &lat = *as_lattice(pb.lat);
-    Context &ctx = *lat.ctx;
-    SGN_HIP(hipSetDevice(ctx.device));
-    // internal vectors have n = 12 S entries (padded component stride), canonical ones nc = 12 V
-    const int64_t V = lat.V, Sst = lat.S, n = 12 * Sst, nc = 12 * V;
-    const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8, c64 = (size_t)nc * 16;
-    const int ns = rf.s;
-    const bool mixed = o.prec != SGN_PREC_F64;
-    const double c2 = rf.c * rf.c;
-    int seed = 0;
-    for (int i = 1; i < ns; ++i)
-        if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed])) seed = i;
-    const double s1 = rf.sigma[seed];
-    const int maxiter = o.maxiter > 0 ? o.maxiter : 10000;
-
-    // Stored-basis form unless per-shift solutions are wanted: slots 1..slot_cap
-    // may hold residuals r_j (slot 0 is y itself).
-    const bool want_shifts = pb.x_shift != nullptr || o.verify;
+// Host state of one problem of a multishift_solve call.
+struct MsProblem {
+    const sgn_problem *pb = nullptr;
+    Lattice *lat = nullptr;
+    sgn_stats *st = nullptr;
+    int64_t V = 0, Sst = 0, n = 0, nc = 0;
+    size_t b64 = 0, b32 = 0, c64 = 0;
+    bool want_shifts = false, explicit_mode = false;
     int slot_cap = 0;
-    if (!want_shifts && o.basis_slots >= 0) {
-        if (o.basis_slots > 0) {
-            slot_cap = o.basis_slots;
-        } else {
-            size_t fr = 0, tot = 0;
-            SGN_HIP(hipMemGetInfo(&fr, &tot));
-            slot_cap = (int)std::min<double>(1e9, 0.5 * (double)(fr + ctx.basis_bytes()) / (double)b64);
-        }
-        slot_cap = std::min(slot_cap, maxiter);
-    }
-    bool explicit_mode = slot_cap < 1;
-    const int np0 = explicit_mode ? ns : 1;  // p and x vectors held in the arena
-    const size_t hist_bytes = explicit_mode ? 0 : (size_t)slot_cap * ns * sizeof(MsHist);
-
-    // workspace carved from the context's arena (kept between calls)
-    const size_t a64 = (8 + 2 * (size_t)np0) * b64 + c64, a32 = mixed ? (7 + 2 * (size_t)np0) * b32 : 0;
-    char *arena = static_cast<char *>(ctx.ensure_arena(a64 + a32 + hist_bytes + sizeof(MsState)));
-    auto carve = [&](size_t bytes) {
-        Span sp{arena};
-        arena += bytes;
-        return sp;
-    };
-    Span y = carve(b64), r = carve(b64), rt = carve(b64), pt = carve(b64), q = carve(b64), qt = carve(b64),
-         tmp = carve(b64), tmpt = carve(b64);
-    Span X = carve((size_t)np0 * b64), P = carve((size_t)np0 * b64);
-    Span r32 = carve(mixed ? b32 : 0), rt32 = carve(mixed ? b32 : 0), pt32 = carve(mixed ? b32 : 0),
-         q32 = carve(mixed ? b32 : 0), qt32 = carve(mixed ? b32 : 0), tmp32 = carve(mixed ? b32 : 0),
-         tmpt32 = carve(mixed ? b32 : 0);
-    Span P32 = carve(mixed ? (size_t)np0 * b32 : 0), Xlo = carve(mixed ? (size_t)np0 * b32 : 0);
-    MsHist *hist = carve(hist_bytes).as<MsHist>();
-    MsState *S = carve(sizeof(MsState)).as<MsState>();
-    Span rcan = carve(c64);
-    std::unique_ptr<DevMem> xp64, xp32;  // per-shift vectors after a change to explicit form
-
-    // x <- x_P, r = (I - P) b (canonical)
-    deflation_prologue(ctx, pb.defl, nc, pb.b, pb.x, rcan.p, nullptr, s);
-
+    Span y{}, r{}, rt{}, pt{}, q{}, qt{}, tmp{}, tmpt{}, X{}, P{};
+    Span r32{}, rt32{}, pt32{}, q32{}, qt32{}, tmp32{}, tmpt32{}, P32{}, Xlo{};
+    Span rcan{};
+    MsHist *hist = nullptr;
+    MsState *S = nullptr;
+    z64 *spart = nullptr, *vpart = nullptr;
+    void **slot_table = nullptr;  // device, slot_cap + 1 entries
+    std::vector<void *> slots;    // host copy of the slot table
+    std::vector<char> slot_f32;   // precision of each stored slot
+    int temp_iter = -1;
+    std::unique_ptr<DevMem> xp64, xp32;  // per-shift vectors after leaving the stored-basis form
     OpSpec opA, opAh;
-    opA.mu = pb.mu;
-    opAh.mu = -pb.mu;
-    // y = c A r
-    pack_spinor(lat, rcan.p, tmp.p, SGN_PREC_F64, s);
+    double ynorm = 0.0;
+    int phase = 0, launched = 0, reliable_updates = 0;
+    bool active = false;
+    sgn_status result = SGN_OK;
+    MsHead hh{};
+    double kry_ms = 0.0;
+};
+
+class MultishiftBatch {
+  public:
+    MultishiftBatch(const sgn_problem *pb, int nprob, const sgn_rational &rf, const sgn_ms_opts &o,
+                    sgn_stats *stats, hipStream_t s);
+    sgn_status run();
+
+  private:
+    std::vector<MsProblem> pr_;
+    const sgn_rational &rf_;
+    const sgn_ms_opts &o_;
+    hipStream_t s_;
+    Context *ctx_ = nullptr;
+    int ns_ = 0, seed_ = 0, maxiter_ = 0, poll_ = 1;
+    double s1_ = 0.0, c2_ = 0.0;
+    bool mixed_ = false;
+    std::chrono::steady_clock::time_point t_start_;
+    MsVec *dvec_ = nullptr;  // device descriptors, one per problem
+    int *dlist_ = nullptr;   // device problem lists: [3 phases][2 forms][nprob]
+    std::vector<MsVec> hvec_;
+    std::vector<int> lists_[3][2];  // active problems per phase and form (0 stored basis, 1 per-shift)
+    StencilBatch stb_[3][4];        // per phase, the four stencil steps of an iteration
+    bool dirty_ = true;             // lists and stencil batches need rebuilding
+    bool dirty_vec_ = false;        // only the descriptors changed
+    std::map<size_t, size_t> pool_next_;  // next unused pooled slot per vector size in this call
+
+    void setup(MsProblem &p);
+    void rebuild();
+    void fill_vec(int k);
+    void iterate(int count);
+    void *slot_ptr(const MsProblem &p, int j) const { return p.slots[(size_t)j]; }
+    bool ensure_slots(MsProblem &p, int upto);
+    void flush(MsProblem &p);
+    void reliable_update(MsProblem &p);
+    void switch_to_f32(MsProblem &p);
+    void to_explicit(MsProblem &p);
+    void lift(MsProblem &p, const std::vector<z64> &coef, void *out, bool accumulate);
+    std::vector<MsHist> history(const MsProblem &p, int k);
+    void finish(MsProblem &p);
+    void read_heads();
+    sgn_prec prec_of(int phase) const
+    {
+        return phase == 0 ? SGN_PREC_F64 : (phase == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16);
+    }
+    void *pseed(const MsProblem &p) const
+    {
+        const size_t off = p.explicit_mode ? (size_t)seed_ : 0;
+        return p.phase >= 1 ? (void *)(p.P32.as<char>() + off * p.b32) : (void *)(p.P.as<char>() + off * p.b64);
+    }
+};
+
+MultishiftBatch::MultishiftBatch(const sgn_problem *pb, int nprob, const sgn_rational &rf, const sgn_ms_opts &o,
+                                 sgn_stats *stats, hipStream_t s)
+    : rf_(rf), o_(o), s_(s)
+{
+    t_start_ = std::chrono::steady_clock::now();
+    ns_ = rf.s;
+    mixed_ = o.prec != SGN_PREC_F64;
+    c2_ = rf.c * rf.c;
+    for (int i = 1; i < ns_; ++i)
+        if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed_])) seed_ = i;
+    s1_ = rf.sigma[seed_];
+    maxiter_ = o.maxiter > 0 ? o.maxiter : 10000;
+    pr_.resize(nprob);
+    double basis_bytes_per_iter = 0.0;
+    int64_t vtot = 0;
+    for (int k = 0; k < nprob; ++k) {
+        MsProblem &p = pr_[k];
+        p.pb = &pb[k];
+        p.lat = as_lattice(pb[k].lat);
+        p.st = stats ? &stats[k] : nullptr;
+        p.V = p.lat->V;
+        p.Sst = p.lat->S;
+        p.n = 12 * p.Sst;
+        p.nc = 12 * p.V;
+        p.b64 = (size_t)p.n * 16;
+        p.b32 = (size_t)p.n * 8;
+        p.c64 = (size_t)p.nc * 16;
+        p.want_shifts = pb[k].x_shift != nullptr || o.verify;
+        vtot += p.V;
+        if (!p.want_shifts) basis_bytes_per_iter += (double)p.b64;
+        if (!ctx_) ctx_ = p.lat->ctx;
+        SGN_REQUIRE(p.lat->ctx == ctx_, "multishift_solve: all lattices must share one context");
+    }
+    SGN_HIP(hipSetDevice(ctx_->device));
+    // iterations between host polls: about 200k sites' worth of stencil work per poll
+    poll_ = o.poll > 0 ? o.poll : (int)std::min<int64_t>(16, std::max<int64_t>(1, (200000 + vtot - 1) / vtot));
+    // stored-basis budget: slots per problem
+    int cap = 0;
+    if (o.basis_slots > 0) {
+        cap = o.basis_slots;
+    } else if (o.basis_slots == 0 && basis_bytes_per_iter > 0) {
+        size_t fr = 0, tot = 0;
+        SGN_HIP(hipMemGetInfo(&fr, &tot));
+        double held = 0.0;
+        for (auto &kv : ctx_->basis_pools) held += (double)kv.first * kv.second.size();
+        cap = (int)std::min<double>(1e9, 0.5 * ((double)fr + held) / basis_bytes_per_iter);
+    }
+    cap = std::min(cap, maxiter_);
+
+    // workspace carved from the context's arena (256-byte aligned pieces)
+    auto rs = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
+    auto pieces = [&](const MsProblem &p, auto &&take) {
+        const size_t np0 = p.explicit_mode ? ns_ : 1;
+        const size_t b64 = p.b64, b32 = mixed_ ? p.b32 : 0;
+        for (int i = 0; i < 8; ++i) take(b64);           // y r rt pt q qt tmp tmpt
+        take(np0 * b64);                                 // X
+        take(np0 * b64);                                 // P
+        for (int i = 0; i < 7; ++i) take(b32);           // r32 rt32 pt32 q32 qt32 tmp32 tmpt32
+        take(np0 * b32);                                 // P32
+        take(np0 * b32);                                 // Xlo
+        take(p.explicit_mode ? 0 : (size_t)p.slot_cap * ns_ * sizeof(MsHist));
+        take(sizeof(MsState));
+        take(sizeof(z64) * (size_t)dslash_blocks(*p.lat));
+        take(sizeof(z64) * (2 * (size_t)kVecGrid + 2 * (size_t)vec_blocks(6 * p.Sst)));
+        take(sizeof(void *) * ((size_t)p.slot_cap + 1));
+        take(p.c64);                                     // rcan
+    };
+    size_t total = 0;
+    for (auto &p : pr_) {
+        p.explicit_mode = p.want_shifts || cap < 1;
+        p.slot_cap = p.explicit_mode ? 0 : cap;
+        pieces(p, [&](size_t b) { total += rs(b); });
+    }
+    total += rs(sizeof(MsVec) * nprob) + rs(sizeof(int) * 6 * nprob);
+    char *arena = static_cast<char *>(ctx_->ensure_arena(total));
+    for (auto &p : pr_) {
+        std::vector<void *> got;
+        pieces(p, [&](size_t b) {
+            got.push_back(arena);
+            arena += rs(b);
+        });
+        int g = 0;
+        for (Span *sp : {&p.y, &p.r, &p.rt, &p.pt, &p.q, &p.qt, &p.tmp, &p.tmpt, &p.X, &p.P, &p.r32, &p.rt32, &p.pt32,
+                         &p.q32, &p.qt32, &p.tmp32, &p.tmpt32, &p.P32, &p.Xlo})
+            sp->p = got[g++];
+        p.hist = static_cast<MsHist *>(got[g++]);
+        p.S = static_cast<MsState *>(got[g++]);
+        p.spart = static_cast<z64 *>(got[g++]);
+        p.vpart = static_cast<z64 *>(got[g++]);
+        p.slot_table = static_cast<void **>(got[g++]);
+        p.rcan.p = got[g++];
+    }
+    dvec_ = reinterpret_cast<MsVec *>(arena);
+    arena += rs(sizeof(MsVec) * nprob);
+    dlist_ = reinterpret_cast<int *>(arena);
+    hvec_.resize(nprob);
+}
+
+// x <- x_P, y = c A (I - P) b, initial state and vectors of one problem
+void MultishiftBatch::setup(MsProblem &p)
+{
+    Lattice &lat = *p.lat;
+    deflation_prologue(*ctx_, p.pb->defl, p.nc, p.pb->b, p.pb->x, p.rcan.p, nullptr, s_);
+    p.opA.mu = p.pb->mu;
+    p.opAh.mu = -p.pb->mu;
+    pack_spinor(lat, p.rcan.p, p.tmp.p, SGN_PREC_F64, s_);
     {
         Epilogue ep;
-        ep.a = rf.c;
-        dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, y.p, ep, s);
+        ep.a = rf_.c;
+        dslash_launch(lat, SGN_PREC_F64, p.opA, p.tmp.p, p.y.p, ep, s_);
     }
-    const double ynorm = norm_sync(ctx, y.p, n, false, s);
-    SGN_REQUIRE(std::isfinite(ynorm), "multishift_solve: b contains NaN or Inf");
-    if (st) {
-        *st = sgn_stats{};
-        st->nshift = ns;
+    p.ynorm = norm_sync(*ctx_, p.y.p, p.n, false, s_);
+    SGN_REQUIRE(std::isfinite(p.ynorm), "multishift_solve: b contains NaN or Inf");
+    if (p.st) {
+        *p.st = sgn_stats{};
+        p.st->nshift = ns_;
     }
-    if (ynorm == 0.0) return SGN_OK;  // x = x_P
-
-    const int nvb = vec_blocks(n);
-    const int nst = dslash_blocks(lat);
-    const int nvbp = vec_blocks(6 * Sst);
-    z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max({nst, 2 * nvb, 2 * nvbp})));
-
-    // initial state
+    p.active = p.ynorm != 0.0;  // y = 0: x = x_P
+    if (!p.active) return;
     MsState h0{};
-    h0.h.rho = {ynorm * ynorm, 0.0};
+    h0.h.rho = {p.ynorm * p.ynorm, 0.0};
     h0.h.alpha_prev = {1.0, 0.0};
     h0.h.beta_prev = {0.0, 0.0};
-    h0.h.rnorm = h0.h.rmax = h0.h.ynorm = ynorm;
-    h0.h.tol = o.tol;
-    h0.h.delta = o.delta > 0 ? o.delta : 0.1;
-    h0.h.theta32 = mixed ? (o.theta32 > 0 ? o.theta32 : 1e-3) : 0.0;
-    h0.h.theta16 = (o.prec == SGN_PREC_F32_H16) ? (o.theta16 > 0 ? o.theta16 : 1e-6) : 0.0;
-    h0.h.maxiter = maxiter;
-    h0.h.nshift = ns;
-    h0.h.seed = seed;
-    for (int i = 0; i < ns; ++i) {
+    h0.h.rnorm = h0.h.rmax = h0.h.ynorm = p.ynorm;
+    h0.h.tol = o_.tol;
+    h0.h.delta = o_.delta > 0 ? o_.delta : 0.1;
+    h0.h.theta32 = mixed_ ? (o_.theta32 > 0 ? o_.theta32 : 1e-3) : 0.0;
+    h0.h.theta16 = (o_.prec == SGN_PREC_F32_H16) ? (o_.theta16 > 0 ? o_.theta16 : 1e-6) : 0.0;
+    h0.h.maxiter = maxiter_;
+    h0.h.nshift = ns_;
+    h0.h.seed = seed_;
+    for (int i = 0; i < ns_; ++i) {
         h0.zeta[i] = h0.zeta_prev[i] = {1.0, 0.0};
-        h0.tau[i] = s1 - rf.sigma[i];
-        h0.omega[i] = rf.omega[i];
+        h0.tau[i] = s1_ - rf_.sigma[i];
+        h0.omega[i] = rf_.omega[i];
         h0.act_next[i] = 1;
-        h0.res[i] = ynorm;
+        h0.res[i] = p.ynorm;
     }
-    SGN_HIP(hipMemcpyAsync(S, &h0, sizeof(MsState), hipMemcpyHostToDevice, s));
-    SGN_HIP(hipMemcpyAsync(r.p, y.p, b64, hipMemcpyDeviceToDevice, s));
-    SGN_HIP(hipMemcpyAsync(rt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
-    SGN_HIP(hipMemcpyAsync(pt.p, y.p, b64, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s, y.as<double2>(), P.as<double2>(), np0, n);
-    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s, X.as<double2>(), make_double2(0, 0),
-                       (int64_t)np0 * n);
+    SGN_HIP(hipMemcpyAsync(p.S, &h0, sizeof(MsState), hipMemcpyHostToDevice, s_));
+    SGN_HIP(hipMemcpyAsync(p.r.p, p.y.p, p.b64, hipMemcpyDeviceToDevice, s_));
+    SGN_HIP(hipMemcpyAsync(p.rt.p, p.y.p, p.b64, hipMemcpyDeviceToDevice, s_));
+    SGN_HIP(hipMemcpyAsync(p.pt.p, p.y.p, p.b64, hipMemcpyDeviceToDevice, s_));
+    const int np0 = p.explicit_mode ? ns_ : 1;
+    const int nvb = vec_blocks(p.n);
+    hipLaunchKernelGGL(copy_rep_kernel, dim3(nvb), dim3(256), 0, s_, p.y.as<double2>(), p.P.as<double2>(), np0, p.n);
+    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s_, p.X.as<double2>(), make_double2(0, 0),
+                       (int64_t)np0 * p.n);
     SGN_HIP(hipGetLastError());
+    p.slots.assign(1, p.y.p);  // slot 0 is y itself
+    p.slot_f32.assign(1, 0);
+    if (!p.explicit_mode) SGN_HIP(hipMemcpyAsync(p.slot_table, p.slots.data(), sizeof(void *), hipMemcpyHostToDevice, s_));
+    SGN_HIP(hipStreamSynchronize(s_));  // h0 and the slot table entry leave scope
+}
 
-    int phase = 0;
-    int poll = o.poll > 0 ? o.poll : (int)std::min<int64_t>(16, std::max<int64_t>(1, (200000 + V - 1) / V));
-    int reliable_updates = 0;
-    const double sigma_seed = s1;
-
-    // stored basis: slot j holds the residual r_j written by iteration j-1
-    std::vector<char> slot_f32(1, 0);
-    auto slot_ptr = [&](int j) -> void * { return j == 0 ? y.p : ctx.basis[(size_t)j - 1]; };
-    void *cur = y.p;  // residual the next seed update starts from (basis form)
-
-    int launched = 0;  // iteration number of the next launch minus one (synced with the device at polls)
-    auto iterate = [&](int count) {
-        for (int it = 0; it < count; ++it) {
-            ++launched;
-            const bool lo = phase >= 1;
-            const sgn_prec sp = phase == 0 ? SGN_PREC_F64 : (phase == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16);
-            const size_t pso = explicit_mode ? (size_t)seed : 0;  // seed's index in P / X
-            void *pseed = lo ? (void *)(P32.as<char>() + pso * b32) : (void *)(P.as<char>() + pso * b64);
-            void *vrt = lo ? rt32.p : rt.p, *vpt = lo ? pt32.p : pt.p;
-            void *vq = lo ? q32.p : q.p, *vqt = lo ? qt32.p : qt.p, *vtmp = lo ? tmp32.p : tmp.p,
-                 *vtmpt = lo ? tmpt32.p : tmpt.p;
-            void *rin, *rout;
-            if (explicit_mode) {
-                rin = rout = lo ? r32.p : r.p;
-            } else {
-                rin = cur;
-                rout = slot_ptr(launched);
-                if ((int)slot_f32.size() <= launched) slot_f32.resize(launched + 1, 0);
-                slot_f32[launched] = lo ? 1 : 0;
-                cur = rout;
+// slots 1..upto exist (taken from the context's pool of vectors of this size)
+bool MultishiftBatch::ensure_slots(MsProblem &p, int upto)
+{
+    if (upto > p.slot_cap) return false;
+    if ((int)p.slots.size() > upto) return true;
+    auto &pool = ctx_->basis_pools[p.b64];
+    size_t &nx = pool_next_[p.b64];
+    const size_t first = p.slots.size();
+    while ((int)p.slots.size() <= upto) {
+        if (nx == pool.size()) {
+            void *b = nullptr;
+            if (hipMalloc(&b, p.b64) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
             }
-            dslash_launch(lat, sp, opA, pseed, vtmp, Epilogue{}, s);
-            Epilogue e1;
-            e1.a = c2;
-            e1.z = pseed;
-            e1.b = {-sigma_seed, 0.0};
-            e1.w = vpt;
-            e1.partials = part;
-            const int nb1 = dslash_launch(lat, sp, opA, vtmp, vq, e1, s);
-            dslash_launch(lat, sp, opAh, vpt, vtmpt, Epilogue{}, s);
-            Epilogue e2;
-            e2.a = c2;
-            e2.z = vpt;
-            e2.b = {-sigma_seed, 0.0};
-            dslash_launch(lat, sp, opAh, vtmpt, vqt, e2, s);
-            hipLaunchKernelGGL(ms_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S);
-            unsigned long long *bc = ctx.prof ? ctx.byte_counter : nullptr;
+            pool.push_back(b);
+        }
+        p.slots.push_back(pool[nx++]);
+    }
+    SGN_HIP(hipMemcpy(p.slot_table + first, p.slots.data() + first, sizeof(void *) * (p.slots.size() - first),
+                      hipMemcpyHostToDevice));
+    return true;
+}
+
+void MultishiftBatch::fill_vec(int k)
+{
+    MsProblem &p = pr_[k];
+    MsVec &v = hvec_[k];
+    const int nst_part = v.nst_part;  // set by rebuild() from the stencil batch
+    v = MsVec{};
+    v.nst_part = nst_part;
+    v.S = p.S;
+    v.n = p.n;
+    v.spart = p.spart;
+    v.vpart = p.vpart;
+    const bool lo = p.phase >= 1;
+    v.r = lo ? p.r32.p : p.r.p;
+    v.slots = p.explicit_mode ? nullptr : p.slot_table;
+    v.temp_iter = p.temp_iter;
+    v.rt = lo ? p.rt32.p : p.rt.p;
+    v.q = lo ? p.q32.p : p.q.p;
+    v.qt = lo ? p.qt32.p : p.qt.p;
+    v.pt = lo ? p.pt32.p : p.pt.p;
+    v.P = lo ? p.P32.p : p.P.p;
+    v.X = lo ? p.Xlo.p : p.X.p;
+    v.hist = p.explicit_mode ? nullptr : p.hist;
+    v.hist_cap = p.explicit_mode ? 0 : p.slot_cap;
+}
+
+// descriptors, problem lists and stencil batches for the current phases and forms
+void MultishiftBatch::rebuild()
+{
+    const int np = (int)pr_.size();
+    for (auto &l : lists_)
+        for (auto &m : l) m.clear();
+    std::vector<StencilJob> jobs[3][4];
+    std::vector<int> job_owner[3];
+    for (int k = 0; k < np; ++k) {
+        MsProblem &p = pr_[k];
+        fill_vec(k);
+        if (!p.active) continue;
+        const MsVec &v = hvec_[k];
+        lists_[p.phase][p.explicit_mode ? 1 : 0].push_back(k);
+        const bool lo = p.phase >= 1;
+        void *ps = pseed(p);
+        void *vtmp = lo ? p.tmp32.p : p.tmp.p, *vtmpt = lo ? p.tmpt32.p : p.tmpt.p;
+        StencilJob j1{p.lat, p.opA, ps, vtmp, Epilogue{}};
+        StencilJob j2{p.lat, p.opA, vtmp, v.q, Epilogue{}};
+        j2.ep.a = c2_;
+        j2.ep.z = ps;
+        j2.ep.b = {-s1_, 0.0};
+        j2.ep.w = v.pt;
+        j2.ep.partials = p.spart;
+        StencilJob j3{p.lat, p.opAh, v.pt, vtmpt, Epilogue{}};
+        StencilJob j4{p.lat, p.opAh, vtmpt, v.qt, Epilogue{}};
+        j4.ep.a = c2_;
+        j4.ep.z = v.pt;
+        j4.ep.b = {-s1_, 0.0};
+        jobs[p.phase][0].push_back(j1);
+        jobs[p.phase][1].push_back(j2);
+        jobs[p.phase][2].push_back(j3);
+        jobs[p.phase][3].push_back(j4);
+        job_owner[p.phase].push_back(k);
+    }
+    for (int ph = 0; ph < 3; ++ph) {
+        for (int st = 0; st < 4; ++st) stb_[ph][st].prepare(jobs[ph][st], prec_of(ph));
+        for (size_t j = 0; j < job_owner[ph].size(); ++j) hvec_[job_owner[ph][j]].nst_part = stb_[ph][1].blocks(j);
+    }
+    SGN_HIP(hipMemcpy(dvec_, hvec_.data(), sizeof(MsVec) * np, hipMemcpyHostToDevice));
+    std::vector<int> hl(6 * (size_t)np, 0);
+    for (int ph = 0; ph < 3; ++ph)
+        for (int form = 0; form < 2; ++form)
+            std::copy(lists_[ph][form].begin(), lists_[ph][form].end(), hl.begin() + (size_t)(2 * ph + form) * np);
+    SGN_HIP(hipMemcpy(dlist_, hl.data(), sizeof(int) * hl.size(), hipMemcpyHostToDevice));
+    dirty_ = dirty_vec_ = false;
+}
+
+void MultishiftBatch::iterate(int count)
+{
+    const int np = (int)pr_.size();
+    unsigned long long *bc = ctx_->prof ? ctx_->byte_counter : nullptr;
+    for (int it = 0; it < count; ++it) {
+        for (int ph = 0; ph < 3; ++ph) {
+            const int nb = (int)lists_[ph][0].size(), ne = (int)lists_[ph][1].size();
+            if (nb + ne == 0) continue;
+            for (int st = 0; st < 4; ++st) stb_[ph][st].launch(s_);
+            const int *lb = dlist_ + (size_t)(2 * ph) * np, *le = dlist_ + (size_t)(2 * ph + 1) * np;
+            const bool lo = ph >= 1;
+            if (nb) hipLaunchKernelGGL(ms_alpha_kernel, dim3(nb), dim3(256), 0, s_, dvec_, lb);
+            if (ne) hipLaunchKernelGGL(ms_alpha_kernel, dim3(ne), dim3(256), 0, s_, dvec_, le);
+            double elems = 0.0;
+            for (int form = 0; form < 2; ++form)
+                for (int k : lists_[ph][form]) elems += (double)pr_[k].n;
             const double eb = lo ? 8.0 : 16.0;
-            int pr = ctx.prof_start(s);
-            if (lo)
-                hipLaunchKernelGGL(ms_seed_update<float>, dim3(nvb), dim3(256), 0, s, (const float2 *)rin,
-                                   (float2 *)rout, (float2 *)vrt, (const float2 *)vq, (const float2 *)vqt, n, S, part);
-            else
-                hipLaunchKernelGGL(ms_seed_update<double>, dim3(nvb), dim3(256), 0, s, (const double2 *)rin,
-                                   (double2 *)rout, (double2 *)vrt, (const double2 *)vq, (const double2 *)vqt, n, S,
-                                   part);
-            ctx.prof_stop(pr, s, SGN_K_SEED_UPDATE, 6.0 * eb * n, 40.0 * n);
-            hipLaunchKernelGGL(ms_beta_kernel, dim3(1), dim3(256), 0, s, part, nvb, S,
-                               explicit_mode ? nullptr : hist, explicit_mode ? 0 : slot_cap);
-            pr = ctx.prof_start(s);
-            if (!explicit_mode) {
+            int pr = ctx_->prof_start(s_);
+            for (int form = 0; form < 2; ++form) {
+                const int cnt = form ? ne : nb;
+                if (!cnt) continue;
+                const int *l = form ? le : lb;
                 if (lo)
-                    hipLaunchKernelGGL((ms_seed_xp_update<float, float2>), dim3(nvb), dim3(256), 0, s,
-                                       P32.as<float2>(), Xlo.as<float2>(), (const float2 *)rout, (const float2 *)vrt,
-                                       (float2 *)vpt, n, S, launched, bc);
+                    hipLaunchKernelGGL(ms_seed_update<float>, dim3(kVecGrid, cnt), dim3(256), 0, s_, dvec_, l);
                 else
-                    hipLaunchKernelGGL((ms_seed_xp_update<double, double2>), dim3(nvb), dim3(256), 0, s,
-                                       P.as<double2>(), X.as<double2>(), (const double2 *)rout, (const double2 *)vrt,
-                                       (double2 *)vpt, n, S, launched, bc);
-            } else if (lo) {
-                hipLaunchKernelGGL((ms_shift_update<float, float2, true>), dim3(nvb), dim3(256), 0, s,
-                                   P32.as<float2>(), Xlo.as<float2>(), (const float2 *)rout, (const float2 *)vrt,
-                                   (float2 *)vpt, n, S, launched, bc);
-            } else {
-                hipLaunchKernelGGL((ms_shift_update<double, double2, true>), dim3(nvb), dim3(256), 0, s,
-                                   P.as<double2>(), X.as<double2>(), (const double2 *)rout, (const double2 *)vrt,
-                                   (double2 *)vpt, n, S, launched, bc);
+                    hipLaunchKernelGGL(ms_seed_update<double>, dim3(kVecGrid, cnt), dim3(256), 0, s_, dvec_, l);
             }
-            ctx.prof_stop(pr, s, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
+            ctx_->prof_stop(pr, s_, SGN_K_SEED_UPDATE, 6.0 * eb * elems, 40.0 * elems);
+            if (nb) hipLaunchKernelGGL(ms_beta_kernel, dim3(nb), dim3(256), 0, s_, dvec_, lb, kVecGrid);
+            if (ne) hipLaunchKernelGGL(ms_beta_kernel, dim3(ne), dim3(256), 0, s_, dvec_, le, kVecGrid);
+            pr = ctx_->prof_start(s_);
+            if (nb) {
+                if (lo)
+                    hipLaunchKernelGGL((ms_seed_xp_update<float, float2>), dim3(kVecGrid, nb), dim3(256), 0, s_,
+                                       dvec_, lb, bc);
+                else
+                    hipLaunchKernelGGL((ms_seed_xp_update<double, double2>), dim3(kVecGrid, nb), dim3(256), 0, s_,
+                                       dvec_, lb, bc);
+            }
+            if (ne) {
+                if (lo)
+                    hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(kVecGrid, ne), dim3(256), 0, s_, dvec_,
+                                       le, bc);
+                else
+                    hipLaunchKernelGGL((ms_shift_update<double, double2>), dim3(kVecGrid, ne), dim3(256), 0, s_,
+                                       dvec_, le, bc);
+            }
+            ctx_->prof_stop(pr, s_, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
         }
-        SGN_HIP(hipGetLastError());
-    };
-
-    auto nxv = [&]() { return explicit_mode ? ns : 1; };
-    auto flush = [&]() {
-        hipLaunchKernelGGL(ms_flush_kernel, dim3(nvbp), dim3(256), 0, s, X.as<double2>(), Xlo.as<float4>(), nxv(),
-                           (int)Sst);
-    };
-
-    auto reliable_update = [&]() {
-        flush();
-        double2 *xs = X.as<double2>() + (explicit_mode ? (size_t)seed * n : 0);
-        dslash_launch(lat, SGN_PREC_F64, opA, xs, tmp.p, Epilogue{}, s);
-        Epilogue ep;
-        ep.a = -c2;
-        ep.z = xs;
-        ep.b = {sigma_seed, 0.0};
-        dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, q.p, ep, s);  // q = -c^2 A A x + sigma x
-        hipLaunchKernelGGL(ms_reliable_kernel, dim3(nvbp), dim3(256), 0, s, y.as<double2>(), q.as<double2>(),
-                           r32.as<float4>(), rt32.as<float4>(), (int)Sst, part);
-        hipLaunchKernelGGL(ms_reliable_coef, dim3(1), dim3(256), 0, s, part, nvbp, S);
-        SGN_HIP(hipGetLastError());
-        if (!explicit_mode) cur = r32.p;
-        ++reliable_updates;
-    };
-
-    auto switch_to_f32 = [&]() {
-        convert_64_to_32(explicit_mode ? r.p : cur, r32.p, Sst, s);
-        if (!explicit_mode) cur = r32.p;
-        convert_64_to_32(rt.p, rt32.p, Sst, s);
-        convert_64_to_32(pt.p, pt32.p, Sst, s);
-        for (int i = 0; i < nxv(); ++i)
-            convert_64_to_32(P.as<char>() + (size_t)i * b64, P32.as<char>() + (size_t)i * b32, Sst, s);
-        hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlo.as<float2>(), make_float2(0, 0),
-                           (int64_t)nxv() * n);
-        SGN_HIP(hipGetLastError());
-    };
-
-    // out (+)= sum_j coef[j] slot_j over slots 0..K-1
-    auto lift = [&](const std::vector<z64> &coef, void *out, bool accumulate) {
-        const int K = (int)coef.size();
-        std::vector<LiftSlot> hs(K);
-        double bytes = accumulate ? 2.0 * b64 : (double)b64;
-        for (int j = 0; j < K; ++j) {
-            hs[j] = LiftSlot{slot_ptr(j), slot_f32[j], 0};
-            bytes += (coef[j].r != 0.0 || coef[j].i != 0.0) ? (slot_f32[j] ? (double)b32 : (double)b64) : 0.0;
+        for (auto &p : pr_) {
+            if (!p.active) continue;
+            ++p.launched;
+            if (!p.explicit_mode) {
+                if ((int)p.slot_f32.size() <= p.launched) p.slot_f32.resize(p.launched + 1, 0);
+                p.slot_f32[p.launched] = p.phase >= 1 ? 1 : 0;
+            }
         }
-        DevMem dsl(sizeof(LiftSlot) * std::max(K, 1)), dcf(sizeof(z64) * std::max(K, 1));
+    }
+    SGN_HIP(hipGetLastError());
+}
+
+void MultishiftBatch::flush(MsProblem &p)
+{
+    hipLaunchKernelGGL(ms_flush_kernel, dim3(vec_blocks(6 * p.Sst)), dim3(256), 0, s_, p.X.as<double2>(),
+                       p.Xlo.as<float4>(), p.explicit_mode ? ns_ : 1, (int)p.Sst);
+}
+
+void MultishiftBatch::reliable_update(MsProblem &p)
+{
+    flush(p);
+    double2 *xs = p.X.as<double2>() + (p.explicit_mode ? (size_t)seed_ * p.n : 0);
+    dslash_launch(*p.lat, SGN_PREC_F64, p.opA, xs, p.tmp.p, Epilogue{}, s_);
+    Epilogue ep;
+    ep.a = -c2_;
+    ep.z = xs;
+    ep.b = {s1_, 0.0};
+    dslash_launch(*p.lat, SGN_PREC_F64, p.opA, p.tmp.p, p.q.p, ep, s_);  // q = -c^2 A A x + sigma x
+    const int nvbp = vec_blocks(6 * p.Sst);
+    z64 *part = p.vpart + 2 * kVecGrid;
+    hipLaunchKernelGGL(ms_reliable_kernel, dim3(nvbp), dim3(256), 0, s_, p.y.as<double2>(), p.q.as<double2>(),
+                       p.r32.as<float4>(), p.rt32.as<float4>(), (int)p.Sst, part);
+    hipLaunchKernelGGL(ms_reliable_coef, dim3(1), dim3(256), 0, s_, part, nvbp, p.S);
+    SGN_HIP(hipGetLastError());
+    if (!p.explicit_mode) {  // the next seed update starts from r32 instead of its slot
+        p.temp_iter = p.launched;
+        dirty_vec_ = true;
+    }
+    ++p.reliable_updates;
+}
+
+void MultishiftBatch::switch_to_f32(MsProblem &p)
+{
+    convert_64_to_32(p.explicit_mode ? p.r.p : slot_ptr(p, p.launched), p.r32.p, p.Sst, s_);
+    if (!p.explicit_mode) p.temp_iter = p.launched;
+    convert_64_to_32(p.rt.p, p.rt32.p, p.Sst, s_);
+    convert_64_to_32(p.pt.p, p.pt32.p, p.Sst, s_);
+    const int np0 = p.explicit_mode ? ns_ : 1;
+    for (int i = 0; i < np0; ++i)
+        convert_64_to_32(p.P.as<char>() + (size_t)i * p.b64, p.P32.as<char>() + (size_t)i * p.b32, p.Sst, s_);
+    hipLaunchKernelGGL(fill_kernel<float2>, dim3(vec_blocks(p.n)), dim3(256), 0, s_, p.Xlo.as<float2>(),
+                       make_float2(0, 0), (int64_t)np0 * p.n);
+    SGN_HIP(hipGetLastError());
+    dirty_ = true;
+}
+
+// out (+)= sum_j coef[j] slot_j over slots 0..K-1
+void MultishiftBatch::lift(MsProblem &p, const std::vector<z64> &coef, void *out, bool accumulate)
+{
+    const int K = (int)coef.size();
+    std::vector<LiftSlot> hs(K);
+    double bytes = accumulate ? 2.0 * p.b64 : (double)p.b64;
+    for (int j = 0; j < K; ++j) {
+        hs[j] = LiftSlot{slot_ptr(p, j), p.slot_f32[j], 0};
+        bytes += (coef[j].r != 0.0 || coef[j].i != 0.0) ? (p.slot_f32[j] ? (double)p.b32 : (double)p.b64) : 0.0;
+    }
+    DevMem dsl(sizeof(LiftSlot) * std::max(K, 1)), dcf(sizeof(z64) * std::max(K, 1));
+    if (K) {
         SGN_HIP(hipMemcpy(dsl.p, hs.data(), sizeof(LiftSlot) * K, hipMemcpyHostToDevice));
         SGN_HIP(hipMemcpy(dcf.p, coef.data(), sizeof(z64) * K, hipMemcpyHostToDevice));
-        const int pr = ctx.prof_start(s);
-        bool acc = accumulate;
-        for (int j0 = 0; j0 < K || (j0 == 0 && !acc); j0 += kLiftChunk) {
-            const int kk = std::min(kLiftChunk, K - j0);
-            hipLaunchKernelGGL(ms_lift_kernel, dim3(nvb), dim3(256), 0, s, dsl.as<LiftSlot>() + j0,
-                               dcf.as<z64>() + j0, kk, (int)Sst, static_cast<double2 *>(out), acc ? 1 : 0);
-            acc = true;
-            if (K == 0) break;
-        }
-        SGN_HIP(hipGetLastError());
-        ctx.prof_stop(pr, s, SGN_K_LIFT, bytes, 8.0 * n * K);
-        SGN_HIP(hipStreamSynchronize(s));  // dsl, dcf go out of scope
-    };
-    auto history = [&](int k) {
-        std::vector<MsHist> H((size_t)k * ns);
-        if (k > 0) SGN_HIP(hipMemcpy(H.data(), hist, sizeof(MsHist) * H.size(), hipMemcpyDeviceToHost));
-        return H;
-    };
+    }
+    const int pr = ctx_->prof_start(s_);
+    const int nvb = vec_blocks(p.n);
+    if (K == 0 && !accumulate)
+        hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s_, static_cast<double2 *>(out),
+                           make_double2(0, 0), p.n);
+    for (int j0 = 0; j0 < K; j0 += kLiftChunk) {
+        const int kk = std::min(kLiftChunk, K - j0);
+        hipLaunchKernelGGL(ms_lift_kernel, dim3(nvb), dim3(256), 0, s_, dsl.as<LiftSlot>() + j0, dcf.as<z64>() + j0,
+                           kk, (int)p.Sst, static_cast<double2 *>(out), (accumulate || j0 > 0) ? 1 : 0);
+    }
+    SGN_HIP(hipGetLastError());
+    ctx_->prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * p.n * K);
+    SGN_HIP(hipStreamSynchronize(s_));  // dsl, dcf go out of scope
+}
 
-    // Turn the stored basis into explicit p_i, x_i at iteration k = launched
-    // (all launched iterations have run) and continue with per-shift vectors.
-    auto to_explicit = [&]() {
-        const int k = launched;
-        const std::vector<MsHist> H = history(k);
-        xp64 = std::make_unique<DevMem>(2 * (size_t)ns * b64);
-        if (mixed) xp32 = std::make_unique<DevMem>(2 * (size_t)ns * b32);
-        Span Xn{xp64->p}, Pn{xp64->as<char>() + (size_t)ns * b64};
-        Span Xlon{mixed ? xp32->p : nullptr}, P32n{mixed ? xp32->as<char>() + (size_t)ns * b32 : nullptr};
-        if (phase >= 1) flush();
-        std::vector<z64> cj, aj;
-        for (int i = 0; i < ns; ++i) {
-            char *xi = Xn.as<char>() + (size_t)i * b64, *pi = Pn.as<char>() + (size_t)i * b64;
-            if (i == seed) {
-                SGN_HIP(hipMemcpyAsync(xi, X.p, b64, hipMemcpyDeviceToDevice, s));
-                if (phase >= 1)
-                    SGN_HIP(hipMemcpyAsync(P32n.as<char>() + (size_t)i * b32, P32.p, b32, hipMemcpyDeviceToDevice, s));
-                else
-                    SGN_HIP(hipMemcpyAsync(pi, P.p, b64, hipMemcpyDeviceToDevice, s));
-                continue;
-            }
-            basis_coefficients(H, ns, k, i, &cj, &aj);
-            lift(cj, xi, false);
-            lift(aj, pi, false);
-            if (phase >= 1) convert_64_to_32(pi, P32n.as<char>() + (size_t)i * b32, Sst, s);
-        }
-        if (mixed)
-            hipLaunchKernelGGL(fill_kernel<float2>, dim3(nvb), dim3(256), 0, s, Xlon.as<float2>(), make_float2(0, 0),
-                               (int64_t)ns * n);
-        // the explicit form keeps the current residual in r (FP64) or r32
-        if (phase >= 1) {
-            if (cur != r32.p) SGN_HIP(hipMemcpyAsync(r32.p, cur, b32, hipMemcpyDeviceToDevice, s));
-        } else {
-            SGN_HIP(hipMemcpyAsync(r.p, cur, b64, hipMemcpyDeviceToDevice, s));
-        }
-        SGN_HIP(hipStreamSynchronize(s));
-        X = Xn;
-        P = Pn;
-        Xlo = Xlon;
-        P32 = P32n;
-        explicit_mode = true;
-    };
+std::vector<MsHist> MultishiftBatch::history(const MsProblem &p, int k)
+{
+    std::vector<MsHist> H((size_t)k * ns_);
+    if (k > 0) SGN_HIP(hipMemcpy(H.data(), p.hist, sizeof(MsHist) * H.size(), hipMemcpyDeviceToHost));
+    return H;
+}
 
-    MsHead hh{};
-    auto read_head = [&]() {
-        SGN_HIP(hipMemcpyAsync(&hh, &S->h, sizeof(MsHead), hipMemcpyDeviceToHost, s));
-        SGN_HIP(hipStreamSynchronize(s));
-        launched = hh.iter;
-    };
-    auto put = [&](void *dst, const void *src, size_t bytes) {
-        SGN_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
-        SGN_HIP(hipStreamSynchronize(s));
-    };
-    auto set_phase = [&](int ph) {
-        phase = ph;
-        const int zero = 0;
-        put(&S->h.phase, &ph, sizeof(int));
-        put(&S->h.want_phase, &zero, sizeof(int));
-    };
-
-    const auto t_kry = std::chrono::steady_clock::now();
-    sgn_status result = SGN_OK;
-    for (;;) {
-        if (!explicit_mode) {
-            // slots for the next chunk; past the budget the basis becomes explicit vectors
-            const int upto = launched + poll;
-            if (upto > slot_cap || !ctx.ensure_basis(upto - 1, b64)) to_explicit();
-        }
-        const int iter_before = launched;
-        iterate(poll);
-        read_head();
-        if (!explicit_mode && hh.iter > iter_before) cur = slot_ptr(hh.iter);
-        if (hh.breakdown) throw Failure{SGN_ERR_BREAKDOWN, "multishift BiCG breakdown at iteration " + std::to_string(hh.iter)};
-        if (hh.done) {
-            if (phase >= 1) {
-                reliable_update();
-                read_head();
-                if (!hh.done) continue;
-            }
-            if (hh.iter >= maxiter && hh.rnorm > o.tol * ynorm) result = SGN_ERR_NOT_CONVERGED;
-            break;
-        }
-        if (mixed && hh.want_phase > phase) {
-            if (phase == 0) {
-                switch_to_f32();
-                set_phase(1);
-                const double rm = hh.rnorm;
-                put(&S->h.rmax, &rm, sizeof(double));
-            } else if (phase == 1 && o.prec == SGN_PREC_F32_H16) {
-                set_phase(2);
-            }
+// Turn the stored basis into explicit p_i, x_i at iteration k = launched
+// (all launched iterations have run) and continue with per-shift vectors.
+void MultishiftBatch::to_explicit(MsProblem &p)
+{
+    const int k = p.launched;
+    const std::vector<MsHist> H = history(p, k);
+    p.xp64 = std::make_unique<DevMem>(2 * (size_t)ns_ * p.b64);
+    if (mixed_) p.xp32 = std::make_unique<DevMem>(2 * (size_t)ns_ * p.b32);
+    Span Xn{p.xp64->p}, Pn{p.xp64->as<char>() + (size_t)ns_ * p.b64};
+    Span Xlon{mixed_ ? p.xp32->p : nullptr}, P32n{mixed_ ? p.xp32->as<char>() + (size_t)ns_ * p.b32 : nullptr};
+    if (p.phase >= 1) flush(p);
+    std::vector<z64> cj, aj;
+    for (int i = 0; i < ns_; ++i) {
+        char *xi = Xn.as<char>() + (size_t)i * p.b64, *pi = Pn.as<char>() + (size_t)i * p.b64;
+        if (i == seed_) {
+            SGN_HIP(hipMemcpyAsync(xi, p.X.p, p.b64, hipMemcpyDeviceToDevice, s_));
+            if (p.phase >= 1)
+                SGN_HIP(hipMemcpyAsync(P32n.as<char>() + (size_t)i * p.b32, p.P32.p, p.b32, hipMemcpyDeviceToDevice, s_));
+            else
+                SGN_HIP(hipMemcpyAsync(pi, p.P.p, p.b64, hipMemcpyDeviceToDevice, s_));
             continue;
         }
-        if (phase >= 1 && hh.reliable) reliable_update();
+        basis_coefficients(H, ns_, k, i, &cj, &aj);
+        lift(p, cj, xi, false);
+        lift(p, aj, pi, false);
+        if (p.phase >= 1) convert_64_to_32(pi, P32n.as<char>() + (size_t)i * p.b32, p.Sst, s_);
     }
-    if (phase >= 1) flush();
-    const double kry_ms = ms_since(t_kry);
+    if (mixed_)
+        hipLaunchKernelGGL(fill_kernel<float2>, dim3(vec_blocks(p.n)), dim3(256), 0, s_, Xlon.as<float2>(),
+                           make_float2(0, 0), (int64_t)ns_ * p.n);
+    // the per-shift form keeps the current residual in r (FP64) or r32
+    void *cur = (p.temp_iter == k) ? (p.phase >= 1 ? p.r32.p : p.r.p) : slot_ptr(p, k);
+    if (p.phase >= 1) {
+        if (cur != p.r32.p) SGN_HIP(hipMemcpyAsync(p.r32.p, cur, p.b32, hipMemcpyDeviceToDevice, s_));
+    } else {
+        if (cur != p.r.p) SGN_HIP(hipMemcpyAsync(p.r.p, cur, p.b64, hipMemcpyDeviceToDevice, s_));
+    }
+    SGN_HIP(hipStreamSynchronize(s_));
+    p.X = Xn;
+    p.P = Pn;
+    p.Xlo = Xlon;
+    p.P32 = P32n;
+    p.explicit_mode = true;
+    dirty_ = true;
+}
 
-    // x += sum_i omega_i x_i
-    {
-        if (explicit_mode) {
-            DevMem w(sizeof(double) * ns);
-            SGN_HIP(hipMemcpy(w.p, rf.omega, sizeof(double) * ns, hipMemcpyHostToDevice));
-            hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s, X.as<double2>(), w.as<double>(), ns, n,
-                               tmp.as<double2>());
+void MultishiftBatch::read_heads()
+{
+    for (auto &p : pr_)
+        if (p.active) SGN_HIP(hipMemcpyAsync(&p.hh, &p.S->h, sizeof(MsHead), hipMemcpyDeviceToHost, s_));
+    SGN_HIP(hipStreamSynchronize(s_));
+    for (auto &p : pr_)
+        if (p.active) p.launched = p.hh.iter;
+}
+
+// x += sum_i omega_i x_i, outputs and statistics of one problem
+void MultishiftBatch::finish(MsProblem &p)
+{
+    Lattice &lat = *p.lat;
+    const int nvb = vec_blocks(p.n);
+    if (p.ynorm != 0.0) {
+        if (p.explicit_mode) {
+            DevMem w(sizeof(double) * ns_);
+            SGN_HIP(hipMemcpy(w.p, rf_.omega, sizeof(double) * ns_, hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(ms_combine_kernel, dim3(nvb), dim3(256), 0, s_, p.X.as<double2>(), w.as<double>(),
+                               ns_, p.n, p.tmp.as<double2>());
             SGN_HIP(hipGetLastError());
-            SGN_HIP(hipStreamSynchronize(s));
+            SGN_HIP(hipStreamSynchronize(s_));
         } else {
             // omega_seed x_seed + sum_j d_j r_j,  d_j = sum_{i != seed} omega_i c_ij
-            const int K = launched;
-            const std::vector<MsHist> H = history(K);
+            const int K = p.launched;
+            const std::vector<MsHist> H = history(p, K);
             std::vector<z64> d(K, z64{0.0, 0.0}), cj;
-            for (int i = 0; i < ns; ++i) {
-                if (i == seed) continue;
-                basis_coefficients(H, ns, K, i, &cj, nullptr);
-                for (int j = 0; j < K; ++j) d[j] = d[j] + rf.omega[i] * cj[j];
+            for (int i = 0; i < ns_; ++i) {
+                if (i == seed_) continue;
+                basis_coefficients(H, ns_, K, i, &cj, nullptr);
+                for (int j = 0; j < K; ++j) d[j] = d[j] + rf_.omega[i] * cj[j];
             }
-            scale64({rf.omega[seed], 0.0}, X.p, tmp.p, n, s);
-            lift(d, tmp.p, true);
+            scale64({rf_.omega[seed_], 0.0}, p.X.p, p.tmp.p, p.n, s_);
+            lift(p, d, p.tmp.p, true);
         }
-        unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
-        axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, nc, s);
-        if (pb.x_shift)
-            for (int i = 0; i < ns; ++i)
-                if (pb.x_shift[i]) unpack_spinor(lat, X.as<char>() + (size_t)i * b64, pb.x_shift[i], SGN_PREC_F64, s);
-        SGN_HIP(hipStreamSynchronize(s));
+        unpack_spinor(lat, p.tmp.p, p.rcan.p, SGN_PREC_F64, s_);
+        axpby64({1.0, 0.0}, p.rcan.p, {1.0, 0.0}, p.pb->x, p.nc, s_);
     }
-    if (st) {
-        MsState hs;
-        SGN_HIP(hipMemcpy(&hs, S, sizeof(MsState), hipMemcpyDeviceToHost));
-        st->iterations = hs.h.iter;
-        st->matvecs = 4 * hs.h.iter + 1 + 2 * reliable_updates;
-        st->reliable_updates = reliable_updates;
-        double mx = 0.0;
-        for (int i = 0; i < ns; ++i) {
-            st->shift_residual[i] = hs.res[i] / ynorm;
+    if (p.pb->x_shift)
+        for (int i = 0; i < ns_; ++i)
+            if (p.pb->x_shift[i]) {
+                if (p.ynorm != 0.0)
+                    unpack_spinor(lat, p.X.as<char>() + (size_t)i * p.b64, p.pb->x_shift[i], SGN_PREC_F64, s_);
+                else
+                    SGN_HIP(hipMemsetAsync(p.pb->x_shift[i], 0, p.c64, s_));
+            }
+    SGN_HIP(hipStreamSynchronize(s_));
+    if (!p.st || p.ynorm == 0.0) return;
+    sgn_stats *st = p.st;
+    MsState hs;
+    SGN_HIP(hipMemcpy(&hs, p.S, sizeof(MsState), hipMemcpyDeviceToHost));
+    st->iterations = hs.h.iter;
+    st->matvecs = 4 * hs.h.iter + 1 + 2 * p.reliable_updates;
+    st->reliable_updates = p.reliable_updates;
+    double mx = 0.0;
+    for (int i = 0; i < ns_; ++i) {
+        st->shift_residual[i] = hs.res[i] / p.ynorm;
+        mx = std::max(mx, st->shift_residual[i]);
+    }
+    if (o_.verify) {  // FP64 true residuals of every shifted system
+        mx = 0.0;
+        for (int i = 0; i < ns_; ++i) {
+            double2 *xi = p.X.as<double2>() + (size_t)i * p.n;
+            dslash_launch(lat, SGN_PREC_F64, p.opA, xi, p.tmp.p, Epilogue{}, s_);
+            Epilogue ep;
+            ep.a = -c2_;
+            ep.z = xi;
+            ep.b = {rf_.sigma[i], 0.0};
+            dslash_launch(lat, SGN_PREC_F64, p.opA, p.tmp.p, p.q.p, ep, s_);
+            axpby64({1.0, 0.0}, p.y.p, {1.0, 0.0}, p.q.p, p.n, s_);
+            st->shift_residual[i] = norm_sync(*ctx_, p.q.p, p.n, false, s_) / p.ynorm;
             mx = std::max(mx, st->shift_residual[i]);
         }
-        if (o.verify) {  // FP64 true residuals of every shifted system
-            mx = 0.0;
-            for (int i = 0; i < ns; ++i) {
-                double2 *xi = X.as<double2>() + (size_t)i * n;
-                dslash_launch(lat, SGN_PREC_F64, opA, xi, tmp.p, Epilogue{}, s);
-                Epilogue ep;
-                ep.a = -c2;
-                ep.z = xi;
-                ep.b = {rf.sigma[i], 0.0};
-                dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, q.p, ep, s);
-                axpby64({1.0, 0.0}, y.p, {1.0, 0.0}, q.p, n, s);
-                st->shift_residual[i] = norm_sync(ctx, q.p, n, false, s) / ynorm;
-                mx = std::max(mx, st->shift_residual[i]);
-            }
-            st->matvecs += 2 * ns;
-        }
-        st->residual = mx;
-        st->krylov_ms = kry_ms;
-        st->total_ms = ms_since(t_start);
+        st->matvecs += 2 * ns_;
     }
-    return result;
+    st->residual = mx;
+    st->krylov_ms = p.kry_ms;
+    st->total_ms = ms_since(t_start_);
+}
+
+sgn_status MultishiftBatch::run()
+{
+    for (auto &p : pr_) setup(p);
+    const auto t_kry = std::chrono::steady_clock::now();
+    for (;;) {
+        bool any = false;
+        for (auto &p : pr_) {
+            if (!p.active) continue;
+            any = true;
+            // slots for the next chunk; past the budget the basis becomes per-shift vectors
+            if (!p.explicit_mode && !ensure_slots(p, p.launched + poll_)) to_explicit(p);
+        }
+        if (!any) break;
+        if (dirty_) {
+            rebuild();
+        } else if (dirty_vec_) {
+            for (int k = 0; k < (int)pr_.size(); ++k) fill_vec(k);
+            SGN_HIP(hipMemcpy(dvec_, hvec_.data(), sizeof(MsVec) * pr_.size(), hipMemcpyHostToDevice));
+            dirty_vec_ = false;
+        }
+        iterate(poll_);
+        read_heads();
+        for (auto &p : pr_) {
+            if (!p.active) continue;
+            MsHead &hh = p.hh;
+            if (hh.breakdown)
+                throw Failure{SGN_ERR_BREAKDOWN, "multishift BiCG breakdown at iteration " + std::to_string(hh.iter)};
+            if (hh.done) {
+                if (p.phase >= 1) {
+                    reliable_update(p);
+                    SGN_HIP(hipMemcpyAsync(&hh, &p.S->h, sizeof(MsHead), hipMemcpyDeviceToHost, s_));
+                    SGN_HIP(hipStreamSynchronize(s_));
+                    if (!hh.done) continue;
+                }
+                if (hh.iter >= maxiter_ && hh.rnorm > o_.tol * p.ynorm) p.result = SGN_ERR_NOT_CONVERGED;
+                if (p.phase >= 1) flush(p);
+                p.kry_ms = ms_since(t_kry);
+                p.active = false;
+                dirty_ = true;
+                continue;
+            }
+            if (mixed_ && hh.want_phase > p.phase) {
+                const int zero = 0;
+                if (p.phase == 0) {
+                    switch_to_f32(p);
+                    p.phase = 1;
+                    const double rm = hh.rnorm;
+                    SGN_HIP(hipMemcpyAsync(&p.S->h.rmax, &rm, sizeof(double), hipMemcpyHostToDevice, s_));
+                    SGN_HIP(hipStreamSynchronize(s_));
+                } else if (p.phase == 1 && o_.prec == SGN_PREC_F32_H16) {
+                    p.phase = 2;
+                }
+                const int ph = p.phase;
+                SGN_HIP(hipMemcpyAsync(&p.S->h.phase, &ph, sizeof(int), hipMemcpyHostToDevice, s_));
+                SGN_HIP(hipMemcpyAsync(&p.S->h.want_phase, &zero, sizeof(int), hipMemcpyHostToDevice, s_));
+                SGN_HIP(hipStreamSynchronize(s_));
+                dirty_ = true;
+                continue;
+            }
+            if (p.phase >= 1 && hh.reliable) reliable_update(p);
+        }
+    }
+    sgn_status worst = SGN_OK;
+    for (auto &p : pr_) {
+        finish(p);
+        if (p.result != SGN_OK && worst == SGN_OK) worst = p.result;
+    }
+    return worst;
 }
 
 }  // namespace
@@ -958,11 +1245,9 @@ extern "C" sgn_status multishift_solve(const sgn_problem *pb, int nprob, const s
             SGN_REQUIRE(pb[p].lat && pb[p].b && pb[p].x, "multishift_solve: null problem field");
             SGN_REQUIRE(std::isfinite(pb[p].mu), "multishift_solve: mu not finite");
         }
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        for (int p = 0; p < nprob; ++p) {
-            const sgn_status r = solve_one(pb[p], *rf, *o, stats ? &stats[p] : nullptr, s);
-            if (r != SGN_OK && worst == SGN_OK) worst = r;
-        }
+        if (nprob == 0) return;
+        MultishiftBatch batch(pb, nprob, *rf, *o, stats, static_cast<hipStream_t>(stream));
+        worst = batch.run();
     });
     return st != SGN_OK ? st : worst;
 }

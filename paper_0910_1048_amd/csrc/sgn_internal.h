@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -119,12 +120,9 @@ struct Context {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     void *ensure_arena(size_t bytes);
-    // stored Krylov vectors of the multishift solver (slot j >= 1), kept between calls;
-    // ensure_basis returns false when slot j cannot be allocated
-    std::vector<void *> basis;
-    size_t basis_slot_bytes = 0;
-    bool ensure_basis(int j, size_t bytes);
-    size_t basis_bytes() const { return basis.size() * basis_slot_bytes; }
+    // stored Krylov vectors of the multishift solver, one pool per vector size,
+    // kept between calls
+    std::map<size_t, std::vector<void *>> basis_pools;
 };
 
 struct Lattice {
@@ -186,6 +184,42 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
 int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,
                   const Epilogue &ep, hipStream_t s);
 int dslash_blocks(const Lattice &lat);
+
+// One single-RHS stencil application of a batch.
+struct StencilJob {
+    const Lattice *lat = nullptr;
+    OpSpec op;
+    const void *in = nullptr;
+    void *out = nullptr;
+    Epilogue ep;
+};
+
+// Independent applications of one precision (own lattices, fields, epilogues)
+// launched together: one launch, blockIdx.y selecting the application, with
+// the parameters kept in device memory between launches.  Falls back to one
+// launch per application when some lattice has no staged block shape.
+class StencilBatch {
+  public:
+    StencilBatch() = default;
+    ~StencilBatch();
+    StencilBatch(const StencilBatch &) = delete;
+    StencilBatch &operator=(const StencilBatch &) = delete;
+    void prepare(const std::vector<StencilJob> &jobs, sgn_prec p);  // synchronous upload
+    void launch(hipStream_t s) const;
+    int blocks(size_t k) const { return nblk_[k]; }  // partials written by application k
+    size_t size() const { return jobs_.size(); }
+
+  private:
+    std::vector<StencilJob> jobs_;
+    std::vector<int> nblk_;
+    sgn_prec prec_ = SGN_PREC_F64;
+    void *dev_ = nullptr;
+    size_t dev_bytes_ = 0;
+    int gx_ = 0, threads_ = 0;
+    size_t lds_ = 0;
+    bool batched_ = false, epi_ = false, dot_ = false;
+    double bytes_ = 0.0, flops_ = 0.0;
+};
 
 void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s);
 void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_prec p, hipStream_t s);
