@@ -237,6 +237,8 @@ typedef struct {
     int basis_slots;    /* Krylov-basis storage of the non-seed shifts (see multishift_solve):
                            0: automatic (up to half of the device memory free at the start),
                            > 0: at most this many stored residual vectors, < 0: never */
+    int graph;          /* 0: the iterations between two polls are captured once as a HIP graph and
+                           replayed (not while profiling); < 0: plain launches */
 } sgn_ms_opts;
 
 /* BiCG-LR(m) (section "Two-sided Lanczos with rational functions"): for each

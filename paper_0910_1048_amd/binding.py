@@ -233,7 +233,7 @@ class _Problem(C.Structure):
 class MsOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("prec", C.c_int), ("theta32", C.c_double),
                 ("theta16", C.c_double), ("delta", C.c_double), ("poll", C.c_int), ("verify", C.c_int),
-                ("basis_slots", C.c_int)]
+                ("basis_slots", C.c_int), ("graph", C.c_int)]
 
 
 lib.sgn_rational_neuberger.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(Rational)]
@@ -262,7 +262,7 @@ class Problem:
 
 
 def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
-                     delta=0.0, poll=0, verify=False, basis_slots=0, stream=None):
+                     delta=0.0, poll=0, verify=False, basis_slots=0, graph=True, stream=None):
     """Multishift BiCG-LR for every problem; returns one stats dict per problem."""
     if isinstance(problems, Problem):
         problems = [problems]
@@ -281,7 +281,7 @@ def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, the
             keep.append(xs)
             arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
     o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll),
-               int(bool(verify)), int(basis_slots))
+               int(bool(verify)), int(basis_slots), 0 if graph else -1)
     st = (Stats * max(n, 1))()
     check(lib.multishift_solve(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_solve")
     return [st[i].as_dict() for i in range(n)]

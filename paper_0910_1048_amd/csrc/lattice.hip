@@ -207,6 +207,7 @@ extern "C" sgn_status sgn_finalize(sgn_handle h)
         if (c->byte_counter) SGN_HIP(hipFree(c->byte_counter));
         for (auto &kv : c->basis_pools)
             for (void *b : kv.second) SGN_HIP(hipFree(b));
+        if (c->capture_stream) SGN_HIP(hipStreamDestroy(c->capture_stream));
         for (auto &r : c->prof_recs) {
             (void)hipEventDestroy(r.start);
             (void)hipEventDestroy(r.stop);

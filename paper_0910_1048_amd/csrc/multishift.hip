@@ -589,6 +589,12 @@ class MultishiftBatch {
   public:
     MultishiftBatch(const sgn_problem *pb, int nprob, const sgn_rational &rf, const sgn_ms_opts &o,
                     sgn_stats *stats, hipStream_t s);
+    ~MultishiftBatch()
+    {
+        if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    }
+    MultishiftBatch(const MultishiftBatch &) = delete;
+    MultishiftBatch &operator=(const MultishiftBatch &) = delete;
     sgn_status run();
 
   private:
@@ -609,11 +615,19 @@ class MultishiftBatch {
     bool dirty_ = true;             // lists and stencil batches need rebuilding
     bool dirty_vec_ = false;        // only the descriptors changed
     std::map<size_t, size_t> pool_next_;  // next unused pooled slot per vector size in this call
+    hipGraphExec_t gexec_ = nullptr;       // captured chunk of poll_ iterations (valid until the next rebuild)
+    bool use_graph_ = false;
 
     void setup(MsProblem &p);
     void rebuild();
     void fill_vec(int k);
-    void iterate(int count);
+    void iterate(int count);               // launches + host bookkeeping of count iterations
+    void launch_iterations(int count, hipStream_t strm);
+    void drop_graph()
+    {
+        if (gexec_) SGN_HIP(hipGraphExecDestroy(gexec_));
+        gexec_ = nullptr;
+    }
     void *slot_ptr(const MsProblem &p, int j) const { return p.slots[(size_t)j]; }
     bool ensure_slots(MsProblem &p, int upto);
     void flush(MsProblem &p);
@@ -647,6 +661,7 @@ MultishiftBatch::MultishiftBatch(const sgn_problem *pb, int nprob, const sgn_rat
         if (std::abs(rf.sigma[i]) < std::abs(rf.sigma[seed_])) seed_ = i;
     s1_ = rf.sigma[seed_];
     maxiter_ = o.maxiter > 0 ? o.maxiter : 10000;
+    use_graph_ = o.graph >= 0;
     pr_.resize(nprob);
     double basis_bytes_per_iter = 0.0;
     int64_t vtot = 0;
@@ -841,6 +856,7 @@ void MultishiftBatch::fill_vec(int k)
 // descriptors, problem lists and stencil batches for the current phases and forms
 void MultishiftBatch::rebuild()
 {
+    drop_graph();
     const int np = (int)pr_.size();
     for (auto &l : lists_)
         for (auto &m : l) m.clear();
@@ -888,53 +904,31 @@ void MultishiftBatch::rebuild()
 
 void MultishiftBatch::iterate(int count)
 {
-    const int np = (int)pr_.size();
-    unsigned long long *bc = ctx_->prof ? ctx_->byte_counter : nullptr;
-    for (int it = 0; it < count; ++it) {
-        for (int ph = 0; ph < 3; ++ph) {
-            const int nb = (int)lists_[ph][0].size(), ne = (int)lists_[ph][1].size();
-            if (nb + ne == 0) continue;
-            for (int st = 0; st < 4; ++st) stb_[ph][st].launch(s_);
-            const int *lb = dlist_ + (size_t)(2 * ph) * np, *le = dlist_ + (size_t)(2 * ph + 1) * np;
-            const bool lo = ph >= 1;
-            if (nb) hipLaunchKernelGGL(ms_alpha_kernel, dim3(nb), dim3(256), 0, s_, dvec_, lb);
-            if (ne) hipLaunchKernelGGL(ms_alpha_kernel, dim3(ne), dim3(256), 0, s_, dvec_, le);
-            double elems = 0.0;
-            for (int form = 0; form < 2; ++form)
-                for (int k : lists_[ph][form]) elems += (double)pr_[k].n;
-            const double eb = lo ? 8.0 : 16.0;
-            int pr = ctx_->prof_start(s_);
-            for (int form = 0; form < 2; ++form) {
-                const int cnt = form ? ne : nb;
-                if (!cnt) continue;
-                const int *l = form ? le : lb;
-                if (lo)
-                    hipLaunchKernelGGL(ms_seed_update<float>, dim3(kVecGrid, cnt), dim3(256), 0, s_, dvec_, l);
-                else
-                    hipLaunchKernelGGL(ms_seed_update<double>, dim3(kVecGrid, cnt), dim3(256), 0, s_, dvec_, l);
+    if (use_graph_ && !ctx_->prof) {
+        if (!gexec_) {
+            // the launches only read device-side state, so one capture serves every chunk until the
+            // descriptors, lists or stencil batches change
+            if (!ctx_->capture_stream) SGN_HIP(hipStreamCreate(&ctx_->capture_stream));
+            hipStream_t cs = ctx_->capture_stream;
+            hipGraph_t g = nullptr;
+            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                launch_iterations(count, cs);
+            } catch (...) {
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
             }
-            ctx_->prof_stop(pr, s_, SGN_K_SEED_UPDATE, 6.0 * eb * elems, 40.0 * elems);
-            if (nb) hipLaunchKernelGGL(ms_beta_kernel, dim3(nb), dim3(256), 0, s_, dvec_, lb, kVecGrid);
-            if (ne) hipLaunchKernelGGL(ms_beta_kernel, dim3(ne), dim3(256), 0, s_, dvec_, le, kVecGrid);
-            pr = ctx_->prof_start(s_);
-            if (nb) {
-                if (lo)
-                    hipLaunchKernelGGL((ms_seed_xp_update<float, float2>), dim3(kVecGrid, nb), dim3(256), 0, s_,
-                                       dvec_, lb, bc);
-                else
-                    hipLaunchKernelGGL((ms_seed_xp_update<double, double2>), dim3(kVecGrid, nb), dim3(256), 0, s_,
-                                       dvec_, lb, bc);
-            }
-            if (ne) {
-                if (lo)
-                    hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(kVecGrid, ne), dim3(256), 0, s_, dvec_,
-                                       le, bc);
-                else
-                    hipLaunchKernelGGL((ms_shift_update<double, double2>), dim3(kVecGrid, ne), dim3(256), 0, s_,
-                                       dvec_, le, bc);
-            }
-            ctx_->prof_stop(pr, s_, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
+            SGN_HIP(hipStreamEndCapture(cs, &g));
+            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SGN_HIP(e);
         }
+        SGN_HIP(hipGraphLaunch(gexec_, s_));
+    } else {
+        launch_iterations(count, s_);
+    }
+    for (int it = 0; it < count; ++it)
         for (auto &p : pr_) {
             if (!p.active) continue;
             ++p.launched;
@@ -942,6 +936,57 @@ void MultishiftBatch::iterate(int count)
                 if ((int)p.slot_f32.size() <= p.launched) p.slot_f32.resize(p.launched + 1, 0);
                 p.slot_f32[p.launched] = p.phase >= 1 ? 1 : 0;
             }
+        }
+}
+
+void MultishiftBatch::launch_iterations(int count, hipStream_t strm)
+{
+    const int np = (int)pr_.size();
+    unsigned long long *bc = ctx_->prof ? ctx_->byte_counter : nullptr;
+    for (int it = 0; it < count; ++it) {
+        for (int ph = 0; ph < 3; ++ph) {
+            const int nb = (int)lists_[ph][0].size(), ne = (int)lists_[ph][1].size();
+            if (nb + ne == 0) continue;
+            for (int st = 0; st < 4; ++st) stb_[ph][st].launch(strm);
+            const int *lb = dlist_ + (size_t)(2 * ph) * np, *le = dlist_ + (size_t)(2 * ph + 1) * np;
+            const bool lo = ph >= 1;
+            if (nb) hipLaunchKernelGGL(ms_alpha_kernel, dim3(nb), dim3(256), 0, strm, dvec_, lb);
+            if (ne) hipLaunchKernelGGL(ms_alpha_kernel, dim3(ne), dim3(256), 0, strm, dvec_, le);
+            double elems = 0.0;
+            for (int form = 0; form < 2; ++form)
+                for (int k : lists_[ph][form]) elems += (double)pr_[k].n;
+            const double eb = lo ? 8.0 : 16.0;
+            int pr = ctx_->prof_start(strm);
+            for (int form = 0; form < 2; ++form) {
+                const int cnt = form ? ne : nb;
+                if (!cnt) continue;
+                const int *l = form ? le : lb;
+                if (lo)
+                    hipLaunchKernelGGL(ms_seed_update<float>, dim3(kVecGrid, cnt), dim3(256), 0, strm, dvec_, l);
+                else
+                    hipLaunchKernelGGL(ms_seed_update<double>, dim3(kVecGrid, cnt), dim3(256), 0, strm, dvec_, l);
+            }
+            ctx_->prof_stop(pr, strm, SGN_K_SEED_UPDATE, 6.0 * eb * elems, 40.0 * elems);
+            if (nb) hipLaunchKernelGGL(ms_beta_kernel, dim3(nb), dim3(256), 0, strm, dvec_, lb, kVecGrid);
+            if (ne) hipLaunchKernelGGL(ms_beta_kernel, dim3(ne), dim3(256), 0, strm, dvec_, le, kVecGrid);
+            pr = ctx_->prof_start(strm);
+            if (nb) {
+                if (lo)
+                    hipLaunchKernelGGL((ms_seed_xp_update<float, float2>), dim3(kVecGrid, nb), dim3(256), 0, strm,
+                                       dvec_, lb, bc);
+                else
+                    hipLaunchKernelGGL((ms_seed_xp_update<double, double2>), dim3(kVecGrid, nb), dim3(256), 0, strm,
+                                       dvec_, lb, bc);
+            }
+            if (ne) {
+                if (lo)
+                    hipLaunchKernelGGL((ms_shift_update<float, float2>), dim3(kVecGrid, ne), dim3(256), 0, strm, dvec_,
+                                       le, bc);
+                else
+                    hipLaunchKernelGGL((ms_shift_update<double, double2>), dim3(kVecGrid, ne), dim3(256), 0, strm,
+                                       dvec_, le, bc);
+            }
+            ctx_->prof_stop(pr, strm, SGN_K_SHIFT_UPDATE, 0.0, 0.0, true);
         }
     }
     SGN_HIP(hipGetLastError());

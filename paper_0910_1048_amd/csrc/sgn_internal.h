@@ -123,6 +123,8 @@ struct Context {
     // stored Krylov vectors of the multishift solver, one pool per vector size,
     // kept between calls
     std::map<size_t, std::vector<void *>> basis_pools;
+    // stream on which solver iterations are captured into HIP graphs
+    hipStream_t capture_stream = nullptr;
 };
 
 struct Lattice {

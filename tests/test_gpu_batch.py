@@ -112,3 +112,18 @@ def test_c4_mixed_batch_of_32():
         e = _rel(x[j], xs[0])
         print(f"C4 problem {j} ({fields[plist[j][0]][0]}): batch mixed vs single FP64 {e:.2e}", flush=True)
         assert e < 1e-8
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32_H16])
+def test_graph_replay_equals_plain_launches(prec):
+    """Iterations replayed from a captured HIP graph (many replays, host work and
+    reliable updates between them) give bit-identical results to plain launches."""
+    rf = sgn.sgn_rational_neuberger(16, ALPHA, BETA)
+    probs = _small_set()
+    xg, sg = _solve(probs, rf, tol=1e-10, prec=prec, poll=3)
+    xp, sp = _solve(probs, rf, tol=1e-10, prec=prec, poll=3, graph=False)
+    for k in range(len(probs)):
+        print(f"prec={prec} problem {k}: iterations {sg[k]['iterations']} / {sp[k]['iterations']}, "
+              f"reliable updates {sg[k]['reliable_updates']}", flush=True)
+        assert sg[k]["iterations"] == sp[k]["iterations"]
+        assert np.array_equal(xg[k], xp[k])
