@@ -198,7 +198,12 @@ typedef struct {
     int kmax;           /* Arnoldi steps per restart cycle (k_max) */
     double tol;         /* every shifted residual |rho_i| ||r|| <= tol ||c H (I-P) b|| */
     int max_restarts;   /* cycles (0: 1000) */
-    sgn_prec prec;      /* SGN_PREC_F64 (the only form implemented; others return SGN_ERR_INVALID) */
+    sgn_prec prec;      /* SGN_PREC_F64: FP64 throughout.  SGN_PREC_F32: cycles start in FP64; once every
+                           shifted residual is below theta32 ||y|| the basis, the stencil and the
+                           Gram-Schmidt vectors are FP32 (FP64 sums, FP64 Hessenberg and x).
+                           SGN_PREC_F32_H16: as F32, with FP16 links below theta16 */
+    double theta32;     /* default 1e-3 if <= 0 */
+    double theta16;     /* default 1e-6 if <= 0 */
 } sgn_arnoldi_opts;
 
 /* Restarted FOM-LR(m, k) (section "Restarted Arnoldi with rational functions"):
@@ -208,7 +213,8 @@ typedef struct {
  * r = (I-P) v_{k+1} after every cycle.  b, x: device canonical complex128.
  * The shifted Hessenberg systems are solved on the host each cycle; the call
  * synchronises `stream`.  SGN_ERR_NOT_CONVERGED after max_restarts cycles
- * (x holds the last iterate). */
+ * (x holds the last iterate).  stats->restarts counts the cycles and
+ * stats->reliable_updates those run with the FP32 basis. */
 sgn_status sign_arnoldi_rational(sgn_lattice lat, double mu, const void *b, void *x, const sgn_rational *r,
                                  const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *stats,
                                  void *stream);

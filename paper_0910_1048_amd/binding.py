@@ -326,7 +326,8 @@ def wilson_apply_multi(lat, mus, xs, outs, prec=F64, flags=INTERNAL_LAYOUT, stre
 
 
 class ArnoldiOpts(C.Structure):
-    _fields_ = [("kmax", C.c_int), ("tol", C.c_double), ("max_restarts", C.c_int), ("prec", C.c_int)]
+    _fields_ = [("kmax", C.c_int), ("tol", C.c_double), ("max_restarts", C.c_int), ("prec", C.c_int),
+                ("theta32", C.c_double), ("theta16", C.c_double)]
 
 
 lib.sign_arnoldi_rational.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(Rational), C.POINTER(_Deflation),
@@ -334,9 +335,9 @@ lib.sign_arnoldi_rational.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(Ratio
 
 
 def sign_arnoldi_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10, max_restarts=0, prec=F64,
-                          stream=None):
+                          theta32=0.0, theta16=0.0, stream=None):
     """x = x_P + g_s(c H_W)(I-P) b by restarted FOM-LR; returns the stats dict."""
-    o = ArnoldiOpts(int(kmax), float(tol), int(max_restarts), int(prec))
+    o = ArnoldiOpts(int(kmax), float(tol), int(max_restarts), int(prec), float(theta32), float(theta16))
     st = Stats()
     d = C.pointer(defl.struct) if defl is not None else None
     check(lib.sign_arnoldi_rational(lat.h, float(mu), _ptr(b), _ptr(x), C.byref(rational), d, C.byref(o),

@@ -42,12 +42,38 @@ __global__ void fom_norm_kernel(const z64 *partials, int nb, z64 *hsub, z64 *inv
     }
 }
 
-__global__ void fom_scale_kernel(const double2 *w, const z64 *inv, double2 *v, int64_t n)
+template <typename T>
+__device__ __forceinline__ T scaled(T t, double s);
+template <> __device__ __forceinline__ double2 scaled<double2>(double2 t, double s) { return make_double2(s * t.x, s * t.y); }
+template <> __device__ __forceinline__ float2 scaled<float2>(float2 t, double s)
 {
-    const double s = inv->r;
+    return make_float2((float)(s * t.x), (float)(s * t.y));
+}
+
+// v = w * (*inv)  (inv on the device) or v = w * a
+template <typename T>
+__global__ void fom_scale_kernel(const T *w, const z64 *inv, double a, T *v, int64_t n)
+{
+    const double s = inv ? inv->r : a;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        v[e] = scaled<T>(w[e], s);
+}
+
+// x[e] += sum_j c_j V_j, V_j FP32 in the [6][S] float4 layout (component c of
+// site st at float2 entry 2 ((c/2) S + st) + c%2), x FP64 in the [12][S] layout
+__global__ void fom_lift32_kernel(const float2 *basis, int Sst, int k, const z64 *c, double2 *x)
+{
+    const int64_t n = (int64_t)12 * Sst;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const double2 t = w[e];
-        v[e] = make_double2(s * t.x, s * t.y);
+        const int comp = (int)(e / Sst), st = (int)(e - (int64_t)comp * Sst);
+        const int64_t e32 = 2 * ((int64_t)(comp >> 1) * Sst + st) + (comp & 1);
+        double2 xv = x[e];
+        z64 acc = {xv.x, xv.y};
+        for (int j = 0; j < k; ++j) {
+            const float2 v = basis[(int64_t)j * n + e32];
+            acc = acc + c[j] * z64{(double)v.x, (double)v.y};
+        }
+        x[e] = make_double2(acc.r, acc.i);
     }
 }
 
@@ -118,7 +144,8 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         SGN_REQUIRE(o->kmax >= 1, "sign_arnoldi_rational: kmax must be >= 1");
         SGN_REQUIRE(o->tol > 0 && o->tol < 1, "sign_arnoldi_rational: tol must be in (0, 1)");
         SGN_REQUIRE(rf->s >= 1 && rf->s <= SGN_MAX_POLES && rf->c > 0, "sign_arnoldi_rational: bad rational function");
-        SGN_REQUIRE(o->prec == SGN_PREC_F64, "sign_arnoldi_rational: only the FP64 form is implemented");
+        SGN_REQUIRE(o->prec == SGN_PREC_F64 || o->prec == SGN_PREC_F32 || o->prec == SGN_PREC_F32_H16,
+                    "sign_arnoldi_rational: unknown precision");
         SGN_REQUIRE(std::isfinite(mu), "sign_arnoldi_rational: mu not finite");
         Lattice &lat = *as_lattice(l);
         Context &ctx = *lat.ctx;
@@ -127,7 +154,9 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         const int k = o->kmax, ns = rf->s;
         // internal vectors: n = 12 S entries (padded stride); canonical: nc = 12 V
         const int64_t V = lat.V, n = 12 * lat.S, nc = 12 * V;
-        const size_t b64 = (size_t)n * 16, c64 = (size_t)nc * 16;
+        const size_t b64 = (size_t)n * 16, b32 = (size_t)n * 8, c64 = (size_t)nc * 16;
+        const bool mixed = o->prec != SGN_PREC_F64;
+        const double theta32 = o->theta32 > 0 ? o->theta32 : 1e-3, theta16 = o->theta16 > 0 ? o->theta16 : 1e-6;
         const int ld = k + 1;
         const double c2 = rf->c * rf->c;
         if (st) {
@@ -141,7 +170,9 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         char *w = Vb + (size_t)(k + 1) * b64, *t = w + b64, *xi = t + b64, *rcan = xi + b64;
         z64 *Hd = reinterpret_cast<z64 *>(rcan + c64);  // column-major (k+1) x k
         z64 *h1 = Hd + (size_t)ld * k, *h2 = h1 + ld, *cd = h2 + ld, *scal = cd + ld;  // scal: hsub, inv
-        auto Vj = [&](int j) { return Vb + (size_t)j * b64; };
+        bool lo = false;                   // this cycle runs in FP32 (basis slots of b32 bytes)
+        sgn_prec sp = SGN_PREC_F64;        // stencil precision of this cycle
+        auto Vj = [&](int j) { return Vb + (size_t)j * (lo ? b32 : b64); };
 
         deflation_prologue(ctx, defl, nc, b, x, rcan, nullptr, s);
         OpSpec opA;
@@ -168,27 +199,42 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         double small_ms = 0.0;
         const auto t_kry = std::chrono::steady_clock::now();
         bool converged = false;
+        double worst_prev = 1.0;  // largest relative shifted residual after the last cycle
+        int lo_cycles = 0;
         for (;;) {
+            // precision of this cycle: FP32 once every shifted residual is below theta32 (then for good)
+            if (mixed && !lo && worst_prev <= theta32) {
+                convert_64_to_32(Vb, t, lat.S, s);  // the start vector v_1 moves to the FP32 basis
+                SGN_HIP(hipMemcpyAsync(Vb, t, b32, hipMemcpyDeviceToDevice, s));
+                lo = true;
+                sp = SGN_PREC_F32;
+            }
+            if (lo && o->prec == SGN_PREC_F32_H16 && worst_prev <= theta16) sp = SGN_PREC_F32_H16;
+            lo_cycles += lo ? 1 : 0;
             int kk = k;
             for (int j = 0; j < k; ++j) {
                 // w = A' v_j
-                dslash_launch(lat, SGN_PREC_F64, opA, Vj(j), t, Epilogue{}, s);
+                dslash_launch(lat, sp, opA, Vj(j), t, Epilogue{}, s);
                 Epilogue ep;
                 ep.a = c2;
-                dslash_launch(lat, SGN_PREC_F64, opA, t, w, ep, s);
+                dslash_launch(lat, sp, opA, t, w, ep, s);
                 matvecs += 2;
-                // classical Gram-Schmidt, twice
-                deflate_dots(Vb, j + 1, w, n, h1, ctx, s);
-                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h1, nullptr, n, s);
-                deflate_dots(Vb, j + 1, w, n, h2, ctx, s);
-                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h2, nullptr, n, s);
+                // classical Gram-Schmidt, twice (FP64 sums also for an FP32 basis)
+                deflate_dots(Vb, j + 1, w, n, h1, ctx, s, lo);
+                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h1, nullptr, n, s, lo);
+                deflate_dots(Vb, j + 1, w, n, h2, ctx, s, lo);
+                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h2, nullptr, n, s, lo);
                 hipLaunchKernelGGL(fom_hcol_kernel, dim3(1), dim3(256), 0, s, h1, h2, j + 1, Hd + (size_t)j * ld);
                 part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nvb, 1)));
-                const int nb = norm2_partials(w, n, false, part, s);
+                const int nb = norm2_partials(w, n, lo, part, s);
                 hipLaunchKernelGGL(fom_norm_kernel, dim3(1), dim3(256), 0, s, part, nb, Hd + (size_t)j * ld + j + 1,
                                    scal + 1);
-                hipLaunchKernelGGL(fom_scale_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)w, scal + 1,
-                                   (double2 *)Vj(j + 1), n);
+                if (lo)
+                    hipLaunchKernelGGL(fom_scale_kernel<float2>, dim3(nvb), dim3(256), 0, s, (const float2 *)w,
+                                       (const z64 *)(scal + 1), 0.0, (float2 *)Vj(j + 1), n);
+                else
+                    hipLaunchKernelGGL(fom_scale_kernel<double2>, dim3(nvb), dim3(256), 0, s, (const double2 *)w,
+                                       (const z64 *)(scal + 1), 0.0, (double2 *)Vj(j + 1), n);
                 SGN_HIP(hipGetLastError());
                 ++steps;
             }
@@ -211,18 +257,32 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
             }
             small_ms += ms_since(t0);
             SGN_HIP(hipMemcpyAsync(cd, comb.data(), sizeof(z64) * kk, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(fom_lift_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)Vb, n, kk, cd,
-                               (double2 *)xi);
+            if (lo)
+                hipLaunchKernelGGL(fom_lift32_kernel, dim3(nvb), dim3(256), 0, s, (const float2 *)Vb, (int)lat.S, kk,
+                                   cd, (double2 *)xi);
+            else
+                hipLaunchKernelGGL(fom_lift_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)Vb, n, kk, cd,
+                                   (double2 *)xi);
             ++cycles;
-            // r = (I - P) v_{k+1}  (canonical round trip for the deflation projection)
+            // r = (I - P) v_{k+1}  (canonical FP64 round trip for the deflation projection)
             double rnorm = 1.0;
             if (defl && defl->m > 0 && kk == k) {
-                unpack_spinor(lat, Vj(k), rcan, SGN_PREC_F64, s);
+                if (lo) {
+                    convert_32_to_64(Vj(k), w, lat.S, s);
+                    unpack_spinor(lat, w, rcan, SGN_PREC_F64, s);
+                } else {
+                    unpack_spinor(lat, Vj(k), rcan, SGN_PREC_F64, s);
+                }
                 deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s);  // t = (I - P) v (canonical)
-                pack_spinor(lat, t, Vj(0), SGN_PREC_F64, s);
-                rnorm = norm_sync(ctx, Vj(0), n, false, s);
+                if (lo) {
+                    pack_spinor(lat, t, w, SGN_PREC_F64, s);
+                    convert_64_to_32(w, Vj(0), lat.S, s);
+                } else {
+                    pack_spinor(lat, t, Vj(0), SGN_PREC_F64, s);
+                }
+                rnorm = norm_sync(ctx, Vj(0), n, lo, s);
             } else if (kk == k) {
-                SGN_HIP(hipMemcpyAsync(Vj(0), Vj(k), b64, hipMemcpyDeviceToDevice, s));
+                SGN_HIP(hipMemcpyAsync(Vj(0), Vj(k), lo ? b32 : b64, hipMemcpyDeviceToDevice, s));
             }
             double worst = 0.0;
             for (int i = 0; i < ns; ++i) {
@@ -235,8 +295,16 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
                 break;
             }
             if (cycles >= max_cycles) break;
+            worst_prev = worst;
             beta = rnorm;
-            if (rnorm != 1.0) scale64({1.0 / rnorm, 0.0}, Vj(0), Vj(0), n, s);
+            if (rnorm != 1.0) {
+                if (lo)
+                    hipLaunchKernelGGL(fom_scale_kernel<float2>, dim3(nvb), dim3(256), 0, s, (const float2 *)Vj(0),
+                                       (const z64 *)nullptr, 1.0 / rnorm, (float2 *)Vj(0), n);
+                else
+                    scale64({1.0 / rnorm, 0.0}, Vj(0), Vj(0), n, s);
+                SGN_HIP(hipGetLastError());
+            }
         }
         // x = x_P + x_int
         unpack_spinor(lat, xi, rcan, SGN_PREC_F64, s);
@@ -246,6 +314,7 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         if (st) {
             st->iterations = steps;
             st->restarts = cycles;
+            st->reliable_updates = lo_cycles;  // cycles run with the FP32 basis
             st->matvecs = matvecs;
             double worst = 0.0;
             for (int i = 0; i < ns; ++i) worst = std::max(worst, st->shift_residual[i]);

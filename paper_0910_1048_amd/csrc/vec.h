@@ -40,9 +40,11 @@ void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s);
 // stored back to back (X + i*n):
 //   c[i] = X_i^H y                              (deflate_dots, c on device)
 //   y = alpha * y + beta * sum_i X_i (d_i c[i])  (deflate_combine; d on device or null = 1)
-void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s);
+// f32: X and y hold complex64 entries (the coefficients and sums stay FP64).
+void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s,
+                  bool f32 = false);
 void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
-                     int64_t n, hipStream_t s);
+                     int64_t n, hipStream_t s, bool f32 = false);
 
 // LR-deflation prologue shared by the solvers (canonical complex128 vectors):
 // x = x_P = R sign(Lambda) L^H b, r = (I - R L^H) b and, if rt != nullptr, the

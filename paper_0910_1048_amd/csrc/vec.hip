@@ -112,15 +112,17 @@ __global__ void cvt32to64(const float4 *__restrict__ x, double2 *__restrict__ y,
 }
 
 // grid (nbx, m): partials[i * nbx + bx] = sum conj(X_i) y over the block's slice
-__global__ void __launch_bounds__(256) mdot_kernel(const double2 *X, const double2 *y, int64_t n, z64 *partials)
+// (T = double2 or float2; FP64 accumulation either way)
+template <typename T>
+__global__ void __launch_bounds__(256) mdot_kernel(const T *X, const T *y, int64_t n, z64 *partials)
 {
     const int i = blockIdx.y;
-    const double2 *xi = X + (int64_t)i * n;
+    const T *xi = X + (int64_t)i * n;
     double re = 0.0, im = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        double2 a = xi[e], b = y[e];
-        re += a.x * b.x + a.y * b.y;
-        im += a.x * b.y - a.y * b.x;
+        const T a = xi[e], b = y[e];
+        re += (double)a.x * b.x + (double)a.y * b.y;
+        im += (double)a.x * b.y - (double)a.y * b.x;
     }
     __shared__ double lds[8];
     double v[2] = {re, im};
@@ -142,20 +144,25 @@ __global__ void __launch_bounds__(256) mfinalize_kernel(const z64 *partials, int
     if (threadIdx.x == 0) out[i] = {v[0], v[1]};
 }
 
-__global__ void mcombine_kernel(double2 *y, z64 alpha, z64 beta, const double2 *X, int m, const z64 *c,
-                                const z64 *d, int64_t n)
+template <typename T>
+__device__ __forceinline__ T mk2(double a, double b);
+template <> __device__ __forceinline__ double2 mk2<double2>(double a, double b) { return make_double2(a, b); }
+template <> __device__ __forceinline__ float2 mk2<float2>(double a, double b) { return make_float2((float)a, (float)b); }
+
+template <typename T>
+__global__ void mcombine_kernel(T *y, z64 alpha, z64 beta, const T *X, int m, const z64 *c, const z64 *d, int64_t n)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         z64 acc = {0.0, 0.0};
         for (int i = 0; i < m; ++i) {
             z64 ci = c[i];
             if (d) ci = d[i] * ci;
-            double2 xv = X[(int64_t)i * n + e];
-            acc = acc + z64{xv.x, xv.y} * ci;
+            const T xv = X[(int64_t)i * n + e];
+            acc = acc + z64{(double)xv.x, (double)xv.y} * ci;
         }
-        double2 yv = y[e];
-        z64 r = alpha * z64{yv.x, yv.y} + beta * acc;
-        y[e] = make_double2(r.r, r.i);
+        const T yv = y[e];
+        z64 r = alpha * z64{(double)yv.x, (double)yv.y} + beta * acc;
+        y[e] = mk2<T>(r.r, r.i);
     }
 }
 
@@ -255,21 +262,30 @@ void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s)
     SGN_HIP(hipGetLastError());
 }
 
-void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s)
+void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s, bool f32)
 {
     if (m <= 0) return;
     const int nbx = std::max(1, std::min(64, vec_blocks(n)));
     z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)m * nbx * sizeof(z64)));
-    hipLaunchKernelGGL(mdot_kernel, dim3(nbx, m), dim3(256), 0, s, (const double2 *)X, (const double2 *)y, n, part);
+    if (f32)
+        hipLaunchKernelGGL(mdot_kernel<float2>, dim3(nbx, m), dim3(256), 0, s, (const float2 *)X, (const float2 *)y, n,
+                           part);
+    else
+        hipLaunchKernelGGL(mdot_kernel<double2>, dim3(nbx, m), dim3(256), 0, s, (const double2 *)X, (const double2 *)y,
+                           n, part);
     hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, c_dev);
     SGN_HIP(hipGetLastError());
 }
 
 void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
-                     int64_t n, hipStream_t s)
+                     int64_t n, hipStream_t s, bool f32)
 {
-    hipLaunchKernelGGL(mcombine_kernel, dim3(vec_blocks(n)), dim3(256), 0, s, (double2 *)y, alpha, beta,
-                       (const double2 *)X, m, c_dev, d_dev, n);
+    if (f32)
+        hipLaunchKernelGGL(mcombine_kernel<float2>, dim3(vec_blocks(n)), dim3(256), 0, s, (float2 *)y, alpha, beta,
+                           (const float2 *)X, m, c_dev, d_dev, n);
+    else
+        hipLaunchKernelGGL(mcombine_kernel<double2>, dim3(vec_blocks(n)), dim3(256), 0, s, (double2 *)y, alpha, beta,
+                           (const double2 *)X, m, c_dev, d_dev, n);
     SGN_HIP(hipGetLastError());
 }
 

@@ -85,8 +85,69 @@ def test_fom_error_paths():
     lat = lattice(U, dims)
     rf = sgn.sgn_rational_neuberger(8, 0.2, 2.4)
     with pytest.raises(sgn.SgnError) as e:
-        _fom(lat, 0.3, b, rf, kmax=10, prec=sgn.F32)
+        _fom(lat, 0.3, b, rf, kmax=10, prec=7)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _fom(lat, 0.3, b, rf, kmax=0)
     assert e.value.status == 1
     with pytest.raises(sgn.SgnError) as e:
         _fom(lat, 0.3, b, rf, kmax=5, tol=1e-13, max_restarts=1)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("prec", [sgn.F32, sgn.F32_H16])
+@pytest.mark.parametrize("kmax", [20, 40])
+def test_c1_mixed_fom_matches_dense_rational(prec, kmax):
+    """FP64 cycles down to theta32, then an FP32 basis and stencil (FP16 links below
+    theta16) with FP64 sums, Hessenberg and x."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    x, st = _fom(lattice(U, dims), 0.3, b, rf, kmax=kmax, tol=1e-10, prec=prec)
+    e = _rel(x, g["g16_b"])
+    print(f"C1 mixed FOM prec={prec} kmax={kmax}: vs dense g16 {e:.2e}, cycles {st['restarts']} "
+          f"({st['reliable_updates']} with the FP32 basis)", flush=True)
+    assert st["reliable_updates"] >= 1
+    assert e < 1e-8
+
+
+def test_8x4_mixed_fom_against_oracle():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(16, 0.15, 2.6)
+    rf = sgn.sgn_rational_neuberger(16, 0.15, 2.6)
+    x, st = _fom(lattice(U, dims), 0.2, b, rf, kmax=40, tol=1e-10, prec=sgn.F32_H16)
+    xo = krylov.fom_rational(lambda v: W.apply(v, 0.2), b, om, sg, c, 40, tol=1e-11)
+    e = _rel(x, xo)
+    print(f"8^4 mixed FOM kmax=40: vs oracle {e:.2e}, cycles {st['restarts']} ({st['reliable_updates']} FP32)",
+          flush=True)
+    assert st["reliable_updates"] >= 1
+    assert e < 1e-8
+
+
+def test_deflated_mixed_fom():
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    H = W.dense(0.3)
+    lam_r, R = np.linalg.eig(H)
+    Linv = np.linalg.inv(R)
+    idx = np.argsort(np.abs(lam_r.real))[:8]
+    Lr, Rr, lm = Linv[idx].conj(), R[:, idx].T.copy(), lam_r[idx]
+    rest = np.delete(lam_r, idx)
+    alpha, beta = float(np.abs(rest).min()), float(np.abs(lam_r).max())
+    om, sg, c = rational.coefficients(16, alpha, beta)
+    rf = sgn.sgn_rational_neuberger(16, alpha, beta)
+    defl = sgn.Deflation(dev(Lr), dev(Rr), lm)
+    x, st = _fom(lattice(U, dims), 0.3, b, rf, defl=defl, kmax=5, tol=1e-10, prec=sgn.F32)
+    target = krylov.deflation_xP(Lr.T, Rr.T, lm, b) + dense.rational_dense(H, krylov.project_out(Lr.T, Rr.T, b),
+                                                                             om, sg, c)
+    e = _rel(x, target)
+    print(f"deflated mixed FOM: vs dense {e:.2e}, cycles {st['restarts']} ({st['reliable_updates']} FP32)", flush=True)
+    assert st["reliable_updates"] >= 1
+    assert e < 1e-8
