@@ -362,8 +362,9 @@ __global__ void __launch_bounds__(256) ms_seed_xp_update(const MsVec *vl, const 
 }
 
 // out (+)= sum_j coef_j v_j over up to kLiftChunk stored vectors, FP64 or FP32 each.
-// out and FP64 vectors use the [12][S] double2 layout; an FP32 vector is [6][S]
-// float4, i.e. component c of site st is float2 entry 2 ((c/2) S + st) + c%2.
+// out and FP64 vectors use the [12][S] double2 layout, FP32 vectors the [6][S]
+// float4 layout (chunk c holds components 2c and 2c+1); a thread takes one
+// component pair of one site, so every load is a full coalesced row.
 constexpr int kLiftChunk = 256;
 struct LiftSlot {
     const void *p;
@@ -381,23 +382,35 @@ __global__ void __launch_bounds__(256) ms_lift_kernel(const LiftSlot *slots, con
         cf[j] = coef[j];
     }
     __syncthreads();
-    const int64_t n = (int64_t)12 * Sst;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int comp = (int)(e / Sst), st = (int)(e - (int64_t)comp * Sst);
-        const int64_t e32 = 2 * ((int64_t)(comp >> 1) * Sst + st) + (comp & 1);
-        z64 acc = {0.0, 0.0};
+    const int64_t np = (int64_t)6 * Sst;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(p / Sst), st = (int)(p - (int64_t)c2 * Sst);
+        const int64_t e0 = (int64_t)(2 * c2) * Sst + st, e1 = e0 + Sst;
+        z64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
         if (accumulate) {
-            const double2 o = out[e];
-            acc = {o.x, o.y};
+            const double2 o0 = out[e0], o1 = out[e1];
+            a0 = {o0.x, o0.y};
+            a1 = {o1.x, o1.y};
         }
         for (int j = 0; j < K; ++j) {
             const z64 c = cf[j];
             if (c.r == 0.0 && c.i == 0.0) continue;  // uniform
-            const z64 v = sl[j].f32 ? ldz(static_cast<const float2 *>(sl[j].p), e32)
-                                    : ldz(static_cast<const double2 *>(sl[j].p), e);
-            acc = acc + c * v;
+            z64 v0, v1;
+            if (sl[j].f32) {
+                const float4 t = static_cast<const float4 *>(sl[j].p)[p];
+                v0 = {(double)t.x, (double)t.y};
+                v1 = {(double)t.z, (double)t.w};
+            } else {
+                const double2 *v = static_cast<const double2 *>(sl[j].p);
+                const double2 t0 = v[e0], t1 = v[e1];
+                v0 = {t0.x, t0.y};
+                v1 = {t1.x, t1.y};
+            }
+            a0 = a0 + c * v0;
+            a1 = a1 + c * v1;
         }
-        out[e] = make_double2(acc.r, acc.i);
+        out[e0] = make_double2(a0.r, a0.i);
+        out[e1] = make_double2(a1.r, a1.i);
     }
 }
 
@@ -1058,8 +1071,8 @@ void MultishiftBatch::lift(MsProblem &p, const std::vector<z64> &coef, void *out
                            make_double2(0, 0), p.n);
     for (int j0 = 0; j0 < K; j0 += kLiftChunk) {
         const int kk = std::min(kLiftChunk, K - j0);
-        hipLaunchKernelGGL(ms_lift_kernel, dim3(nvb), dim3(256), 0, s_, dsl.as<LiftSlot>() + j0, dcf.as<z64>() + j0,
-                           kk, (int)p.Sst, static_cast<double2 *>(out), (accumulate || j0 > 0) ? 1 : 0);
+        hipLaunchKernelGGL(ms_lift_kernel, dim3(vec_blocks(6 * p.Sst)), dim3(256), 0, s_, dsl.as<LiftSlot>() + j0,
+                           dcf.as<z64>() + j0, kk, (int)p.Sst, static_cast<double2 *>(out), (accumulate || j0 > 0) ? 1 : 0);
     }
     SGN_HIP(hipGetLastError());
     ctx_->prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * p.n * K);
