@@ -84,13 +84,20 @@ const char *sgn_last_error(void);
 /* ------------------------------------------------------------------ lattice */
 /* Pack the gauge field `links` (device, canonical layout, complex128) into the
  * library's internal copies.  `prec_mask` is a bit mask of (1 << sgn_prec)
- * values saying which link precisions to keep (0 = all).  The caller may free
- * `links` once the call returns (the call synchronises `stream`). */
+ * values saying which link precisions to keep (0 = all), optionally or-ed with
+ * SGN_LINKS_FULL.  When every link is in SU(3) to 1e-12 (U U^H = I, det U = 1)
+ * only its first two rows are stored and the third is rebuilt in the stencil as
+ * the complex conjugate of their cross product (unitarity and unit determinant
+ * fix it); otherwise, or with SGN_LINKS_FULL, all nine entries are stored.  The
+ * caller may free `links` once the call returns (the call synchronises `stream`). */
+#define SGN_LINKS_FULL 0x100u
 sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d, const void *links,
                               unsigned prec_mask, void *stream, sgn_lattice *out);
 sgn_status sgn_lattice_destroy(sgn_lattice lat);
 /* sites V and bytes of one spinor in the internal layout for precision p */
 int64_t sgn_lattice_volume(sgn_lattice lat);
+/* complex entries stored per link: 6 (two rows, SU(3) links) or 9 */
+int sgn_lattice_link_elements(sgn_lattice lat);
 size_t sgn_spinor_bytes(sgn_lattice lat, sgn_prec p);
 
 /* Canonical <-> internal layout.  `canon` is complex128 for SGN_PREC_F64 and

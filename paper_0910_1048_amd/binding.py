@@ -17,6 +17,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "sgn.h")
 
 F64, F32, F32_H16 = 0, 1, 2
 NO_GAMMA5, INTERNAL_LAYOUT = 1, 2
+LINKS_FULL = 0x100
 
 STATUS = {0: "SGN_OK", 1: "SGN_ERR_INVALID", 2: "SGN_ERR_HIP", 3: "SGN_ERR_NOMEM",
           4: "SGN_ERR_BREAKDOWN", 5: "SGN_ERR_NOT_CONVERGED", 6: "SGN_ERR_IMAG_AXIS",
@@ -56,6 +57,7 @@ lib.sgn_last_error.restype = C.c_char_p
 lib.sgn_lattice_create.argtypes = [_vp, C.POINTER(LatticeDesc), _vp, C.c_uint, _vp, C.POINTER(_vp)]
 lib.sgn_lattice_destroy.argtypes = [_vp]
 lib.sgn_lattice_volume.argtypes = [_vp]
+lib.sgn_lattice_link_elements.argtypes = [_vp]
 lib.sgn_lattice_volume.restype = _i64
 lib.sgn_spinor_bytes.argtypes = [_vp, C.c_int]
 lib.sgn_spinor_bytes.restype = C.c_size_t
@@ -130,6 +132,7 @@ class Lattice:
         self.dims = tuple(int(x) for x in dims)
         self.kappa = float(kappa)
         self.V = int(lib.sgn_lattice_volume(h))
+        self.link_elements = int(lib.sgn_lattice_link_elements(h))
 
     def spinor_bytes(self, prec):
         return int(lib.sgn_spinor_bytes(self.h, int(prec)))

@@ -76,6 +76,7 @@ struct StencilParams {
     int nblk_sites;  // blocks covering the V sites; later blocks zero the padding sites [V, S)
     int blk_sites;   // staged kernel: sites per block (whole x-rows)
     int nblk_total;  // blocks of this application (sites + padding); batched launches skip the rest
+    int link_ne;     // complex entries stored per link (6 or 9)
     RhsParams rhs[kMaxRhs];
 };
 
@@ -178,7 +179,7 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
         const bool wrap = coord == L - 1;
         const int n = wrap ? s - (L - 1) * st : s + st;
         const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
-        load_link<R>(U, P.S, NU, s, u);
+        load_link<R>(U, P.S, P.link_ne, NU, s, u);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             cpx<R> p[12], h[6], chi[6];
@@ -201,7 +202,7 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
         const bool wrap = coord == 0;
         const int n = wrap ? s + (L - 1) * st : s - st;
         const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
-        load_link<R>(U, P.S, NU, n, u);
+        load_link<R>(U, P.S, P.link_ne, NU, n, u);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             cpx<R> p[12], h[6], chi[6];
@@ -405,7 +406,7 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const int n = wrap ? s - (L - 1) * st : s + st;
         const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
-        load_link<R>(U, P.S, NU, s, u);
+        load_link<R>(U, P.S, P.link_ne, NU, s, u);
         fetch_neighbour<R>(P, lds, base, n, p);
         project<NU, true>(p, h);
         link_mul<false>(u, h, chi);
@@ -418,7 +419,7 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const int n = wrap ? s + (L - 1) * st : s - st;
         const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
-        load_link<R>(U, P.S, NU, n, u);
+        load_link<R>(U, P.S, P.link_ne, NU, n, u);
         fetch_neighbour<R>(P, lds, base, n, p);
         project<NU, false>(p, h);
         link_mul<true>(u, h, chi);
@@ -714,7 +715,8 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
     // algorithmic bytes: every input and output spinor once, the 4 links of each
     // site once (shared by the right-hand sides), plus the epilogue operands;
     // 1368 flop per site and right-hand side for the stencil itself
-    const double lb = (p == SGN_PREC_F64) ? 144.0 : (p == SGN_PREC_F32 ? 72.0 : 36.0);
+    P.link_ne = lat.link_ne;
+    const double lb = lat.link_ne * ((p == SGN_PREC_F64) ? 16.0 : (p == SGN_PREC_F32 ? 8.0 : 4.0));
     ps.bytes = (2 * sb * nr + 4 * lb + extra_bytes) * lat.V;
     ps.flops = (1368.0 * nr + extra_flops) * lat.V;
     ps.pl = nr == 1 ? staged_plan(lat, p) : StagedPlan{};

@@ -69,39 +69,47 @@ __device__ __forceinline__ void store_spinor(float4 *__restrict__ p, int S, int 
         st_off(p + (size_t)c * S, off, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i));
 }
 
+// Third row of an SU(3) matrix from its first two: u2 = conj(u0 x u1).
 template <typename R>
-__device__ __forceinline__ void load_link(const double2 *__restrict__ U, int S, int nu, int s, cpx<R> u[9])
+__device__ __forceinline__ void su3_third_row(cpx<R> u[9])
 {
-    const double2 *b = U + (size_t)nu * 9 * S;
-    const uint32_t off = (uint32_t)s * 16u;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        double2 t = ld_off(b + (size_t)e * S, off);
-        u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
-    }
+    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
 }
 
 template <typename R>
-__device__ __forceinline__ void load_link(const float2 *__restrict__ U, int S, int nu, int s, cpx<R> u[9])
+__device__ __forceinline__ void link_entry(const double2 *b, uint32_t off, cpx<R> &u)
 {
-    const float2 *b = U + (size_t)nu * 9 * S;
-    const uint32_t off = (uint32_t)s * 8u;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        float2 t = ld_off(b + (size_t)e * S, off);
-        u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
-    }
+    double2 t = ld_off(b, off * 16u);
+    u = {static_cast<R>(t.x), static_cast<R>(t.y)};
+}
+template <typename R>
+__device__ __forceinline__ void link_entry(const float2 *b, uint32_t off, cpx<R> &u)
+{
+    float2 t = ld_off(b, off * 8u);
+    u = {static_cast<R>(t.x), static_cast<R>(t.y)};
+}
+template <typename R>
+__device__ __forceinline__ void link_entry(const __half2 *b, uint32_t off, cpx<R> &u)
+{
+    float2 t = __half22float2(ld_off(b, off * 4u));
+    u = {static_cast<R>(t.x), static_cast<R>(t.y)};
 }
 
-template <typename R>
-__device__ __forceinline__ void load_link(const __half2 *__restrict__ U, int S, int nu, int s, cpx<R> u[9])
+// U_nu(x) at site s from the [4][ne][S] link array (ne = 6: two rows stored,
+// the third rebuilt; ne = 9: all entries)
+template <typename R, typename LT>
+__device__ __forceinline__ void load_link(const LT *__restrict__ U, int S, int ne, int nu, int s, cpx<R> u[9])
 {
-    const __half2 *b = U + (size_t)nu * 9 * S;
-    const uint32_t off = (uint32_t)s * 4u;
+    const LT *b = U + (size_t)nu * ne * S;
+    if (ne == 6) {
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        float2 t = __half22float2(ld_off(b + (size_t)e * S, off));
-        u[e] = {static_cast<R>(t.x), static_cast<R>(t.y)};
+        for (int e = 0; e < 6; ++e) link_entry<R>(b + (size_t)e * S, (uint32_t)s, u[e]);
+        su3_third_row(u);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) link_entry<R>(b + (size_t)e * S, (uint32_t)s, u[e]);
     }
 }
 

@@ -80,13 +80,44 @@ template <> __device__ inline __half2 to_link<__half2>(double2 v)
 }
 
 template <typename LT>
-__global__ void pack_links_kernel(const double2 *__restrict__ canon, LT *__restrict__ out, int V, int S)
+__global__ void pack_links_kernel(const double2 *__restrict__ canon, LT *__restrict__ out, int V, int S, int ne)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 4 * V) return;
     const int s = t / 4, nu = t % 4;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) out[((size_t)nu * 9 + e) * S + s] = to_link<LT>(canon[(size_t)t * 9 + e]);
+    for (int e = 0; e < ne; ++e) out[((size_t)nu * ne + e) * S + s] = to_link<LT>(canon[(size_t)t * 9 + e]);
+}
+
+// Per block: the largest deviation of a link from SU(3), max(|U U^H - I|_ij, |det U - 1|)
+__global__ void __launch_bounds__(256) su3_check_kernel(const double2 *__restrict__ canon, int nlinks, double *blockmax)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double dev = 0.0;
+    if (t < nlinks) {
+        z64 u[9];
+        for (int e = 0; e < 9; ++e) {
+            const double2 v = canon[(size_t)t * 9 + e];
+            u[e] = {v.x, v.y};
+        }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                z64 acc = {i == j ? -1.0 : 0.0, 0.0};
+                for (int k = 0; k < 3; ++k) acc = acc + u[3 * i + k] * conj(u[3 * j + k]);
+                dev = fmax(dev, sqrt(norm2(acc)));
+            }
+        const z64 det = u[0] * (u[4] * u[8] - u[5] * u[7]) - u[1] * (u[3] * u[8] - u[5] * u[6]) +
+                        u[2] * (u[3] * u[7] - u[4] * u[6]);
+        dev = fmax(dev, sqrt(norm2(det - z64{1.0, 0.0})));
+        if (!(dev == dev)) dev = INFINITY;  // NaN entries: not SU(3)
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = dev;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
 }
 
 // internal layouts: padding sites (V <= s < S) are written as zeros
@@ -243,27 +274,48 @@ extern "C" sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d
         lat->V = V;
         lat->S = component_stride(V);
         const int64_t S = lat->S;
-        const unsigned mask = prec_mask ? prec_mask : 7u;
+        const unsigned pmask = prec_mask & 7u;
+        const unsigned mask = pmask ? pmask : 7u;
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int nthr = (int)(4 * V);
         dim3 g((nthr + 255) / 256), b(256);
+        // two-row storage when every link is SU(3) to 1e-12
+        lat->link_ne = 9;
+        if (!(prec_mask & SGN_LINKS_FULL)) {
+            std::vector<double> bm(g.x);
+            double *dbm = nullptr;
+            if (hipMalloc(&dbm, sizeof(double) * g.x) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "su3 check"};
+            hipLaunchKernelGGL(su3_check_kernel, g, b, 0, s, (const double2 *)links, nthr, dbm);
+            const hipError_t e1 = hipGetLastError();
+            const hipError_t e2 = hipMemcpyAsync(bm.data(), dbm, sizeof(double) * g.x, hipMemcpyDeviceToHost, s);
+            const hipError_t e3 = hipStreamSynchronize(s);
+            (void)hipFree(dbm);
+            SGN_HIP(e1);
+            SGN_HIP(e2);
+            SGN_HIP(e3);
+            double dev = 0.0;
+            for (double v : bm) dev = std::max(dev, v);
+            if (dev <= 1e-12) lat->link_ne = 6;
+        }
+        const size_t nel = (size_t)S * 4 * lat->link_ne;
+        const int ne = lat->link_ne;
         if (mask & (1u << SGN_PREC_F64)) {
-            if (hipMalloc(&lat->links64, (size_t)S * 36 * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links64"};
-            SGN_HIP(hipMemsetAsync(lat->links64, 0, (size_t)S * 36 * 16, s));
+            if (hipMalloc(&lat->links64, nel * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links64"};
+            SGN_HIP(hipMemsetAsync(lat->links64, 0, nel * 16, s));
             hipLaunchKernelGGL(pack_links_kernel<double2>, g, b, 0, s, (const double2 *)links,
-                               (double2 *)lat->links64, (int)V, (int)S);
+                               (double2 *)lat->links64, (int)V, (int)S, ne);
         }
         if (mask & (1u << SGN_PREC_F32)) {
-            if (hipMalloc(&lat->links32, (size_t)S * 36 * 8) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links32"};
-            SGN_HIP(hipMemsetAsync(lat->links32, 0, (size_t)S * 36 * 8, s));
+            if (hipMalloc(&lat->links32, nel * 8) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links32"};
+            SGN_HIP(hipMemsetAsync(lat->links32, 0, nel * 8, s));
             hipLaunchKernelGGL(pack_links_kernel<float2>, g, b, 0, s, (const double2 *)links,
-                               (float2 *)lat->links32, (int)V, (int)S);
+                               (float2 *)lat->links32, (int)V, (int)S, ne);
         }
         if (mask & (1u << SGN_PREC_F32_H16)) {
-            if (hipMalloc(&lat->links16, (size_t)S * 36 * 4) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links16"};
-            SGN_HIP(hipMemsetAsync(lat->links16, 0, (size_t)S * 36 * 4, s));
+            if (hipMalloc(&lat->links16, nel * 4) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "links16"};
+            SGN_HIP(hipMemsetAsync(lat->links16, 0, nel * 4, s));
             hipLaunchKernelGGL(pack_links_kernel<__half2>, g, b, 0, s, (const double2 *)links,
-                               (__half2 *)lat->links16, (int)V, (int)S);
+                               (__half2 *)lat->links16, (int)V, (int)S, ne);
         }
         SGN_HIP(hipGetLastError());
         SGN_HIP(hipStreamSynchronize(s));
@@ -286,6 +338,8 @@ extern "C" sgn_status sgn_lattice_destroy(sgn_lattice l)
 }
 
 extern "C" int64_t sgn_lattice_volume(sgn_lattice l) { return l ? as_lattice(l)->V : 0; }
+
+extern "C" int sgn_lattice_link_elements(sgn_lattice l) { return l ? as_lattice(l)->link_ne : 0; }
 
 extern "C" size_t sgn_spinor_bytes(sgn_lattice l, sgn_prec p) { return l ? spinor_bytes(as_lattice(l)->S, p) : 0; }
 

@@ -137,9 +137,10 @@ struct Lattice {
     // 12 spinor and 36 link component arrays of one site do not fall into the
     // same L2 set)
     int64_t S = 0;
-    void *links64 = nullptr;  // [4][9][S] double2
-    void *links32 = nullptr;  // [4][9][V] float2
-    void *links16 = nullptr;  // [4][9][V] __half2
+    int link_ne = 9;          // complex entries stored per link: 6 (rows 0, 1 of an SU(3) matrix) or 9
+    void *links64 = nullptr;  // [4][link_ne][S] double2
+    void *links32 = nullptr;  // [4][link_ne][S] float2
+    void *links16 = nullptr;  // [4][link_ne][S] __half2
     // canonical <-> internal staging for wilson_apply in canonical layout
     void *stage_in = nullptr, *stage_out = nullptr;
     size_t stage_bytes = 0;

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_0910_1048_amd as sgn  # noqa: E402
+import gpu_util  # noqa: E402
 from gpu_util import dev, host, lattice  # noqa: E402
 
 TOL = {sgn.F64: 1e-13, sgn.F32: 1e-6, sgn.F32_H16: 5e-3}
@@ -152,3 +153,35 @@ def test_multi_rhs_stencil(prec, nrhs, dims):
         out = torch.empty(b.size, dtype=torch.complex128 if prec == sgn.F64 else torch.complex64, device="cuda")
         sgn.sgn_spinor_unpack(lat, t, out, prec)
         assert _rel(host(out).astype(np.complex128).reshape(b.shape), ref.apply(b, mu)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+def test_two_row_links_equal_full_links(prec):
+    """SU(3) links are stored as two rows (third rebuilt in the stencil); the same
+    operator with all nine entries stored, and the oracle, agree."""
+    dims = (4, 6, 4, 8)
+    U = synth.gauge_field(dims, 0.5, 3)
+    b = synth.gaussian_source(dims, 4)
+    ref = WilsonRef(U, dims, 0.2)
+    lat2 = lattice(U, dims)
+    lat3 = sgn.Lattice(gpu_util.ctx(), dev(U), dims, 0.2, prec_mask=sgn.LINKS_FULL)
+    assert lat2.link_elements == 6 and lat3.link_elements == 9
+    y2, y3 = _run(lat2, 0.3, b, prec), _run(lat3, 0.3, b, prec)
+    want = ref.apply(b, 0.3)
+    print(f"prec={prec}: two-row {_rel(y2, want):.2e}, full {_rel(y3, want):.2e}", flush=True)
+    assert _rel(y2, want) < TOL[prec] and _rel(y3, want) < TOL[prec]
+    assert _rel(y2, y3) < (1e-14 if prec == sgn.F64 else 2 * TOL[prec])
+
+
+def test_non_unitary_links_keep_all_entries():
+    """Links that are not SU(3) (here: random complex matrices) keep nine entries and
+    still give the oracle's operator."""
+    dims = (4, 4, 4, 6)
+    rng = np.random.default_rng(11)
+    U = (rng.standard_normal(dims + (4, 3, 3)) + 1j * rng.standard_normal(dims + (4, 3, 3))) * 0.4
+    b = synth.gaussian_source(dims, 2)
+    lat = lattice(U, dims)
+    assert lat.link_elements == 9
+    ref = WilsonRef(U, dims, 0.2)
+    for prec in (sgn.F64, sgn.F32):
+        assert _rel(_run(lat, 0.2, b, prec), ref.apply(b, 0.2)) < TOL[prec]
