@@ -164,6 +164,9 @@ typedef struct {
     double tol;         /* > 0: stop early once the lift coefficients y = sign(T_j) e_1 change by
                            less than tol (relative) between checks */
     int check_every;    /* steps between such checks (used when tol > 0) */
+    int two_pass;       /* nonzero: keep only three basis vectors; a second, identical pass of the
+                           recurrence (the kernels are deterministic) rebuilds v_j and accumulates
+                           x, at twice the stencil work (memory O(n) instead of O(k n)) */
 } sgn_lanczos_opts;
 
 /* Direct two-sided Lanczos-LR(m, k) (section "Direct application of the

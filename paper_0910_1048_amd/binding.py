@@ -177,7 +177,8 @@ class _Deflation(C.Structure):
 
 
 class LanczosOpts(C.Structure):
-    _fields_ = [("k", C.c_int), ("prec", C.c_int), ("tol", C.c_double), ("check_every", C.c_int)]
+    _fields_ = [("k", C.c_int), ("prec", C.c_int), ("tol", C.c_double), ("check_every", C.c_int),
+                ("two_pass", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -214,9 +215,10 @@ lib.sign_lanczos_2sided.argtypes = [_vp, C.c_double, _vp, _vp, _vp, C.POINTER(La
                                     C.POINTER(Stats), _vp]
 
 
-def sign_lanczos_2sided(lat, mu, b, x, defl=None, k=200, prec=F64, tol=0.0, check_every=0, stream=None):
+def sign_lanczos_2sided(lat, mu, b, x, defl=None, k=200, prec=F64, tol=0.0, check_every=0, two_pass=False,
+                        stream=None):
     """x = sign(H_W(mu)) b by the direct two-sided Lanczos-LR method; returns the stats dict."""
-    o = LanczosOpts(int(k), int(prec), float(tol), int(check_every))
+    o = LanczosOpts(int(k), int(prec), float(tol), int(check_every), int(bool(two_pass)))
     st = Stats()
     check(lib.sign_lanczos_2sided(lat.h, float(mu), _ptr(b), _ptr(x), _defl_ptr(defl), C.byref(o), C.byref(st),
                                   _stream(stream)), "sign_lanczos_2sided")

@@ -222,6 +222,18 @@ void deflation_prologue(Context &ctx, const sgn_deflation *defl, int64_t n, cons
     SGN_HIP(hipStreamSynchronize(s));  // c, d are freed on return
 }
 
+namespace {
+// x += c v  (second pass of the two-pass form)
+__global__ void lz_accum_kernel(double2 *x, z64 c, const double2 *v, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 xv = x[e], vv = v[e];
+        const z64 r = z64{xv.x, xv.y} + c * z64{vv.x, vv.y};
+        x[e] = make_double2(r.r, r.i);
+    }
+}
+}  // namespace
+
 }  // namespace sgn
 
 using namespace sgn;
@@ -258,8 +270,10 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         if (!(std::sqrt(norm2(g)) > 1e-14 * beta * norm_sync(ctx, rt.p, n, false, s)))
             throw Failure{SGN_ERR_BREAKDOWN, "shadow vector orthogonal to the residual"};
 
-        // workspace: basis V (k vectors), 3 W vectors, u, z (FP64 internal) + FP32 copies
-        DevBuf Vb((size_t)k * i64), Wb(3 * i64), u(i64), z(i64);
+        // workspace: basis V (k vectors, or a ring of 3 in the two-pass form), 3 W vectors,
+        // u, z (FP64 internal) + FP32 copies
+        const bool two_pass = opts->two_pass != 0;
+        DevBuf Vb((size_t)(two_pass ? 3 : k) * i64), Wb(3 * i64), u(i64), z(i64);
         DevBuf v32(f32 ? b32 : 0), w32(f32 ? b32 : 0), u32(f32 ? b32 : 0), z32(f32 ? b32 : 0);
         DevBuf scal(sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k);
         LzScalars S;
@@ -269,22 +283,26 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         S.sv = S.hsup + k;
         S.tw = S.sv + (k + 1);
         S.flag = reinterpret_cast<int *>(S.tw + (k + 1));
-        SGN_HIP(hipMemsetAsync(scal.p, 0, sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k, s));
         const double s1 = 1.0 / beta;
         const z64 v1rt = {s1 * g.r, s1 * g.i};  // v_1^H r~
         const double m2 = norm2(v1rt);
         const z64 t1 = {v1rt.r / m2, -v1rt.i / m2};  // 1 / (v_1^H r~)
         const z64 sv0 = {s1, 0.0};
-        SGN_HIP(hipMemcpyAsync(S.sv, &sv0, sizeof(z64), hipMemcpyHostToDevice, s));
-        SGN_HIP(hipMemcpyAsync(S.tw, &t1, sizeof(z64), hipMemcpyHostToDevice, s));
-        auto Vj = [&](int j) { return static_cast<char *>(Vb.p) + (size_t)j * i64; };
+        auto Vj = [&](int j) { return static_cast<char *>(Vb.p) + (size_t)(two_pass ? j % 3 : j) * i64; };
         auto Wj = [&](int j) { return static_cast<char *>(Wb.p) + (size_t)(j % 3) * i64; };
-        pack_spinor(lat, r.p, Vj(0), SGN_PREC_F64, s);
-        pack_spinor(lat, rt.p, Wj(0), SGN_PREC_F64, s);
-        if (f32) {
-            convert_64_to_32(Vj(0), v32.p, Sst, s);
-            convert_64_to_32(Wj(0), w32.p, Sst, s);
-        }
+        // start of the recurrence (run once, or twice in the two-pass form, from identical state)
+        auto start = [&]() {
+            SGN_HIP(hipMemsetAsync(scal.p, 0, sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k, s));
+            SGN_HIP(hipMemcpyAsync(S.sv, &sv0, sizeof(z64), hipMemcpyHostToDevice, s));
+            SGN_HIP(hipMemcpyAsync(S.tw, &t1, sizeof(z64), hipMemcpyHostToDevice, s));
+            pack_spinor(lat, r.p, Vj(0), SGN_PREC_F64, s);
+            pack_spinor(lat, rt.p, Wj(0), SGN_PREC_F64, s);
+            if (f32) {
+                convert_64_to_32(Vj(0), v32.p, Sst, s);
+                convert_64_to_32(Wj(0), w32.p, Sst, s);
+            }
+        };
+        start();
 
         const int nst = dslash_blocks(lat);
         const int nvb = vec_blocks(6 * Sst);
@@ -324,16 +342,15 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
             for (int j = 0; j < kk; ++j) y[j] = {yy[j].real(), yy[j].imag()};
         };
 
-        const auto t_kry = std::chrono::steady_clock::now();
-        int kused = k;
-        for (int j = 0; j < k; ++j) {
+        // one step j of the recurrence: alpha_j, and (unless last) v_{j+1}, w_{j+1}
+        auto step = [&](int j, int last) {
             // u = A vh_j with partials of wh_j^H u
             Epilogue ep;
             ep.w = f32 ? w32.p : Wj(j);
             ep.partials = part;
             const int nb1 = dslash_launch(lat, sp, opA, f32 ? v32.p : Vj(j), f32 ? u32.p : u.p, ep, s);
             hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S, j);
-            if (j + 1 == k) break;
+            if (j + 1 == last) return;
             dslash_launch(lat, sp, opAh, f32 ? w32.p : Wj(j), f32 ? z32.p : z.p, Epilogue{}, s);
             void *vn = Vj(j + 1);
             const double2 *vjm = j > 0 ? reinterpret_cast<const double2 *>(Vj(j - 1)) : nullptr;
@@ -348,6 +365,13 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
                                    (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)Sst, part);
             hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(256), 0, s, part, nvb, S, j, 1e-14);
             SGN_HIP(hipGetLastError());
+        };
+
+        const auto t_kry = std::chrono::steady_clock::now();
+        int kused = k;
+        for (int j = 0; j < k; ++j) {
+            step(j, k);
+            if (j + 1 == k) break;
             if (opts->tol > 0 && opts->check_every > 0 && (j + 1) % opts->check_every == 0 && j + 1 < k) {
                 const int kk = j + 1;
                 download(kk);
@@ -377,15 +401,30 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         std::vector<z64> c(kused);
         for (int j = 0; j < kused; ++j) c[j] = (beta * hsv[j].r) * y[j];
         DevBuf cd(sizeof(z64) * kused);
-        SGN_HIP(hipMemcpyAsync(cd.p, c.data(), sizeof(z64) * kused, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(lift_kernel, dim3(vec_blocks(ni)), dim3(256), 0, s, (const double2 *)Vb.p, ni, kused,
-                           cd.as<z64>(), (double2 *)u.p);
+        if (!two_pass) {
+            SGN_HIP(hipMemcpyAsync(cd.p, c.data(), sizeof(z64) * kused, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(lift_kernel, dim3(vec_blocks(ni)), dim3(256), 0, s, (const double2 *)Vb.p, ni, kused,
+                               cd.as<z64>(), (double2 *)u.p);
+        } else {
+            // second pass: the same launches from the same state give the same vh_j bit for bit;
+            // each is added to the solution while it is still in the ring.  x accumulates in xacc
+            // (the first pass is done with the canonical shadow rt, reused here)
+            DevBuf xacc(i64);
+            SGN_HIP(hipMemsetAsync(xacc.p, 0, i64, s));
+            start();
+            for (int j = 0; j < kused; ++j) {
+                hipLaunchKernelGGL(lz_accum_kernel, dim3(vec_blocks(ni)), dim3(256), 0, s, (double2 *)xacc.p, c[j],
+                                   (const double2 *)Vj(j), ni);
+                if (j + 1 < kused) step(j, kused);
+            }
+            SGN_HIP(hipMemcpyAsync(u.p, xacc.p, i64, hipMemcpyDeviceToDevice, s));
+        }
         unpack_spinor(lat, u.p, r.p, SGN_PREC_F64, s);
         axpby64({1.0, 0.0}, r.p, {1.0, 0.0}, x, n, s);
         SGN_HIP(hipStreamSynchronize(s));
         if (stats) {
             stats->iterations = kused;
-            stats->matvecs = 2 * kused - 1;
+            stats->matvecs = (two_pass ? 2 : 1) * (2 * kused - 1);
             stats->min_abs_re = minre;
             stats->krylov_ms = kry_ms;
             stats->small_ms = small_ms;

@@ -149,3 +149,22 @@ def test_error_paths():
     with pytest.raises(sgn.SgnError) as e:
         _gpu_lanczos(lat, 0.3, b, 0)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32])
+def test_two_pass_equals_one_pass(prec):
+    """The two-pass form keeps three basis vectors and replays the recurrence (the
+    kernels are deterministic): same result as the stored basis, also with early stop."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    lat = lattice(U, dims)
+    for kw in ({"k": 200}, {"k": 400, "tol": 1e-10, "check_every": 20}):
+        x1, s1 = _gpu_lanczos(lat, 0.3, b, prec=prec, **kw)
+        x2, s2 = _gpu_lanczos(lat, 0.3, b, prec=prec, two_pass=True, **kw)
+        e = _rel(x2, x1)
+        print(f"prec={prec} {kw}: two-pass vs stored basis {e:.2e}, k used {s1['iterations']} / "
+              f"{s2['iterations']}, matvecs {s1['matvecs']} / {s2['matvecs']}", flush=True)
+        assert s1["iterations"] == s2["iterations"]
+        assert s2["matvecs"] == 2 * s1["matvecs"]
+        assert e < 1e-14
