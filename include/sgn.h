@@ -303,13 +303,17 @@ typedef enum {
 } sgn_kernel_class;
 
 typedef struct {
-    long long launches;
-    double total_ms;
+    long long launches;   /* launches recorded (every N-th one, see sgn_profile_enable) */
+    double total_ms;      /* time, bytes and flops of the recorded launches */
     double bytes;
     double flops;
+    long long calls;      /* all launches of the class while profiling was on */
 } sgn_kernel_profile;
 
-/* enable != 0 starts (and resets) profiling on this context; 0 stops it. */
+/* enable != 0 starts (and resets) profiling on this context; 0 stops it.
+ * enable = N > 1 records only every N-th launch of each kernel class (the
+ * per-launch averages stay representative while the event pairs, which
+ * insert markers into the stream, cost 1/N as much). */
 sgn_status sgn_profile_enable(sgn_handle h, int enable);
 /* Waits for the recorded launches and fills out[SGN_K_COUNT]. */
 sgn_status sgn_profile_read(sgn_handle h, sgn_kernel_profile *out);

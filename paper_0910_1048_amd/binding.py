@@ -297,15 +297,17 @@ KERNEL_NAMES = ["stencil_f64", "stencil_f32", "stencil_h16", "shift_update", "se
 
 
 class KernelProfile(C.Structure):
-    _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
+    _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double),
+                ("calls", C.c_longlong)]
 
 
 lib.sgn_profile_enable.argtypes = [_vp, C.c_int]
 lib.sgn_profile_read.argtypes = [_vp, C.POINTER(KernelProfile)]
 
 
-def sgn_profile_enable(ctx, enable=True):
-    check(lib.sgn_profile_enable(ctx.h, int(bool(enable))), "sgn_profile_enable")
+def sgn_profile_enable(ctx, enable=True, every=1):
+    """Start (and reset) or stop launch profiling; every > 1 records every N-th launch per class."""
+    check(lib.sgn_profile_enable(ctx.h, (max(int(every), 1) if enable else 0)), "sgn_profile_enable")
 
 
 def sgn_profile_read(ctx):
@@ -313,7 +315,7 @@ def sgn_profile_read(ctx):
     arr = (KernelProfile * K_COUNT)()
     check(lib.sgn_profile_read(ctx.h, arr), "sgn_profile_read")
     return {KERNEL_NAMES[i]: {"launches": arr[i].launches, "total_ms": arr[i].total_ms, "bytes": arr[i].bytes,
-                              "flops": arr[i].flops} for i in range(K_COUNT)}
+                              "flops": arr[i].flops, "calls": arr[i].calls} for i in range(K_COUNT)}
 
 
 lib.wilson_apply_multi.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(_vp), C.POINTER(_vp), C.c_int,

@@ -769,7 +769,7 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
                         void *const *out, const Epilogue *ep, hipStream_t s)
 {
     const PreparedStencil ps = prepare_stencil(lat, p, nr, op, in, out, ep);
-    const int prof = lat.ctx->prof_start(s);
+    const int prof = lat.ctx->prof_start(s, kclass(p));
     switch (p) {
     case SGN_PREC_F64:
         if (ps.pl.ok)
@@ -846,7 +846,7 @@ void StencilBatch::launch(hipStream_t s) const
         return;
     }
     Context *ctx = jobs_[0].lat->ctx;
-    const int prof = ctx->prof_start(s);
+    const int prof = ctx->prof_start(s, kclass(prec_));
     const StencilParams *d = static_cast<const StencilParams *>(dev_);
     const int cnt = (int)jobs_.size();
     switch (prec_) {

@@ -366,9 +366,10 @@ extern "C" sgn_status sgn_spinor_unpack(sgn_lattice l, const void *internal, voi
 // ----------------------------------------------------------------------------- profiling
 namespace sgn {
 
-int Context::prof_start(hipStream_t s)
+int Context::prof_start(hipStream_t s, int cls)
 {
     if (!prof) return -1;
+    if (prof_calls[cls]++ % prof_every != 0) return -1;
     ProfRec r{};
     for (hipEvent_t *e : {&r.start, &r.stop}) {
         if (!event_pool.empty()) {
@@ -438,6 +439,8 @@ extern "C" sgn_status sgn_profile_enable(sgn_handle h, int enable)
             SGN_HIP(hipMemcpy(c->byte_counter, &z, sizeof(z), hipMemcpyHostToDevice));
         }
         c->prof = enable != 0;
+        c->prof_every = enable > 1 ? enable : 1;
+        for (int k = 0; k < SGN_K_COUNT; ++k) c->prof_calls[k] = 0;
     });
 }
 
@@ -453,6 +456,7 @@ extern "C" sgn_status sgn_profile_read(sgn_handle h, sgn_kernel_profile *out)
             out[k].total_ms = c->acc_ms[k];
             out[k].bytes = c->acc_bytes[k];
             out[k].flops = c->acc_flops[k];
+            out[k].calls = c->prof_calls[k];
         }
     });
 }

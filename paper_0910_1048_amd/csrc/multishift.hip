@@ -697,8 +697,8 @@ MultishiftBatch::MultishiftBatch(const sgn_problem *pb, int nprob, const sgn_rat
         SGN_REQUIRE(p.lat->ctx == ctx_, "multishift_solve: all lattices must share one context");
     }
     SGN_HIP(hipSetDevice(ctx_->device));
-    // iterations between host polls: about 200k sites' worth of stencil work per poll
-    poll_ = o.poll > 0 ? o.poll : (int)std::min<int64_t>(16, std::max<int64_t>(1, (200000 + vtot - 1) / vtot));
+    // iterations between host polls: about 200k sites' worth of stencil work per poll, at least 4
+    poll_ = o.poll > 0 ? o.poll : (int)std::min<int64_t>(16, std::max<int64_t>(4, (200000 + vtot - 1) / vtot));
     // stored-basis budget: slots per problem
     int cap = 0;
     if (o.basis_slots > 0) {
@@ -955,7 +955,6 @@ void MultishiftBatch::iterate(int count)
 void MultishiftBatch::launch_iterations(int count, hipStream_t strm)
 {
     const int np = (int)pr_.size();
-    unsigned long long *bc = ctx_->prof ? ctx_->byte_counter : nullptr;
     for (int it = 0; it < count; ++it) {
         for (int ph = 0; ph < 3; ++ph) {
             const int nb = (int)lists_[ph][0].size(), ne = (int)lists_[ph][1].size();
@@ -969,7 +968,7 @@ void MultishiftBatch::launch_iterations(int count, hipStream_t strm)
             for (int form = 0; form < 2; ++form)
                 for (int k : lists_[ph][form]) elems += (double)pr_[k].n;
             const double eb = lo ? 8.0 : 16.0;
-            int pr = ctx_->prof_start(strm);
+            int pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE);
             for (int form = 0; form < 2; ++form) {
                 const int cnt = form ? ne : nb;
                 if (!cnt) continue;
@@ -982,7 +981,8 @@ void MultishiftBatch::launch_iterations(int count, hipStream_t strm)
             ctx_->prof_stop(pr, strm, SGN_K_SEED_UPDATE, 6.0 * eb * elems, 40.0 * elems);
             if (nb) hipLaunchKernelGGL(ms_beta_kernel, dim3(nb), dim3(256), 0, strm, dvec_, lb, kVecGrid);
             if (ne) hipLaunchKernelGGL(ms_beta_kernel, dim3(ne), dim3(256), 0, strm, dvec_, le, kVecGrid);
-            pr = ctx_->prof_start(strm);
+            pr = ctx_->prof_start(strm, SGN_K_SHIFT_UPDATE);
+            unsigned long long *bc = pr >= 0 ? ctx_->byte_counter : nullptr;  // bytes of sampled launches only
             if (nb) {
                 if (lo)
                     hipLaunchKernelGGL((ms_seed_xp_update<float, float2>), dim3(kVecGrid, nb), dim3(256), 0, strm,
@@ -1064,7 +1064,7 @@ void MultishiftBatch::lift(MsProblem &p, const std::vector<z64> &coef, void *out
         SGN_HIP(hipMemcpy(dsl.p, hs.data(), sizeof(LiftSlot) * K, hipMemcpyHostToDevice));
         SGN_HIP(hipMemcpy(dcf.p, coef.data(), sizeof(z64) * K, hipMemcpyHostToDevice));
     }
-    const int pr = ctx_->prof_start(s_);
+    const int pr = ctx_->prof_start(s_, SGN_K_LIFT);
     const int nvb = vec_blocks(p.n);
     if (K == 0 && !accumulate)
         hipLaunchKernelGGL(fill_kernel<double2>, dim3(nvb), dim3(256), 0, s_, static_cast<double2 *>(out),

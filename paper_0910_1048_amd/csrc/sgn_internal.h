@@ -105,8 +105,10 @@ struct Context {
     double acc_bytes[SGN_K_COUNT] = {};
     double acc_flops[SGN_K_COUNT] = {};
     long long acc_launches[SGN_K_COUNT] = {};
-    // returns -1 when profiling is off
-    int prof_start(hipStream_t s);
+    // returns -1 when profiling is off or this launch of class cls is not sampled
+    int prof_every = 1;
+    long long prof_calls[SGN_K_COUNT] = {};
+    int prof_start(hipStream_t s, int cls);
     void prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes = false);
     void prof_collect();
     // scratch device buffers owned by the context, grown on demand
