@@ -196,6 +196,86 @@ def fom_rational(A, b, omega, sigma, c, kmax, tol=1e-12, max_cycles=1000,
     return x
 
 
+def gmres_rational(A, b, omega, sigma, c, kmax, tol=1e-12, max_cycles=1000,
+                   L=None, R=None, lam=None, return_info=False):
+    """Restarted GMRES-LR(m, kmax) for g_s(cA)(I-P)b plus the exact deflated part
+    (the algorithm of the section "Restarted Arnoldi with rational functions",
+    following Frommer and Glassner: true restarted GMRES for the seed shift, the
+    other shifts with residuals kept collinear to the seed's).
+
+    Shifted systems (A' - sigma_i) x_i = y with A' = c^2 A^2 and y = c A (I-P) b;
+    the seed is the shift of smallest modulus.  Per cycle: kmax Arnoldi steps
+    (modified Gram-Schmidt) on A' from v_1 = r/beta; the seed's y_1 minimises
+    ||beta e_1 - (H^ - sigma_1 I^) y||; with z = beta e_1 - (H^ - sigma_1 I^) y_1 (the new
+    seed residual in the basis V_{k+1}) every other shift solves the square system
+    [H^ - sigma_i I^ | z] [y_i; rho_i] = rho_i^old beta e_1; x_i += V_k y_i;
+    r = V_{k+1} z, beta = ||r||, r = (I-P) r.  Converged when every shifted residual
+    |rho_i| beta <= tol ||y|| (rho = 1 for the seed)."""
+    b = np.asarray(b, dtype=np.complex128).ravel()
+    Ap = scaled_square(A, c)
+    xP = deflation_xP(L, R, lam, b)
+    r = c * A(project_out(L, R, b))
+    ynorm = np.linalg.norm(r)
+    s = len(omega)
+    n = b.size
+    seed = int(np.argmin(np.abs(sigma)))
+    rho = np.ones(s, dtype=np.complex128)
+    X = np.zeros((s, n), dtype=np.complex128)
+    beta = ynorm
+    cycles = 0
+    matvecs = 1
+    seed_res = []
+    while True:
+        res = np.abs(rho) * beta
+        if np.all(res <= tol * ynorm) or cycles >= max_cycles or beta == 0.0:
+            break
+        V = np.zeros((kmax + 1, n), dtype=np.complex128)
+        H = np.zeros((kmax + 1, kmax), dtype=np.complex128)
+        V[0] = r / beta
+        k = kmax
+        for j in range(kmax):
+            w = Ap(V[j])
+            matvecs += 2
+            for i in range(j + 1):                      # modified Gram-Schmidt
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] == 0.0:                      # invariant subspace: exact
+                k = j + 1
+                break
+            V[j + 1] = w / H[j + 1, j]
+        Hh = H[:k + 1, :k]
+        Ih = np.zeros((k + 1, k))
+        Ih[:k, :k] = np.eye(k)
+        e1 = np.zeros(k + 1, dtype=np.complex128)
+        e1[0] = beta
+        # seed: least squares (minimal residual over the Krylov space)
+        y1 = np.linalg.lstsq(Hh - sigma[seed] * Ih, e1, rcond=None)[0]
+        z = e1 - (Hh - sigma[seed] * Ih) @ y1
+        X[seed] += V[:k].T @ y1
+        new_rho = np.empty(s, dtype=np.complex128)
+        new_rho[seed] = 1.0
+        for i in range(s):
+            if i == seed:
+                continue
+            M = np.zeros((k + 1, k + 1), dtype=np.complex128)
+            M[:, :k] = Hh - sigma[i] * Ih
+            M[:, k] = z
+            sol = np.linalg.solve(M, rho[i] * e1)
+            X[i] += V[:k].T @ sol[:k]
+            new_rho[i] = sol[k]
+        rho = new_rho
+        r = V[:k + 1].T @ z
+        beta = np.linalg.norm(r)
+        seed_res.append(beta)
+        r = project_out(L, R, r)                        # projection step
+        cycles += 1
+    x = xP + np.asarray(omega, dtype=np.complex128) @ X
+    if return_info:
+        return x, dict(cycles=cycles, matvecs=matvecs, rho=rho, ynorm=ynorm, X=X, seed=seed, seed_res=seed_res)
+    return x
+
+
 def multishift_bicg(A, Ah, b, omega, sigma, c, tol=1e-12, maxiter=20000,
                     L=None, R=None, lam=None, return_info=False):
     """BiCG-LR(m): multishift BiCG for (A' - sigma_i) x_i = y, y = c A (I-P) b.

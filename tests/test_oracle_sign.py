@@ -246,3 +246,48 @@ def test_accuracy_measure():
     b = synth.gaussian_source(dims, 0).ravel()
     assert krylov.accuracy_measure(lambda v: S @ v, b) < 1e-12
     assert krylov.accuracy_measure(lambda v: 0.99 * (S @ v), b) > 5e-3
+
+
+def test_restarted_gmres_rational(rng):
+    """Restarted GMRES-LR: the dense rational target; the shifted residuals stay
+    collinear with the seed's (r_i = rho_i r_seed) after every restart; the seed's
+    first-cycle residual is no larger than FOM's (minimal residual over the same
+    Krylov space); one cycle with k = n is exact."""
+    A = _small_nonhermitian(rng, 30)
+    b = rng.standard_normal(30) + 1j * rng.standard_normal(30)
+    om, sg, c = rational.coefficients(8, 0.5, 2.1)
+    want = dense.rational_dense(A, b, om, sg, c)
+    x, info = krylov.gmres_rational(lambda v: A @ v, b, om, sg, c, 6, tol=1e-13, return_info=True)
+    assert rel(x, want) < 1e-10
+    assert info["cycles"] > 3
+    Ap = c * c * (A @ A)
+    y = c * (A @ b)
+    r_seed = y - (Ap - sg[info["seed"]] * np.eye(30)) @ info["X"][info["seed"]]
+    for i, s in enumerate(sg):
+        ri = y - (Ap - s * np.eye(30)) @ info["X"][i]
+        assert np.linalg.norm(ri - info["rho"][i] * r_seed) <= 1e-10 * np.linalg.norm(y)
+    # one cycle each: GMRES seed residual <= FOM seed residual
+    _, ig = krylov.gmres_rational(lambda v: A @ v, b, om, sg, c, 5, max_cycles=1, return_info=True)
+    _, inf = krylov.fom_rational(lambda v: A @ v, b, om, sg, c, 5, max_cycles=1, return_info=True)
+    seed = ig["seed"]
+    assert ig["seed_res"][0] <= abs(inf["rho"][seed]) * ig["ynorm"] * (1 + 1e-12)
+    # Krylov space of full dimension: exact after one cycle
+    x1 = krylov.gmres_rational(lambda v: A @ v, b, om, sg, c, 30, max_cycles=1)
+    assert rel(x1, want) < 1e-9
+
+
+def test_deflated_gmres_rational():
+    dims = (2, 2, 2, 4)
+    W_ = WilsonRef(synth.gauge_field(dims, 0.5, 0), dims, 0.2)
+    mu = 0.3
+    H = W_.dense(mu)
+    b = synth.gaussian_source(dims, 0).ravel()
+    A = lambda v: W_.apply(v, mu)
+    L, R, lam = _lattice_deflation(H, 8)
+    ev = np.linalg.eigvals(H)
+    alpha = np.min(np.abs(np.setdiff1d(ev, lam)))
+    beta = np.max(np.abs(ev))
+    om, sg, c = rational.coefficients(12, alpha, beta)
+    target = krylov.deflation_xP(L, R, lam, b) + dense.rational_dense(H, krylov.project_out(L, R, b), om, sg, c)
+    xg = krylov.gmres_rational(A, b, om, sg, c, 15, tol=1e-13, L=L, R=R, lam=lam)
+    assert rel(xg, target) < 1e-10
