@@ -229,6 +229,21 @@ sgn_status sign_arnoldi_rational(sgn_lattice lat, double mu, const void *b, void
                                  const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *stats,
                                  void *stream);
 
+/* Restarted GMRES-LR(m, k) (Algorithm "Restarted GMRES-LR", section "Restarted
+ * Arnoldi with rational functions", after Frommer and Glassner): the same
+ * restarted Arnoldi process on c^2 H_W^2 as sign_arnoldi_rational, but the seed
+ * system (the shift of smallest modulus) takes the minimal-residual iterate of
+ * each cycle, ||beta e_1 - (Hh_k - sigma Ih_k) y|| over y, and every other shift
+ * solves the (k+1) x (k+1) system that keeps its residual collinear to the
+ * seed's, r_i = rho_i r_seed.  Restart vector v_1 = (I-P) r / beta with r the
+ * seed's residual V_{k+1} z and beta = ||r|| taken before the projection.
+ * Converged when |rho_i| beta <= tol ||c H (I-P) b|| for every shift (rho = 1 for
+ * the seed).  Arguments, layout, precision schedule, statistics and errors as for
+ * sign_arnoldi_rational; SGN_ERR_BREAKDOWN if a small system is singular. */
+sgn_status sign_gmres_rational(sgn_lattice lat, double mu, const void *b, void *x, const sgn_rational *r,
+                               const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *stats,
+                               void *stream);
+
 /* ------------------------------------------------------------------ multishift BiCG */
 typedef struct {
     sgn_lattice lat;

@@ -352,6 +352,20 @@ def sign_arnoldi_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10
     return st.as_dict()
 
 
+lib.sign_gmres_rational.argtypes = lib.sign_arnoldi_rational.argtypes
+
+
+def sign_gmres_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10, max_restarts=0, prec=F64,
+                        theta32=0.0, theta16=0.0, stream=None):
+    """x = x_P + g_s(c H_W)(I-P) b by restarted GMRES-LR; returns the stats dict."""
+    o = ArnoldiOpts(int(kmax), float(tol), int(max_restarts), int(prec), float(theta32), float(theta16))
+    st = Stats()
+    d = C.pointer(defl.struct) if defl is not None else None
+    check(lib.sign_gmres_rational(lat.h, float(mu), _ptr(b), _ptr(x), C.byref(rational), d, C.byref(o),
+                                  C.byref(st), _stream(stream)), "sign_gmres_rational")
+    return st.as_dict()
+
+
 lib.sgn_accuracy_measure.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_double), _vp]
 
 

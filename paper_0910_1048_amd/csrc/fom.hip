@@ -1,14 +1,21 @@
-// Restarted FOM-LR(m, k) for the Neuberger rational function (the algorithm of
-// the section "Restarted Arnoldi with rational functions", with the collinear
-// restart of Eq. (collinearity)).
+// Restarted Arnoldi methods for the Neuberger rational function (section
+// "Restarted Arnoldi with rational functions"): FOM-LR(m, k) with the collinear
+// restart of Eq. (collinearity), and GMRES-LR(m, k) (Algorithm "Restarted
+// GMRES-LR", after Frommer and Glassner).
 //
 // Shifted systems (A' - sigma_i) x_i = y with A' = c^2 H_W(mu)^2, y = c H_W (I-P) b.
-// One cycle: k Arnoldi steps on A' from v_1 = r/||r|| (classical Gram-Schmidt
+// One cycle: k Arnoldi steps on A' from v_1 = r/beta (classical Gram-Schmidt
 // applied twice; the Hessenberg columns stay on the device), then on the host
-// y_i = beta rho_i (H_k - sigma_i)^{-1} e_1 for every shift (Hessenberg LU,
-// O(k^2) each), x += V_k sum_i omega_i y_i on the device, the new collinearity
-// factors rho_i = -h_{k+1,k} e_k^T y_i, and the projection step r = (I-P) v_{k+1}.
-// Converged when every shifted residual |rho_i| ||r|| <= tol ||y||.
+// the small problems of the cycle, x += V_k sum_i omega_i y_i on the device and
+// the projection step.
+//   FOM:   y_i = beta rho_i (H_k - sigma_i)^{-1} e_1 (Hessenberg LU, O(k^2) each),
+//          rho_i <- -h_{k+1,k} e_k^T y_i, r = (I-P) v_{k+1}.
+//   GMRES: the seed (shift of smallest modulus) minimises ||beta e_1 - (Hh - sigma_1 Ih) y||
+//          (Givens rotations), z = beta e_1 - (Hh - sigma_1 Ih) y_1 is its new residual in
+//          the basis V_{k+1}; every other shift solves [Hh - sigma_i Ih | z][y_i; rho_i] =
+//          rho_i beta e_1 (bordered Hessenberg LU); r = V_{k+1} z, beta = ||r||,
+//          v_1 = (I-P) r / beta.
+// Converged when every shifted residual |rho_i| beta <= tol ||y|| (rho = 1 for the seed).
 #include <chrono>
 #include <complex>
 #include <vector>
@@ -91,6 +98,23 @@ __global__ void fom_lift_kernel(const double2 *basis, int64_t n, int k, const z6
     }
 }
 
+// out[e] = sum_j c_j V_j[e]  (FP64 sums; the basis and out in one layout and precision)
+template <typename T>
+__global__ void fom_comb_kernel(const T *basis, int64_t n, int k, const z64 *c, T *out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 acc = {0.0, 0.0};
+        for (int j = 0; j < k; ++j) {
+            const T v = basis[(int64_t)j * n + e];
+            acc = acc + c[j] * z64{(double)v.x, (double)v.y};
+        }
+        T o;
+        o.x = acc.r;
+        o.y = acc.i;
+        out[e] = o;
+    }
+}
+
 // Solve (H - sigma I) y = rhs e_1 for a k x k upper Hessenberg H (column-major
 // hc[j*(kmax+1) + i] = H(i,j)), Gaussian elimination with partial pivoting.
 bool hessenberg_solve(const std::vector<zc> &hc, int ld, int k, double sigma, zc rhs, std::vector<zc> &y)
@@ -122,6 +146,87 @@ bool hessenberg_solve(const std::vector<zc> &hc, int ld, int k, double sigma, zc
     return true;
 }
 
+// Seed of a GMRES cycle: y minimises ||rhs e_1 - (Hh - sigma Ih) y|| for the (k+1) x k
+// upper Hessenberg Hh (Givens rotations with real cosines); z = rhs e_1 - (Hh - sigma Ih) y,
+// the new residual in the basis V_{k+1}.
+bool hessenberg_lsq(const std::vector<zc> &hc, int ld, int k, double sigma, zc rhs, std::vector<zc> &y,
+                    std::vector<zc> &z)
+{
+    auto hs = [&](int i, int j) {  // (Hh - sigma Ih)(i, j)
+        zc h = (i <= j + 1) ? hc[(size_t)j * ld + i] : zc(0, 0);
+        return i == j ? h - sigma : h;
+    };
+    std::vector<zc> A((size_t)(k + 1) * k);
+    for (int i = 0; i <= k; ++i)
+        for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = hs(i, j);
+    std::vector<zc> g(k + 1, zc(0, 0));
+    g[0] = rhs;
+    for (int i = 0; i < k; ++i) {  // rotate rows i, i+1 so that A(i+1, i) = 0
+        const zc a = A[(size_t)i * k + i], bb = A[(size_t)(i + 1) * k + i];
+        const double aa = std::abs(a), ab = std::abs(bb), t = std::hypot(aa, ab);
+        if (t == 0.0) return false;
+        const double cs = aa / t;
+        const zc sn = aa > 0.0 ? (a / aa) * std::conj(bb) / t : std::conj(bb) / ab;
+        for (int j = i; j < k; ++j) {
+            const zc u = A[(size_t)i * k + j], v = A[(size_t)(i + 1) * k + j];
+            A[(size_t)i * k + j] = cs * u + sn * v;
+            A[(size_t)(i + 1) * k + j] = -std::conj(sn) * u + cs * v;
+        }
+        const zc u = g[i], v = g[i + 1];
+        g[i] = cs * u + sn * v;
+        g[i + 1] = -std::conj(sn) * u + cs * v;
+    }
+    y.assign(k, zc(0, 0));
+    for (int i = k - 1; i >= 0; --i) {
+        zc acc = g[i];
+        for (int j = i + 1; j < k; ++j) acc -= A[(size_t)i * k + j] * y[j];
+        y[i] = acc / A[(size_t)i * k + i];
+    }
+    z.assign(k + 1, zc(0, 0));
+    z[0] = rhs;
+    for (int i = 0; i <= k; ++i)
+        for (int j = std::max(i - 1, 0); j < k; ++j) z[i] -= hs(i, j) * y[j];
+    return true;
+}
+
+// [Hh - sigma Ih | z] [y; rho] = rhs e_1, a (k+1) x (k+1) system whose first k columns
+// are upper Hessenberg and whose last column is z; Gaussian elimination with
+// partial pivoting between adjacent rows (O(k^2)).
+bool bordered_solve(const std::vector<zc> &hc, int ld, int k, double sigma, const std::vector<zc> &z, zc rhs,
+                    std::vector<zc> &y, zc &rho)
+{
+    const int m = k + 1;
+    std::vector<zc> A((size_t)m * m, zc(0, 0));
+    for (int j = 0; j < k; ++j) {
+        for (int i = 0; i <= std::min(j + 1, k); ++i) A[(size_t)i * m + j] = hc[(size_t)j * ld + i];
+        A[(size_t)j * m + j] -= sigma;
+    }
+    for (int i = 0; i < m; ++i) A[(size_t)i * m + k] = z[i];
+    std::vector<zc> b(m, zc(0, 0));
+    b[0] = rhs;
+    for (int i = 0; i < k; ++i) {
+        zc *ri = &A[(size_t)i * m], *rn = &A[(size_t)(i + 1) * m];
+        if (std::abs(rn[i]) > std::abs(ri[i])) {
+            for (int j = i; j < m; ++j) std::swap(ri[j], rn[j]);
+            std::swap(b[i], b[i + 1]);
+        }
+        if (ri[i] == zc(0, 0)) return false;
+        const zc f = rn[i] / ri[i];
+        for (int j = i; j < m; ++j) rn[j] -= f * ri[j];
+        b[i + 1] -= f * b[i];
+    }
+    std::vector<zc> u(m);
+    for (int i = m - 1; i >= 0; --i) {
+        zc acc = b[i];
+        for (int j = i + 1; j < m; ++j) acc -= A[(size_t)i * m + j] * u[j];
+        if (A[(size_t)i * m + i] == zc(0, 0)) return false;
+        u[i] = acc / A[(size_t)i * m + i];
+    }
+    y.assign(u.begin(), u.begin() + k);
+    rho = u[k];
+    return true;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -133,20 +238,25 @@ double ms_since(std::chrono::steady_clock::time_point t0)
 
 using namespace sgn;
 
-extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void *b, void *x, const sgn_rational *rf,
-                                           const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *st,
-                                           void *stream)
+namespace {
+
+// One restarted Arnoldi driver for both methods; they differ only in the small
+// problems solved on the host after each cycle and in the restart vector.
+sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, const sgn_rational *rf,
+                             const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *st, void *stream,
+                             bool gmres)
 {
+    const std::string who = gmres ? "sign_gmres_rational" : "sign_arnoldi_rational";
     sgn_status result = SGN_OK;
     sgn_status g = guard([&] {
         const auto t_start = std::chrono::steady_clock::now();
-        SGN_REQUIRE(l && b && x && rf && o, "sign_arnoldi_rational: null argument");
-        SGN_REQUIRE(o->kmax >= 1, "sign_arnoldi_rational: kmax must be >= 1");
-        SGN_REQUIRE(o->tol > 0 && o->tol < 1, "sign_arnoldi_rational: tol must be in (0, 1)");
-        SGN_REQUIRE(rf->s >= 1 && rf->s <= SGN_MAX_POLES && rf->c > 0, "sign_arnoldi_rational: bad rational function");
+        SGN_REQUIRE(l && b && x && rf && o, who + ": null argument");
+        SGN_REQUIRE(o->kmax >= 1, who + ": kmax must be >= 1");
+        SGN_REQUIRE(o->tol > 0 && o->tol < 1, who + ": tol must be in (0, 1)");
+        SGN_REQUIRE(rf->s >= 1 && rf->s <= SGN_MAX_POLES && rf->c > 0, who + ": bad rational function");
         SGN_REQUIRE(o->prec == SGN_PREC_F64 || o->prec == SGN_PREC_F32 || o->prec == SGN_PREC_F32_H16,
-                    "sign_arnoldi_rational: unknown precision");
-        SGN_REQUIRE(std::isfinite(mu), "sign_arnoldi_rational: mu not finite");
+                    who + ": unknown precision");
+        SGN_REQUIRE(std::isfinite(mu), who + ": mu not finite");
         Lattice &lat = *as_lattice(l);
         Context &ctx = *lat.ctx;
         SGN_HIP(hipSetDevice(ctx.device));
@@ -170,6 +280,7 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         char *w = Vb + (size_t)(k + 1) * b64, *t = w + b64, *xi = t + b64, *rcan = xi + b64;
         z64 *Hd = reinterpret_cast<z64 *>(rcan + c64);  // column-major (k+1) x k
         z64 *h1 = Hd + (size_t)ld * k, *h2 = h1 + ld, *cd = h2 + ld, *scal = cd + ld;  // scal: hsub, inv
+        z64 *zd = scal + 4;  // GMRES: the seed's residual z in the basis V_{k+1} (ld entries)
         bool lo = false;                   // this cycle runs in FP32 (basis slots of b32 bytes)
         sgn_prec sp = SGN_PREC_F64;        // stencil precision of this cycle
         auto Vj = [&](int j) { return Vb + (size_t)j * (lo ? b32 : b64); };
@@ -185,13 +296,16 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
             dslash_launch(lat, SGN_PREC_F64, opA, t, Vj(0), ep, s);
         }
         const double ynorm = norm_sync(ctx, Vj(0), n, false, s);
-        SGN_REQUIRE(std::isfinite(ynorm), "sign_arnoldi_rational: b contains NaN or Inf");
+        SGN_REQUIRE(std::isfinite(ynorm), who + ": b contains NaN or Inf");
         if (ynorm == 0.0) return;
         SGN_HIP(hipMemsetAsync(xi, 0, b64, s));
         double beta = ynorm;
         scale64({1.0 / beta, 0.0}, Vj(0), Vj(0), n, s);
         std::vector<zc> rho(ns, zc(1, 0));
-        std::vector<zc> Hh((size_t)ld * k), y, comb(k);
+        std::vector<zc> Hh((size_t)ld * k), y, z, comb(k);
+        int seed = 0;  // GMRES: the shift of smallest modulus runs true restarted GMRES
+        for (int i = 1; i < ns; ++i)
+            if (std::abs(rf->sigma[i]) < std::abs(rf->sigma[seed])) seed = i;
         const int nvb = vec_blocks(n);
         z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nvb, 1)));
         const int max_cycles = o->max_restarts > 0 ? o->max_restarts : 1000;
@@ -241,19 +355,36 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
             // host: shifted Hessenberg systems of this cycle
             SGN_HIP(hipMemcpyAsync(Hh.data(), Hd, sizeof(z64) * (size_t)ld * k, hipMemcpyDeviceToHost, s));
             SGN_HIP(hipStreamSynchronize(s));
-            for (int j = 0; j + 1 < k; ++j)
-                if (std::abs(Hh[(size_t)j * ld + j + 1]) == 0.0) {  // invariant subspace: exact solution in K_{j+1}
+            bool exact = false;  // invariant subspace: the cycle's space holds every solution
+            for (int j = 0; j < (gmres ? k : k - 1); ++j)
+                if (std::abs(Hh[(size_t)j * ld + j + 1]) == 0.0) {
                     kk = j + 1;
+                    exact = true;
                     break;
                 }
             const auto t0 = std::chrono::steady_clock::now();
             std::fill(comb.begin(), comb.end(), zc(0, 0));
-            const zc hnext = Hh[(size_t)(kk - 1) * ld + kk];
-            for (int i = 0; i < ns; ++i) {
-                if (!hessenberg_solve(Hh, ld, kk, rf->sigma[i], beta * rho[i], y))
-                    throw Failure{SGN_ERR_BREAKDOWN, "singular shifted Hessenberg system"};
-                for (int j = 0; j < kk; ++j) comb[j] += rf->omega[i] * y[j];
-                rho[i] = (kk < k) ? zc(0, 0) : -hnext * y[kk - 1];
+            if (!gmres || exact) {
+                const zc hnext = Hh[(size_t)(kk - 1) * ld + kk];
+                for (int i = 0; i < ns; ++i) {
+                    if (!hessenberg_solve(Hh, ld, kk, rf->sigma[i], beta * rho[i], y))
+                        throw Failure{SGN_ERR_BREAKDOWN, "singular shifted Hessenberg system"};
+                    for (int j = 0; j < kk; ++j) comb[j] += rf->omega[i] * y[j];
+                    rho[i] = exact ? zc(0, 0) : -hnext * y[kk - 1];
+                }
+            } else {
+                if (!hessenberg_lsq(Hh, ld, k, rf->sigma[seed], beta, y, z))
+                    throw Failure{SGN_ERR_BREAKDOWN, "rank-deficient seed least-squares problem"};
+                for (int j = 0; j < k; ++j) comb[j] += rf->omega[seed] * y[j];
+                for (int i = 0; i < ns; ++i) {
+                    if (i == seed) continue;
+                    zc ri;
+                    if (!bordered_solve(Hh, ld, k, rf->sigma[i], z, beta * rho[i], y, ri))
+                        throw Failure{SGN_ERR_BREAKDOWN, "singular collinearity system"};
+                    for (int j = 0; j < k; ++j) comb[j] += rf->omega[i] * y[j];
+                    rho[i] = ri;
+                }
+                rho[seed] = zc(1, 0);
             }
             small_ms += ms_since(t0);
             SGN_HIP(hipMemcpyAsync(cd, comb.data(), sizeof(z64) * kk, hipMemcpyHostToDevice, s));
@@ -264,9 +395,44 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
                 hipLaunchKernelGGL(fom_lift_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)Vb, n, kk, cd,
                                    (double2 *)xi);
             ++cycles;
-            // r = (I - P) v_{k+1}  (canonical FP64 round trip for the deflation projection)
-            double rnorm = 1.0;
-            if (defl && defl->m > 0 && kk == k) {
+            const bool project = defl && defl->m > 0;
+            double rnorm = 1.0;  // FOM: ||(I-P) v_{k+1}||; GMRES: beta = ||V_{k+1} z||
+            if (gmres && !exact) {
+                // r = V_{k+1} z in w, beta = ||r||, then v_1 = (I-P) r / beta in V_0
+                SGN_HIP(hipMemcpyAsync(zd, z.data(), sizeof(z64) * (size_t)(k + 1), hipMemcpyHostToDevice, s));
+                if (lo)
+                    hipLaunchKernelGGL(fom_comb_kernel<float2>, dim3(nvb), dim3(256), 0, s, (const float2 *)Vb, n,
+                                       k + 1, (const z64 *)zd, (float2 *)w);
+                else
+                    hipLaunchKernelGGL(fom_comb_kernel<double2>, dim3(nvb), dim3(256), 0, s, (const double2 *)Vb, n,
+                                       k + 1, (const z64 *)zd, (double2 *)w);
+                SGN_HIP(hipGetLastError());
+                rnorm = norm_sync(ctx, w, n, lo, s);
+                if (project) {
+                    if (lo) {
+                        convert_32_to_64(w, t, lat.S, s);
+                        unpack_spinor(lat, t, rcan, SGN_PREC_F64, s);
+                    } else {
+                        unpack_spinor(lat, w, rcan, SGN_PREC_F64, s);
+                    }
+                    deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s);
+                    if (lo) {
+                        pack_spinor(lat, t, w, SGN_PREC_F64, s);
+                        convert_64_to_32(w, Vj(0), lat.S, s);
+                    } else {
+                        pack_spinor(lat, t, Vj(0), SGN_PREC_F64, s);
+                    }
+                } else if (rnorm > 0.0) {  // scaled straight into V_0 below
+                    if (lo)
+                        hipLaunchKernelGGL(fom_scale_kernel<float2>, dim3(nvb), dim3(256), 0, s, (const float2 *)w,
+                                           (const z64 *)nullptr, 1.0 / rnorm, (float2 *)Vj(0), n);
+                    else
+                        hipLaunchKernelGGL(fom_scale_kernel<double2>, dim3(nvb), dim3(256), 0, s, (const double2 *)w,
+                                           (const z64 *)nullptr, 1.0 / rnorm, (double2 *)Vj(0), n);
+                    SGN_HIP(hipGetLastError());
+                }
+            } else if (project && !exact) {
+                // r = (I - P) v_{k+1}  (canonical FP64 round trip for the deflation projection)
                 if (lo) {
                     convert_32_to_64(Vj(k), w, lat.S, s);
                     unpack_spinor(lat, w, rcan, SGN_PREC_F64, s);
@@ -281,7 +447,7 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
                     pack_spinor(lat, t, Vj(0), SGN_PREC_F64, s);
                 }
                 rnorm = norm_sync(ctx, Vj(0), n, lo, s);
-            } else if (kk == k) {
+            } else if (!exact) {
                 SGN_HIP(hipMemcpyAsync(Vj(0), Vj(k), lo ? b32 : b64, hipMemcpyDeviceToDevice, s));
             }
             double worst = 0.0;
@@ -290,14 +456,14 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
                 worst = std::max(worst, ri);
                 if (st) st->shift_residual[i] = ri;
             }
-            if (worst <= o->tol || kk < k) {
+            if (worst <= o->tol || exact) {
                 converged = true;
                 break;
             }
             if (cycles >= max_cycles) break;
             worst_prev = worst;
             beta = rnorm;
-            if (rnorm != 1.0) {
+            if (rnorm != 1.0 && (!gmres || project)) {
                 if (lo)
                     hipLaunchKernelGGL(fom_scale_kernel<float2>, dim3(nvb), dim3(256), 0, s, (const float2 *)Vj(0),
                                        (const z64 *)nullptr, 1.0 / rnorm, (float2 *)Vj(0), n);
@@ -325,4 +491,20 @@ extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void
         }
     });
     return g != SGN_OK ? g : result;
+}
+
+}  // namespace
+
+extern "C" sgn_status sign_arnoldi_rational(sgn_lattice l, double mu, const void *b, void *x, const sgn_rational *rf,
+                                           const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *st,
+                                           void *stream)
+{
+    return restarted_arnoldi(l, mu, b, x, rf, defl, o, st, stream, false);
+}
+
+extern "C" sgn_status sign_gmres_rational(sgn_lattice l, double mu, const void *b, void *x, const sgn_rational *rf,
+                                         const sgn_deflation *defl, const sgn_arnoldi_opts *o, sgn_stats *st,
+                                         void *stream)
+{
+    return restarted_arnoldi(l, mu, b, x, rf, defl, o, st, stream, true);
 }
