@@ -14,6 +14,13 @@ Choice of c and s for a spectrum inside C(m, r) u C(-m, r):
 Spectral-circle heuristic (numerical-results section): m = (alpha+beta)/2,
 r = (beta-alpha)/2 from the smallest non-deflated modulus alpha and the
 largest modulus beta.
+Rescaled Neuberger (footnote on the choice of c): with e_max the largest
+error of g_s(ct) on [alpha, beta], the factor 2/(2 - e_max) lowers it to
+e_max/(2 - e_max).
+Zolotarev's best rational approximation on [-beta,-alpha] u [alpha,beta]
+(named there as the alternative for spectra close to the real axis), in the
+standard form with Jacobi elliptic functions of modulus k' = sqrt(1 - k^2),
+k = alpha/beta.
 """
 from __future__ import annotations
 
@@ -79,3 +86,70 @@ def coefficients(s: int, alpha: float, beta: float):
     c, _ = scale_from_circle(m, r)
     om, sg = neuberger_pfe(s)
     return om, sg, c
+
+
+def neuberger_rescaled(s: int, alpha: float, beta: float, npts: int = 200001):
+    """(omega, sigma, c, e_max) of the rescaled Neuberger approximation: e_max is
+    the largest |1 - g_s(ct)| over a dense grid of [alpha, beta] (g_s monotone on
+    each side of ct = 1, so the grid includes both ends), omega scaled by
+    2/(2 - e_max)."""
+    om, sg, c = coefficients(s, alpha, beta)
+    t = np.geomspace(alpha, beta, npts)
+    e_max = float(np.max(np.abs(1.0 - g_closed(s, c * t).real)))
+    return om * (2.0 / (2.0 - e_max)), sg, c, e_max
+
+
+def zolotarev_product_coefficients(n: int, k: float):
+    """c_1 .. c_{2n-1}: c_l = k^2 sn^2(l K'/(2n); k') / cn^2(l K'/(2n); k'),
+    K' the complete elliptic integral of modulus k' = sqrt(1 - k^2)."""
+    from scipy.special import ellipj, ellipk
+    mp = 1.0 - k * k  # parameter (modulus squared) of k'
+    Kp = float(ellipk(mp))
+    l = np.arange(1, 2 * n, dtype=np.float64)
+    sn, cn, _, _ = ellipj(l * Kp / (2 * n), mp)
+    return k * k * sn ** 2 / cn ** 2
+
+
+def zolotarev_unscaled(n: int, k: float, x):
+    """x prod_{l<n} (x^2 + c_{2l}) / prod_{l<=n} (x^2 + c_{2l-1}) (no factor D)."""
+    cc = zolotarev_product_coefficients(n, k)
+    x = np.asarray(x, dtype=np.complex128)
+    num = x.copy()
+    den = np.ones_like(x)
+    for l in range(1, n):
+        num = num * (x * x + cc[2 * l - 1])
+    for l in range(1, n + 1):
+        den = den * (x * x + cc[2 * l - 2])
+    return num / den
+
+
+def zolotarev(n: int, alpha: float, beta: float, npts: int = 200001):
+    """(omega, sigma, c, delta) with sign(t) ~ t' sum_i omega_i/(t'^2 - sigma_i), t' = c t,
+    c = 1/beta; D = 2/(max + min) of the unscaled function over [k, 1] (dense
+    grid refined by a bounded scalar search around every grid extremum), so that
+    the error equioscillates between -delta and +delta, delta = (max-min)/(max+min).
+    The weights are D times the residues of the product form at x^2 = -c_{2i-1}."""
+    from scipy.optimize import minimize_scalar
+    k = alpha / beta
+    cc = zolotarev_product_coefficients(n, k)
+    odd = cc[0::2]   # c_1, c_3, ..., c_{2n-1}
+    even = cc[1::2]  # c_2, ..., c_{2n-2}
+    x = np.geomspace(k, 1.0, npts)
+    f = zolotarev_unscaled(n, k, x).real
+    vals = [f[0], f[-1]]
+    for j in range(1, npts - 1):
+        if (f[j] - f[j - 1]) * (f[j + 1] - f[j]) <= 0.0:
+            sgn = -1.0 if f[j] > f[j - 1] else 1.0
+            r = minimize_scalar(lambda u: sgn * zolotarev_unscaled(n, k, u).real,
+                                bounds=(x[j - 1], x[j + 1]), method="bounded",
+                                options={"xatol": 1e-14 * x[j]})
+            vals.append(zolotarev_unscaled(n, k, r.x).real)
+    fmax, fmin = max(vals), min(vals)
+    D = 2.0 / (fmax + fmin)
+    delta = (fmax - fmin) / (fmax + fmin)
+    a = np.empty(n)
+    for i in range(n):
+        num = np.prod(even - odd[i])
+        den = np.prod(np.delete(odd, i) - odd[i])
+        a[i] = num / den
+    return D * a, -odd, 1.0 / beta, delta
