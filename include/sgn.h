@@ -202,6 +202,19 @@ sgn_status sgn_rational_neuberger(int s, double alpha, double beta, sgn_rational
 /* Smallest s satisfying Eq. (no_of_poles) for accuracy eps on the circles
  * through alpha and beta (circle theorem).  Host only. */
 sgn_status sgn_poles_needed(double alpha, double beta, double eps, int *s);
+/* Neuberger coefficients as sgn_rational_neuberger with every omega_i multiplied by
+ * 2/(2 - e_max), e_max = max |1 - g_s(ct)| over real t in [alpha, beta] (footnote on the
+ * choice of c): the largest real-axis error drops from e_max to e_max/(2 - e_max).
+ * *err (may be NULL) receives that error.  Host only. */
+sgn_status sgn_rational_neuberger_rescaled(int s, double alpha, double beta, sgn_rational *out, double *err);
+/* Zolotarev's best uniform rational approximation of sign on [-beta,-alpha] u
+ * [alpha,beta] with s poles in t^2 (the alternative named in the numerical-results
+ * section for spectra close to the real axis), in the same partial-fraction form:
+ * c = 1/beta, sigma_i = -c_{2i-1} with c_l = k^2 sn^2(l K'/(2s); k') / cn^2(l K'/(2s); k'),
+ * k = alpha/beta, k' = sqrt(1-k^2), K' = K(k'); omega_i = D times the residues of the
+ * product form, D normalising the error to equioscillate.  *err (may be NULL)
+ * receives the uniform error on the two intervals.  Host only. */
+sgn_status sgn_rational_zolotarev(int s, double alpha, double beta, sgn_rational *out, double *err);
 
 /* ------------------------------------------------------------------ restarted FOM (Arnoldi) */
 typedef struct {

@@ -125,9 +125,10 @@ def zolotarev_unscaled(n: int, k: float, x):
 
 def zolotarev(n: int, alpha: float, beta: float, npts: int = 200001):
     """(omega, sigma, c, delta) with sign(t) ~ t' sum_i omega_i/(t'^2 - sigma_i), t' = c t,
-    c = 1/beta; D = 2/(max + min) of the unscaled function over [k, 1] (dense
-    grid refined by a bounded scalar search around every grid extremum), so that
-    the error equioscillates between -delta and +delta, delta = (max-min)/(max+min).
+    c = 1/beta; D = 2/(max + min) of the unscaled function over [k, 1], so that the
+    error equioscillates between -delta and +delta, delta = (max-min)/(max+min).
+    The extrema: a dense grid, the error of a provisional D split into runs of one
+    sign, the largest deviation of each run refined by a bounded scalar search.
     The weights are D times the residues of the product form at x^2 = -c_{2i-1}."""
     from scipy.optimize import minimize_scalar
     k = alpha / beta
@@ -136,14 +137,16 @@ def zolotarev(n: int, alpha: float, beta: float, npts: int = 200001):
     even = cc[1::2]  # c_2, ..., c_{2n-2}
     x = np.geomspace(k, 1.0, npts)
     f = zolotarev_unscaled(n, k, x).real
+    e0 = 2.0 / (f.max() + f.min()) * f - 1.0
+    cut = np.nonzero(np.sign(e0[1:]) != np.sign(e0[:-1]))[0] + 1
     vals = [f[0], f[-1]]
-    for j in range(1, npts - 1):
-        if (f[j] - f[j - 1]) * (f[j + 1] - f[j]) <= 0.0:
-            sgn = -1.0 if f[j] > f[j - 1] else 1.0
-            r = minimize_scalar(lambda u: sgn * zolotarev_unscaled(n, k, u).real,
-                                bounds=(x[j - 1], x[j + 1]), method="bounded",
-                                options={"xatol": 1e-14 * x[j]})
-            vals.append(zolotarev_unscaled(n, k, r.x).real)
+    for lo, hi in zip(np.concatenate(([0], cut)), np.concatenate((cut, [npts]))):
+        j = lo + int(np.argmax(np.abs(e0[lo:hi])))
+        sgn = -1.0 if e0[j] > 0 else 1.0  # maximise f on runs above 1, minimise below
+        r = minimize_scalar(lambda u: sgn * zolotarev_unscaled(n, k, u).real,
+                            bounds=(x[max(j - 1, 0)], x[min(j + 1, npts - 1)]), method="bounded",
+                            options={"xatol": 1e-14 * x[j]})
+        vals.append(zolotarev_unscaled(n, k, r.x).real)
     fmax, fmin = max(vals), min(vals)
     D = 2.0 / (fmax + fmin)
     delta = (fmax - fmin) / (fmax + fmin)

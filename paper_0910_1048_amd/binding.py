@@ -259,6 +259,27 @@ def sgn_poles_needed(alpha, beta, eps):
     return s.value
 
 
+lib.sgn_rational_neuberger_rescaled.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(Rational),
+                                                C.POINTER(C.c_double)]
+lib.sgn_rational_zolotarev.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(Rational), C.POINTER(C.c_double)]
+
+
+def sgn_rational_neuberger_rescaled(s, alpha, beta):
+    """(coefficients, largest real-axis error on [alpha, beta])."""
+    r, e = Rational(), C.c_double()
+    check(lib.sgn_rational_neuberger_rescaled(int(s), float(alpha), float(beta), C.byref(r), C.byref(e)),
+          "sgn_rational_neuberger_rescaled")
+    return r, e.value
+
+
+def sgn_rational_zolotarev(s, alpha, beta):
+    """(coefficients, uniform error on [-beta,-alpha] u [alpha,beta])."""
+    r, e = Rational(), C.c_double()
+    check(lib.sgn_rational_zolotarev(int(s), float(alpha), float(beta), C.byref(r), C.byref(e)),
+          "sgn_rational_zolotarev")
+    return r, e.value
+
+
 class Problem:
     """One right-hand side of multishift_solve.  x_shift: optional list of s device tensors."""
 

@@ -49,3 +49,29 @@ def test_rational_coefficients_match_oracle():
         sgn.sgn_rational_neuberger(0, 0.1, 1.0)
     with pytest.raises(sgn.SgnError):
         sgn.sgn_rational_neuberger(8, 1.0, 0.5)
+
+
+def test_rescaled_neuberger_and_zolotarev_match_oracle():
+    """Host-only library calls (no GPU): the rescaled Neuberger weights and error, and
+    the Zolotarev coefficients and uniform error (library: its own AGM elliptic
+    functions; oracle: scipy's), for errors down to about 1e-12 (below that both
+    only resolve rounding)."""
+    import numpy as np
+    import pytest
+    from oracle import rational
+    for s, a, b in ((8, 0.15, 2.6), (16, 0.05, 2.5)):
+        r, e = sgn.sgn_rational_neuberger_rescaled(s, a, b)
+        om, sg, c, e_max = rational.neuberger_rescaled(s, a, b)
+        assert e == pytest.approx(e_max / (2 - e_max), rel=1e-8)
+        assert max(abs(r.omega[i] - om[i]) / om[i] for i in range(s)) < 1e-10
+    for n, a, b in ((1, 0.2, 1.0), (4, 0.1, 2.0), (12, 0.05, 2.6), (16, 0.01, 2.6)):
+        r, d = sgn.sgn_rational_zolotarev(n, a, b)
+        om, sg, c, delta = rational.zolotarev(n, a, b)
+        assert r.s == n and r.c == pytest.approx(c, rel=1e-15)
+        assert np.allclose([r.sigma[i] for i in range(n)], sg, rtol=1e-10, atol=0)
+        assert np.allclose([r.omega[i] for i in range(n)], om, rtol=1e-8, atol=0)
+        assert abs(d - delta) <= 1e-5 * delta + 1e-13  # coefficients agree to ~2e-13 relative
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_rational_zolotarev(0, 0.1, 1.0)
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_rational_zolotarev(8, 1.0, 0.5)
