@@ -10,8 +10,9 @@ algorithms are plain numpy/scipy restatements of the paper:
   dense     -- sign(A) b by eigendecomposition, by Schur-Sylvester, Hermitian case;
                exact rational target g_s(cA) b
   rational  -- Neuberger coefficients, circle theorem, number of poles
-  krylov    -- two-sided Lanczos sign, restarted FOM rational, multishift BiCG,
-               LR deflation, accuracy measure
+  krylov    -- two-sided Lanczos sign, restarted FOM and GMRES rational, multishift
+               BiCG, LR deflation, accuracy measure
+  eigen     -- critical left/right eigenpairs for LR deflation (dense definition)
 """
-from . import dense, krylov, rational, wilson  # noqa: F401
+from . import dense, eigen, krylov, rational, wilson  # noqa: F401
 from .wilson import WilsonRef  # noqa: F401

@@ -64,3 +64,19 @@ def test_accuracy_measure_tracks_the_rational_error():
     A = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)) + 3 * np.diag(np.sign(rng.standard_normal(12)))
     v = rng.standard_normal(12) + 1j * rng.standard_normal(12)
     assert krylov.accuracy_measure(lambda w: dense.sign_eig(A, w), v) < 1e-12
+
+
+def test_c1_deflation_fixture_consistent():
+    """The stored deflation data agree with the stored spectrum (the 15 eigenvalues
+    closest to the imaginary axis; alpha of the rest) and with an independent
+    route: sign(H) b - x_P = sign(H)(I - P) b by the undeflated two-sided Lanczos
+    oracle on b - P b, against the stored dense sign(H) b."""
+    W, b, g = _c1()
+    d = np.load(os.path.join(os.path.dirname(GOLD), "c1_deflation.npz"))
+    ev = g["evals"]
+    o = np.argsort(np.abs(ev.real))
+    assert np.allclose(np.sort(np.abs(d["lam"].real)), np.abs(ev.real)[o[:15]], rtol=1e-10)
+    assert abs(d["alpha_rest"] - np.abs(ev[o[15:]]).min()) < 1e-12
+    r = b - d["Pb"]
+    y = krylov.lanczos_sign(lambda v: W.apply(v, 0.3), lambda v: W.apply_adj(v, 0.3), r, 400)
+    assert rel(d["xP"] + y, g["sign_b"]) < 1e-8
