@@ -216,6 +216,35 @@ sgn_status sgn_rational_neuberger_rescaled(int s, double alpha, double beta, sgn
  * receives the uniform error on the two intervals.  Host only. */
 sgn_status sgn_rational_zolotarev(int s, double alpha, double beta, sgn_rational *out, double *err);
 
+/* ------------------------------------------------------------------ critical eigenpairs */
+typedef struct {
+    int m;             /* eigenpairs wanted, m >= 1 */
+    int nev;           /* Ritz pairs kept per restart, nev > m (0: m + max(6, m/2)) */
+    int kmax;          /* Arnoldi basis size, nev + 2 <= kmax <= 1024 (0: 2 nev + 16) */
+    double tol;        /* Ritz residual of H_W^2 <= tol |theta| for the m + 2 wanted (0: 1e-10) */
+    int max_restarts;  /* per side (0: 1000) */
+    unsigned seed;     /* start vectors (a fixed pseudo-random sequence per seed) */
+} sgn_eig_opts;
+
+/* Left and right eigenvectors of H_W(mu) for its m critical eigenvalues, the m
+ * closest to the imaginary axis (section "Deflation"), in the format of
+ * sgn_deflation: L, R (device) receive m canonical complex128 vectors each,
+ * back to back, with L^H R = I_m and unit right vectors; lambda (host) receives
+ * m complex128 values ordered by |Re lambda|.  Method: implicitly restarted
+ * Arnoldi with exact shifts on H_W(mu)^2 and on H_W(-mu)^2 = (H_W^H)^2 for the
+ * eigenvalues of smallest real part of the square, Rayleigh-Ritz with H_W on each
+ * invariant subspace, then the oblique projection that pairs the two.  *alpha
+ * (may be NULL) receives the smallest modulus among the right Ritz values kept
+ * but not selected, an estimate of the smallest non-deflated |lambda|.
+ * stats: iterations = Arnoldi steps, restarts, matvecs, residual = largest
+ * ||H r - lambda r|| / (|lambda| ||r||) over both sides.  The m-th and (m+1)-th
+ * eigenvalues should be separated: a cut inside a cluster leaves the projector
+ * ill-determined.  SGN_ERR_NOT_CONVERGED if a side did not converge within
+ * max_restarts (outputs hold the last approximation), SGN_ERR_BREAKDOWN if the
+ * two subspaces do not pair (singular L^H R).  Synchronises `stream`. */
+sgn_status sgn_critical_eigenpairs(sgn_lattice lat, double mu, const sgn_eig_opts *o, void *L, void *R,
+                                   double *lambda, double *alpha, sgn_stats *stats, void *stream);
+
 /* ------------------------------------------------------------------ restarted FOM (Arnoldi) */
 typedef struct {
     int kmax;           /* Arnoldi steps per restart cycle (k_max) */
@@ -298,6 +327,12 @@ typedef struct {
  * with one stored vector per iteration instead of a read-modify-write of every
  * p_i.  If the stored basis would exceed basis_slots vectors the solver turns
  * the basis into explicit p_i, x_i and continues with per-shift vectors.
+ * With LR deflation the exact x_i lie in range(I - P); the components along the
+ * deflated eigenvectors that rounding leaves (which the bi-Lanczos process,
+ * whose shadow space is orthogonal to them, never reduces) are projected out of
+ * the seed solution at every reliable update and out of the combined result at
+ * the end, and the mixed schedule stops at FP32 (FP16 links would perturb the
+ * operator enough to excite those modes every iteration).
  * Synchronises `stream`.  Returns SGN_ERR_NOT_CONVERGED (x holds the last
  * iterate) if maxiter is reached, SGN_ERR_BREAKDOWN on a BiCG breakdown. */
 sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,

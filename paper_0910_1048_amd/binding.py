@@ -376,6 +376,28 @@ def sign_arnoldi_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10
 lib.sign_gmres_rational.argtypes = lib.sign_arnoldi_rational.argtypes
 
 
+class EigOpts(C.Structure):
+    _fields_ = [("m", C.c_int), ("nev", C.c_int), ("kmax", C.c_int), ("tol", C.c_double),
+                ("max_restarts", C.c_int), ("seed", C.c_uint)]
+
+
+lib.sgn_critical_eigenpairs.argtypes = [_vp, C.c_double, C.POINTER(EigOpts), _vp, _vp, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(Stats), _vp]
+
+
+def sgn_critical_eigenpairs(lat, mu, m, L, R, nev=0, kmax=0, tol=0.0, max_restarts=0, seed=0, stream=None):
+    """Left/right eigenvectors of the m eigenvalues of H_W(mu) closest to the imaginary axis
+    into the device tensors L and R (m x 12V complex128 each).  Returns (lambda, alpha, stats)."""
+    o = EigOpts(int(m), int(nev), int(kmax), float(tol), int(max_restarts), int(seed))
+    lam = (C.c_double * (2 * int(m)))()
+    alpha = C.c_double()
+    st = Stats()
+    check(lib.sgn_critical_eigenpairs(lat.h, float(mu), C.byref(o), _ptr(L), _ptr(R), lam, C.byref(alpha),
+                                      C.byref(st), _stream(stream)), "sgn_critical_eigenpairs")
+    lm = [complex(lam[2 * i], lam[2 * i + 1]) for i in range(int(m))]
+    return lm, alpha.value, st.as_dict()
+
+
 def sign_gmres_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10, max_restarts=0, prec=F64,
                         theta32=0.0, theta16=0.0, stream=None):
     """x = x_P + g_s(c H_W)(I-P) b by restarted GMRES-LR; returns the stats dict."""

@@ -589,6 +589,7 @@ struct MsProblem {
     std::vector<char> slot_f32;   // precision of each stored slot
     int temp_iter = -1;
     std::unique_ptr<DevMem> xp64, xp32;  // per-shift vectors after leaving the stored-basis form
+    std::unique_ptr<DevMem> defl_coef;   // m coefficients L^H v of the deflation projection
     OpSpec opA, opAh;
     double ynorm = 0.0;
     int phase = 0, launched = 0, reliable_updates = 0;
@@ -645,6 +646,7 @@ class MultishiftBatch {
     bool ensure_slots(MsProblem &p, int upto);
     void flush(MsProblem &p);
     void reliable_update(MsProblem &p);
+    void project_out(MsProblem &p, void *v);
     void switch_to_f32(MsProblem &p);
     void to_explicit(MsProblem &p);
     void lift(MsProblem &p, const std::vector<z64> &coef, void *out, bool accumulate);
@@ -790,7 +792,11 @@ void MultishiftBatch::setup(MsProblem &p)
     h0.h.tol = o_.tol;
     h0.h.delta = o_.delta > 0 ? o_.delta : 0.1;
     h0.h.theta32 = mixed_ ? (o_.theta32 > 0 ? o_.theta32 : 1e-3) : 0.0;
-    h0.h.theta16 = (o_.prec == SGN_PREC_F32_H16) ? (o_.theta16 > 0 ? o_.theta16 : 1e-6) : 0.0;
+    // FP16 links perturb the operator by ~1e-3 relative, so its Krylov vectors leave range(I - P)
+    // at that rate and excite the deflated modes, which the bi-Lanczos process never reduces:
+    // with LR deflation the schedule stops at FP32
+    const bool deflated = p.pb->defl && p.pb->defl->m > 0;
+    h0.h.theta16 = (o_.prec == SGN_PREC_F32_H16 && !deflated) ? (o_.theta16 > 0 ? o_.theta16 : 1e-6) : 0.0;
     h0.h.maxiter = maxiter_;
     h0.h.nshift = ns_;
     h0.h.seed = seed_;
@@ -1011,10 +1017,29 @@ void MultishiftBatch::flush(MsProblem &p)
                        p.Xlo.as<float4>(), p.explicit_mode ? ns_ : 1, (int)p.Sst);
 }
 
+// v = (I - P) v for an FP64 vector in the internal layout (canonical round trip),
+// P = R L^H the LR-deflation projector of the problem; no-op without deflation.
+void MultishiftBatch::project_out(MsProblem &p, void *v)
+{
+    const sgn_deflation *defl = p.pb->defl;
+    if (!defl || defl->m <= 0) return;
+    if (!p.defl_coef) p.defl_coef = std::make_unique<DevMem>(sizeof(z64) * defl->m);
+    unpack_spinor(*p.lat, v, p.rcan.p, SGN_PREC_F64, s_);
+    deflate_dots(defl->L, defl->m, p.rcan.p, p.nc, p.defl_coef->as<z64>(), *ctx_, s_);
+    deflate_combine(p.rcan.p, {1.0, 0.0}, {-1.0, 0.0}, defl->R, defl->m, p.defl_coef->as<z64>(), nullptr, p.nc, s_);
+    pack_spinor(*p.lat, p.rcan.p, v, SGN_PREC_F64, s_);
+}
+
 void MultishiftBatch::reliable_update(MsProblem &p)
 {
     flush(p);
     double2 *xs = p.X.as<double2>() + (p.explicit_mode ? (size_t)seed_ * p.n : 0);
+    // the exact solution lies in range(I - P) (y does and P commutes with A); the
+    // reduced-precision iterations leave rounding components along the deflated
+    // eigenvectors that the bi-Lanczos process never reduces (its shadow space is
+    // orthogonal to them), so they are removed here, the projection step of the
+    // restarted methods applied at every true-residual recomputation
+    project_out(p, xs);
     dslash_launch(*p.lat, SGN_PREC_F64, p.opA, xs, p.tmp.p, Epilogue{}, s_);
     Epilogue ep;
     ep.a = -c2_;
@@ -1167,6 +1192,7 @@ void MultishiftBatch::finish(MsProblem &p)
             scale64({rf_.omega[seed_], 0.0}, p.X.p, p.tmp.p, p.n, s_);
             lift(p, d, p.tmp.p, true);
         }
+        project_out(p, p.tmp.p);  // rounding components along the deflated eigenvectors
         unpack_spinor(lat, p.tmp.p, p.rcan.p, SGN_PREC_F64, s_);
         axpby64({1.0, 0.0}, p.rcan.p, {1.0, 0.0}, p.pb->x, p.nc, s_);
     }

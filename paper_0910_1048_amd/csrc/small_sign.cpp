@@ -207,4 +207,73 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
     return 0;
 }
 
+int small_eig(int n, const std::complex<double> *a, std::complex<double> *lam, std::complex<double> *vec)
+{
+    if (n <= 0) return 1;
+    Mat H(n), Z(n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) H(i, j) = a[(size_t)i * n + j];
+    for (int i = 0; i < n; ++i) Z(i, i) = 1.0;
+    // Householder reduction to upper Hessenberg form, H = Z^H A Z
+    for (int k = 0; k + 2 < n; ++k) {
+        double xn = 0.0;
+        for (int i = k + 1; i < n; ++i) xn += std::norm(H(i, k));
+        xn = std::sqrt(xn);
+        if (xn == 0.0) continue;
+        const zc x0 = H(k + 1, k);
+        const zc ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : zc(1.0, 0.0);
+        std::vector<zc> v(n, zc(0, 0));
+        for (int i = k + 1; i < n; ++i) v[i] = H(i, k);
+        v[k + 1] += ph * xn;  // v = x + e^{i arg x0} ||x|| e_1: no cancellation
+        double vn = 0.0;
+        for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
+        vn = std::sqrt(vn);
+        for (int i = k + 1; i < n; ++i) v[i] /= vn;
+        for (int j = 0; j < n; ++j) {  // H = (I - 2 v v^H) H
+            zc d = 0.0;
+            for (int i = k + 1; i < n; ++i) d += std::conj(v[i]) * H(i, j);
+            for (int i = k + 1; i < n; ++i) H(i, j) -= 2.0 * v[i] * d;
+        }
+        for (int i = 0; i < n; ++i) {  // H = H (I - 2 v v^H), Z = Z (I - 2 v v^H)
+            zc d = 0.0, e = 0.0;
+            for (int j = k + 1; j < n; ++j) {
+                d += H(i, j) * v[j];
+                e += Z(i, j) * v[j];
+            }
+            for (int j = k + 1; j < n; ++j) {
+                H(i, j) -= 2.0 * d * std::conj(v[j]);
+                Z(i, j) -= 2.0 * e * std::conj(v[j]);
+            }
+        }
+        for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
+    }
+    if (!hessenberg_schur(H, Z)) return 2;
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i; j < n; ++j) tnorm = std::max(tnorm, std::abs(H(i, j)));
+    const double smin = std::max(std::numeric_limits<double>::epsilon() * tnorm, std::numeric_limits<double>::min());
+    for (int i = 0; i < n; ++i) {
+        lam[i] = H(i, i);
+        // eigenvector of the triangular factor, X(i) = 1, back substitution above it
+        std::vector<zc> x(n, zc(0, 0));
+        x[i] = 1.0;
+        for (int j = i - 1; j >= 0; --j) {
+            zc acc = 0.0;
+            for (int l = j + 1; l <= i; ++l) acc += H(j, l) * x[l];
+            zc den = H(j, j) - lam[i];
+            if (std::abs(den) < smin) den = smin;
+            x[j] = -acc / den;
+        }
+        double nrm = 0.0;
+        std::vector<zc> u(n, zc(0, 0));
+        for (int r = 0; r < n; ++r) {
+            for (int l = 0; l <= i; ++l) u[r] += Z(r, l) * x[l];
+            nrm += std::norm(u[r]);
+        }
+        nrm = std::sqrt(nrm);
+        for (int r = 0; r < n; ++r) vec[(size_t)r * n + i] = u[r] / nrm;
+    }
+    return 0;
+}
+
 }  // namespace sgn

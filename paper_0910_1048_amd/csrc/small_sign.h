@@ -17,4 +17,11 @@ struct SmallSignInfo {
 int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<double> *sub,
                   const std::complex<double> *sup, std::complex<double> *y, SmallSignInfo *info);
 
+// Eigenvalues and unit-norm right eigenvectors of a general complex n x n matrix
+// a (row-major): Householder reduction to Hessenberg form, the complex Schur
+// form by the same QR sweeps, eigenvectors of the triangular factor by back
+// substitution.  vec (row-major n x n) receives the eigenvector of lam[i] in
+// column i.  Returns 0, 1 for a bad size, 2 if the QR iteration did not converge.
+int small_eig(int n, const std::complex<double> *a, std::complex<double> *lam, std::complex<double> *vec);
+
 }  // namespace sgn

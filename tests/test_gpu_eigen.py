@@ -1,0 +1,144 @@
+"""Parity of the HIP critical-eigenpair solver (sgn_critical_eigenpairs) with the
+oracle's dense eigendecomposition, and the eigenpairs it finds used for LR
+deflation end to end."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import WilsonRef, eigen, rational
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_0910_1048_amd as sgn  # noqa: E402
+from gpu_util import dev, host, lattice  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _eig(lat, mu, m, **kw):
+    n = 12 * lat.V
+    L = torch.empty((m, n), dtype=torch.complex128, device="cuda")
+    R = torch.empty_like(L)
+    lam, alpha, st = sgn.sgn_critical_eigenpairs(lat, mu, m, L, R, **kw)
+    return L, R, np.array(lam), alpha, st
+
+
+def _projections(L, R, lam, b):
+    Lh, Rh = host(L), host(R)
+    c = Lh.conj() @ b
+    return Rh.T @ c, Rh.T @ (np.sign(lam.real) * c), Lh.conj() @ Rh.T
+
+
+def test_small_lattice_against_oracle():
+    dims, mu, m = (2, 2, 2, 4), 0.3, 8
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    H = WilsonRef(U, dims, 0.2).dense(mu)
+    Lo, Ro, lo = eigen.critical_eigenpairs(H, m)
+    L, R, lam, alpha, st = _eig(lattice(U, dims), mu, m, tol=1e-12)
+    Pb, xP, LR = _projections(L, R, lam, b)
+    print(f"2x2x2x4 m={m}: eigenvalue error {np.abs(lam - lo).max():.1e}, residual {st['residual']:.1e}, "
+          f"{st['restarts']} restarts, {st['matvecs']} matvecs", flush=True)
+    assert np.abs(lam - lo).max() < 1e-10
+    assert np.abs(LR - np.eye(m)).max() < 1e-10
+    assert _rel(Pb, eigen.projector_apply(Lo, Ro, b)) < 1e-9
+    assert _rel(xP, Ro @ (np.sign(lo.real) * (Lo.conj().T @ b))) < 1e-9
+    assert st["residual"] < 1e-9
+    assert np.allclose(np.linalg.norm(host(R), axis=1), 1.0)
+
+
+def test_c1_against_stored_deflation():
+    """4^4, the 15 critical eigenpairs against the stored dense ones; alpha estimate."""
+    dims, mu, m = (4, 4, 4, 4), 0.3, 15
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    d = np.load(os.path.join(GOLD, "c1_deflation.npz"))
+    L, R, lam, alpha, st = _eig(lattice(U, dims), mu, m, tol=1e-12)
+    Pb, xP, LR = _projections(L, R, lam, b)
+    print(f"C1 m={m}: eigenvalue error {np.abs(lam - d['lam']).max():.1e}, P b {_rel(Pb, d['Pb']):.1e}, "
+          f"x_P {_rel(xP, d['xP']):.1e}, alpha {alpha:.4f} (rest {float(d['alpha_rest']):.4f}), "
+          f"{st['restarts']} restarts, {st['matvecs']} matvecs, {st['total_ms']:.0f} ms", flush=True)
+    assert np.abs(lam - d["lam"]).max() < 1e-10
+    assert np.abs(LR - np.eye(m)).max() < 1e-10
+    assert _rel(Pb, d["Pb"]) < 1e-9
+    assert _rel(xP, d["xP"]) < 1e-9
+    assert float(d["alpha_rest"]) <= alpha * (1 + 1e-6)
+
+
+def test_c1_deflated_sign_with_found_eigenpairs():
+    """Eigensolver -> LR deflation -> multishift sign, against the stored dense sign(H) b;
+    the pole count from Eq. (no_of_poles) for the deflated spectrum."""
+    dims, mu, m = (4, 4, 4, 4), 0.3, 15
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(os.path.join(GOLD, "c1_dense.npz"))
+    lat = lattice(U, dims)
+    L, R, lam, alpha, _ = _eig(lat, mu, m, tol=1e-12)
+    s = sgn.sgn_poles_needed(alpha, float(g["beta"]), 1e-11)
+    rf = sgn.sgn_rational_neuberger(s, alpha, float(g["beta"]))
+    defl = sgn.Deflation(L, R, lam)
+    bd = dev(b)
+    x = torch.empty_like(bd)
+    for prec, tol in ((sgn.F64, 1e-11), (sgn.F32_H16, 1e-10)):
+        st = sgn.multishift_solve(sgn.Problem(lat, mu, bd, x, defl), rf, tol=tol, prec=prec)[0]
+        e = _rel(host(x), g["sign_b"])
+        print(f"C1 deflated sign prec={prec}: {s} poles (alpha {alpha:.4f}), {st['iterations']} iterations, "
+              f"vs dense sign {e:.1e}", flush=True)
+        assert e < 1e-9
+
+
+def test_hermitian_case_left_equals_right():
+    dims, m = (2, 2, 2, 4), 6
+    U = synth.gauge_field(dims, 0.5, 1)
+    H = WilsonRef(U, dims, 0.2).dense(0.0)
+    ev = np.linalg.eigvalsh(H)
+    L, R, lam, _, st = _eig(lattice(U, dims), 0.0, m, tol=1e-12)
+    want = ev[np.argsort(np.abs(ev))[:m]]
+    assert np.abs(lam.imag).max() < 1e-12
+    assert np.allclose(np.sort(lam.real), np.sort(want), atol=1e-11)
+    assert np.abs(host(L) - host(R)).max() < 1e-9
+
+
+def test_8x4_properties():
+    """8^4 (n = 49152, beyond the dense oracle): residuals, biorthonormality,
+    eigenvalues that the Rayleigh quotients of the oracle's operator reproduce."""
+    dims, mu, m = (8, 8, 8, 8), 0.2, 4
+    U = synth.gauge_field(dims, 0.4, 0)
+    W = WilsonRef(U, dims, 0.2)
+    L, R, lam, alpha, st = _eig(lattice(U, dims), mu, m, tol=1e-10, max_restarts=400)
+    Lh, Rh = host(L), host(R)
+    print(f"8^4 m={m}: lambda {np.round(lam, 5)}, residual {st['residual']:.1e}, {st['restarts']} restarts, "
+          f"{st['matvecs']} matvecs, {st['total_ms']:.0f} ms", flush=True)
+    assert np.abs(Lh.conj() @ Rh.T - np.eye(m)).max() < 1e-9
+    for i in range(m):
+        HR = W.apply(Rh[i], mu)
+        assert np.linalg.norm(HR - lam[i] * Rh[i]) < 1e-7 * abs(lam[i])
+        assert np.vdot(Lh[i], HR) == pytest.approx(lam[i], rel=1e-9)
+    assert np.all(np.abs(lam.real) <= alpha)
+
+
+def test_eigen_error_paths():
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    lat = lattice(U, dims)
+    with pytest.raises(sgn.SgnError) as e:
+        _eig(lat, 0.3, 0)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _eig(lat, 0.3, 4, nev=4)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _eig(lat, 0.3, 4, kmax=2000)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _eig(lat, 0.3, 8, tol=1e-14, max_restarts=1)
+    assert e.value.status == 5
