@@ -276,6 +276,95 @@ def gmres_rational(A, b, omega, sigma, c, kmax, tol=1e-12, max_cycles=1000,
     return x
 
 
+def multishift_bicgstab(A, b, omega, sigma, c, tol=1e-12, maxiter=20000,
+                        L=None, R=None, lam=None, return_info=False):
+    """Multishift BiCGStab for (A' - sigma_i) x_i = y, y = c A (I-P) b (the BiCGStab
+    variant the section "Two-sided Lanczos with rational functions" names next to
+    BiCG); only A is applied, never A^H.
+
+    Seed (shift of smallest modulus, M = A' - sigma_seed), shadow r^_0 = y:
+      v = M p,  alpha = (r^^H r) / (r^^H v),  s = r - alpha v,  t = M s,
+      omega = (t^H s) / (t^H t),  r' = s - omega t,
+      beta = (alpha / omega) (r^^H r') / (r^^H r),  p' = r' + beta (p - omega v)
+    alpha and beta are those of BiCG, so the BiCG factors zeta^i (r^i_BiCG = zeta^i r_BiCG,
+    same recurrence as in multishift_bicg) carry over; the stabilising factor
+    1 - omega M becomes 1 - omega^i (M + tau_i) with omega^i = omega / (1 + omega tau_i) up to
+    the scalar pi^i = prod (1 + omega tau_i).  With the seed's r, s:
+      r^i = zeta^i r / pi^i,  s^i = zeta^i_next s / pi^i,
+      x^i += alpha^i p^i + omega^i s^i,
+      p^i' = r^i' + beta^i (p^i - (omega^i / alpha^i)(r^i - s^i))
+    (M_i p^i = (r^i - s^i) / alpha^i), alpha^i = alpha zeta_next / zeta,
+    beta^i = beta (zeta_next / zeta)^2.  Converged when every |zeta^i / pi^i| ||r|| <= tol ||y||."""
+    b = np.asarray(b, dtype=np.complex128).ravel()
+    omega = np.asarray(omega, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    c2 = c * c
+    seed = int(np.argmin(np.abs(sigma)))
+    s0 = sigma[seed]
+    M = lambda v: c2 * A(A(v)) - s0 * v
+    y = c * A(project_out(L, R, b))
+    ynorm = np.linalg.norm(y)
+    ns = len(sigma)
+    tau = s0 - sigma
+    X = np.zeros((ns, b.size), dtype=np.complex128)
+    P = np.tile(y, (ns, 1))
+    r = y.copy()
+    rh = y.copy()
+    zeta = np.ones(ns, dtype=np.complex128)
+    zeta_prev = np.ones(ns, dtype=np.complex128)
+    pi = np.ones(ns, dtype=np.complex128)
+    alpha_prev, beta_prev = 1.0 + 0j, 0.0 + 0j
+    rho = np.vdot(rh, r)
+    active = np.ones(ns, dtype=bool)
+    it = 0
+    while it < maxiter and ynorm > 0:
+        p = P[seed]
+        v = M(p)
+        den = np.vdot(rh, v)
+        if den == 0 or rho == 0:
+            raise Breakdown("BiCGStab breakdown")
+        alpha = rho / den
+        zeta_next = zeta.copy()
+        for i in range(ns):
+            if active[i]:
+                z, zp = zeta[i], zeta_prev[i]
+                denom = alpha_prev * (1.0 + tau[i] * alpha) * zp + alpha * beta_prev * (zp - z)
+                zeta_next[i] = z * zp * alpha_prev / denom
+        s_ = r - alpha * v
+        t = M(s_)
+        tt = np.vdot(t, t)
+        om = np.vdot(t, s_) / tt if tt != 0 else 0.0
+        r_new = s_ - om * t
+        rho_new = np.vdot(rh, r_new)
+        beta = (alpha / om) * (rho_new / rho) if om != 0 else 0.0
+        pi_next = pi.copy()
+        for i in range(ns):
+            if not active[i]:
+                continue
+            ai = alpha * zeta_next[i] / zeta[i]
+            bi = beta * (zeta_next[i] / zeta[i]) ** 2
+            oi = om / (1.0 + om * tau[i])
+            pi_next[i] = pi[i] * (1.0 + om * tau[i])
+            ri = zeta[i] / pi[i] * r
+            si = zeta_next[i] / pi[i] * s_
+            X[i] += ai * P[i] + oi * si
+            P[i] = zeta_next[i] / pi_next[i] * r_new + bi * (P[i] - (oi / ai) * (ri - si))
+        zeta_prev, zeta, pi = zeta, zeta_next, pi_next
+        alpha_prev, beta_prev, rho = alpha, beta, rho_new
+        r = r_new
+        it += 1
+        res = np.abs(zeta / pi) * np.linalg.norm(r)
+        done = res <= tol * ynorm
+        if done.all() or om == 0:
+            break
+        active = ~done
+        active[seed] = True
+    x = deflation_xP(L, R, lam, b) + omega @ X
+    if return_info:
+        return x, dict(iterations=it, X=X, y=y, seed=seed, res=np.abs(zeta / pi) * np.linalg.norm(r) / ynorm)
+    return x
+
+
 def multishift_bicg(A, Ah, b, omega, sigma, c, tol=1e-12, maxiter=20000,
                     L=None, R=None, lam=None, return_info=False):
     """BiCG-LR(m): multishift BiCG for (A' - sigma_i) x_i = y, y = c A (I-P) b.

@@ -291,3 +291,45 @@ def test_deflated_gmres_rational():
     target = krylov.deflation_xP(L, R, lam, b) + dense.rational_dense(H, krylov.project_out(L, R, b), om, sg, c)
     xg = krylov.gmres_rational(A, b, om, sg, c, 15, tol=1e-13, L=L, R=R, lam=lam)
     assert rel(xg, target) < 1e-10
+
+
+def test_multishift_bicgstab_shifted_iterates_solve_their_systems(rng):
+    """Multishift BiCGStab: every shifted iterate solves its own system (true residual,
+    not the collinear estimate), the result equals the dense rational target, and the
+    reported shifted residuals are the true ones."""
+    n = 40
+    A = _small_nonhermitian(rng, n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    om, sg, c = rational.coefficients(8, 0.5, 2.1)
+    x, info = krylov.multishift_bicgstab(lambda v: A @ v, b, om, sg, c, tol=1e-12, return_info=True)
+    want = dense.rational_dense(A, b, om, sg, c)
+    assert rel(x, want) < 1e-9
+    Ap = c * c * (A @ A)
+    y = info["y"]
+    for i, s in enumerate(sg):
+        ri = y - (Ap - s * np.eye(n)) @ info["X"][i]
+        assert np.linalg.norm(ri) <= 1e-10 * np.linalg.norm(y)
+    # stopped early: the seed's collinear estimate is its true residual, and every frozen
+    # shift stopped below the tolerance
+    x2, info2 = krylov.multishift_bicgstab(lambda v: A @ v, b, om, sg, c, tol=1e-4, return_info=True)
+    for i, s in enumerate(sg):
+        ri = np.linalg.norm(y - (Ap - s * np.eye(n)) @ info2["X"][i]) / np.linalg.norm(y)
+        assert ri <= 1.0001e-4
+        if i == info2["seed"]:
+            assert ri == pytest.approx(info2["res"][i], rel=1e-6)
+
+
+def test_deflated_multishift_bicgstab():
+    dims = (2, 2, 2, 4)
+    W_ = WilsonRef(synth.gauge_field(dims, 0.5, 0), dims, 0.2)
+    mu = 0.3
+    H = W_.dense(mu)
+    b = synth.gaussian_source(dims, 0).ravel()
+    L, R, lam = _lattice_deflation(H, 8)
+    ev = np.linalg.eigvals(H)
+    alpha = np.min(np.abs(np.setdiff1d(ev, lam)))
+    beta = np.max(np.abs(ev))
+    om, sg, c = rational.coefficients(12, alpha, beta)
+    target = krylov.deflation_xP(L, R, lam, b) + dense.rational_dense(H, krylov.project_out(L, R, b), om, sg, c)
+    x = krylov.multishift_bicgstab(lambda v: W_.apply(v, mu), b, om, sg, c, tol=1e-12, L=L, R=R, lam=lam)
+    assert rel(x, target) < 1e-9
