@@ -338,6 +338,21 @@ typedef struct {
 sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                             sgn_stats *stats, void *stream);
 
+/* Multishift BiCGStab (the BiCGStab variant named beside BiCG-LR in the section
+ * "Two-sided Lanczos with rational functions"): the same problems, rational
+ * function and result as multishift_solve, but every iteration applies
+ * c^2 H_W(mu)^2 - sigma_seed twice (to p and to s = r - alpha v) and never the
+ * adjoint.  Seed: the shift of smallest modulus, shadow y; the other shifts reuse
+ * BiCG's collinearity factors times the stabilising factors prod (1 + omega tau_i);
+ * p_i and x_i are kept for every shift.  FP64 only (o->prec must be SGN_PREC_F64;
+ * theta32, theta16, delta, poll, basis_slots and graph are ignored); the scalars
+ * are formed on the host, three synchronisations per iteration.  stats: iterations,
+ * matvecs, shift_residual (collinear estimates), residual.  Problems run one after
+ * another.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter (x holds
+ * the last iterate), SGN_ERR_BREAKDOWN if r^^H r or r^^H v vanishes. */
+sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
+                               sgn_stats *stats, void *stream);
+
 /* ------------------------------------------------------------------ accuracy measure */
 /* Accuracy of an approximate sign function S (numerical-results section): as
  * sign(A)^2 = I, the value 1/2 ||S(S b) - b|| / ||b|| estimates the error of S

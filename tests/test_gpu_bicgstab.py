@@ -1,0 +1,116 @@
+"""Parity of the HIP multishift BiCGStab (multishift_bicgstab) with the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import WilsonRef, dense, krylov, rational
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_0910_1048_amd as sgn  # noqa: E402
+from gpu_util import dev, host, lattice  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_dense.npz")
+
+
+def _rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _solve(lat, mu, b, rf, defl=None, want_shifts=False, **kw):
+    bd = dev(b)
+    x = torch.empty_like(bd)
+    xs = [torch.empty_like(bd) for _ in range(rf.s)] if want_shifts else None
+    st = sgn.multishift_bicgstab(sgn.Problem(lat, mu, bd, x, defl, xs), rf, **kw)[0]
+    if want_shifts:
+        return host(x).ravel(), st, [host(t).ravel() for t in xs]
+    return host(x).ravel(), st
+
+
+def test_c1_bicgstab_matches_dense_rational():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    lat = lattice(U, dims)
+    x, st = _solve(lat, 0.3, b, rf, tol=1e-11)
+    e = _rel(x, g["g16_b"])
+    bd = dev(b)
+    xb = torch.empty_like(bd)
+    sb = sgn.multishift_solve(sgn.Problem(lat, 0.3, bd, xb), rf, tol=1e-11)[0]
+    print(f"C1 BiCGStab: vs dense g16 {e:.2e}, {st['iterations']} iterations ({st['matvecs']} matvecs); "
+          f"BiCG {sb['iterations']} iterations, BiCGStab vs BiCG {_rel(x, host(xb)):.1e}", flush=True)
+    assert e < 1e-8
+    assert _rel(x, host(xb)) < 1e-8
+
+
+def test_8x4_bicgstab_against_oracle():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(16, 0.15, 2.6)
+    rf = sgn.sgn_rational_neuberger(16, 0.15, 2.6)
+    x, st = _solve(lattice(U, dims), 0.2, b, rf, tol=1e-11)
+    xo, info = krylov.multishift_bicgstab(lambda v: W.apply(v, 0.2), b, om, sg, c, tol=1e-11, return_info=True)
+    e = _rel(x, xo)
+    print(f"8^4 BiCGStab: vs oracle {e:.2e}, {st['iterations']} iterations (oracle {info['iterations']}), "
+          f"{st['krylov_ms']:.1f} ms", flush=True)
+    assert e < 1e-8
+    assert abs(st["iterations"] - info["iterations"]) <= 2
+
+
+def test_bicgstab_shift_solutions_match_oracle():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 2)
+    b = synth.gaussian_source(dims, 2).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(10, 0.2, 2.4)
+    rf = sgn.sgn_rational_neuberger(10, 0.2, 2.4)
+    _, st, xs = _solve(lattice(U, dims), 0.25, b, rf, want_shifts=True, tol=1e-11)
+    _, info = krylov.multishift_bicgstab(lambda v: W.apply(v, 0.25), b, om, sg, c, tol=1e-11, return_info=True)
+    worst = max(_rel(xs[i], info["X"][i]) for i in range(10))
+    print(f"BiCGStab per-shift solutions vs oracle: worst {worst:.1e}", flush=True)
+    assert worst < 1e-8
+
+
+def test_deflated_bicgstab_against_dense():
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    H = WilsonRef(U, dims, 0.2).dense(0.3)
+    lam, R = np.linalg.eig(H)
+    Linv = np.linalg.inv(R)
+    idx = np.argsort(np.abs(lam.real))[:8]
+    Lr, Rr, lm = Linv[idx].conj(), R[:, idx].T.copy(), lam[idx]
+    rest = np.delete(lam, idx)
+    alpha, beta = float(np.abs(rest).min()), float(np.abs(lam).max())
+    om, sg, c = rational.coefficients(12, alpha, beta)
+    rf = sgn.sgn_rational_neuberger(12, alpha, beta)
+    defl = sgn.Deflation(dev(Lr), dev(Rr), lm)
+    x, _ = _solve(lattice(U, dims), 0.3, b, rf, defl=defl, tol=1e-12)
+    target = krylov.deflation_xP(Lr.T, Rr.T, lm, b) + dense.rational_dense(H, krylov.project_out(Lr.T, Rr.T, b),
+                                                                             om, sg, c)
+    assert _rel(x, target) < 1e-9
+
+
+def test_bicgstab_zero_source_and_errors():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    lat = lattice(U, dims)
+    rf = sgn.sgn_rational_neuberger(8, 0.2, 2.4)
+    x, st = _solve(lat, 0.3, np.zeros_like(b), rf)
+    assert np.all(x == 0) and st["iterations"] == 0
+    with pytest.raises(sgn.SgnError) as e:
+        _solve(lat, 0.3, b, rf, tol=1e-11, maxiter=3)
+    assert e.value.status == 5
+    with pytest.raises(sgn.SgnError) as e:
+        _solve(lat, 0.3, b, rf, prec=sgn.F32)
+    assert e.value.status == 1
