@@ -343,13 +343,20 @@ sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational
  * function and result as multishift_solve, but every iteration applies
  * c^2 H_W(mu)^2 - sigma_seed twice (to p and to s = r - alpha v) and never the
  * adjoint.  Seed: the shift of smallest modulus, shadow y; the other shifts reuse
- * BiCG's collinearity factors times the stabilising factors prod (1 + omega tau_i);
- * p_i and x_i are kept for every shift.  FP64 only (o->prec must be SGN_PREC_F64;
- * theta32, theta16, delta, poll, basis_slots and graph are ignored); the scalars
- * are formed on the host, three synchronisations per iteration.  stats: iterations,
- * matvecs, shift_residual (collinear estimates), residual.  Problems run one after
- * another.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter (x holds
- * the last iterate), SGN_ERR_BREAKDOWN if r^^H r or r^^H v vanishes. */
+ * BiCG's collinearity factors times the stabilising factors prod (1 + omega tau_i).
+ * Default form: the seed's r_k and s_k are stored (two vectors per iteration, in
+ * the iteration's precision) and sum_{i != seed} omega_i x_i is one lift at the end;
+ * scalars stay on the device, the iterations between two polls (o->poll, default 4)
+ * are captured once as a HIP graph (o->graph < 0: plain launches), and o->prec,
+ * theta32, theta16 and delta give the mixed schedule of multishift_solve (FP64 ->
+ * FP32 -> FP16 links, FP64 reliable updates of the seed; FP32 at most with
+ * deflation).  If x_shift is set or o->basis_slots < 0, every shift keeps p_i, x_i
+ * instead (FP64 only, scalars on the host, three synchronisations per iteration).
+ * o->basis_slots > 0 caps the stored vectors (SGN_ERR_NOMEM beyond it; 0: up to half
+ * of the free memory).  o->verify is ignored.  stats: iterations, matvecs,
+ * reliable_updates, shift_residual (collinear estimates), residual.  Problems run
+ * one after another.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter
+ * (x holds the last iterate), SGN_ERR_BREAKDOWN if r^^H r or r^^H v vanishes. */
 sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                                sgn_stats *stats, void *stream);
 
@@ -374,9 +381,10 @@ typedef enum {
     SGN_K_STENCIL_F32 = 1,
     SGN_K_STENCIL_H16 = 2,
     SGN_K_SHIFT_UPDATE = 3,   /* multishift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i (seed only
-                                 when the basis is stored) */
-    SGN_K_SEED_UPDATE = 4,    /* multishift: r, r~ updates with their inner products */
-    SGN_K_LIFT = 5,           /* multishift: sum of the stored residuals with their coefficients */
+                                 when the basis is stored); BiCGStab: the seed's x and p */
+    SGN_K_SEED_UPDATE = 4,    /* multishift: r, r~ updates with their inner products; BiCGStab: s = r -
+                                 alpha v, the t^H s, t^H t dots, r' = s - omega t with its dots */
+    SGN_K_LIFT = 5,           /* multishift: sum of the stored vectors with their coefficients */
     SGN_K_COUNT = 6
 } sgn_kernel_class;
 

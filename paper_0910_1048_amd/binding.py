@@ -316,8 +316,10 @@ def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, the
 lib.multishift_bicgstab.argtypes = lib.multishift_solve.argtypes
 
 
-def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, stream=None):
-    """Multishift BiCGStab (FP64 only) for every problem; returns one stats dict per problem."""
+def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
+                        delta=0.0, poll=0, basis_slots=0, graph=True, stream=None):
+    """Multishift BiCGStab for every problem (stored basis and the mixed schedule unless the
+    per-shift solutions are requested, which is FP64 only); one stats dict per problem."""
     if isinstance(problems, Problem):
         problems = [problems]
     n = len(problems)
@@ -334,7 +336,8 @@ def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, 
             xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
             keep.append(xs)
             arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
-    o = MsOpts(float(tol), int(maxiter), int(prec), 0.0, 0.0, 0.0, 0, 0, 0, 0)
+    o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll), 0,
+               int(basis_slots), 0 if graph else -1)
     st = (Stats * max(n, 1))()
     check(lib.multishift_bicgstab(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_bicgstab")
     return [st[i].as_dict() for i in range(n)]

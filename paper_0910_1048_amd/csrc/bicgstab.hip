@@ -13,10 +13,21 @@
 // omega tau_i).  With r_i = zeta_i r / pi_i and s_i = zeta_i' s / pi_i:
 //   x_i += alpha_i p_i + omega_i s_i,
 //   p_i' = r_i' + beta_i (p_i - (omega_i / alpha_i)(r_i - s_i)),
-// alpha_i = alpha zeta_i' / zeta_i, beta_i = beta (zeta_i' / zeta_i)^2; every shift's
-// p_i and x_i are kept (one pass over all of them per iteration).  FP64; the
-// scalars are formed on the host from deterministic block partial sums, three
-// synchronisations per iteration.
+// alpha_i = alpha zeta_i' / zeta_i, beta_i = beta (zeta_i' / zeta_i)^2.
+//
+// Two forms of the same iteration:
+//  * stored basis (default): the seed's r_k and s_k are kept in slots, the seed
+//    keeps p and x, and the non-seed p_i, x_i are linear combinations of the
+//    slots whose coefficients follow from the recorded alpha, omega, beta; the
+//    omega-weighted sum of the non-seed solutions is one lift at the end.  All
+//    scalars stay on the device (one-block kernels), the iterations between two
+//    host polls are captured once as a HIP graph, and the mixed schedule of the
+//    BiCG solver applies (FP64 while the seed residual is above theta32, then
+//    FP32 vectors and stencil, FP16 links below theta16, FP64 reliable updates
+//    of the seed);
+//  * per-shift vectors (when the x_i are requested): FP64, every shift's p_i and
+//    x_i updated each iteration, scalars formed on the host from deterministic
+//    block partial sums, three synchronisations per iteration.
 #include <chrono>
 #include <complex>
 #include <vector>
@@ -173,8 +184,8 @@ zc host_sum1(const z64 *dpart, int nb, hipStream_t s)
     return a;
 }
 
-sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, sgn_stats *stp,
-                     hipStream_t s)
+sgn_status solve_explicit(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, sgn_stats *stp,
+                          hipStream_t s)
 {
     const auto t_start = std::chrono::steady_clock::now();
     SGN_REQUIRE(pb.lat && pb.b && pb.x, "multishift_bicgstab: null problem field");
@@ -362,6 +373,788 @@ sgn_status solve_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms
     return converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
+
+// ----------------------------------------------------------------------------- stored-basis form
+struct BsHead {
+    z64 rho, alpha, omega, beta, alpha_prev, beta_prev;
+    double rnorm, rmax, ynorm, tol, delta, theta32, theta16;
+    int iter, maxiter, done, breakdown, reliable, want_phase, phase, ns, seed, go;
+};
+struct BsState {
+    BsHead h;
+    z64 zeta[kBsShifts], zeta_prev[kBsShifts], zeta_next[kBsShifts], pi[kBsShifts];
+    double tau[kBsShifts];
+    int act[kBsShifts];
+};
+// scalars of iteration k: alpha_k, omega_k, beta_k and ||r_{k+1}||
+struct BsHist {
+    z64 alpha, omega, beta;
+    double rnorm, pad;
+};
+
+__device__ __forceinline__ z64 bs_div(z64 a, z64 b)
+{
+    const double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+__device__ __forceinline__ bool bs_finite(z64 a) { return isfinite(a.r) && isfinite(a.i); }
+
+template <typename R> struct BsVec;
+template <> struct BsVec<double> { using t = double2; };
+template <> struct BsVec<float> { using t = float2; };
+template <typename T> __device__ __forceinline__ z64 ldz(const T *p, int64_t e)
+{
+    const T v = p[e];
+    return {(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void stz(double2 *p, int64_t e, z64 v) { p[e] = make_double2(v.r, v.i); }
+__device__ __forceinline__ void stz(float2 *p, int64_t e, z64 v) { p[e] = make_float2((float)v.r, (float)v.i); }
+
+// alpha = rho / r^^H v from the dotting stencil's partials; the BiCG factors zeta_next
+__global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *part, int nb)
+{
+    if (S->h.done) return;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        re += part[i].r;
+        im += part[i].i;
+    }
+    __shared__ double lds[8];
+    __shared__ int bad;
+    double v[2] = {re, im};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const z64 den = {v[0], v[1]};
+        z64 a = bs_div(S->h.rho, den);
+        bad = 0;
+        if (!(den.r * den.r + den.i * den.i > 0.0) || !bs_finite(a)) {
+            S->h.breakdown = 1;
+            S->h.done = 1;
+            a = {0.0, 0.0};
+            bad = 1;
+        }
+        S->h.alpha = a;
+    }
+    __syncthreads();
+    if (bad) return;
+    const z64 al = S->h.alpha, ap = S->h.alpha_prev, bp = S->h.beta_prev;
+    for (int i = threadIdx.x; i < S->h.ns; i += blockDim.x) {
+        if (!S->act[i]) {
+            S->zeta_next[i] = S->zeta[i];
+            continue;
+        }
+        const z64 z = S->zeta[i], zp = S->zeta_prev[i];
+        const z64 one_tau = {1.0 + S->tau[i] * al.r, S->tau[i] * al.i};
+        S->zeta_next[i] = bs_div(z * zp * ap, ap * one_tau * zp + al * bp * (zp - z));
+    }
+}
+
+// s = r - alpha v, into the work vector and the slot of iteration k
+template <typename R>
+__global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, const typename BsVec<R>::t *r,
+                                                     const typename BsVec<R>::t *v, typename BsVec<R>::t *s,
+                                                     void *const *sslots, int64_t n)
+{
+    using T = typename BsVec<R>::t;
+    if (S->h.done) return;
+    const z64 al = S->h.alpha;
+    T *slot = static_cast<T *>(sslots[S->h.iter]);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const z64 sv = ldz(r, e) - al * ldz(v, e);
+        stz(s, e, sv);
+        stz(slot, e, sv);
+    }
+}
+
+// partials of t^H s and t^H t
+template <typename R>
+__global__ void __launch_bounds__(256) bs_dots_stored(const BsState *S, const typename BsVec<R>::t *t,
+                                                      const typename BsVec<R>::t *s, int64_t n, z64 *part)
+{
+    if (S->h.done) return;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const z64 tv = ldz(t, e), sv = ldz(s, e);
+        const z64 d = cmulc(tv, sv);
+        a += d.r;
+        b += d.i;
+        c += norm2(tv);
+    }
+    __shared__ double lds[12];
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = {v[0], v[1]};
+        part[2 * blockIdx.x + 1] = {v[2], 0.0};
+    }
+}
+
+// omega = t^H s / t^H t (0 when t = 0: s was the exact residual 0)
+__global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *part, int nb)
+{
+    if (S->h.done) return;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += part[2 * i].r;
+        b += part[2 * i].i;
+        c += part[2 * i + 1].r;
+    }
+    __shared__ double lds[12];
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) S->h.omega = v[2] > 0.0 ? z64{v[0] / v[2], v[1] / v[2]} : z64{0.0, 0.0};
+}
+
+// r' = s - omega t, into the work vector and the slot of iteration k + 1; partials of
+// r^^H r' and ||r'||^2 (of the stored values)
+template <typename R>
+__global__ void __launch_bounds__(256) bs_res_stored(const BsState *S, const typename BsVec<R>::t *s,
+                                                     const typename BsVec<R>::t *t, const typename BsVec<R>::t *rh,
+                                                     typename BsVec<R>::t *r, void *const *rslots, int64_t n, z64 *part)
+{
+    using T = typename BsVec<R>::t;
+    if (S->h.done) return;
+    const z64 om = S->h.omega;
+    T *slot = static_cast<T *>(rslots[S->h.iter + 1]);
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 rv = ldz(s, e) - om * ldz(t, e);
+        stz(r, e, rv);
+        stz(slot, e, rv);
+        if constexpr (sizeof(R) == 4) rv = ldz(r, e);
+        const z64 d = cmulc(ldz(rh, e), rv);
+        a += d.r;
+        b += d.i;
+        c += norm2(rv);
+    }
+    __shared__ double lds[12];
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = {v[0], v[1]};
+        part[2 * blockIdx.x + 1] = {v[2], 0.0};
+    }
+}
+
+// beta, the history entry, the shifted residual estimates and the control flags
+__global__ void __launch_bounds__(256) bs_beta_kernel(BsState *S, const z64 *part, int nb, BsHist *hist, int cap)
+{
+    if (S->h.done) {
+        if (threadIdx.x == 0) S->h.go = 0;
+        return;
+    }
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += part[2 * i].r;
+        b += part[2 * i].i;
+        c += part[2 * i + 1].r;
+    }
+    __shared__ double lds[12];
+    __shared__ int any, bad;
+    __shared__ double rn_sh;
+    double v[3] = {a, b, c};
+    block_sum<3>(v, lds);
+    const z64 om = S->h.omega;
+    if (threadIdx.x == 0) {
+        const z64 rho_new = {v[0], v[1]};
+        const double rn = sqrt(v[2]);
+        const z64 al = S->h.alpha;
+        const bool om0 = om.r == 0.0 && om.i == 0.0;
+        z64 be = om0 ? z64{0.0, 0.0} : bs_div(al, om) * bs_div(rho_new, S->h.rho);
+        bad = 0;
+        if (!bs_finite(be) || !isfinite(rn) || (!om0 && !(norm2(S->h.rho) > 0.0))) {
+            S->h.breakdown = 1;
+            S->h.done = 1;
+            be = {0.0, 0.0};
+            bad = 1;
+        }
+        const int k = S->h.iter;
+        if (k < cap) hist[k] = BsHist{al, om, be, rn, 0.0};
+        S->h.go = bad ? 0 : 1;
+        S->h.beta = be;
+        S->h.rho = rho_new;
+        S->h.rnorm = rn;
+        S->h.rmax = fmax(S->h.rmax, rn);
+        S->h.alpha_prev = al;
+        S->h.beta_prev = be;
+        S->h.iter = k + 1;
+        if (S->h.phase >= 1 && rn < S->h.delta * S->h.rmax) S->h.reliable = 1;
+        if (S->h.phase == 0 && rn < S->h.theta32 * S->h.ynorm) S->h.want_phase = 1;
+        if (S->h.phase == 1 && rn < S->h.theta16 * S->h.ynorm) S->h.want_phase = 2;
+        if (om0) S->h.done = 1;  // t = 0: s, and so r', is zero
+        rn_sh = rn;
+        any = 0;
+    }
+    __syncthreads();
+    if (bad) return;
+    const double lim = S->h.tol * S->h.ynorm, rn = rn_sh;
+    for (int i = threadIdx.x; i < S->h.ns; i += blockDim.x) {
+        if (!S->act[i]) continue;
+        S->zeta_prev[i] = S->zeta[i];
+        S->zeta[i] = S->zeta_next[i];
+        const z64 f = {1.0 + om.r * S->tau[i], om.i * S->tau[i]};
+        S->pi[i] = S->pi[i] * f;
+        const double ri = sqrt(norm2(S->zeta[i]) / norm2(S->pi[i])) * rn;
+        if (ri <= lim) {
+            S->act[i] = 0;
+        } else {
+            atomicOr(&any, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (!any) S->h.done = 1;
+        S->act[S->h.seed] = 1;  // the seed drives the recurrence
+        if (S->h.iter >= S->h.maxiter) S->h.done = 1;
+    }
+}
+
+// the seed: x += alpha p + omega s (x in FP64), p = r' + beta (p - omega v)
+__global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, const double2 *v, const double2 *r,
+                                               const double2 *s, double2 *x, int64_t n)
+{
+    if (!S->h.go || S->h.breakdown) return;
+    const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const z64 pv = ldz(p, e), sv = ldz(s, e);
+        stz(x, e, ldz(x, e) + al * pv + om * sv);
+        stz(p, e, ldz(r, e) + be * (pv - om * ldz(v, e)));
+    }
+}
+
+// FP32 vectors in the [6][S] float4 layout (chunk c holds components 2c, 2c+1), x in [12][S] double2
+__global__ void __launch_bounds__(256) bs_xp32(const BsState *S, float4 *p, const float4 *v, const float4 *r,
+                                               const float4 *s, double2 *x, int Sst)
+{
+    if (!S->h.go || S->h.breakdown) return;
+    const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
+    const int64_t np = (int64_t)6 * Sst;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < np; f += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(f / Sst), st = (int)(f - (int64_t)c2 * Sst);
+        const float4 p4 = p[f], s4 = s[f], v4 = v[f], r4 = r[f];
+        const z64 p0 = {p4.x, p4.y}, p1 = {p4.z, p4.w}, s0 = {s4.x, s4.y}, s1 = {s4.z, s4.w};
+        const int64_t e0 = (int64_t)(2 * c2) * Sst + st, e1 = e0 + Sst;
+        stz(x, e0, ldz(x, e0) + al * p0 + om * s0);
+        stz(x, e1, ldz(x, e1) + al * p1 + om * s1);
+        const z64 q0 = z64{r4.x, r4.y} + be * (p0 - om * z64{v4.x, v4.y});
+        const z64 q1 = z64{r4.z, r4.w} + be * (p1 - om * z64{v4.z, v4.w});
+        p[f] = make_float4((float)q0.r, (float)q0.i, (float)q1.r, (float)q1.i);
+    }
+}
+
+// out (+)= sum_j coef_j slot_j (FP64 or FP32 slots; out in the FP64 layout)
+constexpr int kBsLiftChunk = 256;
+struct BsSlot {
+    const void *p;
+    int f32;
+    int pad;
+};
+__global__ void __launch_bounds__(256) bs_lift_kernel(const BsSlot *slots, const z64 *coef, int K, int Sst,
+                                                      double2 *out)
+{
+    __shared__ BsSlot sl[kBsLiftChunk];
+    __shared__ z64 cf[kBsLiftChunk];
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        sl[j] = slots[j];
+        cf[j] = coef[j];
+    }
+    __syncthreads();
+    const int64_t np = (int64_t)6 * Sst;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < np; f += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(f / Sst), st = (int)(f - (int64_t)c2 * Sst);
+        const int64_t e0 = (int64_t)(2 * c2) * Sst + st, e1 = e0 + Sst;
+        z64 a0 = ldz(out, e0), a1 = ldz(out, e1);
+        for (int j = 0; j < K; ++j) {
+            const z64 c = cf[j];
+            if (c.r == 0.0 && c.i == 0.0) continue;  // uniform
+            z64 v0, v1;
+            if (sl[j].f32) {
+                const float4 t = static_cast<const float4 *>(sl[j].p)[f];
+                v0 = {(double)t.x, (double)t.y};
+                v1 = {(double)t.z, (double)t.w};
+            } else {
+                const double2 *q = static_cast<const double2 *>(sl[j].p);
+                v0 = ldz(q, e0);
+                v1 = ldz(q, e1);
+            }
+            a0 = a0 + c * v0;
+            a1 = a1 + c * v1;
+        }
+        stz(out, e0, a0);
+        stz(out, e1, a1);
+    }
+}
+
+// q = -c^2 A A x + sigma x  (for the reliable update r = y + q)
+__global__ void __launch_bounds__(256) bs_addto64(const double2 *y, double2 *q, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        stz(q, e, ldz(y, e) + ldz(q, e));
+}
+
+class BsStored {
+  public:
+    BsStored(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s)
+        : pb_(pb), rf_(rf), o_(o), s_(s), lat_(*as_lattice(pb.lat)), ctx_(*lat_.ctx)
+    {
+    }
+    ~BsStored()
+    {
+        if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    }
+    sgn_status run(sgn_stats *stp);
+
+  private:
+    const sgn_problem &pb_;
+    const sgn_rational &rf_;
+    const sgn_ms_opts &o_;
+    hipStream_t s_;
+    Lattice &lat_;
+    Context &ctx_;
+    int64_t n_ = 0, nc_ = 0, Sst_ = 0;
+    size_t b64_ = 0, b32_ = 0;
+    int ns_ = 0, seed_ = 0, nvb_ = 0, nst_ = 0, maxiter_ = 0, poll_ = 4;
+    double c2_ = 0.0, s0_ = 0.0;
+    // vectors (internal layouts)
+    char *y_ = nullptr, *rh64_ = nullptr, *r64_ = nullptr, *s64_ = nullptr, *v64_ = nullptr, *t64_ = nullptr,
+         *tmp64_ = nullptr, *p64_ = nullptr, *x64_ = nullptr;
+    char *rh32_ = nullptr, *r32_ = nullptr, *s32_ = nullptr, *v32_ = nullptr, *t32_ = nullptr, *tmp32_ = nullptr,
+         *p32_ = nullptr;
+    char *rcan_ = nullptr;
+    z64 *spart_ = nullptr, *vpart_ = nullptr;
+    BsState *S_ = nullptr;
+    BsHist *hist_ = nullptr;
+    void **rtab_ = nullptr, **stab_ = nullptr;  // device slot tables (r_k, s_k)
+    std::vector<void *> rslots_, sslots_;
+    std::vector<char> rf32_, sf32_;
+    size_t pool_next_ = 0;
+    int slot_cap_ = 0;
+    int phase_ = 0, launched_ = 0, reliable_ = 0;
+    hipGraphExec_t gexec_ = nullptr;
+
+    bool lo() const { return phase_ >= 1; }
+    sgn_prec sprec() const { return phase_ == 0 ? SGN_PREC_F64 : (phase_ == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16); }
+    void *take_slot();
+    void ensure_slots(int upto);
+    void launch_iteration(hipStream_t strm);
+    void iterate(int count);
+    void reliable_update(BsHead &h);
+    void switch_phase(BsHead &h, int to);
+};
+
+void *BsStored::take_slot()
+{
+    auto &pool = ctx_.basis_pools[b64_];
+    if (pool_next_ == pool.size()) {
+        void *b = nullptr;
+        if (hipMalloc(&b, b64_) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: stored basis does not fit"};
+        }
+        pool.push_back(b);
+    }
+    return pool[pool_next_++];
+}
+
+// r-slots 0 .. upto + 1 and s-slots 0 .. upto
+void BsStored::ensure_slots(int upto)
+{
+    if (2 * upto + 3 > slot_cap_) throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: stored basis exceeds basis_slots"};
+    const size_t r0 = rslots_.size(), s0 = sslots_.size();
+    while ((int)rslots_.size() < upto + 2) rslots_.push_back(take_slot());
+    while ((int)sslots_.size() < upto + 1) sslots_.push_back(take_slot());
+    if (rslots_.size() > r0)
+        SGN_HIP(hipMemcpy(rtab_ + r0, rslots_.data() + r0, sizeof(void *) * (rslots_.size() - r0),
+                          hipMemcpyHostToDevice));
+    if (sslots_.size() > s0)
+        SGN_HIP(hipMemcpy(stab_ + s0, sslots_.data() + s0, sizeof(void *) * (sslots_.size() - s0),
+                          hipMemcpyHostToDevice));
+}
+
+void BsStored::launch_iteration(hipStream_t strm)
+{
+    const sgn_prec sp = sprec();
+    const bool f = lo();
+    char *p = f ? p32_ : p64_, *tmp = f ? tmp32_ : tmp64_, *v = f ? v32_ : v64_, *sv = f ? s32_ : s64_,
+         *t = f ? t32_ : t64_, *r = f ? r32_ : r64_, *rh = f ? rh32_ : rh64_;
+    OpSpec op;
+    op.mu = pb_.mu;
+    dslash_launch(lat_, sp, op, p, tmp, Epilogue{}, strm);
+    Epilogue e2;
+    e2.a = c2_;
+    e2.z = p;
+    e2.b = {-s0_, 0.0};
+    e2.w = rh;
+    e2.partials = spart_;
+    const int nb = dslash_launch(lat_, sp, op, tmp, v, e2, strm);
+    hipLaunchKernelGGL(bs_alpha_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)spart_, nb);
+    const int pr = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
+    if (f)
+        hipLaunchKernelGGL(bs_sub_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+                           (const float2 *)r, (const float2 *)v, (float2 *)sv, (void *const *)stab_, n_);
+    else
+        hipLaunchKernelGGL(bs_sub_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+                           (const double2 *)r, (const double2 *)v, (double2 *)sv, (void *const *)stab_, n_);
+    ctx_.prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * (f ? 8.0 : 16.0) * n_, 8.0 * n_);
+    dslash_launch(lat_, sp, op, sv, tmp, Epilogue{}, strm);
+    Epilogue e4;
+    e4.a = c2_;
+    e4.z = sv;
+    e4.b = {-s0_, 0.0};
+    dslash_launch(lat_, sp, op, tmp, t, e4, strm);
+    const double eb = f ? 8.0 : 16.0;
+    int pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
+    if (f)
+        hipLaunchKernelGGL(bs_dots_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+                           (const float2 *)t, (const float2 *)sv, n_, vpart_);
+    else
+        hipLaunchKernelGGL(bs_dots_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+                           (const double2 *)t, (const double2 *)sv, n_, vpart_);
+    ctx_.prof_stop(pr2, strm, SGN_K_SEED_UPDATE, 2.0 * eb * n_, 8.0 * n_);
+    hipLaunchKernelGGL(bs_omega_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nvb_);
+    pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
+    if (f)
+        hipLaunchKernelGGL(bs_res_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+                           (const float2 *)sv, (const float2 *)t, (const float2 *)rh, (float2 *)r,
+                           (void *const *)rtab_, n_, vpart_);
+    else
+        hipLaunchKernelGGL(bs_res_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+                           (const double2 *)sv, (const double2 *)t, (const double2 *)rh, (double2 *)r,
+                           (void *const *)rtab_, n_, vpart_);
+    ctx_.prof_stop(pr2, strm, SGN_K_SEED_UPDATE, 5.0 * eb * n_, 12.0 * n_);
+    hipLaunchKernelGGL(bs_beta_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nvb_, hist_, maxiter_);
+    const int pr3 = ctx_.prof_start(strm, SGN_K_SHIFT_UPDATE);
+    if (f)
+        hipLaunchKernelGGL(bs_xp32, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, strm, (const BsState *)S_, (float4 *)p,
+                           (const float4 *)v, (const float4 *)r, (const float4 *)sv, (double2 *)x64_, (int)Sst_);
+    else
+        hipLaunchKernelGGL(bs_xp64, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_, (double2 *)p,
+                           (const double2 *)v, (const double2 *)r, (const double2 *)sv, (double2 *)x64_, n_);
+    ctx_.prof_stop(pr3, strm, SGN_K_SHIFT_UPDATE, (5.0 * (f ? 8.0 : 16.0) + 32.0) * n_, 28.0 * n_);
+    SGN_HIP(hipGetLastError());
+}
+
+void BsStored::iterate(int count)
+{
+    if (o_.graph >= 0 && !ctx_.prof) {
+        if (!gexec_) {
+            if (!ctx_.capture_stream) SGN_HIP(hipStreamCreate(&ctx_.capture_stream));
+            hipStream_t cs = ctx_.capture_stream;
+            hipGraph_t g = nullptr;
+            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int it = 0; it < count; ++it) launch_iteration(cs);
+            } catch (...) {
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SGN_HIP(hipStreamEndCapture(cs, &g));
+            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SGN_HIP(e);
+        }
+        SGN_HIP(hipGraphLaunch(gexec_, s_));
+    } else {
+        for (int it = 0; it < count; ++it) launch_iteration(s_);
+    }
+    for (int it = 0; it < count; ++it) {  // slot precision of the iterations just launched
+        const int k = launched_ + it;
+        if ((int)sf32_.size() <= k) sf32_.resize(k + 1, 0);
+        if ((int)rf32_.size() <= k + 1) rf32_.resize(k + 2, 0);
+        sf32_[k] = lo() ? 1 : 0;
+        rf32_[k + 1] = lo() ? 1 : 0;
+    }
+    launched_ += count;
+}
+
+// r = y - (c^2 A^2 - sigma_seed) x in FP64; it replaces the work residual and the slot of the
+// current iteration (in that slot's precision); rho, the residual norm and its running maximum
+// restart from it
+void BsStored::reliable_update(BsHead &h)
+{
+    OpSpec op;
+    op.mu = pb_.mu;
+    dslash_launch(lat_, SGN_PREC_F64, op, x64_, tmp64_, Epilogue{}, s_);
+    Epilogue ep;
+    ep.a = -c2_;
+    ep.z = x64_;
+    ep.b = {s0_, 0.0};
+    dslash_launch(lat_, SGN_PREC_F64, op, tmp64_, t64_, ep, s_);
+    hipLaunchKernelGGL(bs_addto64, dim3(nvb_), dim3(256), 0, s_, (const double2 *)y_, (double2 *)t64_, n_);
+    SGN_HIP(hipGetLastError());
+    const int k = h.iter;
+    if (lo()) {
+        convert_64_to_32(t64_, r32_, Sst_, s_);
+        SGN_HIP(hipMemcpyAsync(rslots_[k], r32_, b32_, hipMemcpyDeviceToDevice, s_));
+        const z64 rho = dot_sync(ctx_, rh32_, r32_, n_, true, s_);
+        h.rho = rho;
+        h.rnorm = norm_sync(ctx_, r32_, n_, true, s_);
+    } else {
+        SGN_HIP(hipMemcpyAsync(r64_, t64_, b64_, hipMemcpyDeviceToDevice, s_));
+        SGN_HIP(hipMemcpyAsync(rslots_[k], t64_, b64_, hipMemcpyDeviceToDevice, s_));
+        h.rho = dot_sync(ctx_, rh64_, r64_, n_, false, s_);
+        h.rnorm = norm_sync(ctx_, r64_, n_, false, s_);
+    }
+    h.rmax = h.rnorm;
+    h.reliable = 0;
+    ++reliable_;
+}
+
+void BsStored::switch_phase(BsHead &h, int to)
+{
+    if (phase_ == 0 && to >= 1) {
+        convert_64_to_32(r64_, r32_, Sst_, s_);
+        convert_64_to_32(p64_, p32_, Sst_, s_);
+        convert_64_to_32(rh64_, rh32_, Sst_, s_);
+        // rho and the norm of what the FP32 iteration sees
+        h.rho = dot_sync(ctx_, rh32_, r32_, n_, true, s_);
+        h.rnorm = norm_sync(ctx_, r32_, n_, true, s_);
+        h.rmax = h.rnorm;
+    }
+    phase_ = to;
+    h.phase = to;
+    h.want_phase = 0;
+    if (gexec_) {
+        (void)hipGraphExecDestroy(gexec_);
+        gexec_ = nullptr;
+    }
+}
+
+sgn_status BsStored::run(sgn_stats *stp)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    SGN_HIP(hipSetDevice(ctx_.device));
+    ns_ = rf_.s;
+    Sst_ = lat_.S;
+    n_ = 12 * lat_.S;
+    nc_ = 12 * lat_.V;
+    b64_ = (size_t)n_ * 16;
+    b32_ = (size_t)n_ * 8;
+    const size_t c64 = (size_t)nc_ * 16;
+    nvb_ = vec_blocks(n_);
+    nst_ = dslash_blocks(lat_);
+    maxiter_ = o_.maxiter > 0 ? o_.maxiter : 10000;
+    poll_ = o_.poll > 0 ? o_.poll : 4;
+    const bool mixed = o_.prec != SGN_PREC_F64;
+    for (int i = 1; i < ns_; ++i)
+        if (std::abs(rf_.sigma[i]) < std::abs(rf_.sigma[seed_])) seed_ = i;
+    s0_ = rf_.sigma[seed_];
+    c2_ = rf_.c * rf_.c;
+    // workspace
+    const size_t scal = sizeof(z64) * ((size_t)nst_ + 2 * (size_t)kMaxBlocks) + sizeof(BsState) +
+                        sizeof(BsHist) * (size_t)maxiter_ + 2 * sizeof(void *) * ((size_t)maxiter_ + poll_ + 4);
+    char *a = static_cast<char *>(ctx_.ensure_arena(9 * b64_ + (mixed ? 7 * b32_ : 0) + c64 + scal + 256));
+    char *q = a;
+    for (char **v : {&y_, &rh64_, &r64_, &s64_, &v64_, &t64_, &tmp64_, &p64_, &x64_}) {
+        *v = q;
+        q += b64_;
+    }
+    if (mixed)
+        for (char **v : {&rh32_, &r32_, &s32_, &v32_, &t32_, &tmp32_, &p32_}) {
+            *v = q;
+            q += b32_;
+        }
+    rcan_ = q;
+    q += c64;
+    q = reinterpret_cast<char *>(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    spart_ = reinterpret_cast<z64 *>(q);
+    vpart_ = spart_ + nst_;
+    S_ = reinterpret_cast<BsState *>(vpart_ + 2 * kMaxBlocks);
+    hist_ = reinterpret_cast<BsHist *>(S_ + 1);
+    rtab_ = reinterpret_cast<void **>(hist_ + maxiter_);
+    stab_ = rtab_ + maxiter_ + poll_ + 2;
+    // stored-basis budget: basis_slots > 0 slots, else up to half of the free device memory
+    {
+        size_t fr = 0, tot = 0;
+        SGN_HIP(hipMemGetInfo(&fr, &tot));
+        size_t held = 0;
+        for (auto &kv : ctx_.basis_pools) held += kv.first * kv.second.size();
+        const double budget = o_.basis_slots > 0 ? (double)o_.basis_slots : 0.5 * (double)(fr + held) / (double)b64_;
+        slot_cap_ = (int)std::min<double>(budget, 2.0 * maxiter_ + 2 * poll_ + 4);
+    }
+    sgn_stats st{};
+    st.nshift = ns_;
+    OpSpec op;
+    op.mu = pb_.mu;
+    // x = x_P, y = c H (I - P) b
+    deflation_prologue(ctx_, pb_.defl, nc_, pb_.b, pb_.x, rcan_, nullptr, s_);
+    pack_spinor(lat_, rcan_, tmp64_, SGN_PREC_F64, s_);
+    {
+        Epilogue ep;
+        ep.a = rf_.c;
+        dslash_launch(lat_, SGN_PREC_F64, op, tmp64_, y_, ep, s_);
+    }
+    const double ynorm = norm_sync(ctx_, y_, n_, false, s_);
+    SGN_REQUIRE(std::isfinite(ynorm), "multishift_bicgstab: b contains NaN or Inf");
+    if (ynorm == 0.0) {
+        SGN_HIP(hipStreamSynchronize(s_));
+        if (stp) *stp = st;
+        return SGN_OK;
+    }
+    ensure_slots(poll_);
+    rf32_.assign(1, 0);
+    for (char *v : {rh64_, r64_, p64_}) SGN_HIP(hipMemcpyAsync(v, y_, b64_, hipMemcpyDeviceToDevice, s_));
+    SGN_HIP(hipMemcpyAsync(rslots_[0], y_, b64_, hipMemcpyDeviceToDevice, s_));
+    hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)x64_, make_double2(0.0, 0.0),
+                       n_);
+    SGN_HIP(hipGetLastError());
+    std::vector<double> tau(ns_);
+    BsState h0{};
+    h0.h.rho = {ynorm * ynorm, 0.0};
+    h0.h.alpha_prev = {1.0, 0.0};
+    h0.h.rnorm = h0.h.rmax = h0.h.ynorm = ynorm;
+    h0.h.tol = o_.tol;
+    h0.h.delta = o_.delta > 0 ? o_.delta : 0.1;
+    h0.h.theta32 = mixed ? (o_.theta32 > 0 ? o_.theta32 : 1e-3) : 0.0;
+    const bool deflated = pb_.defl && pb_.defl->m > 0;  // FP16 links would excite the deflated modes
+    h0.h.theta16 = (o_.prec == SGN_PREC_F32_H16 && !deflated) ? (o_.theta16 > 0 ? o_.theta16 : 1e-6) : 0.0;
+    h0.h.maxiter = maxiter_;
+    h0.h.ns = ns_;
+    h0.h.seed = seed_;
+    for (int i = 0; i < ns_; ++i) {
+        tau[i] = s0_ - rf_.sigma[i];
+        h0.zeta[i] = h0.zeta_prev[i] = h0.zeta_next[i] = h0.pi[i] = {1.0, 0.0};
+        h0.tau[i] = tau[i];
+        h0.act[i] = 1;
+    }
+    SGN_HIP(hipMemcpyAsync(S_, &h0, sizeof(BsState), hipMemcpyHostToDevice, s_));
+    SGN_HIP(hipStreamSynchronize(s_));
+    const auto t_kry = std::chrono::steady_clock::now();
+    sgn_status result = SGN_OK;
+    BsHead h{};
+    for (;;) {
+        ensure_slots(launched_ + poll_);
+        iterate(poll_);
+        SGN_HIP(hipMemcpyAsync(&h, &S_->h, sizeof(BsHead), hipMemcpyDeviceToHost, s_));
+        SGN_HIP(hipStreamSynchronize(s_));
+        if (h.breakdown) {
+            result = SGN_ERR_BREAKDOWN;
+            break;
+        }
+        if (h.done) {
+            if (h.iter >= maxiter_) {
+                // converged in the last iteration or not at all: decided from the estimates below
+                result = SGN_ERR_NOT_CONVERGED;
+            }
+            break;
+        }
+        bool changed = false;
+        if (h.reliable) {
+            reliable_update(h);
+            changed = true;
+        }
+        if (h.want_phase) {
+            switch_phase(h, h.want_phase);
+            changed = true;
+        }
+        if (changed) {
+            SGN_HIP(hipMemcpyAsync(&S_->h, &h, sizeof(BsHead), hipMemcpyHostToDevice, s_));
+            SGN_HIP(hipStreamSynchronize(s_));
+        }
+    }
+    const int K = h.iter;
+    // coefficients of sum_{i != seed} omega_i x_i over the slots r_0..r_K, s_0..s_{K-1}
+    std::vector<BsHist> hs(K);
+    if (K) SGN_HIP(hipMemcpy(hs.data(), hist_, sizeof(BsHist) * K, hipMemcpyDeviceToHost));
+    const double lim = o_.tol * ynorm;
+    std::vector<zc> dr(K + 1, 0.0), ds(K, 0.0);
+    double worst = 0.0;
+    for (int i = 0; i < ns_; ++i) {
+        zc zeta = 1.0, zeta_prev = 1.0, pi = 1.0, ap = 1.0, bp = 0.0;
+        std::vector<zc> Pr(K + 1, 0.0), Ps(K, 0.0), Xr(K + 1, 0.0), Xs(K, 0.0);
+        Pr[0] = 1.0;
+        bool frozen = false;
+        double res = 1.0;
+        for (int k = 0; k < K && !frozen; ++k) {
+            const zc al(hs[k].alpha.r, hs[k].alpha.i), om(hs[k].omega.r, hs[k].omega.i), be(hs[k].beta.r, hs[k].beta.i);
+            const zc zn = zeta * zeta_prev * ap / (ap * (1.0 + tau[i] * al) * zeta_prev + al * bp * (zeta_prev - zeta));
+            const zc ai = al * zn / zeta, qq = zn / zeta, bi = be * qq * qq, oi = om / (1.0 + om * tau[i]);
+            const zc pn = pi * (1.0 + om * tau[i]);
+            const zc ks = (std::abs(ai) > 0.0) ? bi * oi / ai : zc(0.0, 0.0);
+            for (int j = 0; j <= k; ++j) {
+                Xr[j] += ai * Pr[j];
+                if (j < k) Xs[j] += ai * Ps[j];
+            }
+            Xs[k] += oi * zn / pi;
+            for (int j = 0; j <= k; ++j) {
+                Pr[j] *= bi;
+                if (j < k) Ps[j] *= bi;
+            }
+            Pr[k] += -ks * zeta / pi;
+            Ps[k] = ks * zn / pi;
+            Pr[k + 1] = zn / pn;
+            zeta_prev = zeta;
+            zeta = zn;
+            pi = pn;
+            ap = al;
+            bp = be;
+            res = std::abs(zeta / pi) * hs[k].rnorm;
+            if (i != seed_ && res <= lim) frozen = true;
+        }
+        if (K == 0) res = ynorm;
+        st.shift_residual[i] = res / ynorm;
+        worst = std::max(worst, st.shift_residual[i]);
+        if (i == seed_) continue;
+        for (int j = 0; j <= K; ++j) dr[j] += rf_.omega[i] * Xr[j];
+        for (int j = 0; j < K; ++j) ds[j] += rf_.omega[i] * Xs[j];
+    }
+    if (result == SGN_ERR_NOT_CONVERGED && worst <= o_.tol) result = SGN_OK;
+    // x_int = omega_seed x_seed + lift
+    scale64({rf_.omega[seed_], 0.0}, x64_, tmp64_, n_, s_);
+    std::vector<BsSlot> sl;
+    std::vector<z64> cf;
+    for (int j = 0; j <= K; ++j) {
+        sl.push_back(BsSlot{rslots_[j], j < (int)rf32_.size() ? rf32_[j] : 0, 0});
+        cf.push_back({dr[j].real(), dr[j].imag()});
+    }
+    for (int j = 0; j < K; ++j) {
+        sl.push_back(BsSlot{sslots_[j], j < (int)sf32_.size() ? sf32_[j] : 0, 0});
+        cf.push_back({ds[j].real(), ds[j].imag()});
+    }
+    {
+        const int nk = (int)sl.size();
+        void *dsl = nullptr, *dcf = nullptr;
+        SGN_HIP(hipMalloc(&dsl, sizeof(BsSlot) * nk));
+        if (hipMalloc(&dcf, sizeof(z64) * nk) != hipSuccess) {
+            (void)hipFree(dsl);
+            throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: lift coefficients"};
+        }
+        SGN_HIP(hipMemcpy(dsl, sl.data(), sizeof(BsSlot) * nk, hipMemcpyHostToDevice));
+        SGN_HIP(hipMemcpy(dcf, cf.data(), sizeof(z64) * nk, hipMemcpyHostToDevice));
+        const int pr = ctx_.prof_start(s_, SGN_K_LIFT);
+        double bytes = 2.0 * b64_;
+        for (int j = 0; j < nk; ++j) bytes += sl[j].f32 ? (double)b32_ : (double)b64_;
+        for (int j0 = 0; j0 < nk; j0 += kBsLiftChunk)
+            hipLaunchKernelGGL(bs_lift_kernel, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, s_,
+                               static_cast<const BsSlot *>(dsl) + j0, static_cast<const z64 *>(dcf) + j0,
+                               std::min(kBsLiftChunk, nk - j0), (int)Sst_, (double2 *)tmp64_);
+        ctx_.prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * nk * (double)n_);
+        SGN_HIP(hipGetLastError());
+        SGN_HIP(hipStreamSynchronize(s_));
+        (void)hipFree(dsl);
+        (void)hipFree(dcf);
+    }
+    unpack_spinor(lat_, tmp64_, rcan_, SGN_PREC_F64, s_);
+    if (pb_.defl && pb_.defl->m > 0) {  // the exact x_i lie in range(I - P): drop rounding components
+        DeviceScratch cd(sizeof(z64) * pb_.defl->m);
+        deflate_dots(pb_.defl->L, pb_.defl->m, rcan_, nc_, static_cast<z64 *>(cd.p), ctx_, s_);
+        deflate_combine(rcan_, {1.0, 0.0}, {-1.0, 0.0}, pb_.defl->R, pb_.defl->m, static_cast<const z64 *>(cd.p),
+                        nullptr, nc_, s_);
+        SGN_HIP(hipStreamSynchronize(s_));
+    }
+    axpby64({1.0, 0.0}, rcan_, {1.0, 0.0}, pb_.x, nc_, s_);
+    SGN_HIP(hipStreamSynchronize(s_));
+    st.iterations = K;
+    st.matvecs = 4 * K + 1 + 2 * reliable_;
+    st.reliable_updates = reliable_;
+    st.residual = worst;
+    st.krylov_ms = ms_since(t_kry);
+    st.total_ms = ms_since(t_start);
+    if (stp) *stp = st;
+    return result;
+}
+
 }  // namespace
 
 }  // namespace sgn
@@ -376,9 +1169,21 @@ extern "C" sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, cons
         SGN_REQUIRE(pb && rf && o && nprob >= 0, "multishift_bicgstab: null argument");
         SGN_REQUIRE(rf->s >= 1 && rf->s <= SGN_MAX_POLES && rf->c > 0, "multishift_bicgstab: bad rational function");
         SGN_REQUIRE(o->tol > 0 && o->tol < 1, "multishift_bicgstab: tol must be in (0, 1)");
-        SGN_REQUIRE(o->prec == SGN_PREC_F64, "multishift_bicgstab: FP64 only");
+        SGN_REQUIRE(o->prec == SGN_PREC_F64 || o->prec == SGN_PREC_F32 || o->prec == SGN_PREC_F32_H16,
+                    "multishift_bicgstab: unknown precision");
+        SGN_REQUIRE(o->maxiter >= 0 && o->maxiter <= 100000, "multishift_bicgstab: maxiter out of range");
         for (int k = 0; k < nprob; ++k) {
-            const sgn_status sk = solve_one(pb[k], *rf, *o, st ? st + k : nullptr, static_cast<hipStream_t>(stream));
+            const hipStream_t s = static_cast<hipStream_t>(stream);
+            sgn_status sk;
+            if (pb[k].x_shift || o->basis_slots < 0) {
+                SGN_REQUIRE(o->prec == SGN_PREC_F64, "multishift_bicgstab: per-shift solutions are FP64 only");
+                sk = solve_explicit(pb[k], *rf, *o, st ? st + k : nullptr, s);
+            } else {
+                SGN_REQUIRE(pb[k].lat && pb[k].b && pb[k].x, "multishift_bicgstab: null problem field");
+                SGN_REQUIRE(std::isfinite(pb[k].mu), "multishift_bicgstab: mu not finite");
+                BsStored solver(pb[k], *rf, *o, s);
+                sk = solver.run(st ? st + k : nullptr);
+            }
             if (sk != SGN_OK && result == SGN_OK) result = sk;
         }
     });

@@ -112,5 +112,56 @@ def test_bicgstab_zero_source_and_errors():
         _solve(lat, 0.3, b, rf, tol=1e-11, maxiter=3)
     assert e.value.status == 5
     with pytest.raises(sgn.SgnError) as e:
-        _solve(lat, 0.3, b, rf, prec=sgn.F32)
+        _solve(lat, 0.3, b, rf, want_shifts=True, prec=sgn.F32)  # per-shift form: FP64 only
     assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _solve(lat, 0.3, b, rf, basis_slots=9)  # stored basis beyond its cap
+    assert e.value.status == 3
+
+
+def test_stored_basis_equals_per_shift_form():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    lat = lattice(U, dims)
+    xs, ss = _solve(lat, 0.3, b, rf, tol=1e-11)
+    xe, se = _solve(lat, 0.3, b, rf, tol=1e-11, basis_slots=-1)
+    print(f"BiCGStab stored vs per-shift: {_rel(xs, xe):.1e}, iterations {ss['iterations']} / {se['iterations']}",
+          flush=True)
+    assert _rel(xs, xe) < 1e-9
+    assert _rel(xs, g["g16_b"]) < 1e-8
+    # graph replays and plain launches give the same bits
+    xg, _ = _solve(lat, 0.3, b, rf, tol=1e-11, graph=False)
+    assert np.array_equal(xg, xs)
+
+
+@pytest.mark.parametrize("prec", [sgn.F32, sgn.F32_H16])
+def test_c1_mixed_bicgstab_matches_dense_rational(prec):
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    x, st = _solve(lattice(U, dims), 0.3, b, rf, tol=1e-10, prec=prec)
+    e = _rel(x, g["g16_b"])
+    print(f"C1 mixed BiCGStab prec={prec}: vs dense g16 {e:.2e}, {st['iterations']} iterations, "
+          f"{st['reliable_updates']} reliable updates", flush=True)
+    assert st["reliable_updates"] >= 1
+    assert e < 1e-8
+
+
+def test_8x4_mixed_bicgstab_against_oracle():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(16, 0.15, 2.6)
+    rf = sgn.sgn_rational_neuberger(16, 0.15, 2.6)
+    x, st = _solve(lattice(U, dims), 0.2, b, rf, tol=1e-10, prec=sgn.F32_H16)
+    xo = krylov.multishift_bicgstab(lambda v: W.apply(v, 0.2), b, om, sg, c, tol=1e-11)
+    e = _rel(x, xo)
+    print(f"8^4 mixed BiCGStab: vs oracle {e:.2e}, {st['iterations']} iterations, {st['reliable_updates']} RU, "
+          f"{st['total_ms']:.1f} ms", flush=True)
+    assert e < 1e-8
