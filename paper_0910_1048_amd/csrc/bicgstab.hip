@@ -449,15 +449,16 @@ __global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *pa
     }
 }
 
-// s = r - alpha v, into the work vector and the slot of iteration k
+// s = r_k - alpha v (r_k read from its slot), into the work vector and the slot of iteration k
 template <typename R>
-__global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, const typename BsVec<R>::t *r,
+__global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, void *const *rslots,
                                                      const typename BsVec<R>::t *v, typename BsVec<R>::t *s,
                                                      void *const *sslots, int64_t n)
 {
     using T = typename BsVec<R>::t;
     if (S->h.done) return;
     const z64 al = S->h.alpha;
+    const T *r = static_cast<const T *>(rslots[S->h.iter]);
     T *slot = static_cast<T *>(sslots[S->h.iter]);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 sv = ldz(r, e) - al * ldz(v, e);
@@ -505,22 +506,21 @@ __global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *pa
     if (threadIdx.x == 0) S->h.omega = v[2] > 0.0 ? z64{v[0] / v[2], v[1] / v[2]} : z64{0.0, 0.0};
 }
 
-// r' = s - omega t, into the work vector and the slot of iteration k + 1; partials of
-// r^^H r' and ||r'||^2 (of the stored values)
+// r' = s - omega t into the slot of iteration k + 1 (the residual lives only there);
+// partials of r^^H r' and ||r'||^2 (of the stored values)
 template <typename R>
 __global__ void __launch_bounds__(256) bs_res_stored(const BsState *S, const typename BsVec<R>::t *s,
                                                      const typename BsVec<R>::t *t, const typename BsVec<R>::t *rh,
-                                                     typename BsVec<R>::t *r, void *const *rslots, int64_t n, z64 *part)
+                                                     void *const *rslots, int64_t n, z64 *part)
 {
     using T = typename BsVec<R>::t;
     if (S->h.done) return;
     const z64 om = S->h.omega;
-    T *slot = static_cast<T *>(rslots[S->h.iter + 1]);
+    T *r = static_cast<T *>(rslots[S->h.iter + 1]);
     double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         z64 rv = ldz(s, e) - om * ldz(t, e);
         stz(r, e, rv);
-        stz(slot, e, rv);
         if constexpr (sizeof(R) == 4) rv = ldz(r, e);
         const z64 d = cmulc(ldz(rh, e), rv);
         a += d.r;
@@ -609,12 +609,14 @@ __global__ void __launch_bounds__(256) bs_beta_kernel(BsState *S, const z64 *par
     }
 }
 
-// the seed: x += alpha p + omega s (x in FP64), p = r' + beta (p - omega v)
-__global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, const double2 *v, const double2 *r,
+// the seed: x += alpha p + omega s (x in FP64), p = r' + beta (p - omega v), r' read from its
+// slot (the iteration counter was advanced by the beta step)
+__global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, const double2 *v, void *const *rslots,
                                                const double2 *s, double2 *x, int64_t n)
 {
     if (!S->h.go || S->h.breakdown) return;
     const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
+    const double2 *r = static_cast<const double2 *>(rslots[S->h.iter]);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 pv = ldz(p, e), sv = ldz(s, e);
         stz(x, e, ldz(x, e) + al * pv + om * sv);
@@ -622,12 +624,14 @@ __global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, con
     }
 }
 
-// FP32 vectors in the [6][S] float4 layout (chunk c holds components 2c, 2c+1), x in [12][S] double2
-__global__ void __launch_bounds__(256) bs_xp32(const BsState *S, float4 *p, const float4 *v, const float4 *r,
+// FP32 phase: p, v, r', s in the [6][S] float4 layout (chunk c holds components 2c, 2c+1), x in
+// FP64 [12][S] (FP32 increments of x lose too much of the seed solution's accuracy here)
+__global__ void __launch_bounds__(256) bs_xp32(const BsState *S, float4 *p, const float4 *v, void *const *rslots,
                                                const float4 *s, double2 *x, int Sst)
 {
     if (!S->h.go || S->h.breakdown) return;
     const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
+    const float4 *r = static_cast<const float4 *>(rslots[S->h.iter]);
     const int64_t np = (int64_t)6 * Sst;
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < np; f += (int64_t)gridDim.x * blockDim.x) {
         const int c2 = (int)(f / Sst), st = (int)(f - (int64_t)c2 * Sst);
@@ -716,8 +720,9 @@ class BsStored {
     int ns_ = 0, seed_ = 0, nvb_ = 0, nst_ = 0, maxiter_ = 0, poll_ = 4;
     double c2_ = 0.0, s0_ = 0.0;
     // vectors (internal layouts)
-    char *y_ = nullptr, *rh64_ = nullptr, *r64_ = nullptr, *s64_ = nullptr, *v64_ = nullptr, *t64_ = nullptr,
-         *tmp64_ = nullptr, *p64_ = nullptr, *x64_ = nullptr;
+    // the residual r_k lives only in its slot; r32_ is a conversion buffer
+    char *y_ = nullptr, *rh64_ = nullptr, *s64_ = nullptr, *v64_ = nullptr, *t64_ = nullptr, *tmp64_ = nullptr,
+         *p64_ = nullptr, *x64_ = nullptr;
     char *rh32_ = nullptr, *r32_ = nullptr, *s32_ = nullptr, *v32_ = nullptr, *t32_ = nullptr, *tmp32_ = nullptr,
          *p32_ = nullptr;
     char *rcan_ = nullptr;
@@ -776,7 +781,7 @@ void BsStored::launch_iteration(hipStream_t strm)
     const sgn_prec sp = sprec();
     const bool f = lo();
     char *p = f ? p32_ : p64_, *tmp = f ? tmp32_ : tmp64_, *v = f ? v32_ : v64_, *sv = f ? s32_ : s64_,
-         *t = f ? t32_ : t64_, *r = f ? r32_ : r64_, *rh = f ? rh32_ : rh64_;
+         *t = f ? t32_ : t64_, *rh = f ? rh32_ : rh64_;
     OpSpec op;
     op.mu = pb_.mu;
     dslash_launch(lat_, sp, op, p, tmp, Epilogue{}, strm);
@@ -791,10 +796,10 @@ void BsStored::launch_iteration(hipStream_t strm)
     const int pr = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
     if (f)
         hipLaunchKernelGGL(bs_sub_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
-                           (const float2 *)r, (const float2 *)v, (float2 *)sv, (void *const *)stab_, n_);
+                           (void *const *)rtab_, (const float2 *)v, (float2 *)sv, (void *const *)stab_, n_);
     else
         hipLaunchKernelGGL(bs_sub_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
-                           (const double2 *)r, (const double2 *)v, (double2 *)sv, (void *const *)stab_, n_);
+                           (void *const *)rtab_, (const double2 *)v, (double2 *)sv, (void *const *)stab_, n_);
     ctx_.prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * (f ? 8.0 : 16.0) * n_, 8.0 * n_);
     dslash_launch(lat_, sp, op, sv, tmp, Epilogue{}, strm);
     Epilogue e4;
@@ -815,22 +820,22 @@ void BsStored::launch_iteration(hipStream_t strm)
     pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
     if (f)
         hipLaunchKernelGGL(bs_res_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
-                           (const float2 *)sv, (const float2 *)t, (const float2 *)rh, (float2 *)r,
-                           (void *const *)rtab_, n_, vpart_);
+                           (const float2 *)sv, (const float2 *)t, (const float2 *)rh, (void *const *)rtab_, n_,
+                           vpart_);
     else
         hipLaunchKernelGGL(bs_res_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
-                           (const double2 *)sv, (const double2 *)t, (const double2 *)rh, (double2 *)r,
-                           (void *const *)rtab_, n_, vpart_);
-    ctx_.prof_stop(pr2, strm, SGN_K_SEED_UPDATE, 5.0 * eb * n_, 12.0 * n_);
+                           (const double2 *)sv, (const double2 *)t, (const double2 *)rh, (void *const *)rtab_, n_,
+                           vpart_);
+    ctx_.prof_stop(pr2, strm, SGN_K_SEED_UPDATE, 4.0 * eb * n_, 12.0 * n_);
     hipLaunchKernelGGL(bs_beta_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nvb_, hist_, maxiter_);
     const int pr3 = ctx_.prof_start(strm, SGN_K_SHIFT_UPDATE);
     if (f)
         hipLaunchKernelGGL(bs_xp32, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, strm, (const BsState *)S_, (float4 *)p,
-                           (const float4 *)v, (const float4 *)r, (const float4 *)sv, (double2 *)x64_, (int)Sst_);
+                           (const float4 *)v, (void *const *)rtab_, (const float4 *)sv, (double2 *)x64_, (int)Sst_);
     else
         hipLaunchKernelGGL(bs_xp64, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_, (double2 *)p,
-                           (const double2 *)v, (const double2 *)r, (const double2 *)sv, (double2 *)x64_, n_);
-    ctx_.prof_stop(pr3, strm, SGN_K_SHIFT_UPDATE, (5.0 * (f ? 8.0 : 16.0) + 32.0) * n_, 28.0 * n_);
+                           (const double2 *)v, (void *const *)rtab_, (const double2 *)sv, (double2 *)x64_, n_);
+    ctx_.prof_stop(pr3, strm, SGN_K_SHIFT_UPDATE, (5.0 * eb + 32.0) * n_, 28.0 * n_);
     SGN_HIP(hipGetLastError());
 }
 
@@ -868,9 +873,9 @@ void BsStored::iterate(int count)
     launched_ += count;
 }
 
-// r = y - (c^2 A^2 - sigma_seed) x in FP64; it replaces the work residual and the slot of the
-// current iteration (in that slot's precision); rho, the residual norm and its running maximum
-// restart from it
+// r = y - (c^2 A^2 - sigma_seed) x in FP64; it replaces the
+// residual of the current iteration in its slot (in the FP32 phase); rho, the residual norm
+// and its running maximum restart from it
 void BsStored::reliable_update(BsHead &h)
 {
     OpSpec op;
@@ -884,18 +889,11 @@ void BsStored::reliable_update(BsHead &h)
     hipLaunchKernelGGL(bs_addto64, dim3(nvb_), dim3(256), 0, s_, (const double2 *)y_, (double2 *)t64_, n_);
     SGN_HIP(hipGetLastError());
     const int k = h.iter;
-    if (lo()) {
-        convert_64_to_32(t64_, r32_, Sst_, s_);
-        SGN_HIP(hipMemcpyAsync(rslots_[k], r32_, b32_, hipMemcpyDeviceToDevice, s_));
-        const z64 rho = dot_sync(ctx_, rh32_, r32_, n_, true, s_);
-        h.rho = rho;
-        h.rnorm = norm_sync(ctx_, r32_, n_, true, s_);
-    } else {
-        SGN_HIP(hipMemcpyAsync(r64_, t64_, b64_, hipMemcpyDeviceToDevice, s_));
-        SGN_HIP(hipMemcpyAsync(rslots_[k], t64_, b64_, hipMemcpyDeviceToDevice, s_));
-        h.rho = dot_sync(ctx_, rh64_, r64_, n_, false, s_);
-        h.rnorm = norm_sync(ctx_, r64_, n_, false, s_);
-    }
+    convert_64_to_32(t64_, r32_, Sst_, s_);
+    SGN_HIP(hipMemcpyAsync(rslots_[k], r32_, b32_, hipMemcpyDeviceToDevice, s_));
+    rf32_[k] = 1;
+    h.rho = dot_sync(ctx_, rh32_, r32_, n_, true, s_);
+    h.rnorm = norm_sync(ctx_, r32_, n_, true, s_);
     h.rmax = h.rnorm;
     h.reliable = 0;
     ++reliable_;
@@ -904,10 +902,14 @@ void BsStored::reliable_update(BsHead &h)
 void BsStored::switch_phase(BsHead &h, int to)
 {
     if (phase_ == 0 && to >= 1) {
-        convert_64_to_32(r64_, r32_, Sst_, s_);
+        // the current residual's slot becomes FP32 (what the FP32 iteration reads); p and the
+        // shadow vector move to FP32
+        const int k = h.iter;
+        convert_64_to_32(rslots_[k], r32_, Sst_, s_);
+        SGN_HIP(hipMemcpyAsync(rslots_[k], r32_, b32_, hipMemcpyDeviceToDevice, s_));
+        rf32_[k] = 1;
         convert_64_to_32(p64_, p32_, Sst_, s_);
         convert_64_to_32(rh64_, rh32_, Sst_, s_);
-        // rho and the norm of what the FP32 iteration sees
         h.rho = dot_sync(ctx_, rh32_, r32_, n_, true, s_);
         h.rnorm = norm_sync(ctx_, r32_, n_, true, s_);
         h.rmax = h.rnorm;
@@ -944,9 +946,9 @@ sgn_status BsStored::run(sgn_stats *stp)
     // workspace
     const size_t scal = sizeof(z64) * ((size_t)nst_ + 2 * (size_t)kMaxBlocks) + sizeof(BsState) +
                         sizeof(BsHist) * (size_t)maxiter_ + 2 * sizeof(void *) * ((size_t)maxiter_ + poll_ + 4);
-    char *a = static_cast<char *>(ctx_.ensure_arena(9 * b64_ + (mixed ? 7 * b32_ : 0) + c64 + scal + 256));
+    char *a = static_cast<char *>(ctx_.ensure_arena(8 * b64_ + (mixed ? 7 * b32_ : 0) + c64 + scal + 256));
     char *q = a;
-    for (char **v : {&y_, &rh64_, &r64_, &s64_, &v64_, &t64_, &tmp64_, &p64_, &x64_}) {
+    for (char **v : {&y_, &rh64_, &s64_, &v64_, &t64_, &tmp64_, &p64_, &x64_}) {
         *v = q;
         q += b64_;
     }
@@ -994,7 +996,7 @@ sgn_status BsStored::run(sgn_stats *stp)
     }
     ensure_slots(poll_);
     rf32_.assign(1, 0);
-    for (char *v : {rh64_, r64_, p64_}) SGN_HIP(hipMemcpyAsync(v, y_, b64_, hipMemcpyDeviceToDevice, s_));
+    for (char *v : {rh64_, p64_}) SGN_HIP(hipMemcpyAsync(v, y_, b64_, hipMemcpyDeviceToDevice, s_));
     SGN_HIP(hipMemcpyAsync(rslots_[0], y_, b64_, hipMemcpyDeviceToDevice, s_));
     hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)x64_, make_double2(0.0, 0.0),
                        n_);
