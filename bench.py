@@ -28,14 +28,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.4, seed=0, kappa=0.2, mu=0.2, poles=16,
-                alpha=0.12, beta=2.6, tol=2e-9)
+                alpha=0.12, beta=2.6, tol=1e-9)
 # the accuracy the throughput is quoted at: relative error against the FP64 solve to 1e-12
 ERR_TARGET = 1e-8
-# precision schedule of the mixed BiCGStab solve: FP32 below 2e-2 ||y||, FP16 links below
+# precision schedule of the mixed BiCGStab solve: FP32 below 1e-2 ||y||, FP16 links below
 # 1e-5 ||y||, reliable update whenever the seed residual drops by 0.05; with the solver
-# tolerance 2e-9 the error against the FP64 reference is 3.7e-9 on this workload (a sweep
-# of the thresholds and tolerance is listed in the design notes)
-MIXED = dict(theta32=2e-2, theta16=1e-5, delta=0.05)
+# tolerance 1e-9 the error against the FP64 reference is 2.2e-9 on this workload, a quarter of
+# the target (BiCGStab's iteration count moves by a few percent with rounding, so the margin
+# is kept wide)
+MIXED = dict(theta32=1e-2, theta16=1e-5, delta=0.05)
 # the BiCG solver at the same target: tolerance 1e-8, FP32 below 1e-1, FP16 links below 1e-3
 BICG_TOL = 1e-8
 BICG_MIXED = dict(theta32=1e-1, theta16=1e-3, delta=0.05)

@@ -467,30 +467,8 @@ __global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, void *con
     }
 }
 
-// partials of t^H s and t^H t
-template <typename R>
-__global__ void __launch_bounds__(256) bs_dots_stored(const BsState *S, const typename BsVec<R>::t *t,
-                                                      const typename BsVec<R>::t *s, int64_t n, z64 *part)
-{
-    if (S->h.done) return;
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const z64 tv = ldz(t, e), sv = ldz(s, e);
-        const z64 d = cmulc(tv, sv);
-        a += d.r;
-        b += d.i;
-        c += norm2(tv);
-    }
-    __shared__ double lds[12];
-    double v[3] = {a, b, c};
-    block_sum<3>(v, lds);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = {v[0], v[1]};
-        part[2 * blockIdx.x + 1] = {v[2], 0.0};
-    }
-}
-
-// omega = t^H s / t^H t (0 when t = 0: s was the exact residual 0)
+// omega = t^H s / t^H t (0 when t = 0: s was the exact residual 0), from the partials
+// {s^H t, ||t||^2} per block of the stencil that produced t
 __global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *part, int nb)
 {
     if (S->h.done) return;
@@ -503,7 +481,7 @@ __global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *pa
     __shared__ double lds[12];
     double v[3] = {a, b, c};
     block_sum<3>(v, lds);
-    if (threadIdx.x == 0) S->h.omega = v[2] > 0.0 ? z64{v[0] / v[2], v[1] / v[2]} : z64{0.0, 0.0};
+    if (threadIdx.x == 0) S->h.omega = v[2] > 0.0 ? z64{v[0] / v[2], -v[1] / v[2]} : z64{0.0, 0.0};
 }
 
 // r' = s - omega t into the slot of iteration k + 1 (the residual lives only there);
@@ -802,21 +780,17 @@ void BsStored::launch_iteration(hipStream_t strm)
                            (void *const *)rtab_, (const double2 *)v, (double2 *)sv, (void *const *)stab_, n_);
     ctx_.prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * (f ? 8.0 : 16.0) * n_, 8.0 * n_);
     dslash_launch(lat_, sp, op, sv, tmp, Epilogue{}, strm);
-    Epilogue e4;
+    Epilogue e4;  // t = M s with the partials of s^H t and ||t||^2
     e4.a = c2_;
     e4.z = sv;
     e4.b = {-s0_, 0.0};
-    dslash_launch(lat_, sp, op, tmp, t, e4, strm);
+    e4.w = sv;
+    e4.partials = vpart_;
+    e4.norm = true;
+    const int nb4 = dslash_launch(lat_, sp, op, tmp, t, e4, strm);
     const double eb = f ? 8.0 : 16.0;
-    int pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
-    if (f)
-        hipLaunchKernelGGL(bs_dots_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
-                           (const float2 *)t, (const float2 *)sv, n_, vpart_);
-    else
-        hipLaunchKernelGGL(bs_dots_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
-                           (const double2 *)t, (const double2 *)sv, n_, vpart_);
-    ctx_.prof_stop(pr2, strm, SGN_K_SEED_UPDATE, 2.0 * eb * n_, 8.0 * n_);
-    hipLaunchKernelGGL(bs_omega_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nvb_);
+    int pr2 = -1;
+    hipLaunchKernelGGL(bs_omega_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nb4);
     pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
     if (f)
         hipLaunchKernelGGL(bs_res_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
@@ -944,7 +918,9 @@ sgn_status BsStored::run(sgn_stats *stp)
     s0_ = rf_.sigma[seed_];
     c2_ = rf_.c * rf_.c;
     // workspace
-    const size_t scal = sizeof(z64) * ((size_t)nst_ + 2 * (size_t)kMaxBlocks) + sizeof(BsState) +
+    // partials: the dotting stencils' (nst_ blocks, two per block for the second one) and the vector kernels'
+    const size_t nvp = 2 * (size_t)std::max(nst_, kMaxBlocks);
+    const size_t scal = sizeof(z64) * ((size_t)nst_ + nvp) + sizeof(BsState) +
                         sizeof(BsHist) * (size_t)maxiter_ + 2 * sizeof(void *) * ((size_t)maxiter_ + poll_ + 4);
     char *a = static_cast<char *>(ctx_.ensure_arena(8 * b64_ + (mixed ? 7 * b32_ : 0) + c64 + scal + 256));
     char *q = a;
@@ -962,7 +938,7 @@ sgn_status BsStored::run(sgn_stats *stp)
     q = reinterpret_cast<char *>(((uintptr_t)q + 255) & ~(uintptr_t)255);
     spart_ = reinterpret_cast<z64 *>(q);
     vpart_ = spart_ + nst_;
-    S_ = reinterpret_cast<BsState *>(vpart_ + 2 * kMaxBlocks);
+    S_ = reinterpret_cast<BsState *>(vpart_ + nvp);
     hist_ = reinterpret_cast<BsHist *>(S_ + 1);
     rtab_ = reinterpret_cast<void **>(hist_ + maxiter_);
     stab_ = rtab_ + maxiter_ + poll_ + 2;

@@ -60,6 +60,7 @@ struct RhsParams {
     const void *w;
     z64 *partials;
     const z64 *in_scale;
+    int norm;  // with w: partials hold {conj(w) . out, ||out||^2} per block
 };
 
 struct StencilParams {
@@ -235,7 +236,14 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
         if constexpr (kDot) {
             if (threadIdx.x == 0)
                 for (int r = 0; r < NR; ++r)
-                    if (P.rhs[r].w) P.rhs[r].partials[blockIdx.x] = {0.0, 0.0};
+                    if (P.rhs[r].w) {
+                        if (P.rhs[r].norm) {
+                            P.rhs[r].partials[2 * blockIdx.x] = {0.0, 0.0};
+                            P.rhs[r].partials[2 * blockIdx.x + 1] = {0.0, 0.0};
+                        } else {
+                            P.rhs[r].partials[blockIdx.x] = {0.0, 0.0};
+                        }
+                    }
         }
         return;
     }
@@ -251,9 +259,9 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
     }
     const int s = blk * SGN_STENCIL_THREADS + threadIdx.x;
     const bool valid = s < P.V;
-    double dr[NR], di[NR];
+    double dr[NR], di[NR], dn[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) dr[r] = di[r] = 0.0;
+    for (int r = 0; r < NR; ++r) dr[r] = di[r] = dn[r] = 0.0;
     if (valid) {
         int c0 = s % P.L[0];
         int q = s / P.L[0];
@@ -310,19 +318,27 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
                         z64 a = cast<double>(ww[k]), o = cast<double>(acc[r][k]);
                         dr[r] += a.r * o.r + a.i * o.i;
                         di[r] += a.r * o.i - a.i * o.r;
+                        dn[r] += o.r * o.r + o.i * o.i;
                     }
                 }
             }
         }
     }
     if constexpr (kDot) {
-        __shared__ double lds[2 * (SGN_STENCIL_THREADS / 64)];
+        __shared__ double lds[3 * (SGN_STENCIL_THREADS / 64)];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (!P.rhs[r].w) continue;  // uniform
-            double v[2] = {dr[r], di[r]};
-            block_sum<2>(v, lds);
-            if (threadIdx.x == 0) P.rhs[r].partials[blockIdx.x] = {v[0], v[1]};
+            double v[3] = {dr[r], di[r], dn[r]};
+            block_sum<3>(v, lds);
+            if (threadIdx.x == 0) {
+                if (P.rhs[r].norm) {
+                    P.rhs[r].partials[2 * blockIdx.x] = {v[0], v[1]};
+                    P.rhs[r].partials[2 * blockIdx.x + 1] = {v[2], 0.0};
+                } else {
+                    P.rhs[r].partials[blockIdx.x] = {v[0], v[1]};
+                }
+            }
             __syncthreads();
         }
     }
@@ -444,7 +460,14 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
             store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, zero);
         }
         if constexpr (kDot) {
-            if (threadIdx.x == 0 && Q.w) Q.partials[bx] = {0.0, 0.0};
+            if (threadIdx.x == 0 && Q.w) {
+                if (Q.norm) {
+                    Q.partials[2 * bx] = {0.0, 0.0};
+                    Q.partials[2 * bx + 1] = {0.0, 0.0};
+                } else {
+                    Q.partials[bx] = {0.0, 0.0};
+                }
+            }
         }
         return;
     }
@@ -476,7 +499,7 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
         lds_store_spinor<R>(lds, B, i, acc);
     }
     __syncthreads();
-    double dr = 0.0, di = 0.0;
+    double dr = 0.0, di = 0.0, dn = 0.0;
     if (valid) {
         int c0 = s % P.L[0];
         int q = s / P.L[0];
@@ -522,16 +545,24 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
                     z64 a = cast<double>(ww[k]), o = cast<double>(acc[k]);
                     dr += a.r * o.r + a.i * o.i;
                     di += a.r * o.i - a.i * o.r;
+                    dn += o.r * o.r + o.i * o.i;
                 }
             }
         }
     }
     if constexpr (kDot) {
-        __shared__ double red[2 * 16];
+        __shared__ double red[3 * 16];
         if (Q.w) {  // uniform
-            double v[2] = {dr, di};
-            block_sum<2>(v, red);
-            if (threadIdx.x == 0) Q.partials[bx] = {v[0], v[1]};
+            double v[3] = {dr, di, dn};
+            block_sum<3>(v, red);
+            if (threadIdx.x == 0) {
+                if (Q.norm) {
+                    Q.partials[2 * bx] = {v[0], v[1]};
+                    Q.partials[2 * bx + 1] = {v[2], 0.0};
+                } else {
+                    Q.partials[bx] = {v[0], v[1]};
+                }
+            }
         }
     }
 }
@@ -692,6 +723,7 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
         Q.w = ep[r].w;
         Q.partials = ep[r].partials;
         Q.in_scale = ep[r].in_scale;
+        Q.norm = ep[r].norm ? 1 : 0;
         if (ep[r].w && !ep[r].partials) throw Failure{SGN_ERR_INVALID, "stencil dot without partial buffer"};
         ps.dot = ps.dot || ep[r].w != nullptr;
         ps.epi = ps.epi || ep[r].w != nullptr || ep[r].z != nullptr || ep[r].a != 1.0 || ep[r].in_scale != nullptr;

@@ -176,8 +176,9 @@ struct Epilogue {
     const z64 *b_dev = nullptr;   // if set, b is read from device memory (times b)
     const void *z = nullptr;      // same precision/layout as out
     const void *w = nullptr;      // dot partner, same precision/layout as out
-    z64 *partials = nullptr;      // one z64 per block when w != nullptr
+    z64 *partials = nullptr;      // one z64 per block when w != nullptr (two with norm)
     const z64 *in_scale = nullptr;  // if set: Op(in) is multiplied by *in_scale (device)
+    bool norm = false;            // with w: also ||out||^2, partials[2b] = dot, partials[2b+1] = {norm, 0}
 };
 
 // Launch the stencil on internal-layout fields.  Returns the number of blocks
