@@ -350,8 +350,9 @@ sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational
  * are captured once as a HIP graph (o->graph < 0: plain launches), and o->prec,
  * theta32, theta16 and delta give the mixed schedule of multishift_solve (FP64 ->
  * FP32 -> FP16 links, FP64 reliable updates of the seed; FP32 at most with
- * deflation).  If x_shift is set or o->basis_slots < 0, every shift keeps p_i, x_i
- * instead (FP64 only, scalars on the host, three synchronisations per iteration).
+ * deflation); requested x_i are lifted one by one at the end.  If o->basis_slots < 0,
+ * every shift keeps p_i, x_i instead (FP64 only, scalars on the host, three
+ * synchronisations per iteration).
  * o->basis_slots > 0 caps the stored vectors (SGN_ERR_NOMEM beyond it; 0: up to half
  * of the free memory).  o->verify is ignored.  stats: iterations, matvecs,
  * reliable_updates, shift_residual (collinear estimates), residual.  Problems run

@@ -318,8 +318,8 @@ lib.multishift_bicgstab.argtypes = lib.multishift_solve.argtypes
 
 def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
                         delta=0.0, poll=0, basis_slots=0, graph=True, stream=None):
-    """Multishift BiCGStab for every problem (stored basis and the mixed schedule unless the
-    per-shift solutions are requested, which is FP64 only); one stats dict per problem."""
+    """Multishift BiCGStab for every problem (stored basis and the mixed schedule; basis_slots < 0:
+    per-shift vectors, FP64 only); one stats dict per problem."""
     if isinstance(problems, Problem):
         problems = [problems]
     n = len(problems)

@@ -25,9 +25,10 @@
 //    BiCG solver applies (FP64 while the seed residual is above theta32, then
 //    FP32 vectors and stencil, FP16 links below theta16, FP64 reliable updates
 //    of the seed);
-//  * per-shift vectors (when the x_i are requested): FP64, every shift's p_i and
-//    x_i updated each iteration, scalars formed on the host from deterministic
-//    block partial sums, three synchronisations per iteration.
+//    When the x_i are requested each is one more lift at the end;
+//  * per-shift vectors (basis_slots < 0): FP64, every shift's p_i and x_i updated
+//    each iteration, scalars formed on the host from deterministic block partial
+//    sums, three synchronisations per iteration.
 #include <chrono>
 #include <complex>
 #include <vector>
@@ -723,6 +724,7 @@ class BsStored {
     void iterate(int count);
     void reliable_update(BsHead &h);
     void switch_phase(BsHead &h, int to);
+    void lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs, char *out);
 };
 
 void *BsStored::take_slot()
@@ -897,6 +899,35 @@ void BsStored::switch_phase(BsHead &h, int to)
     }
 }
 
+// out += sum_j cr_j r_j + sum_j cs_j s_j over the stored slots (r_0..r_K, s_0..s_{K-1})
+void BsStored::lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs, char *out)
+{
+    std::vector<BsSlot> sl;
+    std::vector<z64> cf;
+    for (int j = 0; j <= K; ++j) {
+        sl.push_back(BsSlot{rslots_[j], j < (int)rf32_.size() ? rf32_[j] : 0, 0});
+        cf.push_back({cr[j].real(), cr[j].imag()});
+    }
+    for (int j = 0; j < K; ++j) {
+        sl.push_back(BsSlot{sslots_[j], j < (int)sf32_.size() ? sf32_[j] : 0, 0});
+        cf.push_back({cs[j].real(), cs[j].imag()});
+    }
+    const int nk = (int)sl.size();
+    DeviceScratch dsl(sizeof(BsSlot) * nk), dcf(sizeof(z64) * nk);
+    SGN_HIP(hipMemcpy(dsl.p, sl.data(), sizeof(BsSlot) * nk, hipMemcpyHostToDevice));
+    SGN_HIP(hipMemcpy(dcf.p, cf.data(), sizeof(z64) * nk, hipMemcpyHostToDevice));
+    const int pr = ctx_.prof_start(s_, SGN_K_LIFT);
+    double bytes = 2.0 * b64_;
+    for (int j = 0; j < nk; ++j) bytes += sl[j].f32 ? (double)b32_ : (double)b64_;
+    for (int j0 = 0; j0 < nk; j0 += kBsLiftChunk)
+        hipLaunchKernelGGL(bs_lift_kernel, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, s_,
+                           static_cast<const BsSlot *>(dsl.p) + j0, static_cast<const z64 *>(dcf.p) + j0,
+                           std::min(kBsLiftChunk, nk - j0), (int)Sst_, (double2 *)out);
+    ctx_.prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * nk * (double)n_);
+    SGN_HIP(hipGetLastError());
+    SGN_HIP(hipStreamSynchronize(s_));  // before the coefficient buffers are freed
+}
+
 sgn_status BsStored::run(sgn_stats *stp)
 {
     const auto t_start = std::chrono::steady_clock::now();
@@ -1037,6 +1068,11 @@ sgn_status BsStored::run(sgn_stats *stp)
     if (K) SGN_HIP(hipMemcpy(hs.data(), hist_, sizeof(BsHist) * K, hipMemcpyDeviceToHost));
     const double lim = o_.tol * ynorm;
     std::vector<zc> dr(K + 1, 0.0), ds(K, 0.0);
+    std::vector<std::vector<zc>> xr_i, xs_i;  // per-shift coefficients when the x_i are requested
+    if (pb_.x_shift) {
+        xr_i.resize(ns_);
+        xs_i.resize(ns_);
+    }
     double worst = 0.0;
     for (int i = 0; i < ns_; ++i) {
         zc zeta = 1.0, zeta_prev = 1.0, pi = 1.0, ap = 1.0, bp = 0.0;
@@ -1074,45 +1110,17 @@ sgn_status BsStored::run(sgn_stats *stp)
         st.shift_residual[i] = res / ynorm;
         worst = std::max(worst, st.shift_residual[i]);
         if (i == seed_) continue;
+        if (pb_.x_shift) {
+            xr_i[i] = Xr;
+            xs_i[i] = Xs;
+        }
         for (int j = 0; j <= K; ++j) dr[j] += rf_.omega[i] * Xr[j];
         for (int j = 0; j < K; ++j) ds[j] += rf_.omega[i] * Xs[j];
     }
     if (result == SGN_ERR_NOT_CONVERGED && worst <= o_.tol) result = SGN_OK;
     // x_int = omega_seed x_seed + lift
     scale64({rf_.omega[seed_], 0.0}, x64_, tmp64_, n_, s_);
-    std::vector<BsSlot> sl;
-    std::vector<z64> cf;
-    for (int j = 0; j <= K; ++j) {
-        sl.push_back(BsSlot{rslots_[j], j < (int)rf32_.size() ? rf32_[j] : 0, 0});
-        cf.push_back({dr[j].real(), dr[j].imag()});
-    }
-    for (int j = 0; j < K; ++j) {
-        sl.push_back(BsSlot{sslots_[j], j < (int)sf32_.size() ? sf32_[j] : 0, 0});
-        cf.push_back({ds[j].real(), ds[j].imag()});
-    }
-    {
-        const int nk = (int)sl.size();
-        void *dsl = nullptr, *dcf = nullptr;
-        SGN_HIP(hipMalloc(&dsl, sizeof(BsSlot) * nk));
-        if (hipMalloc(&dcf, sizeof(z64) * nk) != hipSuccess) {
-            (void)hipFree(dsl);
-            throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: lift coefficients"};
-        }
-        SGN_HIP(hipMemcpy(dsl, sl.data(), sizeof(BsSlot) * nk, hipMemcpyHostToDevice));
-        SGN_HIP(hipMemcpy(dcf, cf.data(), sizeof(z64) * nk, hipMemcpyHostToDevice));
-        const int pr = ctx_.prof_start(s_, SGN_K_LIFT);
-        double bytes = 2.0 * b64_;
-        for (int j = 0; j < nk; ++j) bytes += sl[j].f32 ? (double)b32_ : (double)b64_;
-        for (int j0 = 0; j0 < nk; j0 += kBsLiftChunk)
-            hipLaunchKernelGGL(bs_lift_kernel, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, s_,
-                               static_cast<const BsSlot *>(dsl) + j0, static_cast<const z64 *>(dcf) + j0,
-                               std::min(kBsLiftChunk, nk - j0), (int)Sst_, (double2 *)tmp64_);
-        ctx_.prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * nk * (double)n_);
-        SGN_HIP(hipGetLastError());
-        SGN_HIP(hipStreamSynchronize(s_));
-        (void)hipFree(dsl);
-        (void)hipFree(dcf);
-    }
+    lift(K, dr, ds, tmp64_);
     unpack_spinor(lat_, tmp64_, rcan_, SGN_PREC_F64, s_);
     if (pb_.defl && pb_.defl->m > 0) {  // the exact x_i lie in range(I - P): drop rounding components
         DeviceScratch cd(sizeof(z64) * pb_.defl->m);
@@ -1122,6 +1130,19 @@ sgn_status BsStored::run(sgn_stats *stp)
         SGN_HIP(hipStreamSynchronize(s_));
     }
     axpby64({1.0, 0.0}, rcan_, {1.0, 0.0}, pb_.x, nc_, s_);
+    if (pb_.x_shift)  // each shift's own solution (the seed's is x itself)
+        for (int i = 0; i < ns_; ++i) {
+            if (!pb_.x_shift[i]) continue;
+            if (i == seed_) {
+                SGN_HIP(hipMemcpyAsync(tmp64_, x64_, b64_, hipMemcpyDeviceToDevice, s_));
+            } else {
+                hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)tmp64_,
+                                   make_double2(0.0, 0.0), n_);
+                SGN_HIP(hipGetLastError());
+                lift(K, xr_i[i], xs_i[i], tmp64_);
+            }
+            unpack_spinor(lat_, tmp64_, pb_.x_shift[i], SGN_PREC_F64, s_);
+        }
     SGN_HIP(hipStreamSynchronize(s_));
     st.iterations = K;
     st.matvecs = 4 * K + 1 + 2 * reliable_;
@@ -1153,8 +1174,8 @@ extern "C" sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, cons
         for (int k = 0; k < nprob; ++k) {
             const hipStream_t s = static_cast<hipStream_t>(stream);
             sgn_status sk;
-            if (pb[k].x_shift || o->basis_slots < 0) {
-                SGN_REQUIRE(o->prec == SGN_PREC_F64, "multishift_bicgstab: per-shift solutions are FP64 only");
+            if (o->basis_slots < 0) {
+                SGN_REQUIRE(o->prec == SGN_PREC_F64, "multishift_bicgstab: the per-shift form is FP64 only");
                 sk = solve_explicit(pb[k], *rf, *o, st ? st + k : nullptr, s);
             } else {
                 SGN_REQUIRE(pb[k].lat && pb[k].b && pb[k].x, "multishift_bicgstab: null problem field");

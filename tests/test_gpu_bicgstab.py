@@ -73,11 +73,12 @@ def test_bicgstab_shift_solutions_match_oracle():
     W = WilsonRef(U, dims, 0.2)
     om, sg, c = rational.coefficients(10, 0.2, 2.4)
     rf = sgn.sgn_rational_neuberger(10, 0.2, 2.4)
-    _, st, xs = _solve(lattice(U, dims), 0.25, b, rf, want_shifts=True, tol=1e-11)
     _, info = krylov.multishift_bicgstab(lambda v: W.apply(v, 0.25), b, om, sg, c, tol=1e-11, return_info=True)
-    worst = max(_rel(xs[i], info["X"][i]) for i in range(10))
-    print(f"BiCGStab per-shift solutions vs oracle: worst {worst:.1e}", flush=True)
-    assert worst < 1e-8
+    for form, kw in (("per-shift", dict(basis_slots=-1)), ("stored", {})):
+        _, st, xs = _solve(lattice(U, dims), 0.25, b, rf, want_shifts=True, tol=1e-11, **kw)
+        worst = max(_rel(xs[i], info["X"][i]) for i in range(10))
+        print(f"BiCGStab {form} form, shifted solutions vs oracle: worst {worst:.1e}", flush=True)
+        assert worst < 1e-8
 
 
 def test_deflated_bicgstab_against_dense():
@@ -112,7 +113,7 @@ def test_bicgstab_zero_source_and_errors():
         _solve(lat, 0.3, b, rf, tol=1e-11, maxiter=3)
     assert e.value.status == 5
     with pytest.raises(sgn.SgnError) as e:
-        _solve(lat, 0.3, b, rf, want_shifts=True, prec=sgn.F32)  # per-shift form: FP64 only
+        _solve(lat, 0.3, b, rf, basis_slots=-1, prec=sgn.F32)  # per-shift form: FP64 only
     assert e.value.status == 1
     with pytest.raises(sgn.SgnError) as e:
         _solve(lat, 0.3, b, rf, basis_slots=9)  # stored basis beyond its cap
@@ -165,3 +166,29 @@ def test_8x4_mixed_bicgstab_against_oracle():
     print(f"8^4 mixed BiCGStab: vs oracle {e:.2e}, {st['iterations']} iterations, {st['reliable_updates']} RU, "
           f"{st['total_ms']:.1f} ms", flush=True)
     assert e < 1e-8
+
+
+def test_full_size_bench_configuration_residuals_with_oracle_operator():
+    """24^3 x 48 in the benchmark's configuration (stored basis, FP64 -> FP32 -> FP16 links,
+    tolerance 1e-9, thresholds 1e-2 / 1e-5): every returned shifted solution satisfies its
+    system to the tolerance's order, checked with the oracle's operator on the CPU, and x is
+    their omega-weighted sum."""
+    dims = (24, 24, 24, 48)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    alpha, beta = 0.12, 2.6
+    rf = sgn.sgn_rational_neuberger(16, alpha, beta)
+    om, sg, c = rational.coefficients(16, alpha, beta)
+    lat = lattice(U, dims)
+    x, st, xs = _solve(lat, 0.2, b, rf, want_shifts=True, tol=1e-9, prec=sgn.F32_H16, theta32=1e-2,
+                       theta16=1e-5, delta=0.05)
+    print(f"24^3x48 mixed BiCGStab: iters {st['iterations']} reliable {st['reliable_updates']} "
+          f"{st['krylov_ms']:.0f} ms", flush=True)
+    W = WilsonRef(U, dims, 0.2)
+    y = c * W.apply(b, 0.2).ravel()
+    for i in (0, 5, 15):
+        Ax = W.apply(W.apply(xs[i], 0.2), 0.2).ravel()
+        res = np.linalg.norm(y - (c * c * Ax - sg[i] * xs[i])) / np.linalg.norm(y)
+        print(f"  shift {i}: oracle residual {res:.2e}", flush=True)
+        assert res < 1e-7
+    assert _rel(x, om @ np.stack(xs)) < 1e-12
