@@ -190,5 +190,5 @@ def test_full_size_bench_configuration_residuals_with_oracle_operator():
         Ax = W.apply(W.apply(xs[i], 0.2), 0.2).ravel()
         res = np.linalg.norm(y - (c * c * Ax - sg[i] * xs[i])) / np.linalg.norm(y)
         print(f"  shift {i}: oracle residual {res:.2e}", flush=True)
-        assert res < 1e-7
+        assert res < 5e-9  # measured 4.5e-10, 7.9e-10, 1.2e-11
     assert _rel(x, om @ np.stack(xs)) < 1e-12
