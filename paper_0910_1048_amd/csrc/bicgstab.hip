@@ -403,13 +403,20 @@ __device__ __forceinline__ bool bs_finite(z64 a) { return isfinite(a.r) && isfin
 template <typename R> struct BsVec;
 template <> struct BsVec<double> { using t = double2; };
 template <> struct BsVec<float> { using t = float2; };
+// the slot pointers come from device-side tables: state the global address space
 template <typename T> __device__ __forceinline__ z64 ldz(const T *p, int64_t e)
 {
-    const T v = p[e];
+    const T v = ((const SGN_GLOBAL T *)p)[e];
     return {(double)v.x, (double)v.y};
 }
-__device__ __forceinline__ void stz(double2 *p, int64_t e, z64 v) { p[e] = make_double2(v.r, v.i); }
-__device__ __forceinline__ void stz(float2 *p, int64_t e, z64 v) { p[e] = make_float2((float)v.r, (float)v.i); }
+__device__ __forceinline__ void stz(double2 *p, int64_t e, z64 v)
+{
+    ((SGN_GLOBAL double2 *)p)[e] = make_double2(v.r, v.i);
+}
+__device__ __forceinline__ void stz(float2 *p, int64_t e, z64 v)
+{
+    ((SGN_GLOBAL float2 *)p)[e] = make_float2((float)v.r, (float)v.i);
+}
 
 // alpha = rho / r^^H v from the dotting stencil's partials; the BiCG factors zeta_next
 __global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *part, int nb)

@@ -21,16 +21,30 @@ template <> struct SpinorStore<float> { using type = float4; static constexpr in
 // per-lane byte offset: lets the compiler use the SGPR-base addressing mode
 // instead of one 64-bit VGPR address per component (which costs ~2 VGPRs per
 // load in flight and made the stencil spill).
+// The fields always live in device (global) memory; saying so explicitly keeps the
+// accesses global_load/global_store when the pointer itself was read from memory (the
+// batched launches keep their parameters in device memory).  Generic pointers would
+// give flat instructions, which count against the LDS wait counter as well and so
+// serialise the stencil's LDS reads behind its outstanding memory loads.
+// (the host compilation pass of these device functions has no address spaces)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SGN_GLOBAL __attribute__((address_space(1)))
+#else
+#define SGN_GLOBAL
+#endif
+
 template <typename T>
 __device__ __forceinline__ T ld_off(const T *__restrict__ base, uint32_t byte_off)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    const SGN_GLOBAL char *b = (const SGN_GLOBAL char *)base;
+    return *reinterpret_cast<const SGN_GLOBAL T *>(b + byte_off);
 }
 
 template <typename T>
 __device__ __forceinline__ void st_off(T *__restrict__ base, uint32_t byte_off, T v)
 {
-    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+    SGN_GLOBAL char *b = (SGN_GLOBAL char *)base;
+    *reinterpret_cast<SGN_GLOBAL T *>(b + byte_off) = v;
 }
 
 __device__ __forceinline__ void load_spinor(const double2 *__restrict__ p, int S, int s, cpx<double> v[12])

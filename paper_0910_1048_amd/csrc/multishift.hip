@@ -232,13 +232,21 @@ template <typename R> struct VecT;
 template <> struct VecT<double> { using t = double2; };
 template <> struct VecT<float> { using t = float2; };
 
+// vectors are in device memory; the pointers come from device-side descriptors, so the
+// global address space is stated (global rather than flat instructions)
 template <typename T> __device__ __forceinline__ z64 ldz(const T *p, int64_t i)
 {
-    T v = p[i];
+    T v = ((const SGN_GLOBAL T *)p)[i];
     return {(double)v.x, (double)v.y};
 }
-__device__ __forceinline__ void stz(double2 *p, int64_t i, z64 v) { p[i] = make_double2(v.r, v.i); }
-__device__ __forceinline__ void stz(float2 *p, int64_t i, z64 v) { p[i] = make_float2((float)v.r, (float)v.i); }
+__device__ __forceinline__ void stz(double2 *p, int64_t i, z64 v)
+{
+    ((SGN_GLOBAL double2 *)p)[i] = make_double2(v.r, v.i);
+}
+__device__ __forceinline__ void stz(float2 *p, int64_t i, z64 v)
+{
+    ((SGN_GLOBAL float2 *)p)[i] = make_float2((float)v.r, (float)v.i);
+}
 
 // r_{k+1} = r_k - alpha q, r~ -= conj(alpha) q~, with partials of r~^H r_{k+1}
 // and ||r_{k+1}||^2.  Per-shift form: in place.  Stored-basis form: from slot k
