@@ -30,6 +30,7 @@
 //    each iteration, scalars formed on the host from deterministic block partial
 //    sums, three synchronisations per iteration.
 #include <chrono>
+#include <map>
 #include <complex>
 #include <vector>
 
@@ -718,14 +719,14 @@ class BsStored {
     void **rtab_ = nullptr, **stab_ = nullptr;  // device slot tables (r_k, s_k)
     std::vector<void *> rslots_, sslots_;
     std::vector<char> rf32_, sf32_;
-    size_t pool_next_ = 0;
-    int slot_cap_ = 0;
+    std::map<size_t, size_t> pool_next_;  // next unused buffer of each per-size pool
+    double slot_budget_ = 0.0, slot_bytes_ = 0.0;  // stored-basis budget and use, bytes
     int phase_ = 0, launched_ = 0, reliable_ = 0;
     hipGraphExec_t gexec_ = nullptr;
 
     bool lo() const { return phase_ >= 1; }
     sgn_prec sprec() const { return phase_ == 0 ? SGN_PREC_F64 : (phase_ == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16); }
-    void *take_slot();
+    void *take_slot(size_t bytes);
     void ensure_slots(int upto);
     void launch_iteration(hipStream_t strm);
     void iterate(int count);
@@ -734,27 +735,32 @@ class BsStored {
     void lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs, char *out);
 };
 
-void *BsStored::take_slot()
+// a slot buffer of the given size (FP64 or FP32 vector) from the context's pools
+void *BsStored::take_slot(size_t bytes)
 {
-    auto &pool = ctx_.basis_pools[b64_];
-    if (pool_next_ == pool.size()) {
+    if (slot_bytes_ + (double)bytes > slot_budget_)
+        throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: stored basis exceeds its budget (basis_slots)"};
+    auto &pool = ctx_.basis_pools[bytes];
+    size_t &next = pool_next_[bytes];
+    if (next == pool.size()) {
         void *b = nullptr;
-        if (hipMalloc(&b, b64_) != hipSuccess) {
+        if (hipMalloc(&b, bytes) != hipSuccess) {
             (void)hipGetLastError();
             throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: stored basis does not fit"};
         }
         pool.push_back(b);
     }
-    return pool[pool_next_++];
+    slot_bytes_ += (double)bytes;
+    return pool[next++];
 }
 
-// r-slots 0 .. upto + 1 and s-slots 0 .. upto
+// r-slots 0 .. upto + 1 and s-slots 0 .. upto; slots first written in the FP32 phase are FP32-sized
 void BsStored::ensure_slots(int upto)
 {
-    if (2 * upto + 3 > slot_cap_) throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: stored basis exceeds basis_slots"};
     const size_t r0 = rslots_.size(), s0 = sslots_.size();
-    while ((int)rslots_.size() < upto + 2) rslots_.push_back(take_slot());
-    while ((int)sslots_.size() < upto + 1) sslots_.push_back(take_slot());
+    const size_t bytes = lo() ? b32_ : b64_;
+    while ((int)rslots_.size() < upto + 2) rslots_.push_back(take_slot(bytes));
+    while ((int)sslots_.size() < upto + 1) sslots_.push_back(take_slot(bytes));
     if (rslots_.size() > r0)
         SGN_HIP(hipMemcpy(rtab_ + r0, rslots_.data() + r0, sizeof(void *) * (rslots_.size() - r0),
                           hipMemcpyHostToDevice));
@@ -980,14 +986,14 @@ sgn_status BsStored::run(sgn_stats *stp)
     hist_ = reinterpret_cast<BsHist *>(S_ + 1);
     rtab_ = reinterpret_cast<void **>(hist_ + maxiter_);
     stab_ = rtab_ + maxiter_ + poll_ + 2;
-    // stored-basis budget: basis_slots > 0 slots, else up to half of the free device memory
+    // stored-basis budget: basis_slots > 0 FP64-sized vectors, else up to half of the free device
+    // memory (counting the pooled buffers as free)
     {
         size_t fr = 0, tot = 0;
         SGN_HIP(hipMemGetInfo(&fr, &tot));
-        size_t held = 0;
-        for (auto &kv : ctx_.basis_pools) held += kv.first * kv.second.size();
-        const double budget = o_.basis_slots > 0 ? (double)o_.basis_slots : 0.5 * (double)(fr + held) / (double)b64_;
-        slot_cap_ = (int)std::min<double>(budget, 2.0 * maxiter_ + 2 * poll_ + 4);
+        double held = 0.0;
+        for (auto &kv : ctx_.basis_pools) held += (double)kv.first * kv.second.size();
+        slot_budget_ = o_.basis_slots > 0 ? (double)o_.basis_slots * b64_ : 0.5 * ((double)fr + held);
     }
     sgn_stats st{};
     st.nshift = ns_;
