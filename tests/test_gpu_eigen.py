@@ -88,12 +88,13 @@ def test_c1_deflated_sign_with_found_eigenpairs():
     defl = sgn.Deflation(L, R, lam)
     bd = dev(b)
     x = torch.empty_like(bd)
-    for prec, tol in ((sgn.F64, 1e-11), (sgn.F32_H16, 1e-10)):
-        st = sgn.multishift_solve(sgn.Problem(lat, mu, bd, x, defl), rf, tol=tol, prec=prec)[0]
-        e = _rel(host(x), g["sign_b"])
-        print(f"C1 deflated sign prec={prec}: {s} poles (alpha {alpha:.4f}), {st['iterations']} iterations, "
-              f"vs dense sign {e:.1e}", flush=True)
-        assert e < 1e-9
+    for solver in (sgn.multishift_solve, sgn.multishift_bicgstab):
+        for prec, tol in ((sgn.F64, 1e-11), (sgn.F32_H16, 1e-10)):
+            st = solver(sgn.Problem(lat, mu, bd, x, defl), rf, tol=tol, prec=prec)[0]
+            e = _rel(host(x), g["sign_b"])
+            print(f"C1 deflated sign, {solver.__name__} prec={prec}: {s} poles (alpha {alpha:.4f}), "
+                  f"{st['iterations']} iterations, vs dense sign {e:.1e}", flush=True)
+            assert e < 1e-9
 
 
 def test_hermitian_case_left_equals_right():
