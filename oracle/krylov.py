@@ -9,6 +9,9 @@
   multishift_bicg-- BiCG-LR(m): BiCG iterates for all shifted systems from one
                     two-sided Lanczos sequence (section "Two-sided Lanczos with
                     rational functions"; shift invariance of Krylov spaces).
+  multishift_qmr -- QMR iterates for all shifted systems from one two-sided
+                    Lanczos sequence (the QMR variant named beside BiCG in the
+                    same section): per-shift least squares on the tridiagonal.
   deflation      -- LR deflation: P = R L^H, x_P = R f(Lambda) L^H b (section
                     "Deflation", Eqs. (eq:action), (exact_proj)).
 
@@ -443,6 +446,82 @@ def multishift_bicg(A, Ah, b, omega, sigma, c, tol=1e-12, maxiter=20000,
     x = deflation_xP(L, R, lam, b) + omega @ X
     if return_info:
         return x, dict(iterations=it, X=X, ynorm=ynorm, seed=seed)
+    return x
+
+
+def multishift_qmr(A, Ah, b, omega, sigma, c, tol=1e-12, maxiter=2000, k=None, check_every=1,
+                   L=None, R=None, lam=None, return_info=False):
+    """Multishift QMR for (A' - sigma_i) x_i = y, y = c A (I-P) b (QMR is the
+    smoother alternative to BiCG named in the section "Two-sided Lanczos with
+    rational functions"; shifted QMR after Freund).
+
+    One two-sided Lanczos sequence on A' = c^2 A^2 with v_1 = y/||y|| and shadow
+    w_1 = v_1 (||v_j|| = 1, w_j^H v_j = 1) gives A' V_k = V_{k+1} Tbar_k, Tbar_k
+    the (k+1) x k tridiagonal matrix of the recurrence coefficients.  As the
+    Krylov space does not depend on the shift,
+      (A' - sigma_i) V_k = V_{k+1} (Tbar_k - sigma_i Ibar_k),
+    and the QMR iterate of shift i is x_i = V_k z_i with z_i the least-squares
+    solution of  min || ||y|| e_1 - (Tbar_k - sigma_i Ibar_k) z ||_2;  the
+    minimum tau_i (quasi-residual) bounds the true residual by ||V_{k+1}|| tau_i.
+    Stops after k steps if k is given, else once tau_i <= tol ||y|| for every
+    shift (checked every check_every steps).  Returns x = x_P + sum_i omega_i x_i."""
+    b = np.asarray(b, dtype=np.complex128).ravel()
+    omega = np.asarray(omega, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    c2 = c * c
+    Ap = lambda v: c2 * A(A(v))
+    Aph = lambda v: c2 * Ah(Ah(v))
+    xP = deflation_xP(L, R, lam, b)
+    y = c * A(project_out(L, R, b))
+    ynorm = np.linalg.norm(y)
+    s = len(sigma)
+    n = b.size
+    X = np.zeros((s, n), dtype=np.complex128)
+    tau = np.zeros(s)
+    if ynorm == 0.0:
+        return (xP, dict(iterations=0, X=X, tau=tau, ynorm=0.0, Tbar=None)) if return_info else xP
+    kmax = k if k is not None else maxiter
+    V = [y / ynorm]
+    Tbar = np.zeros((kmax + 1, kmax), dtype=np.complex128)
+    v_prev = w_prev = np.zeros(n, dtype=np.complex128)
+    w = V[0].copy()
+    Z = None
+    steps = 0
+    for j in range(kmax):
+        v = V[j]
+        u = Ap(v)
+        alpha = np.vdot(w, u)                      # w_j^H A' v_j
+        vh = u - alpha * v - (Tbar[j - 1, j] * v_prev if j > 0 else 0.0)
+        delta = np.linalg.norm(vh)                 # h_{j+1,j}
+        Tbar[j, j] = alpha
+        Tbar[j + 1, j] = delta
+        steps = j + 1
+        if (k is None and steps % check_every == 0) or steps == kmax or delta == 0.0:
+            rhs = np.zeros(steps + 1, dtype=np.complex128)
+            rhs[0] = ynorm
+            Z = []
+            for i in range(s):
+                M = Tbar[:steps + 1, :steps] - sigma[i] * np.eye(steps + 1, steps)
+                z = np.linalg.lstsq(M, rhs, rcond=None)[0]
+                Z.append(z)
+                tau[i] = np.linalg.norm(rhs - M @ z)
+            if delta == 0.0 or steps == kmax or (k is None and np.all(tau <= tol * ynorm)):
+                break
+        wh = Aph(w) - np.conj(alpha) * w - (np.conj(Tbar[j, j - 1]) * w_prev if j > 0 else 0.0)
+        vn = vh / delta
+        gamma = np.vdot(wh, vn)                    # h_{j,j+1} = w_hat^H v_{j+1}
+        if abs(gamma) < 1e-14 * np.linalg.norm(wh):
+            raise Breakdown(f"two-sided Lanczos breakdown at step {j + 1}")
+        Tbar[j, j + 1] = gamma
+        v_prev, w_prev = v, w
+        w = wh / np.conj(gamma)
+        V.append(vn)
+    Vk = np.array(V[:steps])
+    for i in range(s):
+        X[i] = Vk.T @ Z[i]
+    x = xP + omega @ X
+    if return_info:
+        return x, dict(iterations=steps, X=X, tau=tau.copy(), ynorm=ynorm, y=y, Tbar=Tbar[:steps + 1, :steps])
     return x
 
 
