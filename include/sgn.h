@@ -361,6 +361,31 @@ sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational
 sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                                sgn_stats *stats, void *stream);
 
+/* Multishift QMR (the QMR variant named beside BiCG in the section "Two-sided
+ * Lanczos with rational functions"; shifted QMR after Freund): the same problems,
+ * rational function and result as multishift_solve.  One two-sided Lanczos
+ * sequence on A' = c^2 H_W(mu)^2 (v_1 = y/||y||, shadow w_1 = v_1; four stencil
+ * applications per step, two with mu and two with -mu) serves every shift: with
+ * A' V_k = V_{k+1} Tbar_k, the iterate of shift i is x_i = V_k z_i where z_i
+ * minimises || ||y|| e_1 - (Tbar_k - sigma_i Ibar_k) z ||_2 (Givens QR on the
+ * host, one column per step).  Converged when that quasi-residual tau_i is at
+ * most tol ||y|| for every shift (checked every o->poll steps, default 4); the
+ * true residual is at most ||V_{k+1}||_2 tau_i <= sqrt(k+1) tau_i.  Every basis
+ * vector is stored (FP64, pooled in the context between calls; o->basis_slots > 0
+ * caps them, 0: up to half of the free device memory, SGN_ERR_NOMEM beyond the
+ * cap, < 0 is invalid) and x = x_P + V_k sum_i omega_i z_i is one lift at the
+ * end; requested x_i are lifted one by one.  With LR deflation the Krylov part
+ * of x and of each x_i is projected with (I - P) at the end.  o->prec: SGN_PREC_F64,
+ * or SGN_PREC_F32 / SGN_PREC_F32_H16 for the stencil in FP32 (FP16 links) with
+ * FP64 recurrences, no reliable updates (accuracy ~ the stencil's rounding);
+ * theta32, theta16, delta and graph are ignored.  stats: iterations, matvecs,
+ * shift_residual (tau_i / ||y||; with o->verify the FP64 true residuals), residual,
+ * krylov_ms, small_ms (Givens updates).  Problems run one after another.
+ * Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter (x holds the last
+ * iterate), SGN_ERR_BREAKDOWN on a Lanczos breakdown (w^^H v vanishing). */
+sgn_status multishift_qmr(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
+                          sgn_stats *stats, void *stream);
+
 /* ------------------------------------------------------------------ accuracy measure */
 /* Accuracy of an approximate sign function S (numerical-results section): as
  * sign(A)^2 = I, the value 1/2 ||S(S b) - b|| / ||b|| estimates the error of S
@@ -384,7 +409,8 @@ typedef enum {
     SGN_K_SHIFT_UPDATE = 3,   /* multishift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i (seed only
                                  when the basis is stored); BiCGStab: the seed's x and p */
     SGN_K_SEED_UPDATE = 4,    /* multishift: r, r~ updates with their inner products; BiCGStab: s = r -
-                                 alpha v, the t^H s, t^H t dots, r' = s - omega t with its dots */
+                                 alpha v, the t^H s, t^H t dots, r' = s - omega t with its dots; QMR:
+                                 the Lanczos update of v and w with their inner products */
     SGN_K_LIFT = 5,           /* multishift: sum of the stored vectors with their coefficients */
     SGN_K_COUNT = 6
 } sgn_kernel_class;

@@ -343,6 +343,36 @@ def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, 
     return [st[i].as_dict() for i in range(n)]
 
 
+lib.multishift_qmr.argtypes = lib.multishift_solve.argtypes
+
+
+def multishift_qmr(problems, rational, tol=1e-10, maxiter=10000, prec=F64, poll=0, basis_slots=0, verify=False,
+                   stream=None):
+    """Multishift QMR for every problem (stored Lanczos basis, per-shift least squares); one stats dict
+    per problem."""
+    if isinstance(problems, Problem):
+        problems = [problems]
+    n = len(problems)
+    arr = (_Problem * n)()
+    keep = []
+    for i, p in enumerate(problems):
+        arr[i].lat = p.lat.h
+        arr[i].mu = float(p.mu)
+        arr[i].b = C.c_void_p(p.b.data_ptr())
+        arr[i].x = C.c_void_p(p.x.data_ptr())
+        if p.defl is not None:
+            arr[i].defl = C.pointer(p.defl.struct)
+        if p.x_shift is not None:
+            xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
+            keep.append(xs)
+            arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
+    o = MsOpts(float(tol), int(maxiter), int(prec), 0.0, 0.0, 0.0, int(poll), 1 if verify else 0,
+               int(basis_slots), 0)
+    st = (Stats * max(n, 1))()
+    check(lib.multishift_qmr(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_qmr")
+    return [st[i].as_dict() for i in range(n)]
+
+
 K_STENCIL_F64, K_STENCIL_F32, K_STENCIL_H16, K_SHIFT_UPDATE, K_SEED_UPDATE, K_LIFT, K_COUNT = range(7)
 KERNEL_NAMES = ["stencil_f64", "stencil_f32", "stencil_h16", "shift_update", "seed_update", "basis_lift"]
 

@@ -1,0 +1,169 @@
+"""Parity of the HIP multishift QMR (multishift_qmr) with the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import WilsonRef, dense, krylov, rational
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_0910_1048_amd as sgn  # noqa: E402
+from gpu_util import dev, host, lattice  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_dense.npz")
+
+
+def _rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _solve(lat, mu, b, rf, defl=None, want_shifts=False, **kw):
+    bd = dev(b)
+    x = torch.empty_like(bd)
+    xs = [torch.empty_like(bd) for _ in range(rf.s)] if want_shifts else None
+    st = sgn.multishift_qmr(sgn.Problem(lat, mu, bd, x, defl, xs), rf, **kw)[0]
+    if want_shifts:
+        return host(x).ravel(), st, [host(t).ravel() for t in xs]
+    return host(x).ravel(), st
+
+
+def test_c1_qmr_matches_dense_rational():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    lat = lattice(U, dims)
+    x, st = _solve(lat, 0.3, b, rf, tol=1e-11)
+    e = _rel(x, g["g16_b"])
+    bd = dev(b)
+    xb = torch.empty_like(bd)
+    sb = sgn.multishift_solve(sgn.Problem(lat, 0.3, bd, xb), rf, tol=1e-11)[0]
+    print(f"C1 QMR: vs dense g16 {e:.2e}, {st['iterations']} iterations ({st['matvecs']} matvecs); "
+          f"BiCG {sb['iterations']} iterations, QMR vs BiCG {_rel(x, host(xb)):.1e}", flush=True)
+    assert e < 1e-8
+    assert _rel(x, host(xb)) < 1e-8
+
+
+def test_8x4_qmr_against_oracle_same_steps():
+    """The oracle runs exactly the GPU's number of Lanczos steps; x and every x_i agree."""
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(16, 0.15, 2.6)
+    rf = sgn.sgn_rational_neuberger(16, 0.15, 2.6)
+    x, st, xs = _solve(lattice(U, dims), 0.2, b, rf, want_shifts=True, tol=1e-11)
+    k = st["iterations"]
+    xo, info = krylov.multishift_qmr(lambda v: W.apply(v, 0.2), lambda v: W.apply_adj(v, 0.2), b, om, sg, c,
+                                     k=k, return_info=True)
+    e = _rel(x, xo)
+    worst = max(_rel(xs[i], info["X"][i]) for i in range(16))
+    tau_gpu = np.array(st["shift_residual"][:16])
+    tau_or = info["tau"] / info["ynorm"]
+    print(f"8^4 QMR: {k} steps, {st['krylov_ms']:.1f} ms; vs oracle x {e:.2e}, worst x_i {worst:.2e}; "
+          f"max tau {tau_gpu.max():.2e} (oracle {tau_or.max():.2e})", flush=True)
+    assert e < 1e-8
+    assert worst < 1e-8
+    assert np.all(tau_gpu <= 1e-11)
+    assert tau_or.max() <= 1e-10
+
+
+def test_qmr_verified_residuals_and_bound():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 2)
+    b = synth.gaussian_source(dims, 2).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    rf = sgn.sgn_rational_neuberger(10, 0.2, 2.4)
+    om, sg, c = rational.coefficients(10, 0.2, 2.4)
+    x, st, xs = _solve(lattice(U, dims), 0.25, b, rf, want_shifts=True, tol=1e-10, verify=True)
+    k = st["iterations"]
+    y = c * W.apply(b, 0.25).ravel()
+    for i in range(10):
+        Ax = W.apply(W.apply(xs[i], 0.25), 0.25).ravel()
+        res = np.linalg.norm(y - (c * c * Ax - sg[i] * xs[i])) / np.linalg.norm(y)
+        assert res == pytest.approx(st["shift_residual"][i], rel=1e-3, abs=1e-14)
+        assert res <= np.sqrt(k + 1) * 1e-10
+    assert _rel(x, om @ np.stack(xs)) < 1e-12
+    print(f"QMR verified residuals: {k} steps, max {st['residual']:.2e}", flush=True)
+
+
+def test_deflated_qmr_against_dense():
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    H = WilsonRef(U, dims, 0.2).dense(0.3)
+    lam, R = np.linalg.eig(H)
+    Linv = np.linalg.inv(R)
+    idx = np.argsort(np.abs(lam.real))[:8]
+    Lr, Rr, lm = Linv[idx].conj(), R[:, idx].T.copy(), lam[idx]
+    rest = np.delete(lam, idx)
+    alpha, beta = float(np.abs(rest).min()), float(np.abs(lam).max())
+    om, sg, c = rational.coefficients(12, alpha, beta)
+    rf = sgn.sgn_rational_neuberger(12, alpha, beta)
+    defl = sgn.Deflation(dev(Lr), dev(Rr), lm)
+    x, st = _solve(lattice(U, dims), 0.3, b, rf, defl=defl, tol=1e-12)
+    target = krylov.deflation_xP(Lr.T, Rr.T, lm, b) + dense.rational_dense(H, krylov.project_out(Lr.T, Rr.T, b),
+                                                                             om, sg, c)
+    print(f"deflated QMR: {st['iterations']} steps, vs dense {_rel(x, target):.1e}", flush=True)
+    assert _rel(x, target) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [sgn.F32, sgn.F32_H16])
+def test_c1_qmr_low_precision_stencil(prec):
+    """FP32 (FP16-link) stencil with FP64 recurrences: accuracy at the stencil's rounding level."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    x, st = _solve(lattice(U, dims), 0.3, b, rf, tol=1e-9, prec=prec)
+    e = _rel(x, g["g16_b"])
+    print(f"C1 QMR prec={prec}: vs dense g16 {e:.2e}, {st['iterations']} steps", flush=True)
+    assert e < (1e-5 if prec == sgn.F32 else 1e-2)
+
+
+def test_qmr_zero_source_and_errors():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    lat = lattice(U, dims)
+    rf = sgn.sgn_rational_neuberger(8, 0.2, 2.4)
+    x, st = _solve(lat, 0.3, np.zeros_like(b), rf)
+    assert np.all(x == 0) and st["iterations"] == 0
+    with pytest.raises(sgn.SgnError) as e:
+        _solve(lat, 0.3, b, rf, tol=1e-11, maxiter=3)
+    assert e.value.status == 5
+    with pytest.raises(sgn.SgnError) as e:
+        _solve(lat, 0.3, b, rf, basis_slots=-1)
+    assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        _solve(lat, 0.3, b, rf, basis_slots=9)  # stored basis beyond its cap
+    assert e.value.status == 3
+
+
+def test_full_size_qmr_residuals_with_oracle_operator():
+    """24^3 x 48, 16 poles, tolerance 1e-9 on the quasi-residual: sampled shifted solutions
+    satisfy their systems (checked with the oracle's operator on the CPU)."""
+    dims = (24, 24, 24, 48)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    alpha, beta = 0.12, 2.6
+    rf = sgn.sgn_rational_neuberger(16, alpha, beta)
+    om, sg, c = rational.coefficients(16, alpha, beta)
+    x, st, xs = _solve(lattice(U, dims), 0.2, b, rf, want_shifts=True, tol=1e-9)
+    k = st["iterations"]
+    print(f"24^3x48 QMR: {k} steps, {st['krylov_ms']:.0f} ms", flush=True)
+    W = WilsonRef(U, dims, 0.2)
+    y = c * W.apply(b, 0.2).ravel()
+    for i in (0, 5, 15):
+        Ax = W.apply(W.apply(xs[i], 0.2), 0.2).ravel()
+        res = np.linalg.norm(y - (c * c * Ax - sg[i] * xs[i])) / np.linalg.norm(y)
+        print(f"  shift {i}: oracle residual {res:.2e}, quasi-residual {st['shift_residual'][i]:.2e}", flush=True)
+        assert res < np.sqrt(k + 1) * 1e-9
+    assert _rel(x, om @ np.stack(xs)) < 1e-12

@@ -105,9 +105,10 @@ def test_qmr_residual_bound_and_monotone_quasi_residual(rng):
         _, info = krylov.multishift_qmr(*_ops(A), b, om, sg, c, k=k, return_info=True)
         for i, s in enumerate(sg):
             r = np.linalg.norm(info["y"] - (Ap - s * np.eye(n)) @ info["X"][i])
-            assert r <= np.sqrt(k + 1) * info["tau"][i] * (1 + 1e-10)
+            # slack for the rounding floor of r and tau (~1e-15 ||y||)
+            assert r <= np.sqrt(k + 1) * info["tau"][i] * (1 + 1e-10) + 1e-13 * info["ynorm"]
         if prev is not None:
-            assert np.all(info["tau"] <= prev * (1 + 1e-12))
+            assert np.all(info["tau"] <= prev * (1 + 1e-12) + 1e-13 * info["ynorm"])
         prev = info["tau"]
 
 
