@@ -9,8 +9,8 @@ multishift_bicgstab.  Inputs (gauge links, source, coefficients) are resident in
 HBM before the timed region.
 
 Reported beside it on the same GPU: the plain FP64 single-RHS form of the same
-solve (solves/s), the multishift BiCG solver (multishift_solve) mixed and FP64 at
-the same accuracy target, the error of every result against an FP64 solve to
+solve (solves/s), the multishift BiCG solver (multishift_solve) mixed and FP64 and
+the multishift QMR solver (multishift_qmr) mixed and FP64 at the same accuracy target, the error of every result against an FP64 solve to
 tolerance 1e-12, the live per-kernel timing of the solver's own launches (HIP
 events on the launch stream) as HBM roofline fractions, and the CPU oracle timed
 on this host's cores on a bounded sample of the same solve.
@@ -40,6 +40,9 @@ MIXED = dict(theta32=1e-2, theta16=1e-5, delta=0.05)
 # the BiCG solver at the same target: tolerance 1e-8, FP32 below 1e-1, FP16 links below 1e-3
 BICG_TOL = 1e-8
 BICG_MIXED = dict(theta32=1e-1, theta16=1e-3, delta=0.05)
+# the QMR solver at the same target: FP32 stencil below a quasi-residual of 1e-3 ||y||, FP16 links
+# below 1e-6 ||y|| (error 2.4e-9 on this workload; (1e-2, 1e-5) gives 5.8e-9)
+QMR_MIXED = dict(theta32=1e-3, theta16=1e-6)
 PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
 # PMC byte counts of the solver kernels, taken with rocprofv3 on this benchmark; valid only
 # while the kernel sources are the ones they were measured on
@@ -86,7 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bicg", action="store_true", help="skip the multishift BiCG comparison legs")
+    ap.add_argument("--no-bicg", action="store_true",
+                    help="skip the comparison legs (multishift BiCG and multishift QMR, mixed and FP64)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device-to-device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -187,6 +191,23 @@ def main():
             log(f"[bench] BiCG {name}: {tb * 1e3:.1f} ms/solve, {sb['iterations']} iterations, "
                 f"err {bicg[name]['err_vs_fp64_ref']:.2e}")
 
+    # ---- multishift QMR (stored Lanczos basis, per-shift least squares) at the same target
+    qmr = None
+    if not args.no_bicg:
+        qmr = {"tol": BICG_TOL, "mixed_schedule": QMR_MIXED}
+        for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
+            kw = QMR_MIXED if prec != sgn.F64 else {}
+            sgn.multishift_qmr(prob, rf, tol=BICG_TOL, prec=prec, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sq = sgn.multishift_qmr(prob, rf, tol=BICG_TOL, prec=prec, **kw)[0]
+            torch.cuda.synchronize()
+            tq = time.perf_counter() - t0
+            qmr[name] = {"solves_per_s": round(1.0 / tq, 4), "ms_per_solve": round(tq * 1e3, 2),
+                         "iterations": sq["iterations"], "err_vs_fp64_ref": err_of(x)}
+            log(f"[bench] QMR {name}: {tq * 1e3:.1f} ms/solve, {sq['iterations']} steps, "
+                f"err {qmr[name]['err_vs_fp64_ref']:.2e}")
+
     # ---- roofline: dominant kernel by time, and the stencil (Dslash) itself
     traffic = measured_traffic()
 
@@ -254,6 +275,7 @@ def main():
         "fp64_err_vs_ref": err64,
         "speedup_vs_fp64": round(value * t64, 3),
         "bicg": bicg,
+        "qmr": qmr,
         "roofline": roofline,
         "stencil_roofline": stencils,
         "kernel_time_share": time_share,

@@ -376,9 +376,12 @@ sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_ratio
  * cap, < 0 is invalid) and x = x_P + V_k sum_i omega_i z_i is one lift at the
  * end; requested x_i are lifted one by one.  With LR deflation the Krylov part
  * of x and of each x_i is projected with (I - P) at the end.  o->prec: SGN_PREC_F64,
- * or SGN_PREC_F32 / SGN_PREC_F32_H16 for the stencil in FP32 (FP16 links) with
- * FP64 recurrences, no reliable updates (accuracy ~ the stencil's rounding);
- * theta32, theta16, delta and graph are ignored.  stats: iterations, matvecs,
+ * or the mixed schedule SGN_PREC_F32: FP64 steps while the largest tau_i is above
+ * theta32 ||y||, then the stencil in FP32 (SGN_PREC_F32_H16: and with FP16 links
+ * below theta16 ||y||); the recurrences, coefficients and basis stay FP64.  There
+ * are no reliable updates: the stencil's rounding enters the Lanczos relation
+ * weighted by the size of the late coefficients, which shrink with tau, so the
+ * thresholds set the accuracy.  delta and graph are ignored.  stats: iterations, matvecs,
  * shift_residual (tau_i / ||y||; with o->verify the FP64 true residuals), residual,
  * krylov_ms, small_ms (Givens updates).  Problems run one after another.
  * Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter (x holds the last

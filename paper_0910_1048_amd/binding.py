@@ -346,10 +346,10 @@ def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, 
 lib.multishift_qmr.argtypes = lib.multishift_solve.argtypes
 
 
-def multishift_qmr(problems, rational, tol=1e-10, maxiter=10000, prec=F64, poll=0, basis_slots=0, verify=False,
-                   stream=None):
-    """Multishift QMR for every problem (stored Lanczos basis, per-shift least squares); one stats dict
-    per problem."""
+def multishift_qmr(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0, poll=0,
+                   basis_slots=0, verify=False, stream=None):
+    """Multishift QMR for every problem (stored Lanczos basis, per-shift least squares, FP64 or the
+    mixed stencil schedule); one stats dict per problem."""
     if isinstance(problems, Problem):
         problems = [problems]
     n = len(problems)
@@ -366,8 +366,8 @@ def multishift_qmr(problems, rational, tol=1e-10, maxiter=10000, prec=F64, poll=
             xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
             keep.append(xs)
             arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
-    o = MsOpts(float(tol), int(maxiter), int(prec), 0.0, 0.0, 0.0, int(poll), 1 if verify else 0,
-               int(basis_slots), 0)
+    o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), 0.0, int(poll),
+               1 if verify else 0, int(basis_slots), 0)
     st = (Stats * max(n, 1))()
     check(lib.multishift_qmr(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_qmr")
     return [st[i].as_dict() for i in range(n)]

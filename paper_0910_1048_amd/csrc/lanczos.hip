@@ -530,8 +530,14 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     SGN_HIP(hipSetDevice(ctx.device));
     const int64_t V = lat.V, Sst = lat.S, nc = 12 * V, ni = 12 * Sst;
     const size_t b64 = (size_t)nc * 16, i64 = (size_t)ni * 16, b32 = (size_t)ni * 8;
-    const sgn_prec sp = o.prec;
-    const bool f32 = sp != SGN_PREC_F64;
+    // precision schedule: FP64 steps while the largest quasi-residual is above theta32 ||y||,
+    // then the stencil in FP32 (and with FP16 links below theta16 ||y|| for SGN_PREC_F32_H16);
+    // the recurrences and the basis stay FP64
+    const bool mixed = o.prec != SGN_PREC_F64;
+    const double theta32 = mixed ? (o.theta32 > 0 ? o.theta32 : 1e-3) : 0.0;
+    const double theta16 = o.prec == SGN_PREC_F32_H16 ? (o.theta16 > 0 ? o.theta16 : 1e-6) : 0.0;
+    sgn_prec sp = SGN_PREC_F64;
+    bool f32 = false;
     const int ns = rf.s;
     const double c2 = rf.c * rf.c;
     const int maxiter = o.maxiter > 0 ? o.maxiter : 10000;
@@ -590,8 +596,9 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
         }
     };
     ensure(0);
-    DevBuf Wb(3 * i64), u(f32 ? 0 : i64), z(f32 ? 0 : i64);
-    DevBuf v32(f32 ? b32 : 0), w32(f32 ? b32 : 0), t32(f32 ? b32 : 0), u32(f32 ? b32 : 0), z32(f32 ? b32 : 0);
+    DevBuf Wb(3 * i64), u(i64), z(i64);
+    DevBuf v32(mixed ? b32 : 0), w32(mixed ? b32 : 0), t32(mixed ? b32 : 0), u32(mixed ? b32 : 0),
+        z32(mixed ? b32 : 0);
     const size_t nscal = sizeof(z64) * (5 * (size_t)maxiter + 2) + sizeof(int) * maxiter;
     DevBuf scal(nscal);
     LzScalars S;
@@ -608,10 +615,6 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     SGN_HIP(hipMemcpyAsync(S.tw, &s0, sizeof(z64), hipMemcpyHostToDevice, s));
     SGN_HIP(hipMemcpyAsync(slots[0], y.p, i64, hipMemcpyDeviceToDevice, s));
     SGN_HIP(hipMemcpyAsync(Wj(0), y.p, i64, hipMemcpyDeviceToDevice, s));
-    if (f32) {
-        convert_64_to_32(slots[0], v32.p, Sst, s);
-        convert_64_to_32(Wj(0), w32.p, Sst, s);
-    }
     const int nst = dslash_blocks(lat);
     const int nvb = vec_blocks(6 * Sst);
     z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nst, 2 * nvb)));
@@ -691,6 +694,17 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
         if (kused < 0 && launched >= maxiter) {
             kused = launched;
             result = SGN_ERR_NOT_CONVERGED;
+        }
+        if (kused < 0 && mixed) {
+            double tmax = 0.0;
+            for (const auto &g : G) tmax = std::max(tmax, g.tau());
+            if (!f32 && tmax < theta32 * ynorm) {  // FP32 copies of the current vh_j, wh_j
+                convert_64_to_32(slots[launched], v32.p, Sst, s);
+                convert_64_to_32(Wj(launched), w32.p, Sst, s);
+                f32 = true;
+                sp = SGN_PREC_F32;
+            }
+            if (f32 && sp == SGN_PREC_F32 && tmax < theta16 * ynorm) sp = SGN_PREC_F32_H16;
         }
     }
     const double kry_ms = ms_since(t_kry);

@@ -115,17 +115,35 @@ def test_deflated_qmr_against_dense():
 
 
 @pytest.mark.parametrize("prec", [sgn.F32, sgn.F32_H16])
-def test_c1_qmr_low_precision_stencil(prec):
-    """FP32 (FP16-link) stencil with FP64 recurrences: accuracy at the stencil's rounding level."""
+def test_c1_mixed_qmr_matches_dense_rational(prec):
+    """Mixed schedule: FP64 steps until tau < 1e-3 ||y||, then the FP32 stencil (FP16 links below
+    1e-6 ||y||) with FP64 recurrences."""
     dims = (4, 4, 4, 4)
     U = synth.gauge_field(dims, 0.5, 0)
     b = synth.gaussian_source(dims, 0).ravel()
     g = np.load(GOLD)
     rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
-    x, st = _solve(lattice(U, dims), 0.3, b, rf, tol=1e-9, prec=prec)
+    x, st = _solve(lattice(U, dims), 0.3, b, rf, tol=1e-11, prec=prec, verify=True)
     e = _rel(x, g["g16_b"])
-    print(f"C1 QMR prec={prec}: vs dense g16 {e:.2e}, {st['iterations']} steps", flush=True)
-    assert e < (1e-5 if prec == sgn.F32 else 1e-2)
+    print(f"C1 mixed QMR prec={prec}: vs dense g16 {e:.2e}, {st['iterations']} steps, "
+          f"max true residual {st['residual']:.1e}", flush=True)
+    assert e < 1e-8
+
+
+def test_8x4_mixed_qmr_against_oracle():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    om, sg, c = rational.coefficients(16, 0.15, 2.6)
+    rf = sgn.sgn_rational_neuberger(16, 0.15, 2.6)
+    x, st = _solve(lattice(U, dims), 0.2, b, rf, tol=1e-11, prec=sgn.F32_H16, theta32=1e-2, theta16=1e-5)
+    xo = krylov.multishift_qmr(lambda v: W.apply(v, 0.2), lambda v: W.apply_adj(v, 0.2), b, om, sg, c,
+                               tol=1e-11, check_every=8)
+    e = _rel(x, xo)
+    print(f"8^4 mixed QMR (1e-2, 1e-5): vs oracle {e:.2e}, {st['iterations']} steps, {st['total_ms']:.1f} ms",
+          flush=True)
+    assert e < 1e-8
 
 
 def test_qmr_zero_source_and_errors():
