@@ -353,8 +353,9 @@ sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational
  * deflation); requested x_i are lifted one by one at the end.  If o->basis_slots < 0,
  * every shift keeps p_i, x_i instead (FP64 only, scalars on the host, three
  * synchronisations per iteration).
- * o->basis_slots > 0 caps the stored vectors (SGN_ERR_NOMEM beyond it; 0: up to half
- * of the free memory).  o->verify is ignored.  stats: iterations, matvecs,
+ * Slots first written in the FP32 phase hold FP32 vectors.  o->basis_slots > 0 caps the
+ * stored bytes at that many FP64 vectors (an FP32 slot counts half; SGN_ERR_NOMEM beyond
+ * it; 0: up to half of the free memory).  o->verify is ignored.  stats: iterations, matvecs,
  * reliable_updates, shift_residual (collinear estimates), residual.  Problems run
  * one after another.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter
  * (x holds the last iterate), SGN_ERR_BREAKDOWN if r^^H r or r^^H v vanishes. */

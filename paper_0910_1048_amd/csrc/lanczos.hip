@@ -714,10 +714,29 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     SGN_HIP(hipMemcpy(hsv.data(), S.sv, sizeof(z64) * kused, hipMemcpyDeviceToHost));
     std::vector<std::vector<cplx>> Z(ns);
     for (int i = 0; i < ns; ++i) Z[i] = G[i].solve(kused);
-    DevBuf dtab(sizeof(void *) * kused), dcoef(sizeof(z64) * kused), dcoef_i(sizeof(z64) * kused);
+    // coefficient sets: 0 = sum_i omega_i x_i, then one per shift whose x_i is requested or
+    // verified; all are uploaded before the first lift is queued (no buffer is reused)
+    std::vector<int> sel;
+    for (int i = 0; i < ns; ++i)
+        if ((pb.x_shift && pb.x_shift[i]) || o.verify) sel.push_back(i);
+    const size_t nset = 1 + sel.size();
+    std::vector<z64> hcoef(nset * kused);
+    for (int j = 0; j < kused; ++j) {
+        cplx d = 0.0;
+        for (int i = 0; i < ns; ++i) d += rf.omega[i] * Z[i][j];
+        d *= hsv[j].r;
+        hcoef[j] = {d.real(), d.imag()};
+    }
+    for (size_t q = 0; q < sel.size(); ++q)
+        for (int j = 0; j < kused; ++j) {
+            const cplx d = Z[sel[q]][j] * hsv[j].r;
+            hcoef[(q + 1) * kused + j] = {d.real(), d.imag()};
+        }
+    DevBuf dtab(sizeof(void *) * kused), dcoef(sizeof(z64) * hcoef.size());
     SGN_HIP(hipMemcpy(dtab.p, slots.data(), sizeof(void *) * kused, hipMemcpyHostToDevice));
-    auto lift = [&](const std::vector<z64> &coef, z64 *dc, void *out) {
-        SGN_HIP(hipMemcpy(dc, coef.data(), sizeof(z64) * kused, hipMemcpyHostToDevice));
+    SGN_HIP(hipMemcpy(dcoef.p, hcoef.data(), sizeof(z64) * hcoef.size(), hipMemcpyHostToDevice));
+    auto lift = [&](size_t set, void *out) {
+        const z64 *dc = dcoef.as<z64>() + set * kused;
         const int pr = ctx.prof_start(s, SGN_K_LIFT);
         for (int j0 = 0; j0 < kused; j0 += kQmrLiftChunk) {
             const int kk = std::min(kQmrLiftChunk, kused - j0);
@@ -736,14 +755,7 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
         deflate_dots(pb.defl->L, pb.defl->m, v, nc, dfc.as<z64>(), ctx, s);
         deflate_combine(v, {1.0, 0.0}, {-1.0, 0.0}, pb.defl->R, pb.defl->m, dfc.as<z64>(), nullptr, nc, s);
     };
-    std::vector<z64> coef(kused);
-    for (int j = 0; j < kused; ++j) {
-        cplx d = 0.0;
-        for (int i = 0; i < ns; ++i) d += rf.omega[i] * Z[i][j];
-        d *= hsv[j].r;
-        coef[j] = {d.real(), d.imag()};
-    }
-    lift(coef, dcoef.as<z64>(), tmp.p);
+    lift(0, tmp.p);
     unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
     project_out(rcan.p);
     axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, nc, s);
@@ -752,16 +764,11 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     std::vector<double> res(ns);
     for (int i = 0; i < ns; ++i) res[i] = G[i].tau() / ynorm;
     int extra_mv = 0;
-    for (int i = 0; i < ns; ++i) {
-        const bool want = pb.x_shift && pb.x_shift[i];
-        if (!want && !o.verify) continue;
-        for (int j = 0; j < kused; ++j) {
-            const cplx d = Z[i][j] * hsv[j].r;
-            coef[j] = {d.real(), d.imag()};
-        }
-        lift(coef, dcoef_i.as<z64>(), tmp.p);
+    DevBuf h(o.verify ? i64 : 0), q(o.verify ? i64 : 0);
+    for (size_t k = 0; k < sel.size(); ++k) {
+        const int i = sel[k];
+        lift(k + 1, tmp.p);
         if (o.verify) {  // r_i = y - (c^2 H^2 - sigma_i) x_i in FP64
-            DevBuf h(i64), q(i64);
             dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, h.p, Epilogue{}, s);
             Epilogue ep;
             ep.a = -c2;
@@ -772,7 +779,7 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
             res[i] = norm_sync(ctx, q.p, ni, false, s) / ynorm;
             extra_mv += 2;
         }
-        if (want) {
+        if (pb.x_shift && pb.x_shift[i]) {
             unpack_spinor(lat, tmp.p, pb.x_shift[i], SGN_PREC_F64, s);
             project_out(pb.x_shift[i]);
         }

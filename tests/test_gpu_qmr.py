@@ -185,3 +185,46 @@ def test_full_size_qmr_residuals_with_oracle_operator():
         print(f"  shift {i}: oracle residual {res:.2e}, quasi-residual {st['shift_residual'][i]:.2e}", flush=True)
         assert res < np.sqrt(k + 1) * 1e-9
     assert _rel(x, om @ np.stack(xs)) < 1e-12
+
+
+def test_qmr_on_a_side_stream_matches_default_stream():
+    """The solve, its per-shift lifts and the verification on a non-default stream give the same
+    bits as on the default stream."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 3)
+    b = synth.gaussian_source(dims, 3).ravel()
+    lat = lattice(U, dims)
+    rf = sgn.sgn_rational_neuberger(10, 0.2, 2.4)
+    x0, st0, xs0 = _solve(lat, 0.25, b, rf, want_shifts=True, tol=1e-10, verify=True)
+    side = torch.cuda.Stream()
+    bd = dev(b)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        x = torch.empty_like(bd)
+        xs = [torch.empty_like(bd) for _ in range(rf.s)]
+        st = sgn.multishift_qmr(sgn.Problem(lat, 0.25, bd, x, None, xs), rf, tol=1e-10, verify=True,
+                                stream=side)[0]
+    side.synchronize()
+    assert np.array_equal(host(x).ravel(), x0)
+    for i in range(rf.s):
+        assert np.array_equal(host(xs[i]).ravel(), xs0[i])
+    assert st["iterations"] == st0["iterations"] and st["shift_residual"] == st0["shift_residual"]
+
+
+def test_qmr_two_problems_in_one_call():
+    """Problems of one call (different mu and sources) run one after another and give the same bits
+    as separate calls; stats come back per problem."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    lat = lattice(U, dims)
+    rf = sgn.sgn_rational_neuberger(12, 0.2, 2.4)
+    cases = [(0.3, synth.gaussian_source(dims, 4).ravel()), (0.1, synth.gaussian_source(dims, 5).ravel())]
+    single = [_solve(lat, mu, b, rf, tol=1e-10) for mu, b in cases]
+    bds = [dev(b) for _, b in cases]
+    xs = [torch.empty_like(t) for t in bds]
+    sts = sgn.multishift_qmr([sgn.Problem(lat, mu, bd, x) for (mu, _), bd, x in zip(cases, bds, xs)], rf,
+                             tol=1e-10)
+    assert len(sts) == 2
+    for k in range(2):
+        assert np.array_equal(host(xs[k]).ravel(), single[k][0])
+        assert sts[k]["iterations"] == single[k][1]["iterations"]
