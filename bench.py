@@ -96,7 +96,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the solver path is single-GPU "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)",
+                                   "(sharding over several GPUs is designed but not built)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
