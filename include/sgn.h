@@ -146,7 +146,7 @@ typedef struct {
     int matvecs;             /* applications of H_W or H_W^H */
     int restarts;            /* FOM restart cycles */
     int reliable_updates;    /* FP64 true-residual recomputations (mixed precision) */
-    int refine_iterations;   /* iterations spent in the per-shift FP64 refinement */
+    int refine_iterations;   /* multishift_solve with verify: iterations of the per-shift FP64 refinement */
     int nshift;
     double shift_residual[SGN_MAX_POLES]; /* final relative residual of each shifted system */
     double residual;         /* largest final relative residual (rational methods) */
@@ -306,7 +306,8 @@ typedef struct {
     double theta16;     /* relative seed residual at which FP16 links take over (default 1e-6 if <= 0) */
     double delta;       /* reliable update when the seed residual drops by this factor (default 0.1) */
     int poll;           /* iterations between host checks of the device flags (0: automatic) */
-    int verify;         /* nonzero: recompute every shifted residual in FP64 at the end (stats) */
+    int verify;         /* nonzero: recompute every shifted residual in FP64 at the end (stats) and, in
+                           multishift_solve, refine each system still above tol (see there) */
     int basis_slots;    /* Krylov-basis storage of the non-seed shifts (see multishift_solve):
                            0: automatic (up to half of the device memory free at the start),
                            > 0: at most this many stored residual vectors, < 0: never */
@@ -333,6 +334,12 @@ typedef struct {
  * the seed solution at every reliable update and out of the combined result at
  * the end, and the mixed schedule stops at FP32 (FP16 links would perturb the
  * operator enough to excite those modes every iteration).
+ * With o->verify the per-shift solutions are kept explicitly, every shifted
+ * residual y - (c^2 H^2 - sigma_i) x_i is recomputed in FP64 at the end, and each
+ * system still above tol gets an FP64 correction before the combination: x_i += e
+ * with (c^2 H^2 - sigma_i) e = r_i solved by single-shift FP64 BiCGStab to tol/2
+ * (stats: refine_iterations, matvecs; shift_residual holds the final FP64 residuals;
+ * SGN_ERR_NOT_CONVERGED if a system stays above tol).
  * Synchronises `stream`.  Returns SGN_ERR_NOT_CONVERGED (x holds the last
  * iterate) if maxiter is reached, SGN_ERR_BREAKDOWN on a BiCG breakdown. */
 sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,

@@ -206,3 +206,25 @@ def test_basis_budget_fallback(prec):
         e = _rel(x, g["g16_b"])
         print(f"prec={prec} basis_slots={slots}: vs dense g16 {e:.2e}, iterations {st['iterations']}", flush=True)
         assert e < 1e-8
+
+
+def test_verify_refines_shifted_systems_above_tolerance():
+    """FP16 links from the first iteration leave the shifted systems far above the tolerance; with
+    verify every one of them is refined in FP64 before the combination, and the result meets the
+    FP64 target."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    g = np.load(GOLD)
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    lat = lattice(U, dims)
+    coarse = dict(prec=sgn.F32_H16, theta32=1.0, theta16=1.0)
+    x0, st0 = _solve(lat, 0.3, b, rf, tol=1e-10, **coarse)
+    x, st = _solve(lat, 0.3, b, rf, tol=1e-10, verify=True, **coarse)
+    e0, e = _rel(x0, g["g16_b"]), _rel(x, g["g16_b"])
+    print(f"FP16 links throughout: error {e0:.1e} without refinement, {e:.1e} with "
+          f"({st['refine_iterations']} refinement iterations, max shifted residual {st['residual']:.1e})",
+          flush=True)
+    assert st["refine_iterations"] > 0 and st0["refine_iterations"] == 0
+    assert st["residual"] <= 1e-10
+    assert e < 1e-8 < e0
