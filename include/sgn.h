@@ -183,6 +183,19 @@ typedef struct {
 sgn_status sign_lanczos_2sided(sgn_lattice lat, double mu, const void *b, void *x, const sgn_deflation *defl,
                                const sgn_lanczos_opts *opts, sgn_stats *stats, void *stream);
 
+/* sign(T) e_1 for a k x k complex tridiagonal T, on the host: the small-matrix
+ * step of the direct two-sided Lanczos method (section "Short recurrences":
+ * f(H_k) of the projected matrix), the routine sign_lanczos_2sided calls.
+ * diag[k], sub[k-1] (T(i+1,i)) and sup[k-1] (T(i,i+1)) are interleaved
+ * (re, im) doubles (sub, sup may be NULL when k = 1); y[k] receives the
+ * result, by the complex Schur form of T (implicit single-shift QR, O(k^3)) and
+ * the eigenvectors of its triangular factor.  *min_abs_re (may be NULL)
+ * receives min |Re lambda|.  SGN_ERR_INVALID for k < 1 or NULL arrays,
+ * SGN_ERR_IMAG_AXIS if |Re lambda| <= 1e-12 ||T||_inf for an eigenvalue,
+ * SGN_ERR_BREAKDOWN if the QR iteration does not converge. */
+sgn_status sgn_small_sign(int k, const double *diag, const double *sub, const double *sup, double *y,
+                          double *min_abs_re);
+
 /* ------------------------------------------------------------------ rational approximation */
 /* sign(t) ~ g_s(c t) = c t sum_i omega_i / (c^2 t^2 - sigma_i)   (Eqs. (neuberger_mit_c), (pfe_s)):
  * the shifted systems of the rational methods are (c^2 H_W^2 - sigma_i) x_i = c H_W r. */

@@ -280,6 +280,25 @@ def sgn_rational_zolotarev(s, alpha, beta):
     return r, e.value
 
 
+lib.sgn_small_sign.argtypes = [C.c_int, _vp, _vp, _vp, _vp, C.POINTER(C.c_double)]
+
+
+def sgn_small_sign(diag, sub, sup):
+    """sign(T) e_1 for the complex tridiagonal T (host); returns (y, min |Re lambda|)."""
+    import numpy as np
+    d = np.ascontiguousarray(diag, dtype=np.complex128)
+    k = d.size
+    lo = np.ascontiguousarray(sub, dtype=np.complex128) if k > 1 else None
+    up = np.ascontiguousarray(sup, dtype=np.complex128) if k > 1 else None
+    if k > 1 and (lo.size != k - 1 or up.size != k - 1):
+        raise ValueError("sub and sup need k - 1 entries")
+    y = np.empty(k, dtype=np.complex128)
+    mr = C.c_double()
+    ptr = lambda a: C.c_void_p(a.ctypes.data) if a is not None else None
+    check(lib.sgn_small_sign(k, ptr(d), ptr(lo), ptr(up), ptr(y), C.byref(mr)), "sgn_small_sign")
+    return y, mr.value
+
+
 class Problem:
     """One right-hand side of multishift_solve.  x_shift: optional list of s device tensors."""
 

@@ -1,15 +1,17 @@
 // sign(T) e_1 for the small projected matrix of the direct two-sided Lanczos
 // method (section "Short recurrences": f(H_k) of the k x k projected matrix,
-// computed here through its eigendecomposition; cost O(k^3), the last term of
-// the cost proposition of the direct method).
+// computed here through its eigendecomposition; the O(k^3) last term of the
+// cost proposition of the direct method, which dominates at small volumes).
 //
 // Route: complex Schur form T = Z S Z^H by the implicit single-shift QR
 // algorithm on the (tridiagonal, hence Hessenberg) input; eigenvectors of the
 // triangular S by back substitution; then
 //   sign(T) e_1 = Z X sign(Lambda) X^{-1} Z^H e_1,
-// where X (unit upper triangular) holds the eigenvectors of S.  Only O(k^2)
-// work besides the QR sweeps and the eigenvector back substitution.
+// where X (unit upper triangular) holds the eigenvectors of S.  Z is never
+// formed: the QR sweeps record their rotations, and Z^H e_1 and Z u are two
+// replays of them (O(1) per rotation instead of a length-k column update).
 #include "small_sign.h"
+#include "sgn_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -33,6 +35,14 @@ struct Mat {
 
 inline double cabs1(zc z) { return std::abs(z.real()) + std::abs(z.imag()); }
 
+// Complex product written out: std::complex's operator* goes through a library
+// routine that handles infinities and NaNs, several times slower in these loops
+// (all values here are finite).
+inline zc cmul(zc a, zc b)
+{
+    return zc(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+
 // Givens (c real, s complex) with G [x; y] = [r; 0], G = [[c, s], [-conj(s), c]].
 inline void givens(zc x, zc y, double &c, zc &s)
 {
@@ -52,9 +62,19 @@ inline void givens(zc x, zc y, double &c, zc &s)
     s = (x / ax) * std::conj(y) / nrm;
 }
 
-// Complex Schur decomposition of upper Hessenberg H (overwritten by S); Z accumulates.
-// Returns false if the iteration did not converge.
-bool hessenberg_schur(Mat &H, Mat &Z)
+// One plane rotation of the QR sweeps: columns m, m+1 of Z are replaced by
+// (c Z_m + conj(s) Z_{m+1}, -s Z_m + c Z_{m+1}), i.e. Z <- Z G with
+// G = [c, -s; conj(s), c] on (m, m+1).
+struct Rot {
+    int m;
+    double c;
+    zc s;
+};
+
+// Complex Schur decomposition of upper Hessenberg H (overwritten by S).  The unitary
+// factor is accumulated into *Z, or, with Z null, its rotations are appended to *rots
+// (Z = G_1 G_2 ... in that order).  Returns false if the iteration did not converge.
+bool hessenberg_schur(Mat &H, Mat *Z, std::vector<Rot> *rots = nullptr)
 {
     const int n = H.n;
     const double ulp = std::numeric_limits<double>::epsilon();
@@ -106,21 +126,25 @@ bool hessenberg_schur(Mat &H, Mat &Z)
             // rows m, m+1  (all columns from the bulge column to the end: full Schur form)
             for (int j = (m == l ? l : m - 1); j < n; ++j) {
                 const zc t1 = H(m, j), t2 = H(m + 1, j);
-                H(m, j) = c * t1 + s * t2;
-                H(m + 1, j) = -std::conj(s) * t1 + c * t2;
+                H(m, j) = c * t1 + cmul(s, t2);
+                H(m + 1, j) = c * t2 - cmul(std::conj(s), t1);
             }
             if (m > l) H(m + 1, m - 1) = 0.0;
             // columns m, m+1
             const int imax = std::min(m + 2, ihi);
             for (int i = 0; i <= imax; ++i) {
                 const zc t1 = H(i, m), t2 = H(i, m + 1);
-                H(i, m) = t1 * c + t2 * std::conj(s);
-                H(i, m + 1) = -t1 * s + t2 * c;
+                H(i, m) = t1 * c + cmul(t2, std::conj(s));
+                H(i, m + 1) = t2 * c - cmul(t1, s);
             }
-            for (int i = 0; i < n; ++i) {
-                const zc t1 = Z(i, m), t2 = Z(i, m + 1);
-                Z(i, m) = t1 * c + t2 * std::conj(s);
-                Z(i, m + 1) = -t1 * s + t2 * c;
+            if (Z) {
+                for (int i = 0; i < n; ++i) {
+                    const zc t1 = (*Z)(i, m), t2 = (*Z)(i, m + 1);
+                    (*Z)(i, m) = t1 * c + cmul(t2, std::conj(s));
+                    (*Z)(i, m + 1) = t2 * c - cmul(t1, s);
+                }
+            } else {
+                rots->push_back({m, c, s});
             }
         }
     }
@@ -135,7 +159,7 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
                   const std::complex<double> *sup, std::complex<double> *y, SmallSignInfo *info)
 {
     if (k <= 0) return 1;
-    Mat S(k), Z(k);
+    Mat S(k);
     double tnorm = 0.0;
     for (int i = 0; i < k; ++i) {
         S(i, i) = diag[i];
@@ -143,7 +167,6 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
             S(i + 1, i) = sub[i];
             S(i, i + 1) = sup[i];
         }
-        Z(i, i) = 1.0;
     }
     for (int i = 0; i < k; ++i) {
         double row = std::abs(diag[i]);
@@ -151,7 +174,8 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
         if (i > 0) row += std::abs(sub[i - 1]);
         tnorm = std::max(tnorm, row);
     }
-    if (!hessenberg_schur(S, Z)) return 2;
+    std::vector<Rot> rots;
+    if (!hessenberg_schur(S, nullptr, &rots)) return 2;
     // eigenvalues and the imaginary-axis check
     double minre = std::numeric_limits<double>::infinity();
     std::vector<double> sgn(k);
@@ -175,7 +199,7 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
         const zc lam = S(i, i);
         for (int j = i - 1; j >= 0; --j) {
             zc acc = 0.0;
-            for (int l = j + 1; l <= i; ++l) acc += S(j, l) * X(l, i);
+            for (int l = j + 1; l <= i; ++l) acc += cmul(S(j, l), X(l, i));
             zc den = S(j, j) - lam;
             if (std::abs(den) < smin) den = smin;
             X(j, i) = -acc / den;
@@ -185,25 +209,34 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
         cond_est = std::max(cond_est, std::sqrt(cn));
     }
     if (info) info->eigvec_growth = cond_est;
-    // q = Z^H e_1;  c = X^{-1} q (unit upper triangular back substitution)
-    std::vector<zc> c(k);
-    for (int i = 0; i < k; ++i) c[i] = std::conj(Z(0, i));
+    // q = Z^H e_1 (the first row of Z: e_1^T G_1 G_2 ..., conjugated);
+    // c = X^{-1} q (unit upper triangular back substitution)
+    std::vector<zc> c(k, zc(0.0, 0.0));
+    c[0] = 1.0;
+    for (const Rot &g : rots) {
+        const zc t1 = c[g.m], t2 = c[g.m + 1];
+        c[g.m] = t1 * g.c + t2 * std::conj(g.s);
+        c[g.m + 1] = -t1 * g.s + t2 * g.c;
+    }
+    for (int i = 0; i < k; ++i) c[i] = std::conj(c[i]);
     for (int i = k - 1; i >= 0; --i) {
         zc acc = c[i];
-        for (int j = i + 1; j < k; ++j) acc -= X(i, j) * c[j];
+        for (int j = i + 1; j < k; ++j) acc -= cmul(X(i, j), c[j]);
         c[i] = acc;
     }
     // u = X sign(Lambda) c ; y = Z u
     std::vector<zc> u(k, zc(0, 0));
     for (int j = 0; j < k; ++j) {
         const zc cj = sgn[j] * c[j];
-        for (int i = 0; i <= j; ++i) u[i] += X(i, j) * cj;
+        for (int i = 0; i <= j; ++i) u[i] += cmul(X(i, j), cj);
     }
-    for (int i = 0; i < k; ++i) {
-        zc acc = 0.0;
-        for (int j = 0; j < k; ++j) acc += Z(i, j) * u[j];
-        y[i] = acc;
+    // y = Z u = G_1 (G_2 (... u)): the rotations in reverse order
+    for (auto it = rots.rbegin(); it != rots.rend(); ++it) {
+        const zc t1 = u[it->m], t2 = u[it->m + 1];
+        u[it->m] = it->c * t1 - it->s * t2;
+        u[it->m + 1] = std::conj(it->s) * t1 + it->c * t2;
     }
+    for (int i = 0; i < k; ++i) y[i] = u[i];
     return 0;
 }
 
@@ -247,7 +280,7 @@ int small_eig(int n, const std::complex<double> *a, std::complex<double> *lam, s
         }
         for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
     }
-    if (!hessenberg_schur(H, Z)) return 2;
+    if (!hessenberg_schur(H, &Z)) return 2;
     double tnorm = 0.0;
     for (int i = 0; i < n; ++i)
         for (int j = i; j < n; ++j) tnorm = std::max(tnorm, std::abs(H(i, j)));
@@ -277,3 +310,18 @@ int small_eig(int n, const std::complex<double> *a, std::complex<double> *lam, s
 }
 
 }  // namespace sgn
+
+extern "C" sgn_status sgn_small_sign(int k, const double *diag, const double *sub, const double *sup, double *y,
+                                     double *min_abs_re)
+{
+    using zc = std::complex<double>;
+    return sgn::guard([&] {
+        SGN_REQUIRE(k >= 1 && diag && y && (k == 1 || (sub && sup)), "sgn_small_sign: bad arguments");
+        sgn::SmallSignInfo info;
+        const int rc = sgn::small_sign_e1(k, reinterpret_cast<const zc *>(diag), reinterpret_cast<const zc *>(sub),
+                                          reinterpret_cast<const zc *>(sup), reinterpret_cast<zc *>(y), &info);
+        if (rc == 3) throw sgn::Failure{SGN_ERR_IMAG_AXIS, "sgn_small_sign: eigenvalue on the imaginary axis"};
+        if (rc != 0) throw sgn::Failure{SGN_ERR_BREAKDOWN, "sgn_small_sign: QR iteration did not converge"};
+        if (min_abs_re) *min_abs_re = info.min_abs_re;
+    });
+}
