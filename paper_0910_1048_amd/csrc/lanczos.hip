@@ -16,6 +16,9 @@
 //            partials of ||vh||^2, wh^H vh, ||wh||^2
 //   finalize h_{j+1,j} = ||vh_{j+1}||, s_{j+1} = 1/h_{j+1,j},
 //            h_{j,j+1} = wh_{j+1}^H v_{j+1},  t_{j+1} = 1/conj(h_{j,j+1})
+//
+// The second part of the file runs the same recurrence on c^2 H_W^2 for the
+// multishift QMR solver (multishift_qmr).
 #include <chrono>
 #include <complex>
 #include <vector>
@@ -450,7 +453,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
 namespace sgn {
 namespace {
 
-constexpr int kQmrLiftChunk = 16;
+constexpr int kQmrLiftChunk = 64;
 
 // out[e] (+)= sum_j coef_j vec_j[e] over a table of FP64 vectors (K <= kQmrLiftChunk)
 __global__ void __launch_bounds__(256) qmr_lift_kernel(const double2 *const *vecs, const z64 *coef, int K,
