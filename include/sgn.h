@@ -176,7 +176,10 @@ typedef struct {
  *   Lanczos with A = H_W(mu), A^H = H_W(-mu), T_k tridiagonal,
  *   x = x_P + ||r|| V_k sign(T_k) e_1.
  * b, x: device, canonical complex128.  The small sign is evaluated on the host
- * in FP64 (complex Schur form); the call synchronises `stream`.
+ * in FP64 (complex Schur form); the call synchronises `stream`.  The basis
+ * vectors v_j (FP64) are taken from the context's pool as the steps proceed and
+ * stay with the context after the call (memory follows the steps taken, at most
+ * k vectors; SGN_ERR_NOMEM when one cannot be allocated).
  * Returns SGN_ERR_BREAKDOWN if |w^H v| < 1e-14 ||w|| ||v|| at some step,
  * SGN_ERR_IMAG_AXIS if a deflated eigenvalue or an eigenvalue of T_k has
  * |Re| <= 1e-12 of the norm. */

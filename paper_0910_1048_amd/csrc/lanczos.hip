@@ -160,13 +160,24 @@ __global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const vo
     }
 }
 
-// x[e] = sum_j c_j V_j[e]
-__global__ void __launch_bounds__(256) lift_kernel(const double2 *basis, int64_t n, int k, const z64 *c, double2 *x)
+constexpr int kLiftChunk = 64;
+
+// out[e] (+)= sum_j coef_j vec_j[e] over a table of K <= kLiftChunk FP64 vectors
+__global__ void __launch_bounds__(256) basis_lift_kernel(const double2 *const *vecs, const z64 *coef, int K,
+                                                         int64_t n, double2 *out, int accumulate)
 {
+    __shared__ const double2 *vp[kLiftChunk];
+    __shared__ z64 cf[kLiftChunk];
+    if ((int)threadIdx.x < K) {
+        vp[threadIdx.x] = vecs[threadIdx.x];
+        cf[threadIdx.x] = coef[threadIdx.x];
+    }
+    __syncthreads();
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         z64 acc = {0.0, 0.0};
-        for (int jj = 0; jj < k; ++jj) acc = acc + c[jj] * ld2(basis, (int64_t)jj * n + e);
-        x[e] = make_double2(acc.r, acc.i);
+        if (accumulate) acc = ld2(out, e);
+        for (int j = 0; j < K; ++j) acc = acc + cf[j] * ld2(vp[j], e);
+        out[e] = make_double2(acc.r, acc.i);
     }
 }
 
@@ -190,6 +201,47 @@ double ms_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
+
+// Stored Krylov vectors (FP64, internal layout) taken on demand from the context's pool of
+// vectors of this size; the pool keeps them between calls, so memory follows the steps
+// actually taken.  At most cap vectors (SGN_ERR_NOMEM beyond, or when allocation fails).
+struct PooledBasis {
+    Context &ctx;
+    size_t bytes, cap;
+    const char *who;
+    std::vector<void *> slots;
+    PooledBasis(Context &c, size_t b, size_t cap_, const char *w) : ctx(c), bytes(b), cap(cap_), who(w) {}
+    void *operator[](int j) const { return slots[j]; }
+    void ensure(int upto)  // slots 0 .. upto exist
+    {
+        auto &pool = ctx.basis_pools[bytes];
+        while ((int)slots.size() <= upto) {
+            const size_t idx = slots.size();
+            if (idx >= cap) throw Failure{SGN_ERR_NOMEM, std::string(who) + ": Krylov basis exceeds its slot budget"};
+            if (idx == pool.size()) {
+                void *v = nullptr;
+                if (hipMalloc(&v, bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    throw Failure{SGN_ERR_NOMEM, std::string(who) + ": Krylov basis does not fit"};
+                }
+                pool.push_back(v);
+            }
+            slots.push_back(pool[idx]);
+        }
+    }
+    // out = sum_{j < K} dcoef[j] slot_j; dtab holds the K slot pointers on the device.  The
+    // launches are stream-ordered: dcoef and dtab must stay valid until they have run.
+    void lift(const z64 *dcoef, const void *const *dtab, int K, int64_t n, void *out, hipStream_t s) const
+    {
+        for (int j0 = 0; j0 < K; j0 += kLiftChunk) {
+            const int kk = std::min(kLiftChunk, K - j0);
+            hipLaunchKernelGGL(basis_lift_kernel, dim3(vec_blocks(n)), dim3(256), 0, s,
+                               reinterpret_cast<const double2 *const *>(dtab) + j0, dcoef + j0, kk, n,
+                               static_cast<double2 *>(out), j0 > 0 ? 1 : 0);
+        }
+        SGN_HIP(hipGetLastError());
+    }
+};
 
 }  // namespace
 
@@ -276,7 +328,10 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         // workspace: basis V (k vectors, or a ring of 3 in the two-pass form), 3 W vectors,
         // u, z (FP64 internal) + FP32 copies
         const bool two_pass = opts->two_pass != 0;
-        DevBuf Vb((size_t)(two_pass ? 3 : k) * i64), Wb(3 * i64), u(i64), z(i64);
+        // basis: stored vectors from the context's pool, or a ring of 3 in the two-pass form
+        DevBuf ring(two_pass ? 3 * i64 : 0), Wb(3 * i64), u(i64), z(i64);
+        PooledBasis basis(ctx, i64, (size_t)k, "sign_lanczos_2sided");
+        if (!two_pass) basis.ensure(0);
         DevBuf v32(f32 ? b32 : 0), w32(f32 ? b32 : 0), u32(f32 ? b32 : 0), z32(f32 ? b32 : 0);
         DevBuf scal(sizeof(z64) * (5 * (size_t)k + 2) + sizeof(int) * k);
         LzScalars S;
@@ -291,7 +346,9 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         const double m2 = norm2(v1rt);
         const z64 t1 = {v1rt.r / m2, -v1rt.i / m2};  // 1 / (v_1^H r~)
         const z64 sv0 = {s1, 0.0};
-        auto Vj = [&](int j) { return static_cast<char *>(Vb.p) + (size_t)(two_pass ? j % 3 : j) * i64; };
+        auto Vj = [&](int j) {
+            return two_pass ? static_cast<char *>(ring.p) + (size_t)(j % 3) * i64 : static_cast<char *>(basis[j]);
+        };
         auto Wj = [&](int j) { return static_cast<char *>(Wb.p) + (size_t)(j % 3) * i64; };
         // start of the recurrence (run once, or twice in the two-pass form, from identical state)
         auto start = [&]() {
@@ -354,6 +411,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
             const int nb1 = dslash_launch(lat, sp, opA, f32 ? v32.p : Vj(j), f32 ? u32.p : u.p, ep, s);
             hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S, j);
             if (j + 1 == last) return;
+            if (!two_pass) basis.ensure(j + 1);
             dslash_launch(lat, sp, opAh, f32 ? w32.p : Wj(j), f32 ? z32.p : z.p, Epilogue{}, s);
             void *vn = Vj(j + 1);
             const double2 *vjm = j > 0 ? reinterpret_cast<const double2 *>(Vj(j - 1)) : nullptr;
@@ -371,7 +429,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         };
 
         const auto t_kry = std::chrono::steady_clock::now();
-        int kused = k;
+        int kused = k, checked = 0;  // checked: size of the last small sign computed in the loop
         for (int j = 0; j < k; ++j) {
             step(j, k);
             if (j + 1 == k) break;
@@ -379,6 +437,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
                 const int kk = j + 1;
                 download(kk);
                 small_sign(kk, ycur);
+                checked = kk;
                 if (!yprev.empty()) {
                     double num = 0.0, den = 0.0;
                     for (int i = 0; i < kk; ++i) {
@@ -399,15 +458,18 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         download(kused);
         const double kry_ms = ms_since(t_kry);
         std::vector<z64> y;
-        small_sign(kused, y);
+        if (checked == kused)
+            y = ycur;  // the stopping check already computed sign(T_k) e_1 for this k
+        else
+            small_sign(kused, y);
         // x = x_P + beta * sum_j y_j s_j vh_j
         std::vector<z64> c(kused);
         for (int j = 0; j < kused; ++j) c[j] = (beta * hsv[j].r) * y[j];
-        DevBuf cd(sizeof(z64) * kused);
+        DevBuf cd(sizeof(z64) * kused), tab(sizeof(void *) * kused);
         if (!two_pass) {
             SGN_HIP(hipMemcpyAsync(cd.p, c.data(), sizeof(z64) * kused, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(lift_kernel, dim3(vec_blocks(ni)), dim3(256), 0, s, (const double2 *)Vb.p, ni, kused,
-                               cd.as<z64>(), (double2 *)u.p);
+            SGN_HIP(hipMemcpyAsync(tab.p, basis.slots.data(), sizeof(void *) * kused, hipMemcpyHostToDevice, s));
+            basis.lift(cd.as<z64>(), static_cast<const void *const *>(tab.p), kused, ni, u.p, s);
         } else {
             // second pass: the same launches from the same state give the same vh_j bit for bit;
             // each is added to the solution while it is still in the ring.  x accumulates in xacc
@@ -452,27 +514,6 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
 // sum_i omega_i x_i = V_k (sum_i omega_i z_i) is one lift at the end.
 namespace sgn {
 namespace {
-
-constexpr int kQmrLiftChunk = 64;
-
-// out[e] (+)= sum_j coef_j vec_j[e] over a table of FP64 vectors (K <= kQmrLiftChunk)
-__global__ void __launch_bounds__(256) qmr_lift_kernel(const double2 *const *vecs, const z64 *coef, int K,
-                                                       int64_t n, double2 *out, int accumulate)
-{
-    __shared__ const double2 *vp[kQmrLiftChunk];
-    __shared__ z64 cf[kQmrLiftChunk];
-    if ((int)threadIdx.x < K) {
-        vp[threadIdx.x] = vecs[threadIdx.x];
-        cf[threadIdx.x] = coef[threadIdx.x];
-    }
-    __syncthreads();
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        z64 acc = {0.0, 0.0};
-        if (accumulate) acc = ld2(out, e);
-        for (int j = 0; j < K; ++j) acc = acc + cf[j] * ld2(vp[j], e);
-        out[e] = make_double2(acc.r, acc.i);
-    }
-}
 
 using cplx = std::complex<double>;
 
@@ -573,32 +614,16 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     }
 
     // stored basis: slot j holds vh_j (FP64, internal layout), from the context's pool
-    auto &pool = ctx.basis_pools[i64];
     size_t cap;
     if (o.basis_slots > 0) {
         cap = (size_t)o.basis_slots;
     } else {
         size_t fr = 0, tot = 0;
         SGN_HIP(hipMemGetInfo(&fr, &tot));
-        cap = pool.size() + fr / 2 / i64;
+        cap = ctx.basis_pools[i64].size() + fr / 2 / i64;
     }
-    std::vector<void *> slots;
-    auto ensure = [&](int upto) {
-        while ((int)slots.size() <= upto) {
-            const size_t idx = slots.size();
-            if (idx >= cap) throw Failure{SGN_ERR_NOMEM, "multishift_qmr: Krylov basis exceeds the slot budget"};
-            if (idx == pool.size()) {
-                void *v = nullptr;
-                if (hipMalloc(&v, i64) != hipSuccess) {
-                    (void)hipGetLastError();
-                    throw Failure{SGN_ERR_NOMEM, "multishift_qmr: Krylov basis"};
-                }
-                pool.push_back(v);
-            }
-            slots.push_back(pool[idx]);
-        }
-    };
-    ensure(0);
+    PooledBasis basis(ctx, i64, cap, "multishift_qmr");
+    basis.ensure(0);
     DevBuf Wb(3 * i64), u(i64), z(i64);
     DevBuf v32(mixed ? b32 : 0), w32(mixed ? b32 : 0), t32(mixed ? b32 : 0), u32(mixed ? b32 : 0),
         z32(mixed ? b32 : 0);
@@ -616,7 +641,7 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     SGN_HIP(hipMemsetAsync(scal.p, 0, nscal, s));
     SGN_HIP(hipMemcpyAsync(S.sv, &s0, sizeof(z64), hipMemcpyHostToDevice, s));
     SGN_HIP(hipMemcpyAsync(S.tw, &s0, sizeof(z64), hipMemcpyHostToDevice, s));
-    SGN_HIP(hipMemcpyAsync(slots[0], y.p, i64, hipMemcpyDeviceToDevice, s));
+    SGN_HIP(hipMemcpyAsync(basis[0], y.p, i64, hipMemcpyDeviceToDevice, s));
     SGN_HIP(hipMemcpyAsync(Wj(0), y.p, i64, hipMemcpyDeviceToDevice, s));
     const int nst = dslash_blocks(lat);
     const int nvb = vec_blocks(6 * Sst);
@@ -624,7 +649,7 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
 
     // one Lanczos step on A': alpha_j, vh_{j+1}, wh_{j+1}, h_{j+1,j}, h_{j,j+1}
     auto step = [&](int j) {
-        dslash_launch(lat, sp, opA, f32 ? v32.p : slots[j], f32 ? t32.p : tmp.p, Epilogue{}, s);
+        dslash_launch(lat, sp, opA, f32 ? v32.p : basis[j], f32 ? t32.p : tmp.p, Epilogue{}, s);
         Epilogue ep;  // u = c^2 H (H vh_j), partials of wh_j^H u
         ep.a = c2;
         ep.w = f32 ? w32.p : Wj(j);
@@ -635,16 +660,16 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
         Epilogue ez;  // z = c^2 H^H (H^H wh_j)
         ez.a = c2;
         dslash_launch(lat, sp, opAh, f32 ? t32.p : tmp.p, f32 ? z32.p : z.p, ez, s);
-        const double2 *vjm = j > 0 ? static_cast<const double2 *>(slots[j - 1]) : nullptr;
+        const double2 *vjm = j > 0 ? static_cast<const double2 *>(basis[j - 1]) : nullptr;
         const double2 *wjm = j > 0 ? reinterpret_cast<const double2 *>(Wj(j - 1)) : nullptr;
         const int pr = ctx.prof_start(s, SGN_K_SEED_UPDATE);
         if (f32)
             hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb), dim3(256), 0, s, u32.p, z32.p,
-                               (const double2 *)slots[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)slots[j + 1],
+                               (const double2 *)basis[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1],
                                (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, S, j, (int)Sst, part);
         else
             hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb), dim3(256), 0, s, u.p, z.p,
-                               (const double2 *)slots[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)slots[j + 1],
+                               (const double2 *)basis[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1],
                                (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)Sst, part);
         const double io = (f32 ? 2.0 * b32 : 2.0 * i64) + (j > 0 ? 4.0 : 2.0) * i64 + 2.0 * i64 + (f32 ? 2.0 * b32 : 0.0);
         ctx.prof_stop(pr, s, SGN_K_SEED_UPDATE, io, 40.0 * ni);
@@ -665,7 +690,7 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     const auto t_kry = std::chrono::steady_clock::now();
     while (kused < 0) {
         const int chunk = std::min(poll, maxiter - launched);
-        ensure(launched + chunk);
+        basis.ensure(launched + chunk);
         for (int q = 0; q < chunk; ++q) step(launched + q);
         const int j0 = launched;
         launched += chunk;
@@ -702,7 +727,7 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
             double tmax = 0.0;
             for (const auto &g : G) tmax = std::max(tmax, g.tau());
             if (!f32 && tmax < theta32 * ynorm) {  // FP32 copies of the current vh_j, wh_j
-                convert_64_to_32(slots[launched], v32.p, Sst, s);
+                convert_64_to_32(basis[launched], v32.p, Sst, s);
                 convert_64_to_32(Wj(launched), w32.p, Sst, s);
                 f32 = true;
                 sp = SGN_PREC_F32;
@@ -736,18 +761,11 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
             hcoef[(q + 1) * kused + j] = {d.real(), d.imag()};
         }
     DevBuf dtab(sizeof(void *) * kused), dcoef(sizeof(z64) * hcoef.size());
-    SGN_HIP(hipMemcpy(dtab.p, slots.data(), sizeof(void *) * kused, hipMemcpyHostToDevice));
+    SGN_HIP(hipMemcpy(dtab.p, basis.slots.data(), sizeof(void *) * kused, hipMemcpyHostToDevice));
     SGN_HIP(hipMemcpy(dcoef.p, hcoef.data(), sizeof(z64) * hcoef.size(), hipMemcpyHostToDevice));
     auto lift = [&](size_t set, void *out) {
-        const z64 *dc = dcoef.as<z64>() + set * kused;
         const int pr = ctx.prof_start(s, SGN_K_LIFT);
-        for (int j0 = 0; j0 < kused; j0 += kQmrLiftChunk) {
-            const int kk = std::min(kQmrLiftChunk, kused - j0);
-            hipLaunchKernelGGL(qmr_lift_kernel, dim3(vec_blocks(ni)), dim3(256), 0, s,
-                               dtab.as<const double2 *>() + j0, dc + j0, kk, ni, static_cast<double2 *>(out),
-                               j0 > 0 ? 1 : 0);
-        }
-        SGN_HIP(hipGetLastError());
+        basis.lift(dcoef.as<z64>() + set * kused, static_cast<const void *const *>(dtab.p), kused, ni, out, s);
         ctx.prof_stop(pr, s, SGN_K_LIFT, (double)i64 * (kused + 1), 8.0 * ni * kused);
     };
     // canonical v <- (I - P) v (rounding components along the deflated eigenvectors)
