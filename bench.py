@@ -10,7 +10,9 @@ HBM before the timed region.
 
 Reported beside it on the same GPU: the plain FP64 single-RHS form of the same
 solve (solves/s), the multishift BiCG solver (multishift_solve) mixed and FP64 and
-the multishift QMR solver (multishift_qmr) mixed and FP64 at the same accuracy target, the error of every result against an FP64 solve to
+the multishift QMR solver (multishift_qmr) mixed and FP64 at the same accuracy target, the
+direct two-sided Lanczos method (exact sign, with the accuracy measure) and restarted
+FOM-LR (FP64 and mixed), the error of every result against an FP64 solve to
 tolerance 1e-12, the live per-kernel timing of the solver's own launches (HIP
 events on the launch stream) as HBM roofline fractions, and the CPU oracle timed
 on this host's cores on a bounded sample of the same solve.
@@ -43,6 +45,13 @@ BICG_MIXED = dict(theta32=1e-1, theta16=1e-3, delta=0.05)
 # the QMR solver at the same target: FP32 stencil below a quasi-residual of 1e-3 ||y||, FP16 links
 # below 1e-6 ||y|| (error 2.4e-9 on this workload; (1e-2, 1e-5) gives 5.8e-9)
 QMR_MIXED = dict(theta32=1e-3, theta16=1e-6)
+# the direct two-sided Lanczos method (exact sign, no rational approximation): k grows until
+# sign(T_k) e_1 changes by less than 1e-10 between checks 100 steps apart
+LANCZOS = dict(k=1000, tol=1e-10, check_every=100)
+# restarted FOM-LR with the bench's rational function: 30 Arnoldi steps per cycle, shifted
+# residuals to 1e-9; mixed: FP32 below 1e-2, FP16 links below 1e-5
+FOM = dict(kmax=30, tol=1e-9)
+FOM_MIXED = dict(theta32=1e-2, theta16=1e-5)
 PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
 # PMC byte counts of the solver kernels, taken with rocprofv3 on this benchmark; valid only
 # while the kernel sources are the ones they were measured on
@@ -90,7 +99,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bicg", action="store_true",
-                    help="skip the comparison legs (multishift BiCG and multishift QMR, mixed and FP64)")
+                    help="skip the comparison legs (multishift BiCG and QMR, direct Lanczos, restarted FOM)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device-to-device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -208,6 +217,39 @@ def main():
             log(f"[bench] QMR {name}: {tq * 1e3:.1f} ms/solve, {sq['iterations']} steps, "
                 f"err {qmr[name]['err_vs_fp64_ref']:.2e}")
 
+    # ---- the direct two-sided Lanczos method: its accuracy by the measure 1/2 ||S(S b) - b|| / ||b||
+    #      (its distance to the FP64 rational reference is the rational approximation's error)
+    lanczos = fom = None
+    if not args.no_bicg:
+        sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sl = sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        ssb = torch.empty_like(bd)
+        sgn.sign_lanczos_2sided(lat, W["mu"], x, ssb, **LANCZOS)
+        acc = sgn.sgn_accuracy_measure(lat, bd, ssb)
+        del ssb
+        lanczos = {"settings": LANCZOS, "solves_per_s": round(1.0 / tl, 4), "ms_per_solve": round(tl * 1e3, 2),
+                   "k": sl["iterations"], "small_sign_ms": round(sl["small_ms"], 2), "accuracy_measure": acc,
+                   "diff_vs_rational_ref": err_of(x)}
+        log(f"[bench] direct Lanczos: {tl * 1e3:.1f} ms/solve, k = {sl['iterations']}, small sign "
+            f"{sl['small_ms']:.1f} ms, accuracy measure {acc:.2e}")
+        # ---- restarted FOM-LR (the rational function of the headline), FP64 and mixed
+        fom = {"settings": FOM, "mixed_schedule": FOM_MIXED}
+        for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
+            kw = dict(FOM, **(FOM_MIXED if prec != sgn.F64 else {}))
+            sgn.sign_arnoldi_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sf = sgn.sign_arnoldi_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t0
+            fom[name] = {"solves_per_s": round(1.0 / tf, 4), "ms_per_solve": round(tf * 1e3, 2),
+                         "restarts": sf["restarts"], "arnoldi_steps": sf["iterations"], "err_vs_fp64_ref": err_of(x)}
+            log(f"[bench] FOM {name}: {tf * 1e3:.1f} ms/solve, {sf['restarts']} cycles, err {fom[name]['err_vs_fp64_ref']:.2e}")
+
     # ---- roofline: dominant kernel by time, and the stencil (Dslash) itself
     traffic = measured_traffic()
 
@@ -276,6 +318,8 @@ def main():
         "speedup_vs_fp64": round(value * t64, 3),
         "bicg": bicg,
         "qmr": qmr,
+        "direct_lanczos": lanczos,
+        "fom": fom,
         "roofline": roofline,
         "stencil_roofline": stencils,
         "kernel_time_share": time_share,
