@@ -193,7 +193,7 @@ sgn_status sign_lanczos_2sided(sgn_lattice lat, double mu, const void *b, void *
  * (re, im) doubles (sub, sup may be NULL when k = 1); y[k] receives the
  * result, by the complex Schur form of T (implicit single-shift QR, O(k^3)) and
  * the eigenvectors of its triangular factor.  *min_abs_re (may be NULL)
- * receives min |Re lambda|.  SGN_ERR_INVALID for k < 1 or NULL arrays,
+ * receives min |Re lambda|.  SGN_ERR_INVALID for k < 1, NULL arrays or entries that are not finite,
  * SGN_ERR_IMAG_AXIS if |Re lambda| <= 1e-12 ||T||_inf for an eigenvalue,
  * SGN_ERR_BREAKDOWN if the QR iteration does not converge. */
 sgn_status sgn_small_sign(int k, const double *diag, const double *sub, const double *sup, double *y,

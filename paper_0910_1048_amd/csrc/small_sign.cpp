@@ -317,6 +317,9 @@ extern "C" sgn_status sgn_small_sign(int k, const double *diag, const double *su
     using zc = std::complex<double>;
     return sgn::guard([&] {
         SGN_REQUIRE(k >= 1 && diag && y && (k == 1 || (sub && sup)), "sgn_small_sign: bad arguments");
+        for (int i = 0; i < 2 * k; ++i) SGN_REQUIRE(std::isfinite(diag[i]), "sgn_small_sign: diag not finite");
+        for (int i = 0; i < 2 * (k - 1); ++i)
+            SGN_REQUIRE(std::isfinite(sub[i]) && std::isfinite(sup[i]), "sgn_small_sign: sub/sup not finite");
         sgn::SmallSignInfo info;
         const int rc = sgn::small_sign_e1(k, reinterpret_cast<const zc *>(diag), reinterpret_cast<const zc *>(sub),
                                           reinterpret_cast<const zc *>(sup), reinterpret_cast<zc *>(y), &info);

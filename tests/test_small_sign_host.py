@@ -71,3 +71,6 @@ def test_errors():
     with pytest.raises(sgn.SgnError) as e:
         sgn.sgn_small_sign([], [], [])
     assert e.value.status == 1
+    with pytest.raises(sgn.SgnError) as e:
+        sgn.sgn_small_sign([1.0, np.nan], [0.5], [0.5])
+    assert e.value.status == 1
