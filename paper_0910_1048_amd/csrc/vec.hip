@@ -113,21 +113,34 @@ __global__ void cvt32to64(const float4 *__restrict__ x, double2 *__restrict__ y,
 
 // grid (nbx, m): partials[i * nbx + bx] = sum conj(X_i) y over the block's slice
 // (T = double2 or float2; FP64 accumulation either way)
+constexpr int kDotGroup = 8;   // dot products per pass of y
+constexpr int kDotBlocks = 512;  // blocks per pass (grid-stride over the elements)
+
+// partials[i * gridDim.x + b] = sum over block b's slice of conj(X_i) . y for the kDotGroup
+// vectors i of group blockIdx.y (fewer in the last group); y is read once per group
 template <typename T>
-__global__ void __launch_bounds__(256) mdot_kernel(const T *X, const T *y, int64_t n, z64 *partials)
+__global__ void __launch_bounds__(256) mdot_kernel(const T *X, const T *y, int64_t n, int m, z64 *partials)
 {
-    const int i = blockIdx.y;
-    const T *xi = X + (int64_t)i * n;
-    double re = 0.0, im = 0.0;
+    const int i0 = blockIdx.y * kDotGroup;
+    const int cnt = min(kDotGroup, m - i0);
+    double acc[2 * kDotGroup];
+#pragma unroll
+    for (int c = 0; c < 2 * kDotGroup; ++c) acc[c] = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const T a = xi[e], b = y[e];
-        re += (double)a.x * b.x + (double)a.y * b.y;
-        im += (double)a.x * b.y - (double)a.y * b.x;
+        const T b = y[e];
+#pragma unroll
+        for (int c = 0; c < kDotGroup; ++c) {
+            if (c < cnt) {
+                const T a = X[(int64_t)(i0 + c) * n + e];
+                acc[2 * c] += (double)a.x * b.x + (double)a.y * b.y;
+                acc[2 * c + 1] += (double)a.x * b.y - (double)a.y * b.x;
+            }
+        }
     }
-    __shared__ double lds[8];
-    double v[2] = {re, im};
-    block_sum<2>(v, lds);
-    if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = {v[0], v[1]};
+    __shared__ double lds[2 * kDotGroup * 4];
+    block_sum<2 * kDotGroup>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < cnt; ++c) partials[(int64_t)(i0 + c) * gridDim.x + blockIdx.x] = {acc[2 * c], acc[2 * c + 1]};
 }
 
 __global__ void __launch_bounds__(256) mfinalize_kernel(const z64 *partials, int nbx, z64 *out)
@@ -265,14 +278,15 @@ void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s)
 void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s, bool f32)
 {
     if (m <= 0) return;
-    const int nbx = std::max(1, std::min(64, vec_blocks(n)));
+    const int nbx = std::max(1, std::min(kDotBlocks, vec_blocks(n)));
+    const int ng = (m + kDotGroup - 1) / kDotGroup;
     z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)m * nbx * sizeof(z64)));
     if (f32)
-        hipLaunchKernelGGL(mdot_kernel<float2>, dim3(nbx, m), dim3(256), 0, s, (const float2 *)X, (const float2 *)y, n,
-                           part);
+        hipLaunchKernelGGL(mdot_kernel<float2>, dim3(nbx, ng), dim3(256), 0, s, (const float2 *)X, (const float2 *)y, n,
+                           m, part);
     else
-        hipLaunchKernelGGL(mdot_kernel<double2>, dim3(nbx, m), dim3(256), 0, s, (const double2 *)X, (const double2 *)y,
-                           n, part);
+        hipLaunchKernelGGL(mdot_kernel<double2>, dim3(nbx, ng), dim3(256), 0, s, (const double2 *)X, (const double2 *)y,
+                           n, m, part);
     hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, c_dev);
     SGN_HIP(hipGetLastError());
 }
