@@ -163,7 +163,10 @@ typedef struct {
                            per step run in FP32 (FP16 links), the recurrence stays FP64 */
     double tol;         /* > 0: stop early once the lift coefficients y = sign(T_j) e_1 change by
                            less than tol (relative) between checks */
-    int check_every;    /* steps between such checks (used when tol > 0) */
+    int check_every;    /* steps between such checks (used when tol > 0).  The next check_every
+                           steps are queued before the host evaluates a check, so up to that many
+                           steps beyond the stopping point run and are discarded (counted in
+                           stats->matvecs, not in stats->iterations) */
     int two_pass;       /* nonzero: keep only three basis vectors; a second, identical pass of the
                            recurrence (the kernels are deterministic) rebuilds v_j and accumulates
                            x, at twice the stencil work (memory O(n) instead of O(k n)) */

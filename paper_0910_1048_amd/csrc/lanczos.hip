@@ -430,29 +430,37 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
 
         const auto t_kry = std::chrono::steady_clock::now();
         int kused = k, checked = 0;  // checked: size of the last small sign computed in the loop
-        for (int j = 0; j < k; ++j) {
-            step(j, k);
-            if (j + 1 == k) break;
-            if (opts->tol > 0 && opts->check_every > 0 && (j + 1) % opts->check_every == 0 && j + 1 < k) {
-                const int kk = j + 1;
-                download(kk);
-                small_sign(kk, ycur);
-                checked = kk;
-                if (!yprev.empty()) {
-                    double num = 0.0, den = 0.0;
-                    for (int i = 0; i < kk; ++i) {
-                        z64 d = ycur[i];
-                        if (i < (int)yprev.size()) d = d - yprev[i];
-                        num += norm2(d);
-                        den += norm2(ycur[i]);
-                    }
-                    if (std::sqrt(num) <= opts->tol * std::sqrt(den)) {
-                        kused = kk;
-                        break;
-                    }
+        // With an early stop, T_kk is downloaded at every check point kk and the next check_every
+        // steps are queued before the host evaluates sign(T_kk) e_1, so the host's small sign and the
+        // device's Lanczos steps overlap.  When the check stops at kk, the steps queued beyond it are
+        // discarded (they do not change steps < kk: the same launches give the same results).
+        const bool adaptive = opts->tol > 0 && opts->check_every > 0;
+        const int ce = adaptive ? opts->check_every : k;
+        int launched = 0;
+        auto launch_to = [&](int upto) {
+            for (; launched < upto; ++launched) step(launched, k);
+        };
+        launch_to(std::min(ce, k));
+        while (adaptive && launched < k) {
+            const int kk = launched;
+            download(kk);
+            launch_to(std::min(kk + ce, k));
+            small_sign(kk, ycur);
+            checked = kk;
+            if (!yprev.empty()) {
+                double num = 0.0, den = 0.0;
+                for (int i = 0; i < kk; ++i) {
+                    z64 d = ycur[i];
+                    if (i < (int)yprev.size()) d = d - yprev[i];
+                    num += norm2(d);
+                    den += norm2(ycur[i]);
                 }
-                yprev = ycur;
+                if (std::sqrt(num) <= opts->tol * std::sqrt(den)) {
+                    kused = kk;
+                    break;
+                }
             }
+            yprev = ycur;
         }
         SGN_HIP(hipGetLastError());
         download(kused);
@@ -489,7 +497,7 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
         SGN_HIP(hipStreamSynchronize(s));
         if (stats) {
             stats->iterations = kused;
-            stats->matvecs = (two_pass ? 2 : 1) * (2 * kused - 1);
+            stats->matvecs = 2 * launched - (launched == k ? 1 : 0) + (two_pass ? 2 * (kused - 1) : 0);
             stats->min_abs_re = minre;
             stats->krylov_ms = kry_ms;
             stats->small_ms = small_ms;
