@@ -10,6 +10,9 @@
 // where X (unit upper triangular) holds the eigenvectors of S.  Z is never
 // formed: the QR sweeps record their rotations, and Z^H e_1 and Z u are two
 // replays of them (O(1) per rotation instead of a length-k column update).
+// The sweeps work on separate real and imaginary planes, apply the column part
+// of each rotation along rows after the sweep wherever the sweep no longer reads
+// it, and are built for AVX2/FMA as well as for the baseline x86-64 set.
 #include "small_sign.h"
 #include "sgn_internal.h"
 
@@ -17,6 +20,7 @@
 #include <cmath>
 #include <complex>
 #include <limits>
+#include <memory>
 #include <vector>
 
 namespace sgn {
@@ -71,24 +75,144 @@ struct Rot {
     zc s;
 };
 
+// The sweep kernels are inlined into two builds of the Schur routine (below).
+#define SGN_INLINE inline __attribute__((always_inline))
+
+// A square matrix as two row-major planes (real and imaginary parts): the rotation
+// loops of the QR sweeps then run on plain double arrays, which the compiler vectorises.
+struct Planes {
+    int n;
+    std::vector<double> re, im;
+    explicit Planes(const Mat &A) : n(A.n), re((size_t)A.n * A.n), im((size_t)A.n * A.n)
+    {
+        for (size_t q = 0; q < A.a.size(); ++q) {
+            re[q] = A.a[q].real();
+            im[q] = A.a[q].imag();
+        }
+    }
+    zc get(int i, int j) const { return zc(re[(size_t)i * n + j], im[(size_t)i * n + j]); }
+    void set(int i, int j, zc v)
+    {
+        re[(size_t)i * n + j] = v.real();
+        im[(size_t)i * n + j] = v.imag();
+    }
+    double *rr(int i) { return re.data() + (size_t)i * n; }
+    double *ri(int i) { return im.data() + (size_t)i * n; }
+    void store(Mat &A) const
+    {
+        for (size_t q = 0; q < A.a.size(); ++q) A.a[q] = zc(re[q], im[q]);
+    }
+};
+
+// Rows a, b <- G [a; b] over len entries, G = [[c, s], [-conj(s), c]].
+SGN_INLINE void rotate_row_pair(double *__restrict ar, double *__restrict ai, double *__restrict br,
+                            double *__restrict bi, int len, double c, double sr, double si)
+{
+    for (int j = 0; j < len; ++j) {
+        const double xr = ar[j], xi = ai[j], yr = br[j], yi = bi[j];
+        ar[j] = c * xr + sr * yr - si * yi;
+        ai[j] = c * xi + sr * yi + si * yr;
+        br[j] = c * yr - sr * xr - si * xi;
+        bi[j] = c * yi - sr * xi + si * xr;
+    }
+}
+
+// Rotations of one sweep from the right, applied along R rows at once: for q = 0..cnt-1 in order,
+// (row[m], row[m+1]) <- (row[m] c + row[m+1] conj(s), row[m+1] c - row[m] s) with m = m0 + q and
+// (c, s) = (gc[q], gsr[q] + i gsi[q]).  The entry moving right is carried in registers (each entry
+// is read and written once); the R rows are independent chains, interleaved for the pipelines.
+template <int R>
+SGN_INLINE void rotate_rows_right(double *const *re, double *const *im, const double *gc, const double *gsr,
+                              const double *gsi, int m0, int cnt)
+{
+    if (cnt <= 0) return;
+    double tr[R], ti[R];
+    for (int r = 0; r < R; ++r) {
+        tr[r] = re[r][m0];
+        ti[r] = im[r][m0];
+    }
+    for (int q = 0; q < cnt; ++q) {
+        const double c = gc[q], sr = gsr[q], si = gsi[q];
+        const int m = m0 + q;
+        for (int r = 0; r < R; ++r) {
+            const double yr = re[r][m + 1], yi = im[r][m + 1];
+            re[r][m] = c * tr[r] + sr * yr + si * yi;
+            im[r][m] = c * ti[r] + sr * yi - si * yr;
+            const double nr = c * yr - sr * tr[r] + si * ti[r];
+            const double ni = c * yi - sr * ti[r] - si * tr[r];
+            tr[r] = nr;
+            ti[r] = ni;
+        }
+    }
+    for (int r = 0; r < R; ++r) {
+        re[r][m0 + cnt] = tr[r];
+        im[r][m0 + cnt] = ti[r];
+    }
+}
+
+// The sweep's rotations m = max(l, i) .. ihi-1 on rows i = i0 .. i1-1 of P (row i is touched by
+// rotation m only if i <= m + 2; rows i <= m are the ones left for after the sweep).
+SGN_INLINE void rotate_rows_after_sweep(Planes &P, int i0, int i1, int l, int ihi, const std::vector<double> &gc,
+                             const std::vector<double> &gsr, const std::vector<double> &gsi)
+{
+    constexpr int R = 4;
+    int i = i0;
+    for (; i + R <= i1; i += R) {
+        // rows i..i+R-1 start at max(l, row); bring the earlier ones up to the last row's start
+        const int mc = std::max(l, i + R - 1);
+        for (int r = 0; r < R - 1; ++r) {
+            const int m0 = std::max(l, i + r);
+            double *pr[1] = {P.rr(i + r)}, *pi[1] = {P.ri(i + r)};
+            rotate_rows_right<1>(pr, pi, gc.data() + (m0 - l), gsr.data() + (m0 - l), gsi.data() + (m0 - l), m0,
+                                 std::min(mc, ihi) - m0);
+        }
+        if (mc >= ihi) continue;
+        double *pr[R], *pi[R];
+        for (int r = 0; r < R; ++r) {
+            pr[r] = P.rr(i + r);
+            pi[r] = P.ri(i + r);
+        }
+        rotate_rows_right<R>(pr, pi, gc.data() + (mc - l), gsr.data() + (mc - l), gsi.data() + (mc - l), mc,
+                             ihi - mc);
+    }
+    for (; i < i1; ++i) {
+        const int m0 = std::max(l, i);
+        double *pr[1] = {P.rr(i)}, *pi[1] = {P.ri(i)};
+        rotate_rows_right<1>(pr, pi, gc.data() + (m0 - l), gsr.data() + (m0 - l), gsi.data() + (m0 - l), m0,
+                             ihi - m0);
+    }
+}
+
 // Complex Schur decomposition of upper Hessenberg H (overwritten by S).  The unitary
 // factor is accumulated into *Z, or, with Z null, its rotations are appended to *rots
 // (Z = G_1 G_2 ... in that order).  Returns false if the iteration did not converge.
-bool hessenberg_schur(Mat &H, Mat *Z, std::vector<Rot> *rots = nullptr)
+//
+// Within a sweep, rotation m acts on rows m, m+1 (from the left) and on columns m, m+1
+// (from the right).  Its column part is needed at once only on rows m+1 and m+2, which
+// the next rotation reads; rows 0..m are touched by no later row rotation of the sweep,
+// so their column rotations are applied after the sweep, along the rows (contiguous in
+// the row-major storage) instead of down the columns.
+SGN_INLINE bool hessenberg_schur_body(Mat &Hm, Mat *Zm, std::vector<Rot> *rots)
 {
-    const int n = H.n;
+    const int n = Hm.n;
+    Planes H(Hm);
+    std::unique_ptr<Planes> Z(Zm ? new Planes(*Zm) : nullptr);
     const double ulp = std::numeric_limits<double>::epsilon();
     const double smallnum = std::numeric_limits<double>::min() * (n / ulp);
     int ihi = n - 1;
     int its = 0, total = 0;
     const int max_total = 60 * std::max(n, 10);
+    std::vector<double> gc, gsr, gsi;
+    gc.reserve(n);
+    gsr.reserve(n);
+    gsi.reserve(n);
     while (ihi >= 0) {
         // look for a negligible subdiagonal entry
         int l = ihi;
         for (; l > 0; --l) {
-            const double tst = cabs1(H(l - 1, l - 1)) + cabs1(H(l, l));
-            if (cabs1(H(l, l - 1)) <= std::max(ulp * tst, smallnum)) {
-                H(l, l - 1) = 0.0;
+            const double tst = cabs1(H.get(l - 1, l - 1)) + cabs1(H.get(l, l));
+            if (cabs1(H.get(l, l - 1)) <= std::max(ulp * tst, smallnum)) {
+                H.set(l, l - 1, 0.0);
                 break;
             }
         }
@@ -102,55 +226,87 @@ bool hessenberg_schur(Mat &H, Mat *Z, std::vector<Rot> *rots = nullptr)
         // shift
         zc sigma;
         if (its % 11 == 10) {  // exceptional shift
-            sigma = H(ihi, ihi) + 0.75 * std::abs(H(ihi, ihi - 1).real());
+            sigma = H.get(ihi, ihi) + 0.75 * std::abs(H.get(ihi, ihi - 1).real());
         } else {
-            const zc a = H(ihi - 1, ihi - 1), b = H(ihi - 1, ihi), c = H(ihi, ihi - 1), d = H(ihi, ihi);
+            const zc a = H.get(ihi - 1, ihi - 1), b = H.get(ihi - 1, ihi), c = H.get(ihi, ihi - 1),
+                     d = H.get(ihi, ihi);
             const zc tr2 = 0.5 * (a + d);
             const zc disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
             const zc e1 = tr2 + disc, e2 = tr2 - disc;
             sigma = (std::abs(e1 - d) <= std::abs(e2 - d)) ? e1 : e2;
         }
         // implicit single-shift QR sweep on rows/columns l..ihi
+        gc.clear();
+        gsr.clear();
+        gsi.clear();
         for (int m = l; m < ihi; ++m) {
             zc x, y;
             if (m == l) {
-                x = H(l, l) - sigma;
-                y = H(l + 1, l);
+                x = H.get(l, l) - sigma;
+                y = H.get(l + 1, l);
             } else {
-                x = H(m, m - 1);
-                y = H(m + 1, m - 1);
+                x = H.get(m, m - 1);
+                y = H.get(m + 1, m - 1);
             }
             double c;
             zc s;
             givens(x, y, c, s);
             // rows m, m+1  (all columns from the bulge column to the end: full Schur form)
-            for (int j = (m == l ? l : m - 1); j < n; ++j) {
-                const zc t1 = H(m, j), t2 = H(m + 1, j);
-                H(m, j) = c * t1 + cmul(s, t2);
-                H(m + 1, j) = c * t2 - cmul(std::conj(s), t1);
-            }
-            if (m > l) H(m + 1, m - 1) = 0.0;
-            // columns m, m+1
+            const int j0 = (m == l ? l : m - 1);
+            rotate_row_pair(H.rr(m) + j0, H.ri(m) + j0, H.rr(m + 1) + j0, H.ri(m + 1) + j0, n - j0, c, s.real(),
+                            s.imag());
+            if (m > l) H.set(m + 1, m - 1, 0.0);
+            // columns m, m+1 on rows m+1, m+2 now; rows 0..m after the sweep
             const int imax = std::min(m + 2, ihi);
-            for (int i = 0; i <= imax; ++i) {
-                const zc t1 = H(i, m), t2 = H(i, m + 1);
-                H(i, m) = t1 * c + cmul(t2, std::conj(s));
-                H(i, m + 1) = t2 * c - cmul(t1, s);
+            for (int i = m + 1; i <= imax; ++i) {
+                const zc t1 = H.get(i, m), t2 = H.get(i, m + 1);
+                H.set(i, m, t1 * c + cmul(t2, std::conj(s)));
+                H.set(i, m + 1, t2 * c - cmul(t1, s));
             }
-            if (Z) {
-                for (int i = 0; i < n; ++i) {
-                    const zc t1 = (*Z)(i, m), t2 = (*Z)(i, m + 1);
-                    (*Z)(i, m) = t1 * c + cmul(t2, std::conj(s));
-                    (*Z)(i, m + 1) = t2 * c - cmul(t1, s);
+            gc.push_back(c);
+            gsr.push_back(s.real());
+            gsi.push_back(s.imag());
+            if (rots) rots->push_back({m, c, s});
+        }
+        rotate_rows_after_sweep(H, 0, ihi, l, ihi, gc, gsr, gsi);
+        if (Z) {
+            // every row of Z takes every rotation of the sweep
+            constexpr int R = 4;
+            int i = 0;
+            for (; i + R <= n; i += R) {
+                double *pr[R], *pi[R];
+                for (int r = 0; r < R; ++r) {
+                    pr[r] = Z->rr(i + r);
+                    pi[r] = Z->ri(i + r);
                 }
-            } else {
-                rots->push_back({m, c, s});
+                rotate_rows_right<R>(pr, pi, gc.data(), gsr.data(), gsi.data(), l, ihi - l);
+            }
+            for (; i < n; ++i) {
+                double *pr[1] = {Z->rr(i)}, *pi[1] = {Z->ri(i)};
+                rotate_rows_right<1>(pr, pi, gc.data(), gsr.data(), gsi.data(), l, ihi - l);
             }
         }
     }
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < i; ++j) H(i, j) = 0.0;
+        for (int j = 0; j < i; ++j) H.set(i, j, 0.0);
+    H.store(Hm);
+    if (Z) Z->store(*Zm);
     return true;
+}
+
+// The same routine built for x86-64 with AVX2 and FMA and for the baseline instruction set,
+// chosen once from the host's CPU features.
+__attribute__((target("avx2,fma"))) bool hessenberg_schur_avx2(Mat &H, Mat *Z, std::vector<Rot> *rots)
+{
+    return hessenberg_schur_body(H, Z, rots);
+}
+
+bool hessenberg_schur_base(Mat &H, Mat *Z, std::vector<Rot> *rots) { return hessenberg_schur_body(H, Z, rots); }
+
+bool hessenberg_schur(Mat &H, Mat *Z, std::vector<Rot> *rots)
+{
+    static const bool avx2 = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+    return avx2 ? hessenberg_schur_avx2(H, Z, rots) : hessenberg_schur_base(H, Z, rots);
 }
 
 }  // namespace
@@ -189,28 +345,37 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
         info->norm = tnorm;
     }
     if (!(minre > 1e-12 * tnorm)) return 3;
-    // eigenvectors of S: X(:, i) with X(i, i) = 1, X(j > i, i) = 0
+    // eigenvectors of S: column i of X with X(i, i) = 1, X(j > i, i) = 0, built in a
+    // contiguous vector (the sums run along rows of S) and kept as row i of Xt = X^T
     const double ulp = std::numeric_limits<double>::epsilon();
     const double smin = std::max(ulp * tnorm, std::numeric_limits<double>::min());
-    Mat X(k);
+    Mat Xt(k);
+    std::vector<zc> xv(k);
     double cond_est = 1.0;
     for (int i = 0; i < k; ++i) {
-        X(i, i) = 1.0;
+        xv[i] = 1.0;
         const zc lam = S(i, i);
         for (int j = i - 1; j >= 0; --j) {
-            zc acc = 0.0;
-            for (int l = j + 1; l <= i; ++l) acc += cmul(S(j, l), X(l, i));
+            const zc *srow = &S(j, 0);
+            double ar = 0.0, ai = 0.0;
+            for (int l = j + 1; l <= i; ++l) {
+                ar += srow[l].real() * xv[l].real() - srow[l].imag() * xv[l].imag();
+                ai += srow[l].real() * xv[l].imag() + srow[l].imag() * xv[l].real();
+            }
             zc den = S(j, j) - lam;
             if (std::abs(den) < smin) den = smin;
-            X(j, i) = -acc / den;
+            xv[j] = -zc(ar, ai) / den;
         }
         double cn = 0.0;
-        for (int j = 0; j <= i; ++j) cn += std::norm(X(j, i));
+        for (int j = 0; j <= i; ++j) {
+            cn += std::norm(xv[j]);
+            Xt(i, j) = xv[j];
+        }
         cond_est = std::max(cond_est, std::sqrt(cn));
     }
     if (info) info->eigvec_growth = cond_est;
     // q = Z^H e_1 (the first row of Z: e_1^T G_1 G_2 ..., conjugated);
-    // c = X^{-1} q (unit upper triangular back substitution)
+    // c = X^{-1} q (unit upper triangular, solved column by column: rows of Xt)
     std::vector<zc> c(k, zc(0.0, 0.0));
     c[0] = 1.0;
     for (const Rot &g : rots) {
@@ -219,16 +384,17 @@ int small_sign_e1(int k, const std::complex<double> *diag, const std::complex<do
         c[g.m + 1] = -t1 * g.s + t2 * g.c;
     }
     for (int i = 0; i < k; ++i) c[i] = std::conj(c[i]);
-    for (int i = k - 1; i >= 0; --i) {
-        zc acc = c[i];
-        for (int j = i + 1; j < k; ++j) acc -= cmul(X(i, j), c[j]);
-        c[i] = acc;
+    for (int j = k - 1; j > 0; --j) {
+        const zc cj = c[j];
+        const zc *xrow = &Xt(j, 0);
+        for (int i = 0; i < j; ++i) c[i] -= cmul(xrow[i], cj);
     }
     // u = X sign(Lambda) c ; y = Z u
     std::vector<zc> u(k, zc(0, 0));
     for (int j = 0; j < k; ++j) {
         const zc cj = sgn[j] * c[j];
-        for (int i = 0; i <= j; ++i) u[i] += cmul(X(i, j), cj);
+        const zc *xrow = &Xt(j, 0);
+        for (int i = 0; i <= j; ++i) u[i] += cmul(xrow[i], cj);
     }
     // y = Z u = G_1 (G_2 (... u)): the rotations in reverse order
     for (auto it = rots.rbegin(); it != rots.rend(); ++it) {
@@ -280,7 +446,7 @@ int small_eig(int n, const std::complex<double> *a, std::complex<double> *lam, s
         }
         for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
     }
-    if (!hessenberg_schur(H, &Z)) return 2;
+    if (!hessenberg_schur(H, &Z, nullptr)) return 2;
     double tnorm = 0.0;
     for (int i = 0; i < n; ++i)
         for (int j = i; j < n; ++j) tnorm = std::max(tnorm, std::abs(H(i, j)));
