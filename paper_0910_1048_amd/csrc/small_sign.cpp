@@ -19,8 +19,10 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <limits>
 #include <memory>
+#include <string>
 #include <vector>
 
 namespace sgn {
@@ -295,7 +297,8 @@ SGN_INLINE bool hessenberg_schur_body(Mat &Hm, Mat *Zm, std::vector<Rot> *rots)
 }
 
 // The same routine built for x86-64 with AVX2 and FMA and for the baseline instruction set,
-// chosen once from the host's CPU features.
+// chosen once from the host's CPU features (SGN_HOST_ISA=baseline in the environment forces
+// the baseline build).
 __attribute__((target("avx2,fma"))) bool hessenberg_schur_avx2(Mat &H, Mat *Z, std::vector<Rot> *rots)
 {
     return hessenberg_schur_body(H, Z, rots);
@@ -305,7 +308,11 @@ bool hessenberg_schur_base(Mat &H, Mat *Z, std::vector<Rot> *rots) { return hess
 
 bool hessenberg_schur(Mat &H, Mat *Z, std::vector<Rot> *rots)
 {
-    static const bool avx2 = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+    static const bool avx2 = [] {
+        const char *isa = std::getenv("SGN_HOST_ISA");
+        if (isa && std::string(isa) == "baseline") return false;
+        return __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+    }();
     return avx2 ? hessenberg_schur_avx2(H, Z, rots) : hessenberg_schur_base(H, Z, rots);
 }
 

@@ -74,3 +74,29 @@ def test_errors():
     with pytest.raises(sgn.SgnError) as e:
         sgn.sgn_small_sign([1.0, np.nan], [0.5], [0.5])
     assert e.value.status == 1
+
+
+def test_baseline_isa_build_matches_oracle():
+    """The Schur routine is built for AVX2/FMA and for baseline x86-64; the library picks one
+    per host.  SGN_HOST_ISA=baseline forces the baseline build in a fresh process."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, sys\n"
+        "sys.path.insert(0, 'tests')\n"
+        "from test_small_sign_host import _lanczos_T, _parts\n"
+        "import paper_0910_1048_amd as sgn\n"
+        "from oracle import krylov\n"
+        "T = _lanczos_T((4, 4, 4, 4), 0.3, 200)\n"
+        "y, _ = sgn.sgn_small_sign(*_parts(T))\n"
+        "w = krylov.small_sign_e1(T)\n"
+        "print(np.linalg.norm(y - w) / np.linalg.norm(w))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, SGN_HOST_ISA="baseline")
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                         timeout=600)
+    assert out.returncode == 0, out.stderr[-2000:]
+    err = float(out.stdout.strip().splitlines()[-1])
+    print(f"baseline build: rel err {err:.1e}")
+    assert err < 1e-11
