@@ -169,3 +169,25 @@ def test_two_pass_equals_one_pass(prec):
         # the second pass replays the k - 1 full steps that built v_1 .. v_k
         assert s2["matvecs"] == s1["matvecs"] + 2 * (s1["iterations"] - 1)
         assert e < 1e-14
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32])
+def test_adaptive_stop_equals_fixed_k(prec):
+    """With an early stop the steps queued past the stopping check are discarded: the result
+    equals the fixed-k run with k = the k used (same launches up to that step), and the
+    extra steps show up only in the matvec count."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    lat = lattice(U, dims)
+    xa, sa = _gpu_lanczos(lat, 0.3, b, 400, prec=prec, tol=1e-10, check_every=20)
+    kused = sa["iterations"]
+    assert kused < 400 and kused % 20 == 0
+    xf, sf = _gpu_lanczos(lat, 0.3, b, kused, prec=prec)
+    e = _rel(xa, xf)
+    print(f"prec={prec}: k used {kused}, matvecs adaptive {sa['matvecs']} / fixed {sf['matvecs']}, "
+          f"adaptive vs fixed {e:.1e}", flush=True)
+    assert e < 1e-14
+    # fixed k: 2k - 1 applications; adaptive: every queued step in full (up to 20 beyond k used)
+    assert sf["matvecs"] == 2 * kused - 1
+    assert sa["matvecs"] == 2 * min(kused + 20, 400) - (1 if kused + 20 >= 400 else 0)
