@@ -30,9 +30,20 @@ namespace {
 using zc = std::complex<double>;
 
 // H[:, j] = a + b (device, j+1 entries); then hsub = ||w|| and its inverse for the scaling
-__global__ void fom_hcol_kernel(const z64 *a, const z64 *b, int nj, z64 *hcol)
+// Arnoldi column of step j (nj = j + 1 basis vectors): hcol = (2 I - G) h1, with h1 = V^H w and
+// G = V^H V (Hermitian; column l of G holds v_i^H v_l for i <= l).  This is classical Gram-Schmidt
+// with one reorthogonalisation, whose second-pass dots V^H (w - V h1) = h1 - G h1 come from the
+// Gram matrix rather than from a second pass over the basis.
+__global__ void fom_gram_kernel(const z64 *G, int ld, int nj, const z64 *h1, z64 *hcol)
 {
-    for (int i = threadIdx.x; i < nj; i += blockDim.x) hcol[i] = a[i] + b[i];
+    for (int i = threadIdx.x; i < nj; i += blockDim.x) {
+        z64 acc = {0.0, 0.0};
+        for (int l = 0; l < nj; ++l) {
+            const z64 g = l >= i ? G[(size_t)l * ld + i] : conj(G[(size_t)i * ld + l]);
+            acc = acc + g * h1[l];
+        }
+        hcol[i] = z64{2.0 * h1[i].r - acc.r, 2.0 * h1[i].i - acc.i};
+    }
 }
 
 __global__ void fom_norm_kernel(const z64 *partials, int nb, z64 *hsub, z64 *inv)
@@ -274,13 +285,14 @@ sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, c
             st->nshift = ns;
         }
         // workspace: basis V_{k+1}, w, t, x_int, canonical r (from the arena)
-        const size_t hbytes = sizeof(z64) * ((size_t)ld * k + 4 * (size_t)ld + 4);
+        const size_t hbytes = sizeof(z64) * ((size_t)ld * k + 4 * (size_t)ld + 4 + (size_t)ld * ld);
         char *arena = static_cast<char *>(ctx.ensure_arena((size_t)(k + 1) * b64 + 3 * b64 + c64 + hbytes));
         char *Vb = arena;
         char *w = Vb + (size_t)(k + 1) * b64, *t = w + b64, *xi = t + b64, *rcan = xi + b64;
         z64 *Hd = reinterpret_cast<z64 *>(rcan + c64);  // column-major (k+1) x k
         z64 *h1 = Hd + (size_t)ld * k, *h2 = h1 + ld, *cd = h2 + ld, *scal = cd + ld;  // scal: hsub, inv
         z64 *zd = scal + 4;  // GMRES: the seed's residual z in the basis V_{k+1} (ld entries)
+        z64 *Gd = zd + ld;   // Gram matrix V^H V of the cycle's basis, column-major ld x ld (upper triangle)
         bool lo = false;                   // this cycle runs in FP32 (basis slots of b32 bytes)
         sgn_prec sp = SGN_PREC_F64;        // stencil precision of this cycle
         auto Vj = [&](int j) { return Vb + (size_t)j * (lo ? b32 : b64); };
@@ -307,7 +319,9 @@ sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, c
         for (int i = 1; i < ns; ++i)
             if (std::abs(rf->sigma[i]) < std::abs(rf->sigma[seed])) seed = i;
         const int nvb = vec_blocks(n);
-        z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nvb, 1)));
+        // partials for the widest reduction of a step (two dots per basis vector), sized once
+        z64 *part = static_cast<z64 *>(
+            ctx.ensure_partials(sizeof(z64) * std::max<size_t>(2 * (size_t)ld * kGramBlocks, (size_t)nvb)));
         const int max_cycles = o->max_restarts > 0 ? o->max_restarts : 1000;
         int cycles = 0, matvecs = 1, steps = 0;
         double small_ms = 0.0;
@@ -333,14 +347,13 @@ sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, c
                 ep.a = c2;
                 dslash_launch(lat, sp, opA, t, w, ep, s);
                 matvecs += 2;
-                // classical Gram-Schmidt, twice (FP64 sums also for an FP32 basis)
-                deflate_dots(Vb, j + 1, w, n, h1, ctx, s, lo);
-                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h1, nullptr, n, s, lo);
-                deflate_dots(Vb, j + 1, w, n, h2, ctx, s, lo);
-                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, Vb, j + 1, h2, nullptr, n, s, lo);
-                hipLaunchKernelGGL(fom_hcol_kernel, dim3(1), dim3(256), 0, s, h1, h2, j + 1, Hd + (size_t)j * ld);
-                part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nvb, 1)));
-                const int nb = norm2_partials(w, n, lo, part, s);
+                // classical Gram-Schmidt with one reorthogonalisation in two passes over the basis
+                // (FP64 sums also for an FP32 basis): h1 = V^H w together with the Gram column
+                // V^H v_j, the column h = (2 I - G) h1, then w -= V h with the partials of ||w||^2
+                gram_dots(Vb, j + 1, w, Vj(j), n, h1, Gd + (size_t)j * ld, ctx, s, lo);
+                hipLaunchKernelGGL(fom_gram_kernel, dim3(1), dim3(64), 0, s, (const z64 *)Gd, ld, j + 1,
+                                   (const z64 *)h1, Hd + (size_t)j * ld);
+                const int nb = combine_norm(w, Vb, j + 1, Hd + (size_t)j * ld, n, part, s, lo);
                 hipLaunchKernelGGL(fom_norm_kernel, dim3(1), dim3(256), 0, s, part, nb, Hd + (size_t)j * ld + j + 1,
                                    scal + 1);
                 if (lo)

@@ -13,6 +13,7 @@ namespace sgn {
 
 constexpr int kVecThreads = 256;
 constexpr int kMaxBlocks = 1024;
+constexpr int kGramBlocks = 2048;
 
 int vec_blocks(int64_t n);
 
@@ -45,6 +46,15 @@ void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Co
                   bool f32 = false);
 void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
                      int64_t n, hipStream_t s, bool f32 = false);
+
+// Arnoldi orthogonalisation on a basis X of m vectors (same layout and precision as y):
+//   (gram_dots uses up to 2 m kGramBlocks partials)
+//   c1[i] = X_i^H y1 and c2[i] = X_i^H y2 in one pass over X  (gram_dots, c on device)
+//   y -= sum_i X_i c[i], partials[b] = sum |y|^2 of the new y  (combine_norm; returns the block count,
+//   vec_blocks(n), of the partials)
+void gram_dots(const void *X, int m, const void *y1, const void *y2, int64_t n, z64 *c1_dev, z64 *c2_dev,
+               Context &ctx, hipStream_t s, bool f32);
+int combine_norm(void *y, const void *X, int m, const z64 *c_dev, int64_t n, z64 *partials, hipStream_t s, bool f32);
 
 // LR-deflation prologue shared by the solvers (canonical complex128 vectors):
 // x = x_P = R sign(Lambda) L^H b, r = (I - R L^H) b and, if rt != nullptr, the

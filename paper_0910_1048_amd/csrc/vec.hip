@@ -143,6 +143,60 @@ __global__ void __launch_bounds__(256) mdot_kernel(const T *X, const T *y, int64
         for (int c = 0; c < cnt; ++c) partials[(int64_t)(i0 + c) * gridDim.x + blockIdx.x] = {acc[2 * c], acc[2 * c + 1]};
 }
 
+// conj(a) . b accumulated in FP64: one complex entry (double2, float2) or two (float4)
+__device__ __forceinline__ void acc_cdot(double2 a, double2 b, double &re, double &im)
+{
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+}
+__device__ __forceinline__ void acc_cdot(float2 a, float2 b, double &re, double &im)
+{
+    re += (double)a.x * b.x + (double)a.y * b.y;
+    im += (double)a.x * b.y - (double)a.y * b.x;
+}
+__device__ __forceinline__ void acc_cdot(float4 a, float4 b, double &re, double &im)
+{
+    re += (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+    im += (double)a.x * b.y - (double)a.y * b.x + (double)a.z * b.w - (double)a.w * b.z;
+}
+
+// Two right-hand sides in one pass over X: partials[i * gridDim.x + b] for conj(X_i) . y1 and
+// partials[(m + i) * gridDim.x + b] for conj(X_i) . y2, the kDotGroup vectors i of group blockIdx.y
+// (T = float4 takes complex64 entries two at a time: n counts such pairs)
+template <typename T>
+__global__ void __launch_bounds__(256) mdot2_kernel(const T *X, const T *y1, const T *y2, int64_t n, int m,
+                                                    z64 *partials)
+{
+    const int i0 = blockIdx.y * kDotGroup;
+    const int cnt = min(kDotGroup, m - i0);
+    double acc[4 * kDotGroup];
+#pragma unroll
+    for (int c = 0; c < 4 * kDotGroup; ++c) acc[c] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const T b1 = y1[e], b2 = y2[e];
+#pragma unroll
+        for (int c = 0; c < kDotGroup; ++c) {
+            if (c < cnt) {
+                const T a = X[(int64_t)(i0 + c) * n + e];
+                acc_cdot(a, b1, acc[2 * c], acc[2 * c + 1]);
+                acc_cdot(a, b2, acc[2 * kDotGroup + 2 * c], acc[2 * kDotGroup + 2 * c + 1]);
+            }
+        }
+    }
+    __shared__ double lds[4 * kDotGroup * 4];
+    block_sum<4 * kDotGroup>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < kDotGroup; ++c) {  // constant indices keep acc in registers
+            if (c < cnt) {
+                partials[(int64_t)(i0 + c) * gridDim.x + blockIdx.x] = {acc[2 * c], acc[2 * c + 1]};
+                partials[(int64_t)(m + i0 + c) * gridDim.x + blockIdx.x] = {acc[2 * kDotGroup + 2 * c],
+                                                                             acc[2 * kDotGroup + 2 * c + 1]};
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) mfinalize_kernel(const z64 *partials, int nbx, z64 *out)
 {
     const int i = blockIdx.x;
@@ -177,6 +231,73 @@ __global__ void mcombine_kernel(T *y, z64 alpha, z64 beta, const T *X, int m, co
         z64 r = alpha * z64{(double)yv.x, (double)yv.y} + beta * acc;
         y[e] = mk2<T>(r.r, r.i);
     }
+}
+
+// y -= sum_i X_i c[i]; partials[block] = sum |y|^2 of the stored (rounded) new y over the block's slice
+template <typename T>
+__global__ void __launch_bounds__(256) mcombine_norm_kernel(T *y, const T *X, int m, const z64 *c, int64_t n,
+                                                            z64 *partials)
+{
+    double nrm = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 acc = {0.0, 0.0};
+        int i = 0;
+        for (; i + 4 <= m; i += 4) {  // four independent loads in flight
+            const T x0 = X[(int64_t)i * n + e], x1 = X[(int64_t)(i + 1) * n + e], x2 = X[(int64_t)(i + 2) * n + e],
+                    x3 = X[(int64_t)(i + 3) * n + e];
+            acc = acc + z64{(double)x0.x, (double)x0.y} * c[i];
+            acc = acc + z64{(double)x1.x, (double)x1.y} * c[i + 1];
+            acc = acc + z64{(double)x2.x, (double)x2.y} * c[i + 2];
+            acc = acc + z64{(double)x3.x, (double)x3.y} * c[i + 3];
+        }
+        for (; i < m; ++i) {
+            const T xv = X[(int64_t)i * n + e];
+            acc = acc + z64{(double)xv.x, (double)xv.y} * c[i];
+        }
+        const T yv = y[e];
+        const T r = mk2<T>((double)yv.x - acc.r, (double)yv.y - acc.i);
+        y[e] = r;
+        nrm += (double)r.x * r.x + (double)r.y * r.y;
+    }
+    __shared__ double lds[4];
+    double v[1] = {nrm};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = {v[0], 0.0};
+}
+
+// mcombine_norm_kernel for complex64 vectors taken two entries at a time (n2 float4 pairs)
+__global__ void __launch_bounds__(256) mcombine_norm_pairs_kernel(float4 *y, const float4 *X, int m, const z64 *c,
+                                                                  int64_t n2, z64 *partials)
+{
+    double nrm = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += (int64_t)gridDim.x * blockDim.x) {
+        z64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+        int i = 0;
+        for (; i + 4 <= m; i += 4) {
+            float4 xv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = X[(int64_t)(i + q) * n2 + e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a0 = a0 + z64{(double)xv[q].x, (double)xv[q].y} * c[i + q];
+                a1 = a1 + z64{(double)xv[q].z, (double)xv[q].w} * c[i + q];
+            }
+        }
+        for (; i < m; ++i) {
+            const float4 xv = X[(int64_t)i * n2 + e];
+            a0 = a0 + z64{(double)xv.x, (double)xv.y} * c[i];
+            a1 = a1 + z64{(double)xv.z, (double)xv.w} * c[i];
+        }
+        const float4 yv = y[e];
+        const float4 r = make_float4((float)((double)yv.x - a0.r), (float)((double)yv.y - a0.i),
+                                     (float)((double)yv.z - a1.r), (float)((double)yv.w - a1.i));
+        y[e] = r;
+        nrm += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+    }
+    __shared__ double lds[4];
+    double v[1] = {nrm};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = {v[0], 0.0};
 }
 
 // partials[block] = ( sum |y - x|^2 , sum |x|^2 ) over the block's slice
@@ -289,6 +410,44 @@ void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Co
                            n, m, part);
     hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, c_dev);
     SGN_HIP(hipGetLastError());
+}
+
+void gram_dots(const void *X, int m, const void *y1, const void *y2, int64_t n, z64 *c1_dev, z64 *c2_dev,
+               Context &ctx, hipStream_t s, bool f32)
+{
+    if (m <= 0) return;
+    // enough blocks to keep loads in flight when there is a single group (small m)
+    const int nbx = std::max(1, std::min(kGramBlocks, (int)((n + 255) / 256)));
+    const int ng = (m + kDotGroup - 1) / kDotGroup;
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)2 * m * nbx * sizeof(z64)));
+    if (f32 && n % 2 == 0)  // pairs of complex64 entries: 16-byte loads, as for complex128
+        hipLaunchKernelGGL(mdot2_kernel<float4>, dim3(nbx, ng), dim3(256), 0, s, (const float4 *)X, (const float4 *)y1,
+                           (const float4 *)y2, n / 2, m, part);
+    else if (f32)
+        hipLaunchKernelGGL(mdot2_kernel<float2>, dim3(nbx, ng), dim3(256), 0, s, (const float2 *)X, (const float2 *)y1,
+                           (const float2 *)y2, n, m, part);
+    else
+        hipLaunchKernelGGL(mdot2_kernel<double2>, dim3(nbx, ng), dim3(256), 0, s, (const double2 *)X,
+                           (const double2 *)y1, (const double2 *)y2, n, m, part);
+    hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, c1_dev);
+    hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part + (size_t)m * nbx, nbx, c2_dev);
+    SGN_HIP(hipGetLastError());
+}
+
+int combine_norm(void *y, const void *X, int m, const z64 *c_dev, int64_t n, z64 *partials, hipStream_t s, bool f32)
+{
+    const int nb = vec_blocks(n);
+    if (f32 && n % 2 == 0)
+        hipLaunchKernelGGL(mcombine_norm_pairs_kernel, dim3(nb), dim3(256), 0, s, (float4 *)y, (const float4 *)X, m,
+                           c_dev, n / 2, partials);
+    else if (f32)
+        hipLaunchKernelGGL(mcombine_norm_kernel<float2>, dim3(nb), dim3(256), 0, s, (float2 *)y, (const float2 *)X, m,
+                           c_dev, n, partials);
+    else
+        hipLaunchKernelGGL(mcombine_norm_kernel<double2>, dim3(nb), dim3(256), 0, s, (double2 *)y,
+                           (const double2 *)X, m, c_dev, n, partials);
+    SGN_HIP(hipGetLastError());
+    return nb;
 }
 
 void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
