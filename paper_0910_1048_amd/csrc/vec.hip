@@ -114,7 +114,7 @@ __global__ void cvt32to64(const float4 *__restrict__ x, double2 *__restrict__ y,
 // grid (nbx, m): partials[i * nbx + bx] = sum conj(X_i) y over the block's slice
 // (T = double2 or float2; FP64 accumulation either way)
 constexpr int kDotGroup = 8;   // dot products per pass of y
-constexpr int kDotBlocks = 512;  // blocks per pass (grid-stride over the elements)
+constexpr int kDotBlocks = 2048;  // blocks per pass (grid-stride over the elements; enough loads in flight)
 
 // partials[i * gridDim.x + b] = sum over block b's slice of conj(X_i) . y for the kDotGroup
 // vectors i of group blockIdx.y (fewer in the last group); y is read once per group
@@ -221,7 +221,19 @@ __global__ void mcombine_kernel(T *y, z64 alpha, z64 beta, const T *X, int m, co
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         z64 acc = {0.0, 0.0};
-        for (int i = 0; i < m; ++i) {
+        int i = 0;
+        for (; i + 4 <= m; i += 4) {  // four independent loads in flight
+            T xv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = X[(int64_t)(i + q) * n + e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                z64 ci = c[i + q];
+                if (d) ci = d[i + q] * ci;
+                acc = acc + z64{(double)xv[q].x, (double)xv[q].y} * ci;
+            }
+        }
+        for (; i < m; ++i) {
             z64 ci = c[i];
             if (d) ci = d[i] * ci;
             const T xv = X[(int64_t)i * n + e];
@@ -399,7 +411,7 @@ void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s)
 void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s, bool f32)
 {
     if (m <= 0) return;
-    const int nbx = std::max(1, std::min(kDotBlocks, vec_blocks(n)));
+    const int nbx = std::max(1, std::min(kDotBlocks, (int)((n + 255) / 256)));
     const int ng = (m + kDotGroup - 1) / kDotGroup;
     z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)m * nbx * sizeof(z64)));
     if (f32)
