@@ -11,8 +11,10 @@ HBM before the timed region.
 Reported beside it on the same GPU: the plain FP64 single-RHS form of the same
 solve (solves/s), the multishift BiCG solver (multishift_solve) mixed and FP64 and
 the multishift QMR solver (multishift_qmr) mixed and FP64 at the same accuracy target, the
-direct two-sided Lanczos method (exact sign, with the accuracy measure) and restarted
-FOM-LR (FP64 and mixed), the error of every result against an FP64 solve to
+direct two-sided Lanczos method (exact sign, with the accuracy measure; stored basis and
+two-pass), restarted FOM-LR and GMRES-LR (FP64 and mixed), LR deflation on an 8^4 lattice
+(critical eigenpairs, then the deflated mixed BiCGStab solve beside the undeflated one), the
+error of every result against an FP64 solve to
 tolerance 1e-12, the live per-kernel timing of the solver's own launches (HIP
 events on the launch stream) as HBM roofline fractions, and the CPU oracle timed
 on this host's cores on a bounded sample of the same solve.
@@ -52,6 +54,8 @@ LANCZOS = dict(k=1000, tol=1e-10, check_every=100)
 # residuals to 1e-9; mixed: FP32 below 1e-2, FP16 links below 1e-5
 FOM = dict(kmax=30, tol=1e-9)
 FOM_MIXED = dict(theta32=1e-2, theta16=1e-5)
+# LR deflation leg: 8^4 lattice (same field recipe, kappa and mu), m critical eigenpairs
+DEFL = dict(dims=(8, 8, 8, 8), m=4, eig_tol=1e-10, max_restarts=400, tol=1e-9)
 PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
 # PMC byte counts of the solver kernels, taken with rocprofv3 on this benchmark; valid only
 # while the kernel sources are the ones they were measured on
@@ -219,7 +223,7 @@ def main():
 
     # ---- the direct two-sided Lanczos method: its accuracy by the measure 1/2 ||S(S b) - b|| / ||b||
     #      (its distance to the FP64 rational reference is the rational approximation's error)
-    lanczos = fom = None
+    lanczos = lanczos2 = fom = gmres = defl = None
     if not args.no_bicg:
         sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
         torch.cuda.synchronize()
@@ -227,6 +231,7 @@ def main():
         sl = sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
         torch.cuda.synchronize()
         tl = time.perf_counter() - t0
+        x_lz = x.clone()
         ssb = torch.empty_like(bd)
         sgn.sign_lanczos_2sided(lat, W["mu"], x, ssb, **LANCZOS)
         acc = sgn.sgn_accuracy_measure(lat, bd, ssb)
@@ -249,6 +254,71 @@ def main():
             fom[name] = {"solves_per_s": round(1.0 / tf, 4), "ms_per_solve": round(tf * 1e3, 2),
                          "restarts": sf["restarts"], "arnoldi_steps": sf["iterations"], "err_vs_fp64_ref": err_of(x)}
             log(f"[bench] FOM {name}: {tf * 1e3:.1f} ms/solve, {sf['restarts']} cycles, err {fom[name]['err_vs_fp64_ref']:.2e}")
+        # ---- restarted GMRES-LR, same settings
+        gmres = {"settings": FOM, "mixed_schedule": FOM_MIXED}
+        for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
+            kw = dict(FOM, **(FOM_MIXED if prec != sgn.F64 else {}))
+            sgn.sign_gmres_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sg_ = sgn.sign_gmres_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
+            torch.cuda.synchronize()
+            tg = time.perf_counter() - t0
+            gmres[name] = {"solves_per_s": round(1.0 / tg, 4), "ms_per_solve": round(tg * 1e3, 2),
+                           "restarts": sg_["restarts"], "arnoldi_steps": sg_["iterations"],
+                           "err_vs_fp64_ref": err_of(x)}
+            log(f"[bench] GMRES {name}: {tg * 1e3:.1f} ms/solve, {sg_['restarts']} cycles, "
+                f"err {gmres[name]['err_vs_fp64_ref']:.2e}")
+        # ---- two-pass direct Lanczos: three basis vectors, the recurrence run a second time
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s2 = sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, two_pass=True, **LANCZOS)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t0
+        d2 = float(torch.linalg.norm(x - x_lz) / torch.linalg.norm(x_lz))
+        lanczos2 = {"settings": dict(LANCZOS, two_pass=True), "solves_per_s": round(1.0 / t2, 4),
+                    "ms_per_solve": round(t2 * 1e3, 2), "k": s2["iterations"], "matvecs": s2["matvecs"],
+                    "diff_vs_stored_basis": d2}
+        log(f"[bench] two-pass direct Lanczos: {t2 * 1e3:.1f} ms/solve, k = {s2['iterations']}, "
+            f"{s2['matvecs']} matvecs, vs stored basis {d2:.1e}")
+        del x_lz
+        # ---- LR deflation on 8^4: critical eigenpairs, then the deflated mixed BiCGStab solve
+        d8 = DEFL["dims"]
+        U8 = synth.gauge_field(d8, W["eps"], W["seed"])
+        lat8 = sgn.Lattice(ctx, torch.from_numpy(U8).cuda(), d8, W["kappa"])
+        b8 = torch.from_numpy(synth.gaussian_source(d8, W["seed"])).cuda()
+        x8, x8ref = torch.empty_like(b8), torch.empty_like(b8)
+        sgn.multishift_solve(sgn.Problem(lat8, W["mu"], b8, x8ref), rf, tol=1e-12, prec=sgn.F64)
+        m = DEFL["m"]
+        L8 = torch.empty((m, b8.numel()), dtype=torch.complex128, device="cuda")
+        R8 = torch.empty_like(L8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam8, alpha8, se = sgn.sgn_critical_eigenpairs(lat8, W["mu"], m, L8, R8, tol=DEFL["eig_tol"],
+                                                        max_restarts=DEFL["max_restarts"])
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        dfl = sgn.Deflation(L8, R8, np.array(lam8))
+        legs = {}
+        for name, d in (("undeflated", None), ("deflated", dfl)):
+            p8 = sgn.Problem(lat8, W["mu"], b8, x8, d)
+            sgn.multishift_bicgstab(p8, rf, tol=DEFL["tol"], prec=sgn.F32_H16, **MIXED)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s8 = sgn.multishift_bicgstab(p8, rf, tol=DEFL["tol"], prec=sgn.F32_H16, **MIXED)[0]
+            torch.cuda.synchronize()
+            t8 = time.perf_counter() - t0
+            legs[name] = {"ms_per_solve": round(t8 * 1e3, 3), "iterations": s8["iterations"],
+                          "err_vs_fp64_ref": float(torch.linalg.norm(x8 - x8ref) / torch.linalg.norm(x8ref))}
+        defl = {"lattice": list(d8), "m": m, "eigenpairs_ms": round(te * 1e3, 1), "eig_restarts": se["restarts"],
+                "eig_residual": se["residual"], "lambda_abs": [round(abs(complex(v)), 5) for v in lam8],
+                "deflation_gap": alpha8, "solves": legs}
+        log(f"[bench] deflation 8^4: {m} eigenpairs in {te * 1e3:.0f} ms ({se['restarts']} restarts), gap "
+            f"{alpha8:.4f}; mixed BiCGStab undeflated {legs['undeflated']['ms_per_solve']:.1f} ms "
+            f"({legs['undeflated']['iterations']} it), deflated {legs['deflated']['ms_per_solve']:.1f} ms "
+            f"({legs['deflated']['iterations']} it, err {legs['deflated']['err_vs_fp64_ref']:.1e})")
+        lat8.close()
+        del U8, L8, R8, dfl
 
     # ---- roofline: dominant kernel by time, and the stencil (Dslash) itself
     traffic = measured_traffic()
@@ -319,7 +389,10 @@ def main():
         "bicg": bicg,
         "qmr": qmr,
         "direct_lanczos": lanczos,
+        "direct_lanczos_two_pass": lanczos2,
         "fom": fom,
+        "gmres": gmres,
+        "deflation": defl,
         "roofline": roofline,
         "stencil_roofline": stencils,
         "kernel_time_share": time_share,
