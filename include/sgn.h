@@ -279,8 +279,9 @@ typedef struct {
 
 /* Restarted FOM-LR(m, k) (section "Restarted Arnoldi with rational functions"):
  * x = x_P + sum_i omega_i x_i with (c^2 H_W^2 - sigma_i) x_i = c H_W (I-P) b, all
- * shifts from one restarted Arnoldi process (classical Gram-Schmidt twice) on
- * c^2 H_W^2; the collinear restart of Eq. (collinearity); the projection step
+ * shifts from one restarted Arnoldi process (classical Gram-Schmidt with one
+ * reorthogonalisation, its second-pass coefficients taken from the basis's Gram
+ * matrix: two passes over the basis per step) on c^2 H_W^2; the collinear restart of Eq. (collinearity); the projection step
  * r = (I-P) v_{k+1} after every cycle.  b, x: device canonical complex128.
  * The shifted Hessenberg systems are solved on the host each cycle; the call
  * synchronises `stream`.  SGN_ERR_NOT_CONVERGED after max_restarts cycles

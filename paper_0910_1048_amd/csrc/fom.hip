@@ -285,12 +285,12 @@ sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, c
             st->nshift = ns;
         }
         // workspace: basis V_{k+1}, w, t, x_int, canonical r (from the arena)
-        const size_t hbytes = sizeof(z64) * ((size_t)ld * k + 4 * (size_t)ld + 4 + (size_t)ld * ld);
+        const size_t hbytes = sizeof(z64) * ((size_t)ld * k + 3 * (size_t)ld + 4 + (size_t)ld * ld);
         char *arena = static_cast<char *>(ctx.ensure_arena((size_t)(k + 1) * b64 + 3 * b64 + c64 + hbytes));
         char *Vb = arena;
         char *w = Vb + (size_t)(k + 1) * b64, *t = w + b64, *xi = t + b64, *rcan = xi + b64;
         z64 *Hd = reinterpret_cast<z64 *>(rcan + c64);  // column-major (k+1) x k
-        z64 *h1 = Hd + (size_t)ld * k, *h2 = h1 + ld, *cd = h2 + ld, *scal = cd + ld;  // scal: hsub, inv
+        z64 *h1 = Hd + (size_t)ld * k, *cd = h1 + ld, *scal = cd + ld;  // scal: hsub, inv
         z64 *zd = scal + 4;  // GMRES: the seed's residual z in the basis V_{k+1} (ld entries)
         z64 *Gd = zd + ld;   // Gram matrix V^H V of the cycle's basis, column-major ld x ld (upper triangle)
         bool lo = false;                   // this cycle runs in FP32 (basis slots of b32 bytes)
