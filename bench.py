@@ -55,7 +55,7 @@ LANCZOS = dict(k=1000, tol=1e-10, check_every=100)
 FOM = dict(kmax=30, tol=1e-9)
 FOM_MIXED = dict(theta32=1e-2, theta16=1e-5)
 # LR deflation leg: 8^4 lattice (same field recipe, kappa and mu), m critical eigenpairs
-# (24 Ritz pairs kept from a 64-vector basis: 86 restarts against 545 with the library's default 10 / 36)
+# (24 Ritz pairs kept from a 64-vector basis, the library's default for m = 4: 86 restarts against 545 with 10 / 36)
 DEFL = dict(dims=(8, 8, 8, 8), m=4, nev=24, kmax=64, eig_tol=1e-10, max_restarts=400, tol=1e-9)
 PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
 # PMC byte counts of the solver kernels, taken with rocprofv3 on this benchmark; valid only

@@ -238,8 +238,9 @@ sgn_status sgn_rational_zolotarev(int s, double alpha, double beta, sgn_rational
 /* ------------------------------------------------------------------ critical eigenpairs */
 typedef struct {
     int m;             /* eigenpairs wanted, m >= 1 */
-    int nev;           /* Ritz pairs kept per restart, nev > m (0: m + max(6, m/2)) */
-    int kmax;          /* Arnoldi basis size, nev + 2 <= kmax <= 1024 (0: 2 nev + 16) */
+    int nev;           /* Ritz pairs kept per restart, nev > m (0: m + max(20, m), at most kmax - 2) */
+    int kmax;          /* Arnoldi basis size, nev + 2 <= kmax <= 1024 and below 12 V
+                          (0: 2 (m + max(20, m)) + 16, held below both limits) */
     double tol;        /* Ritz residual of H_W^2 <= tol |theta| for the m + 2 wanted (0: 1e-10) */
     int max_restarts;  /* per side (0: 1000) */
     unsigned seed;     /* start vectors (a fixed pseudo-random sequence per seed) */

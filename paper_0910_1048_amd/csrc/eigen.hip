@@ -442,8 +442,12 @@ extern "C" sgn_status sgn_critical_eigenpairs(sgn_lattice l, double mu, const sg
         Context &ctx = *lat.ctx;
         SGN_HIP(hipSetDevice(ctx.device));
         const int m = o->m;
-        const int p = o->nev > 0 ? o->nev : m + std::max(6, m / 2);
-        const int k = o->kmax > 0 ? o->kmax : 2 * p + 16;
+        // defaults: a basis large enough for clustered spectra (at 8^4 with m = 4, 24 kept pairs of a
+        // 64-vector basis need 86 restarts where 10 of 36 need 545), held below the vector length
+        const int64_t nlen = 12 * lat.V;
+        const int k = o->kmax > 0 ? o->kmax
+                                  : (int)std::min<int64_t>({2 * (m + std::max(20, m)) + 16, 1024, nlen - 1});
+        const int p = o->nev > 0 ? o->nev : std::min(m + std::max(20, m), k - 2);
         SGN_REQUIRE(m >= 1, "sgn_critical_eigenpairs: m must be >= 1");
         SGN_REQUIRE(p > m, "sgn_critical_eigenpairs: nev must exceed m");
         SGN_REQUIRE(k >= p + 2 && k <= 1024, "sgn_critical_eigenpairs: kmax must be in [nev + 2, 1024]");

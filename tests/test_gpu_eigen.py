@@ -141,5 +141,5 @@ def test_eigen_error_paths():
         _eig(lat, 0.3, 4, kmax=2000)
     assert e.value.status == 1
     with pytest.raises(sgn.SgnError) as e:
-        _eig(lat, 0.3, 8, tol=1e-14, max_restarts=1)
+        _eig(lat, 0.3, 8, nev=10, kmax=36, tol=1e-14, max_restarts=1)  # small basis, one restart
     assert e.value.status == 5
