@@ -75,3 +75,17 @@ def test_rescaled_neuberger_and_zolotarev_match_oracle():
         sgn.sgn_rational_zolotarev(0, 0.1, 1.0)
     with pytest.raises(sgn.SgnError):
         sgn.sgn_rational_zolotarev(8, 1.0, 0.5)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with status 2 and one JSON line saying so
+    (before anything touches a GPU)."""
+    import json
+    import os
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    line = json.loads(out.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
