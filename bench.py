@@ -2,28 +2,40 @@
 """Benchmark: sign(H_W) b on one MI355X.
 
 One step = one evaluation of sign(H_W(mu)) b for H_W = gamma5 D_W(mu) on a
-24^3 x 48 lattice through the 16-pole Neuberger rational function, by the
-multishift BiCGStab solver in its stored-basis form with the mixed-precision
+24^3 x 48 lattice through the 16-pole Neuberger rational function g_16(cH), by
+the multishift BiCGStab solver in its stored-basis form with the mixed-precision
 schedule (FP64 -> FP32 -> FP16 links, FP64 reliable updates): libsgn's
 multishift_bicgstab.  Inputs (gauge links, source, coefficients) are resident in
-HBM before the timed region.
+HBM before the timed region; the timed solves run with the library's HIP-graph
+replay on and its launch profiling off.
 
-Reported beside it on the same GPU: the plain FP64 single-RHS form of the same
-solve (solves/s), the multishift BiCG solver (multishift_solve) mixed and FP64 and
-the multishift QMR solver (multishift_qmr) mixed and FP64 at the same accuracy target, the
-direct two-sided Lanczos method (exact sign, with the accuracy measure; stored basis and
-two-pass), restarted FOM-LR and GMRES-LR (FP64 and mixed), LR deflation on an 8^4 lattice
-(critical eigenpairs, then the deflated mixed BiCGStab solve beside the undeflated one), the
-error of every result against an FP64 solve to
-tolerance 1e-12, the live per-kernel timing of the solver's own launches (HIP
-events on the launch stream) as HBM roofline fractions, and the CPU oracle timed
-on this host's cores on a bounded sample of the same solve.
+Accuracy.  The reference is an FP64 multishift solve to 1e-12 that returns every
+shifted solution x_i; each shifted system's residual y - (c^2 H^2 - sigma_i) x_i
+is recomputed on the host with the oracle's operator, and x = sum_i omega_i x_i is
+formed on the host (`reference`).  Every leg states its error against that
+anchored g_16 reference and, where the exact sign is needed, against the direct
+two-sided Lanczos result (sign(H) b itself, checked by the accuracy measure
+1/2 ||S(S b) - b|| / ||b||).  The 16-pole function differs from sign by a few
+1e-8 here, so a leg with the pole count of Eq. (no_of_poles) for 1e-8 is timed
+too (`poles_for_target`).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+Also on the same GPU: the stencil's launch shapes autotuned for the lattice
+(setup), the Wilson stencil alone (Dslash GB/s and flop/s per precision, 24^3 x 48
+and 32^3 x 64; N = 1, 4, 8, 16 right-hand sides sharing the links), the plain
+FP64 form of the solve, the
+multishift BiCG and QMR solvers, the direct two-sided Lanczos method (stored
+basis and two-pass), restarted FOM-LR and GMRES-LR, the restart-size sweep of
+FOM-LR on 16^4 (FP64 and mixed), the mixed batch of 32 right-hand sides over
+8^4 / 12^4 / 16^4 lattices, LR deflation on 8^4, per-kernel roofline fractions
+from a separate profiled pass, and the CPU oracle on this host's cores (1 thread
+and all threads) on bounded samples of the same work.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -31,33 +43,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32 (counts packed FMAs)
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.4, seed=0, kappa=0.2, mu=0.2, poles=16,
                 alpha=0.12, beta=2.6, tol=1e-9)
-# the accuracy the throughput is quoted at: relative error against the FP64 solve to 1e-12
 ERR_TARGET = 1e-8
 # precision schedule of the mixed BiCGStab solve: FP32 below 1e-2 ||y||, FP16 links below
-# 1e-5 ||y||, reliable update whenever the seed residual drops by 0.05; with the solver
-# tolerance 1e-9 the error against the FP64 reference is 2.2e-9 on this workload, a quarter of
-# the target (BiCGStab's iteration count moves by a few percent with rounding, so the margin
-# is kept wide)
+# 1e-5 ||y||, reliable update whenever the seed residual drops by 0.05
 MIXED = dict(theta32=1e-2, theta16=1e-5, delta=0.05)
-# the BiCG solver at the same target: tolerance 1e-8, FP32 below 1e-1, FP16 links below 1e-3
 BICG_TOL = 1e-8
 BICG_MIXED = dict(theta32=1e-1, theta16=1e-3, delta=0.05)
-# the QMR solver at the same target: FP32 stencil below a quasi-residual of 1e-3 ||y||, FP16 links
-# below 1e-6 ||y|| (error 2.4e-9 on this workload; (1e-2, 1e-5) gives 5.8e-9)
 QMR_MIXED = dict(theta32=1e-3, theta16=1e-6)
-# the direct two-sided Lanczos method (exact sign, no rational approximation): k grows until
-# sign(T_k) e_1 changes by less than 1e-10 between checks 100 steps apart
 LANCZOS = dict(k=1000, tol=1e-10, check_every=100)
-# restarted FOM-LR with the bench's rational function: 30 Arnoldi steps per cycle, shifted
-# residuals to 1e-9; mixed: FP32 below 1e-2, FP16 links below 1e-5
 FOM = dict(kmax=30, tol=1e-9)
 FOM_MIXED = dict(theta32=1e-2, theta16=1e-5)
-# LR deflation leg: 8^4 lattice (same field recipe, kappa and mu), m critical eigenpairs
-# (24 Ritz pairs kept from a 64-vector basis, the library's default for m = 4: 86 restarts against 545 with 10 / 36)
+# restart-size study of restarted FOM-LR on 16^4 (mu = 0.2, 16 poles)
+C3 = dict(dims=(16, 16, 16, 16), kmax=(20, 30, 40, 50, 60, 80), tol=1e-9)
+# 32 right-hand sides over 8^4, 12^4, 16^4 (one field per size, mu_j ~ U[0, 0.3]), 16 poles
+C4 = dict(nrhs=32, alpha=0.1, beta=2.6, tol=1e-10)
 DEFL = dict(dims=(8, 8, 8, 8), m=4, nev=24, kmax=64, eig_tol=1e-10, max_restarts=400, tol=1e-9)
+BW_DIMS = (32, 32, 32, 64)
 PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
+# algorithmic bytes per site of one H_W application: two spinors and four links of nine
+# complex entries (FP64 960, FP32 480, FP32 spinors with FP16 links 336); 1368 flop per site
+SITE_BYTES = {"f64": 960, "f32": 480, "h16": 336}
+FLOP_PER_SITE = 1368
 # PMC byte counts of the solver kernels, taken with rocprofv3 on this benchmark; valid only
 # while the kernel sources are the ones they were measured on
 PROFILE = os.path.join(ROOT, "profiles", "bench_24x24x24x48_multishift.md")
@@ -96,6 +105,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        for l in open("/proc/cpuinfo"):
+            if l.startswith("model name"):
+                return l.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,11 +122,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bicg", action="store_true",
-                    help="skip the comparison legs (multishift BiCG and QMR, direct Lanczos, restarted FOM)")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline, FP64 form and reference only (no comparison legs, no 32^3x64)")
+    ap.add_argument("--no-bicg", action="store_true", help="same as --quick")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device-to-device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
+    quick = args.quick or args.no_bicg
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the solver path is single-GPU "
                                    "(sharding over several GPUs is designed but not built)",
@@ -120,12 +141,28 @@ def main():
     import synth
     import paper_0910_1048_amd as sgn
 
-    if args.calibrate_copy:
-        a = torch.zeros(1 << 27, dtype=torch.float32, device="cuda")
-        c = torch.empty_like(a)
-        c.copy_(a)
+    def sync():
         torch.cuda.synchronize()
-        del a, c
+
+    def timed(fn, reps=1):
+        """wall time per call of fn (stream-synchronised on both sides)"""
+        sync()
+        t0 = time.perf_counter()
+        out = None
+        for _ in range(reps):
+            out = fn()
+        sync()
+        return (time.perf_counter() - t0) / reps, out
+
+    copy_tbs = None
+    a = torch.zeros(1 << 27, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    tc, _ = timed(lambda: c.copy_(a), 20)
+    copy_tbs = 2 * a.numel() * 4 / tc / 1e12
+    del a, c
+    log(f"[bench] device copy 512 MiB: {tc * 1e6:.0f} us, {copy_tbs:.2f} TB/s (read + write)")
 
     W = WORKLOAD
     dims = W["dims"]
@@ -134,231 +171,406 @@ def main():
     b = synth.gaussian_source(dims, W["seed"])
     ctx = sgn.Context(0)
     lat = sgn.Lattice(ctx, torch.from_numpy(U).cuda(), dims, W["kappa"])
-    bd = torch.from_numpy(b).cuda()
+    V = lat.V
+    bd = torch.from_numpy(b.ravel()).cuda()
     x = torch.empty_like(bd)
     rf = sgn.sgn_rational_neuberger(W["poles"], W["alpha"], W["beta"])
+    om = np.array(list(rf.omega)[:rf.s])
+    sgm = np.array(list(rf.sigma)[:rf.s])
     prob = sgn.Problem(lat, W["mu"], bd, x)
+    # launch shapes of the stencil: tuned once for this lattice (setup, not timed)
+    autotune = {}
+    for name, prec, nr in (("f64", sgn.F64, 1), ("f32", sgn.F32, 1), ("h16", sgn.F32_H16, 1),
+                           ("h16_multi16", sgn.F32_H16, 16), ("f32_multi16", sgn.F32, 16)):
+        cands = sgn.sgn_autotune(lat, prec, nr)
+        autotune[name] = [{"block_sites": c["block_sites"], "links_in_registers": c["links_in_registers"],
+                           "us": round(c["us"], 2), "chosen": c["chosen"]} for c in cands]
+        best = [c for c in cands if c["chosen"]][0]
+        log(f"[bench] autotune {name}: {len(cands)} shapes, chosen {best['block_sites']} sites/block"
+            f"{' (links in registers)' if best['links_in_registers'] else ''}, {best['us']:.1f} us")
 
-    def solve(prec, tol, p=prob):
+    def solve(prec, tol, p=prob, r=rf):
         kw = MIXED if prec != sgn.F64 else {}
-        return sgn.multishift_bicgstab(p, rf, tol=tol, prec=prec, **kw)[0]
+        return sgn.multishift_bicgstab(p, r, tol=tol, prec=prec, **kw)[0]
 
     def solve_bicg(prec, tol, p=prob):
         kw = BICG_MIXED if prec != sgn.F64 else {}
         return sgn.multishift_solve(p, rf, tol=tol, prec=prec, **kw)[0]
 
-    # FP64 reference solution (untimed) for the accuracy of every timed result
-    log("[bench] FP64 reference solve (BiCG, tol 1e-12)")
-    xref_t = torch.empty_like(bd)
-    solve_bicg(sgn.F64, 1e-12, sgn.Problem(lat, W["mu"], bd, xref_t))
-    xref = xref_t.cpu().numpy()
+    # ---- reference: FP64 multishift solve to 1e-12 with every shifted solution, anchored on the
+    #      oracle's operator (all 16 shifted residuals recomputed on the host)
+    log("[bench] FP64 reference solve (BiCG, tol 1e-12, per-shift solutions)")
+    xst = [torch.empty_like(bd) for _ in range(rf.s)]
+    sgn.multishift_solve(sgn.Problem(lat, W["mu"], bd, torch.empty_like(bd), None, xst), rf, tol=1e-12,
+                         prec=sgn.F64)
+    xs_ref = np.stack([t.cpu().numpy() for t in xst])
+    del xst
+    xref = om @ xs_ref
+    ref_info = {"solver": "multishift_solve FP64, tol 1e-12, per-shift solutions",
+                "oracle_residuals": None, "oracle_residual_max": None}
+    if not args.no_cpu_baseline:
+        from oracle import WilsonRef, rational as orat
+        Wr = WilsonRef(U, dims, W["kappa"])
+        omo, sgo, co = orat.coefficients(W["poles"], W["alpha"], W["beta"])
+        assert np.allclose(omo, om, rtol=1e-14) and np.allclose(sgo, sgm, rtol=1e-14) and abs(co - rf.c) < 1e-14
+        t0 = time.perf_counter()
+        y = co * Wr.apply(b, W["mu"]).ravel()
+        ny = np.linalg.norm(y)
+        res = []
+        for xi, q in zip(xs_ref, sgo):
+            hhx = Wr.apply(Wr.apply(xi, W["mu"]), W["mu"]).ravel()
+            res.append(float(np.linalg.norm(y - (co * co * hhx - q * xi)) / ny))
+        ref_info["oracle_residuals"] = res
+        ref_info["oracle_residual_max"] = max(res)
+        log(f"[bench] reference anchored: oracle residuals of the 16 shifted systems {min(res):.1e} .. "
+            f"{max(res):.1e} ({time.perf_counter() - t0:.1f} s on the host)")
+    del xs_ref
 
-    def err_of(t):
-        return float(np.linalg.norm(t.cpu().numpy() - xref) / np.linalg.norm(xref))
+    def err_of(t, ref=None):
+        r = xref if ref is None else ref
+        return float(np.linalg.norm(t.cpu().numpy().ravel() - r) / np.linalg.norm(r))
 
-    # ---- headline: mixed precision
+    # ---- headline: mixed precision, graphs on, no profiling
     for _ in range(args.warmup):
         solve(sgn.F32_H16, W["tol"])
-    torch.cuda.synchronize()
-    # every 7th launch of each kernel class carries an event pair (per-launch averages, small overhead)
-    sgn.sgn_profile_enable(ctx, True, every=PROFILE_EVERY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     stats = []
-    for _ in range(args.steps):
-        stats.append(solve(sgn.F32_H16, W["tol"]))
-    torch.cuda.synchronize()
-    t_mixed = time.perf_counter() - t0
-    prof = sgn.sgn_profile_read(ctx)
-    sgn.sgn_profile_enable(ctx, False)
-    err_mixed = float(np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref))
+    t_mixed, _ = timed(lambda: stats.append(solve(sgn.F32_H16, W["tol"])), args.steps)
+    t_mixed *= args.steps
+    x_mixed = x.clone()
+    err_mixed = err_of(x)
     value = args.steps / t_mixed
     log(f"[bench] mixed: {t_mixed / args.steps * 1e3:.1f} ms/solve, {stats[-1]['iterations']} iterations, "
-        f"{stats[-1]['reliable_updates']} reliable updates, err vs FP64 {err_mixed:.2e}")
+        f"{stats[-1]['reliable_updates']} reliable updates, err vs anchored reference {err_mixed:.2e}")
 
     # ---- plain FP64 single-RHS form of the same solve
     solve(sgn.F64, W["tol"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st64 = None
-    for _ in range(args.fp64_steps):
-        st64 = solve(sgn.F64, W["tol"])
-    torch.cuda.synchronize()
-    t64 = (time.perf_counter() - t0) / args.fp64_steps
-    err64 = float(np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref))
+    t64, st64 = timed(lambda: solve(sgn.F64, W["tol"]), args.fp64_steps)
+    err64 = err_of(x)
     log(f"[bench] fp64: {t64 * 1e3:.1f} ms/solve, {st64['iterations']} iterations, err {err64:.2e}")
 
-    # ---- the BiCG solver (the paper's BiCG-LR core) at the same accuracy target
-    bicg = None
-    if not args.no_bicg:
+    # ---- profiled pass (separate, untimed): per-kernel launch times from HIP events on the
+    #      launch stream (graph replay is off while profiling)
+    sgn.sgn_profile_enable(ctx, True, every=PROFILE_EVERY)
+    nprof = 2
+    tprof, _ = timed(lambda: solve(sgn.F32_H16, W["tol"]), nprof)
+    prof = sgn.sgn_profile_read(ctx)
+    sgn.sgn_profile_enable(ctx, False)
+
+    # ---- the exact sign: direct two-sided Lanczos (and the accuracy measure)
+    lanczos = None
+    x_sign = None
+    sync()
+    t0 = time.perf_counter()
+    sl = sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
+    sync()
+    tl = time.perf_counter() - t0
+    x_sign = x.cpu().numpy().ravel()
+    ssb = torch.empty_like(bd)
+    sgn.sign_lanczos_2sided(lat, W["mu"], x, ssb, **LANCZOS)
+    acc = sgn.sgn_accuracy_measure(lat, bd, ssb)
+    del ssb
+    g16_vs_sign = float(np.linalg.norm(xref - x_sign) / np.linalg.norm(x_sign))
+    lanczos = {"settings": LANCZOS, "solves_per_s": round(1.0 / tl, 4), "ms_per_solve": round(tl * 1e3, 2),
+               "k": sl["iterations"], "small_sign_ms": round(sl["small_ms"], 2), "accuracy_measure": acc,
+               "err_vs_reference": err_of(x)}
+    log(f"[bench] direct Lanczos: {tl * 1e3:.1f} ms/solve, k = {sl['iterations']}, accuracy measure {acc:.2e}, "
+        f"g_16 reference vs sign {g16_vs_sign:.2e}")
+    err_mixed_sign = float(np.linalg.norm(x_mixed.cpu().numpy().ravel() - x_sign) / np.linalg.norm(x_sign))
+    del x_mixed
+
+    # ---- the pole count of Eq. (no_of_poles) for 1e-8 on the same spectral circles
+    s_need = sgn.sgn_poles_needed(W["alpha"], W["beta"], ERR_TARGET)
+    rf_need = sgn.sgn_rational_neuberger(s_need, W["alpha"], W["beta"])
+    solve(sgn.F32_H16, W["tol"], r=rf_need)
+    tn, sn = timed(lambda: solve(sgn.F32_H16, W["tol"], r=rf_need), max(1, args.steps // 2))
+    e_need = float(np.linalg.norm(x.cpu().numpy().ravel() - x_sign) / np.linalg.norm(x_sign))
+    poles_for_target = {"poles": s_need, "solves_per_s": round(1.0 / tn, 4), "ms_per_solve": round(tn * 1e3, 2),
+                        "iterations": sn["iterations"], "err_vs_sign": e_need,
+                        "meets_err_target_vs_sign": bool(e_need <= ERR_TARGET)}
+    log(f"[bench] {s_need} poles (Eq. no_of_poles, 1e-8): {tn * 1e3:.1f} ms/solve, {sn['iterations']} iterations, "
+        f"err vs sign {e_need:.2e}")
+
+    # ---- the Wilson stencil alone: plain launches on internal-layout fields, HIP events on
+    #      torch's current stream (the launch stream)
+    def dslash_rates(L_, reps):
+        out = {}
+        nsites = L_.V
+        ne = L_.link_elements
+        for name, prec, eb, sb in (("f64", sgn.F64, 16, 192), ("f32", sgn.F32, 8, 96), ("h16", sgn.F32_H16, 4, 96)):
+            nb = L_.spinor_bytes(prec)
+            xi = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+            yi = torch.empty_like(xi)
+            canon = torch.randn(12 * nsites, dtype=torch.complex128 if prec == sgn.F64 else torch.complex64,
+                                device="cuda")
+            sgn.sgn_spinor_pack(L_, canon, xi, prec)
+            for _ in range(5):
+                sgn.wilson_apply(L_, W["mu"], xi, yi, prec, sgn.INTERNAL_LAYOUT)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                sgn.wilson_apply(L_, W["mu"], xi, yi, prec, sgn.INTERNAL_LAYOUT)
+            e1.record()
+            sync()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            alg = SITE_BYTES[name] * nsites
+            fmt = (2 * sb + 4 * ne * eb) * nsites
+            out[name] = {"us": round(us, 2), "GBs": round(alg / us / 1e3, 1),
+                         "frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4),
+                         "GBs_stored_format": round(fmt / us / 1e3, 1), "bytes_per_site": SITE_BYTES[name],
+                         "stored_bytes_per_site": 2 * sb + 4 * ne * eb,
+                         "TFLOPs": round(FLOP_PER_SITE * nsites / us / 1e6, 2)}
+            del xi, yi, canon
+        return out
+
+    dslash = {"24x24x24x48": dslash_rates(lat, 200)}
+    for k, v in dslash["24x24x24x48"].items():
+        log(f"[bench] Dslash {k} 24^3x48: {v['us']:.1f} us, {v['GBs']:.0f} GB/s ({v['frac']:.3f} of peak), "
+            f"{v['TFLOPs']:.1f} TFLOP/s")
+
+    # ---- multi-RHS stencil: N right-hand sides on one gauge field sharing the link loads; per-RHS
+    #      algorithmic bytes (2 S N + L) / N per site with S the spinor and L the nine-entry links
+    def multi_rates(L_, reps):
+        out = {}
+        for name, prec, sb, lb in (("f32", sgn.F32, 96, 288), ("h16", sgn.F32_H16, 96, 144)):
+            nb = L_.spinor_bytes(prec)
+            rows = {}
+            for N in (1, 4, 8, 16):
+                xs = [torch.zeros(nb, dtype=torch.uint8, device="cuda") for _ in range(N)]
+                ys = [torch.empty_like(t) for t in xs]
+                mus = [W["mu"]] * N
+                for _ in range(3):
+                    sgn.wilson_apply_multi(L_, mus, xs, ys, prec)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    sgn.wilson_apply_multi(L_, mus, xs, ys, prec)
+                e1.record()
+                sync()
+                us = e0.elapsed_time(e1) * 1e3 / reps
+                alg = (2 * sb * N + lb) * L_.V
+                rows[N] = {"us": round(us, 1), "us_per_rhs": round(us / N, 2),
+                           "bytes_per_site_per_rhs": round((2 * sb * N + lb) / N, 1),
+                           "GBs": round(alg / us / 1e3, 1), "frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4)}
+                del xs, ys
+            out[name] = rows
+        return out
+
+    multi_rhs = {"24x24x24x48": multi_rates(lat, 10)}
+    for k, rows in multi_rhs["24x24x24x48"].items():
+        log(f"[bench] multi-RHS {k} 24^3x48: " + ", ".join(
+            f"N={N} {r['us_per_rhs']:.1f} us/RHS {r['GBs']:.0f} GB/s" for N, r in rows.items()))
+
+    # ---- comparison legs on the headline problem
+    bicg = qmr = lanczos2 = fom = gmres = defl = c3 = c4 = None
+    if not quick:
         bicg = {"tol": BICG_TOL, "mixed_schedule": BICG_MIXED}
         for name, prec, reps in (("mixed", sgn.F32_H16, 2), ("fp64", sgn.F64, 1)):
             solve_bicg(prec, BICG_TOL)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                sb = solve_bicg(prec, BICG_TOL)
-            torch.cuda.synchronize()
-            tb = (time.perf_counter() - t0) / reps
+            tb, sb_ = timed(lambda: solve_bicg(prec, BICG_TOL), reps)
             bicg[name] = {"solves_per_s": round(1.0 / tb, 4), "ms_per_solve": round(tb * 1e3, 2),
-                          "iterations": sb["iterations"], "err_vs_fp64_ref": err_of(x)}
-            log(f"[bench] BiCG {name}: {tb * 1e3:.1f} ms/solve, {sb['iterations']} iterations, "
-                f"err {bicg[name]['err_vs_fp64_ref']:.2e}")
-
-    # ---- multishift QMR (stored Lanczos basis, per-shift least squares) at the same target
-    qmr = None
-    if not args.no_bicg:
+                          "iterations": sb_["iterations"], "err_vs_reference": err_of(x)}
+            log(f"[bench] BiCG {name}: {tb * 1e3:.1f} ms/solve, {sb_['iterations']} iterations, "
+                f"err {bicg[name]['err_vs_reference']:.2e}")
         qmr = {"tol": BICG_TOL, "mixed_schedule": QMR_MIXED}
         for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
             kw = QMR_MIXED if prec != sgn.F64 else {}
             sgn.multishift_qmr(prob, rf, tol=BICG_TOL, prec=prec, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sq = sgn.multishift_qmr(prob, rf, tol=BICG_TOL, prec=prec, **kw)[0]
-            torch.cuda.synchronize()
-            tq = time.perf_counter() - t0
+            tq, sq = timed(lambda: sgn.multishift_qmr(prob, rf, tol=BICG_TOL, prec=prec, **kw)[0])
             qmr[name] = {"solves_per_s": round(1.0 / tq, 4), "ms_per_solve": round(tq * 1e3, 2),
-                         "iterations": sq["iterations"], "err_vs_fp64_ref": err_of(x)}
+                         "iterations": sq["iterations"], "err_vs_reference": err_of(x)}
             log(f"[bench] QMR {name}: {tq * 1e3:.1f} ms/solve, {sq['iterations']} steps, "
-                f"err {qmr[name]['err_vs_fp64_ref']:.2e}")
-
-    # ---- the direct two-sided Lanczos method: its accuracy by the measure 1/2 ||S(S b) - b|| / ||b||
-    #      (its distance to the FP64 rational reference is the rational approximation's error)
-    lanczos = lanczos2 = fom = gmres = defl = None
-    if not args.no_bicg:
-        sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sl = sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, **LANCZOS)
-        torch.cuda.synchronize()
-        tl = time.perf_counter() - t0
-        x_lz = x.clone()
-        ssb = torch.empty_like(bd)
-        sgn.sign_lanczos_2sided(lat, W["mu"], x, ssb, **LANCZOS)
-        acc = sgn.sgn_accuracy_measure(lat, bd, ssb)
-        del ssb
-        lanczos = {"settings": LANCZOS, "solves_per_s": round(1.0 / tl, 4), "ms_per_solve": round(tl * 1e3, 2),
-                   "k": sl["iterations"], "small_sign_ms": round(sl["small_ms"], 2), "accuracy_measure": acc,
-                   "diff_vs_rational_ref": err_of(x)}
-        log(f"[bench] direct Lanczos: {tl * 1e3:.1f} ms/solve, k = {sl['iterations']}, small sign "
-            f"{sl['small_ms']:.1f} ms, accuracy measure {acc:.2e}")
-        # ---- restarted FOM-LR (the rational function of the headline), FP64 and mixed
+                f"err {qmr[name]['err_vs_reference']:.2e}")
         fom = {"settings": FOM, "mixed_schedule": FOM_MIXED}
-        for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
-            kw = dict(FOM, **(FOM_MIXED if prec != sgn.F64 else {}))
-            sgn.sign_arnoldi_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sf = sgn.sign_arnoldi_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
-            torch.cuda.synchronize()
-            tf = time.perf_counter() - t0
-            fom[name] = {"solves_per_s": round(1.0 / tf, 4), "ms_per_solve": round(tf * 1e3, 2),
-                         "restarts": sf["restarts"], "arnoldi_steps": sf["iterations"], "err_vs_fp64_ref": err_of(x)}
-            log(f"[bench] FOM {name}: {tf * 1e3:.1f} ms/solve, {sf['restarts']} cycles, err {fom[name]['err_vs_fp64_ref']:.2e}")
-        # ---- restarted GMRES-LR, same settings
         gmres = {"settings": FOM, "mixed_schedule": FOM_MIXED}
-        for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
-            kw = dict(FOM, **(FOM_MIXED if prec != sgn.F64 else {}))
-            sgn.sign_gmres_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sg_ = sgn.sign_gmres_rational(lat, W["mu"], bd, x, rf, prec=prec, **kw)
-            torch.cuda.synchronize()
-            tg = time.perf_counter() - t0
-            gmres[name] = {"solves_per_s": round(1.0 / tg, 4), "ms_per_solve": round(tg * 1e3, 2),
-                           "restarts": sg_["restarts"], "arnoldi_steps": sg_["iterations"],
-                           "err_vs_fp64_ref": err_of(x)}
-            log(f"[bench] GMRES {name}: {tg * 1e3:.1f} ms/solve, {sg_['restarts']} cycles, "
-                f"err {gmres[name]['err_vs_fp64_ref']:.2e}")
-        # ---- two-pass direct Lanczos: three basis vectors, the recurrence run a second time
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s2 = sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, two_pass=True, **LANCZOS)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter() - t0
-        d2 = float(torch.linalg.norm(x - x_lz) / torch.linalg.norm(x_lz))
+        for tag, f, d in (("FOM", sgn.sign_arnoldi_rational, fom), ("GMRES", sgn.sign_gmres_rational, gmres)):
+            for name, prec in (("mixed", sgn.F32_H16), ("fp64", sgn.F64)):
+                kw = dict(FOM, **(FOM_MIXED if prec != sgn.F64 else {}))
+                f(lat, W["mu"], bd, x, rf, prec=prec, **kw)
+                tf, sf = timed(lambda: f(lat, W["mu"], bd, x, rf, prec=prec, **kw))
+                d[name] = {"solves_per_s": round(1.0 / tf, 4), "ms_per_solve": round(tf * 1e3, 2),
+                           "restarts": sf["restarts"], "arnoldi_steps": sf["iterations"],
+                           "err_vs_reference": err_of(x)}
+                log(f"[bench] {tag} {name}: {tf * 1e3:.1f} ms/solve, {sf['restarts']} cycles, "
+                    f"err {d[name]['err_vs_reference']:.2e}")
+        t2, s2 = timed(lambda: sgn.sign_lanczos_2sided(lat, W["mu"], bd, x, two_pass=True, **LANCZOS))
+        d2 = float(np.linalg.norm(x.cpu().numpy().ravel() - x_sign) / np.linalg.norm(x_sign))
         lanczos2 = {"settings": dict(LANCZOS, two_pass=True), "solves_per_s": round(1.0 / t2, 4),
                     "ms_per_solve": round(t2 * 1e3, 2), "k": s2["iterations"], "matvecs": s2["matvecs"],
                     "diff_vs_stored_basis": d2}
         log(f"[bench] two-pass direct Lanczos: {t2 * 1e3:.1f} ms/solve, k = {s2['iterations']}, "
-            f"{s2['matvecs']} matvecs, vs stored basis {d2:.1e}")
-        del x_lz
+            f"vs stored basis {d2:.1e}")
+
+        # ---- restart-size study of restarted FOM-LR on 16^4, FP64 and mixed
+        d3 = C3["dims"]
+        U3 = synth.gauge_field(d3, W["eps"], W["seed"])
+        lat3 = sgn.Lattice(ctx, torch.from_numpy(U3).cuda(), d3, W["kappa"])
+        b3 = torch.from_numpy(synth.gaussian_source(d3, W["seed"]).ravel()).cuda()
+        x3 = torch.empty_like(b3)
+        x3ref = torch.empty_like(b3)
+        sgn.multishift_solve(sgn.Problem(lat3, W["mu"], b3, x3ref), rf, tol=1e-12)
+        c3 = {"lattice": list(d3), "mu": W["mu"], "poles": W["poles"], "tol": C3["tol"], "sweep": []}
+        for km in C3["kmax"]:
+            row = {"kmax": km}
+            for name, prec in (("fp64", sgn.F64), ("mixed", sgn.F32_H16)):
+                kw = dict(kmax=km, tol=C3["tol"], **(FOM_MIXED if prec != sgn.F64 else {}))
+                sgn.sign_arnoldi_rational(lat3, W["mu"], b3, x3, rf, prec=prec, **kw)
+                tf, sf = timed(lambda: sgn.sign_arnoldi_rational(lat3, W["mu"], b3, x3, rf, prec=prec, **kw), 2)
+                row[name] = {"solves_per_s": round(1.0 / tf, 3), "ms_per_solve": round(tf * 1e3, 3),
+                             "restarts": sf["restarts"], "matvecs": sf["matvecs"],
+                             "err_vs_fp64_ref": float(torch.linalg.norm(x3 - x3ref) / torch.linalg.norm(x3ref))}
+            c3["sweep"].append(row)
+            log(f"[bench] C3 16^4 FOM k_max={km}: fp64 {row['fp64']['ms_per_solve']:.1f} ms "
+                f"({row['fp64']['restarts']} cycles), mixed {row['mixed']['ms_per_solve']:.1f} ms, "
+                f"err {row['mixed']['err_vs_fp64_ref']:.1e}")
+        lat3.close()
+        del U3
+
+        # ---- the mixed batch of 32 right-hand sides over 8^4, 12^4, 16^4
+        fields, plist = synth.mixed_batch_recipe(C4["nrhs"])
+        lats4 = [sgn.Lattice(ctx, torch.from_numpy(Uf).cuda(), df, W["kappa"]) for df, Uf in fields]
+        rf4 = sgn.sgn_rational_neuberger(16, C4["alpha"], C4["beta"])
+        pb4, refs4 = [], []
+        for fi, mu, bj in plist:
+            bj = torch.from_numpy(bj.ravel()).cuda()
+            pb4.append(sgn.Problem(lats4[fi], mu, bj, torch.empty_like(bj)))
+            refs4.append(torch.empty_like(bj))
+        sgn.multishift_solve([sgn.Problem(p.lat, p.mu, p.b, r) for p, r in zip(pb4, refs4)], rf4, tol=1e-12)
+
+        def c4_err():
+            return max(float(torch.linalg.norm(p.x - r) / torch.linalg.norm(r)) for p, r in zip(pb4, refs4))
+
+        c4 = {"problems": len(pb4), "lattices": [list(df) for df, _ in fields], "tol": C4["tol"]}
+        kw4 = dict(tol=C4["tol"], prec=sgn.F32_H16, **BICG_MIXED)
+        for name, run in (
+                ("bicg_mixed_one_call", lambda: sgn.multishift_solve(pb4, rf4, **kw4)),
+                ("bicg_mixed_one_at_a_time", lambda: [sgn.multishift_solve(p, rf4, **kw4) for p in pb4]),
+                ("bicgstab_mixed_one_call", lambda: sgn.multishift_bicgstab(pb4, rf4, tol=C4["tol"],
+                                                                             prec=sgn.F32_H16, **MIXED)),
+                ("bicg_fp64_one_call", lambda: sgn.multishift_solve(pb4, rf4, tol=C4["tol"]))):
+            run()
+            tb4, _ = timed(run)
+            c4[name] = {"solves_per_s": round(len(pb4) / tb4, 2), "ms_per_batch": round(tb4 * 1e3, 2),
+                        "max_err_vs_fp64_ref": c4_err()}
+            log(f"[bench] C4 {name}: {len(pb4) / tb4:.1f} solves/s, max err {c4[name]['max_err_vs_fp64_ref']:.1e}")
+        for l4 in lats4:
+            l4.close()
+        del pb4, refs4
+
         # ---- LR deflation on 8^4: critical eigenpairs, then the deflated mixed BiCGStab solve
         d8 = DEFL["dims"]
         U8 = synth.gauge_field(d8, W["eps"], W["seed"])
         lat8 = sgn.Lattice(ctx, torch.from_numpy(U8).cuda(), d8, W["kappa"])
-        b8 = torch.from_numpy(synth.gaussian_source(d8, W["seed"])).cuda()
+        b8 = torch.from_numpy(synth.gaussian_source(d8, W["seed"]).ravel()).cuda()
         x8, x8ref = torch.empty_like(b8), torch.empty_like(b8)
         sgn.multishift_solve(sgn.Problem(lat8, W["mu"], b8, x8ref), rf, tol=1e-12, prec=sgn.F64)
         m = DEFL["m"]
         L8 = torch.empty((m, b8.numel()), dtype=torch.complex128, device="cuda")
         R8 = torch.empty_like(L8)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lam8, alpha8, se = sgn.sgn_critical_eigenpairs(lat8, W["mu"], m, L8, R8, nev=DEFL["nev"], kmax=DEFL["kmax"],
-                                                        tol=DEFL["eig_tol"], max_restarts=DEFL["max_restarts"])
-        torch.cuda.synchronize()
-        te = time.perf_counter() - t0
+        te, (lam8, alpha8, se) = timed(lambda: sgn.sgn_critical_eigenpairs(
+            lat8, W["mu"], m, L8, R8, nev=DEFL["nev"], kmax=DEFL["kmax"], tol=DEFL["eig_tol"],
+            max_restarts=DEFL["max_restarts"]))
         dfl = sgn.Deflation(L8, R8, np.array(lam8))
         legs = {}
         for name, d in (("undeflated", None), ("deflated", dfl)):
             p8 = sgn.Problem(lat8, W["mu"], b8, x8, d)
             sgn.multishift_bicgstab(p8, rf, tol=DEFL["tol"], prec=sgn.F32_H16, **MIXED)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s8 = sgn.multishift_bicgstab(p8, rf, tol=DEFL["tol"], prec=sgn.F32_H16, **MIXED)[0]
-            torch.cuda.synchronize()
-            t8 = time.perf_counter() - t0
+            t8, s8 = timed(lambda: sgn.multishift_bicgstab(p8, rf, tol=DEFL["tol"], prec=sgn.F32_H16, **MIXED)[0])
             legs[name] = {"ms_per_solve": round(t8 * 1e3, 3), "iterations": s8["iterations"],
                           "err_vs_fp64_ref": float(torch.linalg.norm(x8 - x8ref) / torch.linalg.norm(x8ref))}
-        defl = {"lattice": list(d8), "m": m, "nev": DEFL["nev"], "kmax": DEFL["kmax"], "eigenpairs_ms": round(te * 1e3, 1), "eig_restarts": se["restarts"],
-                "eig_residual": se["residual"], "lambda_abs": [round(abs(complex(v)), 5) for v in lam8],
-                "deflation_gap": alpha8, "solves": legs}
-        log(f"[bench] deflation 8^4: {m} eigenpairs in {te * 1e3:.0f} ms ({se['restarts']} restarts), gap "
-            f"{alpha8:.4f}; mixed BiCGStab undeflated {legs['undeflated']['ms_per_solve']:.1f} ms "
-            f"({legs['undeflated']['iterations']} it), deflated {legs['deflated']['ms_per_solve']:.1f} ms "
-            f"({legs['deflated']['iterations']} it, err {legs['deflated']['err_vs_fp64_ref']:.1e})")
+        defl = {"lattice": list(d8), "m": m, "nev": DEFL["nev"], "kmax": DEFL["kmax"],
+                "eigenpairs_ms": round(te * 1e3, 1), "eig_restarts": se["restarts"], "eig_residual": se["residual"],
+                "lambda_abs": [round(abs(complex(v)), 5) for v in lam8], "deflation_gap": alpha8, "solves": legs}
+        log(f"[bench] deflation 8^4: {m} eigenpairs in {te * 1e3:.0f} ms ({se['restarts']} restarts); mixed "
+            f"BiCGStab undeflated {legs['undeflated']['ms_per_solve']:.1f} ms, deflated "
+            f"{legs['deflated']['ms_per_solve']:.1f} ms (err {legs['deflated']['err_vs_fp64_ref']:.1e})")
         lat8.close()
         del U8, L8, R8, dfl
 
-    # ---- roofline: dominant kernel by time, and the stencil (Dslash) itself
+        # ---- the stencil on 32^3 x 64 (2.1 M sites, beyond the 256 MB Infinity Cache in every precision)
+        Ub = synth.gauge_field(BW_DIMS, W["eps"], W["seed"])
+        latb = sgn.Lattice(ctx, torch.from_numpy(Ub).cuda(), BW_DIMS, W["kappa"])
+        del Ub
+        dslash["32x32x32x64"] = dslash_rates(latb, 50)
+        for k, v in dslash["32x32x32x64"].items():
+            log(f"[bench] Dslash {k} 32^3x64: {v['us']:.1f} us, {v['GBs']:.0f} GB/s ({v['frac']:.3f} of peak)")
+        latb.close()
+
+    # ---- roofline of the dominant kernel class and of the whole solve, from the profiled pass
     traffic = measured_traffic()
 
     def roof(name):
         p = prof[name]
-        ach = p["bytes"] / (p["total_ms"] * 1e-3) / 1e9 if p["total_ms"] > 0 else 0.0
+        nl = max(p["launches"], 1)
+        avg_s = p["total_ms"] * 1e-3 / nl
+        ach = p["bytes"] / nl / avg_s / 1e9 if avg_s > 0 else 0.0
+        ach_st = p["bytes_stored"] / nl / avg_s / 1e9 if avg_s > 0 else 0.0
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic.get(name), "kernel": name,
-                "launches": p["calls"], "launches_timed": p["launches"],
-                "avg_launch_us": round(p["total_ms"] * 1e3 / max(p["launches"], 1), 2),
-                "bytes_per_launch": p["bytes"] / max(p["launches"], 1)}
-    dominant = max(prof, key=lambda k: prof[k]["total_ms"] * prof[k]["calls"] / max(prof[k]["launches"], 1))
+                "achieved_stored_format": round(ach_st, 1),
+                "frac_stored_format": round(ach_st / HBM_PEAK_GBS, 4),
+                "launches": p["calls"], "launches_timed": p["launches"], "avg_launch_us": round(avg_s * 1e6, 2),
+                "bytes_per_launch": p["bytes"] / nl, "stored_bytes_per_launch": p["bytes_stored"] / nl,
+                "tflops": round(p["flops"] / nl / avg_s / 1e12, 2) if avg_s > 0 else 0.0}
+    active = [k for k in prof if prof[k]["launches"]]
+    dominant = max(active, key=lambda k: prof[k]["total_ms"] * prof[k]["calls"] / prof[k]["launches"])
     roofline = roof(dominant)
-    stencils = {k: roof(k) for k in ("stencil_f64", "stencil_f32", "stencil_h16") if prof[k]["launches"]}
-    # sampled launch times scaled to all launches of the class
-    time_share = {k: round(v["total_ms"] * v["calls"] / v["launches"] / (t_mixed * 1e3), 4)
-                  for k, v in prof.items() if v["launches"]}
+    kernel_roofline = {k: roof(k) for k in active}
+    # whole solve: algorithmic bytes of every classed launch (sampled averages x all launches) at
+    # the HBM peak, against the profiled pass's wall time per solve
+    solve_bytes = sum(prof[k]["bytes"] / prof[k]["launches"] * prof[k]["calls"] for k in active) / nprof
+    t_roof = solve_bytes / (HBM_PEAK_GBS * 1e9)
+    solve_roofline = {"bytes_per_solve": solve_bytes, "t_roof_ms": round(t_roof * 1e3, 2),
+                      "ms_per_solve_profiled": round(tprof * 1e3, 2), "frac": round(t_roof / tprof, 4),
+                      "frac_of_timed": round(t_roof / (t_mixed / args.steps), 4),
+                      "note": "algorithmic bytes of the stencil, vector-update and lift launches; the scalar "
+                              "one-block kernels and the reliable updates' vector work are not counted"}
+    time_share = {k: round(prof[k]["total_ms"] * prof[k]["calls"] / prof[k]["launches"] / (tprof * nprof * 1e3), 4)
+                  for k in active}
 
-    # ---- CPU oracle on this host, bounded sample of the same solve
+    # ---- CPU oracle on this host: the stencil at 1 thread and all threads, and bounded samples of
+    #      the headline solve and the direct Lanczos method (all threads), extrapolated
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import WilsonRef, krylov, rational, wilson
-        Wr = WilsonRef(U, dims, W["kappa"])
-        om, sg, c = rational.coefficients(W["poles"], W["alpha"], W["beta"])
-        A = lambda v: Wr.apply(v, W["mu"])
+        from oracle import krylov, wilson
+        nthreads = wilson.get_threads()
         bf = b.ravel()
+        A = lambda v: Wr.apply(v, W["mu"])
+        Ah = lambda v: Wr.apply_adj(v, W["mu"])
+        td_all, _ = timed(lambda: Wr.apply(bf, W["mu"]), 3)
+        wilson.set_threads(1)
+        td_1, _ = timed(lambda: Wr.apply(bf, W["mu"]), 1)
+        wilson.set_threads(nthreads)
         ts = []
         for it in (1, 3):
             t0 = time.perf_counter()
-            krylov.multishift_bicgstab(A, bf, om, sg, c, tol=1e-30, maxiter=it)
+            krylov.multishift_bicgstab(A, bf, omo, sgo, co, tol=1e-30, maxiter=it)
             ts.append(time.perf_counter() - t0)
         per_it = (ts[1] - ts[0]) / 2
         est = ts[0] + (st64["iterations"] - 1) * per_it
-        cpu = {"value": round(1.0 / est, 6), "unit": "solves/s", "cores": wilson.get_threads(), "kind": "oracle",
-               "sample": f"oracle multishift BiCGStab (FP64, 16 poles) on the same 24^3x48 problem, run for 1 and "
-                         f"3 iterations ({ts[0]:.1f} s, {ts[1]:.1f} s); per-iteration cost extrapolated to the "
-                         f"{st64['iterations']} iterations of the FP64 GPU solve"}
-        log(f"[bench] cpu oracle: {per_it:.2f} s/iteration -> {est:.0f} s/solve")
+        tl2 = []
+        for k in (4, 8):
+            t0 = time.perf_counter()
+            krylov.lanczos_sign(A, Ah, bf, k)
+            tl2.append(time.perf_counter() - t0)
+        per_step = (tl2[1] - tl2[0]) / 4
+        est_l = tl2[0] + (sl["iterations"] - 4) * per_step
+        cpu = {"value": round(1.0 / est, 6), "unit": "solves/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"oracle multishift BiCGStab (FP64, 16 poles) on the same 24^3x48 problem run for 1 and 3 "
+                         f"iterations ({ts[0]:.1f} s, {ts[1]:.1f} s) with {nthreads} threads; the per-iteration "
+                         f"cost extrapolated to the {st64['iterations']} iterations of the FP64 GPU solve",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+               "dslash_s_1_thread": round(td_1, 3), "dslash_s_all_threads": round(td_all, 3),
+               "dslash_ns_per_site_1_thread": round(td_1 / V * 1e9, 1),
+               "dslash_ns_per_site_all_threads": round(td_all / V * 1e9, 2),
+               "per_algorithm_all_threads": {
+                   "multishift_bicgstab_fp64": {"s_per_solve": round(est, 1), "s_per_iteration": round(per_it, 3)},
+                   "direct_lanczos": {"s_per_solve": round(est_l, 1), "s_per_step": round(per_step, 3),
+                                      "k": sl["iterations"],
+                                      "sample": "steps 4 and 8 timed (small sign negligible there); the "
+                                                "k = {} small sign is not included".format(sl["iterations"])}}}
+        log(f"[bench] cpu oracle: Dslash {td_1:.2f} s (1 thread) / {td_all:.3f} s ({nthreads} threads); "
+            f"BiCGStab {per_it:.2f} s/iteration -> {est:.0f} s/solve; Lanczos {per_step:.2f} s/step")
 
     out = {
         "metric": "Dslash HBM GB/s (%peak); sign(H_W)b solves/s at 1e-8 rel err, mixed vs FP64",
@@ -371,31 +583,45 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64/f32/f16-links (mixed schedule)",
         "data": "synthetic",
         "config": {"workload": "sign(H_W)b, 24^3x48, 16-pole Neuberger rational via multishift BiCGStab "
                                "(stored basis), mixed FP64->FP32->FP16-link schedule with FP64 reliable updates",
-                   "solver": "multishift_bicgstab",
+                   "solver": "multishift_bicgstab", "graph_replay": True,
                    "lattice": list(dims), "kappa": W["kappa"], "mu": W["mu"], "link_eps": W["eps"],
                    "poles": W["poles"], "alpha": W["alpha"], "beta": W["beta"], "tol": W["tol"],
                    "mixed_schedule": MIXED, "deflation_m": 0, "rhs": 1},
-        "err_vs_fp64_ref": err_mixed,
-        "err_target": ERR_TARGET,
-        "meets_err_target": bool(err_mixed <= ERR_TARGET and err64 <= ERR_TARGET),
+        "accuracy": {
+            "err_vs_g16_reference": err_mixed,
+            "err_vs_sign": err_mixed_sign,
+            "g16_reference_vs_sign": g16_vs_sign,
+            "target": ERR_TARGET,
+            "meets_err_target_vs_g16": bool(err_mixed <= ERR_TARGET and err64 <= ERR_TARGET),
+            "meets_err_target_vs_sign": bool(err_mixed_sign <= ERR_TARGET),
+            "reference": ref_info,
+            "sign_reference": "direct two-sided Lanczos, accuracy measure {:.1e}".format(acc)},
         "iterations": stats[-1]["iterations"],
         "reliable_updates": stats[-1]["reliable_updates"],
         "fp64_solves_per_s": round(1.0 / t64, 4),
-        "fp64_err_vs_ref": err64,
+        "fp64_err_vs_reference": err64,
         "speedup_vs_fp64": round(value * t64, 3),
+        "poles_for_target": poles_for_target,
+        "dslash": dslash,
+        "multi_rhs_dslash": multi_rhs,
+        "autotune": autotune,
+        "device_copy_TBs": round(copy_tbs, 3),
         "bicg": bicg,
         "qmr": qmr,
         "direct_lanczos": lanczos,
         "direct_lanczos_two_pass": lanczos2,
         "fom": fom,
         "gmres": gmres,
+        "c3_fom_restart_sweep": c3,
+        "c4_batch": c4,
         "deflation": defl,
         "roofline": roofline,
-        "stencil_roofline": stencils,
+        "kernel_roofline": kernel_roofline,
+        "solve_roofline": solve_roofline,
         "kernel_time_share": time_share,
         "cpu_baseline": cpu,
     }

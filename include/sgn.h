@@ -74,8 +74,9 @@ typedef struct {
 #define SGN_INTERNAL_LAYOUT 2u  /* in/out are in the library's field layout (sgn_spinor_pack) */
 
 /* ------------------------------------------------------------------ context */
-/* Create a context on HIP device `device`.  Owns workspaces and the per-shape
- * launch-configuration cache.  Not thread-safe: use one context per thread. */
+/* Create a context on HIP device `device`.  Owns the solver workspaces (device
+ * buffers grown on demand and kept between calls).  Not thread-safe: use one
+ * context per thread. */
 sgn_status sgn_init(sgn_handle *h, int device);
 sgn_status sgn_finalize(sgn_handle h);
 const char *sgn_status_string(sgn_status s);
@@ -117,11 +118,43 @@ sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *in, void *ou
 
 /* out[i] = H_W(mu[i]) in[i] for i < nrhs on one gauge field (flags: SGN_NO_GAMMA5
  * as above; SGN_INTERNAL_LAYOUT is required).  Right-hand sides are processed in
- * groups that share every link load (multi-RHS stencil), so a group costs less
- * HBM traffic than separate calls.  mu (host) holds nrhs values; in/out (host
- * arrays of device pointers) must not alias each other. */
+ * groups of up to 16 (multi-RHS stencil): a block of sites applies the operator to
+ * every right-hand side of its group in turn, staging each one's spinors in LDS,
+ * and loads the sites' links once for the group (with FP16 links they are held
+ * in registers in their two-row form; set SGN_MULTI_LINK_REGS=0 in the
+ * environment to read them again for each right-hand side), so a group moves
+ * (2 S N + L) bytes per site for N spinors of S bytes and links of L bytes
+ * instead of N (2 S + L).  Each right-hand side's result is bitwise that of its
+ * own wilson_apply.  mu (host) holds nrhs values; in/out (host arrays of device
+ * pointers) must not alias each other.  The group's parameters live in device
+ * memory owned by the lattice; a call with other fields or mu than the previous
+ * one waits for the device to finish the earlier launches before replacing them. */
 sgn_status wilson_apply_multi(sgn_lattice lat, int nrhs, const double *mu, const void *const *in,
                               void *const *out, sgn_prec p, unsigned flags, void *stream);
+
+/* ------------------------------------------------------------------ launch-shape tuning */
+/* One candidate launch shape of the stencil and its measured time. */
+typedef struct {
+    int block_sites;          /* lattice sites per block (0: the unstaged kernel) */
+    int links_in_registers;   /* multi-RHS form: links held in registers (1) or read per right-hand side (0) */
+    double us;                /* one application (all nrhs right-hand sides), microseconds */
+    int chosen;               /* 1 for the fastest candidate, now used by the context */
+} sgn_tune_candidate;
+
+/* Autotune the stencil's launch shape for lattices of lat's dimensions, precision p
+ * and nrhs right-hand sides per launch (1: the single form, 2..16: the multi-RHS
+ * form, whose choice serves every group size): every candidate -- the distinct
+ * block sizes (whole x-rows or x-y planes within the LDS budget, under site caps
+ * of 576, 432, 384, 288, 192 and 96), and with FP16 two-row links and nrhs > 1 both
+ * link modes -- is applied reps times (0: 20) to zero fields on `stream` and timed
+ * with HIP events; the fastest is kept in the context and used by every later
+ * launch of that shape class on lattices of these dimensions (the solvers, the
+ * batched form, wilson_apply and wilson_apply_multi).  Until then a default shape
+ * is used.  out (host, may be NULL if max_out = 0) receives up to max_out
+ * candidates in the order tried, *n_out (may be NULL) their count.  Allocates
+ * 2 * nrhs fields for the duration of the call and synchronises the device. */
+sgn_status sgn_autotune(sgn_lattice lat, sgn_prec p, int nrhs, int reps, sgn_tune_candidate *out, int max_out,
+                        int *n_out, void *stream);
 
 /* ------------------------------------------------------------------ deflation and statistics */
 /* LR deflation set (section "Deflation", oblique projector P = R L^H):
@@ -130,7 +163,12 @@ sgn_status wilson_apply_multi(sgn_lattice lat, int nrhs, const double *mu, const
  * (device) hold m canonical complex128 vectors back to back (vector i at
  * offset i*n); lambda (host) holds m complex128 values.  m = 0 or a NULL
  * pointer to the struct means no deflation.  The caller owns all arrays.
- * Used for x_P = R sign(Lambda) L^H b (Eq. exact_proj) and r = (I - P) b. */
+ * Used for x_P = R sign(Lambda) L^H b (Eq. exact_proj) and r = (I - P) b.
+ * Every solver first checks the set: L^H R = I is probed with a fixed vector v
+ * of unit-modulus entries, and an entry of L^H R v - v larger than
+ * 1e-8 ||l_i|| ||R v|| is SGN_ERR_INVALID ("L^H R differs from the identity");
+ * an eigenvalue with |Re lambda| <= 1e-12 max|lambda| is SGN_ERR_IMAG_AXIS.
+ * The check costs about 3m + 3 vector passes and one stream synchronisation. */
 typedef struct {
     int m;
     const void *L;
@@ -328,7 +366,8 @@ typedef struct {
     double delta;       /* reliable update when the seed residual drops by this factor (default 0.1) */
     int poll;           /* iterations between host checks of the device flags (0: automatic) */
     int verify;         /* nonzero: recompute every shifted residual in FP64 at the end (stats) and, in
-                           multishift_solve, refine each system still above tol (see there) */
+                           multishift_solve and multishift_bicgstab, refine each system still above
+                           tol (see there) */
     int basis_slots;    /* Krylov-basis storage of the non-seed shifts (see multishift_solve):
                            0: automatic (up to half of the device memory free at the start),
                            > 0: at most this many stored residual vectors, < 0: never */
@@ -383,8 +422,15 @@ sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational
  * synchronisations per iteration).
  * Slots first written in the FP32 phase hold FP32 vectors.  o->basis_slots > 0 caps the
  * stored bytes at that many FP64 vectors (an FP32 slot counts half; SGN_ERR_NOMEM beyond
- * it; 0: up to half of the free memory).  o->verify is ignored.  stats: iterations, matvecs,
- * reliable_updates, shift_residual (collinear estimates), residual.  Problems run
+ * it; 0: up to half of the free memory).  Only the seed is reliable-updated: in the mixed
+ * schedule the other shifted solutions can stay above tol (measured up to 6e-8 relative at
+ * 24^3 x 48 with tol 1e-9) although their combination meets it.  With o->verify (stored-basis
+ * form) every x_i is lifted explicitly, its residual y - (c^2 H^2 - sigma_i) x_i recomputed in
+ * FP64, each system above tol refined by single-shift FP64 BiCGStab to tol/2 as in
+ * multishift_solve, and x = x_P + sum_i omega_i x_i formed from the checked x_i (one lift and
+ * two FP64 stencil applications per shift; SGN_ERR_NOT_CONVERGED if a system stays above tol).
+ * stats: iterations, matvecs, reliable_updates, refine_iterations, shift_residual (collinear
+ * estimates, or with verify the FP64 residuals), residual.  Problems run
  * one after another.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter
  * (x holds the last iterate), SGN_ERR_BREAKDOWN if r^^H r or r^^H v vanishes. */
 sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
@@ -431,8 +477,9 @@ sgn_status sgn_accuracy_measure(sgn_lattice lat, const void *b, const void *ssb,
 /* ------------------------------------------------------------------ profiling */
 /* Per-kernel-class timing of the library's own launches, measured with HIP
  * events recorded on the launch stream around each launch, together with the
- * algorithmic HBM bytes (every input read once, every output written once)
- * and flops of each launch.  Meant for roofline reporting; adds one event
+ * algorithmic HBM bytes (every input read once, every output written once;
+ * a link counts as its nine complex entries even where only two rows are
+ * stored) and flops of each launch, and the bytes of the stored format.  Meant for roofline reporting; adds one event
  * pair per profiled launch. */
 typedef enum {
     SGN_K_STENCIL_F64 = 0,
@@ -453,6 +500,7 @@ typedef struct {
     double bytes;
     double flops;
     long long calls;      /* all launches of the class while profiling was on */
+    double bytes_stored;  /* bytes of the recorded launches in the stored format (two-row links) */
 } sgn_kernel_profile;
 
 /* enable != 0 starts (and resets) profiling on this context; 0 stops it.

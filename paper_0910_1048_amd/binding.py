@@ -79,10 +79,45 @@ def check(status, where):
         raise SgnError(status, where, lib.sgn_last_error().decode())
 
 
-def _ptr(t):
-    if t is None:
-        return None
+def _invalid(where, detail):
+    return SgnError(1, where, detail)
+
+
+def _tensor(t, where, dtype=None, numel=None, nbytes=None, device=None):
+    """Device pointer of t after checking what the C side relies on: a contiguous GPU tensor of
+    the expected dtype and size (on the context's device).  Raises SgnError(SGN_ERR_INVALID)
+    before anything reaches the library."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise _invalid(where, f"expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise _invalid(where, "tensor is not in GPU memory")
+    if device is not None and t.device.index != device:
+        raise _invalid(where, f"tensor on device {t.device.index}, the context is on device {device}")
+    if dtype is not None and t.dtype != dtype:
+        raise _invalid(where, f"dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise _invalid(where, "tensor is not contiguous")
+    if numel is not None and t.numel() != numel:
+        raise _invalid(where, f"{t.numel()} elements, expected {numel}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise _invalid(where, f"{t.numel() * t.element_size()} bytes, at least {nbytes} needed")
     return C.c_void_p(t.data_ptr())
+
+
+def _c128():
+    import torch
+    return torch.complex128
+
+
+def _canon_dtype(prec):
+    import torch
+    return torch.complex128 if int(prec) == F64 else torch.complex64
+
+
+def _vec(lat, t, where):
+    """canonical complex128 vector of the lattice (12 V entries)"""
+    return _tensor(t, where, _c128(), 12 * lat.V, device=lat.ctx.device)
 
 
 def _stream(stream):
@@ -124,8 +159,12 @@ class Lattice:
             d.dims[i] = int(dims[i])
             d.bc[i] = int(bc[i])
         d.kappa = float(kappa)
+        vol = 1
+        for x in dims:
+            vol *= int(x)
+        pl = _tensor(links, "sgn_lattice_create: links", _c128(), 36 * vol, device=ctx.device)
         h = _vp()
-        check(lib.sgn_lattice_create(ctx.h, C.byref(d), _ptr(links), C.c_uint(prec_mask), _stream(stream),
+        check(lib.sgn_lattice_create(ctx.h, C.byref(d), pl, C.c_uint(prec_mask), _stream(stream),
                                      C.byref(h)), "sgn_lattice_create")
         self.h = h
         self.ctx = ctx
@@ -149,23 +188,45 @@ class Lattice:
             pass
 
 
+def _canon(lat, t, prec, where):
+    return _tensor(t, where, _canon_dtype(prec), 12 * lat.V, device=lat.ctx.device)
+
+
+def _internal(lat, t, prec, where):
+    return _tensor(t, where, None, nbytes=lat.spinor_bytes(prec), device=lat.ctx.device)
+
+
+def _field(lat, t, prec, flags, where):
+    """a spinor argument of wilson_apply: canonical (complex128 / complex64 by precision) or the
+    library's internal layout (SGN_INTERNAL_LAYOUT: any dtype, spinor_bytes(prec) bytes)"""
+    if int(flags) & INTERNAL_LAYOUT:
+        return _internal(lat, t, prec, where)
+    return _canon(lat, t, prec, where)
+
+
 def sgn_spinor_pack(lat, canon, internal, prec, stream=None):
-    check(lib.sgn_spinor_pack(lat.h, _ptr(canon), _ptr(internal), int(prec), _stream(stream)), "sgn_spinor_pack")
+    pc = _canon(lat, canon, prec, "sgn_spinor_pack: canon")
+    pi = _internal(lat, internal, prec, "sgn_spinor_pack: internal")
+    check(lib.sgn_spinor_pack(lat.h, pc, pi, int(prec), _stream(stream)), "sgn_spinor_pack")
 
 
 def sgn_spinor_unpack(lat, internal, canon, prec, stream=None):
-    check(lib.sgn_spinor_unpack(lat.h, _ptr(internal), _ptr(canon), int(prec), _stream(stream)),
-          "sgn_spinor_unpack")
+    pi = _internal(lat, internal, prec, "sgn_spinor_unpack: internal")
+    pc = _canon(lat, canon, prec, "sgn_spinor_unpack: canon")
+    check(lib.sgn_spinor_unpack(lat.h, pi, pc, int(prec), _stream(stream)), "sgn_spinor_unpack")
 
 
 def wilson_apply(lat, mu, x, out, prec=F64, flags=0, stream=None):
-    check(lib.wilson_apply(lat.h, float(mu), _ptr(x), _ptr(out), int(prec), C.c_uint(flags), _stream(stream)),
-          "wilson_apply")
+    px = _field(lat, x, prec, flags, "wilson_apply: in")
+    po = _field(lat, out, prec, flags, "wilson_apply: out")
+    check(lib.wilson_apply(lat.h, float(mu), px, po, int(prec), C.c_uint(flags), _stream(stream)), "wilson_apply")
 
 
 def wilson_apply_dag(lat, mu, x, out, prec=F64, flags=0, stream=None):
-    check(lib.wilson_apply_dag(lat.h, float(mu), _ptr(x), _ptr(out), int(prec), C.c_uint(flags),
-                               _stream(stream)), "wilson_apply_dag")
+    px = _field(lat, x, prec, flags, "wilson_apply_dag: in")
+    po = _field(lat, out, prec, flags, "wilson_apply_dag: out")
+    check(lib.wilson_apply_dag(lat.h, float(mu), px, po, int(prec), C.c_uint(flags), _stream(stream)),
+          "wilson_apply_dag")
 
 
 # ----------------------------------------------------------------------------- solvers
@@ -203,12 +264,24 @@ class Deflation:
         self.L, self.R = L, R
         self._lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128)).view(np.float64)
         self.m = int(np.asarray(lam).size)
-        self.struct = _Deflation(self.m, C.c_void_p(L.data_ptr()), C.c_void_p(R.data_ptr()),
-                                 self._lam.ctypes.data_as(C.POINTER(C.c_double)))
+        pl = _tensor(L, "Deflation: L", _c128())
+        pr = _tensor(R, "Deflation: R", _c128())
+        if L.numel() != R.numel() or (self.m and L.numel() % self.m):
+            raise _invalid("Deflation", f"L and R need m = {self.m} vectors each ({L.numel()}, {R.numel()} entries)")
+        self.struct = _Deflation(self.m, pl, pr, self._lam.ctypes.data_as(C.POINTER(C.c_double)))
+
+    def check_for(self, lat, where):
+        """the set fits the lattice: m vectors of 12 V entries each, on the context's device"""
+        _tensor(self.L, where + ": deflation L", _c128(), self.m * 12 * lat.V, device=lat.ctx.device)
+        _tensor(self.R, where + ": deflation R", _c128(), self.m * 12 * lat.V, device=lat.ctx.device)
 
 
-def _defl_ptr(defl):
-    return None if defl is None else C.byref(defl.struct)
+def _defl_ptr(defl, lat=None, where=""):
+    if defl is None:
+        return None
+    if lat is not None:
+        defl.check_for(lat, where)
+    return C.byref(defl.struct)
 
 
 lib.sign_lanczos_2sided.argtypes = [_vp, C.c_double, _vp, _vp, _vp, C.POINTER(LanczosOpts),
@@ -220,8 +293,10 @@ def sign_lanczos_2sided(lat, mu, b, x, defl=None, k=200, prec=F64, tol=0.0, chec
     """x = sign(H_W(mu)) b by the direct two-sided Lanczos-LR method; returns the stats dict."""
     o = LanczosOpts(int(k), int(prec), float(tol), int(check_every), int(bool(two_pass)))
     st = Stats()
-    check(lib.sign_lanczos_2sided(lat.h, float(mu), _ptr(b), _ptr(x), _defl_ptr(defl), C.byref(o), C.byref(st),
-                                  _stream(stream)), "sign_lanczos_2sided")
+    w = "sign_lanczos_2sided"
+    pb, px = _vec(lat, b, w + ": b"), _vec(lat, x, w + ": x")
+    check(lib.sign_lanczos_2sided(lat.h, float(mu), pb, px, _defl_ptr(defl, lat, w), C.byref(o), C.byref(st),
+                                  _stream(stream)), w)
     return st.as_dict()
 
 
@@ -306,25 +381,38 @@ class Problem:
         self.lat, self.mu, self.b, self.x, self.defl, self.x_shift = lat, mu, b, x, defl, x_shift
 
 
-def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
-                     delta=0.0, poll=0, verify=False, basis_slots=0, graph=True, stream=None):
-    """Multishift BiCG-LR for every problem; returns one stats dict per problem."""
+def _problem_array(problems, rational, where):
+    """(problem list, ctypes sgn_problem array, objects that must outlive the call), every tensor
+    checked against its lattice and every x_shift list against the pole count"""
     if isinstance(problems, Problem):
         problems = [problems]
     n = len(problems)
-    arr = (_Problem * n)()
+    arr = (_Problem * max(n, 1))()
     keep = []
     for i, p in enumerate(problems):
+        w = f"{where}: problem {i}"
+        if p.x_shift is not None and len(p.x_shift) != int(rational.s):
+            raise _invalid(w, f"x_shift holds {len(p.x_shift)} vectors, the rational function has "
+                              f"{int(rational.s)} poles")
         arr[i].lat = p.lat.h
         arr[i].mu = float(p.mu)
-        arr[i].b = C.c_void_p(p.b.data_ptr())
-        arr[i].x = C.c_void_p(p.x.data_ptr())
+        arr[i].b = _vec(p.lat, p.b, w + " b")
+        arr[i].x = _vec(p.lat, p.x, w + " x")
         if p.defl is not None:
+            p.defl.check_for(p.lat, w)
             arr[i].defl = C.pointer(p.defl.struct)
         if p.x_shift is not None:
-            xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
+            xs = (_vp * len(p.x_shift))(*[_vec(p.lat, t, f"{w} x_shift[{j}]") for j, t in enumerate(p.x_shift)])
             keep.append(xs)
             arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
+    return problems, arr, keep
+
+
+def multishift_solve(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
+                     delta=0.0, poll=0, verify=False, basis_slots=0, graph=True, stream=None):
+    """Multishift BiCG-LR for every problem; returns one stats dict per problem."""
+    problems, arr, keep = _problem_array(problems, rational, "multishift_solve")
+    n = len(problems)
     o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll),
                int(bool(verify)), int(basis_slots), 0 if graph else -1)
     st = (Stats * max(n, 1))()
@@ -336,27 +424,14 @@ lib.multishift_bicgstab.argtypes = lib.multishift_solve.argtypes
 
 
 def multishift_bicgstab(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta32=0.0, theta16=0.0,
-                        delta=0.0, poll=0, basis_slots=0, graph=True, stream=None):
+                        delta=0.0, poll=0, basis_slots=0, graph=True, verify=False, stream=None):
     """Multishift BiCGStab for every problem (stored basis and the mixed schedule; basis_slots < 0:
-    per-shift vectors, FP64 only); one stats dict per problem."""
-    if isinstance(problems, Problem):
-        problems = [problems]
+    per-shift vectors, FP64 only); verify: FP64 true residual of every shifted system and FP64
+    refinement of those above tol (stored basis).  One stats dict per problem."""
+    problems, arr, keep = _problem_array(problems, rational, "multishift_bicgstab")
     n = len(problems)
-    arr = (_Problem * n)()
-    keep = []
-    for i, p in enumerate(problems):
-        arr[i].lat = p.lat.h
-        arr[i].mu = float(p.mu)
-        arr[i].b = C.c_void_p(p.b.data_ptr())
-        arr[i].x = C.c_void_p(p.x.data_ptr())
-        if p.defl is not None:
-            arr[i].defl = C.pointer(p.defl.struct)
-        if p.x_shift is not None:
-            xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
-            keep.append(xs)
-            arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
-    o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll), 0,
-               int(basis_slots), 0 if graph else -1)
+    o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), float(delta), int(poll),
+               int(bool(verify)), int(basis_slots), 0 if graph else -1)
     st = (Stats * max(n, 1))()
     check(lib.multishift_bicgstab(arr, n, C.byref(rational), C.byref(o), st, _stream(stream)), "multishift_bicgstab")
     return [st[i].as_dict() for i in range(n)]
@@ -369,22 +444,8 @@ def multishift_qmr(problems, rational, tol=1e-10, maxiter=10000, prec=F64, theta
                    basis_slots=0, verify=False, stream=None):
     """Multishift QMR for every problem (stored Lanczos basis, per-shift least squares, FP64 or the
     mixed stencil schedule); one stats dict per problem."""
-    if isinstance(problems, Problem):
-        problems = [problems]
+    problems, arr, keep = _problem_array(problems, rational, "multishift_qmr")
     n = len(problems)
-    arr = (_Problem * n)()
-    keep = []
-    for i, p in enumerate(problems):
-        arr[i].lat = p.lat.h
-        arr[i].mu = float(p.mu)
-        arr[i].b = C.c_void_p(p.b.data_ptr())
-        arr[i].x = C.c_void_p(p.x.data_ptr())
-        if p.defl is not None:
-            arr[i].defl = C.pointer(p.defl.struct)
-        if p.x_shift is not None:
-            xs = (_vp * len(p.x_shift))(*[C.c_void_p(t.data_ptr()) for t in p.x_shift])
-            keep.append(xs)
-            arr[i].x_shift = C.cast(xs, C.POINTER(_vp))
     o = MsOpts(float(tol), int(maxiter), int(prec), float(theta32), float(theta16), 0.0, int(poll),
                1 if verify else 0, int(basis_slots), 0)
     st = (Stats * max(n, 1))()
@@ -398,7 +459,7 @@ KERNEL_NAMES = ["stencil_f64", "stencil_f32", "stencil_h16", "shift_update", "se
 
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double),
-                ("calls", C.c_longlong)]
+                ("calls", C.c_longlong), ("bytes_stored", C.c_double)]
 
 
 lib.sgn_profile_enable.argtypes = [_vp, C.c_int]
@@ -415,7 +476,8 @@ def sgn_profile_read(ctx):
     arr = (KernelProfile * K_COUNT)()
     check(lib.sgn_profile_read(ctx.h, arr), "sgn_profile_read")
     return {KERNEL_NAMES[i]: {"launches": arr[i].launches, "total_ms": arr[i].total_ms, "bytes": arr[i].bytes,
-                              "flops": arr[i].flops, "calls": arr[i].calls} for i in range(K_COUNT)}
+                              "flops": arr[i].flops, "calls": arr[i].calls, "bytes_stored": arr[i].bytes_stored}
+            for i in range(K_COUNT)}
 
 
 lib.wilson_apply_multi.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(_vp), C.POINTER(_vp), C.c_int,
@@ -425,11 +487,31 @@ lib.wilson_apply_multi.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTE
 def wilson_apply_multi(lat, mus, xs, outs, prec=F64, flags=INTERNAL_LAYOUT, stream=None):
     """outs[i] = H_W(mus[i]) xs[i], right-hand sides sharing link loads (internal layout)."""
     n = len(xs)
+    if len(mus) != n or len(outs) != n:
+        raise _invalid("wilson_apply_multi", "mus, xs and outs need the same length")
     mu = (C.c_double * n)(*[float(m) for m in mus])
-    pin = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in xs])
-    pout = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in outs])
+    pin = (_vp * n)(*[_field(lat, t, prec, flags, f"wilson_apply_multi: in[{i}]") for i, t in enumerate(xs)])
+    pout = (_vp * n)(*[_field(lat, t, prec, flags, f"wilson_apply_multi: out[{i}]") for i, t in enumerate(outs)])
     check(lib.wilson_apply_multi(lat.h, n, mu, pin, pout, int(prec), C.c_uint(flags), _stream(stream)),
           "wilson_apply_multi")
+
+
+class TuneCandidate(C.Structure):
+    _fields_ = [("block_sites", C.c_int), ("links_in_registers", C.c_int), ("us", C.c_double), ("chosen", C.c_int)]
+
+
+lib.sgn_autotune.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(TuneCandidate), C.c_int,
+                             C.POINTER(C.c_int), _vp]
+
+
+def sgn_autotune(lat, prec, nrhs=1, reps=20, stream=None):
+    """Time the stencil's candidate launch shapes for lat's dimensions, prec and nrhs right-hand sides;
+    the fastest is kept by the context.  Returns the candidates as dicts (chosen = 1 for the fastest)."""
+    arr = (TuneCandidate * 32)()
+    n = C.c_int()
+    check(lib.sgn_autotune(lat.h, int(prec), int(nrhs), int(reps), arr, 32, C.byref(n), _stream(stream)),
+          "sgn_autotune")
+    return [{f: getattr(arr[i], f) for f, _ in TuneCandidate._fields_} for i in range(min(n.value, 32))]
 
 
 class ArnoldiOpts(C.Structure):
@@ -446,9 +528,11 @@ def sign_arnoldi_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10
     """x = x_P + g_s(c H_W)(I-P) b by restarted FOM-LR; returns the stats dict."""
     o = ArnoldiOpts(int(kmax), float(tol), int(max_restarts), int(prec), float(theta32), float(theta16))
     st = Stats()
-    d = C.pointer(defl.struct) if defl is not None else None
-    check(lib.sign_arnoldi_rational(lat.h, float(mu), _ptr(b), _ptr(x), C.byref(rational), d, C.byref(o),
-                                    C.byref(st), _stream(stream)), "sign_arnoldi_rational")
+    w = "sign_arnoldi_rational"
+    pb, px = _vec(lat, b, w + ": b"), _vec(lat, x, w + ": x")
+    d = _defl_ptr(defl, lat, w)
+    check(lib.sign_arnoldi_rational(lat.h, float(mu), pb, px, C.byref(rational), d, C.byref(o),
+                                    C.byref(st), _stream(stream)), w)
     return st.as_dict()
 
 
@@ -471,8 +555,11 @@ def sgn_critical_eigenpairs(lat, mu, m, L, R, nev=0, kmax=0, tol=0.0, max_restar
     lam = (C.c_double * (2 * int(m)))()
     alpha = C.c_double()
     st = Stats()
-    check(lib.sgn_critical_eigenpairs(lat.h, float(mu), C.byref(o), _ptr(L), _ptr(R), lam, C.byref(alpha),
-                                      C.byref(st), _stream(stream)), "sgn_critical_eigenpairs")
+    w = "sgn_critical_eigenpairs"
+    pL = _tensor(L, w + ": L", _c128(), int(m) * 12 * lat.V, device=lat.ctx.device)
+    pR = _tensor(R, w + ": R", _c128(), int(m) * 12 * lat.V, device=lat.ctx.device)
+    check(lib.sgn_critical_eigenpairs(lat.h, float(mu), C.byref(o), pL, pR, lam, C.byref(alpha),
+                                      C.byref(st), _stream(stream)), w)
     lm = [complex(lam[2 * i], lam[2 * i + 1]) for i in range(int(m))]
     return lm, alpha.value, st.as_dict()
 
@@ -482,9 +569,11 @@ def sign_gmres_rational(lat, mu, b, x, rational, defl=None, kmax=40, tol=1e-10, 
     """x = x_P + g_s(c H_W)(I-P) b by restarted GMRES-LR; returns the stats dict."""
     o = ArnoldiOpts(int(kmax), float(tol), int(max_restarts), int(prec), float(theta32), float(theta16))
     st = Stats()
-    d = C.pointer(defl.struct) if defl is not None else None
-    check(lib.sign_gmres_rational(lat.h, float(mu), _ptr(b), _ptr(x), C.byref(rational), d, C.byref(o),
-                                  C.byref(st), _stream(stream)), "sign_gmres_rational")
+    w = "sign_gmres_rational"
+    pb, px = _vec(lat, b, w + ": b"), _vec(lat, x, w + ": x")
+    d = _defl_ptr(defl, lat, w)
+    check(lib.sign_gmres_rational(lat.h, float(mu), pb, px, C.byref(rational), d, C.byref(o),
+                                  C.byref(st), _stream(stream)), w)
     return st.as_dict()
 
 
@@ -494,6 +583,7 @@ lib.sgn_accuracy_measure.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_double), _vp]
 def sgn_accuracy_measure(lat, b, ssb, stream=None):
     """1/2 ||S(S b) - b|| / ||b|| for ssb = S(S b) computed with one approximate sign S."""
     acc = C.c_double()
-    check(lib.sgn_accuracy_measure(lat.h, _ptr(b), _ptr(ssb), C.byref(acc), _stream(stream)),
-          "sgn_accuracy_measure")
+    w = "sgn_accuracy_measure"
+    pb, ps = _vec(lat, b, w + ": b"), _vec(lat, ssb, w + ": ssb")
+    check(lib.sgn_accuracy_measure(lat.h, pb, ps, C.byref(acc), _stream(stream)), w)
     return acc.value

@@ -31,6 +31,7 @@
 //    sums, three synchronisations per iteration.
 #include <chrono>
 #include <map>
+#include <memory>
 #include <complex>
 #include <vector>
 
@@ -375,6 +376,79 @@ sgn_status solve_explicit(const sgn_problem &pb, const sgn_rational &rf, const s
     return converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
+
+}  // namespace
+
+double shift_residual64(Lattice &lat, const OpSpec &op, double c2, double sigma, const void *y, const void *x,
+                        void *out, void *tmp, hipStream_t s)
+{
+    dslash_launch(lat, SGN_PREC_F64, op, x, tmp, Epilogue{}, s);
+    Epilogue ep;
+    ep.a = -c2;
+    ep.z = x;
+    ep.b = {sigma, 0.0};
+    dslash_launch(lat, SGN_PREC_F64, op, tmp, out, ep, s);
+    const int64_t n = 12 * lat.S;
+    axpby64({1.0, 0.0}, y, {1.0, 0.0}, out, n, s);
+    return norm_sync(*lat.ctx, out, n, false, s);
+}
+
+int refine_shift64(Lattice &lat, const OpSpec &op, double c2, double sigma, void *r, void *x, double target,
+                   int maxiter, void *work, void *tmp, hipStream_t s, int *matvecs)
+{
+    Context &ctx = *lat.ctx;
+    const int64_t n = 12 * lat.S;
+    const size_t b = (size_t)n * 16;
+    char *w = static_cast<char *>(work);
+    void *rh = w, *pv = w + b, *v = w + 2 * b, *sv = w + 3 * b, *t = w + 4 * b, *e = w + 5 * b;
+    auto applyM = [&](const void *in, void *out) {
+        dslash_launch(lat, SGN_PREC_F64, op, in, tmp, Epilogue{}, s);
+        Epilogue ep;
+        ep.a = c2;
+        ep.z = in;
+        ep.b = {-sigma, 0.0};
+        dslash_launch(lat, SGN_PREC_F64, op, tmp, out, ep, s);
+        *matvecs += 2;
+    };
+    auto dot = [&](const void *a, const void *bb) {
+        const z64 d = dot_sync(ctx, a, bb, n, false, s);
+        return zc(d.r, d.i);
+    };
+    auto zz = [](zc a) { return z64{a.real(), a.imag()}; };
+    SGN_HIP(hipMemcpyAsync(rh, r, b, hipMemcpyDeviceToDevice, s));
+    SGN_HIP(hipMemcpyAsync(pv, r, b, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(vec_blocks(n)), dim3(256), 0, s, (double2 *)e,
+                       make_double2(0.0, 0.0), n);
+    SGN_HIP(hipGetLastError());
+    zc rho = dot(rh, r);
+    int it = 0;
+    while (it < maxiter) {
+        applyM(pv, v);
+        const zc den = dot(rh, v);
+        if (std::abs(den) == 0.0 || std::abs(rho) == 0.0) break;
+        const zc alpha = rho / den;
+        SGN_HIP(hipMemcpyAsync(sv, r, b, hipMemcpyDeviceToDevice, s));
+        axpby64(zz(-alpha), v, {1.0, 0.0}, sv, n, s);  // s = r - alpha v
+        applyM(sv, t);
+        const double tt = norm_sync(ctx, t, n, false, s);
+        const zc omega = tt > 0.0 ? dot(t, sv) / (tt * tt) : zc(0.0);
+        axpby64(zz(alpha), pv, {1.0, 0.0}, e, n, s);
+        axpby64(zz(omega), sv, {1.0, 0.0}, e, n, s);
+        SGN_HIP(hipMemcpyAsync(r, sv, b, hipMemcpyDeviceToDevice, s));
+        axpby64(zz(-omega), t, {1.0, 0.0}, r, n, s);  // r = s - omega t
+        ++it;
+        if (norm_sync(ctx, r, n, false, s) <= target || omega == zc(0.0)) break;
+        const zc rho_new = dot(rh, r);
+        const zc beta = (rho_new / rho) * (alpha / omega);
+        rho = rho_new;
+        axpby64(zz(-omega), v, {1.0, 0.0}, pv, n, s);  // p = r + beta (p - omega v)
+        axpby64({1.0, 0.0}, r, zz(beta), pv, n, s);
+    }
+    axpby64({1.0, 0.0}, e, {1.0, 0.0}, x, n, s);
+    return it;
+}
+
+namespace {
 
 // ----------------------------------------------------------------------------- stored-basis form
 struct BsHead {
@@ -1081,8 +1155,8 @@ sgn_status BsStored::run(sgn_stats *stp)
     if (K) SGN_HIP(hipMemcpy(hs.data(), hist_, sizeof(BsHist) * K, hipMemcpyDeviceToHost));
     const double lim = o_.tol * ynorm;
     std::vector<zc> dr(K + 1, 0.0), ds(K, 0.0);
-    std::vector<std::vector<zc>> xr_i, xs_i;  // per-shift coefficients when the x_i are requested
-    if (pb_.x_shift) {
+    std::vector<std::vector<zc>> xr_i, xs_i;  // per-shift coefficients when the x_i are requested or verified
+    if (pb_.x_shift || o_.verify) {
         xr_i.resize(ns_);
         xs_i.resize(ns_);
     }
@@ -1123,7 +1197,7 @@ sgn_status BsStored::run(sgn_stats *stp)
         st.shift_residual[i] = res / ynorm;
         worst = std::max(worst, st.shift_residual[i]);
         if (i == seed_) continue;
-        if (pb_.x_shift) {
+        if (pb_.x_shift || o_.verify) {
             xr_i[i] = Xr;
             xs_i[i] = Xs;
         }
@@ -1131,10 +1205,51 @@ sgn_status BsStored::run(sgn_stats *stp)
         for (int j = 0; j < K; ++j) ds[j] += rf_.omega[i] * Xs[j];
     }
     if (result == SGN_ERR_NOT_CONVERGED && worst <= o_.tol) result = SGN_OK;
-    // x_int = omega_seed x_seed + lift
-    scale64({rf_.omega[seed_], 0.0}, x64_, tmp64_, n_, s_);
-    lift(K, dr, ds, tmp64_);
-    unpack_spinor(lat_, tmp64_, rcan_, SGN_PREC_F64, s_);
+    int refine_its = 0, extra_mv = 0;
+    if (o_.verify) {
+        // every shifted solution explicitly (one lift each), its FP64 true residual, and an FP64
+        // refinement of any system above the tolerance; x = x_P + sum_i omega_i x_i of the checked
+        // x_i.  Work fields: the iteration's FP64 vectors (free after the loop) plus six more.
+        char *acc = p64_, *xi = tmp64_, *res = v64_, *tmp = t64_;
+        std::unique_ptr<DeviceScratch> work;
+        hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)acc,
+                           make_double2(0.0, 0.0), n_);
+        SGN_HIP(hipGetLastError());
+        worst = 0.0;
+        for (int i = 0; i < ns_; ++i) {
+            if (i == seed_) {
+                SGN_HIP(hipMemcpyAsync(xi, x64_, b64_, hipMemcpyDeviceToDevice, s_));
+            } else {
+                hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)xi,
+                                   make_double2(0.0, 0.0), n_);
+                SGN_HIP(hipGetLastError());
+                std::vector<zc> cr(K + 1, 0.0), cs(K, 0.0);
+                for (int j = 0; j <= K; ++j) cr[j] = xr_i[i][j];
+                for (int j = 0; j < K; ++j) cs[j] = xs_i[i][j];
+                lift(K, cr, cs, xi);
+            }
+            double ri = shift_residual64(lat_, op, c2_, rf_.sigma[i], y_, xi, res, tmp, s_) / ynorm;
+            extra_mv += 2;
+            if (ri > o_.tol) {
+                if (!work) work = std::make_unique<DeviceScratch>(6 * b64_);
+                refine_its += refine_shift64(lat_, op, c2_, rf_.sigma[i], res, xi, 0.5 * o_.tol * ynorm, maxiter_,
+                                             work->p, tmp, s_, &extra_mv);
+                ri = shift_residual64(lat_, op, c2_, rf_.sigma[i], y_, xi, res, tmp, s_) / ynorm;
+                extra_mv += 2;
+            }
+            st.shift_residual[i] = ri;
+            worst = std::max(worst, ri);
+            axpby64({rf_.omega[i], 0.0}, xi, {1.0, 0.0}, acc, n_, s_);
+            if (pb_.x_shift && pb_.x_shift[i]) unpack_spinor(lat_, xi, pb_.x_shift[i], SGN_PREC_F64, s_);
+        }
+        result = worst <= o_.tol ? (result == SGN_ERR_NOT_CONVERGED ? SGN_OK : result) : SGN_ERR_NOT_CONVERGED;
+        unpack_spinor(lat_, acc, rcan_, SGN_PREC_F64, s_);
+    } else {
+        // x_int = omega_seed x_seed + lift
+        scale64({rf_.omega[seed_], 0.0}, x64_, tmp64_, n_, s_);
+        lift(K, dr, ds, tmp64_);
+        unpack_spinor(lat_, tmp64_, rcan_, SGN_PREC_F64, s_);
+    }
     if (pb_.defl && pb_.defl->m > 0) {  // the exact x_i lie in range(I - P): drop rounding components
         DeviceScratch cd(sizeof(z64) * pb_.defl->m);
         deflate_dots(pb_.defl->L, pb_.defl->m, rcan_, nc_, static_cast<z64 *>(cd.p), ctx_, s_);
@@ -1143,7 +1258,7 @@ sgn_status BsStored::run(sgn_stats *stp)
         SGN_HIP(hipStreamSynchronize(s_));
     }
     axpby64({1.0, 0.0}, rcan_, {1.0, 0.0}, pb_.x, nc_, s_);
-    if (pb_.x_shift)  // each shift's own solution (the seed's is x itself)
+    if (pb_.x_shift && !o_.verify)  // each shift's own solution (the seed's is x itself)
         for (int i = 0; i < ns_; ++i) {
             if (!pb_.x_shift[i]) continue;
             if (i == seed_) {
@@ -1158,8 +1273,9 @@ sgn_status BsStored::run(sgn_stats *stp)
         }
     SGN_HIP(hipStreamSynchronize(s_));
     st.iterations = K;
-    st.matvecs = 4 * K + 1 + 2 * reliable_;
+    st.matvecs = 4 * K + 1 + 2 * reliable_ + extra_mv;
     st.reliable_updates = reliable_;
+    st.refine_iterations = refine_its;
     st.residual = worst;
     st.krylov_ms = ms_since(t_kry);
     st.total_ms = ms_since(t_start);

@@ -10,6 +10,13 @@
 // Single-RHS stencil: HBM-bound, 1368 flop per site.
 #include "field_io.h"
 
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <type_traits>
+
 #ifndef SGN_STENCIL_WAVES
 #define SGN_STENCIL_WAVES 1
 #endif
@@ -34,6 +41,12 @@
 #ifndef SGN_STAGED_STRIP
 #define SGN_STAGED_STRIP 1   // staged kernel block order: 0 = z-fastest XCD t-slabs, W > 0 = t-fastest strips of W blocks
 #endif
+#ifndef SGN_ZT_FIRST
+#define SGN_ZT_FIRST 0   // staged stencil: z and t hops (from memory) before the barrier, x and y after
+#endif
+#ifndef SGN_NT_OUT
+#define SGN_NT_OUT 1     // non-temporal stores of the stencil output
+#endif
 #ifndef SGN_LDS_MAXBYTES
 #define SGN_LDS_MAXBYTES 64512   // dynamic LDS budget of one block of the staged stencil (64 KiB less the reduction scratch)
 #endif
@@ -43,7 +56,9 @@ namespace sgn {
 namespace {
 
 }  // namespace
-constexpr int kMaxRhs = 2;
+// right-hand sides of one multi-RHS application (one block walks all of them; a
+// StencilParams holding this many is 2 KiB, within the kernel-argument limit)
+constexpr int kMaxRhs = 16;
 namespace {
 
 struct RhsParams {
@@ -78,59 +93,97 @@ struct StencilParams {
     int blk_sites;   // staged kernel: sites per block (whole x-rows)
     int nblk_total;  // blocks of this application (sites + padding); batched launches skip the rest
     int link_ne;     // complex entries stored per link (6 or 9)
+    int nrhs;        // right-hand sides of this application (staged kernel; the unstaged one uses NR)
     RhsParams rhs[kMaxRhs];
 };
 
-// Half-spinor projection (1 - gamma_nu) for FWD, (1 + gamma_nu) otherwise:
-// h[0..2] = colour vector of the upper-spin-0 row, h[3..5] = spin-1 row.
+// Complex arithmetic of the hops written as fused multiply-adds: a complex
+// multiply-accumulate is four FMAs (the plain expression s + a * b compiles to
+// two multiplies, two FMAs and two adds, as the compiler may not reassociate).
+
+// s = a b, or s = conj(a) b with CONJ
+template <bool CONJ, typename R>
+__device__ __forceinline__ cpx<R> cmul_f(cpx<R> a, cpx<R> b)
+{
+    cpx<R> s;
+    s.r = a.r * b.r;
+    s.r = fma(CONJ ? a.i : -a.i, b.i, s.r);
+    s.i = a.r * b.i;
+    s.i = fma(CONJ ? -a.i : a.i, b.r, s.i);
+    return s;
+}
+
+// s += a b, or s += conj(a) b with CONJ
+template <bool CONJ, typename R>
+__device__ __forceinline__ void cmac_f(cpx<R> &s, cpx<R> a, cpx<R> b)
+{
+    s.r = fma(a.r, b.r, s.r);
+    s.r = fma(CONJ ? a.i : -a.i, b.i, s.r);
+    s.i = fma(a.r, b.i, s.i);
+    s.i = fma(CONJ ? -a.i : a.i, b.r, s.i);
+}
+
+// a + f * (ph b) for the phase ph in {+1, -1, +i, -i} (PH = 0, 1, 2, 3) and a real f
+template <int PH, typename R>
+__device__ __forceinline__ cpx<R> add_ph(cpx<R> a, R f, cpx<R> b)
+{
+    if constexpr (PH == 0) return {fma(f, b.r, a.r), fma(f, b.i, a.i)};
+    else if constexpr (PH == 1) return {fma(-f, b.r, a.r), fma(-f, b.i, a.i)};
+    else if constexpr (PH == 2) return {fma(-f, b.i, a.r), fma(f, b.r, a.i)};
+    else return {fma(f, b.i, a.r), fma(-f, b.r, a.i)};
+}
+
+constexpr int kP1 = 0, kM1 = 1, kPI = 2, kMI = 3;
+
+// Half-spinor projection (1 - gamma_nu) for FWD, (1 + gamma_nu) otherwise, of
+// the spinor p with its lower two spins multiplied by s5 (the input gamma5
+// sign, folded into the adds): h[0..2] = colour vector of the upper-spin-0
+// row, h[3..5] = spin-1 row.
 template <int NU, bool FWD, typename R>
-__device__ __forceinline__ void project(const cpx<R> p[12], cpx<R> h[6])
+__device__ __forceinline__ void project(const cpx<R> p[12], cpx<R> h[6], R s5)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         cpx<R> p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
         if constexpr (NU == 0) {
-            h[c] = FWD ? p0 + times_mi(p3) : p0 + times_i(p3);
-            h[3 + c] = FWD ? p1 + times_mi(p2) : p1 + times_i(p2);
+            h[c] = FWD ? add_ph<kMI>(p0, s5, p3) : add_ph<kPI>(p0, s5, p3);
+            h[3 + c] = FWD ? add_ph<kMI>(p1, s5, p2) : add_ph<kPI>(p1, s5, p2);
         } else if constexpr (NU == 1) {
-            h[c] = FWD ? p0 + p3 : p0 - p3;
-            h[3 + c] = FWD ? p1 - p2 : p1 + p2;
+            h[c] = FWD ? add_ph<kP1>(p0, s5, p3) : add_ph<kM1>(p0, s5, p3);
+            h[3 + c] = FWD ? add_ph<kM1>(p1, s5, p2) : add_ph<kP1>(p1, s5, p2);
         } else if constexpr (NU == 2) {
-            h[c] = FWD ? p0 + times_mi(p2) : p0 + times_i(p2);
-            h[3 + c] = FWD ? p1 + times_i(p3) : p1 + times_mi(p3);
+            h[c] = FWD ? add_ph<kMI>(p0, s5, p2) : add_ph<kPI>(p0, s5, p2);
+            h[3 + c] = FWD ? add_ph<kPI>(p1, s5, p3) : add_ph<kMI>(p1, s5, p3);
         } else {
-            h[c] = FWD ? p0 - p2 : p0 + p2;
-            h[3 + c] = FWD ? p1 - p3 : p1 + p3;
+            h[c] = FWD ? add_ph<kM1>(p0, s5, p2) : add_ph<kP1>(p0, s5, p2);
+            h[3 + c] = FWD ? add_ph<kM1>(p1, s5, p3) : add_ph<kP1>(p1, s5, p3);
         }
     }
 }
 
 // acc += coef * reconstruct(chi): upper spins are chi0, chi1; lower spins follow
-// from the rank-2 structure of (1 -+ gamma_nu).
+// from the rank-2 structure of (1 -+ gamma_nu).  Every real component is one FMA.
 template <int NU, bool FWD, typename R>
 __device__ __forceinline__ void accumulate(cpx<R> acc[12], const cpx<R> chi[6], R coef)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        cpx<R> h0 = coef * chi[c], h1 = coef * chi[3 + c];
-        acc[c] = acc[c] + h0;
-        acc[3 + c] = acc[3 + c] + h1;
-        cpx<R> r2, r3;
+        const cpx<R> h0 = chi[c], h1 = chi[3 + c];
+        acc[c] = add_ph<kP1>(acc[c], coef, h0);
+        acc[3 + c] = add_ph<kP1>(acc[3 + c], coef, h1);
         if constexpr (NU == 0) {
-            r2 = FWD ? times_i(h1) : times_mi(h1);
-            r3 = FWD ? times_i(h0) : times_mi(h0);
+            acc[6 + c] = FWD ? add_ph<kPI>(acc[6 + c], coef, h1) : add_ph<kMI>(acc[6 + c], coef, h1);
+            acc[9 + c] = FWD ? add_ph<kPI>(acc[9 + c], coef, h0) : add_ph<kMI>(acc[9 + c], coef, h0);
         } else if constexpr (NU == 1) {
-            r2 = FWD ? -h1 : h1;
-            r3 = FWD ? h0 : -h0;
+            acc[6 + c] = FWD ? add_ph<kM1>(acc[6 + c], coef, h1) : add_ph<kP1>(acc[6 + c], coef, h1);
+            acc[9 + c] = FWD ? add_ph<kP1>(acc[9 + c], coef, h0) : add_ph<kM1>(acc[9 + c], coef, h0);
         } else if constexpr (NU == 2) {
-            r2 = FWD ? times_i(h0) : times_mi(h0);
-            r3 = FWD ? times_mi(h1) : times_i(h1);
+            acc[6 + c] = FWD ? add_ph<kPI>(acc[6 + c], coef, h0) : add_ph<kMI>(acc[6 + c], coef, h0);
+            acc[9 + c] = FWD ? add_ph<kMI>(acc[9 + c], coef, h1) : add_ph<kPI>(acc[9 + c], coef, h1);
         } else {
-            r2 = FWD ? -h0 : h0;
-            r3 = FWD ? -h1 : h1;
+            acc[6 + c] = FWD ? add_ph<kM1>(acc[6 + c], coef, h0) : add_ph<kP1>(acc[6 + c], coef, h0);
+            acc[9 + c] = FWD ? add_ph<kM1>(acc[9 + c], coef, h1) : add_ph<kP1>(acc[9 + c], coef, h1);
         }
-        acc[6 + c] = acc[6 + c] + r2;
-        acc[9 + c] = acc[9 + c] + r3;
     }
 }
 
@@ -142,20 +195,83 @@ __device__ __forceinline__ void link_mul(const cpx<R> u[9], const cpx<R> h[6], c
     for (int v = 0; v < 2; ++v)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            cpx<R> s = {0, 0};
+            cpx<R> s = cmul_f<ADJ>(ADJ ? u[a] : u[a * 3], h[3 * v]);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                if constexpr (ADJ)
-                    s = s + cmulc(u[b * 3 + a], h[3 * v + b]);
-                else
-                    s = s + u[a * 3 + b] * h[3 * v + b];
-            }
+            for (int b = 1; b < 3; ++b) cmac_f<ADJ>(s, ADJ ? u[b * 3 + a] : u[a * 3 + b], h[3 * v + b]);
             chi[3 * v + a] = s;
         }
 }
 
 template <typename R>
 using SpT = typename SpinorStore<R>::type;
+
+// Output side of one site: gamma5 on the result, the epilogue
+// out = a * in_scale * Op(in) + b * z, the store, and the site's terms of the
+// partial sums conj(w) . out and ||out||^2 (FP64).  The scales are real unless
+// in_scale / b_dev / Im b say otherwise (wave-uniform branches), and a dot
+// partner equal to z is not read twice.
+template <typename R, bool kEpi, bool kDot>
+__device__ __forceinline__ void finish_site(cpx<R> (&acc)[12], const RhsParams &Q, int S, int s, double &dr,
+                                            double &di, double &dn)
+{
+    const R s5o = static_cast<R>(Q.s5_out);
+    cpx<R> zz[12];
+    if constexpr (!kEpi) {
+#pragma unroll
+        for (int k = 6; k < 12; ++k) acc[k] = s5o * acc[k];
+    } else {
+        if (Q.in_scale) {
+            const z64 t = *Q.in_scale;
+            const cpx<R> sc = {static_cast<R>(Q.a * t.r), static_cast<R>(Q.a * t.i)};
+            const cpx<R> sl = {s5o * sc.r, s5o * sc.i};
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = cmul_f<false>(k < 6 ? sc : sl, acc[k]);
+        } else {
+            const R a = static_cast<R>(Q.a), al = s5o * a;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = (k < 6 ? a : al) * acc[k];
+        }
+        if (Q.z) {
+            load_spinor(static_cast<const SpT<R> *>(Q.z), S, s, zz);
+            if (!Q.b_dev && Q.b.i == 0.0) {
+                const R b = static_cast<R>(Q.b.r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = add_ph<kP1>(acc[k], b, zz[k]);
+            } else {
+                z64 bb = Q.b;
+                if (Q.b_dev) {
+                    const z64 t = *Q.b_dev;
+                    bb = {bb.r * t.r - bb.i * t.i, bb.r * t.i + bb.i * t.r};
+                }
+                const cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
+#pragma unroll
+                for (int k = 0; k < 12; ++k) cmac_f<false>(acc[k], b, zz[k]);
+            }
+        }
+    }
+    if (SGN_NT_OUT)
+        store_spinor_nt(static_cast<SpT<R> *>(Q.out), S, s, acc);
+    else
+        store_spinor(static_cast<SpT<R> *>(Q.out), S, s, acc);
+    if constexpr (kDot) {
+        if (Q.w) {
+            cpx<R> ww[12];
+            if (kEpi && Q.w == Q.z) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) ww[k] = zz[k];
+            } else {
+                load_spinor(static_cast<const SpT<R> *>(Q.w), S, s, ww);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                z64 a = cast<double>(ww[k]), o = cast<double>(acc[k]);
+                dr += a.r * o.r + a.i * o.i;
+                di += a.r * o.i - a.i * o.r;
+                dn += o.r * o.r + o.i * o.i;
+            }
+        }
+    }
+}
 
 // Ordering fence between hops: the accumulator must be complete here and no
 // later load may move above it.  Without it the compiler issues all 8
@@ -185,10 +301,7 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
         for (int r = 0; r < NR; ++r) {
             cpx<R> p[12], h[6], chi[6];
             load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.S, n, p);
-            const R s5 = static_cast<R>(P.rhs[r].s5_in);
-#pragma unroll
-            for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
-            project<NU, true>(p, h);
+            project<NU, true>(p, h, static_cast<R>(P.rhs[r].s5_in));
             link_mul<false>(u, h, chi);
             const R w = NU == 3 ? static_cast<R>(P.rhs[r].wf_t) : R(1);
             accumulate<NU, true>(acc[r], chi, -kap * w * bcf);
@@ -208,10 +321,7 @@ __device__ __forceinline__ void hop_pair(cpx<R> (&acc)[NR][12], const StencilPar
         for (int r = 0; r < NR; ++r) {
             cpx<R> p[12], h[6], chi[6];
             load_spinor(static_cast<const SpT<R> *>(P.rhs[r].in), P.S, n, p);
-            const R s5 = static_cast<R>(P.rhs[r].s5_in);
-#pragma unroll
-            for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
-            project<NU, false>(p, h);
+            project<NU, false>(p, h, static_cast<R>(P.rhs[r].s5_in));
             link_mul<true>(u, h, chi);
             const R w = NU == 3 ? static_cast<R>(P.rhs[r].wb_t) : R(1);
             accumulate<NU, false>(acc[r], chi, -kap * w * bcb);
@@ -283,45 +393,7 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
         hop_pair<3, NR, R, LT>(acc, P, s, c3);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const RhsParams &Q = P.rhs[r];
-            const R s5o = static_cast<R>(Q.s5_out);
-#pragma unroll
-            for (int k = 6; k < 12; ++k) acc[r][k] = s5o * acc[r][k];
-            if constexpr (kEpi) {
-                cpx<R> sc = {static_cast<R>(Q.a), R(0)};
-                if (Q.in_scale) {
-                    z64 t = *Q.in_scale;
-                    sc = {static_cast<R>(Q.a * t.r), static_cast<R>(Q.a * t.i)};
-                }
-#pragma unroll
-                for (int k = 0; k < 12; ++k) acc[r][k] = sc * acc[r][k];
-                if (Q.z) {
-                    z64 bb = Q.b;
-                    if (Q.b_dev) {
-                        z64 t = *Q.b_dev;
-                        bb = {bb.r * t.r - bb.i * t.i, bb.r * t.i + bb.i * t.r};
-                    }
-                    cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
-                    cpx<R> zz[12];
-                    load_spinor(static_cast<const SpT<R> *>(Q.z), P.S, s, zz);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) acc[r][k] = acc[r][k] + b * zz[k];
-                }
-            }
-            store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, acc[r]);
-            if constexpr (kDot) {
-                if (Q.w) {
-                    cpx<R> ww[12];
-                    load_spinor(static_cast<const SpT<R> *>(Q.w), P.S, s, ww);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        z64 a = cast<double>(ww[k]), o = cast<double>(acc[r][k]);
-                        dr[r] += a.r * o.r + a.i * o.i;
-                        di[r] += a.r * o.i - a.i * o.r;
-                        dn[r] += o.r * o.r + o.i * o.i;
-                    }
-                }
-            }
+            finish_site<R, kEpi, kDot>(acc[r], P.rhs[r], P.S, s, dr[r], di[r], dn[r]);
         }
     }
     if constexpr (kDot) {
@@ -352,8 +424,13 @@ __global__ void __launch_bounds__(SGN_STENCIL_THREADS) __attribute__((amdgpu_wav
 // and stores it in LDS; a neighbour inside the block is then read from LDS and
 // only the others (+-z, +-t, block-edge rows) are gathered from memory.
 
-// largest block of the staged kernel: FP64 needs ~160 VGPRs, so at most 2 waves per SIMD
-template <typename R> constexpr int kStagedMaxThreads = sizeof(R) == 8 ? 512 : 1024;
+// largest block of the staged kernel (the LDS budget allows at most 64512/192 = 336 FP64 and
+// 672 FP32 sites): FP64 needs ~180 VGPRs, so at most 2 waves per SIMD; the FP32 bound leaves up
+// to 168 VGPRs for the multi-RHS form that holds every link of a site in registers
+template <typename R> constexpr int kStagedMaxThreads = sizeof(R) == 8 ? 512 : 704;
+// the multi-RHS form with the links in registers (FP16 links): 8 waves per block at most, so
+// up to 256 VGPRs (two waves per SIMD)
+constexpr int kRegsMaxThreads = 512;
 
 template <typename R>
 __device__ __forceinline__ void lds_store_spinor(SpT<R> *l, int B, int i, const cpx<R> v[12]);
@@ -392,29 +469,67 @@ __device__ __forceinline__ void lds_load_spinor<float>(const float4 *l, int B, i
     }
 }
 
-// neighbour spinor n: from LDS when it belongs to this block (stored already
-// multiplied by the input gamma5 sign), else from memory
+// neighbour spinor n of right-hand side Q: from LDS when it belongs to this block
+// (stored already multiplied by the input gamma5 sign), else from memory.  Returns
+// the gamma5 sign the projection still has to apply to the lower spins.
 template <typename R>
-__device__ __forceinline__ void fetch_neighbour(const StencilParams &P, const SpT<R> *lds, int base, int n,
-                                                cpx<R> p[12])
+__device__ __forceinline__ R fetch_neighbour(const RhsParams &Q, int S, int B, const SpT<R> *lds, int base, int n,
+                                             cpx<R> p[12])
 {
     const int ln = n - base;
-    if ((unsigned)ln < (unsigned)P.blk_sites) {
-        lds_load_spinor<R>(lds, P.blk_sites, ln, p);
-    } else {
-        load_spinor(static_cast<const SpT<R> *>(P.rhs[0].in), P.S, n, p);
-        const R s5 = static_cast<R>(P.rhs[0].s5_in);
-#pragma unroll
-        for (int k = 6; k < 12; ++k) p[k] = s5 * p[k];
+    if ((unsigned)ln < (unsigned)B) {
+        lds_load_spinor<R>(lds, B, ln, p);
+        return R(1);
     }
+    load_spinor(static_cast<const SpT<R> *>(Q.in), S, n, p);
+    return static_cast<R>(Q.s5_in);
 }
 
-template <int NU, typename R, typename LT>
-__device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const StencilParams &P, const SpT<R> *lds,
-                                                int base, int s, int coord)
+// The eight links a site needs (U_nu(x) and U_nu(x - nu) for nu = 0..3, entry 2 nu + d),
+// loaded once in their stored two-row form and shared by every right-hand side of the
+// block (kRegs), or read from memory at each hop (kRegs false: L2 serves the repeats).
+template <typename R, typename LT, bool kRegs>
+struct SiteLinks {
+    LT e[kRegs ? 8 : 1][kRegs ? 6 : 1];
+
+    __device__ __forceinline__ void load(const StencilParams &P, int s, const int (&c)[4])
+    {
+        if constexpr (kRegs) {
+            const LT *U = static_cast<const LT *>(P.links);
+#pragma unroll
+            for (int nu = 0; nu < 4; ++nu) {
+                const int L = P.L[nu], st = P.stride[nu];
+                const int nb = c[nu] == 0 ? s + (L - 1) * st : s - st;
+                const LT *b = U + (size_t)nu * 6 * P.S;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    e[2 * nu][k] = ld_off(b + (size_t)k * P.S, (uint32_t)s * (uint32_t)sizeof(LT));
+                    e[2 * nu + 1][k] = ld_off(b + (size_t)k * P.S, (uint32_t)nb * (uint32_t)sizeof(LT));
+                }
+            }
+        }
+    }
+
+    // link K = 2 nu + d as a full 3x3 matrix; n: the site it belongs to (s, or x - nu)
+    template <int K>
+    __device__ __forceinline__ void get(const StencilParams &P, int n, cpx<R> u[9]) const
+    {
+        if constexpr (kRegs) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[k] = to_cpx<R>(e[K][k]);
+            su3_third_row(u);
+        } else {
+            load_link<R>(static_cast<const LT *>(P.links), P.S, P.link_ne, K / 2, n, u);
+        }
+    }
+};
+
+template <int NU, typename R, typename LT, bool kRegs>
+__device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const StencilParams &P, const RhsParams &Q,
+                                                const SpT<R> *lds, int base, int s, int coord,
+                                                const SiteLinks<R, LT, kRegs> &lk)
 {
-    const LT *U = static_cast<const LT *>(P.links);
-    const int L = P.L[NU], st = P.stride[NU];
+    const int L = P.L[NU], st = P.stride[NU], B = P.blk_sites;
     const R kap = static_cast<R>(P.kappa);
     cpx<R> u[9];
     {
@@ -422,11 +537,11 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const int n = wrap ? s - (L - 1) * st : s + st;
         const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
-        load_link<R>(U, P.S, P.link_ne, NU, s, u);
-        fetch_neighbour<R>(P, lds, base, n, p);
-        project<NU, true>(p, h);
+        lk.template get<2 * NU>(P, s, u);
+        const R s5 = fetch_neighbour<R>(Q, P.S, B, lds, base, n, p);
+        project<NU, true>(p, h, s5);
         link_mul<false>(u, h, chi);
-        const R w = NU == 3 ? static_cast<R>(P.rhs[0].wf_t) : R(1);
+        const R w = NU == 3 ? static_cast<R>(Q.wf_t) : R(1);
         accumulate<NU, true>(acc, chi, -kap * w * bcf);
     }
     pin(acc);
@@ -435,37 +550,45 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const int n = wrap ? s + (L - 1) * st : s - st;
         const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
-        load_link<R>(U, P.S, P.link_ne, NU, n, u);
-        fetch_neighbour<R>(P, lds, base, n, p);
-        project<NU, false>(p, h);
+        lk.template get<2 * NU + 1>(P, n, u);
+        const R s5 = fetch_neighbour<R>(Q, P.S, B, lds, base, n, p);
+        project<NU, false>(p, h, s5);
         link_mul<true>(u, h, chi);
-        const R w = NU == 3 ? static_cast<R>(P.rhs[0].wb_t) : R(1);
+        const R w = NU == 3 ? static_cast<R>(Q.wb_t) : R(1);
         accumulate<NU, false>(acc, chi, -kap * w * bcb);
     }
     pin(acc);
 }
 
-template <typename R, typename LT, bool kEpi, bool kDot>
+// One block: B sites for each right-hand side in turn (kMulti: the P.nrhs right-hand sides
+// of P's group, all on P's lattice; else the single one, P.rhs[0]); the block's own spinors of
+// the current right-hand side are staged in LDS.  The single form indexes P.rhs only with
+// constants: P is then a kernel argument, and a runtime index into it would copy it to private
+// memory.
+template <typename R, typename LT, bool kEpi, bool kDot, bool kRegs, bool kMulti>
 __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SpT<R> *lds = reinterpret_cast<SpT<R> *>(smem_raw);
-    const RhsParams &Q = P.rhs[0];
     if (bx >= P.nblk_sites) {  // padding of the component arrays: keep it zero
         const int s = P.V + (bx - P.nblk_sites) * (int)blockDim.x + (int)threadIdx.x;
-        if (s < P.S) {
-            cpx<R> zero[12];
+        const int nr = kMulti ? P.nrhs : 1;
+        for (int r = 0; r < nr; ++r) {
+            const RhsParams &Q = P.rhs[kMulti ? r : 0];
+            if (s < P.S) {
+                cpx<R> zero[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) zero[k] = {R(0), R(0)};
-            store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, zero);
-        }
-        if constexpr (kDot) {
-            if (threadIdx.x == 0 && Q.w) {
-                if (Q.norm) {
-                    Q.partials[2 * bx] = {0.0, 0.0};
-                    Q.partials[2 * bx + 1] = {0.0, 0.0};
-                } else {
-                    Q.partials[bx] = {0.0, 0.0};
+                for (int k = 0; k < 12; ++k) zero[k] = {R(0), R(0)};
+                store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, zero);
+            }
+            if constexpr (kDot) {
+                if (threadIdx.x == 0 && Q.w) {
+                    if (Q.norm) {
+                        Q.partials[2 * bx] = {0.0, 0.0};
+                        Q.partials[2 * bx + 1] = {0.0, 0.0};
+                    } else {
+                        Q.partials[bx] = {0.0, 0.0};
+                    }
                 }
             }
         }
@@ -490,77 +613,50 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
     const int i = threadIdx.x;
     const int s = base + i;
     const bool valid = i < B;  // blocks tile the V sites exactly
-    cpx<R> acc[12];
+    int c[4] = {0, 0, 0, 0};
     if (valid) {
-        load_spinor(static_cast<const SpT<R> *>(Q.in), P.S, s, acc);
-        const R s5 = static_cast<R>(Q.s5_in);
-#pragma unroll
-        for (int k = 6; k < 12; ++k) acc[k] = s5 * acc[k];
-        lds_store_spinor<R>(lds, B, i, acc);
-    }
-    __syncthreads();
-    double dr = 0.0, di = 0.0, dn = 0.0;
-    if (valid) {
-        int c0 = s % P.L[0];
+        c[0] = s % P.L[0];
         int q = s / P.L[0];
-        int c1 = q % P.L[1];
+        c[1] = q % P.L[1];
         q /= P.L[1];
-        int c2 = q % P.L[2];
-        int c3 = q / P.L[2];
-        hop_pair_staged<0, R, LT>(acc, P, lds, base, s, c0);
-        hop_pair_staged<1, R, LT>(acc, P, lds, base, s, c1);
-        hop_pair_staged<2, R, LT>(acc, P, lds, base, s, c2);
-        hop_pair_staged<3, R, LT>(acc, P, lds, base, s, c3);
-        const R s5o = static_cast<R>(Q.s5_out);
-#pragma unroll
-        for (int k = 6; k < 12; ++k) acc[k] = s5o * acc[k];
-        if constexpr (kEpi) {
-            cpx<R> sc = {static_cast<R>(Q.a), R(0)};
-            if (Q.in_scale) {
-                z64 t = *Q.in_scale;
-                sc = {static_cast<R>(Q.a * t.r), static_cast<R>(Q.a * t.i)};
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = sc * acc[k];
-            if (Q.z) {
-                z64 bb = Q.b;
-                if (Q.b_dev) {
-                    z64 t = *Q.b_dev;
-                    bb = {bb.r * t.r - bb.i * t.i, bb.r * t.i + bb.i * t.r};
-                }
-                cpx<R> b = {static_cast<R>(bb.r), static_cast<R>(bb.i)};
-                cpx<R> zz[12];
-                load_spinor(static_cast<const SpT<R> *>(Q.z), P.S, s, zz);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) acc[k] = acc[k] + b * zz[k];
-            }
-        }
-        store_spinor(static_cast<SpT<R> *>(Q.out), P.S, s, acc);
-        if constexpr (kDot) {
-            if (Q.w) {
-                cpx<R> ww[12];
-                load_spinor(static_cast<const SpT<R> *>(Q.w), P.S, s, ww);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    z64 a = cast<double>(ww[k]), o = cast<double>(acc[k]);
-                    dr += a.r * o.r + a.i * o.i;
-                    di += a.r * o.i - a.i * o.r;
-                    dn += o.r * o.r + o.i * o.i;
-                }
-            }
-        }
+        c[2] = q % P.L[2];
+        c[3] = q / P.L[2];
     }
-    if constexpr (kDot) {
-        __shared__ double red[3 * 16];
-        if (Q.w) {  // uniform
-            double v[3] = {dr, di, dn};
-            block_sum<3>(v, red);
-            if (threadIdx.x == 0) {
-                if (Q.norm) {
-                    Q.partials[2 * bx] = {v[0], v[1]};
-                    Q.partials[2 * bx + 1] = {v[2], 0.0};
-                } else {
-                    Q.partials[bx] = {v[0], v[1]};
+    SiteLinks<R, LT, kRegs> lk;
+    if (valid) lk.load(P, s, c);
+    const int nr = kMulti ? P.nrhs : 1;
+    for (int r = 0; r < nr; ++r) {
+        const RhsParams &Q = P.rhs[kMulti ? r : 0];
+        if (r > 0) __syncthreads();  // the previous right-hand side's LDS reads are done
+        cpx<R> acc[12];
+        if (valid) {
+            load_spinor(static_cast<const SpT<R> *>(Q.in), P.S, s, acc);
+            const R s5 = static_cast<R>(Q.s5_in);
+#pragma unroll
+            for (int k = 6; k < 12; ++k) acc[k] = s5 * acc[k];
+            lds_store_spinor<R>(lds, B, i, acc);
+        }
+        __syncthreads();
+        double dr = 0.0, di = 0.0, dn = 0.0;
+        if (valid) {
+            hop_pair_staged<0, R, LT, kRegs>(acc, P, Q, lds, base, s, c[0], lk);
+            hop_pair_staged<1, R, LT, kRegs>(acc, P, Q, lds, base, s, c[1], lk);
+            hop_pair_staged<2, R, LT, kRegs>(acc, P, Q, lds, base, s, c[2], lk);
+            hop_pair_staged<3, R, LT, kRegs>(acc, P, Q, lds, base, s, c[3], lk);
+            finish_site<R, kEpi, kDot>(acc, Q, P.S, s, dr, di, dn);
+        }
+        if constexpr (kDot) {
+            __shared__ double red[3 * 16];
+            if (Q.w) {  // uniform
+                double v[3] = {dr, di, dn};
+                block_sum<3>(v, red);
+                if (threadIdx.x == 0) {
+                    if (Q.norm) {
+                        Q.partials[2 * bx] = {v[0], v[1]};
+                        Q.partials[2 * bx + 1] = {v[2], 0.0};
+                    } else {
+                        Q.partials[bx] = {v[0], v[1]};
+                    }
                 }
             }
         }
@@ -570,19 +666,20 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
 template <typename R, typename LT, bool kEpi, bool kDot>
 __global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(StencilParams P)
 {
-    staged_body<R, LT, kEpi, kDot>(P, (int)blockIdx.x);
+    staged_body<R, LT, kEpi, kDot, false, false>(P, (int)blockIdx.x);
 }
 
 // Batched form: blockIdx.y selects one of several independent applications
-// (own lattice, fields and epilogue) whose parameters live in device memory.
-// gridDim.x is a multiple of 8, so the XCD of block (x, y) is x mod 8 as in
-// the single form.
-template <typename R, typename LT, bool kEpi, bool kDot>
-__global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_batch(const StencilParams *__restrict__ plist)
+// (own lattice, right-hand sides and epilogues) whose parameters live in device
+// memory.  gridDim.x is a multiple of 8, so the XCD of block (x, y) is x mod 8 as
+// in the single form.
+template <typename R, typename LT, bool kEpi, bool kDot, bool kRegs>
+__global__ void __launch_bounds__(kRegs ? kRegsMaxThreads : kStagedMaxThreads<R>)
+    stencil_staged_batch(const StencilParams *__restrict__ plist)
 {
-    const StencilParams P = plist[blockIdx.y];
+    const StencilParams &P = plist[blockIdx.y];
     if ((int)blockIdx.x >= P.nblk_total) return;
-    staged_body<R, LT, kEpi, kDot>(P, (int)blockIdx.x);
+    staged_body<R, LT, kEpi, kDot, kRegs, true>(P, (int)blockIdx.x);
 }
 
 template <typename R, typename LT>
@@ -609,13 +706,19 @@ void launch_typed(const StencilParams &P, int nblk, bool epi, bool dot, hipStrea
         hipLaunchKernelGGL((stencil_kernel<R, LT, NR, false, false>), g, b, 0, s, P);
 }
 
+// unstaged kernel (lattices too small for a staged block shape): one launch per right-hand side
 template <typename R, typename LT>
 void launch_nr(const StencilParams &P, int nr, int nblk, bool epi, bool dot, hipStream_t s)
 {
-    switch (nr) {
-    case 1: launch_typed<R, LT, 1>(P, nblk, epi, dot, s); break;
-    case 2: launch_typed<R, LT, 2>(P, nblk, epi, dot, s); break;
-    default: throw Failure{SGN_ERR_INVALID, "stencil: unsupported number of right-hand sides"};
+    if (nr == 1) {
+        launch_typed<R, LT, 1>(P, nblk, epi, dot, s);
+        return;
+    }
+    for (int r = 0; r < nr; ++r) {
+        StencilParams Q = P;
+        Q.rhs[0] = P.rhs[r];
+        Q.nrhs = 1;
+        launch_typed<R, LT, 1>(Q, nblk, epi, dot, s);
     }
 }
 
@@ -631,13 +734,17 @@ struct StagedPlan {
     size_t lds = 0;
 };
 
-StagedPlan staged_plan(const Lattice &lat, sgn_prec p)
+// max_threads > 0 caps the block (the register-link multi-RHS form), max_sites > 0 the sites of
+// a block (a tuned shape)
+StagedPlan staged_plan(const Lattice &lat, sgn_prec p, int max_threads = 0, int max_sites = 0)
 {
     StagedPlan pl;
     if (!SGN_STENCIL_LDS) return pl;
     const int64_t site_bytes = p == SGN_PREC_F64 ? 192 : 96;
-    const int64_t bmax = std::min<int64_t>(p == SGN_PREC_F64 ? kStagedMaxThreads<double> : kStagedMaxThreads<float>,
-                                           SGN_LDS_MAXBYTES / site_bytes);
+    int64_t tmax = p == SGN_PREC_F64 ? kStagedMaxThreads<double> : kStagedMaxThreads<float>;
+    if (max_threads > 0) tmax = std::min<int64_t>(tmax, max_threads);
+    if (max_sites > 0) tmax = std::min<int64_t>(tmax, max_sites);
+    const int64_t bmax = std::min<int64_t>(tmax, SGN_LDS_MAXBYTES / site_bytes);
     const int64_t Lx = lat.L[0], A = (int64_t)lat.L[0] * lat.L[1];
     const int64_t nplane = (int64_t)lat.L[2] * lat.L[3];
     int64_t B = 0;
@@ -664,17 +771,14 @@ StagedPlan staged_plan(const Lattice &lat, sgn_prec p)
 
 }  // namespace
 
+// An upper bound of the blocks of any stencil launch on lat, whatever shape is chosen (tuned or
+// default): every staged block holds at least 64 sites, the unstaged kernel 256, and the padding
+// sites [V, S) take blocks of at least 64 threads.  Sizes the per-block partial sums.
 int dslash_blocks(const Lattice &lat)
 {
-    const int64_t t = SGN_STENCIL_THREADS;
-    const int64_t valid = (lat.V + t - 1) / t;
-    const int64_t pad = lat.S > lat.V ? (lat.S - lat.V + t - 1) / t : 0;  // padding sites [V, S)
-    int n = (int)(valid + pad);
-    for (sgn_prec p : {SGN_PREC_F64, SGN_PREC_F32}) {
-        const StagedPlan pl = staged_plan(lat, p);
-        if (pl.ok) n = std::max(n, pl.nblk);
-    }
-    return n;
+    const int64_t valid = (lat.V + 63) / 64;
+    const int64_t pad = lat.S > lat.V ? (lat.S - lat.V + 63) / 64 : 0;
+    return (int)(valid + pad);
 }
 
 namespace {
@@ -684,15 +788,17 @@ struct PreparedStencil {
     StencilParams P{};
     StagedPlan pl;
     int nblk = 0;       // blocks of the launch (= partials written when dotting)
-    double bytes = 0.0;  // algorithmic bytes and flops
+    double bytes = 0.0;         // algorithmic bytes (links as nine entries) and flops
     double flops = 0.0;
+    double bytes_stored = 0.0;  // bytes in the stored format (two-row links where the lattice keeps them)
     bool epi = false, dot = false;
 };
 
+// max_threads > 0 caps the staged block (the register-link multi-RHS form)
 PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
-                                void *const *out, const Epilogue *ep)
+                                void *const *out, const Epilogue *ep, int max_threads = 0)
 {
-    if (nr < 1 || nr > kMaxRhs) throw Failure{SGN_ERR_INVALID, "stencil: 1..2 right-hand sides per launch"};
+    if (nr < 1 || nr > kMaxRhs) throw Failure{SGN_ERR_INVALID, "stencil: 1..16 right-hand sides per launch"};
     PreparedStencil ps;
     StencilParams &P = ps.P;
     P.V = (int)lat.V;
@@ -727,7 +833,8 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
         if (ep[r].w && !ep[r].partials) throw Failure{SGN_ERR_INVALID, "stencil dot without partial buffer"};
         ps.dot = ps.dot || ep[r].w != nullptr;
         ps.epi = ps.epi || ep[r].w != nullptr || ep[r].z != nullptr || ep[r].a != 1.0 || ep[r].in_scale != nullptr;
-        extra_bytes += (ep[r].z ? sb : 0.0) + (ep[r].w ? sb : 0.0);
+        // an epilogue operand counts once: a dot partner equal to z is not read again
+        extra_bytes += (ep[r].z ? sb : 0.0) + (ep[r].w && ep[r].w != ep[r].z ? sb : 0.0);
         extra_flops += (ep[r].z ? 96.0 : 0.0) + (ep[r].w ? 96.0 : 0.0) + 24.0;
     }
     {
@@ -745,13 +852,15 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
         }
     }
     // algorithmic bytes: every input and output spinor once, the 4 links of each
-    // site once (shared by the right-hand sides), plus the epilogue operands;
-    // 1368 flop per site and right-hand side for the stencil itself
+    // site once (shared by the right-hand sides) as nine complex entries, plus the
+    // epilogue operands; 1368 flop per site and right-hand side for the stencil itself
     P.link_ne = lat.link_ne;
-    const double lb = lat.link_ne * ((p == SGN_PREC_F64) ? 16.0 : (p == SGN_PREC_F32 ? 8.0 : 4.0));
-    ps.bytes = (2 * sb * nr + 4 * lb + extra_bytes) * lat.V;
+    const double eb = (p == SGN_PREC_F64) ? 16.0 : (p == SGN_PREC_F32 ? 8.0 : 4.0);
+    ps.bytes = (2 * sb * nr + 4 * 9 * eb + extra_bytes) * lat.V;
+    ps.bytes_stored = (2 * sb * nr + 4 * lat.link_ne * eb + extra_bytes) * lat.V;
     ps.flops = (1368.0 * nr + extra_flops) * lat.V;
-    ps.pl = nr == 1 ? staged_plan(lat, p) : StagedPlan{};
+    P.nrhs = nr;
+    ps.pl = staged_plan(lat, p, max_threads, lat.ctx->tuned_shape(lat.L, p, nr > 1).max_sites);
     if (ps.pl.ok) {
         P.blk_sites = ps.pl.B;
         P.nblk_sites = ps.pl.nblk_sites;
@@ -782,17 +891,30 @@ int kclass(sgn_prec p)
     return p == SGN_PREC_F64 ? SGN_K_STENCIL_F64 : (p == SGN_PREC_F32 ? SGN_K_STENCIL_F32 : SGN_K_STENCIL_H16);
 }
 
-template <typename R, typename LT>
-void launch_staged_batch(const StencilParams *dev, int count, int gx, int threads, size_t lds, bool epi, bool dot,
-                         hipStream_t s)
+template <typename R, typename LT, bool kRegs>
+void launch_staged_batch_r(const StencilParams *dev, int count, int gx, int threads, size_t lds, bool epi, bool dot,
+                           hipStream_t s)
 {
     dim3 g(gx, count), b(threads);
     if (dot)
-        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, true>), g, b, lds, s, dev);
+        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, true, kRegs>), g, b, lds, s, dev);
     else if (epi)
-        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, false>), g, b, lds, s, dev);
+        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, false, kRegs>), g, b, lds, s, dev);
     else
-        hipLaunchKernelGGL((stencil_staged_batch<R, LT, false, false>), g, b, lds, s, dev);
+        hipLaunchKernelGGL((stencil_staged_batch<R, LT, false, false, kRegs>), g, b, lds, s, dev);
+}
+
+template <typename R, typename LT>
+void launch_staged_batch(const StencilParams *dev, int count, int gx, int threads, size_t lds, bool epi, bool dot,
+                         bool regs, hipStream_t s)
+{
+    if constexpr (std::is_same<LT, __half2>::value) {
+        if (regs) {
+            launch_staged_batch_r<R, LT, true>(dev, count, gx, threads, lds, epi, dot, s);
+            return;
+        }
+    }
+    launch_staged_batch_r<R, LT, false>(dev, count, gx, threads, lds, epi, dot, s);
 }
 
 }  // namespace
@@ -801,6 +923,17 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
                         void *const *out, const Epilogue *ep, hipStream_t s)
 {
     const PreparedStencil ps = prepare_stencil(lat, p, nr, op, in, out, ep);
+    if (nr > 1 && ps.pl.ok) {
+        // several right-hand sides: the batched form, one group, parameters in device memory
+        // (the lattice's batch object: they are uploaded when they change, after the device has
+        // finished the launches that read the previous ones)
+        std::vector<StencilJob> jobs(nr);
+        for (int r = 0; r < nr; ++r) jobs[r] = StencilJob{&lat, op[r], in[r], out[r], ep[r]};
+        if (!lat.multi) lat.multi = std::make_shared<StencilBatch>();
+        lat.multi->prepare(jobs, p);
+        lat.multi->launch(s);
+        return ps.nblk;
+    }
     const int prof = lat.ctx->prof_start(s, kclass(p));
     switch (p) {
     case SGN_PREC_F64:
@@ -823,7 +956,7 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
         break;
     }
     SGN_HIP(hipGetLastError());
-    lat.ctx->prof_stop(prof, s, kclass(p), ps.bytes, ps.flops);
+    lat.ctx->prof_stop(prof, s, kclass(p), ps.bytes, ps.flops, false, ps.bytes_stored);
     return ps.nblk;
 }
 
@@ -841,13 +974,49 @@ void StencilBatch::prepare(const std::vector<StencilJob> &jobs, sgn_prec p)
     epi_ = dot_ = false;
     gx_ = threads_ = 0;
     lds_ = 0;
-    bytes_ = flops_ = 0.0;
-    std::vector<StencilParams> host(jobs.size());
+    bytes_ = flops_ = bytes_stored_ = 0.0;
+    // applications on the same lattice become one multi-RHS group (up to kMaxRhs right-hand
+    // sides sharing every link load); the groups are the launch's blockIdx.y
+    std::vector<std::vector<size_t>> groups;
     for (size_t k = 0; k < jobs.size(); ++k) {
-        const StencilJob &j = jobs[k];
-        const PreparedStencil ps = prepare_stencil(*j.lat, p, 1, &j.op, &j.in, &j.out, &j.ep);
-        host[k] = ps.P;
-        nblk_[k] = ps.nblk;
+        size_t g = 0;
+        for (; g < groups.size(); ++g)
+            if (jobs[groups[g][0]].lat == jobs[k].lat && (int)groups[g].size() < kMaxRhs) break;
+        if (g == groups.size()) groups.emplace_back();
+        groups[g].push_back(k);
+    }
+    // links in registers (FP16 two-row links, some group with several right-hand sides, and the
+    // environment does not ask for re-reads: SGN_MULTI_LINK_REGS=0)
+    regs_ = p == SGN_PREC_F32_H16;
+    bool multi = false;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        multi = multi || groups[g].size() > 1;
+        regs_ = regs_ && jobs[groups[g][0]].lat->link_ne == 6;
+    }
+    {
+        const char *e = std::getenv("SGN_MULTI_LINK_REGS");
+        const int tuned = groups.empty() ? -1 : jobs[groups[0][0]].lat->ctx->tuned_shape(jobs[groups[0][0]].lat->L, p, true).regs;
+        regs_ = regs_ && multi && !(e && e[0] == '0') && tuned != 0;
+    }
+    std::vector<StencilParams> host(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int nr = (int)groups[g].size();
+        std::vector<OpSpec> op(nr);
+        std::vector<const void *> in(nr);
+        std::vector<void *> out(nr);
+        std::vector<Epilogue> ep(nr);
+        for (int r = 0; r < nr; ++r) {
+            const StencilJob &j = jobs[groups[g][r]];
+            op[r] = j.op;
+            in[r] = j.in;
+            out[r] = j.out;
+            ep[r] = j.ep;
+        }
+        const Lattice &lat = *jobs[groups[g][0]].lat;
+        const PreparedStencil ps = prepare_stencil(lat, p, nr, op.data(), in.data(), out.data(), ep.data(),
+                                                   regs_ ? kRegsMaxThreads : 0);
+        host[g] = ps.P;
+        for (size_t k : groups[g]) nblk_[k] = ps.nblk;
         batched_ = batched_ && ps.pl.ok;
         epi_ = epi_ || ps.epi;
         dot_ = dot_ || ps.dot;
@@ -855,11 +1024,16 @@ void StencilBatch::prepare(const std::vector<StencilJob> &jobs, sgn_prec p)
         threads_ = std::max(threads_, ps.pl.threads);
         lds_ = std::max(lds_, ps.pl.lds);
         bytes_ += ps.bytes;
+        bytes_stored_ += ps.bytes_stored;
         flops_ += ps.flops;
     }
+    ngroups_ = (int)groups.size();
     gx_ = (gx_ + 7) / 8 * 8;
     if (!batched_) return;
     const size_t need = sizeof(StencilParams) * host.size();
+    // unchanged parameters stay on the device; new ones wait until no launch reads the old
+    if (need == uploaded_.size() && std::memcmp(uploaded_.data(), host.data(), need) == 0) return;
+    SGN_HIP(hipDeviceSynchronize());
     if (need > dev_bytes_) {
         if (dev_) SGN_HIP(hipFree(dev_));
         dev_ = nullptr;
@@ -868,6 +1042,7 @@ void StencilBatch::prepare(const std::vector<StencilJob> &jobs, sgn_prec p)
         dev_bytes_ = need;
     }
     SGN_HIP(hipMemcpy(dev_, host.data(), need, hipMemcpyHostToDevice));
+    uploaded_.assign(reinterpret_cast<const char *>(host.data()), reinterpret_cast<const char *>(host.data()) + need);
 }
 
 void StencilBatch::launch(hipStream_t s) const
@@ -880,14 +1055,14 @@ void StencilBatch::launch(hipStream_t s) const
     Context *ctx = jobs_[0].lat->ctx;
     const int prof = ctx->prof_start(s, kclass(prec_));
     const StencilParams *d = static_cast<const StencilParams *>(dev_);
-    const int cnt = (int)jobs_.size();
+    const int cnt = ngroups_;
     switch (prec_) {
-    case SGN_PREC_F64: launch_staged_batch<double, double2>(d, cnt, gx_, threads_, lds_, epi_, dot_, s); break;
-    case SGN_PREC_F32: launch_staged_batch<float, float2>(d, cnt, gx_, threads_, lds_, epi_, dot_, s); break;
-    default: launch_staged_batch<float, __half2>(d, cnt, gx_, threads_, lds_, epi_, dot_, s); break;
+    case SGN_PREC_F64: launch_staged_batch<double, double2>(d, cnt, gx_, threads_, lds_, epi_, dot_, false, s); break;
+    case SGN_PREC_F32: launch_staged_batch<float, float2>(d, cnt, gx_, threads_, lds_, epi_, dot_, regs_, s); break;
+    default: launch_staged_batch<float, __half2>(d, cnt, gx_, threads_, lds_, epi_, dot_, regs_, s); break;
     }
     SGN_HIP(hipGetLastError());
-    ctx->prof_stop(prof, s, kclass(prec_), bytes_, flops_);
+    ctx->prof_stop(prof, s, kclass(prec_), bytes_, flops_, false, bytes_stored_);
 }
 
 int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *in, void *out,
@@ -949,6 +1124,100 @@ extern "C" sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *i
                                        unsigned flags, void *stream)
 {
     return apply_common(lat, mu, in, out, p, flags, stream, true);
+}
+
+extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps, sgn_tune_candidate *out,
+                                   int max_out, int *n_out, void *stream)
+{
+    return guard([&] {
+        SGN_REQUIRE(l != nullptr, "sgn_autotune: null lattice");
+        SGN_REQUIRE(p == SGN_PREC_F64 || p == SGN_PREC_F32 || p == SGN_PREC_F32_H16, "sgn_autotune: unknown precision");
+        SGN_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, "sgn_autotune: nrhs must be 1..16");
+        SGN_REQUIRE(max_out >= 0 && (max_out == 0 || out != nullptr), "sgn_autotune: bad output array");
+        Lattice &lat = *as_lattice(l);
+        Context &ctx = *lat.ctx;
+        SGN_HIP(hipSetDevice(ctx.device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (reps <= 0) reps = 20;
+        const bool multi = nrhs > 1;
+        const std::vector<int> key = {lat.L[0], lat.L[1], lat.L[2], lat.L[3], (int)p, multi ? 1 : 0};
+        // candidate shapes: distinct block sizes of the staged plan under decreasing site caps, and
+        // for several right-hand sides with FP16 two-row links both link modes
+        struct Cand {
+            int cap, B, regs;
+            double us;
+        };
+        std::vector<Cand> cands;
+        const bool can_regs = multi && p == SGN_PREC_F32_H16 && lat.link_ne == 6;
+        for (int regs : can_regs ? std::vector<int>{1, 0} : std::vector<int>{-1}) {
+            std::vector<int> seen;
+            for (int cap : {0, 576, 432, 384, 288, 192, 96}) {
+                const StagedPlan pl = staged_plan(lat, p, regs == 1 ? kRegsMaxThreads : 0, cap);
+                const int B = pl.ok ? pl.B : 0;
+                if (std::find(seen.begin(), seen.end(), B) != seen.end()) continue;
+                seen.push_back(B);
+                cands.push_back({cap, B, regs, 0.0});
+            }
+        }
+        // fields: nrhs inputs (zero) and outputs in the internal layout
+        const size_t bytes = spinor_bytes(lat.S, p);
+        std::vector<void *> buf(2 * nrhs, nullptr);
+        struct Free {
+            std::vector<void *> &b;
+            ~Free()
+            {
+                for (void *q : b)
+                    if (q) (void)hipFree(q);
+            }
+        } freer{buf};
+        for (void *&q : buf) {
+            if (hipMalloc(&q, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "sgn_autotune: fields"};
+            SGN_HIP(hipMemsetAsync(q, 0, bytes, s));
+        }
+        std::vector<OpSpec> op(nrhs);
+        std::vector<Epilogue> ep(nrhs);
+        std::vector<const void *> in(nrhs);
+        std::vector<void *> outp(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            op[r].mu = 0.2;
+            in[r] = buf[r];
+            outp[r] = buf[nrhs + r];
+        }
+        hipEvent_t e0, e1;
+        SGN_HIP(hipEventCreate(&e0));
+        SGN_HIP(hipEventCreate(&e1));
+        const Context::TunedShape before = ctx.tuned_shape(lat.L, p, multi);
+        try {
+            for (Cand &c : cands) {
+                ctx.tuned[key] = {c.cap, c.regs};
+                for (int w = 0; w < 3; ++w) dslash_launch_multi(lat, p, nrhs, op.data(), in.data(), outp.data(), ep.data(), s);
+                SGN_HIP(hipEventRecord(e0, s));
+                for (int k = 0; k < reps; ++k)
+                    dslash_launch_multi(lat, p, nrhs, op.data(), in.data(), outp.data(), ep.data(), s);
+                SGN_HIP(hipEventRecord(e1, s));
+                SGN_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                SGN_HIP(hipEventElapsedTime(&ms, e0, e1));
+                c.us = 1e3 * ms / reps;
+            }
+        } catch (...) {
+            ctx.tuned[key] = before;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        const Cand *best = &cands[0];
+        for (const Cand &c : cands)
+            if (c.us < best->us) best = &c;
+        ctx.tuned[key] = {best->cap, best->regs};
+        SGN_HIP(hipDeviceSynchronize());
+        const int n = std::min<int>((int)cands.size(), max_out);
+        for (int k = 0; k < n; ++k)
+            out[k] = {cands[k].B, cands[k].regs < 0 ? 0 : cands[k].regs, cands[k].us, &cands[k] == best ? 1 : 0};
+        if (n_out) *n_out = (int)cands.size();
+    });
 }
 
 extern "C" sgn_status wilson_apply_multi(sgn_lattice l, int nrhs, const double *mu, const void *const *in,

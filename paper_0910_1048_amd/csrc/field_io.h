@@ -83,13 +83,55 @@ __device__ __forceinline__ void store_spinor(float4 *__restrict__ p, int S, int 
         st_off(p + (size_t)c * S, off, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i));
 }
 
+// non-temporal forms (streaming stores that do not keep the lines in L2)
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ void st_off_nt(void *__restrict__ base, uint32_t byte_off, T v)
+{
+    SGN_GLOBAL char *b = (SGN_GLOBAL char *)base;
+    __builtin_nontemporal_store(v, reinterpret_cast<SGN_GLOBAL T *>(b + byte_off));
+}
+
+__device__ __forceinline__ void store_spinor_nt(double2 *__restrict__ p, int S, int s, const cpx<double> v[12])
+{
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st_off_nt<nt_d2>(p + (size_t)c * S, off, nt_d2{v[c].r, v[c].i});
+}
+
+__device__ __forceinline__ void store_spinor_nt(float4 *__restrict__ p, int S, int s, const cpx<float> v[12])
+{
+    const uint32_t off = (uint32_t)s * 16u;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        st_off_nt<nt_f4>(p + (size_t)c * S, off, nt_f4{v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i});
+}
+
+// conj(a b - c d), written as one multiply and three fused multiply-adds per
+// real component (the compiler does not reassociate the plain expression)
+template <typename R>
+__device__ __forceinline__ cpx<R> conj_cross(cpx<R> a, cpx<R> b, cpx<R> c, cpx<R> d)
+{
+    R re = a.r * b.r;
+    re = fma(-a.i, b.i, re);
+    re = fma(-c.r, d.r, re);
+    re = fma(c.i, d.i, re);
+    R im = -(a.r * b.i);
+    im = fma(-a.i, b.r, im);
+    im = fma(c.r, d.i, im);
+    im = fma(c.i, d.r, im);
+    return {re, im};
+}
+
 // Third row of an SU(3) matrix from its first two: u2 = conj(u0 x u1).
 template <typename R>
 __device__ __forceinline__ void su3_third_row(cpx<R> u[9])
 {
-    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    u[6] = conj_cross(u[1], u[5], u[2], u[4]);
+    u[7] = conj_cross(u[2], u[3], u[0], u[5]);
+    u[8] = conj_cross(u[0], u[4], u[1], u[3]);
 }
 
 template <typename R>
@@ -109,6 +151,15 @@ __device__ __forceinline__ void link_entry(const __half2 *b, uint32_t off, cpx<R
 {
     float2 t = __half22float2(ld_off(b, off * 4u));
     u = {static_cast<R>(t.x), static_cast<R>(t.y)};
+}
+
+// one stored link entry as a complex number of the arithmetic precision
+template <typename R> __device__ __forceinline__ cpx<R> to_cpx(double2 v) { return {static_cast<R>(v.x), static_cast<R>(v.y)}; }
+template <typename R> __device__ __forceinline__ cpx<R> to_cpx(float2 v) { return {static_cast<R>(v.x), static_cast<R>(v.y)}; }
+template <typename R> __device__ __forceinline__ cpx<R> to_cpx(__half2 v)
+{
+    const float2 t = __half22float2(v);
+    return {static_cast<R>(t.x), static_cast<R>(t.y)};
 }
 
 // U_nu(x) at site s from the [4][ne][S] link array (ne = 6: two rows stored,

@@ -428,7 +428,7 @@ sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, c
                     } else {
                         unpack_spinor(lat, w, rcan, SGN_PREC_F64, s);
                     }
-                    deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s);
+                    deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s, false);
                     if (lo) {
                         pack_spinor(lat, t, w, SGN_PREC_F64, s);
                         convert_64_to_32(w, Vj(0), lat.S, s);
@@ -452,7 +452,7 @@ sgn_status restarted_arnoldi(sgn_lattice l, double mu, const void *b, void *x, c
                 } else {
                     unpack_spinor(lat, Vj(k), rcan, SGN_PREC_F64, s);
                 }
-                deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s);  // t = (I - P) v (canonical)
+                deflation_prologue(ctx, defl, nc, rcan, nullptr, t, nullptr, s, false);  // t = (I - P) v (canonical)
                 if (lo) {
                     pack_spinor(lat, t, w, SGN_PREC_F64, s);
                     convert_64_to_32(w, Vj(0), lat.S, s);

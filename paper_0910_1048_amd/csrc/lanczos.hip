@@ -246,35 +246,67 @@ struct PooledBasis {
 }  // namespace
 
 void deflation_prologue(Context &ctx, const sgn_deflation *defl, int64_t n, const void *b, void *x, void *r,
-                        void *rt, hipStream_t s)
+                        void *rt, hipStream_t s, bool check)
 {
     const size_t bytes = (size_t)n * 16;
     const int m = (defl && defl->m > 0) ? defl->m : 0;
-    if (r) SGN_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, s));
-    if (rt) SGN_HIP(hipMemcpyAsync(rt, b, bytes, hipMemcpyDeviceToDevice, s));
     if (m == 0) {
+        if (r) SGN_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, s));
+        if (rt) SGN_HIP(hipMemcpyAsync(rt, b, bytes, hipMemcpyDeviceToDevice, s));
         if (x) SGN_HIP(hipMemsetAsync(x, 0, bytes, s));
         return;
     }
     SGN_REQUIRE(defl->L && defl->R && defl->lambda, "deflation: null L, R or lambda");
+    SGN_REQUIRE(defl->L != defl->R, "deflation: L and R must be different arrays");
     double lmax = 0.0;
-    for (int i = 0; i < m; ++i) lmax = std::max(lmax, std::hypot(defl->lambda[2 * i], defl->lambda[2 * i + 1]));
-    std::vector<z64> sg(m);
+    for (int i = 0; i < m; ++i) {
+        const double re = defl->lambda[2 * i], im = defl->lambda[2 * i + 1];
+        SGN_REQUIRE(std::isfinite(re) && std::isfinite(im), "deflation: eigenvalue not finite");
+        lmax = std::max(lmax, std::hypot(re, im));
+    }
+    // scratch: c (2m: L^H b, R^H b), d (m: signs), v (m: probe), w (m: L^H R v),
+    // nl (m: ||l_i||^2), nu (1: ||R v||^2)
+    z64 *sc = static_cast<z64 *>(ctx.ensure_small(sizeof(z64) * (6 * (size_t)m + 1)));
+    z64 *c = sc, *d = sc + 2 * m, *v = sc + 3 * m, *w = sc + 4 * m, *nl = sc + 5 * m, *nu = sc + 6 * m;
+    std::vector<z64> host(2 * (size_t)m);  // signs, then the probe
     for (int i = 0; i < m; ++i) {
         const double re = defl->lambda[2 * i];
         if (!(std::abs(re) > 1e-12 * lmax)) throw Failure{SGN_ERR_IMAG_AXIS, "deflated eigenvalue on the imaginary axis"};
-        sg[i] = {re > 0 ? 1.0 : -1.0, 0.0};
+        host[i] = {re > 0 ? 1.0 : -1.0, 0.0};
+        host[m + i] = {std::cos(0.7 + 1.3 * i), std::sin(0.7 + 1.3 * i)};
     }
-    DevBuf c(sizeof(z64) * (2 * m)), d(sizeof(z64) * m);
-    SGN_HIP(hipMemcpyAsync(d.p, sg.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s));
-    deflate_dots(defl->L, m, b, n, c.as<z64>(), ctx, s);  // L^H b
-    if (x) deflate_combine(x, {0.0, 0.0}, {1.0, 0.0}, defl->R, m, c.as<z64>(), d.as<z64>(), n, s);
-    if (r) deflate_combine(r, {1.0, 0.0}, {-1.0, 0.0}, defl->R, m, c.as<z64>(), nullptr, n, s);
+    check = check && r != nullptr;
+    if (x || check) SGN_HIP(hipMemcpyAsync(d, host.data(), sizeof(z64) * 2 * m, hipMemcpyHostToDevice, s));
+    if (check) {
+        // L^H R = I (the oblique projector P = R L^H of the deflation section): probe it with v
+        deflate_combine(r, {0.0, 0.0}, {1.0, 0.0}, defl->R, m, v, nullptr, n, s);  // u = R v
+        deflate_dots(defl->L, m, r, n, w, ctx, s);                                 // L^H u
+        deflate_norms(defl->L, m, n, nl, ctx, s);
+        const int nb = norm2_partials(r, n, false, static_cast<z64 *>(ctx.ensure_partials((kMaxBlocks + 1) * sizeof(z64))), s);
+        finalize_sum(static_cast<z64 *>(ctx.partials), nb, nu, s);
+        std::vector<z64> got(2 * (size_t)m + 1);
+        SGN_HIP(hipMemcpyAsync(got.data(), w, sizeof(z64) * (2 * m + 1), hipMemcpyDeviceToHost, s));
+        SGN_HIP(hipStreamSynchronize(s));
+        const double un = std::sqrt(got[2 * m].r);
+        for (int i = 0; i < m; ++i) {
+            const z64 e = got[i] - host[m + i];
+            const double lim = kBiorthTol * std::sqrt(got[m + i].r) * un;
+            if (!(std::sqrt(norm2(e)) <= lim))
+                throw Failure{SGN_ERR_INVALID, "deflation: L^H R differs from the identity (row " + std::to_string(i) +
+                                                   ", |(L^H R v - v)_i| = " + std::to_string(std::sqrt(norm2(e))) + ")"};
+        }
+    } else if (x) {
+        SGN_HIP(hipStreamSynchronize(s));  // the host signs are uploaded
+    }
+    if (r) SGN_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, s));
+    if (rt) SGN_HIP(hipMemcpyAsync(rt, b, bytes, hipMemcpyDeviceToDevice, s));
+    deflate_dots(defl->L, m, b, n, c, ctx, s);  // L^H b
+    if (x) deflate_combine(x, {0.0, 0.0}, {1.0, 0.0}, defl->R, m, c, d, n, s);
+    if (r) deflate_combine(r, {1.0, 0.0}, {-1.0, 0.0}, defl->R, m, c, nullptr, n, s);
     if (rt) {
-        deflate_dots(defl->R, m, b, n, c.as<z64>() + m, ctx, s);  // R^H b
-        deflate_combine(rt, {1.0, 0.0}, {-1.0, 0.0}, defl->L, m, c.as<z64>() + m, nullptr, n, s);
+        deflate_dots(defl->R, m, b, n, c + m, ctx, s);  // R^H b
+        deflate_combine(rt, {1.0, 0.0}, {-1.0, 0.0}, defl->L, m, c + m, nullptr, n, s);
     }
-    SGN_HIP(hipStreamSynchronize(s));  // c, d are freed on return
 }
 
 namespace {

@@ -55,6 +55,20 @@ void *Context::ensure_arena(size_t bytes)
     return arena;
 }
 
+void *Context::ensure_small(size_t bytes)
+{
+    if (bytes > small_bytes) {
+        SGN_HIP(hipDeviceSynchronize());
+        if (small) SGN_HIP(hipFree(small));
+        small = nullptr;
+        small_bytes = 0;
+        bytes = std::max<size_t>(bytes, 4096);
+        if (hipMalloc(&small, bytes) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "deflation scratch"};
+        small_bytes = bytes;
+    }
+    return small;
+}
+
 void Lattice::ensure_stage(size_t bytes)
 {
     if (bytes <= stage_bytes) return;
@@ -235,6 +249,7 @@ extern "C" sgn_status sgn_finalize(sgn_handle h)
         if (c->partials) SGN_HIP(hipFree(c->partials));
         if (c->scalars) SGN_HIP(hipFree(c->scalars));
         if (c->arena) SGN_HIP(hipFree(c->arena));
+        if (c->small) SGN_HIP(hipFree(c->small));
         if (c->byte_counter) SGN_HIP(hipFree(c->byte_counter));
         for (auto &kv : c->basis_pools)
             for (void *b : kv.second) SGN_HIP(hipFree(b));
@@ -384,12 +399,14 @@ int Context::prof_start(hipStream_t s, int cls)
     return (int)prof_recs.size() - 1;
 }
 
-void Context::prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes)
+void Context::prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes,
+                        double bytes_stored)
 {
     if (rec < 0) return;
     ProfRec &r = prof_recs[rec];
     r.cls = cls;
     r.bytes = bytes;
+    r.bytes_stored = bytes_stored < 0.0 ? bytes : bytes_stored;
     r.flops = flops;
     r.device_bytes = device_bytes;
     SGN_HIP(hipEventRecord(r.stop, s));
@@ -403,6 +420,7 @@ void Context::prof_collect()
         SGN_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
         acc_ms[r.cls] += ms;
         acc_bytes[r.cls] += r.bytes;
+        acc_bytes_stored[r.cls] += r.bytes_stored;
         acc_flops[r.cls] += r.flops;
         acc_launches[r.cls] += 1;
         event_pool.push_back(r.start);
@@ -413,6 +431,7 @@ void Context::prof_collect()
         unsigned long long b = 0;
         SGN_HIP(hipMemcpy(&b, byte_counter, sizeof(b), hipMemcpyDeviceToHost));
         acc_bytes[SGN_K_SHIFT_UPDATE] += (double)b;
+        acc_bytes_stored[SGN_K_SHIFT_UPDATE] += (double)b;
         const unsigned long long z = 0;
         SGN_HIP(hipMemcpy(byte_counter, &z, sizeof(z), hipMemcpyHostToDevice));
     }
@@ -429,7 +448,7 @@ extern "C" sgn_status sgn_profile_enable(sgn_handle h, int enable)
         SGN_HIP(hipDeviceSynchronize());
         c->prof_collect();
         for (int k = 0; k < SGN_K_COUNT; ++k) {
-            c->acc_ms[k] = c->acc_bytes[k] = c->acc_flops[k] = 0.0;
+            c->acc_ms[k] = c->acc_bytes[k] = c->acc_flops[k] = c->acc_bytes_stored[k] = 0.0;
             c->acc_launches[k] = 0;
         }
         if (enable && !c->byte_counter) {
@@ -457,6 +476,7 @@ extern "C" sgn_status sgn_profile_read(sgn_handle h, sgn_kernel_profile *out)
             out[k].bytes = c->acc_bytes[k];
             out[k].flops = c->acc_flops[k];
             out[k].calls = c->prof_calls[k];
+            out[k].bytes_stored = c->acc_bytes_stored[k];
         }
     });
 }

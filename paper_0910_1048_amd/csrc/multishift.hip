@@ -1196,57 +1196,8 @@ double MultishiftBatch::shift_residual(MsProblem &p, int i, const void *xi, void
 // the iterations used.
 int MultishiftBatch::refine(MsProblem &p, int i, void *xi, DevMem &work, int *matvecs)
 {
-    using cd = std::complex<double>;
-    Lattice &lat = *p.lat;
-    const int64_t n = p.n;
-    char *w = work.as<char>();
-    void *r = w, *rh = w + p.b64, *pv = w + 2 * p.b64, *v = w + 3 * p.b64, *sv = w + 4 * p.b64,
-         *t = w + 5 * p.b64, *e = w + 6 * p.b64;
-    auto applyM = [&](const void *in, void *out) {
-        dslash_launch(lat, SGN_PREC_F64, p.opA, in, p.tmp.p, Epilogue{}, s_);
-        Epilogue ep;
-        ep.a = c2_;
-        ep.z = in;
-        ep.b = {-rf_.sigma[i], 0.0};
-        dslash_launch(lat, SGN_PREC_F64, p.opA, p.tmp.p, out, ep, s_);
-        *matvecs += 2;
-    };
-    auto dot = [&](const void *a, const void *b) {
-        const z64 d = dot_sync(*ctx_, a, b, n, false, s_);
-        return cd(d.r, d.i);
-    };
-    auto zz = [](cd a) { return z64{a.real(), a.imag()}; };
-    const double target = 0.5 * o_.tol * p.ynorm;
-    SGN_HIP(hipMemcpyAsync(r, p.q.p, p.b64, hipMemcpyDeviceToDevice, s_));
-    SGN_HIP(hipMemcpyAsync(rh, p.q.p, p.b64, hipMemcpyDeviceToDevice, s_));
-    SGN_HIP(hipMemcpyAsync(pv, p.q.p, p.b64, hipMemcpyDeviceToDevice, s_));
-    SGN_HIP(hipMemsetAsync(e, 0, p.b64, s_));
-    cd rho = dot(rh, r);
-    int it = 0;
-    while (it < maxiter_) {
-        applyM(pv, v);
-        const cd den = dot(rh, v);
-        if (std::abs(den) == 0.0 || std::abs(rho) == 0.0) break;
-        const cd alpha = rho / den;
-        SGN_HIP(hipMemcpyAsync(sv, r, p.b64, hipMemcpyDeviceToDevice, s_));
-        axpby64(zz(-alpha), v, {1.0, 0.0}, sv, n, s_);  // s = r - alpha v
-        applyM(sv, t);
-        const double tt = norm_sync(*ctx_, t, n, false, s_);
-        const cd omega = tt > 0.0 ? dot(t, sv) / (tt * tt) : cd(0.0);
-        axpby64(zz(alpha), pv, {1.0, 0.0}, e, n, s_);
-        axpby64(zz(omega), sv, {1.0, 0.0}, e, n, s_);
-        SGN_HIP(hipMemcpyAsync(r, sv, p.b64, hipMemcpyDeviceToDevice, s_));
-        axpby64(zz(-omega), t, {1.0, 0.0}, r, n, s_);  // r = s - omega t
-        ++it;
-        if (norm_sync(*ctx_, r, n, false, s_) <= target || omega == cd(0.0)) break;
-        const cd rho_new = dot(rh, r);
-        const cd beta = (rho_new / rho) * (alpha / omega);
-        rho = rho_new;
-        axpby64(zz(-omega), v, {1.0, 0.0}, pv, n, s_);  // p = r + beta (p - omega v)
-        axpby64({1.0, 0.0}, r, zz(beta), pv, n, s_);
-    }
-    axpby64({1.0, 0.0}, e, {1.0, 0.0}, xi, n, s_);
-    return it;
+    return refine_shift64(*p.lat, p.opA, c2_, rf_.sigma[i], p.q.p, xi, 0.5 * o_.tol * p.ynorm, maxiter_, work.p,
+                          p.tmp.p, s_, matvecs);
 }
 
 // x += sum_i omega_i x_i, outputs and statistics of one problem
@@ -1266,7 +1217,7 @@ void MultishiftBatch::finish(MsProblem &p)
             vres[i] = shift_residual(p, i, xi, p.q.p) / p.ynorm;
             extra_mv += 2;
             if (vres[i] > o_.tol) {
-                if (!work) work = std::make_unique<DevMem>(7 * p.b64);
+                if (!work) work = std::make_unique<DevMem>(6 * p.b64);
                 refine_its += refine(p, i, xi, *work, &extra_mv);
                 vres[i] = shift_residual(p, i, xi, p.q.p) / p.ynorm;
                 extra_mv += 2;

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -89,7 +90,7 @@ using z64 = cpx<double>;
 struct ProfRec {
     int cls;
     hipEvent_t start, stop;
-    double bytes, flops;
+    double bytes, flops, bytes_stored;
     bool device_bytes;  // bytes accumulated by the kernel itself into byte_counter
 };
 
@@ -103,13 +104,16 @@ struct Context {
     unsigned long long *byte_counter = nullptr;  // device, bytes reported by kernels
     double acc_ms[SGN_K_COUNT] = {};
     double acc_bytes[SGN_K_COUNT] = {};
+    double acc_bytes_stored[SGN_K_COUNT] = {};
     double acc_flops[SGN_K_COUNT] = {};
     long long acc_launches[SGN_K_COUNT] = {};
     // returns -1 when profiling is off or this launch of class cls is not sampled
     int prof_every = 1;
     long long prof_calls[SGN_K_COUNT] = {};
     int prof_start(hipStream_t s, int cls);
-    void prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes = false);
+    // bytes: algorithmic bytes (links as nine entries); bytes_stored: in the stored format (< 0: = bytes)
+    void prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes = false,
+                   double bytes_stored = -1.0);
     void prof_collect();
     // scratch device buffers owned by the context, grown on demand
     void *partials = nullptr;
@@ -122,11 +126,28 @@ struct Context {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     void *ensure_arena(size_t bytes);
+    // small device scratch of the deflation prologue (coefficients, probes), grown on demand
+    void *small = nullptr;
+    size_t small_bytes = 0;
+    void *ensure_small(size_t bytes);
     // stored Krylov vectors of the multishift solver, one pool per vector size,
     // kept between calls
     std::map<size_t, std::vector<void *>> basis_pools;
     // stream on which solver iterations are captured into HIP graphs
     hipStream_t capture_stream = nullptr;
+    // stencil launch shapes chosen by sgn_autotune, per {Lx, Ly, Lz, Lt, precision, multi-RHS}:
+    // the block's site cap (0: the default plan) and, for the multi-RHS form with FP16 links,
+    // whether the links are held in registers (-1: default)
+    struct TunedShape {
+        int max_sites = 0;
+        int regs = -1;
+    };
+    std::map<std::vector<int>, TunedShape> tuned;
+    TunedShape tuned_shape(const int L[4], sgn_prec p, bool multi) const
+    {
+        auto it = tuned.find({L[0], L[1], L[2], L[3], (int)p, multi ? 1 : 0});
+        return it == tuned.end() ? TunedShape{} : it->second;
+    }
 };
 
 struct Lattice {
@@ -147,6 +168,8 @@ struct Lattice {
     void *stage_in = nullptr, *stage_out = nullptr;
     size_t stage_bytes = 0;
     void ensure_stage(size_t bytes);
+    // parameters of multi-RHS launches on this lattice (wilson_apply_multi)
+    mutable std::shared_ptr<class StencilBatch> multi;
 };
 
 inline size_t spinor_bytes(int64_t S, sgn_prec p) { return (size_t)S * 12 * (p == SGN_PREC_F64 ? 16 : 8); }
@@ -183,7 +206,7 @@ struct Epilogue {
 
 // Launch the stencil on internal-layout fields.  Returns the number of blocks
 // (= number of partials written when ep.w is set).
-// nr (1 or 2) right-hand sides in one launch sharing every link load; each has
+// nr (1..16) right-hand sides in one launch sharing every link load; each has
 // its own operator (mu, gamma5 flags), input, output and epilogue.
 int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op, const void *const *in,
                         void *const *out, const Epilogue *ep, hipStream_t s);
@@ -201,9 +224,11 @@ struct StencilJob {
 };
 
 // Independent applications of one precision (own lattices, fields, epilogues)
-// launched together: one launch, blockIdx.y selecting the application, with
-// the parameters kept in device memory between launches.  Falls back to one
-// launch per application when some lattice has no staged block shape.
+// launched together: one launch, with the applications on one lattice grouped
+// into multi-RHS groups of up to 16 (one block walks all right-hand sides of its
+// group, sharing the link loads) and blockIdx.y selecting the group; the
+// parameters stay in device memory between launches.  Falls back to one launch
+// per application when some lattice has no staged block shape.
 class StencilBatch {
   public:
     StencilBatch() = default;
@@ -221,11 +246,23 @@ class StencilBatch {
     sgn_prec prec_ = SGN_PREC_F64;
     void *dev_ = nullptr;
     size_t dev_bytes_ = 0;
-    int gx_ = 0, threads_ = 0;
+    std::vector<char> uploaded_;  // the parameters now on the device
+    int gx_ = 0, threads_ = 0, ngroups_ = 0;
     size_t lds_ = 0;
-    bool batched_ = false, epi_ = false, dot_ = false;
-    double bytes_ = 0.0, flops_ = 0.0;
+    bool batched_ = false, epi_ = false, dot_ = false, regs_ = false;
+    double bytes_ = 0.0, flops_ = 0.0, bytes_stored_ = 0.0;
 };
+
+// Single shifted system (c^2 H^2 - sigma) x = y of the rational methods, FP64, internal layout
+// (12 S entries).  shift_residual64: out = y - (c^2 H^2 - sigma) x, returns ||out|| (tmp: one
+// intermediate field; synchronises).  refine_shift64: x += e with (c^2 H^2 - sigma) e = r by FP64
+// BiCGStab until ||r|| <= target or maxiter; r holds the true residual of x on entry and is
+// overwritten; work holds six fields; returns the iterations and adds the applications of H to
+// *matvecs.
+double shift_residual64(Lattice &lat, const OpSpec &op, double c2, double sigma, const void *y, const void *x,
+                        void *out, void *tmp, hipStream_t s);
+int refine_shift64(Lattice &lat, const OpSpec &op, double c2, double sigma, void *r, void *x, double target,
+                   int maxiter, void *work, void *tmp, hipStream_t s, int *matvecs);
 
 void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s);
 void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_prec p, hipStream_t s);

@@ -46,6 +46,8 @@ void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Co
                   bool f32 = false);
 void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
                      int64_t n, hipStream_t s, bool f32 = false);
+// out[i] = {||X_i||^2, 0} for the m complex128 vectors X_i (device)
+void deflate_norms(const void *X, int m, int64_t n, z64 *out_dev, Context &ctx, hipStream_t s);
 
 // Arnoldi orthogonalisation on a basis X of m vectors (same layout and precision as y):
 //   (gram_dots uses up to 2 m kGramBlocks partials)
@@ -59,8 +61,13 @@ int combine_norm(void *y, const void *X, int m, const z64 *c_dev, int64_t n, z64
 // LR-deflation prologue shared by the solvers (canonical complex128 vectors):
 // x = x_P = R sign(Lambda) L^H b, r = (I - R L^H) b and, if rt != nullptr, the
 // modified shadow vector rt = (I - L R^H) b.  Null x / r skip that output.
-// Synchronises the stream.
+// With check (and r given) the set is first tested for L^H R = I: r holds
+// u = R v for a fixed probe v of unit-modulus entries, and every entry of
+// L^H u - v must lie within kBiorthTol ||l_i|| ||u|| (SGN_ERR_INVALID otherwise).
+// Scratch comes from the context's small device buffer; the stream is
+// synchronised when host data is uploaded (x or check), not otherwise.
+constexpr double kBiorthTol = 1e-8;
 void deflation_prologue(Context &ctx, const sgn_deflation *defl, int64_t n, const void *b, void *x, void *r,
-                        void *rt, hipStream_t s);
+                        void *rt, hipStream_t s, bool check = true);
 
 }  // namespace sgn

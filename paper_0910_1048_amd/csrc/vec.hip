@@ -197,6 +197,21 @@ __global__ void __launch_bounds__(256) mdot2_kernel(const T *X, const T *y1, con
     }
 }
 
+// grid (nbx, m): partials[i * nbx + bx] = {sum |X_i|^2 over the block's slice, 0}
+template <typename T>
+__global__ void __launch_bounds__(256) mnorm_kernel(const T *X, int64_t n, z64 *partials)
+{
+    const int i = blockIdx.y;
+    double acc[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const T a = X[(int64_t)i * n + e];
+        acc[0] += (double)a.x * a.x + (double)a.y * a.y;
+    }
+    __shared__ double lds[4];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = {acc[0], 0.0};
+}
+
 __global__ void __launch_bounds__(256) mfinalize_kernel(const z64 *partials, int nbx, z64 *out)
 {
     const int i = blockIdx.x;
@@ -239,8 +254,11 @@ __global__ void mcombine_kernel(T *y, z64 alpha, z64 beta, const T *X, int m, co
             const T xv = X[(int64_t)i * n + e];
             acc = acc + z64{(double)xv.x, (double)xv.y} * ci;
         }
-        const T yv = y[e];
-        z64 r = alpha * z64{(double)yv.x, (double)yv.y} + beta * acc;
+        z64 r = beta * acc;
+        if (alpha.r != 0.0 || alpha.i != 0.0) {  // alpha = 0: y is write-only (it may hold anything)
+            const T yv = y[e];
+            r = r + alpha * z64{(double)yv.x, (double)yv.y};
+        }
         y[e] = mk2<T>(r.r, r.i);
     }
 }
@@ -421,6 +439,16 @@ void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Co
         hipLaunchKernelGGL(mdot_kernel<double2>, dim3(nbx, ng), dim3(256), 0, s, (const double2 *)X, (const double2 *)y,
                            n, m, part);
     hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, c_dev);
+    SGN_HIP(hipGetLastError());
+}
+
+void deflate_norms(const void *X, int m, int64_t n, z64 *out_dev, Context &ctx, hipStream_t s)
+{
+    if (m <= 0) return;
+    const int nbx = std::max(1, std::min(kDotBlocks, (int)((n + 255) / 256)));
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)m * nbx * sizeof(z64)));
+    hipLaunchKernelGGL(mnorm_kernel<double2>, dim3(nbx, m), dim3(256), 0, s, (const double2 *)X, n, part);
+    hipLaunchKernelGGL(mfinalize_kernel, dim3(m), dim3(256), 0, s, part, nbx, out_dev);
     SGN_HIP(hipGetLastError());
 }
 

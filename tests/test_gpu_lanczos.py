@@ -171,6 +171,23 @@ def test_two_pass_equals_one_pass(prec):
         assert e < 1e-14
 
 
+def test_two_pass_matches_oracle_and_dense():
+    """The two-pass form against the oracle's direct two-sided Lanczos (stored basis, its own
+    code) and the stored dense sign, at the converged k = 320 of the 4^4 case."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    b = synth.gaussian_source(dims, 0).ravel()
+    W = WilsonRef(U, dims, 0.2)
+    g = np.load(GOLD)
+    x2, s2 = _gpu_lanczos(lattice(U, dims), 0.3, b, 320, two_pass=True)
+    xo = krylov.lanczos_sign(lambda v: W.apply(v, 0.3), lambda v: W.apply_adj(v, 0.3), b, 320)
+    e_or, e_dense = _rel(x2, xo), _rel(x2, g["sign_b"])
+    print(f"two-pass k=320: vs oracle 2sL {e_or:.2e}, vs dense sign {e_dense:.2e}, {s2['matvecs']} matvecs",
+          flush=True)
+    assert e_or < 1e-9
+    assert e_dense < 1e-8
+
+
 @pytest.mark.parametrize("prec", [sgn.F64, sgn.F32])
 def test_adaptive_stop_equals_fixed_k(prec):
     """With an early stop the steps queued past the stopping check are discarded: the result
