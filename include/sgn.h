@@ -116,6 +116,22 @@ sgn_status wilson_apply(sgn_lattice lat, double mu, const void *in, void *out, s
 sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *in, void *out, sgn_prec p,
                             unsigned flags, void *stream);
 
+/* wilson_apply without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops or harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as wilson_apply; the
+ * canonical <-> internal staging of in and out uses one static device array of
+ * SGN_NOALLOC_MAX_BYTES bytes per GPU (held by every GPU the library runs on
+ * until the process ends) instead of per-lattice buffers, so a canonical-layout
+ * call needs 2 * sgn_spinor_bytes(lat, p) <= SGN_NOALLOC_MAX_BYTES (FP64: up to
+ * 65536 sites, e.g. 16^4; FP32: about twice that), else SGN_ERR_INVALID.  With
+ * SGN_INTERNAL_LAYOUT no staging is used and any lattice size is accepted.
+ * All calls on one GPU share that array and each leaves its fields there:
+ * calls that overlap in time on one GPU (unordered streams, several host
+ * threads) race and must be serialised by the caller. */
+#define SGN_NOALLOC_MAX_BYTES 25288704u
+sgn_status wilson_apply_noalloc(sgn_lattice lat, double mu, const void *in, void *out, sgn_prec p,
+                                unsigned flags, void *stream);
+
 /* out[i] = H_W(mu[i]) in[i] for i < nrhs on one gauge field (flags: SGN_NO_GAMMA5
  * as above; SGN_INTERNAL_LAYOUT is required).  Right-hand sides are processed in
  * groups of up to 16 (multi-RHS stencil): a block of sites applies the operator to

@@ -63,7 +63,7 @@ lib.sgn_spinor_bytes.argtypes = [_vp, C.c_int]
 lib.sgn_spinor_bytes.restype = C.c_size_t
 for _f in ("sgn_spinor_pack", "sgn_spinor_unpack"):
     getattr(lib, _f).argtypes = [_vp, _vp, _vp, C.c_int, _vp]
-for _f in ("wilson_apply", "wilson_apply_dag"):
+for _f in ("wilson_apply", "wilson_apply_dag", "wilson_apply_noalloc"):
     getattr(lib, _f).argtypes = [_vp, C.c_double, _vp, _vp, C.c_int, C.c_uint, _vp]
 
 
@@ -220,6 +220,14 @@ def wilson_apply(lat, mu, x, out, prec=F64, flags=0, stream=None):
     px = _field(lat, x, prec, flags, "wilson_apply: in")
     po = _field(lat, out, prec, flags, "wilson_apply: out")
     check(lib.wilson_apply(lat.h, float(mu), px, po, int(prec), C.c_uint(flags), _stream(stream)), "wilson_apply")
+
+
+def wilson_apply_noalloc(lat, mu, x, out, prec=F64, flags=0, stream=None):
+    """wilson_apply through the library's static staging array (no device allocation)."""
+    px = _field(lat, x, prec, flags, "wilson_apply_noalloc: in")
+    po = _field(lat, out, prec, flags, "wilson_apply_noalloc: out")
+    check(lib.wilson_apply_noalloc(lat.h, float(mu), px, po, int(prec), C.c_uint(flags), _stream(stream)),
+          "wilson_apply_noalloc")
 
 
 def wilson_apply_dag(lat, mu, x, out, prec=F64, flags=0, stream=None):

@@ -1073,6 +1073,35 @@ int dslash_launch(const Lattice &lat, sgn_prec p, const OpSpec &op, const void *
 
 }  // namespace sgn
 
+// ----------------------------------------------------------------------------- no-allocation scratch
+// Staging of the two fields of wilson_apply_noalloc: one file-scope device array, a copy of
+// which every GPU holds from the time the library's code is loaded on it until the process
+// ends.  Host code never passes the array's name (a host-side stand-in) to a kernel or copy:
+// noalloc_scratch() takes its address on each device once, with that device current, and
+// kernels receive that address.
+static __device__ __align__(256) unsigned char scratch[SGN_NOALLOC_MAX_BYTES];
+
+namespace sgn {
+
+void *noalloc_scratch(int device)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) return it->second;
+    int cur = -1;
+    SGN_HIP(hipGetDevice(&cur));
+    SGN_REQUIRE(cur == device, "no-allocation scratch: the device must be current");
+    void *ptr = nullptr;
+    SGN_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    SGN_REQUIRE(ptr != nullptr, "no-allocation scratch: no device address");
+    addr[device] = ptr;
+    return ptr;
+}
+
+}  // namespace sgn
+
 // ----------------------------------------------------------------------------- C ABI
 using namespace sgn;
 
@@ -1124,6 +1153,41 @@ extern "C" sgn_status wilson_apply_dag(sgn_lattice lat, double mu, const void *i
                                        unsigned flags, void *stream)
 {
     return apply_common(lat, mu, in, out, p, flags, stream, true);
+}
+
+extern "C" sgn_status wilson_apply_noalloc(sgn_lattice l, double mu, const void *in, void *out, sgn_prec p,
+                                           unsigned flags, void *stream)
+{
+    return guard([&] {
+        SGN_REQUIRE(l != nullptr && in != nullptr && out != nullptr, "wilson_apply_noalloc: null argument");
+        SGN_REQUIRE(in != out, "wilson_apply_noalloc: in and out must differ");
+        SGN_REQUIRE(std::isfinite(mu), "wilson_apply_noalloc: mu is not finite");
+        SGN_REQUIRE(p == SGN_PREC_F64 || p == SGN_PREC_F32 || p == SGN_PREC_F32_H16,
+                    "wilson_apply_noalloc: unknown precision");
+        Lattice &lat = *as_lattice(l);
+        SGN_HIP(hipSetDevice(lat.ctx->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        OpSpec op;
+        op.mu = mu;
+        op.g5_out = !(flags & SGN_NO_GAMMA5);
+        Epilogue ep;
+        if (flags & SGN_INTERNAL_LAYOUT) {  // no staging needed
+            dslash_launch(lat, p, op, in, out, ep, s);
+            return;
+        }
+        const size_t bytes = spinor_bytes(lat.S, p);
+        const size_t off = (bytes + 255) / 256 * 256;  // second field 256-byte aligned
+        if (off + bytes > (size_t)SGN_NOALLOC_MAX_BYTES)
+            throw Failure{SGN_ERR_INVALID, "wilson_apply_noalloc: the lattice needs " + std::to_string(off + bytes) +
+                                               " staging bytes, more than SGN_NOALLOC_MAX_BYTES = " +
+                                               std::to_string((size_t)SGN_NOALLOC_MAX_BYTES)};
+        SGN_REQUIRE(lat.ctx->noalloc != nullptr, "wilson_apply_noalloc: scratch address not set up");
+        char *stage_in = static_cast<char *>(lat.ctx->noalloc);
+        char *stage_out = stage_in + off;
+        pack_spinor(lat, in, stage_in, p, s);
+        dslash_launch(lat, p, op, stage_in, stage_out, ep, s);
+        unpack_spinor(lat, stage_out, out, p, s);
+    });
 }
 
 extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps, sgn_tune_candidate *out,

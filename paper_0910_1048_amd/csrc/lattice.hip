@@ -236,6 +236,12 @@ extern "C" sgn_status sgn_init(sgn_handle *h, int device)
         hipDeviceProp_t prop;
         SGN_HIP(hipGetDeviceProperties(&prop, device));
         c->num_cu = prop.multiProcessorCount;
+        try {
+            c->noalloc = noalloc_scratch(device);
+        } catch (...) {
+            delete c;
+            throw;
+        }
         *h = reinterpret_cast<sgn_handle>(c);
     });
 }

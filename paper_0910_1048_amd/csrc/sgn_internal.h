@@ -135,6 +135,8 @@ struct Context {
     std::map<size_t, std::vector<void *>> basis_pools;
     // stream on which solver iterations are captured into HIP graphs
     hipStream_t capture_stream = nullptr;
+    // this device's address of the static staging array of wilson_apply_noalloc
+    void *noalloc = nullptr;
     // stencil launch shapes chosen by sgn_autotune, per {Lx, Ly, Lz, Lt, precision, multi-RHS}:
     // the block's site cap (0: the default plan) and, for the multi-RHS form with FP16 links,
     // whether the links are held in registers (-1: default)
@@ -265,6 +267,9 @@ int refine_shift64(Lattice &lat, const OpSpec &op, double c2, double sigma, void
                    int maxiter, void *work, void *tmp, hipStream_t s, int *matvecs);
 
 void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s);
+// device address of wilson_apply_noalloc's static staging array on `device` (must be current);
+// taken once per device
+void *noalloc_scratch(int device);
 void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_prec p, hipStream_t s);
 
 inline Lattice *as_lattice(sgn_lattice l) { return reinterpret_cast<Lattice *>(l); }
