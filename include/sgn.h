@@ -446,8 +446,11 @@ sgn_status multishift_solve(const sgn_problem *pb, int nprob, const sgn_rational
  * multishift_solve, and x = x_P + sum_i omega_i x_i formed from the checked x_i (one lift and
  * two FP64 stencil applications per shift; SGN_ERR_NOT_CONVERGED if a system stays above tol).
  * stats: iterations, matvecs, reliable_updates, refine_iterations, shift_residual (collinear
- * estimates, or with verify the FP64 residuals), residual.  Problems run
- * one after another.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter
+ * estimates, or with verify the FP64 residuals), residual.  Several problems (stored-basis form)
+ * run in lockstep: one launch per step of the iteration for all of them (their stencils grouped by
+ * lattice into multi-RHS launches, the vector updates and scalar steps over every problem at once,
+ * per precision phase), a chunk of o->poll iterations captured once as a HIP graph; each problem
+ * has its own reliable updates, precision switches and convergence.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter
  * (x holds the last iterate), SGN_ERR_BREAKDOWN if r^^H r or r^^H v vanishes. */
 sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                                sgn_stats *stats, void *stream);

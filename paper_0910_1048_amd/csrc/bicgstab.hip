@@ -494,7 +494,7 @@ __device__ __forceinline__ void stz(float2 *p, int64_t e, z64 v)
 }
 
 // alpha = rho / r^^H v from the dotting stencil's partials; the BiCG factors zeta_next
-__global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *part, int nb)
+__device__ __forceinline__ void bs_alpha_kernel_body(BsState *S, const z64 *part, int nb)
 {
     if (S->h.done) return;
     double re = 0.0, im = 0.0;
@@ -531,12 +531,15 @@ __global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *pa
         S->zeta_next[i] = bs_div(z * zp * ap, ap * one_tau * zp + al * bp * (zp - z));
     }
 }
+__global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *part, int nb)
+{
+    bs_alpha_kernel_body(S, part, nb);
+}
 
 // s = r_k - alpha v (r_k read from its slot), into the work vector and the slot of iteration k
 template <typename R>
-__global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, void *const *rslots,
-                                                     const typename BsVec<R>::t *v, typename BsVec<R>::t *s,
-                                                     void *const *sslots, int64_t n)
+__device__ __forceinline__ void bs_sub_stored_body(const BsState *S, void *const *rslots, const typename BsVec<R>::t *v,
+                              typename BsVec<R>::t *s, void *const *sslots, int64_t n)
 {
     using T = typename BsVec<R>::t;
     if (S->h.done) return;
@@ -549,10 +552,16 @@ __global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, void *con
         stz(slot, e, sv);
     }
 }
+template <typename R>
+__global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, void *const *rslots, const typename BsVec<R>::t *v,
+                              typename BsVec<R>::t *s, void *const *sslots, int64_t n)
+{
+    bs_sub_stored_body<R>(S, rslots, v, s, sslots, n);
+}
 
 // omega = t^H s / t^H t (0 when t = 0: s was the exact residual 0), from the partials
 // {s^H t, ||t||^2} per block of the stencil that produced t
-__global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *part, int nb)
+__device__ __forceinline__ void bs_omega_kernel_body(BsState *S, const z64 *part, int nb)
 {
     if (S->h.done) return;
     double a = 0.0, b = 0.0, c = 0.0;
@@ -566,13 +575,16 @@ __global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *pa
     block_sum<3>(v, lds);
     if (threadIdx.x == 0) S->h.omega = v[2] > 0.0 ? z64{v[0] / v[2], -v[1] / v[2]} : z64{0.0, 0.0};
 }
+__global__ void __launch_bounds__(256) bs_omega_kernel(BsState *S, const z64 *part, int nb)
+{
+    bs_omega_kernel_body(S, part, nb);
+}
 
 // r' = s - omega t into the slot of iteration k + 1 (the residual lives only there);
 // partials of r^^H r' and ||r'||^2 (of the stored values)
 template <typename R>
-__global__ void __launch_bounds__(256) bs_res_stored(const BsState *S, const typename BsVec<R>::t *s,
-                                                     const typename BsVec<R>::t *t, const typename BsVec<R>::t *rh,
-                                                     void *const *rslots, int64_t n, z64 *part)
+__device__ __forceinline__ void bs_res_stored_body(const BsState *S, const typename BsVec<R>::t *s, const typename BsVec<R>::t *t,
+                              const typename BsVec<R>::t *rh, void *const *rslots, int64_t n, z64 *part)
 {
     using T = typename BsVec<R>::t;
     if (S->h.done) return;
@@ -596,9 +608,15 @@ __global__ void __launch_bounds__(256) bs_res_stored(const BsState *S, const typ
         part[2 * blockIdx.x + 1] = {v[2], 0.0};
     }
 }
+template <typename R>
+__global__ void __launch_bounds__(256) bs_res_stored(const BsState *S, const typename BsVec<R>::t *s, const typename BsVec<R>::t *t,
+                              const typename BsVec<R>::t *rh, void *const *rslots, int64_t n, z64 *part)
+{
+    bs_res_stored_body<R>(S, s, t, rh, rslots, n, part);
+}
 
 // beta, the history entry, the shifted residual estimates and the control flags
-__global__ void __launch_bounds__(256) bs_beta_kernel(BsState *S, const z64 *part, int nb, BsHist *hist, int cap)
+__device__ __forceinline__ void bs_beta_kernel_body(BsState *S, const z64 *part, int nb, BsHist *hist, int cap)
 {
     if (S->h.done) {
         if (threadIdx.x == 0) S->h.go = 0;
@@ -669,11 +687,15 @@ __global__ void __launch_bounds__(256) bs_beta_kernel(BsState *S, const z64 *par
         if (S->h.iter >= S->h.maxiter) S->h.done = 1;
     }
 }
+__global__ void __launch_bounds__(256) bs_beta_kernel(BsState *S, const z64 *part, int nb, BsHist *hist, int cap)
+{
+    bs_beta_kernel_body(S, part, nb, hist, cap);
+}
 
 // the seed: x += alpha p + omega s (x in FP64), p = r' + beta (p - omega v), r' read from its
 // slot (the iteration counter was advanced by the beta step)
-__global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, const double2 *v, void *const *rslots,
-                                               const double2 *s, double2 *x, int64_t n)
+__device__ __forceinline__ void bs_xp64_body(const BsState *S, double2 *p, const double2 *v, void *const *rslots, const double2 *s,
+                              double2 *x, int64_t n)
 {
     if (!S->h.go || S->h.breakdown) return;
     const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
@@ -684,11 +706,16 @@ __global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, con
         stz(p, e, ldz(r, e) + be * (pv - om * ldz(v, e)));
     }
 }
+__global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, const double2 *v, void *const *rslots, const double2 *s,
+                              double2 *x, int64_t n)
+{
+    bs_xp64_body(S, p, v, rslots, s, x, n);
+}
 
 // FP32 phase: p, v, r', s in the [6][S] float4 layout (chunk c holds components 2c, 2c+1), x in
 // FP64 [12][S] (FP32 increments of x lose too much of the seed solution's accuracy here)
-__global__ void __launch_bounds__(256) bs_xp32(const BsState *S, float4 *p, const float4 *v, void *const *rslots,
-                                               const float4 *s, double2 *x, int Sst)
+__device__ __forceinline__ void bs_xp32_body(const BsState *S, float4 *p, const float4 *v, void *const *rslots, const float4 *s,
+                              double2 *x, int Sst)
 {
     if (!S->h.go || S->h.breakdown) return;
     const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
@@ -705,6 +732,11 @@ __global__ void __launch_bounds__(256) bs_xp32(const BsState *S, float4 *p, cons
         const z64 q1 = z64{r4.z, r4.w} + be * (p1 - om * z64{v4.z, v4.w});
         p[f] = make_float4((float)q0.r, (float)q0.i, (float)q1.r, (float)q1.i);
     }
+}
+__global__ void __launch_bounds__(256) bs_xp32(const BsState *S, float4 *p, const float4 *v, void *const *rslots, const float4 *s,
+                              double2 *x, int Sst)
+{
+    bs_xp32_body(S, p, v, rslots, s, x, Sst);
 }
 
 // out (+)= sum_j coef_j slot_j (FP64 or FP32 slots; out in the FP64 layout)
@@ -757,10 +789,80 @@ __global__ void __launch_bounds__(256) bs_addto64(const double2 *y, double2 *q, 
         stz(q, e, ldz(y, e) + ldz(q, e));
 }
 
+// Lockstep batches: one descriptor per problem (device memory), the vectors in the precision of
+// the problem's current phase; blockIdx.y (vector kernels) or blockIdx.x (the one-block scalar
+// kernels) selects the problem.
+struct BsDesc {
+    BsState *S;
+    void *const *rtab;
+    void *const *stab;
+    void *p, *v, *sv, *t, *rh;
+    double2 *x64;
+    z64 *spart, *vpart;
+    BsHist *hist;
+    int64_t n;   // complex entries (12 S)
+    int Sst;
+    int nb_s;    // blocks (partials) of the stencil that forms v, and of the one that forms t
+    int nb_v;
+    int cap;     // history capacity (maxiter)
+};
+
+__global__ void __launch_bounds__(256) bs_alpha_batch(const BsDesc *d)
+{
+    const BsDesc &D = d[blockIdx.x];
+    bs_alpha_kernel_body(D.S, D.spart, D.nb_s);
+}
+__global__ void __launch_bounds__(256) bs_omega_batch(const BsDesc *d)
+{
+    const BsDesc &D = d[blockIdx.x];
+    bs_omega_kernel_body(D.S, D.vpart, D.nb_v);
+}
+// nb: the grid width of the residual kernel that wrote the partials
+__global__ void __launch_bounds__(256) bs_beta_batch(const BsDesc *d, int nb)
+{
+    const BsDesc &D = d[blockIdx.x];
+    bs_beta_kernel_body(D.S, D.vpart, nb, D.hist, D.cap);
+}
+template <typename R>
+__global__ void __launch_bounds__(256) bs_sub_batch(const BsDesc *d)
+{
+    using T = typename BsVec<R>::t;
+    const BsDesc &D = d[blockIdx.y];
+    bs_sub_stored_body<R>(D.S, D.rtab, (const T *)D.v, (T *)D.sv, D.stab, D.n);
+}
+template <typename R>
+__global__ void __launch_bounds__(256) bs_res_batch(const BsDesc *d)
+{
+    using T = typename BsVec<R>::t;
+    const BsDesc &D = d[blockIdx.y];
+    bs_res_stored_body<R>(D.S, (const T *)D.sv, (const T *)D.t, (const T *)D.rh, D.rtab, D.n, D.vpart);
+}
+__global__ void __launch_bounds__(256) bs_xp64_batch(const BsDesc *d)
+{
+    const BsDesc &D = d[blockIdx.y];
+    bs_xp64_body(D.S, (double2 *)D.p, (const double2 *)D.v, D.rtab, (const double2 *)D.sv, D.x64, D.n);
+}
+__global__ void __launch_bounds__(256) bs_xp32_batch(const BsDesc *d)
+{
+    const BsDesc &D = d[blockIdx.y];
+    bs_xp32_body(D.S, (float4 *)D.p, (const float4 *)D.v, D.rtab, (const float4 *)D.sv, D.x64, D.Sst);
+}
+
+// Stored-basis slots handed out from the context's per-size pools; shared by the problems of a
+// lockstep batch (each takes the next unused buffers) together with one byte budget.
+struct BsSlotPools {
+    std::map<size_t, size_t> next;  // next unused buffer of each per-size pool
+    double budget = 0.0, used = 0.0;
+};
+
 class BsStored {
+    friend class BsBatch;
+
   public:
-    BsStored(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s)
-        : pb_(pb), rf_(rf), o_(o), s_(s), lat_(*as_lattice(pb.lat)), ctx_(*lat_.ctx)
+    BsStored(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s,
+             BsSlotPools *pools = nullptr)
+        : pb_(pb), rf_(rf), o_(o), s_(s), lat_(*as_lattice(pb.lat)), ctx_(*lat_.ctx),
+          pools_(pools ? pools : &own_pools_)
     {
     }
     ~BsStored()
@@ -770,6 +872,15 @@ class BsStored {
     sgn_status run(sgn_stats *stp);
 
   private:
+    // the steps of run(): sizes, workspace bytes, setup in a given workspace (false: y = 0, the
+    // result x_P is already written), the host's reaction to the device flags after a chunk of
+    // iterations (true: stop), and the combination of the result
+    void init_sizes();
+    size_t ws_bytes() const;
+    bool setup(char *ws, sgn_stats *stp);
+    bool poll(BsHead &h);
+    sgn_status finish(sgn_stats *stp);
+    void note_launched(int count);
     const sgn_problem &pb_;
     const sgn_rational &rf_;
     const sgn_ms_opts &o_;
@@ -793,10 +904,17 @@ class BsStored {
     void **rtab_ = nullptr, **stab_ = nullptr;  // device slot tables (r_k, s_k)
     std::vector<void *> rslots_, sslots_;
     std::vector<char> rf32_, sf32_;
-    std::map<size_t, size_t> pool_next_;  // next unused buffer of each per-size pool
-    double slot_budget_ = 0.0, slot_bytes_ = 0.0;  // stored-basis budget and use, bytes
+    BsSlotPools own_pools_;
+    BsSlotPools *pools_;
     int phase_ = 0, launched_ = 0, reliable_ = 0;
     hipGraphExec_t gexec_ = nullptr;
+    // state of run() between its steps
+    std::chrono::steady_clock::time_point t_start_, t_kry_;
+    double ynorm_ = 0.0;
+    std::vector<double> tau_;
+    sgn_status result_ = SGN_OK;
+    BsHead head_{};
+    bool done_ = false;
 
     bool lo() const { return phase_ >= 1; }
     sgn_prec sprec() const { return phase_ == 0 ? SGN_PREC_F64 : (phase_ == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16); }
@@ -812,10 +930,10 @@ class BsStored {
 // a slot buffer of the given size (FP64 or FP32 vector) from the context's pools
 void *BsStored::take_slot(size_t bytes)
 {
-    if (slot_bytes_ + (double)bytes > slot_budget_)
+    if (pools_->used + (double)bytes > pools_->budget)
         throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: stored basis exceeds its budget (basis_slots)"};
     auto &pool = ctx_.basis_pools[bytes];
-    size_t &next = pool_next_[bytes];
+    size_t &next = pools_->next[bytes];
     if (next == pool.size()) {
         void *b = nullptr;
         if (hipMalloc(&b, bytes) != hipSuccess) {
@@ -824,7 +942,7 @@ void *BsStored::take_slot(size_t bytes)
         }
         pool.push_back(b);
     }
-    slot_bytes_ += (double)bytes;
+    pools_->used += (double)bytes;
     return pool[next++];
 }
 
@@ -926,6 +1044,11 @@ void BsStored::iterate(int count)
     } else {
         for (int it = 0; it < count; ++it) launch_iteration(s_);
     }
+    note_launched(count);
+}
+
+void BsStored::note_launched(int count)
+{
     for (int it = 0; it < count; ++it) {  // slot precision of the iterations just launched
         const int k = launched_ + it;
         if ((int)sf32_.size() <= k) sf32_.resize(k + 1, 0);
@@ -1015,32 +1138,41 @@ void BsStored::lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs,
     SGN_HIP(hipStreamSynchronize(s_));  // before the coefficient buffers are freed
 }
 
-sgn_status BsStored::run(sgn_stats *stp)
+void BsStored::init_sizes()
 {
-    const auto t_start = std::chrono::steady_clock::now();
-    SGN_HIP(hipSetDevice(ctx_.device));
     ns_ = rf_.s;
     Sst_ = lat_.S;
     n_ = 12 * lat_.S;
     nc_ = 12 * lat_.V;
     b64_ = (size_t)n_ * 16;
     b32_ = (size_t)n_ * 8;
-    const size_t c64 = (size_t)nc_ * 16;
     nvb_ = vec_blocks(n_);
     nst_ = dslash_blocks(lat_);
     maxiter_ = o_.maxiter > 0 ? o_.maxiter : 10000;
     poll_ = o_.poll > 0 ? o_.poll : 4;
-    const bool mixed = o_.prec != SGN_PREC_F64;
     for (int i = 1; i < ns_; ++i)
         if (std::abs(rf_.sigma[i]) < std::abs(rf_.sigma[seed_])) seed_ = i;
     s0_ = rf_.sigma[seed_];
     c2_ = rf_.c * rf_.c;
-    // workspace
-    // partials: the dotting stencils' (nst_ blocks, two per block for the second one) and the vector kernels'
+}
+
+// partials: the dotting stencils' (nst_ blocks, two per block for the second one) and the vector kernels'
+size_t BsStored::ws_bytes() const
+{
+    const bool mixed = o_.prec != SGN_PREC_F64;
     const size_t nvp = 2 * (size_t)std::max(nst_, kMaxBlocks);
-    const size_t scal = sizeof(z64) * ((size_t)nst_ + nvp) + sizeof(BsState) +
-                        sizeof(BsHist) * (size_t)maxiter_ + 2 * sizeof(void *) * ((size_t)maxiter_ + poll_ + 4);
-    char *a = static_cast<char *>(ctx_.ensure_arena(8 * b64_ + (mixed ? 7 * b32_ : 0) + c64 + scal + 256));
+    const size_t scal = sizeof(z64) * ((size_t)nst_ + nvp) + sizeof(BsState) + sizeof(BsHist) * (size_t)maxiter_ +
+                        2 * sizeof(void *) * ((size_t)maxiter_ + poll_ + 4);
+    return (8 * b64_ + (mixed ? 7 * b32_ : 0) + (size_t)nc_ * 16 + scal + 512 + 255) / 256 * 256;
+}
+
+bool BsStored::setup(char *a, sgn_stats *stp)
+{
+    t_start_ = std::chrono::steady_clock::now();
+    SGN_HIP(hipSetDevice(ctx_.device));
+    const bool mixed = o_.prec != SGN_PREC_F64;
+    const size_t c64 = (size_t)nc_ * 16;
+    const size_t nvp = 2 * (size_t)std::max(nst_, kMaxBlocks);
     char *q = a;
     for (char **v : {&y_, &rh64_, &s64_, &v64_, &t64_, &tmp64_, &p64_, &x64_}) {
         *v = q;
@@ -1061,16 +1193,14 @@ sgn_status BsStored::run(sgn_stats *stp)
     rtab_ = reinterpret_cast<void **>(hist_ + maxiter_);
     stab_ = rtab_ + maxiter_ + poll_ + 2;
     // stored-basis budget: basis_slots > 0 FP64-sized vectors, else up to half of the free device
-    // memory (counting the pooled buffers as free)
-    {
+    // memory (counting the pooled buffers as free); a batch sets it once for all its problems
+    if (pools_ == &own_pools_) {
         size_t fr = 0, tot = 0;
         SGN_HIP(hipMemGetInfo(&fr, &tot));
         double held = 0.0;
         for (auto &kv : ctx_.basis_pools) held += (double)kv.first * kv.second.size();
-        slot_budget_ = o_.basis_slots > 0 ? (double)o_.basis_slots * b64_ : 0.5 * ((double)fr + held);
+        pools_->budget = o_.basis_slots > 0 ? (double)o_.basis_slots * b64_ : 0.5 * ((double)fr + held);
     }
-    sgn_stats st{};
-    st.nshift = ns_;
     OpSpec op;
     op.mu = pb_.mu;
     // x = x_P, y = c H (I - P) b
@@ -1081,12 +1211,16 @@ sgn_status BsStored::run(sgn_stats *stp)
         ep.a = rf_.c;
         dslash_launch(lat_, SGN_PREC_F64, op, tmp64_, y_, ep, s_);
     }
-    const double ynorm = norm_sync(ctx_, y_, n_, false, s_);
-    SGN_REQUIRE(std::isfinite(ynorm), "multishift_bicgstab: b contains NaN or Inf");
-    if (ynorm == 0.0) {
+    ynorm_ = norm_sync(ctx_, y_, n_, false, s_);
+    SGN_REQUIRE(std::isfinite(ynorm_), "multishift_bicgstab: b contains NaN or Inf");
+    if (ynorm_ == 0.0) {
         SGN_HIP(hipStreamSynchronize(s_));
-        if (stp) *stp = st;
-        return SGN_OK;
+        if (stp) {
+            *stp = sgn_stats{};
+            stp->nshift = ns_;
+        }
+        done_ = true;
+        return false;
     }
     ensure_slots(poll_);
     rf32_.assign(1, 0);
@@ -1095,11 +1229,11 @@ sgn_status BsStored::run(sgn_stats *stp)
     hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)x64_, make_double2(0.0, 0.0),
                        n_);
     SGN_HIP(hipGetLastError());
-    std::vector<double> tau(ns_);
+    tau_.assign(ns_, 0.0);
     BsState h0{};
-    h0.h.rho = {ynorm * ynorm, 0.0};
+    h0.h.rho = {ynorm_ * ynorm_, 0.0};
     h0.h.alpha_prev = {1.0, 0.0};
-    h0.h.rnorm = h0.h.rmax = h0.h.ynorm = ynorm;
+    h0.h.rnorm = h0.h.rmax = h0.h.ynorm = ynorm_;
     h0.h.tol = o_.tol;
     h0.h.delta = o_.delta > 0 ? o_.delta : 0.1;
     h0.h.theta32 = mixed ? (o_.theta32 > 0 ? o_.theta32 : 1e-3) : 0.0;
@@ -1109,46 +1243,77 @@ sgn_status BsStored::run(sgn_stats *stp)
     h0.h.ns = ns_;
     h0.h.seed = seed_;
     for (int i = 0; i < ns_; ++i) {
-        tau[i] = s0_ - rf_.sigma[i];
+        tau_[i] = s0_ - rf_.sigma[i];
         h0.zeta[i] = h0.zeta_prev[i] = h0.zeta_next[i] = h0.pi[i] = {1.0, 0.0};
-        h0.tau[i] = tau[i];
+        h0.tau[i] = tau_[i];
         h0.act[i] = 1;
     }
     SGN_HIP(hipMemcpyAsync(S_, &h0, sizeof(BsState), hipMemcpyHostToDevice, s_));
     SGN_HIP(hipStreamSynchronize(s_));
-    const auto t_kry = std::chrono::steady_clock::now();
-    sgn_status result = SGN_OK;
-    BsHead h{};
+    t_kry_ = std::chrono::steady_clock::now();
+    return true;
+}
+
+// h: the device head just read after a chunk of iterations; a reliable update or a precision
+// switch it asks for is done here (and the head written back)
+bool BsStored::poll(BsHead &h)
+{
+    head_ = h;
+    if (h.breakdown) {
+        result_ = SGN_ERR_BREAKDOWN;
+        done_ = true;
+        return true;
+    }
+    if (h.done) {
+        if (h.iter >= maxiter_) {
+            // converged in the last iteration or not at all: decided from the estimates in finish()
+            result_ = SGN_ERR_NOT_CONVERGED;
+        }
+        done_ = true;
+        return true;
+    }
+    bool changed = false;
+    if (h.reliable) {
+        reliable_update(h);
+        changed = true;
+    }
+    if (h.want_phase) {
+        switch_phase(h, h.want_phase);
+        changed = true;
+    }
+    if (changed) {
+        SGN_HIP(hipMemcpyAsync(&S_->h, &h, sizeof(BsHead), hipMemcpyHostToDevice, s_));
+        SGN_HIP(hipStreamSynchronize(s_));
+    }
+    head_ = h;
+    return false;
+}
+
+sgn_status BsStored::run(sgn_stats *stp)
+{
+    init_sizes();
+    if (!setup(static_cast<char *>(ctx_.ensure_arena(ws_bytes())), stp)) return SGN_OK;
     for (;;) {
         ensure_slots(launched_ + poll_);
         iterate(poll_);
+        BsHead h{};
         SGN_HIP(hipMemcpyAsync(&h, &S_->h, sizeof(BsHead), hipMemcpyDeviceToHost, s_));
         SGN_HIP(hipStreamSynchronize(s_));
-        if (h.breakdown) {
-            result = SGN_ERR_BREAKDOWN;
-            break;
-        }
-        if (h.done) {
-            if (h.iter >= maxiter_) {
-                // converged in the last iteration or not at all: decided from the estimates below
-                result = SGN_ERR_NOT_CONVERGED;
-            }
-            break;
-        }
-        bool changed = false;
-        if (h.reliable) {
-            reliable_update(h);
-            changed = true;
-        }
-        if (h.want_phase) {
-            switch_phase(h, h.want_phase);
-            changed = true;
-        }
-        if (changed) {
-            SGN_HIP(hipMemcpyAsync(&S_->h, &h, sizeof(BsHead), hipMemcpyHostToDevice, s_));
-            SGN_HIP(hipStreamSynchronize(s_));
-        }
+        if (poll(h)) break;
     }
+    return finish(stp);
+}
+
+sgn_status BsStored::finish(sgn_stats *stp)
+{
+    const BsHead &h = head_;
+    const double ynorm = ynorm_;
+    const std::vector<double> &tau = tau_;
+    sgn_status result = result_;
+    sgn_stats st{};
+    st.nshift = ns_;
+    OpSpec op;
+    op.mu = pb_.mu;
     const int K = h.iter;
     // coefficients of sum_{i != seed} omega_i x_i over the slots r_0..r_K, s_0..s_{K-1}
     std::vector<BsHist> hs(K);
@@ -1277,9 +1442,257 @@ sgn_status BsStored::run(sgn_stats *stp)
     st.reliable_updates = reliable_;
     st.refine_iterations = refine_its;
     st.residual = worst;
-    st.krylov_ms = ms_since(t_kry);
-    st.total_ms = ms_since(t_start);
+    st.krylov_ms = ms_since(t_kry_);
+    st.total_ms = ms_since(t_start_);
     if (stp) *stp = st;
+    return result;
+}
+
+// Lockstep batch of stored-basis problems (own lattices, mu and b; one rational function):
+// every iteration of all active problems is one set of launches per precision phase -- the four
+// stencil applications as StencilBatch launches (problems on one lattice share their link loads in
+// multi-RHS groups), the scalar steps one block per problem, the vector updates with blockIdx.y over
+// the problems -- and a chunk of poll iterations is captured once as a HIP graph and replayed until
+// a problem changes precision or several have finished.  Setup, reliable updates, precision switches
+// and the final combination are each problem's own (BsStored's steps).
+class BsBatch {
+  public:
+    BsBatch(const sgn_problem *pb, int np, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s)
+        : o_(o), s_(s)
+    {
+        for (int k = 0; k < np; ++k) {
+            SGN_REQUIRE(pb[k].lat && pb[k].b && pb[k].x, "multishift_bicgstab: null problem field");
+            SGN_REQUIRE(std::isfinite(pb[k].mu), "multishift_bicgstab: mu not finite");
+            pr_.push_back(std::make_unique<BsStored>(pb[k], rf, o, s, &pools_));
+        }
+        ctx_ = pr_.empty() ? nullptr : &pr_[0]->ctx_;
+        for (auto &p : pr_) SGN_REQUIRE(&p->ctx_ == ctx_, "multishift_bicgstab: problems of one call need one context");
+    }
+    ~BsBatch()
+    {
+        drop_graph();
+        for (BsDesc *d : ddesc_)
+            if (d) (void)hipFree(d);
+    }
+    sgn_status run(sgn_stats *st);
+
+  private:
+    std::vector<std::unique_ptr<BsStored>> pr_;
+    BsSlotPools pools_;
+    const sgn_ms_opts &o_;
+    hipStream_t s_;
+    Context *ctx_ = nullptr;
+    int poll_ = 4;
+    std::vector<int> group_[3];          // active problems of each phase
+    BsDesc *ddesc_[3] = {nullptr, nullptr, nullptr};
+    size_t dcap_[3] = {0, 0, 0};
+    StencilBatch stb_[3][4];
+    int nvb_max_[3] = {0, 0, 0}, nxp_max_[3] = {0, 0, 0};
+    double vbytes_[3] = {0, 0, 0};       // bytes of one element pass of every problem of the phase
+    hipGraphExec_t gexec_ = nullptr;
+
+    void drop_graph()
+    {
+        if (gexec_) (void)hipGraphExecDestroy(gexec_);
+        gexec_ = nullptr;
+    }
+    void rebuild();
+    void launch_iteration(hipStream_t strm);
+    void iterate(int count);
+};
+
+void BsBatch::rebuild()
+{
+    drop_graph();
+    for (auto &g : group_) g.clear();
+    for (int k = 0; k < (int)pr_.size(); ++k)
+        if (!pr_[k]->done_) group_[pr_[k]->phase_].push_back(k);
+    for (int ph = 0; ph < 3; ++ph) {
+        const std::vector<int> &g = group_[ph];
+        std::vector<StencilJob> jobs[4];
+        std::vector<BsDesc> desc(g.size());
+        nvb_max_[ph] = nxp_max_[ph] = 0;
+        vbytes_[ph] = 0.0;
+        for (size_t j = 0; j < g.size(); ++j) {
+            BsStored &b = *pr_[g[j]];
+            const bool f = b.lo();
+            char *p = f ? b.p32_ : b.p64_, *tmp = f ? b.tmp32_ : b.tmp64_, *v = f ? b.v32_ : b.v64_,
+                 *sv = f ? b.s32_ : b.s64_, *t = f ? b.t32_ : b.t64_, *rh = f ? b.rh32_ : b.rh64_;
+            OpSpec op;
+            op.mu = b.pb_.mu;
+            jobs[0].push_back(StencilJob{&b.lat_, op, p, tmp, Epilogue{}});
+            StencilJob j2{&b.lat_, op, tmp, v, Epilogue{}};
+            j2.ep.a = b.c2_;
+            j2.ep.z = p;
+            j2.ep.b = {-b.s0_, 0.0};
+            j2.ep.w = rh;
+            j2.ep.partials = b.spart_;
+            jobs[1].push_back(j2);
+            jobs[2].push_back(StencilJob{&b.lat_, op, sv, tmp, Epilogue{}});
+            StencilJob j4{&b.lat_, op, tmp, t, Epilogue{}};
+            j4.ep.a = b.c2_;
+            j4.ep.z = sv;
+            j4.ep.b = {-b.s0_, 0.0};
+            j4.ep.w = sv;
+            j4.ep.partials = b.vpart_;
+            j4.ep.norm = true;
+            jobs[3].push_back(j4);
+            desc[j] = BsDesc{b.S_, b.rtab_, b.stab_, p, v, sv, t, rh, (double2 *)b.x64_, b.spart_, b.vpart_,
+                             b.hist_, b.n_, (int)b.Sst_, 0, 0, b.maxiter_};
+            nvb_max_[ph] = std::max(nvb_max_[ph], b.nvb_);
+            nxp_max_[ph] = std::max(nxp_max_[ph], f ? vec_blocks(6 * b.Sst_) : b.nvb_);
+            vbytes_[ph] += (double)b.n_ * (f ? 8.0 : 16.0);
+        }
+        const sgn_prec sp = ph == 0 ? SGN_PREC_F64 : (ph == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16);
+        for (int k = 0; k < 4; ++k) stb_[ph][k].prepare(jobs[k], sp);
+        for (size_t j = 0; j < g.size(); ++j) {
+            desc[j].nb_s = stb_[ph][1].blocks(j);
+            desc[j].nb_v = stb_[ph][3].blocks(j);
+        }
+        if (g.empty()) continue;
+        const size_t need = sizeof(BsDesc) * g.size();
+        if (need > dcap_[ph]) {
+            if (ddesc_[ph]) SGN_HIP(hipFree(ddesc_[ph]));
+            ddesc_[ph] = nullptr;
+            dcap_[ph] = 0;
+            if (hipMalloc(&ddesc_[ph], need) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "multishift_bicgstab: batch"};
+            dcap_[ph] = need;
+        }
+        SGN_HIP(hipMemcpy(ddesc_[ph], desc.data(), need, hipMemcpyHostToDevice));
+    }
+}
+
+void BsBatch::launch_iteration(hipStream_t strm)
+{
+    for (int ph = 0; ph < 3; ++ph) {
+        const int np = (int)group_[ph].size();
+        if (!np) continue;
+        const BsDesc *d = ddesc_[ph];
+        const bool f = ph >= 1;
+        const double nvec = vbytes_[ph] / (f ? 8.0 : 16.0);  // complex entries of all the phase's problems
+        stb_[ph][0].launch(strm);
+        stb_[ph][1].launch(strm);
+        hipLaunchKernelGGL(bs_alpha_batch, dim3(np), dim3(256), 0, strm, d);
+        int pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE);
+        if (f)
+            hipLaunchKernelGGL(bs_sub_batch<float>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        else
+            hipLaunchKernelGGL(bs_sub_batch<double>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        ctx_->prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * vbytes_[ph], 8.0 * nvec);
+        stb_[ph][2].launch(strm);
+        stb_[ph][3].launch(strm);
+        hipLaunchKernelGGL(bs_omega_batch, dim3(np), dim3(256), 0, strm, d);
+        pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE);
+        if (f)
+            hipLaunchKernelGGL(bs_res_batch<float>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        else
+            hipLaunchKernelGGL(bs_res_batch<double>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        ctx_->prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * vbytes_[ph], 12.0 * nvec);
+        hipLaunchKernelGGL(bs_beta_batch, dim3(np), dim3(256), 0, strm, d, nvb_max_[ph]);
+        pr = ctx_->prof_start(strm, SGN_K_SHIFT_UPDATE);
+        if (f)
+            hipLaunchKernelGGL(bs_xp32_batch, dim3(nxp_max_[ph], np), dim3(256), 0, strm, d);
+        else
+            hipLaunchKernelGGL(bs_xp64_batch, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        ctx_->prof_stop(pr, strm, SGN_K_SHIFT_UPDATE, 5.0 * vbytes_[ph] + 32.0 * nvec, 28.0 * nvec);
+    }
+    SGN_HIP(hipGetLastError());
+}
+
+void BsBatch::iterate(int count)
+{
+    if (o_.graph >= 0 && !ctx_->prof) {
+        if (!gexec_) {
+            if (!ctx_->capture_stream) SGN_HIP(hipStreamCreate(&ctx_->capture_stream));
+            hipStream_t cs = ctx_->capture_stream;
+            hipGraph_t g = nullptr;
+            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int it = 0; it < count; ++it) launch_iteration(cs);
+            } catch (...) {
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SGN_HIP(hipStreamEndCapture(cs, &g));
+            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SGN_HIP(e);
+        }
+        SGN_HIP(hipGraphLaunch(gexec_, s_));
+    } else {
+        for (int it = 0; it < count; ++it) launch_iteration(s_);
+    }
+    for (int ph = 0; ph < 3; ++ph)
+        for (int k : group_[ph]) pr_[k]->note_launched(count);
+}
+
+sgn_status BsBatch::run(sgn_stats *st)
+{
+    if (pr_.empty()) return SGN_OK;
+    SGN_HIP(hipSetDevice(ctx_->device));
+    size_t total = 0;
+    double b64sum = 0.0;
+    for (auto &p : pr_) {
+        p->init_sizes();
+        total += p->ws_bytes();
+        b64sum += (double)p->b64_;
+    }
+    poll_ = pr_[0]->poll_;
+    {
+        size_t fr = 0, tot = 0;
+        SGN_HIP(hipMemGetInfo(&fr, &tot));
+        double held = 0.0;
+        for (auto &kv : ctx_->basis_pools) held += (double)kv.first * kv.second.size();
+        pools_.budget = o_.basis_slots > 0 ? (double)o_.basis_slots * b64sum : 0.5 * ((double)fr + held);
+    }
+    char *a = static_cast<char *>(ctx_->ensure_arena(total));
+    for (size_t k = 0; k < pr_.size(); ++k) {
+        pr_[k]->setup(a, st ? st + k : nullptr);
+        a += pr_[k]->ws_bytes();
+    }
+    int active = 0;
+    for (auto &p : pr_) active += p->done_ ? 0 : 1;
+    bool dirty = true;
+    int finished_since = 0;
+    std::vector<BsHead> heads(pr_.size());
+    while (active > 0) {
+        for (auto &p : pr_)
+            if (!p->done_) p->ensure_slots(p->launched_ + poll_);
+        if (dirty) {
+            rebuild();
+            dirty = false;
+            finished_since = 0;
+        }
+        iterate(poll_);
+        for (size_t k = 0; k < pr_.size(); ++k)
+            if (!pr_[k]->done_)
+                SGN_HIP(hipMemcpyAsync(&heads[k], &pr_[k]->S_->h, sizeof(BsHead), hipMemcpyDeviceToHost, s_));
+        SGN_HIP(hipStreamSynchronize(s_));
+        for (size_t k = 0; k < pr_.size(); ++k) {
+            BsStored &p = *pr_[k];
+            if (p.done_) continue;
+            const int phase = p.phase_;
+            if (p.poll(heads[k])) {
+                --active;
+                ++finished_since;
+            } else if (p.phase_ != phase) {
+                dirty = true;
+            }
+        }
+        // finished problems only idle in the launches (their kernels see the done flag); drop
+        // them once they are a quarter of the launch
+        int launched = 0;
+        for (auto &g : group_) launched += (int)g.size();
+        if (active > 0 && 4 * finished_since >= launched) dirty = true;
+    }
+    drop_graph();
+    sgn_status result = SGN_OK;
+    for (size_t k = 0; k < pr_.size(); ++k) {
+        if (pr_[k]->ynorm_ == 0.0) continue;  // x = x_P was written by setup
+        const sgn_status sk = pr_[k]->finish(st ? st + k : nullptr);
+        if (sk != SGN_OK && result == SGN_OK) result = sk;
+    }
     return result;
 }
 
@@ -1300,6 +1713,11 @@ extern "C" sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, cons
         SGN_REQUIRE(o->prec == SGN_PREC_F64 || o->prec == SGN_PREC_F32 || o->prec == SGN_PREC_F32_H16,
                     "multishift_bicgstab: unknown precision");
         SGN_REQUIRE(o->maxiter >= 0 && o->maxiter <= 100000, "multishift_bicgstab: maxiter out of range");
+        if (o->basis_slots >= 0 && nprob > 1) {  // stored-basis problems in lockstep
+            BsBatch batch(pb, nprob, *rf, *o, static_cast<hipStream_t>(stream));
+            result = batch.run(st);
+            return;
+        }
         for (int k = 0; k < nprob; ++k) {
             const hipStream_t s = static_cast<hipStream_t>(stream);
             sgn_status sk;

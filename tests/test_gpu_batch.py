@@ -127,3 +127,66 @@ def test_graph_replay_equals_plain_launches(prec):
               f"reliable updates {sg[k]['reliable_updates']}", flush=True)
         assert sg[k]["iterations"] == sp[k]["iterations"]
         assert np.array_equal(xg[k], xp[k])
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32_H16])
+def test_bicgstab_lockstep_batch_equals_single_solves(prec):
+    """multishift_bicgstab with several problems runs them in lockstep (one launch per step for all
+    of them); each result equals its own single-problem solve to the tolerance's order, and the
+    batch of problems on one lattice (multi-RHS stencil groups) gives the same as on separate ones."""
+    rf = sgn.sgn_rational_neuberger(16, ALPHA, BETA)
+    probs = _small_set()
+    U = synth.gauge_field((8, 8, 8, 8), 0.4, 2)
+    lat8 = lattice(U, (8, 8, 8, 8))
+    probs += [(lat8, 0.1, synth.gaussian_source((8, 8, 8, 8), 7)), (lat8, 0.3, synth.gaussian_source((8, 8, 8, 8), 8))]
+    kw = dict(tol=1e-10, prec=prec, poll=4)
+    if prec != sgn.F64:
+        kw.update(theta32=1e-2, theta16=1e-5, delta=0.05)
+    outs, bprobs = [], []
+    for lat, mu, b in probs:
+        bd = dev(np.ascontiguousarray(b).ravel())
+        x = torch.empty_like(bd)
+        bprobs.append(sgn.Problem(lat, mu, bd, x))
+        outs.append(x)
+    sb = sgn.multishift_bicgstab(bprobs, rf, **kw)
+    for k, (lat, mu, b) in enumerate(probs):
+        bd = dev(np.ascontiguousarray(b).ravel())
+        xs = torch.empty_like(bd)
+        ss = sgn.multishift_bicgstab(sgn.Problem(lat, mu, bd, xs), rf, **kw)[0]
+        e = _rel(host(outs[k]), host(xs))
+        print(f"prec={prec} problem {k}: batch vs single {e:.2e}, iterations {sb[k]['iterations']} / "
+              f"{ss['iterations']}, reliable updates {sb[k]['reliable_updates']} / {ss['reliable_updates']}",
+              flush=True)
+        assert e < (1e-9 if prec == sgn.F64 else 1e-8)
+        assert abs(sb[k]["iterations"] - ss["iterations"]) <= max(2, ss["iterations"] // 10)
+
+
+def test_bicgstab_lockstep_c4_against_oracle():
+    """The 32 right-hand sides over 8^4 / 12^4 / 16^4 through the lockstep BiCGStab batch (mixed
+    precision, every shifted system verified in FP64): the 8^4 problems against the oracle's
+    multishift BiCGStab."""
+    fields, plist = synth.mixed_batch_recipe(32)
+    lats = [lattice(U, dims) for dims, U in fields]
+    rf = sgn.sgn_rational_neuberger(16, ALPHA, BETA)
+    om, sg, c = rational.coefficients(16, ALPHA, BETA)
+    probs, outs = [], []
+    for fi, mu, b in plist:
+        bd = dev(b.ravel())
+        x = torch.empty_like(bd)
+        probs.append(sgn.Problem(lats[fi], mu, bd, x))
+        outs.append(x)
+    st = sgn.multishift_bicgstab(probs, rf, tol=1e-10, prec=sgn.F32_H16, theta32=1e-2, theta16=1e-5, delta=0.05,
+                                 verify=True)
+    its = [s["iterations"] for s in st]
+    print(f"C4 BiCGStab lockstep: iterations {min(its)}..{max(its)}, verified shifted residuals <= "
+          f"{max(s['residual'] for s in st):.1e}", flush=True)
+    assert max(s["residual"] for s in st) <= 1e-10
+    for j in (0, 3, 6):
+        fi, mu, b = plist[j]
+        dims, U = fields[fi]
+        assert dims == (8, 8, 8, 8)
+        W = WilsonRef(U, dims, 0.2)
+        ref = krylov.multishift_bicgstab(lambda v: W.apply(v, mu), b.ravel(), om, sg, c, tol=1e-11)
+        e = _rel(host(outs[j]), ref)
+        print(f"C4 problem {j}: lockstep BiCGStab vs oracle {e:.2e}", flush=True)
+        assert e < 1e-9
