@@ -23,6 +23,7 @@ __all__ = [
     "gell_mann",
     "gauge_field",
     "unit_gauge_field",
+    "constant_gauge_field",
     "gaussian_source",
     "ones_source",
     "mixed_batch_recipe",
@@ -92,6 +93,19 @@ def unit_gauge_field(dims) -> np.ndarray:
     Lx, Ly, Lz, Lt = lattice_dims(dims)
     U = np.zeros((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=np.complex128)
     U[..., 0, 0] = U[..., 1, 1] = U[..., 2, 2] = 1.0
+    return U
+
+
+def constant_gauge_field(dims, seed=0) -> np.ndarray:
+    """Constant diagonal SU(3) links U_nu = diag(e^{i a}, e^{i b}, e^{-i (a + b)}), the phases
+    a, b of each direction uniform in [-pi, pi) from the seed: a translation-invariant background
+    whose colours see different momenta."""
+    Lx, Ly, Lz, Lt = lattice_dims(dims)
+    ph = np.random.default_rng(np.random.SeedSequence([seed, 7])).uniform(-np.pi, np.pi, (4, 2))
+    d = np.exp(1j * np.concatenate([ph, -ph.sum(axis=1, keepdims=True)], axis=1))
+    U = np.zeros((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=np.complex128)
+    for c in range(3):
+        U[..., c, c] = d[:, c]
     return U
 
 
