@@ -314,7 +314,9 @@ typedef struct {
  * ||H r - lambda r|| / (|lambda| ||r||) over both sides.  The m-th and (m+1)-th
  * eigenvalues should be separated: a cut inside a cluster leaves the projector
  * ill-determined.  SGN_ERR_NOT_CONVERGED if a side did not converge within
- * max_restarts (outputs hold the last approximation), SGN_ERR_BREAKDOWN if the
+ * max_restarts (outputs hold the last approximation), or if it has fewer than m
+ * Ritz pairs with residual <= 1e-4 |theta| (outputs not written; stats hold the
+ * work done and sgn_last_error the count), SGN_ERR_BREAKDOWN if the
  * two subspaces do not pair (singular L^H R).  Synchronises `stream`. */
 sgn_status sgn_critical_eigenpairs(sgn_lattice lat, double mu, const sgn_eig_opts *o, void *L, void *R,
                                    double *lambda, double *alpha, sgn_stats *stats, void *stream);

@@ -31,6 +31,7 @@
 #include <chrono>
 #include <complex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "field_io.h"
@@ -406,7 +407,9 @@ struct EigSolver {
             if (std::sqrt(std::max(r2, 0.0)) <= kRitzScreen * std::abs(th[j])) keep.push_back(j);
         }
         if ((int)keep.size() < m)
-            throw Failure{SGN_ERR_NOT_CONVERGED, "eigensolver: fewer than m accurate Ritz pairs"};
+            throw Failure{SGN_ERR_NOT_CONVERGED, "eigensolver: " + std::to_string(keep.size()) + " of the " +
+                                                     std::to_string(m) + " wanted Ritz pairs accurate (" +
+                                                     std::to_string(restarts) + " restarts)"};
         std::stable_sort(keep.begin(), keep.end(),
                          [&](int a, int b) { return std::abs(th[a].real()) < std::abs(th[b].real()); });
         theta_rest.clear();
@@ -479,14 +482,29 @@ extern "C" sgn_status sgn_critical_eigenpairs(sgn_lattice l, double mu, const sg
         char *Qs[2] = {QR, QL};
         std::vector<double> rest_right;
         bool converged = true;
-        for (int side = 0; side < 2; ++side) {
-            char *V = nullptr;
-            std::vector<zc> Yw, Z;
-            std::vector<double> th;
-            converged = E.iram(mus[side], E.seed * 2 + side + 1, V, Yw) && converged;
-            E.ritz_select(mus[side], V, Yw, T, Z, th);
-            E.combine(V, k, Z, m, Qs[side]);
-            if (side == 0) rest_right = th;
+        // the work done so far, also when a side stops without enough accurate pairs
+        auto record = [&](double worst) {
+            if (!st) return;
+            st->iterations = E.steps;
+            st->matvecs = E.matvecs;
+            st->restarts = E.restarts;
+            st->residual = worst;
+            st->small_ms = E.small_ms;
+            st->total_ms = ms_since(t_start);
+        };
+        try {
+            for (int side = 0; side < 2; ++side) {
+                char *V = nullptr;
+                std::vector<zc> Yw, Z;
+                std::vector<double> th;
+                converged = E.iram(mus[side], E.seed * 2 + side + 1, V, Yw) && converged;
+                E.ritz_select(mus[side], V, Yw, T, Z, th);
+                E.combine(V, k, Z, m, Qs[side]);
+                if (side == 0) rest_right = th;
+            }
+        } catch (...) {
+            record(0.0);
+            throw;
         }
         // oblique projection on the pair of invariant subspaces
         OpSpec op;
@@ -564,14 +582,7 @@ extern "C" sgn_status sgn_critical_eigenpairs(sgn_lattice l, double mu, const sg
             for (size_t j = 0; j < rest_right.size(); ++j) a = (j == 0) ? rest_right[j] : std::min(a, rest_right[j]);
             *alpha = a;
         }
-        if (st) {
-            st->iterations = E.steps;
-            st->matvecs = E.matvecs;
-            st->restarts = E.restarts;
-            st->residual = worst;
-            st->small_ms = E.small_ms;
-            st->total_ms = ms_since(t_start);
-        }
+        record(worst);
         if (!converged) throw Failure{SGN_ERR_NOT_CONVERGED, "eigensolver: not converged within max_restarts"};
     });
 }
