@@ -151,18 +151,21 @@ sgn_status wilson_apply_multi(sgn_lattice lat, int nrhs, const double *mu, const
 /* ------------------------------------------------------------------ launch-shape tuning */
 /* One candidate launch shape of the stencil and its measured time. */
 typedef struct {
-    int block_sites;          /* lattice sites per block (0: the unstaged kernel) */
+    int block_sites;          /* lattice sites per block, all its t-slices (0: the unstaged kernel) */
     int links_in_registers;   /* multi-RHS form: links held in registers (1) or read per right-hand side (0) */
     double us;                /* one application (all nrhs right-hand sides), microseconds */
     int chosen;               /* 1 for the fastest candidate, now used by the context */
+    int t_slices;             /* 1: the block's sites lie in one t-slice; 2: a brick of the same sites at
+                                 t and t + 1, whose time hops between the two slices read LDS */
 } sgn_tune_candidate;
 
 /* Autotune the stencil's launch shape for lattices of lat's dimensions, precision p
  * and nrhs right-hand sides per launch (1: the single form, 2..16: the multi-RHS
  * form, whose choice serves every group size): every candidate -- the distinct
  * block sizes (whole x-rows or x-y planes within the LDS budget, under site caps
- * of 576, 432, 384, 288, 192 and 96), and with FP16 two-row links and nrhs > 1 both
- * link modes -- is applied reps times (0: 20) to zero fields on `stream` and timed
+ * of 576, 432, 384, 288, 192 and 96), each as one t-slice and, for even L_t, as a
+ * brick of two, and with FP16 two-row links and nrhs > 1 both link modes -- is
+ * applied reps times (0: 20) to zero fields on `stream` and timed
  * with HIP events; the fastest is kept in the context and used by every later
  * launch of that shape class on lattices of these dimensions (the solvers, the
  * batched form, wilson_apply and wilson_apply_multi).  Until then a default shape
@@ -171,6 +174,15 @@ typedef struct {
  * 2 * nrhs fields for the duration of the call and synchronises the device. */
 sgn_status sgn_autotune(sgn_lattice lat, sgn_prec p, int nrhs, int reps, sgn_tune_candidate *out, int max_out,
                         int *n_out, void *stream);
+
+/* Set the launch shape used for lattices of lat's dimensions in precision p (multi = 0: the
+ * single-RHS form, 1: the multi-RHS form) by hand, as sgn_autotune would: blocks of at most
+ * max_sites sites (0: no cap beyond the LDS budget and the launch bound), t_slices = 1 or 2
+ * (bricks of two t-slices, even L_t), links_in_registers = -1 (default), 0 or 1 (multi-RHS form
+ * with FP16 two-row links).  For replaying a saved tuning result or pinning a shape.
+ * SGN_ERR_INVALID if no staged block of that shape fits the lattice.  Synchronises the device. */
+sgn_status sgn_tune_set(sgn_lattice lat, sgn_prec p, int multi, int max_sites, int t_slices,
+                        int links_in_registers);
 
 /* ------------------------------------------------------------------ deflation and statistics */
 /* LR deflation set (section "Deflation", oblique projector P = R L^H):

@@ -505,7 +505,8 @@ def wilson_apply_multi(lat, mus, xs, outs, prec=F64, flags=INTERNAL_LAYOUT, stre
 
 
 class TuneCandidate(C.Structure):
-    _fields_ = [("block_sites", C.c_int), ("links_in_registers", C.c_int), ("us", C.c_double), ("chosen", C.c_int)]
+    _fields_ = [("block_sites", C.c_int), ("links_in_registers", C.c_int), ("us", C.c_double), ("chosen", C.c_int),
+                ("t_slices", C.c_int)]
 
 
 lib.sgn_autotune.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(TuneCandidate), C.c_int,
@@ -520,6 +521,15 @@ def sgn_autotune(lat, prec, nrhs=1, reps=20, stream=None):
     check(lib.sgn_autotune(lat.h, int(prec), int(nrhs), int(reps), arr, 32, C.byref(n), _stream(stream)),
           "sgn_autotune")
     return [{f: getattr(arr[i], f) for f, _ in TuneCandidate._fields_} for i in range(min(n.value, 32))]
+
+
+lib.sgn_tune_set.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+
+
+def sgn_tune_set(lat, prec, multi=False, max_sites=0, t_slices=1, links_in_registers=-1):
+    """Pin the stencil's launch shape for lattices of lat's dimensions (see sgn_autotune)."""
+    check(lib.sgn_tune_set(lat.h, int(prec), int(bool(multi)), int(max_sites), int(t_slices),
+                           int(links_in_registers)), "sgn_tune_set")
 
 
 class ArnoldiOpts(C.Structure):

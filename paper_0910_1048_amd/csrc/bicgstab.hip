@@ -713,7 +713,11 @@ __global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, con
 }
 
 // FP32 phase: p, v, r', s in the [6][S] float4 layout (chunk c holds components 2c, 2c+1), x in
-// FP64 [12][S] (FP32 increments of x lose too much of the seed solution's accuracy here)
+// FP64 [12][S].  An FP32 increment of x (folded into an FP64 base at each reliable update) would
+// save a third of this kernel's bytes, but a reliable update hands the seed's true residual to
+// every shifted system through the collinear residuals, so the increment's rounding becomes an
+// error of the non-seed solutions: at 24^3 x 48 the unverified result moved from 1.4e-9 to
+// 7.6e-9 of the verified one.
 __device__ __forceinline__ void bs_xp32_body(const BsState *S, float4 *p, const float4 *v, void *const *rslots, const float4 *s,
                               double2 *x, int Sst)
 {

@@ -90,7 +90,8 @@ struct StencilParams {
     // walks it region by region with t fastest (sched_R spatial regions per slice)
     int sched_T, sched_R;
     int nblk_sites;  // blocks covering the V sites; later blocks zero the padding sites [V, S)
-    int blk_sites;   // staged kernel: sites per block (whole x-rows)
+    int blk_sites;   // staged kernel: sites per block and t-slice (whole x-rows)
+    int tslices;     // staged kernel: t-slices per block (1, or 2: a brick of the same B sites at t and t + 1)
     int nblk_total;  // blocks of this application (sites + padding); batched launches skip the rest
     int link_ne;     // complex entries stored per link (6 or 9)
     int nrhs;        // right-hand sides of this application (staged kernel; the unstaged one uses NR)
@@ -473,15 +474,23 @@ __device__ __forceinline__ void lds_load_spinor<float>(const float4 *l, int B, i
 // (stored already multiplied by the input gamma5 sign), else from memory.  Returns
 // the gamma5 sign the projection still has to apply to the lower spins.
 template <typename R>
-__device__ __forceinline__ R fetch_neighbour(const RhsParams &Q, int S, int B, const SpT<R> *lds, int base, int n,
-                                             cpx<R> p[12])
+__device__ __forceinline__ R fetch_neighbour(const RhsParams &Q, const StencilParams &P, const SpT<R> *lds, int base,
+                                             int n, cpx<R> p[12])
 {
-    const int ln = n - base;
+    const int B = P.blk_sites, NB = B * P.tslices;
+    int ln = n - base;
     if ((unsigned)ln < (unsigned)B) {
-        lds_load_spinor<R>(lds, B, ln, p);
+        lds_load_spinor<R>(lds, NB, ln, p);
         return R(1);
     }
-    load_spinor(static_cast<const SpT<R> *>(Q.in), S, n, p);
+    if (P.tslices == 2) {  // the brick's second slice (uniform branch)
+        ln = n - base - P.stride[3];
+        if ((unsigned)ln < (unsigned)B) {
+            lds_load_spinor<R>(lds, NB, B + ln, p);
+            return R(1);
+        }
+    }
+    load_spinor(static_cast<const SpT<R> *>(Q.in), P.S, n, p);
     return static_cast<R>(Q.s5_in);
 }
 
@@ -529,7 +538,7 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
                                                 const SpT<R> *lds, int base, int s, int coord,
                                                 const SiteLinks<R, LT, kRegs> &lk)
 {
-    const int L = P.L[NU], st = P.stride[NU], B = P.blk_sites;
+    const int L = P.L[NU], st = P.stride[NU];
     const R kap = static_cast<R>(P.kappa);
     cpx<R> u[9];
     {
@@ -538,7 +547,7 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
         lk.template get<2 * NU>(P, s, u);
-        const R s5 = fetch_neighbour<R>(Q, P.S, B, lds, base, n, p);
+        const R s5 = fetch_neighbour<R>(Q, P, lds, base, n, p);
         project<NU, true>(p, h, s5);
         link_mul<false>(u, h, chi);
         const R w = NU == 3 ? static_cast<R>(Q.wf_t) : R(1);
@@ -551,7 +560,7 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
         lk.template get<2 * NU + 1>(P, n, u);
-        const R s5 = fetch_neighbour<R>(Q, P.S, B, lds, base, n, p);
+        const R s5 = fetch_neighbour<R>(Q, P, lds, base, n, p);
         project<NU, false>(p, h, s5);
         link_mul<true>(u, h, chi);
         const R w = NU == 3 ? static_cast<R>(Q.wb_t) : R(1);
@@ -594,12 +603,12 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
         }
         return;
     }
-    const int B = P.blk_sites;
+    const int B = P.blk_sites, NB = B * P.tslices;
     int blk;
     if (P.sched_T > 0) {
-        // XCD k owns the t-slab [k T, (k+1) T) of sched_R blocks per t-slice and
-        // walks it in strips of W consecutive blocks with t fastest, so the
-        // t-neighbours of a block run on the same XCD at about the same time
+        // XCD k owns the t-slab [k T, (k+1) T) of sched_R blocks per t-slice (per pair of
+        // t-slices for bricks) and walks it in strips of W consecutive blocks with t fastest, so
+        // the t-neighbours of a block run on the same XCD at about the same time
         const int W = SGN_STAGED_STRIP;
         const int k = bx % 8, j = bx / 8;
         const int per_strip = P.sched_T * W;
@@ -609,10 +618,18 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
     } else {
         blk = SGN_XCD_REMAP ? xcd_block(bx, P.nblk_sites) : bx;
     }
-    const int base = blk * B;
+    // first site of the block: B consecutive sites of one t-slice, for bricks the same B sites
+    // of the next slice too (threads B.. 2B-1); blocks tile the V sites exactly
+    int base;
+    if (P.tslices == 2) {
+        const int nreg = P.stride[3] / B, g = blk / nreg;
+        base = 2 * g * P.stride[3] + (blk - g * nreg) * B;
+    } else {
+        base = blk * B;
+    }
     const int i = threadIdx.x;
-    const int s = base + i;
-    const bool valid = i < B;  // blocks tile the V sites exactly
+    const bool valid = i < NB;
+    const int s = i < B ? base + i : base + P.stride[3] + (i - B);
     int c[4] = {0, 0, 0, 0};
     if (valid) {
         c[0] = s % P.L[0];
@@ -634,7 +651,7 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
             const R s5 = static_cast<R>(Q.s5_in);
 #pragma unroll
             for (int k = 6; k < 12; ++k) acc[k] = s5 * acc[k];
-            lds_store_spinor<R>(lds, B, i, acc);
+            lds_store_spinor<R>(lds, NB, i, acc);
         }
         __syncthreads();
         double dr = 0.0, di = 0.0, dn = 0.0;
@@ -730,23 +747,26 @@ namespace {
 // when they fit the LDS budget), B dividing V; not used when B < 64.
 struct StagedPlan {
     bool ok = false;
-    int B = 0, threads = 0, nblk_sites = 0, nblk = 0;
+    int B = 0, T = 1, threads = 0, nblk_sites = 0, nblk = 0;  // B sites per t-slice, T slices per block
     size_t lds = 0;
 };
 
 // max_threads > 0 caps the block (the register-link multi-RHS form), max_sites > 0 the sites of
-// a block (a tuned shape)
-StagedPlan staged_plan(const Lattice &lat, sgn_prec p, int max_threads = 0, int max_sites = 0)
+// a block (a tuned shape); tslices = 2 asks for bricks of two t-slices (even L_t; B then divides
+// one slice, so a brick never straddles a time boundary)
+StagedPlan staged_plan(const Lattice &lat, sgn_prec p, int max_threads = 0, int max_sites = 0, int tslices = 1)
 {
     StagedPlan pl;
     if (!SGN_STENCIL_LDS) return pl;
+    const int T = tslices == 2 ? 2 : 1;
+    if (T == 2 && lat.L[3] % 2) return pl;
     const int64_t site_bytes = p == SGN_PREC_F64 ? 192 : 96;
     int64_t tmax = p == SGN_PREC_F64 ? kStagedMaxThreads<double> : kStagedMaxThreads<float>;
     if (max_threads > 0) tmax = std::min<int64_t>(tmax, max_threads);
     if (max_sites > 0) tmax = std::min<int64_t>(tmax, max_sites);
-    const int64_t bmax = std::min<int64_t>(tmax, SGN_LDS_MAXBYTES / site_bytes);
+    const int64_t bmax = std::min<int64_t>(tmax, SGN_LDS_MAXBYTES / site_bytes) / T;
     const int64_t Lx = lat.L[0], A = (int64_t)lat.L[0] * lat.L[1];
-    const int64_t nplane = (int64_t)lat.L[2] * lat.L[3];
+    const int64_t nplane = (int64_t)lat.L[2] * (T == 2 ? 1 : lat.L[3]);
     int64_t B = 0;
     if (A <= bmax) {
         int64_t P = bmax / A;
@@ -758,14 +778,15 @@ StagedPlan staged_plan(const Lattice &lat, sgn_prec p, int max_threads = 0, int 
         while (rows > 0 && nrows % rows) --rows;
         B = rows * Lx;
     }
-    if (B < 64) return pl;
+    if (B * T < 64) return pl;
     pl.ok = true;
     pl.B = (int)B;
-    pl.threads = (int)((B + 63) / 64 * 64);
-    pl.nblk_sites = (int)(lat.V / B);
+    pl.T = T;
+    pl.threads = (int)((B * T + 63) / 64 * 64);
+    pl.nblk_sites = (int)(lat.V / (B * T));
     const int64_t pad = lat.S > lat.V ? (lat.S - lat.V + pl.threads - 1) / pl.threads : 0;
     pl.nblk = pl.nblk_sites + (int)pad;
-    pl.lds = (size_t)B * site_bytes;
+    pl.lds = (size_t)B * T * site_bytes;
     return pl;
 }
 
@@ -860,15 +881,22 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
     ps.bytes_stored = (2 * sb * nr + 4 * lat.link_ne * eb + extra_bytes) * lat.V;
     ps.flops = (1368.0 * nr + extra_flops) * lat.V;
     P.nrhs = nr;
-    ps.pl = staged_plan(lat, p, max_threads, lat.ctx->tuned_shape(lat.L, p, nr > 1).max_sites);
+    P.tslices = 1;
+    {
+        const Context::TunedShape ts = lat.ctx->tuned_shape(lat.L, p, nr > 1);
+        ps.pl = staged_plan(lat, p, max_threads, ts.max_sites, ts.tslices);
+        if (!ps.pl.ok && ts.tslices == 2) ps.pl = staged_plan(lat, p, max_threads, ts.max_sites, 1);
+    }
     if (ps.pl.ok) {
         P.blk_sites = ps.pl.B;
+        P.tslices = ps.pl.T;
         P.nblk_sites = ps.pl.nblk_sites;
         ps.nblk = ps.pl.nblk;
         P.sched_T = P.sched_R = 0;
         const int64_t v3 = (int64_t)lat.L[0] * lat.L[1] * lat.L[2];
-        if (SGN_STAGED_STRIP > 0 && v3 % ps.pl.B == 0 && lat.L[3] % 8 == 0 && (v3 / ps.pl.B) % SGN_STAGED_STRIP == 0) {
-            P.sched_T = lat.L[3] / 8;
+        const int tg = lat.L[3] / ps.pl.T;  // t-slices, or pairs of them for bricks
+        if (SGN_STAGED_STRIP > 0 && v3 % ps.pl.B == 0 && tg % 8 == 0 && (v3 / ps.pl.B) % SGN_STAGED_STRIP == 0) {
+            P.sched_T = tg / 8;
             P.sched_R = (int)(v3 / ps.pl.B);
         }
     }
@@ -1205,22 +1233,26 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
         if (reps <= 0) reps = 20;
         const bool multi = nrhs > 1;
         const std::vector<int> key = {lat.L[0], lat.L[1], lat.L[2], lat.L[3], (int)p, multi ? 1 : 0};
-        // candidate shapes: distinct block sizes of the staged plan under decreasing site caps, and
-        // for several right-hand sides with FP16 two-row links both link modes
+        // candidate shapes: distinct blocks of the staged plan under decreasing site caps, as one
+        // t-slice or as bricks of two, and for several right-hand sides with FP16 two-row links both
+        // link modes
         struct Cand {
-            int cap, B, regs;
+            int cap, B, T, regs;
             double us;
         };
         std::vector<Cand> cands;
         const bool can_regs = multi && p == SGN_PREC_F32_H16 && lat.link_ne == 6;
         for (int regs : can_regs ? std::vector<int>{1, 0} : std::vector<int>{-1}) {
-            std::vector<int> seen;
-            for (int cap : {0, 576, 432, 384, 288, 192, 96}) {
-                const StagedPlan pl = staged_plan(lat, p, regs == 1 ? kRegsMaxThreads : 0, cap);
-                const int B = pl.ok ? pl.B : 0;
-                if (std::find(seen.begin(), seen.end(), B) != seen.end()) continue;
-                seen.push_back(B);
-                cands.push_back({cap, B, regs, 0.0});
+            for (int T : {1, 2}) {
+                std::vector<int> seen;
+                for (int cap : {0, 576, 432, 384, 288, 192, 96}) {
+                    const StagedPlan pl = staged_plan(lat, p, regs == 1 ? kRegsMaxThreads : 0, cap, T);
+                    if (!pl.ok && T == 2) continue;
+                    const int B = pl.ok ? pl.B : 0;
+                    if (std::find(seen.begin(), seen.end(), B) != seen.end()) continue;
+                    seen.push_back(B);
+                    cands.push_back({cap, B, pl.ok ? pl.T : 1, regs, 0.0});
+                }
             }
         }
         // fields: nrhs inputs (zero) and outputs in the internal layout
@@ -1253,7 +1285,7 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
         const Context::TunedShape before = ctx.tuned_shape(lat.L, p, multi);
         try {
             for (Cand &c : cands) {
-                ctx.tuned[key] = {c.cap, c.regs};
+                ctx.tuned[key] = {c.cap, c.regs, c.T};
                 for (int w = 0; w < 3; ++w) dslash_launch_multi(lat, p, nrhs, op.data(), in.data(), outp.data(), ep.data(), s);
                 SGN_HIP(hipEventRecord(e0, s));
                 for (int k = 0; k < reps; ++k)
@@ -1275,12 +1307,33 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
         const Cand *best = &cands[0];
         for (const Cand &c : cands)
             if (c.us < best->us) best = &c;
-        ctx.tuned[key] = {best->cap, best->regs};
+        ctx.tuned[key] = {best->cap, best->regs, best->T};
         SGN_HIP(hipDeviceSynchronize());
         const int n = std::min<int>((int)cands.size(), max_out);
         for (int k = 0; k < n; ++k)
-            out[k] = {cands[k].B, cands[k].regs < 0 ? 0 : cands[k].regs, cands[k].us, &cands[k] == best ? 1 : 0};
+            out[k] = {cands[k].B * cands[k].T, cands[k].regs < 0 ? 0 : cands[k].regs, cands[k].us,
+                      &cands[k] == best ? 1 : 0, cands[k].T};
         if (n_out) *n_out = (int)cands.size();
+    });
+}
+
+extern "C" sgn_status sgn_tune_set(sgn_lattice l, sgn_prec p, int multi, int max_sites, int t_slices,
+                                   int links_in_registers)
+{
+    return guard([&] {
+        SGN_REQUIRE(l != nullptr, "sgn_tune_set: null lattice");
+        SGN_REQUIRE(p == SGN_PREC_F64 || p == SGN_PREC_F32 || p == SGN_PREC_F32_H16, "sgn_tune_set: unknown precision");
+        SGN_REQUIRE(max_sites >= 0, "sgn_tune_set: max_sites must be >= 0");
+        SGN_REQUIRE(t_slices == 1 || t_slices == 2, "sgn_tune_set: t_slices must be 1 or 2");
+        SGN_REQUIRE(links_in_registers >= -1 && links_in_registers <= 1, "sgn_tune_set: links_in_registers is -1, 0 or 1");
+        Lattice &lat = *as_lattice(l);
+        const StagedPlan pl = staged_plan(lat, p, 0, max_sites, t_slices);
+        SGN_REQUIRE(pl.ok && pl.T == t_slices, "sgn_tune_set: no staged block of this shape fits the lattice");
+        // the parameters of earlier multi-RHS launches may still be read by the device
+        SGN_HIP(hipSetDevice(lat.ctx->device));
+        SGN_HIP(hipDeviceSynchronize());
+        lat.ctx->tuned[{lat.L[0], lat.L[1], lat.L[2], lat.L[3], (int)p, multi ? 1 : 0}] =
+            Context::TunedShape{max_sites, links_in_registers, t_slices};
     });
 }
 

@@ -143,6 +143,7 @@ struct Context {
     struct TunedShape {
         int max_sites = 0;
         int regs = -1;
+        int tslices = 1;  // staged blocks of 1 t-slice, or bricks of 2
     };
     std::map<std::vector<int>, TunedShape> tuned;
     TunedShape tuned_shape(const int L[4], sgn_prec p, bool multi) const

@@ -88,3 +88,72 @@ def test_solvers_after_autotune_match_the_oracle():
     sgn.multishift_solve(probs, rf, tol=1e-10, prec=sgn.F32_H16, theta32=1e-1, theta16=1e-3, delta=0.05)
     for p, r in zip(probs, refs):
         assert _rel(host(p.x), r) < 1e-8
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
+@pytest.mark.parametrize("dims", [(12, 12, 12, 24), (4, 6, 4, 8), (6, 4, 6, 10), (24, 24, 24, 48)])
+def test_bricks_are_the_same_operator(prec, dims):
+    """Blocks of two t-slices (pinned with sgn_tune_set at several site caps) give bit for bit
+    the result of one-slice blocks, for one and for three right-hand sides, and the oracle's
+    operator (every site at the small sizes, sampled sites at 24^3 x 48)."""
+    U = synth.gauge_field(dims, 0.4, 5)
+    lat = lattice(U, dims)
+    W = WilsonRef(U, dims, 0.2)
+    nb = lat.spinor_bytes(prec)
+    srcs = [synth.gaussian_source(dims, 40 + i) for i in range(3)]
+    mus = [0.2, -0.1, 0.3]
+    xi = []
+    for b in srcs:
+        t = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        sgn.sgn_spinor_pack(lat, dev(b.astype(CDT[prec])), t, prec)
+        xi.append(t)
+
+    def apply(nrhs):
+        ys = [torch.empty_like(t) for t in xi[:nrhs]]
+        if nrhs == 1:
+            sgn.wilson_apply(lat, mus[0], xi[0], ys[0], prec, sgn.INTERNAL_LAYOUT)
+        else:
+            sgn.wilson_apply_multi(lat, mus[:nrhs], xi[:nrhs], ys, prec)
+        torch.cuda.synchronize()
+        return ys
+
+    try:
+        for multi, nrhs in ((False, 1), (True, 3)):
+            sgn.sgn_tune_set(lat, prec, multi, 0, 1)
+            ref = apply(nrhs)
+            tried = 0
+            for cap in (0, 384, 192, 96):
+                try:
+                    sgn.sgn_tune_set(lat, prec, multi, cap, 2)
+                except sgn.SgnError:
+                    continue  # no brick of this cap fits the lattice
+                tried += 1
+                got = apply(nrhs)
+                for y0, y1 in zip(ref, got):
+                    assert torch.equal(y0, y1), f"cap {cap}, nrhs {nrhs}"
+            assert tried >= 1
+            for b, mu, y in zip(srcs, mus, ref):
+                out = torch.empty(b.size, dtype=torch.complex128 if prec == sgn.F64 else torch.complex64, device="cuda")
+                sgn.sgn_spinor_unpack(lat, y, out, prec)
+                got = host(out).astype(np.complex128)
+                if lat.V <= 20000:
+                    assert _rel(got, W.apply(b, mu)) < TOL[prec]
+                else:
+                    sites = np.random.default_rng(3).choice(lat.V, 400, replace=False)
+                    want = W.apply_sites(b, mu, sites)
+                    g = got.reshape(lat.V, 4, 3)[sites]
+                    assert np.linalg.norm(g - want) / np.linalg.norm(want) < TOL[prec]
+    finally:
+        sgn.sgn_tune_set(lat, prec, False, 0, 1)
+        sgn.sgn_tune_set(lat, prec, True, 0, 1)
+
+
+def test_tune_set_refusals():
+    dims = (4, 4, 4, 5)
+    lat = lattice(synth.gauge_field(dims, 0.4, 0), dims)
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_tune_set(lat, sgn.F32, False, 0, 2)   # odd L_t: no brick
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_tune_set(lat, sgn.F32, False, 0, 3)
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_tune_set(lat, sgn.F32, False, -1, 1)
