@@ -489,11 +489,16 @@ sgn_status multishift_bicgstab(const sgn_problem *pb, int nprob, const sgn_ratio
  * below theta16 ||y||); the recurrences, coefficients and basis stay FP64.  There
  * are no reliable updates: the stencil's rounding enters the Lanczos relation
  * weighted by the size of the late coefficients, which shrink with tau, so the
- * thresholds set the accuracy.  delta and graph are ignored.  stats: iterations, matvecs,
+ * thresholds set the accuracy.  delta is ignored.  stats: iterations, matvecs,
  * shift_residual (tau_i / ||y||; with o->verify the FP64 true residuals), residual,
- * krylov_ms, small_ms (Givens updates).  Problems run one after another.
- * Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after maxiter (x holds the last
- * iterate), SGN_ERR_BREAKDOWN on a Lanczos breakdown (w^^H v vanishing). */
+ * krylov_ms, small_ms (Givens updates).  Several problems run in lockstep: per step
+ * one launch for all of them of each stencil application (grouped by lattice into
+ * multi-RHS launches), of the update and of the two scalar steps, the step index
+ * kept on the device; a chunk of o->poll steps is captured once as a HIP graph
+ * (o->graph is ignored) and replayed until a problem changes precision or a quarter
+ * of the launch has converged.  Synchronises `stream`.  SGN_ERR_NOT_CONVERGED after
+ * maxiter (x holds the last iterate), SGN_ERR_BREAKDOWN on a Lanczos breakdown
+ * (w^^H v vanishing; for a batch, the whole call). */
 sgn_status multishift_qmr(const sgn_problem *pb, int nprob, const sgn_rational *r, const sgn_ms_opts *o,
                           sgn_stats *stats, void *stream);
 

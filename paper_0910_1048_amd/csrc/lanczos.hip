@@ -19,8 +19,12 @@
 //
 // The second part of the file runs the same recurrence on c^2 H_W^2 for the
 // multishift QMR solver (multishift_qmr).
+#include <algorithm>
 #include <chrono>
 #include <complex>
+#include <map>
+#include <memory>
+#include <string>
 #include <vector>
 
 #include "field_io.h"
@@ -41,7 +45,7 @@ struct LzScalars {
     int *flag;   // [k]   breakdown flags
 };
 
-__global__ void lz_alpha_kernel(const z64 *partials, int nblk, LzScalars S, int j)
+__device__ __forceinline__ void lz_alpha_body(const z64 *partials, int nblk, const LzScalars &S, int j)
 {
     double re = 0.0, im = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
@@ -56,8 +60,12 @@ __global__ void lz_alpha_kernel(const z64 *partials, int nblk, LzScalars S, int 
         S.alpha[j] = S.sv[j].r * cmulc(S.tw[j], d);  // conj(t_j) s_j (wh^H u)
     }
 }
+__global__ void lz_alpha_kernel(const z64 *partials, int nblk, LzScalars S, int j)
+{
+    lz_alpha_body(partials, nblk, S, j);
+}
 
-__global__ void lz_step_kernel(const z64 *partials, int nblk, LzScalars S, int j, double tol)
+__device__ __forceinline__ void lz_step_body(const z64 *partials, int nblk, const LzScalars &S, int j, double tol)
 {
     double a = 0.0, br = 0.0, bi = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
@@ -83,6 +91,10 @@ __global__ void lz_step_kernel(const z64 *partials, int nblk, LzScalars S, int j
         S.flag[j] = (!(delta > 0.0) || !(sqrt(norm2(wv)) > tol * sqrt(vv * ww))) ? 1 : 0;
     }
 }
+__global__ void lz_step_kernel(const z64 *partials, int nblk, LzScalars S, int j, double tol)
+{
+    lz_step_body(partials, nblk, S, j, tol);
+}
 
 __device__ __forceinline__ z64 ld2(const double2 *p, int64_t i)
 {
@@ -91,13 +103,14 @@ __device__ __forceinline__ z64 ld2(const double2 *p, int64_t i)
 }
 
 // One thread per pair of complex entries (e0 = 2*c2*V + s, e1 = e0 + V) so that
-// the FP32 stencil outputs ([6][V] float4) and FP64 vectors line up.
+// the FP32 stencil outputs ([6][V] float4) and FP64 vectors line up.  vc, wc (may be null): second
+// FP64 copies of vh_{j+1}, wh_{j+1} (the fixed stencil inputs of a lockstep batch).
 template <bool F32>
-__global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const void *z_, const double2 *vj,
-                                                        const double2 *vjm, const double2 *wj, const double2 *wjm,
-                                                        double2 *vn, double2 *wn, float4 *vn32, float4 *wn32,
-                                                        LzScalars S, int j, int V /* component stride */,
-                                                        z64 *partials)
+__device__ __forceinline__ void lz_update_body(const void *u_, const void *z_, const double2 *vj, const double2 *vjm,
+                                               const double2 *wj, const double2 *wjm, double2 *vn, double2 *wn,
+                                               float4 *vn32, float4 *wn32, double2 *vc, double2 *wc,
+                                               const LzScalars &S, int j, int V /* component stride */,
+                                               z64 *partials)
 {
     // coefficients of the two three-term recurrences
     const double s0 = S.sv[j].r;
@@ -145,6 +158,12 @@ __global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const vo
             vn32[p] = make_float4((float)v0.r, (float)v0.i, (float)v1.r, (float)v1.i);
             wn32[p] = make_float4((float)w0.r, (float)w0.i, (float)w1.r, (float)w1.i);
         }
+        if (vc) {  // uniform
+            vc[e0] = make_double2(v0.r, v0.i);
+            vc[e1] = make_double2(v1.r, v1.i);
+            wc[e0] = make_double2(w0.r, w0.i);
+            wc[e1] = make_double2(w1.r, w1.i);
+        }
         a += norm2(v0) + norm2(v1);
         const z64 d = cmulc(w0, v0) + cmulc(w1, v1);
         br += d.r;
@@ -158,6 +177,15 @@ __global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const vo
         partials[2 * blockIdx.x] = {v[0], v[1]};
         partials[2 * blockIdx.x + 1] = {v[2], v[3]};
     }
+}
+template <bool F32>
+__global__ void __launch_bounds__(256) lz_update_kernel(const void *u_, const void *z_, const double2 *vj,
+                                                        const double2 *vjm, const double2 *wj, const double2 *wjm,
+                                                        double2 *vn, double2 *wn, float4 *vn32, float4 *wn32,
+                                                        double2 *vc, double2 *wc, LzScalars S, int j, int V,
+                                                        z64 *partials)
+{
+    lz_update_body<F32>(u_, z_, vj, vjm, wj, wjm, vn, wn, vn32, wn32, vc, wc, S, j, V, partials);
 }
 
 constexpr int kLiftChunk = 64;
@@ -210,14 +238,16 @@ struct PooledBasis {
     size_t bytes, cap;
     const char *who;
     std::vector<void *> slots;
+    size_t *shared_next = nullptr;  // bases sharing one pool (a batch): the next unused pool buffer
     PooledBasis(Context &c, size_t b, size_t cap_, const char *w) : ctx(c), bytes(b), cap(cap_), who(w) {}
     void *operator[](int j) const { return slots[j]; }
     void ensure(int upto)  // slots 0 .. upto exist
     {
         auto &pool = ctx.basis_pools[bytes];
         while ((int)slots.size() <= upto) {
-            const size_t idx = slots.size();
-            if (idx >= cap) throw Failure{SGN_ERR_NOMEM, std::string(who) + ": Krylov basis exceeds its slot budget"};
+            if (slots.size() >= cap)
+                throw Failure{SGN_ERR_NOMEM, std::string(who) + ": Krylov basis exceeds its slot budget"};
+            const size_t idx = shared_next ? (*shared_next)++ : slots.size();
             if (idx == pool.size()) {
                 void *v = nullptr;
                 if (hipMalloc(&v, bytes) != hipSuccess) {
@@ -451,11 +481,13 @@ extern "C" sgn_status sign_lanczos_2sided(sgn_lattice l, double mu, const void *
             if (f32)
                 hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb), dim3(256), 0, s, u32.p, z32.p,
                                    (const double2 *)Vj(j), vjm, (const double2 *)Wj(j), wjm, (double2 *)vn,
-                                   (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, S, j, (int)Sst, part);
+                                   (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, (double2 *)nullptr,
+                                   (double2 *)nullptr, S, j, (int)Sst, part);
             else
                 hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb), dim3(256), 0, s, u.p, z.p,
                                    (const double2 *)Vj(j), vjm, (const double2 *)Wj(j), wjm, (double2 *)vn,
-                                   (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)Sst, part);
+                                   (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, (double2 *)nullptr,
+                                   (double2 *)nullptr, S, j, (int)Sst, part);
             hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(256), 0, s, part, nvb, S, j, 1e-14);
             SGN_HIP(hipGetLastError());
         };
@@ -606,192 +638,319 @@ struct QmrShift {
     }
 };
 
-sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, sgn_stats *st, hipStream_t s)
+// One problem of multishift QMR: setup, the Lanczos steps (launched one by one for a single problem,
+// or by QmrBatch for several in lockstep), the host's absorption of finished steps (a Givens column
+// per shift), the precision schedule, and the final lift.
+class QmrSolve {
+  public:
+    // pool_next (a batch): the next unused buffer of each per-size pool, shared by the batch's problems
+    QmrSolve(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s,
+             std::map<size_t, size_t> *pool_next = nullptr)
+        : pb_(pb), rf_(rf), o_(o), s_(s), lat_(*as_lattice(pb.lat)), ctx_(*lat_.ctx), pool_next_(pool_next)
+    {
+    }
+    // x = x_P, y = c H (I - P) b; false if y = 0 (x = x_P is written, nothing else to do)
+    bool setup(sgn_stats *st, bool batch);
+    void step(int j);  // one Lanczos step on A' (single-problem form)
+    // the steps j0 .. launched-1 have run: their coefficients into every shift's QR; true once done
+    bool absorb(int j0, int launched);
+    bool switch_precision();  // the mixed schedule after a chunk; true if the phase changed
+    sgn_status finish(sgn_stats *st);
+    sgn_status run(sgn_stats *st);
+
+  private:
+    friend class QmrBatch;
+    const sgn_problem &pb_;
+    const sgn_rational &rf_;
+    const sgn_ms_opts &o_;
+    hipStream_t s_;
+    Lattice &lat_;
+    Context &ctx_;
+    std::map<size_t, size_t> *pool_next_;
+    int64_t V_ = 0, Sst_ = 0, nc_ = 0, ni_ = 0;
+    size_t b64_ = 0, i64_ = 0, b32_ = 0;
+    bool mixed_ = false, f32_ = false;
+    double theta32_ = 0.0, theta16_ = 0.0, c2_ = 0.0, ynorm_ = 0.0, small_ms_ = 0.0;
+    sgn_prec sp_ = SGN_PREC_F64;
+    int ns_ = 0, maxiter_ = 0, poll_ = 4, nst_ = 0, nvb_ = 0;
+    OpSpec opA_, opAh_;
+    std::unique_ptr<DevBuf> rcan_, y_, tmp_, Wb_, u_, z_, v32_, w32_, t32_, u32_, z32_, scal_;
+    std::unique_ptr<PooledBasis> basis_;
+    LzScalars S_{};
+    z64 *part_ = nullptr;
+    std::vector<QmrShift> G_;
+    std::vector<z64> halpha_, hsub_, hsup_;
+    std::vector<int> hflag_;
+    sgn_status result_ = SGN_OK;
+    int launched_ = 0, kused_ = -1;
+    std::chrono::steady_clock::time_point t_start_, t_kry_;
+    // batch form: stencil inputs at fixed addresses, a device step counter and done flag, own partials
+    std::unique_ptr<DevBuf> vcur_, wcur_, bpart_, dslot_buf_;
+    void **dslots_ = nullptr;  // device copy of the basis slot table (batch form)
+    size_t dslots_n_ = 0;
+    int *dstep_ = nullptr, *ddone_ = nullptr;
+    z64 *part1_ = nullptr, *part2_ = nullptr;
+    void ensure_slots(int upto);  // slots 0 .. upto, and their device table
+
+    char *Wj(int j) const { return static_cast<char *>(Wb_->p) + (size_t)(j % 3) * i64_; }
+};
+
+bool QmrSolve::setup(sgn_stats *st, bool batch)
 {
-    const auto t_start = std::chrono::steady_clock::now();
-    Lattice &lat = *as_lattice(pb.lat);
-    Context &ctx = *lat.ctx;
-    SGN_HIP(hipSetDevice(ctx.device));
-    const int64_t V = lat.V, Sst = lat.S, nc = 12 * V, ni = 12 * Sst;
-    const size_t b64 = (size_t)nc * 16, i64 = (size_t)ni * 16, b32 = (size_t)ni * 8;
+    t_start_ = std::chrono::steady_clock::now();
+    SGN_HIP(hipSetDevice(ctx_.device));
+    V_ = lat_.V;
+    Sst_ = lat_.S;
+    nc_ = 12 * V_;
+    ni_ = 12 * Sst_;
+    b64_ = (size_t)nc_ * 16;
+    i64_ = (size_t)ni_ * 16;
+    b32_ = (size_t)ni_ * 8;
     // precision schedule: FP64 steps while the largest quasi-residual is above theta32 ||y||,
     // then the stencil in FP32 (and with FP16 links below theta16 ||y|| for SGN_PREC_F32_H16);
     // the recurrences and the basis stay FP64
-    const bool mixed = o.prec != SGN_PREC_F64;
-    const double theta32 = mixed ? (o.theta32 > 0 ? o.theta32 : 1e-3) : 0.0;
-    const double theta16 = o.prec == SGN_PREC_F32_H16 ? (o.theta16 > 0 ? o.theta16 : 1e-6) : 0.0;
-    sgn_prec sp = SGN_PREC_F64;
-    bool f32 = false;
-    const int ns = rf.s;
-    const double c2 = rf.c * rf.c;
-    const int maxiter = o.maxiter > 0 ? o.maxiter : 10000;
-    const int poll = o.poll > 0 ? o.poll : 4;
+    mixed_ = o_.prec != SGN_PREC_F64;
+    theta32_ = mixed_ ? (o_.theta32 > 0 ? o_.theta32 : 1e-3) : 0.0;
+    theta16_ = o_.prec == SGN_PREC_F32_H16 ? (o_.theta16 > 0 ? o_.theta16 : 1e-6) : 0.0;
+    ns_ = rf_.s;
+    c2_ = rf_.c * rf_.c;
+    maxiter_ = o_.maxiter > 0 ? o_.maxiter : 10000;
+    poll_ = o_.poll > 0 ? o_.poll : 4;
     if (st) {
         *st = sgn_stats{};
-        st->nshift = ns;
+        st->nshift = ns_;
     }
-    OpSpec opA, opAh;
-    opA.mu = pb.mu;
-    opAh.mu = -pb.mu;
+    opA_.mu = pb_.mu;
+    opAh_.mu = -pb_.mu;
 
     // x <- x_P, y = c H (I - P) b
-    DevBuf rcan(b64), y(i64), tmp(i64);
-    deflation_prologue(ctx, pb.defl, nc, pb.b, pb.x, rcan.p, nullptr, s);
-    pack_spinor(lat, rcan.p, tmp.p, SGN_PREC_F64, s);
+    rcan_ = std::make_unique<DevBuf>(b64_);
+    y_ = std::make_unique<DevBuf>(i64_);
+    tmp_ = std::make_unique<DevBuf>(i64_);
+    deflation_prologue(ctx_, pb_.defl, nc_, pb_.b, pb_.x, rcan_->p, nullptr, s_);
+    pack_spinor(lat_, rcan_->p, tmp_->p, SGN_PREC_F64, s_);
     {
         Epilogue ep;
-        ep.a = rf.c;
-        dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, y.p, ep, s);
+        ep.a = rf_.c;
+        dslash_launch(lat_, SGN_PREC_F64, opA_, tmp_->p, y_->p, ep, s_);
     }
-    const double ynorm = norm_sync(ctx, y.p, ni, false, s);
-    SGN_REQUIRE(std::isfinite(ynorm), "multishift_qmr: b contains NaN or Inf");
-    if (ynorm == 0.0) {  // x = x_P
-        if (pb.x_shift)
-            for (int i = 0; i < ns; ++i)
-                if (pb.x_shift[i]) SGN_HIP(hipMemsetAsync(pb.x_shift[i], 0, b64, s));
-        SGN_HIP(hipStreamSynchronize(s));
-        return SGN_OK;
+    ynorm_ = norm_sync(ctx_, y_->p, ni_, false, s_);
+    SGN_REQUIRE(std::isfinite(ynorm_), "multishift_qmr: b contains NaN or Inf");
+    if (ynorm_ == 0.0) {  // x = x_P
+        if (pb_.x_shift)
+            for (int i = 0; i < ns_; ++i)
+                if (pb_.x_shift[i]) SGN_HIP(hipMemsetAsync(pb_.x_shift[i], 0, b64_, s_));
+        SGN_HIP(hipStreamSynchronize(s_));
+        return false;
     }
 
     // stored basis: slot j holds vh_j (FP64, internal layout), from the context's pool
     size_t cap;
-    if (o.basis_slots > 0) {
-        cap = (size_t)o.basis_slots;
+    if (o_.basis_slots > 0) {
+        cap = (size_t)o_.basis_slots;
     } else {
         size_t fr = 0, tot = 0;
         SGN_HIP(hipMemGetInfo(&fr, &tot));
-        cap = ctx.basis_pools[i64].size() + fr / 2 / i64;
+        cap = ctx_.basis_pools[i64_].size() + fr / 2 / i64_;
     }
-    PooledBasis basis(ctx, i64, cap, "multishift_qmr");
-    basis.ensure(0);
-    DevBuf Wb(3 * i64), u(i64), z(i64);
-    DevBuf v32(mixed ? b32 : 0), w32(mixed ? b32 : 0), t32(mixed ? b32 : 0), u32(mixed ? b32 : 0),
-        z32(mixed ? b32 : 0);
-    const size_t nscal = sizeof(z64) * (5 * (size_t)maxiter + 2) + sizeof(int) * maxiter;
-    DevBuf scal(nscal);
-    LzScalars S;
-    S.alpha = scal.as<z64>();
-    S.hsub = S.alpha + maxiter;
-    S.hsup = S.hsub + maxiter;
-    S.sv = S.hsup + maxiter;
-    S.tw = S.sv + (maxiter + 1);
-    S.flag = reinterpret_cast<int *>(S.tw + (maxiter + 1));
-    auto Wj = [&](int j) { return static_cast<char *>(Wb.p) + (size_t)(j % 3) * i64; };
-    const z64 s0 = {1.0 / ynorm, 0.0};  // v_1 = s_0 y,  w_1 = t_0 y = v_1
-    SGN_HIP(hipMemsetAsync(scal.p, 0, nscal, s));
-    SGN_HIP(hipMemcpyAsync(S.sv, &s0, sizeof(z64), hipMemcpyHostToDevice, s));
-    SGN_HIP(hipMemcpyAsync(S.tw, &s0, sizeof(z64), hipMemcpyHostToDevice, s));
-    SGN_HIP(hipMemcpyAsync(basis[0], y.p, i64, hipMemcpyDeviceToDevice, s));
-    SGN_HIP(hipMemcpyAsync(Wj(0), y.p, i64, hipMemcpyDeviceToDevice, s));
-    const int nst = dslash_blocks(lat);
-    const int nvb = vec_blocks(6 * Sst);
-    z64 *part = static_cast<z64 *>(ctx.ensure_partials(sizeof(z64) * std::max(nst, 2 * nvb)));
-
-    // one Lanczos step on A': alpha_j, vh_{j+1}, wh_{j+1}, h_{j+1,j}, h_{j,j+1}
-    auto step = [&](int j) {
-        dslash_launch(lat, sp, opA, f32 ? v32.p : basis[j], f32 ? t32.p : tmp.p, Epilogue{}, s);
-        Epilogue ep;  // u = c^2 H (H vh_j), partials of wh_j^H u
-        ep.a = c2;
-        ep.w = f32 ? w32.p : Wj(j);
-        ep.partials = part;
-        const int nb1 = dslash_launch(lat, sp, opA, f32 ? t32.p : tmp.p, f32 ? u32.p : u.p, ep, s);
-        hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(256), 0, s, part, nb1, S, j);
-        dslash_launch(lat, sp, opAh, f32 ? w32.p : Wj(j), f32 ? t32.p : tmp.p, Epilogue{}, s);
-        Epilogue ez;  // z = c^2 H^H (H^H wh_j)
-        ez.a = c2;
-        dslash_launch(lat, sp, opAh, f32 ? t32.p : tmp.p, f32 ? z32.p : z.p, ez, s);
-        const double2 *vjm = j > 0 ? static_cast<const double2 *>(basis[j - 1]) : nullptr;
-        const double2 *wjm = j > 0 ? reinterpret_cast<const double2 *>(Wj(j - 1)) : nullptr;
-        const int pr = ctx.prof_start(s, SGN_K_SEED_UPDATE);
-        if (f32)
-            hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb), dim3(256), 0, s, u32.p, z32.p,
-                               (const double2 *)basis[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1],
-                               (double2 *)Wj(j + 1), (float4 *)v32.p, (float4 *)w32.p, S, j, (int)Sst, part);
-        else
-            hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb), dim3(256), 0, s, u.p, z.p,
-                               (const double2 *)basis[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1],
-                               (double2 *)Wj(j + 1), (float4 *)nullptr, (float4 *)nullptr, S, j, (int)Sst, part);
-        const double io = (f32 ? 2.0 * b32 : 2.0 * i64) + (j > 0 ? 4.0 : 2.0) * i64 + 2.0 * i64 + (f32 ? 2.0 * b32 : 0.0);
-        ctx.prof_stop(pr, s, SGN_K_SEED_UPDATE, io, 40.0 * ni);
-        hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(256), 0, s, part, nvb, S, j, 1e-14);
-        SGN_HIP(hipGetLastError());
-    };
-
-    std::vector<QmrShift> G(ns);
-    for (int i = 0; i < ns; ++i) {
-        G[i].sigma = rf.sigma[i];
-        G[i].g.assign(1, cplx(ynorm, 0.0));
+    basis_ = std::make_unique<PooledBasis>(ctx_, i64_, cap, "multishift_qmr");
+    if (pool_next_) basis_->shared_next = &(*pool_next_)[i64_];
+    basis_->ensure(0);
+    Wb_ = std::make_unique<DevBuf>(3 * i64_);
+    u_ = std::make_unique<DevBuf>(i64_);
+    z_ = std::make_unique<DevBuf>(i64_);
+    const size_t f = mixed_ ? b32_ : 0;
+    v32_ = std::make_unique<DevBuf>(f);
+    w32_ = std::make_unique<DevBuf>(f);
+    t32_ = std::make_unique<DevBuf>(f);
+    u32_ = std::make_unique<DevBuf>(f);
+    z32_ = std::make_unique<DevBuf>(f);
+    const size_t nscal = sizeof(z64) * (5 * (size_t)maxiter_ + 2) + sizeof(int) * (maxiter_ + 2);
+    scal_ = std::make_unique<DevBuf>(nscal);
+    S_.alpha = scal_->as<z64>();
+    S_.hsub = S_.alpha + maxiter_;
+    S_.hsup = S_.hsub + maxiter_;
+    S_.sv = S_.hsup + maxiter_;
+    S_.tw = S_.sv + (maxiter_ + 1);
+    S_.flag = reinterpret_cast<int *>(S_.tw + (maxiter_ + 1));
+    const z64 s0 = {1.0 / ynorm_, 0.0};  // v_1 = s_0 y,  w_1 = t_0 y = v_1
+    SGN_HIP(hipMemsetAsync(scal_->p, 0, nscal, s_));
+    SGN_HIP(hipMemcpyAsync(S_.sv, &s0, sizeof(z64), hipMemcpyHostToDevice, s_));
+    SGN_HIP(hipMemcpyAsync(S_.tw, &s0, sizeof(z64), hipMemcpyHostToDevice, s_));
+    SGN_HIP(hipMemcpyAsync((*basis_)[0], y_->p, i64_, hipMemcpyDeviceToDevice, s_));
+    SGN_HIP(hipMemcpyAsync(Wj(0), y_->p, i64_, hipMemcpyDeviceToDevice, s_));
+    nst_ = dslash_blocks(lat_);
+    nvb_ = vec_blocks(6 * Sst_);
+    if (batch) {
+        // the step counter and done flag live after the flags; own partials (the context's are shared)
+        dstep_ = S_.flag + maxiter_;
+        ddone_ = dstep_ + 1;
+        vcur_ = std::make_unique<DevBuf>(i64_);
+        wcur_ = std::make_unique<DevBuf>(i64_);
+        SGN_HIP(hipMemcpyAsync(vcur_->p, y_->p, i64_, hipMemcpyDeviceToDevice, s_));
+        SGN_HIP(hipMemcpyAsync(wcur_->p, y_->p, i64_, hipMemcpyDeviceToDevice, s_));
+        const size_t n1 = (size_t)nst_, n2 = 2 * (size_t)kMaxBlocks;
+        bpart_ = std::make_unique<DevBuf>(sizeof(z64) * (n1 + n2));
+        part1_ = bpart_->as<z64>();
+        part2_ = part1_ + n1;
+        dslot_buf_ = std::make_unique<DevBuf>(sizeof(void *) * ((size_t)maxiter_ + poll_ + 2));
+        dslots_ = dslot_buf_->as<void *>();
+        ensure_slots(0);
+    } else {
+        part_ = static_cast<z64 *>(ctx_.ensure_partials(sizeof(z64) * std::max(nst_, 2 * nvb_)));
     }
-    std::vector<z64> halpha(maxiter), hsub(maxiter), hsup(maxiter);
-    std::vector<int> hflag(maxiter);
-    sgn_status result = SGN_OK;
-    double small_ms = 0.0;
-    int launched = 0, kused = -1;
-    const auto t_kry = std::chrono::steady_clock::now();
-    while (kused < 0) {
-        const int chunk = std::min(poll, maxiter - launched);
-        basis.ensure(launched + chunk);
-        for (int q = 0; q < chunk; ++q) step(launched + q);
-        const int j0 = launched;
-        launched += chunk;
-        const int nn = launched - j0;
-        SGN_HIP(hipMemcpyAsync(halpha.data() + j0, S.alpha + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s));
-        SGN_HIP(hipMemcpyAsync(hsub.data() + j0, S.hsub + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s));
-        SGN_HIP(hipMemcpyAsync(hsup.data() + j0, S.hsup + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s));
-        SGN_HIP(hipMemcpyAsync(hflag.data() + j0, S.flag + j0, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
-        SGN_HIP(hipStreamSynchronize(s));
-        const auto t0 = std::chrono::steady_clock::now();
-        for (int j = j0; j < launched; ++j) {
-            const cplx al(halpha[j].r, halpha[j].i), hp = j > 0 ? cplx(hsup[j - 1].r, hsup[j - 1].i) : cplx(0.0);
-            double tmax = 0.0;
-            for (auto &g : G) {
-                if (!g.add_column(j, hp, al, hsub[j].r))
-                    throw Failure{SGN_ERR_BREAKDOWN, "multishift_qmr: singular shifted tridiagonal"};
-                tmax = std::max(tmax, g.tau());
-            }
-            if (!std::isfinite(tmax))
-                throw Failure{SGN_ERR_BREAKDOWN, "multishift_qmr: non-finite Lanczos coefficients"};
-            if (tmax <= o.tol * ynorm || hsub[j].r == 0.0) {  // converged, or invariant subspace (exact)
-                kused = j + 1;
-                break;
-            }
-            if (hflag[j])
-                throw Failure{SGN_ERR_BREAKDOWN, "two-sided Lanczos breakdown at step " + std::to_string(j + 1)};
-        }
-        small_ms += ms_since(t0);
-        if (kused < 0 && launched >= maxiter) {
-            kused = launched;
-            result = SGN_ERR_NOT_CONVERGED;
-        }
-        if (kused < 0 && mixed) {
-            double tmax = 0.0;
-            for (const auto &g : G) tmax = std::max(tmax, g.tau());
-            if (!f32 && tmax < theta32 * ynorm) {  // FP32 copies of the current vh_j, wh_j
-                convert_64_to_32(basis[launched], v32.p, Sst, s);
-                convert_64_to_32(Wj(launched), w32.p, Sst, s);
-                f32 = true;
-                sp = SGN_PREC_F32;
-            }
-            if (f32 && sp == SGN_PREC_F32 && tmax < theta16 * ynorm) sp = SGN_PREC_F32_H16;
-        }
+    G_.assign(ns_, QmrShift{});
+    for (int i = 0; i < ns_; ++i) {
+        G_[i].sigma = rf_.sigma[i];
+        G_[i].g.assign(1, cplx(ynorm_, 0.0));
     }
-    const double kry_ms = ms_since(t_kry);
+    halpha_.assign(maxiter_, {});
+    hsub_.assign(maxiter_, {});
+    hsup_.assign(maxiter_, {});
+    hflag_.assign(maxiter_, 0);
+    SGN_HIP(hipStreamSynchronize(s_));
+    t_kry_ = std::chrono::steady_clock::now();
+    return true;
+}
 
+// one Lanczos step on A': alpha_j, vh_{j+1}, wh_{j+1}, h_{j+1,j}, h_{j,j+1}
+void QmrSolve::step(int j)
+{
+    const bool f32 = f32_;
+    PooledBasis &basis = *basis_;
+    char *tmp = static_cast<char *>(tmp_->p), *u = static_cast<char *>(u_->p), *z = static_cast<char *>(z_->p);
+    dslash_launch(lat_, sp_, opA_, f32 ? v32_->p : basis[j], f32 ? t32_->p : tmp, Epilogue{}, s_);
+    Epilogue ep;  // u = c^2 H (H vh_j), partials of wh_j^H u
+    ep.a = c2_;
+    ep.w = f32 ? w32_->p : Wj(j);
+    ep.partials = part_;
+    const int nb1 = dslash_launch(lat_, sp_, opA_, f32 ? t32_->p : tmp, f32 ? u32_->p : u, ep, s_);
+    hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(256), 0, s_, part_, nb1, S_, j);
+    dslash_launch(lat_, sp_, opAh_, f32 ? w32_->p : Wj(j), f32 ? t32_->p : tmp, Epilogue{}, s_);
+    Epilogue ez;  // z = c^2 H^H (H^H wh_j)
+    ez.a = c2_;
+    dslash_launch(lat_, sp_, opAh_, f32 ? t32_->p : tmp, f32 ? z32_->p : z, ez, s_);
+    const double2 *vjm = j > 0 ? static_cast<const double2 *>(basis[j - 1]) : nullptr;
+    const double2 *wjm = j > 0 ? reinterpret_cast<const double2 *>(Wj(j - 1)) : nullptr;
+    const int pr = ctx_.prof_start(s_, SGN_K_SEED_UPDATE);
+    if (f32)
+        hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb_), dim3(256), 0, s_, u32_->p, z32_->p,
+                           (const double2 *)basis[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1],
+                           (double2 *)Wj(j + 1), (float4 *)v32_->p, (float4 *)w32_->p, (double2 *)nullptr,
+                           (double2 *)nullptr, S_, j, (int)Sst_, part_);
+    else
+        hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb_), dim3(256), 0, s_, u, z, (const double2 *)basis[j],
+                           vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1], (double2 *)Wj(j + 1),
+                           (float4 *)nullptr, (float4 *)nullptr, (double2 *)nullptr, (double2 *)nullptr, S_, j,
+                           (int)Sst_, part_);
+    const double io = (f32 ? 2.0 * b32_ : 2.0 * i64_) + (j > 0 ? 4.0 : 2.0) * i64_ + 2.0 * i64_ + (f32 ? 2.0 * b32_ : 0.0);
+    ctx_.prof_stop(pr, s_, SGN_K_SEED_UPDATE, io, 40.0 * ni_);
+    hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(256), 0, s_, part_, nvb_, S_, j, 1e-14);
+    SGN_HIP(hipGetLastError());
+}
+
+void QmrSolve::ensure_slots(int upto)
+{
+    basis_->ensure(upto);
+    const size_t n = basis_->slots.size();
+    if (dslots_ && n > dslots_n_) {
+        SGN_HIP(hipMemcpy(dslots_ + dslots_n_, basis_->slots.data() + dslots_n_, sizeof(void *) * (n - dslots_n_),
+                          hipMemcpyHostToDevice));
+        dslots_n_ = n;
+    }
+}
+
+bool QmrSolve::absorb(int j0, int launched)
+{
+    const int nn = launched - j0;
+    SGN_HIP(hipMemcpyAsync(halpha_.data() + j0, S_.alpha + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s_));
+    SGN_HIP(hipMemcpyAsync(hsub_.data() + j0, S_.hsub + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s_));
+    SGN_HIP(hipMemcpyAsync(hsup_.data() + j0, S_.hsup + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s_));
+    SGN_HIP(hipMemcpyAsync(hflag_.data() + j0, S_.flag + j0, sizeof(int) * nn, hipMemcpyDeviceToHost, s_));
+    SGN_HIP(hipStreamSynchronize(s_));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int j = j0; j < launched; ++j) {
+        const cplx al(halpha_[j].r, halpha_[j].i), hp = j > 0 ? cplx(hsup_[j - 1].r, hsup_[j - 1].i) : cplx(0.0);
+        double tmax = 0.0;
+        for (auto &g : G_) {
+            if (!g.add_column(j, hp, al, hsub_[j].r))
+                throw Failure{SGN_ERR_BREAKDOWN, "multishift_qmr: singular shifted tridiagonal"};
+            tmax = std::max(tmax, g.tau());
+        }
+        if (!std::isfinite(tmax)) throw Failure{SGN_ERR_BREAKDOWN, "multishift_qmr: non-finite Lanczos coefficients"};
+        if (tmax <= o_.tol * ynorm_ || hsub_[j].r == 0.0) {  // converged, or invariant subspace (exact)
+            kused_ = j + 1;
+            break;
+        }
+        if (hflag_[j]) throw Failure{SGN_ERR_BREAKDOWN, "two-sided Lanczos breakdown at step " + std::to_string(j + 1)};
+    }
+    small_ms_ += ms_since(t0);
+    launched_ = launched;
+    if (kused_ < 0 && launched >= maxiter_) {
+        kused_ = launched;
+        result_ = SGN_ERR_NOT_CONVERGED;
+    }
+    return kused_ >= 0;
+}
+
+bool QmrSolve::switch_precision()
+{
+    if (kused_ >= 0 || !mixed_) return false;
+    double tmax = 0.0;
+    for (const auto &g : G_) tmax = std::max(tmax, g.tau());
+    bool changed = false;
+    if (!f32_ && tmax < theta32_ * ynorm_) {  // FP32 copies of the current vh_j, wh_j
+        const void *vc = vcur_ ? vcur_->p : (*basis_)[launched_];
+        const void *wc = wcur_ ? wcur_->p : Wj(launched_);
+        convert_64_to_32(vc, v32_->p, Sst_, s_);
+        convert_64_to_32(wc, w32_->p, Sst_, s_);
+        f32_ = true;
+        sp_ = SGN_PREC_F32;
+        changed = true;
+    }
+    if (f32_ && sp_ == SGN_PREC_F32 && tmax < theta16_ * ynorm_) {
+        sp_ = SGN_PREC_F32_H16;
+        changed = true;
+    }
+    return changed;
+}
+
+sgn_status QmrSolve::run(sgn_stats *st)
+{
+    if (!setup(st, false)) return SGN_OK;
+    while (kused_ < 0) {
+        const int chunk = std::min(poll_, maxiter_ - launched_);
+        basis_->ensure(launched_ + chunk);
+        for (int q = 0; q < chunk; ++q) step(launched_ + q);
+        if (!absorb(launched_, launched_ + chunk)) switch_precision();
+    }
+    return finish(st);
+}
+
+sgn_status QmrSolve::finish(sgn_stats *st)
+{
+    const double kry_ms = ms_since(t_kry_);
+    const int kused = kused_;
+    const int ns = ns_;
+    const hipStream_t s = s_;
+    Lattice &lat = lat_;
+    Context &ctx = ctx_;
+    PooledBasis &basis = *basis_;
     // coefficients of the stored vectors: x_i = sum_j z_ij s_j vh_j
     std::vector<z64> hsv(kused);
-    SGN_HIP(hipMemcpy(hsv.data(), S.sv, sizeof(z64) * kused, hipMemcpyDeviceToHost));
+    SGN_HIP(hipMemcpy(hsv.data(), S_.sv, sizeof(z64) * kused, hipMemcpyDeviceToHost));
     std::vector<std::vector<cplx>> Z(ns);
-    for (int i = 0; i < ns; ++i) Z[i] = G[i].solve(kused);
+    for (int i = 0; i < ns; ++i) Z[i] = G_[i].solve(kused);
     // coefficient sets: 0 = sum_i omega_i x_i, then one per shift whose x_i is requested or
     // verified; all are uploaded before the first lift is queued (no buffer is reused)
     std::vector<int> sel;
     for (int i = 0; i < ns; ++i)
-        if ((pb.x_shift && pb.x_shift[i]) || o.verify) sel.push_back(i);
+        if ((pb_.x_shift && pb_.x_shift[i]) || o_.verify) sel.push_back(i);
     const size_t nset = 1 + sel.size();
     std::vector<z64> hcoef(nset * kused);
     for (int j = 0; j < kused; ++j) {
         cplx d = 0.0;
-        for (int i = 0; i < ns; ++i) d += rf.omega[i] * Z[i][j];
+        for (int i = 0; i < ns; ++i) d += rf_.omega[i] * Z[i][j];
         d *= hsv[j].r;
         hcoef[j] = {d.real(), d.imag()};
     }
@@ -805,50 +964,50 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
     SGN_HIP(hipMemcpy(dcoef.p, hcoef.data(), sizeof(z64) * hcoef.size(), hipMemcpyHostToDevice));
     auto lift = [&](size_t set, void *out) {
         const int pr = ctx.prof_start(s, SGN_K_LIFT);
-        basis.lift(dcoef.as<z64>() + set * kused, static_cast<const void *const *>(dtab.p), kused, ni, out, s);
-        ctx.prof_stop(pr, s, SGN_K_LIFT, (double)i64 * (kused + 1), 8.0 * ni * kused);
+        basis.lift(dcoef.as<z64>() + set * kused, static_cast<const void *const *>(dtab.p), kused, ni_, out, s);
+        ctx.prof_stop(pr, s, SGN_K_LIFT, (double)i64_ * (kused + 1), 8.0 * ni_ * kused);
     };
     // canonical v <- (I - P) v (rounding components along the deflated eigenvectors)
-    const bool deflated = pb.defl && pb.defl->m > 0;
-    DevBuf dfc(deflated ? sizeof(z64) * pb.defl->m : 0);
+    const bool deflated = pb_.defl && pb_.defl->m > 0;
+    DevBuf dfc(deflated ? sizeof(z64) * pb_.defl->m : 0);
     auto project_out = [&](void *v) {
         if (!deflated) return;
-        deflate_dots(pb.defl->L, pb.defl->m, v, nc, dfc.as<z64>(), ctx, s);
-        deflate_combine(v, {1.0, 0.0}, {-1.0, 0.0}, pb.defl->R, pb.defl->m, dfc.as<z64>(), nullptr, nc, s);
+        deflate_dots(pb_.defl->L, pb_.defl->m, v, nc_, dfc.as<z64>(), ctx, s);
+        deflate_combine(v, {1.0, 0.0}, {-1.0, 0.0}, pb_.defl->R, pb_.defl->m, dfc.as<z64>(), nullptr, nc_, s);
     };
-    lift(0, tmp.p);
-    unpack_spinor(lat, tmp.p, rcan.p, SGN_PREC_F64, s);
-    project_out(rcan.p);
-    axpby64({1.0, 0.0}, rcan.p, {1.0, 0.0}, pb.x, nc, s);
+    lift(0, tmp_->p);
+    unpack_spinor(lat, tmp_->p, rcan_->p, SGN_PREC_F64, s);
+    project_out(rcan_->p);
+    axpby64({1.0, 0.0}, rcan_->p, {1.0, 0.0}, pb_.x, nc_, s);
 
     // per-shift solutions: requested ones, and all of them for the FP64 residual check
     std::vector<double> res(ns);
-    for (int i = 0; i < ns; ++i) res[i] = G[i].tau() / ynorm;
+    for (int i = 0; i < ns; ++i) res[i] = G_[i].tau() / ynorm_;
     int extra_mv = 0;
-    DevBuf h(o.verify ? i64 : 0), q(o.verify ? i64 : 0);
+    DevBuf h(o_.verify ? i64_ : 0), q(o_.verify ? i64_ : 0);
     for (size_t k = 0; k < sel.size(); ++k) {
         const int i = sel[k];
-        lift(k + 1, tmp.p);
-        if (o.verify) {  // r_i = y - (c^2 H^2 - sigma_i) x_i in FP64
-            dslash_launch(lat, SGN_PREC_F64, opA, tmp.p, h.p, Epilogue{}, s);
+        lift(k + 1, tmp_->p);
+        if (o_.verify) {  // r_i = y - (c^2 H^2 - sigma_i) x_i in FP64
+            dslash_launch(lat, SGN_PREC_F64, opA_, tmp_->p, h.p, Epilogue{}, s);
             Epilogue ep;
-            ep.a = -c2;
-            ep.z = tmp.p;
-            ep.b = {rf.sigma[i], 0.0};
-            dslash_launch(lat, SGN_PREC_F64, opA, h.p, q.p, ep, s);
-            axpby64({1.0, 0.0}, y.p, {1.0, 0.0}, q.p, ni, s);
-            res[i] = norm_sync(ctx, q.p, ni, false, s) / ynorm;
+            ep.a = -c2_;
+            ep.z = tmp_->p;
+            ep.b = {rf_.sigma[i], 0.0};
+            dslash_launch(lat, SGN_PREC_F64, opA_, h.p, q.p, ep, s);
+            axpby64({1.0, 0.0}, y_->p, {1.0, 0.0}, q.p, ni_, s);
+            res[i] = norm_sync(ctx, q.p, ni_, false, s) / ynorm_;
             extra_mv += 2;
         }
-        if (pb.x_shift && pb.x_shift[i]) {
-            unpack_spinor(lat, tmp.p, pb.x_shift[i], SGN_PREC_F64, s);
-            project_out(pb.x_shift[i]);
+        if (pb_.x_shift && pb_.x_shift[i]) {
+            unpack_spinor(lat, tmp_->p, pb_.x_shift[i], SGN_PREC_F64, s);
+            project_out(pb_.x_shift[i]);
         }
     }
     SGN_HIP(hipStreamSynchronize(s));
     if (st) {
         st->iterations = kused;
-        st->matvecs = 4 * launched + 1 + extra_mv;
+        st->matvecs = 4 * launched_ + 1 + extra_mv;
         double mx = 0.0;
         for (int i = 0; i < ns; ++i) {
             st->shift_residual[i] = res[i];
@@ -856,12 +1015,255 @@ sgn_status qmr_one(const sgn_problem &pb, const sgn_rational &rf, const sgn_ms_o
         }
         st->residual = mx;
         st->krylov_ms = kry_ms;
-        st->small_ms = small_ms;
-        st->total_ms = ms_since(t_start);
+        st->small_ms = small_ms_;
+        st->total_ms = ms_since(t_start_);
+    }
+    return result_;
+}
+
+// Lockstep batch of QMR problems: one descriptor per problem in device memory; the step index comes
+// from the problem's device counter (advanced by its step kernel), so a chunk of steps is one graph
+// replayed until a problem changes precision or several have finished.  The stencils read the
+// current basis vectors from fixed copies (vcur, wcur in FP64; the FP32 copies in the FP32 phases).
+struct QbDesc {
+    LzScalars S;
+    int *step, *done;
+    void *const *slots;  // basis slot table
+    double2 *W[3];       // the W ring
+    double2 *vcur, *wcur;
+    float4 *v32, *w32;
+    const void *u, *z;   // stencil outputs of the problem's phase
+    z64 *part1, *part2;
+    int nb1, Sst;
+};
+
+__global__ void __launch_bounds__(256) qb_alpha_batch(const QbDesc *d)
+{
+    const QbDesc &D = d[blockIdx.x];
+    if (*D.done) return;
+    lz_alpha_body(D.part1, D.nb1, D.S, *D.step);
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(256) qb_update_batch(const QbDesc *d)
+{
+    const QbDesc &D = d[blockIdx.y];
+    if (*D.done) return;
+    const int j = *D.step;
+    const double2 *vj = static_cast<const double2 *>(D.slots[j]);
+    const double2 *vjm = j > 0 ? static_cast<const double2 *>(D.slots[j - 1]) : nullptr;
+    lz_update_body<F32>(D.u, D.z, vj, vjm, D.W[j % 3], j > 0 ? D.W[(j + 2) % 3] : nullptr,
+                        static_cast<double2 *>(D.slots[j + 1]), D.W[(j + 1) % 3], D.v32, D.w32,
+                        F32 ? nullptr : D.vcur, F32 ? nullptr : D.wcur, D.S, j, D.Sst, D.part2);
+}
+
+// nb: the grid width of the update that wrote the partials
+__global__ void __launch_bounds__(256) qb_step_batch(const QbDesc *d, int nb)
+{
+    const QbDesc &D = d[blockIdx.x];
+    if (*D.done) return;
+    const int j = *D.step;
+    lz_step_body(D.part2, nb, D.S, j, 1e-14);
+    if (threadIdx.x == 0) *D.step = j + 1;
+}
+
+class QmrBatch {
+  public:
+    QmrBatch(const sgn_problem *pb, int np, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s)
+        : o_(o), s_(s)
+    {
+        for (int k = 0; k < np; ++k) pr_.push_back(std::make_unique<QmrSolve>(pb[k], rf, o, s, &next_));
+        ctx_ = pr_.empty() ? nullptr : &pr_[0]->ctx_;
+        for (auto &p : pr_) SGN_REQUIRE(&p->ctx_ == ctx_, "multishift_qmr: problems of one call need one context");
+    }
+    ~QmrBatch()
+    {
+        drop_graph();
+        for (QbDesc *d : ddesc_)
+            if (d) (void)hipFree(d);
+    }
+    sgn_status run(sgn_stats *st);
+
+  private:
+    std::vector<std::unique_ptr<QmrSolve>> pr_;
+    std::map<size_t, size_t> next_;  // basis slots handed out from the context's pools, per vector size
+    const sgn_ms_opts &o_;
+    hipStream_t s_;
+    Context *ctx_ = nullptr;
+    std::vector<int> group_[3];  // problems of each stencil precision still stepping
+    std::vector<bool> active_;
+    QbDesc *ddesc_[3] = {nullptr, nullptr, nullptr};
+    size_t dcap_[3] = {0, 0, 0};
+    StencilBatch stb_[3][4];
+    int nvb_max_[3] = {0, 0, 0};
+    hipGraphExec_t gexec_ = nullptr;
+
+    static int phase_of(const QmrSolve &q) { return !q.f32_ ? 0 : (q.sp_ == SGN_PREC_F32 ? 1 : 2); }
+    void drop_graph()
+    {
+        if (gexec_) (void)hipGraphExecDestroy(gexec_);
+        gexec_ = nullptr;
+    }
+    void rebuild();
+    void launch_step(hipStream_t strm);
+    void iterate(int count);
+};
+
+void QmrBatch::rebuild()
+{
+    drop_graph();
+    for (auto &g : group_) g.clear();
+    for (int k = 0; k < (int)pr_.size(); ++k)
+        if (active_[k]) group_[phase_of(*pr_[k])].push_back(k);
+    for (int ph = 0; ph < 3; ++ph) {
+        const std::vector<int> &g = group_[ph];
+        std::vector<StencilJob> jobs[4];
+        std::vector<QbDesc> desc(g.size());
+        nvb_max_[ph] = 0;
+        for (size_t j = 0; j < g.size(); ++j) {
+            QmrSolve &q = *pr_[g[j]];
+            const bool f = ph >= 1;
+            void *vin = f ? q.v32_->p : q.vcur_->p, *win = f ? q.w32_->p : q.wcur_->p;
+            void *t = f ? q.t32_->p : q.tmp_->p, *u = f ? q.u32_->p : q.u_->p, *z = f ? q.z32_->p : q.z_->p;
+            jobs[0].push_back(StencilJob{&q.lat_, q.opA_, vin, t, Epilogue{}});
+            StencilJob j2{&q.lat_, q.opA_, t, u, Epilogue{}};  // u = c^2 H (H vh_j), partials of wh_j^H u
+            j2.ep.a = q.c2_;
+            j2.ep.w = win;
+            j2.ep.partials = q.part1_;
+            jobs[1].push_back(j2);
+            jobs[2].push_back(StencilJob{&q.lat_, q.opAh_, win, t, Epilogue{}});
+            StencilJob j4{&q.lat_, q.opAh_, t, z, Epilogue{}};  // z = c^2 H^H (H^H wh_j)
+            j4.ep.a = q.c2_;
+            jobs[3].push_back(j4);
+            char *wb = static_cast<char *>(q.Wb_->p);
+            desc[j] = QbDesc{q.S_, q.dstep_, q.ddone_, nullptr,
+                             {(double2 *)wb, (double2 *)(wb + q.i64_), (double2 *)(wb + 2 * q.i64_)},
+                             (double2 *)q.vcur_->p, (double2 *)q.wcur_->p, (float4 *)(f ? q.v32_->p : nullptr),
+                             (float4 *)(f ? q.w32_->p : nullptr), u, z, q.part1_, q.part2_, 0, (int)q.Sst_};
+            nvb_max_[ph] = std::max(nvb_max_[ph], q.nvb_);
+        }
+        const sgn_prec sp = ph == 0 ? SGN_PREC_F64 : (ph == 1 ? SGN_PREC_F32 : SGN_PREC_F32_H16);
+        for (int k = 0; k < 4; ++k) stb_[ph][k].prepare(jobs[k], sp);
+        if (g.empty()) continue;
+        for (size_t j = 0; j < g.size(); ++j) {
+            QmrSolve &q = *pr_[g[j]];
+            desc[j].nb1 = stb_[ph][1].blocks(j);
+            desc[j].slots = q.dslots_;
+        }
+        const size_t need = sizeof(QbDesc) * g.size();
+        if (need > dcap_[ph]) {
+            if (ddesc_[ph]) SGN_HIP(hipFree(ddesc_[ph]));
+            ddesc_[ph] = nullptr;
+            dcap_[ph] = 0;
+            if (hipMalloc(&ddesc_[ph], need) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "multishift_qmr: batch"};
+            dcap_[ph] = need;
+        }
+        SGN_HIP(hipMemcpy(ddesc_[ph], desc.data(), need, hipMemcpyHostToDevice));
+    }
+}
+
+void QmrBatch::launch_step(hipStream_t strm)
+{
+    for (int ph = 0; ph < 3; ++ph) {
+        const int np = (int)group_[ph].size();
+        if (!np) continue;
+        const QbDesc *d = ddesc_[ph];
+        stb_[ph][0].launch(strm);
+        stb_[ph][1].launch(strm);
+        hipLaunchKernelGGL(qb_alpha_batch, dim3(np), dim3(256), 0, strm, d);
+        stb_[ph][2].launch(strm);
+        stb_[ph][3].launch(strm);
+        if (ph >= 1)
+            hipLaunchKernelGGL(qb_update_batch<true>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        else
+            hipLaunchKernelGGL(qb_update_batch<false>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+        hipLaunchKernelGGL(qb_step_batch, dim3(np), dim3(256), 0, strm, d, nvb_max_[ph]);
+    }
+    SGN_HIP(hipGetLastError());
+}
+
+void QmrBatch::iterate(int count)
+{
+    if (!ctx_->prof) {
+        if (!gexec_) {
+            if (!ctx_->capture_stream) SGN_HIP(hipStreamCreate(&ctx_->capture_stream));
+            hipStream_t cs = ctx_->capture_stream;
+            hipGraph_t g = nullptr;
+            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int it = 0; it < count; ++it) launch_step(cs);
+            } catch (...) {
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SGN_HIP(hipStreamEndCapture(cs, &g));
+            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SGN_HIP(e);
+        }
+        SGN_HIP(hipGraphLaunch(gexec_, s_));
+    } else {
+        for (int it = 0; it < count; ++it) launch_step(s_);
+    }
+}
+
+sgn_status QmrBatch::run(sgn_stats *st)
+{
+    if (pr_.empty()) return SGN_OK;
+    SGN_HIP(hipSetDevice(ctx_->device));
+    active_.assign(pr_.size(), false);
+    int nactive = 0;
+    for (size_t k = 0; k < pr_.size(); ++k) {
+        active_[k] = pr_[k]->setup(st ? st + k : nullptr, true);
+        nactive += active_[k] ? 1 : 0;
+    }
+    const int poll = pr_[0]->poll_;
+    int launched = 0, finished_since = 0, in_launch = 0;
+    bool dirty = true;
+    const int one = 1;
+    while (nactive > 0) {
+        // every problem in the launch takes `poll` more steps (a finished one only idles: its
+        // kernels see its done flag)
+        int maxit = 0;
+        for (size_t k = 0; k < pr_.size(); ++k)
+            if (active_[k]) maxit = std::max(maxit, pr_[k]->maxiter_);
+        const int chunk = std::min(poll, maxit - launched);
+        for (size_t k = 0; k < pr_.size(); ++k)
+            if (active_[k]) pr_[k]->ensure_slots(launched + chunk);
+        if (dirty || chunk != poll) {
+            rebuild();
+            dirty = false;
+            finished_since = 0;
+            in_launch = nactive;
+        }
+        iterate(chunk);
+        const int j0 = launched;
+        launched += chunk;
+        for (size_t k = 0; k < pr_.size(); ++k) {
+            if (!active_[k]) continue;
+            QmrSolve &q = *pr_[k];
+            if (q.absorb(j0, std::min(launched, q.maxiter_))) {
+                active_[k] = false;
+                --nactive;
+                ++finished_since;
+                SGN_HIP(hipMemcpyAsync(q.ddone_, &one, sizeof(int), hipMemcpyHostToDevice, s_));
+            } else if (q.switch_precision()) {
+                dirty = true;
+            }
+        }
+        SGN_HIP(hipStreamSynchronize(s_));  // the done flags are written before the next replay
+        if (nactive > 0 && 4 * finished_since >= in_launch) dirty = true;
+    }
+    drop_graph();
+    sgn_status result = SGN_OK;
+    for (size_t k = 0; k < pr_.size(); ++k) {
+        if (pr_[k]->ynorm_ == 0.0) continue;  // x = x_P was written by setup
+        const sgn_status sk = pr_[k]->finish(st ? st + k : nullptr);
+        if (sk != SGN_OK && result == SGN_OK) result = sk;
     }
     return result;
 }
-
 }  // namespace
 }  // namespace sgn
 
@@ -883,8 +1285,14 @@ extern "C" sgn_status multishift_qmr(const sgn_problem *pb, int nprob, const sgn
             SGN_REQUIRE(pb[p].lat && pb[p].b && pb[p].x, "multishift_qmr: null problem field");
             SGN_REQUIRE(std::isfinite(pb[p].mu), "multishift_qmr: mu not finite");
         }
+        if (nprob > 1) {  // the problems in lockstep
+            QmrBatch batch(pb, nprob, *rf, *o, static_cast<hipStream_t>(stream));
+            worst = batch.run(stats);
+            return;
+        }
         for (int p = 0; p < nprob; ++p) {
-            const sgn_status r = qmr_one(pb[p], *rf, *o, stats ? stats + p : nullptr, static_cast<hipStream_t>(stream));
+            QmrSolve solver(pb[p], *rf, *o, static_cast<hipStream_t>(stream));
+            const sgn_status r = solver.run(stats ? stats + p : nullptr);
             if (r != SGN_OK && worst == SGN_OK) worst = r;
         }
     });

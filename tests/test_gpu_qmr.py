@@ -212,8 +212,8 @@ def test_qmr_on_a_side_stream_matches_default_stream():
 
 
 def test_qmr_two_problems_in_one_call():
-    """Problems of one call (different mu and sources) run one after another and give the same bits
-    as separate calls; stats come back per problem."""
+    """Problems of one call (different mu and sources on one lattice) run in lockstep (their stencils
+    as one multi-RHS launch) and give the same bits as separate calls; stats come back per problem."""
     dims = (4, 4, 4, 4)
     U = synth.gauge_field(dims, 0.5, 0)
     lat = lattice(U, dims)
@@ -228,3 +228,39 @@ def test_qmr_two_problems_in_one_call():
     for k in range(2):
         assert np.array_equal(host(xs[k]).ravel(), single[k][0])
         assert sts[k]["iterations"] == single[k][1]["iterations"]
+
+
+@pytest.mark.parametrize("prec", [sgn.F64, sgn.F32_H16])
+def test_qmr_lockstep_batch_of_uneven_lattices(prec):
+    """Problems on lattices of different sizes (and two on one lattice) in one call: each result
+    equals its own single-problem solve to the tolerance's order with the same number of steps (to
+    within two), and the 8^4 ones equal the oracle's multishift QMR."""
+    rf = sgn.sgn_rational_neuberger(16, 0.1, 2.6)
+    om, sg, c = rational.coefficients(16, 0.1, 2.6)
+    cases = []
+    for dims, seed, mu in (((4, 4, 4, 4), 0, 0.3), ((4, 6, 4, 8), 1, 0.1), ((8, 8, 8, 8), 2, 0.25)):
+        U = synth.gauge_field(dims, 0.4, seed)
+        cases.append((U, dims, lattice(U, dims), mu, synth.gaussian_source(dims, seed).ravel()))
+    U8, d8, l8 = cases[2][:3]
+    cases.append((U8, d8, l8, 0.05, synth.gaussian_source(d8, 9).ravel()))
+    kw = dict(tol=1e-10, prec=prec, poll=4)
+    if prec != sgn.F64:
+        kw.update(theta32=1e-3, theta16=1e-6)
+    bds = [dev(b) for *_, b in cases]
+    xs = [torch.empty_like(t) for t in bds]
+    sts = sgn.multishift_qmr([sgn.Problem(lat, mu, bd, x) for (_, _, lat, mu, _), bd, x in zip(cases, bds, xs)],
+                             rf, **kw)
+    for k, (U, dims, lat, mu, b) in enumerate(cases):
+        xk, sk = _solve(lat, mu, b, rf, **kw)
+        e = _rel(host(xs[k]), xk)
+        print(f"prec={prec} problem {k} {dims}: batch vs single {e:.2e}, steps {sts[k]['iterations']} / "
+              f"{sk['iterations']}", flush=True)
+        assert e < (1e-11 if prec == sgn.F64 else 1e-8)
+        assert abs(sts[k]["iterations"] - sk["iterations"]) <= 2
+        if dims == (8, 8, 8, 8):
+            W = WilsonRef(U, dims, 0.2)
+            ref = krylov.multishift_qmr(lambda v: W.apply(v, mu), lambda v: W.apply_adj(v, mu), b, om, sg, c,
+                                        tol=1e-11)
+            eo = _rel(host(xs[k]), ref)
+            print(f"   vs oracle {eo:.2e}", flush=True)
+            assert eo < (1e-9 if prec == sgn.F64 else 1e-8)
