@@ -101,6 +101,124 @@ def measured_traffic():
     return out
 
 
+def kernel_class(name):
+    """The library's profiling class of a kernel of the headline solver (None for the others)."""
+    if "stencil" in name:
+        if "__half2" in name:
+            return "stencil_h16"
+        if "<double" in name:
+            return "stencil_f64"
+        if "<float" in name:
+            return "stencil_f32"
+    for key, cls in (("bs_sub_stored", "seed_update"), ("bs_res_stored", "seed_update"), ("bs_xp32", "shift_update"),
+                     ("bs_xp64", "shift_update"), ("bs_lift_kernel", "basis_lift")):
+        if key in name:
+            return cls
+    return None
+
+
+def _short(name):
+    import re
+    n = name.replace("sgn::(anonymous namespace)::", "").replace("HIP_vector_type", "V")
+    n = re.sub(r"\(.*", "", n).replace("void ", "")
+    return n.strip()
+
+
+def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
+    """Write the markdown summary (kernel time, HBM traffic per dispatch scaled by a plain copy's
+    counters, per-class traffic lines and the kernel sources' hash) from three rocprofv3 runs of the
+    same bench command with --output-format csv: --kernel-trace --stats, --pmc FETCH_SIZE, --pmc
+    WRITE_SIZE."""
+    import collections
+    import csv
+    import glob
+
+    def files(d, suffix):
+        f = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+        if not f:
+            raise SystemExit(f"no *{suffix} under {d}")
+        return f
+    stats = []
+    for f in files(trace_dir, "kernel_stats.csv"):
+        stats += list(csv.DictReader(open(f)))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    ctr = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = collections.defaultdict(list)
+        for f in files(d, "counter_collection.csv"):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == cname:
+                    per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        ctr[cname] = per
+    # calibration: the 512 MiB device copies (WRITE_SIZE = 524288 KiB)
+    copies_w = [v for k, vs in ctr["WRITE_SIZE"].items() if "copyBuffer" in k for v in vs if abs(v - 524288) < 5243]
+    copies_f = [v for k, vs in ctr["FETCH_SIZE"].items() if "copyBuffer" in k for v in vs
+                if abs(2 * v - 524288) < 0.05 * 524288 or abs(v - 524288) < 0.05 * 524288]
+    fw = 524288.0 / (sum(copies_w) / len(copies_w)) if copies_w else 1.0
+    ff = 524288.0 / (sum(copies_f) / len(copies_f)) if copies_f else 1.0
+    L = [f"# rocprofv3 summary: sign(H_W)b bench, 24^3x48, 16-pole multishift BiCGStab (mixed + FP64 legs)", "",
+         "Commands (from the repository root, one MI355X; each writes CSV under its own directory):", ""]
+    for flag in ("--kernel-trace --stats", "--pmc FETCH_SIZE", "--pmc WRITE_SIZE"):
+        L.append(f"    rocprofv3 {flag} --output-format csv -d <dir> -o run -- {command}")
+    L += ["", "Summarised by `python bench.py --summarize-rocprof <trace dir> <FETCH dir> <WRITE dir> --out <this file>`.",
+          "", "## Kernel time (kernel trace, all dispatches of the run)", "",
+          "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in stats[:30]:
+        L.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                 f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    L += ["", "## HBM traffic per dispatch (PMC)", "",
+          f"Calibration: the bench's plain 512 MiB device copies (`__amd_rocclr_copyBuffer`, {len(copies_f)} dispatches) "
+          f"read FETCH_SIZE = {524288.0 / ff:.0f} KiB and WRITE_SIZE = {524288.0 / fw:.0f} KiB on average, so FETCH "
+          f"is scaled by {ff:.3f} and WRITE by {fw:.3f} (bytes = KiB x 1024; one 128-byte read request counts as "
+          "64 B in FETCH_SIZE on this GPU).", "",
+          "| kernel | dispatches | FETCH KiB (raw) | WRITE KiB (raw) | scaled MB per dispatch |", "|---|---|---|---|---|"]
+    rows = []
+    for k, fv in ctr["FETCH_SIZE"].items():
+        wv = ctr["WRITE_SIZE"].get(k, [])
+        if not wv:
+            continue
+        fa, wa = sum(fv) / len(fv), sum(wv) / len(wv)
+        rows.append((len(fv) * (fa * ff + wa * fw), k, len(fv), fa, wa))
+    rows.sort(reverse=True)
+    for _, k, n, fa, wa in rows[:24]:
+        L.append(f"| {_short(k)} | {n} | {fa:.0f} | {wa:.0f} | {(fa * ff + wa * fw) * 1024 / 1e6:.1f} |")
+    cls = collections.defaultdict(lambda: [0.0, 0])
+    for k, fv in ctr["FETCH_SIZE"].items():
+        c = kernel_class(k)
+        wv = ctr["WRITE_SIZE"].get(k, [])
+        if c is None or not wv or len(wv) != len(fv):
+            continue
+        cls[c][0] += sum(f * ff + w * fw for f, w in zip(fv, wv)) * 1024
+        cls[c][1] += len(fv)
+    L += ["", "## Per class (the library's profiling classes of the headline solver's kernels; bench.py reads "
+          "these lines while the kernel sources still hash to the value below)", "", "```"]
+    for c in sorted(cls):
+        tot, n = cls[c]
+        L.append(f"traffic {c} {tot / n:.0f} bytes_per_launch over {n} dispatches")
+    L += [f"source_sha256 {source_digest()}", "```", ""]
+    open(out, "w").write("\n".join(L))
+    print(f"wrote {out}")
+
+
+def summarize_autotune(bench_json, out, command):
+    """Markdown table of the autotuner's candidates from a bench JSON line."""
+    d = json.loads([l for l in open(bench_json).read().splitlines() if l.startswith("{")][-1])
+    L = ["# Stencil launch-shape autotuning, 24^3x48 (sgn_autotune, HIP events on zero fields)", "",
+         f"Command: `{command}` (the `autotune` field of its JSON line; summarised by "
+         "`python bench.py --summarize-autotune <json> --out <this file>`).", "",
+         "Candidates: block sizes under site caps 576, 432, 384, 288, 192, 96 (whole x-rows or x-y planes within "
+         "the LDS budget), as one t-slice (T1) or as a brick of two t-slices (T2); with FP16 links and 16 right-hand "
+         "sides also the register-link mode (r). Time per application (all right-hand sides).", ""]
+    for name, cands in d["autotune"].items():
+        L += [f"## {name}", "", "| sites per block | slices | links in registers | us | chosen |", "|---|---|---|---|---|"]
+        for c in cands:
+            L.append(f"| {c['block_sites']} | {c.get('t_slices', 1)} | {c['links_in_registers']} | {c['us']} | "
+                     f"{'yes' if c['chosen'] else ''} |")
+        L.append("")
+    open(out, "w").write("\n".join(L))
+    print(f"wrote {out}")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -127,7 +245,21 @@ def main():
     ap.add_argument("--no-bicg", action="store_true", help="same as --quick")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device-to-device copy first (reference for PMC byte counters)")
+    ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summary from three rocprofv3 CSV runs of the bench command and exit")
+    ap.add_argument("--summarize-autotune", metavar="BENCH_JSON",
+                    help="write the autotuning summary from a bench JSON line and exit")
+    ap.add_argument("--out", default=None, help="output file of the --summarize-* modes")
+    ap.add_argument("--profiled-command", default="python3 bench.py --quick --steps 2 --warmup 1 --no-cpu-baseline",
+                    help="the command the summarised runs profiled (recorded in the summary)")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        summarize_rocprof(*args.summarize_rocprof, args.out or PROFILE, args.profiled_command)
+        return
+    if args.summarize_autotune:
+        summarize_autotune(args.summarize_autotune, args.out or os.path.join(ROOT, "profiles", "autotune_24x24x24x48.md"),
+                           "python bench.py")
+        return
     quick = args.quick or args.no_bicg
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the solver path is single-GPU "
@@ -183,8 +315,9 @@ def main():
     for name, prec, nr in (("f64", sgn.F64, 1), ("f32", sgn.F32, 1), ("h16", sgn.F32_H16, 1),
                            ("h16_multi16", sgn.F32_H16, 16), ("f32_multi16", sgn.F32, 16)):
         cands = sgn.sgn_autotune(lat, prec, nr)
-        autotune[name] = [{"block_sites": c["block_sites"], "links_in_registers": c["links_in_registers"],
-                           "us": round(c["us"], 2), "chosen": c["chosen"]} for c in cands]
+        autotune[name] = [{"block_sites": c["block_sites"], "t_slices": c["t_slices"],
+                           "links_in_registers": c["links_in_registers"], "us": round(c["us"], 2),
+                           "chosen": c["chosen"]} for c in cands]
         best = [c for c in cands if c["chosen"]][0]
         log(f"[bench] autotune {name}: {len(cands)} shapes, chosen {best['block_sites']} sites/block"
             f"{' (links in registers)' if best['links_in_registers'] else ''}, {best['us']:.1f} us")
@@ -439,19 +572,37 @@ def main():
         def c4_err():
             return max(float(torch.linalg.norm(p.x - r) / torch.linalg.norm(r)) for p, r in zip(pb4, refs4))
 
-        c4 = {"problems": len(pb4), "lattices": [list(df) for df, _ in fields], "tol": C4["tol"]}
-        kw4 = dict(tol=C4["tol"], prec=sgn.F32_H16, **BICG_MIXED)
+        c4 = {"problems": len(pb4), "lattices": [list(df) for df, _ in fields], "tol": C4["tol"],
+              "mixed_schedule": MIXED,
+              "note": "one call: every problem of the batch in lockstep (one batched launch per kernel and step, "
+                      "stencils grouped by lattice into multi-RHS launches); one at a time: a call per problem"}
+        km4 = dict(tol=C4["tol"], prec=sgn.F32_H16, **MIXED)
+        # BiCGStab's mixed legs verify every shifted system (its reliable updates serve the seed only)
+        kv4 = dict(km4, verify=True)
+        kq4 = dict(tol=C4["tol"], prec=sgn.F32_H16, **QMR_MIXED)
         for name, run in (
-                ("bicg_mixed_one_call", lambda: sgn.multishift_solve(pb4, rf4, **kw4)),
-                ("bicg_mixed_one_at_a_time", lambda: [sgn.multishift_solve(p, rf4, **kw4) for p in pb4]),
-                ("bicgstab_mixed_one_call", lambda: sgn.multishift_bicgstab(pb4, rf4, tol=C4["tol"],
-                                                                             prec=sgn.F32_H16, **MIXED)),
-                ("bicg_fp64_one_call", lambda: sgn.multishift_solve(pb4, rf4, tol=C4["tol"]))):
+                ("bicg_mixed_one_call", lambda: sgn.multishift_solve(pb4, rf4, **km4)),
+                ("bicg_mixed_one_at_a_time", lambda: [sgn.multishift_solve(p, rf4, **km4) for p in pb4]),
+                ("bicg_fp64_one_call", lambda: sgn.multishift_solve(pb4, rf4, tol=C4["tol"])),
+                ("bicgstab_mixed_one_call", lambda: sgn.multishift_bicgstab(pb4, rf4, **kv4)),
+                ("bicgstab_mixed_one_at_a_time", lambda: [sgn.multishift_bicgstab(p, rf4, **kv4) for p in pb4]),
+                ("bicgstab_fp64_one_call", lambda: sgn.multishift_bicgstab(pb4, rf4, tol=C4["tol"])),
+                ("bicgstab_fp64_one_at_a_time", lambda: [sgn.multishift_bicgstab(p, rf4, tol=C4["tol"])
+                                                         for p in pb4]),
+                ("qmr_mixed_one_call", lambda: sgn.multishift_qmr(pb4, rf4, **kq4)),
+                ("qmr_fp64_one_call", lambda: sgn.multishift_qmr(pb4, rf4, tol=C4["tol"]))):
             run()
             tb4, _ = timed(run)
             c4[name] = {"solves_per_s": round(len(pb4) / tb4, 2), "ms_per_batch": round(tb4 * 1e3, 2),
                         "max_err_vs_fp64_ref": c4_err()}
             log(f"[bench] C4 {name}: {len(pb4) / tb4:.1f} solves/s, max err {c4[name]['max_err_vs_fp64_ref']:.1e}")
+        ok4 = {k: v for k, v in c4.items() if isinstance(v, dict) and "solves_per_s" in v
+               and v["max_err_vs_fp64_ref"] <= ERR_TARGET}
+        best4 = max((k for k in ok4 if "mixed_one_call" in k), key=lambda k: ok4[k]["solves_per_s"], default=None)
+        if best4 and "bicgstab_fp64_one_at_a_time" in ok4:
+            c4["best_mixed_batched"] = best4
+            c4["best_mixed_batched_vs_plain_fp64_one_at_a_time"] = round(
+                ok4[best4]["solves_per_s"] / ok4["bicgstab_fp64_one_at_a_time"]["solves_per_s"], 3)
         for l4 in lats4:
             l4.close()
         del pb4, refs4
