@@ -164,7 +164,8 @@ typedef struct {
  * form, whose choice serves every group size): every candidate -- the distinct
  * block sizes (whole x-rows or x-y planes within the LDS budget, under site caps
  * of 576, 432, 384, 288, 192 and 96), each as one t-slice and, for even L_t, as a
- * brick of two, and with FP16 two-row links and nrhs > 1 both link modes -- is
+ * brick of two, for nrhs = 1 also the kernel without LDS staging (block_sites 0),
+ * and with FP16 two-row links and nrhs > 1 both link modes -- is
  * applied reps times (0: 20) to zero fields on `stream` and timed
  * with HIP events; the fastest is kept in the context and used by every later
  * launch of that shape class on lattices of these dimensions (the solvers, the
@@ -177,7 +178,8 @@ sgn_status sgn_autotune(sgn_lattice lat, sgn_prec p, int nrhs, int reps, sgn_tun
 
 /* Set the launch shape used for lattices of lat's dimensions in precision p (multi = 0: the
  * single-RHS form, 1: the multi-RHS form) by hand, as sgn_autotune would: blocks of at most
- * max_sites sites (0: no cap beyond the LDS budget and the launch bound), t_slices = 1 or 2
+ * max_sites sites (0: no cap beyond the LDS budget and the launch bound; -1: the kernel without
+ * LDS staging, one launch per right-hand side in the multi-RHS form), t_slices = 1 or 2
  * (bricks of two t-slices, even L_t), links_in_registers = -1 (default), 0 or 1 (multi-RHS form
  * with FP16 two-row links).  For replaying a saved tuning result or pinning a shape.
  * SGN_ERR_INVALID if no staged block of that shape fits the lattice.  Synchronises the device. */

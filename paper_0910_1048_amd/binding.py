@@ -516,11 +516,11 @@ lib.sgn_autotune.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(TuneCandi
 def sgn_autotune(lat, prec, nrhs=1, reps=20, stream=None):
     """Time the stencil's candidate launch shapes for lat's dimensions, prec and nrhs right-hand sides;
     the fastest is kept by the context.  Returns the candidates as dicts (chosen = 1 for the fastest)."""
-    arr = (TuneCandidate * 32)()
+    arr = (TuneCandidate * 64)()
     n = C.c_int()
-    check(lib.sgn_autotune(lat.h, int(prec), int(nrhs), int(reps), arr, 32, C.byref(n), _stream(stream)),
+    check(lib.sgn_autotune(lat.h, int(prec), int(nrhs), int(reps), arr, 64, C.byref(n), _stream(stream)),
           "sgn_autotune")
-    return [{f: getattr(arr[i], f) for f, _ in TuneCandidate._fields_} for i in range(min(n.value, 32))]
+    return [{f: getattr(arr[i], f) for f, _ in TuneCandidate._fields_} for i in range(min(n.value, 64))]
 
 
 lib.sgn_tune_set.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]

@@ -884,8 +884,10 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
     P.tslices = 1;
     {
         const Context::TunedShape ts = lat.ctx->tuned_shape(lat.L, p, nr > 1);
-        ps.pl = staged_plan(lat, p, max_threads, ts.max_sites, ts.tslices);
-        if (!ps.pl.ok && ts.tslices == 2) ps.pl = staged_plan(lat, p, max_threads, ts.max_sites, 1);
+        if (!ts.unstaged) {
+            ps.pl = staged_plan(lat, p, max_threads, ts.max_sites, ts.tslices);
+            if (!ps.pl.ok && ts.tslices == 2) ps.pl = staged_plan(lat, p, max_threads, ts.max_sites, 1);
+        }
     }
     if (ps.pl.ok) {
         P.blk_sites = ps.pl.B;
@@ -1239,8 +1241,10 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
         struct Cand {
             int cap, B, T, regs;
             double us;
+            int unstaged;
         };
         std::vector<Cand> cands;
+        if (!multi) cands.push_back({0, 0, 1, -1, 0.0, 1});  // the unstaged kernel
         const bool can_regs = multi && p == SGN_PREC_F32_H16 && lat.link_ne == 6;
         for (int regs : can_regs ? std::vector<int>{1, 0} : std::vector<int>{-1}) {
             for (int T : {1, 2}) {
@@ -1251,7 +1255,7 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
                     const int B = pl.ok ? pl.B : 0;
                     if (std::find(seen.begin(), seen.end(), B) != seen.end()) continue;
                     seen.push_back(B);
-                    cands.push_back({cap, B, pl.ok ? pl.T : 1, regs, 0.0});
+                    cands.push_back({cap, B, pl.ok ? pl.T : 1, regs, 0.0, 0});
                 }
             }
         }
@@ -1285,7 +1289,7 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
         const Context::TunedShape before = ctx.tuned_shape(lat.L, p, multi);
         try {
             for (Cand &c : cands) {
-                ctx.tuned[key] = {c.cap, c.regs, c.T};
+                ctx.tuned[key] = {c.cap, c.regs, c.T, c.unstaged};
                 for (int w = 0; w < 3; ++w) dslash_launch_multi(lat, p, nrhs, op.data(), in.data(), outp.data(), ep.data(), s);
                 SGN_HIP(hipEventRecord(e0, s));
                 for (int k = 0; k < reps; ++k)
@@ -1307,7 +1311,7 @@ extern "C" sgn_status sgn_autotune(sgn_lattice l, sgn_prec p, int nrhs, int reps
         const Cand *best = &cands[0];
         for (const Cand &c : cands)
             if (c.us < best->us) best = &c;
-        ctx.tuned[key] = {best->cap, best->regs, best->T};
+        ctx.tuned[key] = {best->cap, best->regs, best->T, best->unstaged};
         SGN_HIP(hipDeviceSynchronize());
         const int n = std::min<int>((int)cands.size(), max_out);
         for (int k = 0; k < n; ++k)
@@ -1323,17 +1327,20 @@ extern "C" sgn_status sgn_tune_set(sgn_lattice l, sgn_prec p, int multi, int max
     return guard([&] {
         SGN_REQUIRE(l != nullptr, "sgn_tune_set: null lattice");
         SGN_REQUIRE(p == SGN_PREC_F64 || p == SGN_PREC_F32 || p == SGN_PREC_F32_H16, "sgn_tune_set: unknown precision");
-        SGN_REQUIRE(max_sites >= 0, "sgn_tune_set: max_sites must be >= 0");
+        SGN_REQUIRE(max_sites >= -1, "sgn_tune_set: max_sites must be >= -1");
         SGN_REQUIRE(t_slices == 1 || t_slices == 2, "sgn_tune_set: t_slices must be 1 or 2");
         SGN_REQUIRE(links_in_registers >= -1 && links_in_registers <= 1, "sgn_tune_set: links_in_registers is -1, 0 or 1");
         Lattice &lat = *as_lattice(l);
-        const StagedPlan pl = staged_plan(lat, p, 0, max_sites, t_slices);
-        SGN_REQUIRE(pl.ok && pl.T == t_slices, "sgn_tune_set: no staged block of this shape fits the lattice");
+        const bool unstaged = max_sites == -1;
+        if (!unstaged) {
+            const StagedPlan pl = staged_plan(lat, p, 0, max_sites, t_slices);
+            SGN_REQUIRE(pl.ok && pl.T == t_slices, "sgn_tune_set: no staged block of this shape fits the lattice");
+        }
         // the parameters of earlier multi-RHS launches may still be read by the device
         SGN_HIP(hipSetDevice(lat.ctx->device));
         SGN_HIP(hipDeviceSynchronize());
         lat.ctx->tuned[{lat.L[0], lat.L[1], lat.L[2], lat.L[3], (int)p, multi ? 1 : 0}] =
-            Context::TunedShape{max_sites, links_in_registers, t_slices};
+            Context::TunedShape{unstaged ? 0 : max_sites, links_in_registers, t_slices, unstaged ? 1 : 0};
     });
 }
 

@@ -144,6 +144,7 @@ struct Context {
         int max_sites = 0;
         int regs = -1;
         int tslices = 1;  // staged blocks of 1 t-slice, or bricks of 2
+        int unstaged = 0;  // 1: the kernel without LDS staging (every neighbour through the caches)
     };
     std::map<std::vector<int>, TunedShape> tuned;
     TunedShape tuned_shape(const int L[4], sgn_prec p, bool multi) const

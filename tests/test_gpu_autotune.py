@@ -93,9 +93,10 @@ def test_solvers_after_autotune_match_the_oracle():
 @pytest.mark.parametrize("prec", [sgn.F64, sgn.F32, sgn.F32_H16])
 @pytest.mark.parametrize("dims", [(12, 12, 12, 24), (4, 6, 4, 8), (6, 4, 6, 10), (24, 24, 24, 48)])
 def test_bricks_are_the_same_operator(prec, dims):
-    """Blocks of two t-slices (pinned with sgn_tune_set at several site caps) give bit for bit
-    the result of one-slice blocks, for one and for three right-hand sides, and the oracle's
-    operator (every site at the small sizes, sampled sites at 24^3 x 48)."""
+    """Blocks of two t-slices (pinned with sgn_tune_set at several site caps), and for one
+    right-hand side the kernel without LDS staging, give bit for bit the result of one-slice
+    blocks, for one and for three right-hand sides, and the oracle's operator (every site at the
+    small sizes, sampled sites at 24^3 x 48)."""
     U = synth.gauge_field(dims, 0.4, 5)
     lat = lattice(U, dims)
     W = WilsonRef(U, dims, 0.2)
@@ -132,6 +133,10 @@ def test_bricks_are_the_same_operator(prec, dims):
                 for y0, y1 in zip(ref, got):
                     assert torch.equal(y0, y1), f"cap {cap}, nrhs {nrhs}"
             assert tried >= 1
+            if not multi:  # the kernel without LDS staging
+                sgn.sgn_tune_set(lat, prec, False, -1, 1)
+                got = apply(1)
+                assert torch.equal(ref[0], got[0]), "unstaged kernel"
             for b, mu, y in zip(srcs, mus, ref):
                 out = torch.empty(b.size, dtype=torch.complex128 if prec == sgn.F64 else torch.complex64, device="cuda")
                 sgn.sgn_spinor_unpack(lat, y, out, prec)
@@ -156,4 +161,4 @@ def test_tune_set_refusals():
     with pytest.raises(sgn.SgnError):
         sgn.sgn_tune_set(lat, sgn.F32, False, 0, 3)
     with pytest.raises(sgn.SgnError):
-        sgn.sgn_tune_set(lat, sgn.F32, False, -1, 1)
+        sgn.sgn_tune_set(lat, sgn.F32, False, -2, 1)
