@@ -1005,13 +1005,40 @@ void StencilBatch::prepare(const std::vector<StencilJob> &jobs, sgn_prec p)
     gx_ = threads_ = 0;
     lds_ = 0;
     bytes_ = flops_ = bytes_stored_ = 0.0;
-    // applications on the same lattice become one multi-RHS group (up to kMaxRhs right-hand
-    // sides sharing every link load); the groups are the launch's blockIdx.y
+    // applications on the same lattice become multi-RHS groups (right-hand sides sharing every
+    // link load); the groups are the launch's blockIdx.y.  A group's block walks its right-hand
+    // sides one after another, so the group size is the largest (up to kMaxRhs) that still leaves
+    // the launch 1024 blocks of sites (four per CU), or as many as groups of one would: small
+    // lattices trade link sharing for parallelism
+    int gsize = kMaxRhs;
+    {
+        std::vector<const Lattice *> lats;
+        std::vector<int64_t> cnt, per;
+        for (const StencilJob &j : jobs) {
+            size_t l = 0;
+            while (l < lats.size() && lats[l] != j.lat) ++l;
+            if (l == lats.size()) {
+                lats.push_back(j.lat);
+                cnt.push_back(0);
+                const Context::TunedShape ts = j.lat->ctx->tuned_shape(j.lat->L, p, true);
+                const StagedPlan pl = staged_plan(*j.lat, p, 0, ts.max_sites, ts.tslices);
+                per.push_back(pl.ok ? pl.nblk_sites : (j.lat->V + 255) / 256);
+            }
+            ++cnt[l];
+        }
+        auto blocks = [&](int g) {
+            int64_t b = 0;
+            for (size_t l = 0; l < lats.size(); ++l) b += (cnt[l] + g - 1) / g * per[l];
+            return b;
+        };
+        const int64_t want = std::min<int64_t>(1024, blocks(1));
+        while (gsize > 1 && blocks(gsize) < want) --gsize;
+    }
     std::vector<std::vector<size_t>> groups;
     for (size_t k = 0; k < jobs.size(); ++k) {
         size_t g = 0;
         for (; g < groups.size(); ++g)
-            if (jobs[groups[g][0]].lat == jobs[k].lat && (int)groups[g].size() < kMaxRhs) break;
+            if (jobs[groups[g][0]].lat == jobs[k].lat && (int)groups[g].size() < gsize) break;
         if (g == groups.size()) groups.emplace_back();
         groups[g].push_back(k);
     }
