@@ -214,8 +214,9 @@ def summarize_autotune(bench_json, out, command):
          f"Command: `{command}` (the `autotune` field of its JSON line; summarised by "
          "`python bench.py --summarize-autotune <json> --out <this file>`).", "",
          "Candidates: block sizes under site caps 576, 432, 384, 288, 192, 96 (whole x-rows or x-y planes within "
-         "the LDS budget), as one t-slice (T1) or as a brick of two t-slices (T2); with FP16 links and 16 right-hand "
-         "sides also the register-link mode (r). Time per application (all right-hand sides).", ""]
+         "the LDS budget; sites per block counts all its t-slices), as one t-slice or as a brick of two t-slices; "
+         "for one right-hand side also the kernel without LDS staging (0 sites per block); with FP16 links and 16 "
+         "right-hand sides also the register-link mode. Time per application (all right-hand sides).", ""]
     for name, cands in d["autotune"].items():
         L += [f"## {name}", "", "| sites per block | slices | links in registers | us | chosen |", "|---|---|---|---|---|"]
         for c in cands:

@@ -190,3 +190,46 @@ def test_bicgstab_lockstep_c4_against_oracle():
         e = _rel(host(outs[j]), ref)
         print(f"C4 problem {j}: lockstep BiCGStab vs oracle {e:.2e}", flush=True)
         assert e < 1e-9
+
+
+@pytest.mark.parametrize("solver", ["bicg", "bicgstab", "qmr"])
+def test_lockstep_batches_with_deflated_problems(solver):
+    """A batch mixing deflated problems (each its own deflation set, on two lattices) with an
+    undeflated one: every result equals the dense target x_P + g(cH)(I - P) b (Eq. exact_proj)."""
+    from oracle import dense
+    cases = []
+    for dims, seed, mu in (((2, 2, 2, 4), 0, 0.3), ((2, 2, 4, 4), 1, 0.2)):
+        U = synth.gauge_field(dims, 0.5, seed)
+        H = WilsonRef(U, dims, 0.2).dense(mu)
+        lam, R = np.linalg.eig(H)
+        Linv = np.linalg.inv(R)
+        idx = np.argsort(np.abs(lam.real))[:8]
+        cases.append((U, dims, mu, H, Linv[idx].conj(), R[:, idx].T.copy(), lam[idx]))
+    alpha = 0.15
+    beta = max(float(np.abs(np.linalg.eigvals(c[3])).max()) for c in cases)
+    rf = sgn.sgn_rational_neuberger(14, alpha, beta)
+    om, sg, c = rational.coefficients(14, alpha, beta)
+    probs, outs, targets, keep = [], [], [], []
+    for k, (U, dims, mu, H, Lr, Rr, lm) in enumerate(cases):
+        lat = lattice(U, dims)
+        for j, deflate in enumerate((True, False) if k == 0 else (True,)):
+            b = synth.gaussian_source(dims, 10 + 3 * k + j).ravel()
+            bd = dev(b)
+            x = torch.empty_like(bd)
+            defl = sgn.Deflation(dev(Lr), dev(Rr), lm) if deflate else None
+            keep.append(defl)
+            probs.append(sgn.Problem(lat, mu, bd, x, defl))
+            outs.append(x)
+            if deflate:
+                t = krylov.deflation_xP(Lr.T, Rr.T, lm, b) + dense.rational_dense(
+                    H, krylov.project_out(Lr.T, Rr.T, b), om, sg, c)
+            else:
+                t = dense.rational_dense(H, b, om, sg, c)
+            targets.append(t)
+    kw = dict(tol=1e-12)
+    f = {"bicg": sgn.multishift_solve, "bicgstab": sgn.multishift_bicgstab, "qmr": sgn.multishift_qmr}[solver]
+    st = f(probs, rf, **kw)
+    for k, (x, t) in enumerate(zip(outs, targets)):
+        e = _rel(host(x), t)
+        print(f"{solver} problem {k}: vs dense target {e:.2e}, {st[k]['iterations']} iterations", flush=True)
+        assert e < 1e-9
