@@ -786,6 +786,61 @@ __global__ void __launch_bounds__(256) bs_lift_kernel(const BsSlot *slots, const
     }
 }
 
+// Several lifts in one pass over the slots: outs[o] (o < nout <= kLiftOut) = sum_j coef[j kLiftOut + o]
+// slot_j (+ outs[o] with accumulate); for the per-shift solutions of verify and of requested x_i
+constexpr int kLiftOut = 8;
+constexpr int kLiftMultiChunk = 64;
+__global__ void __launch_bounds__(256) bs_lift_multi_kernel(const BsSlot *slots, const z64 *coef, int K, int Sst,
+                                                            double2 *const *outs, int nout, int accumulate)
+{
+    __shared__ BsSlot sl[kLiftMultiChunk];
+    __shared__ z64 cf[kLiftMultiChunk * kLiftOut];
+    __shared__ double2 *op[kLiftOut];
+    for (int j = threadIdx.x; j < K; j += blockDim.x) sl[j] = slots[j];
+    for (int j = threadIdx.x; j < K * kLiftOut; j += blockDim.x) cf[j] = coef[j];
+    if (threadIdx.x < kLiftOut) op[threadIdx.x] = (int)threadIdx.x < nout ? outs[threadIdx.x] : nullptr;
+    __syncthreads();
+    const int64_t np = (int64_t)6 * Sst;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < np; f += (int64_t)gridDim.x * blockDim.x) {
+        const int c2 = (int)(f / Sst), st = (int)(f - (int64_t)c2 * Sst);
+        const int64_t e0 = (int64_t)(2 * c2) * Sst + st, e1 = e0 + Sst;
+        z64 a0[kLiftOut], a1[kLiftOut];
+#pragma unroll
+        for (int o = 0; o < kLiftOut; ++o) {
+            if (accumulate && o < nout) {
+                a0[o] = ldz(op[o], e0);
+                a1[o] = ldz(op[o], e1);
+            } else {
+                a0[o] = a1[o] = z64{0.0, 0.0};
+            }
+        }
+        for (int j = 0; j < K; ++j) {
+            z64 v0, v1;
+            if (sl[j].f32) {
+                const float4 t = static_cast<const float4 *>(sl[j].p)[f];
+                v0 = {(double)t.x, (double)t.y};
+                v1 = {(double)t.z, (double)t.w};
+            } else {
+                const double2 *q = static_cast<const double2 *>(sl[j].p);
+                v0 = ldz(q, e0);
+                v1 = ldz(q, e1);
+            }
+#pragma unroll
+            for (int o = 0; o < kLiftOut; ++o) {
+                const z64 c = cf[j * kLiftOut + o];
+                a0[o] = a0[o] + c * v0;
+                a1[o] = a1[o] + c * v1;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < kLiftOut; ++o)
+            if (o < nout) {
+                stz(op[o], e0, a0[o]);
+                stz(op[o], e1, a1[o]);
+            }
+    }
+}
+
 // q = -c^2 A A x + sigma x  (for the reliable update r = y + q)
 __global__ void __launch_bounds__(256) bs_addto64(const double2 *y, double2 *q, int64_t n)
 {
@@ -929,6 +984,9 @@ class BsStored {
     void reliable_update(BsHead &h);
     void switch_phase(BsHead &h, int to);
     void lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs, char *out);
+    // outs[o] = the lift of (cr[o], cs[o]) for up to kLiftOut sets, one pass over the slots
+    void lift_multi(int K, const std::vector<const std::vector<zc> *> &cr, const std::vector<const std::vector<zc> *> &cs,
+                    const std::vector<char *> &outs);
 };
 
 // a slot buffer of the given size (FP64 or FP32 vector) from the context's pools
@@ -1138,6 +1196,39 @@ void BsStored::lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs,
                            static_cast<const BsSlot *>(dsl.p) + j0, static_cast<const z64 *>(dcf.p) + j0,
                            std::min(kBsLiftChunk, nk - j0), (int)Sst_, (double2 *)out);
     ctx_.prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * nk * (double)n_);
+    SGN_HIP(hipGetLastError());
+    SGN_HIP(hipStreamSynchronize(s_));  // before the coefficient buffers are freed
+}
+
+void BsStored::lift_multi(int K, const std::vector<const std::vector<zc> *> &cr,
+                          const std::vector<const std::vector<zc> *> &cs, const std::vector<char *> &outs)
+{
+    const int nout = (int)outs.size();
+    SGN_REQUIRE(nout >= 1 && nout <= kLiftOut && (int)cr.size() == nout && (int)cs.size() == nout,
+                "multishift_bicgstab: lift sets");
+    std::vector<BsSlot> sl;
+    for (int j = 0; j <= K; ++j) sl.push_back(BsSlot{rslots_[j], j < (int)rf32_.size() ? rf32_[j] : 0, 0});
+    for (int j = 0; j < K; ++j) sl.push_back(BsSlot{sslots_[j], j < (int)sf32_.size() ? sf32_[j] : 0, 0});
+    const int nk = (int)sl.size();
+    std::vector<z64> cf((size_t)nk * kLiftOut, z64{0.0, 0.0});
+    for (int o = 0; o < nout; ++o) {
+        for (int j = 0; j <= K; ++j) cf[(size_t)j * kLiftOut + o] = {(*cr[o])[j].real(), (*cr[o])[j].imag()};
+        for (int j = 0; j < K; ++j)
+            cf[(size_t)(K + 1 + j) * kLiftOut + o] = {(*cs[o])[j].real(), (*cs[o])[j].imag()};
+    }
+    DeviceScratch dsl(sizeof(BsSlot) * nk), dcf(sizeof(z64) * cf.size()), dout(sizeof(void *) * kLiftOut);
+    SGN_HIP(hipMemcpy(dsl.p, sl.data(), sizeof(BsSlot) * nk, hipMemcpyHostToDevice));
+    SGN_HIP(hipMemcpy(dcf.p, cf.data(), sizeof(z64) * cf.size(), hipMemcpyHostToDevice));
+    SGN_HIP(hipMemcpy(dout.p, outs.data(), sizeof(void *) * nout, hipMemcpyHostToDevice));
+    const int pr = ctx_.prof_start(s_, SGN_K_LIFT);
+    double bytes = 2.0 * nout * b64_;
+    for (int j = 0; j < nk; ++j) bytes += sl[j].f32 ? (double)b32_ : (double)b64_;
+    for (int j0 = 0; j0 < nk; j0 += kLiftMultiChunk)
+        hipLaunchKernelGGL(bs_lift_multi_kernel, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, s_,
+                           static_cast<const BsSlot *>(dsl.p) + j0,
+                           static_cast<const z64 *>(dcf.p) + (size_t)j0 * kLiftOut, std::min(kLiftMultiChunk, nk - j0),
+                           (int)Sst_, static_cast<double2 *const *>(dout.p), nout, j0 > 0 ? 1 : 0);
+    ctx_.prof_stop(pr, s_, SGN_K_LIFT, bytes, 8.0 * nk * nout * (double)n_);
     SGN_HIP(hipGetLastError());
     SGN_HIP(hipStreamSynchronize(s_));  // before the coefficient buffers are freed
 }
@@ -1379,38 +1470,50 @@ sgn_status BsStored::finish(sgn_stats *stp)
         // every shifted solution explicitly (one lift each), its FP64 true residual, and an FP64
         // refinement of any system above the tolerance; x = x_P + sum_i omega_i x_i of the checked
         // x_i.  Work fields: the iteration's FP64 vectors (free after the loop) plus six more.
-        char *acc = p64_, *xi = tmp64_, *res = v64_, *tmp = t64_;
+        char *acc = p64_, *res = v64_, *tmp = t64_;
         std::unique_ptr<DeviceScratch> work;
         hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)acc,
                            make_double2(0.0, 0.0), n_);
         SGN_HIP(hipGetLastError());
         worst = 0.0;
-        for (int i = 0; i < ns_; ++i) {
-            if (i == seed_) {
-                SGN_HIP(hipMemcpyAsync(xi, x64_, b64_, hipMemcpyDeviceToDevice, s_));
+        // the seed's x first, then the other shifts' x_i lifted kLiftOut at a time in one pass
+        std::vector<int> order{seed_};
+        for (int i = 0; i < ns_; ++i)
+            if (i != seed_) order.push_back(i);
+        DeviceScratch xbuf((size_t)kLiftOut * b64_);
+        for (size_t g0 = 0; g0 < order.size(); g0 += (g0 == 0 ? 1 : kLiftOut)) {
+            const size_t g1 = g0 == 0 ? 1 : std::min(order.size(), g0 + kLiftOut);
+            std::vector<char *> outs;
+            for (size_t q = g0; q < g1; ++q) outs.push_back(static_cast<char *>(xbuf.p) + (q - g0) * b64_);
+            if (g0 == 0) {
+                SGN_HIP(hipMemcpyAsync(outs[0], x64_, b64_, hipMemcpyDeviceToDevice, s_));
             } else {
-                hipLaunchKernelGGL(bs_fill_kernel<double2>, dim3(nvb_), dim3(256), 0, s_, (double2 *)xi,
-                                   make_double2(0.0, 0.0), n_);
-                SGN_HIP(hipGetLastError());
-                std::vector<zc> cr(K + 1, 0.0), cs(K, 0.0);
-                for (int j = 0; j <= K; ++j) cr[j] = xr_i[i][j];
-                for (int j = 0; j < K; ++j) cs[j] = xs_i[i][j];
-                lift(K, cr, cs, xi);
+                std::vector<const std::vector<zc> *> cr, cs;
+                for (size_t q = g0; q < g1; ++q) {
+                    cr.push_back(&xr_i[order[q]]);
+                    cs.push_back(&xs_i[order[q]]);
+                }
+                lift_multi(K, cr, cs, outs);
             }
-            double ri = shift_residual64(lat_, op, c2_, rf_.sigma[i], y_, xi, res, tmp, s_) / ynorm;
-            extra_mv += 2;
-            if (ri > o_.tol) {
-                if (!work) work = std::make_unique<DeviceScratch>(6 * b64_);
-                refine_its += refine_shift64(lat_, op, c2_, rf_.sigma[i], res, xi, 0.5 * o_.tol * ynorm, maxiter_,
-                                             work->p, tmp, s_, &extra_mv);
-                ri = shift_residual64(lat_, op, c2_, rf_.sigma[i], y_, xi, res, tmp, s_) / ynorm;
+            for (size_t q = g0; q < g1; ++q) {
+                const int i = order[q];
+                char *xi = outs[q - g0];
+                double ri = shift_residual64(lat_, op, c2_, rf_.sigma[i], y_, xi, res, tmp, s_) / ynorm;
                 extra_mv += 2;
+                if (ri > o_.tol) {
+                    if (!work) work = std::make_unique<DeviceScratch>(6 * b64_);
+                    refine_its += refine_shift64(lat_, op, c2_, rf_.sigma[i], res, xi, 0.5 * o_.tol * ynorm, maxiter_,
+                                                 work->p, tmp, s_, &extra_mv);
+                    ri = shift_residual64(lat_, op, c2_, rf_.sigma[i], y_, xi, res, tmp, s_) / ynorm;
+                    extra_mv += 2;
+                }
+                st.shift_residual[i] = ri;
+                worst = std::max(worst, ri);
+                axpby64({rf_.omega[i], 0.0}, xi, {1.0, 0.0}, acc, n_, s_);
+                if (pb_.x_shift && pb_.x_shift[i]) unpack_spinor(lat_, xi, pb_.x_shift[i], SGN_PREC_F64, s_);
             }
-            st.shift_residual[i] = ri;
-            worst = std::max(worst, ri);
-            axpby64({rf_.omega[i], 0.0}, xi, {1.0, 0.0}, acc, n_, s_);
-            if (pb_.x_shift && pb_.x_shift[i]) unpack_spinor(lat_, xi, pb_.x_shift[i], SGN_PREC_F64, s_);
         }
+        SGN_HIP(hipStreamSynchronize(s_));  // the lifted x_i are read until here
         result = worst <= o_.tol ? (result == SGN_ERR_NOT_CONVERGED ? SGN_OK : result) : SGN_ERR_NOT_CONVERGED;
         unpack_spinor(lat_, acc, rcan_, SGN_PREC_F64, s_);
     } else {
