@@ -907,6 +907,23 @@ __global__ void __launch_bounds__(256) bs_xp32_batch(const BsDesc *d)
     bs_xp32_body(D.S, (float4 *)D.p, (const float4 *)D.v, D.rtab, (const float4 *)D.sv, D.x64, D.Sst);
 }
 
+// the heads of a batch's problems into one array (one copy to the host per chunk), and back for the
+// problems flagged in mask
+static_assert(sizeof(BsHead) % 8 == 0, "BsHead is copied in 8-byte words");
+__global__ void __launch_bounds__(64) bs_gather_heads(BsState *const *S, BsHead *out)
+{
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(&S[blockIdx.x]->h);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(out + blockIdx.x);
+    for (int i = threadIdx.x; i < (int)(sizeof(BsHead) / 8); i += blockDim.x) dst[i] = src[i];
+}
+__global__ void __launch_bounds__(64) bs_scatter_heads(BsState *const *S, const BsHead *in, const int *mask)
+{
+    if (!mask[blockIdx.x]) return;
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(in + blockIdx.x);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(&S[blockIdx.x]->h);
+    for (int i = threadIdx.x; i < (int)(sizeof(BsHead) / 8); i += blockDim.x) dst[i] = src[i];
+}
+
 // Stored-basis slots handed out from the context's per-size pools; shared by the problems of a
 // lockstep batch (each takes the next unused buffers) together with one byte budget.
 struct BsSlotPools {
@@ -982,6 +999,10 @@ class BsStored {
     void launch_iteration(hipStream_t strm);
     void iterate(int count);
     void reliable_update(BsHead &h);
+    // the same in two parts for a batch: the device work, with rho and ||r||^2 into out[0], out[1]
+    // (device memory), then the host's update of the head from them
+    void reliable_update_async(int k, z64 *out);
+    void reliable_update_finish(BsHead &h, z64 rho, double nrm2);
     void switch_phase(BsHead &h, int to);
     void lift(int K, const std::vector<zc> &cr, const std::vector<zc> &cs, char *out);
     // outs[o] = the lift of (cr[o], cs[o]) for up to kLiftOut sets, one pass over the slots
@@ -1145,6 +1166,40 @@ void BsStored::reliable_update(BsHead &h)
     h.rmax = h.rnorm;
     h.reliable = 0;
     ++reliable_;
+}
+
+void BsStored::reliable_update_async(int k, z64 *out)
+{
+    OpSpec op;
+    op.mu = pb_.mu;
+    dslash_launch(lat_, SGN_PREC_F64, op, x64_, tmp64_, Epilogue{}, s_);
+    Epilogue ep;
+    ep.a = -c2_;
+    ep.z = x64_;
+    ep.b = {s0_, 0.0};
+    dslash_launch(lat_, SGN_PREC_F64, op, tmp64_, t64_, ep, s_);
+    hipLaunchKernelGGL(bs_addto64, dim3(nvb_), dim3(256), 0, s_, (const double2 *)y_, (double2 *)t64_, n_);
+    SGN_HIP(hipGetLastError());
+    convert_64_to_32(t64_, r32_, Sst_, s_);
+    SGN_HIP(hipMemcpyAsync(rslots_[k], r32_, b32_, hipMemcpyDeviceToDevice, s_));
+    rf32_[k] = 1;
+    // the same reductions as dot_sync / norm_sync, left on the device (stream order lets the
+    // context's partials be reused by the next problem)
+    z64 *part = static_cast<z64 *>(ctx_.ensure_partials((kMaxBlocks + 1) * sizeof(z64)));
+    int nb = dot_partials(rh32_, r32_, n_, true, part, s_);
+    finalize_sum(part, nb, out, s_);
+    nb = norm2_partials(r32_, n_, true, part, s_);
+    finalize_sum(part, nb, out + 1, s_);
+}
+
+void BsStored::reliable_update_finish(BsHead &h, z64 rho, double nrm2)
+{
+    h.rho = rho;
+    h.rnorm = std::sqrt(nrm2);
+    h.rmax = h.rnorm;
+    h.reliable = 0;
+    ++reliable_;
+    head_ = h;
 }
 
 void BsStored::switch_phase(BsHead &h, int to)
@@ -1580,6 +1635,8 @@ class BsBatch {
         drop_graph();
         for (BsDesc *d : ddesc_)
             if (d) (void)hipFree(d);
+        if (hpin_) (void)hipHostFree(hpin_);
+        if (hru_) (void)hipHostFree(hru_);
     }
     sgn_status run(sgn_stats *st);
 
@@ -1597,6 +1654,12 @@ class BsBatch {
     int nvb_max_[3] = {0, 0, 0}, nxp_max_[3] = {0, 0, 0};
     double vbytes_[3] = {0, 0, 0};       // bytes of one element pass of every problem of the phase
     hipGraphExec_t gexec_ = nullptr;
+    // host <-> device traffic of the polls: the problems' state pointers, their heads gathered in
+    // device memory, a pinned host mirror (heads, then the write-back mask), the reliable updates'
+    // reductions (two per problem) and their pinned mirror
+    std::unique_ptr<DeviceScratch> dsptr_, dheads_, dru_;
+    char *hpin_ = nullptr;
+    z64 *hru_ = nullptr;
 
     void drop_graph()
     {
@@ -1760,9 +1823,26 @@ sgn_status BsBatch::run(sgn_stats *st)
     }
     int active = 0;
     for (auto &p : pr_) active += p->done_ ? 0 : 1;
+    const int np = (int)pr_.size();
+    {
+        std::vector<BsState *> sp(np);
+        for (int k = 0; k < np; ++k) sp[k] = pr_[k]->S_;
+        dsptr_ = std::make_unique<DeviceScratch>(sizeof(BsState *) * np);
+        dheads_ = std::make_unique<DeviceScratch>((sizeof(BsHead) + sizeof(int)) * np);
+        dru_ = std::make_unique<DeviceScratch>(2 * sizeof(z64) * np);
+        SGN_HIP(hipMemcpy(dsptr_->p, sp.data(), sizeof(BsState *) * np, hipMemcpyHostToDevice));
+        SGN_HIP(hipHostMalloc(reinterpret_cast<void **>(&hpin_), (sizeof(BsHead) + sizeof(int)) * np));
+        SGN_HIP(hipHostMalloc(reinterpret_cast<void **>(&hru_), 2 * sizeof(z64) * np));
+    }
+    BsState *const *dsp = static_cast<BsState *const *>(dsptr_->p);
+    BsHead *dh = static_cast<BsHead *>(dheads_->p), *hh = reinterpret_cast<BsHead *>(hpin_);
+    int *hmask = reinterpret_cast<int *>(hh + np);
+    const int *dmask = reinterpret_cast<const int *>(dh + np);
+    z64 *dru = static_cast<z64 *>(dru_->p);
     bool dirty = true;
     int finished_since = 0;
     std::vector<BsHead> heads(pr_.size());
+    std::vector<int> rus;
     while (active > 0) {
         for (auto &p : pr_)
             if (!p->done_) p->ensure_slots(p->launched_ + poll_);
@@ -1772,20 +1852,46 @@ sgn_status BsBatch::run(sgn_stats *st)
             finished_since = 0;
         }
         iterate(poll_);
-        for (size_t k = 0; k < pr_.size(); ++k)
-            if (!pr_[k]->done_)
-                SGN_HIP(hipMemcpyAsync(&heads[k], &pr_[k]->S_->h, sizeof(BsHead), hipMemcpyDeviceToHost, s_));
+        hipLaunchKernelGGL(bs_gather_heads, dim3(np), dim3(64), 0, s_, dsp, dh);
+        SGN_HIP(hipGetLastError());
+        SGN_HIP(hipMemcpyAsync(hh, dh, sizeof(BsHead) * np, hipMemcpyDeviceToHost, s_));
         SGN_HIP(hipStreamSynchronize(s_));
-        for (size_t k = 0; k < pr_.size(); ++k) {
+        // completions, breakdowns and precision switches take the single-problem path (it writes
+        // its head back itself); the reliable updates of all problems go to the device together
+        rus.clear();
+        for (int k = 0; k < np; ++k) {
             BsStored &p = *pr_[k];
             if (p.done_) continue;
+            heads[k] = hh[k];
+            const BsHead &h = heads[k];
             const int phase = p.phase_;
-            if (p.poll(heads[k])) {
-                --active;
-                ++finished_since;
-            } else if (p.phase_ != phase) {
-                dirty = true;
+            if (h.breakdown || h.done || h.want_phase) {
+                if (p.poll(heads[k])) {
+                    --active;
+                    ++finished_since;
+                } else if (p.phase_ != phase) {
+                    dirty = true;
+                }
+            } else if (h.reliable) {
+                p.reliable_update_async(h.iter, dru + 2 * k);
+                rus.push_back(k);
+            } else {
+                p.head_ = h;
             }
+        }
+        if (!rus.empty()) {
+            SGN_HIP(hipMemcpyAsync(hru_, dru, 2 * sizeof(z64) * np, hipMemcpyDeviceToHost, s_));
+            SGN_HIP(hipStreamSynchronize(s_));
+            for (int k = 0; k < np; ++k) hmask[k] = 0;
+            for (int k : rus) {
+                pr_[k]->reliable_update_finish(heads[k], hru_[2 * k], hru_[2 * k + 1].r);
+                hh[k] = heads[k];
+                hmask[k] = 1;
+            }
+            // one copy back and a scatter; the next chunk's launches follow in stream order
+            SGN_HIP(hipMemcpyAsync(dh, hh, (sizeof(BsHead) + sizeof(int)) * np, hipMemcpyHostToDevice, s_));
+            hipLaunchKernelGGL(bs_scatter_heads, dim3(np), dim3(64), 0, s_, dsp, (const BsHead *)dh, dmask);
+            SGN_HIP(hipGetLastError());
         }
         // finished problems only idle in the launches (their kernels see the done flag); drop
         // them once they are a quarter of the launch
