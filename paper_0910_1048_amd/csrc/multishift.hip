@@ -60,6 +60,9 @@ struct MsHead {
     int go;  // set by the beta step of an iteration: that iteration's solution/direction update may run
 };
 
+struct MsState;
+__global__ void __launch_bounds__(64) ms_gather_heads(MsState *const *S, MsHead *out);
+
 struct MsState {
     MsHead h;
     z64 zeta[kS], zeta_prev[kS], zeta_next[kS], alpha_i[kS], beta_i[kS];
@@ -68,6 +71,15 @@ struct MsState {
     double res[kS];
     int act[kS], act_next[kS];
 };
+
+// the heads of a batch's problems into one array (one copy to the host per chunk)
+static_assert(sizeof(MsHead) % 8 == 0, "MsHead is copied in 8-byte words");
+__global__ void __launch_bounds__(64) ms_gather_heads(MsState *const *S, MsHead *out)
+{
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(&S[blockIdx.x]->h);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(out + blockIdx.x);
+    for (int i = threadIdx.x; i < (int)(sizeof(MsHead) / 8); i += blockDim.x) dst[i] = src[i];
+}
 
 // Scalars of iteration k for shift i (zero when the shift was frozen): the
 // stored-basis form rebuilds p_i and x_i from them.
@@ -615,6 +627,8 @@ class MultishiftBatch {
     ~MultishiftBatch()
     {
         if (gexec_) (void)hipGraphExecDestroy(gexec_);
+        if (dheads_) (void)hipFree(dheads_);
+        if (hheads_) (void)hipHostFree(hheads_);
     }
     MultishiftBatch(const MultishiftBatch &) = delete;
     MultishiftBatch &operator=(const MultishiftBatch &) = delete;
@@ -631,6 +645,10 @@ class MultishiftBatch {
     bool mixed_ = false;
     std::chrono::steady_clock::time_point t_start_;
     MsVec *dvec_ = nullptr;  // device descriptors, one per problem
+    // the heads read after each chunk: the problems' state pointers and a gather buffer (device),
+    // and their pinned host mirror (one copy per chunk)
+    char *dheads_ = nullptr;
+    MsHead *hheads_ = nullptr;
     int *dlist_ = nullptr;   // device problem lists: [3 phases][2 forms][nprob]
     std::vector<MsVec> hvec_;
     std::vector<int> lists_[3][2];  // active problems per phase and form (0 stored basis, 1 per-shift)
@@ -1170,11 +1188,28 @@ void MultishiftBatch::to_explicit(MsProblem &p)
 
 void MultishiftBatch::read_heads()
 {
-    for (auto &p : pr_)
-        if (p.active) SGN_HIP(hipMemcpyAsync(&p.hh, &p.S->h, sizeof(MsHead), hipMemcpyDeviceToHost, s_));
+    const int np = (int)pr_.size();
+    if (!dheads_) {
+        std::vector<MsState *> sp(np);
+        for (int k = 0; k < np; ++k) sp[k] = pr_[k].S;
+        if (hipMalloc(&dheads_, (sizeof(MsState *) + sizeof(MsHead)) * np) != hipSuccess) {
+            dheads_ = nullptr;
+            throw Failure{SGN_ERR_NOMEM, "multishift_solve: batch heads"};
+        }
+        SGN_HIP(hipMemcpy(dheads_, sp.data(), sizeof(MsState *) * np, hipMemcpyHostToDevice));
+        SGN_HIP(hipHostMalloc(reinterpret_cast<void **>(&hheads_), sizeof(MsHead) * np));
+    }
+    MsState *const *dsp = reinterpret_cast<MsState *const *>(dheads_);
+    MsHead *dh = reinterpret_cast<MsHead *>(dheads_ + sizeof(MsState *) * np);
+    hipLaunchKernelGGL(ms_gather_heads, dim3(np), dim3(64), 0, s_, dsp, dh);
+    SGN_HIP(hipGetLastError());
+    SGN_HIP(hipMemcpyAsync(hheads_, dh, sizeof(MsHead) * np, hipMemcpyDeviceToHost, s_));
     SGN_HIP(hipStreamSynchronize(s_));
-    for (auto &p : pr_)
-        if (p.active) p.launched = p.hh.iter;
+    for (int k = 0; k < np; ++k)
+        if (pr_[k].active) {
+            pr_[k].hh = hheads_[k];
+            pr_[k].launched = pr_[k].hh.iter;
+        }
 }
 
 // out = y - (c^2 A^2 - sigma_i) x_i in FP64 (internal layout); returns its norm
