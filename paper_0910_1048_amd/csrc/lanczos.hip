@@ -654,6 +654,7 @@ class QmrSolve {
     void step(int j);  // one Lanczos step on A' (single-problem form)
     // the steps j0 .. launched-1 have run: their coefficients into every shift's QR; true once done
     bool absorb(int j0, int launched);
+    bool absorb_host(int j0, int launched);  // absorb with the coefficients copied in already
     bool switch_precision();  // the mixed schedule after a chunk; true if the phase changed
     sgn_status finish(sgn_stats *st);
     sgn_status run(sgn_stats *st);
@@ -868,6 +869,12 @@ bool QmrSolve::absorb(int j0, int launched)
     SGN_HIP(hipMemcpyAsync(hsup_.data() + j0, S_.hsup + j0, sizeof(z64) * nn, hipMemcpyDeviceToHost, s_));
     SGN_HIP(hipMemcpyAsync(hflag_.data() + j0, S_.flag + j0, sizeof(int) * nn, hipMemcpyDeviceToHost, s_));
     SGN_HIP(hipStreamSynchronize(s_));
+    return absorb_host(j0, launched);
+}
+
+// the coefficients of steps j0 .. launched-1 are on the host already
+bool QmrSolve::absorb_host(int j0, int launched)
+{
     const auto t0 = std::chrono::steady_clock::now();
     for (int j = j0; j < launched; ++j) {
         const cplx al(halpha_[j].r, halpha_[j].i), hp = j > 0 ? cplx(hsup_[j - 1].r, hsup_[j - 1].i) : cplx(0.0);
@@ -1067,6 +1074,23 @@ __global__ void __launch_bounds__(256) qb_step_batch(const QbDesc *d, int nb)
     if (threadIdx.x == 0) *D.step = j + 1;
 }
 
+// the coefficients of steps j0 .. j0+nn-1 of every problem of a batch into one buffer (one copy to the
+// host per chunk): per problem nn alpha, nn h_{j+1,j}, nn h_{j,j+1} (z64), then nn flags
+__global__ void __launch_bounds__(64) qb_gather_coef(const LzScalars *S, int j0, int nn, char *out)
+{
+    const LzScalars &L = S[blockIdx.x];
+    if (!L.alpha) return;  // a problem with y = 0 has no scalar table
+    const size_t per = 3 * sizeof(z64) * (size_t)nn + sizeof(int) * (size_t)nn;
+    z64 *o = reinterpret_cast<z64 *>(out + per * blockIdx.x);
+    int *f = reinterpret_cast<int *>(o + 3 * nn);
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+        o[i] = L.alpha[j0 + i];
+        o[nn + i] = L.hsub[j0 + i];
+        o[2 * nn + i] = L.hsup[j0 + i];
+        f[i] = L.flag[j0 + i];
+    }
+}
+
 class QmrBatch {
   public:
     QmrBatch(const sgn_problem *pb, int np, const sgn_rational &rf, const sgn_ms_opts &o, hipStream_t s)
@@ -1081,6 +1105,8 @@ class QmrBatch {
         drop_graph();
         for (QbDesc *d : ddesc_)
             if (d) (void)hipFree(d);
+        if (dcoef_) (void)hipFree(dcoef_);
+        if (hcoef_) (void)hipHostFree(hcoef_);
     }
     sgn_status run(sgn_stats *st);
 
@@ -1097,6 +1123,9 @@ class QmrBatch {
     StencilBatch stb_[3][4];
     int nvb_max_[3] = {0, 0, 0};
     hipGraphExec_t gexec_ = nullptr;
+    // the chunk's coefficients of every problem: scalar tables and a gather buffer (device), and
+    // the pinned host mirror
+    char *dcoef_ = nullptr, *hcoef_ = nullptr;
 
     static int phase_of(const QmrSolve &q) { return !q.f32_ ? 0 : (q.sp_ == SGN_PREC_F32 ? 1 : 2); }
     void drop_graph()
@@ -1219,6 +1248,20 @@ sgn_status QmrBatch::run(sgn_stats *st)
         nactive += active_[k] ? 1 : 0;
     }
     const int poll = pr_[0]->poll_;
+    const int np = (int)pr_.size();
+    const size_t per = 3 * sizeof(z64) * (size_t)poll + sizeof(int) * (size_t)poll;
+    {
+        std::vector<LzScalars> tab(np);
+        for (int k = 0; k < np; ++k) tab[k] = pr_[k]->S_;
+        if (hipMalloc(&dcoef_, sizeof(LzScalars) * np + per * np) != hipSuccess) {
+            dcoef_ = nullptr;
+            throw Failure{SGN_ERR_NOMEM, "multishift_qmr: batch"};
+        }
+        SGN_HIP(hipMemcpy(dcoef_, tab.data(), sizeof(LzScalars) * np, hipMemcpyHostToDevice));
+        SGN_HIP(hipHostMalloc(reinterpret_cast<void **>(&hcoef_), per * np));
+    }
+    const LzScalars *dtab = reinterpret_cast<const LzScalars *>(dcoef_);
+    char *dbuf = dcoef_ + sizeof(LzScalars) * np;
     int launched = 0, finished_since = 0, in_launch = 0;
     bool dirty = true;
     const int one = 1;
@@ -1240,10 +1283,25 @@ sgn_status QmrBatch::run(sgn_stats *st)
         iterate(chunk);
         const int j0 = launched;
         launched += chunk;
+        // every problem's coefficients of the chunk in one copy (problems with y = 0 have no scalar
+        // table and are skipped by the kernel; only active problems' entries are read)
+        const size_t pc = 3 * sizeof(z64) * (size_t)chunk + sizeof(int) * (size_t)chunk;
+        hipLaunchKernelGGL(qb_gather_coef, dim3(np), dim3(64), 0, s_, dtab, j0, chunk, dbuf);
+        SGN_HIP(hipGetLastError());
+        SGN_HIP(hipMemcpyAsync(hcoef_, dbuf, pc * np, hipMemcpyDeviceToHost, s_));
+        SGN_HIP(hipStreamSynchronize(s_));
         for (size_t k = 0; k < pr_.size(); ++k) {
             if (!active_[k]) continue;
             QmrSolve &q = *pr_[k];
-            if (q.absorb(j0, std::min(launched, q.maxiter_))) {
+            const z64 *o = reinterpret_cast<const z64 *>(hcoef_ + pc * k);
+            const int *f = reinterpret_cast<const int *>(o + 3 * chunk);
+            for (int i = 0; i < chunk; ++i) {
+                q.halpha_[j0 + i] = o[i];
+                q.hsub_[j0 + i] = o[chunk + i];
+                q.hsup_[j0 + i] = o[2 * chunk + i];
+                q.hflag_[j0 + i] = f[i];
+            }
+            if (q.absorb_host(j0, std::min(launched, q.maxiter_))) {
                 active_[k] = false;
                 --nactive;
                 ++finished_since;

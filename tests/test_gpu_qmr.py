@@ -264,3 +264,20 @@ def test_qmr_lockstep_batch_of_uneven_lattices(prec):
             eo = _rel(host(xs[k]), ref)
             print(f"   vs oracle {eo:.2e}", flush=True)
             assert eo < (1e-9 if prec == sgn.F64 else 1e-8)
+
+
+def test_qmr_batch_with_a_zero_source():
+    """A zero right-hand side inside a lockstep QMR batch gives x = 0 and leaves the other problem
+    as its single solve."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 0)
+    lat = lattice(U, dims)
+    rf = sgn.sgn_rational_neuberger(12, 0.2, 2.4)
+    b = synth.gaussian_source(dims, 4).ravel()
+    xs, _ = _solve(lat, 0.3, b, rf, tol=1e-10)
+    bd = dev(b)
+    zd = torch.zeros_like(bd)
+    x0, x1 = torch.full_like(bd, 3.0), torch.empty_like(bd)
+    sgn.multishift_qmr([sgn.Problem(lat, 0.1, zd, x0), sgn.Problem(lat, 0.3, bd, x1)], rf, tol=1e-10)
+    assert np.all(host(x0) == 0)
+    assert _rel(host(x1), xs) < 1e-12
