@@ -49,7 +49,9 @@ WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.4, seed=0, kappa=0.2, mu=0.2, poles
 ERR_TARGET = 1e-8
 # precision schedule of the mixed BiCGStab solve: FP32 below 1e-2 ||y||, FP16 links below
 # 1e-5 ||y||, reliable update whenever the seed residual drops by 0.05
-MIXED = dict(theta32=1e-2, theta16=1e-5, delta=0.05)
+# the headline BiCGStab's schedule: FP32 after the first polling chunk, FP16 links below 1e-5 ||y||,
+# a reliable update whenever the residual has dropped tenfold (best mean over four sources)
+MIXED = dict(theta32=1.0, theta16=1e-5, delta=0.1)
 BICG_TOL = 1e-8
 BICG_MIXED = dict(theta32=1e-1, theta16=1e-3, delta=0.05)
 QMR_MIXED = dict(theta32=1e-3, theta16=1e-6)
@@ -61,6 +63,7 @@ C3 = dict(dims=(16, 16, 16, 16), kmax=(20, 30, 40, 50, 60, 80), tol=1e-9)
 # 32 right-hand sides over 8^4, 12^4, 16^4 (one field per size, mu_j ~ U[0, 0.3]), 16 poles
 C4 = dict(nrhs=32, alpha=0.1, beta=2.6, tol=1e-10)
 C4_MIXED = dict(theta32=1e-3, theta16=1e-6, delta=0.05)
+C4_BICG_MIXED = dict(theta32=1e-2, theta16=1e-5, delta=0.05)
 DEFL = dict(dims=(8, 8, 8, 8), m=4, nev=24, kmax=64, eig_tol=1e-10, max_restarts=400, tol=1e-9)
 BW_DIMS = (32, 32, 32, 64)
 PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
@@ -581,10 +584,10 @@ def main():
             return max(float(torch.linalg.norm(p.x - r) / torch.linalg.norm(r)) for p, r in zip(pb4, refs4))
 
         c4 = {"problems": len(pb4), "lattices": [list(df) for df, _ in fields], "tol": C4["tol"],
-              "mixed_schedule": {"bicg": MIXED, "bicgstab": C4_MIXED, "qmr": QMR_MIXED},
+              "mixed_schedule": {"bicg": C4_BICG_MIXED, "bicgstab": C4_MIXED, "qmr": QMR_MIXED},
               "note": "one call: every problem of the batch in lockstep (one batched launch per kernel and step, "
                       "stencils grouped by lattice into multi-RHS launches); one at a time: a call per problem"}
-        km4 = dict(tol=C4["tol"], prec=sgn.F32_H16, **MIXED)
+        km4 = dict(tol=C4["tol"], prec=sgn.F32_H16, **C4_BICG_MIXED)
         # BiCGStab's reliable updates serve the seed only; at C4's tolerance its non-seed shifts need
         # the tighter thresholds (at the headline's they drift to ~2e-8; verify, the other remedy,
         # costs a factor of 4 here)
