@@ -1105,28 +1105,9 @@ void BsStored::launch_iteration(hipStream_t strm)
 
 void BsStored::iterate(int count)
 {
-    if (o_.graph >= 0 && !ctx_.prof) {
-        if (!gexec_) {
-            if (!ctx_.capture_stream) SGN_HIP(hipStreamCreate(&ctx_.capture_stream));
-            hipStream_t cs = ctx_.capture_stream;
-            hipGraph_t g = nullptr;
-            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int it = 0; it < count; ++it) launch_iteration(cs);
-            } catch (...) {
-                (void)hipStreamEndCapture(cs, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            SGN_HIP(hipStreamEndCapture(cs, &g));
-            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            SGN_HIP(e);
-        }
-        SGN_HIP(hipGraphLaunch(gexec_, s_));
-    } else {
-        for (int it = 0; it < count; ++it) launch_iteration(s_);
-    }
+    replay_or_capture(ctx_, gexec_, o_.graph >= 0, s_, [&](hipStream_t strm) {
+        for (int it = 0; it < count; ++it) launch_iteration(strm);
+    });
     note_launched(count);
 }
 
@@ -1771,28 +1752,9 @@ void BsBatch::launch_iteration(hipStream_t strm)
 
 void BsBatch::iterate(int count)
 {
-    if (o_.graph >= 0 && !ctx_->prof) {
-        if (!gexec_) {
-            if (!ctx_->capture_stream) SGN_HIP(hipStreamCreate(&ctx_->capture_stream));
-            hipStream_t cs = ctx_->capture_stream;
-            hipGraph_t g = nullptr;
-            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int it = 0; it < count; ++it) launch_iteration(cs);
-            } catch (...) {
-                (void)hipStreamEndCapture(cs, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            SGN_HIP(hipStreamEndCapture(cs, &g));
-            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            SGN_HIP(e);
-        }
-        SGN_HIP(hipGraphLaunch(gexec_, s_));
-    } else {
-        for (int it = 0; it < count; ++it) launch_iteration(s_);
-    }
+    replay_or_capture(*ctx_, gexec_, o_.graph >= 0, s_, [&](hipStream_t strm) {
+        for (int it = 0; it < count; ++it) launch_iteration(strm);
+    });
     for (int ph = 0; ph < 3; ++ph)
         for (int k : group_[ph]) pr_[k]->note_launched(count);
 }

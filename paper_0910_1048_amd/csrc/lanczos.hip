@@ -1213,28 +1213,9 @@ void QmrBatch::launch_step(hipStream_t strm)
 
 void QmrBatch::iterate(int count)
 {
-    if (!ctx_->prof) {
-        if (!gexec_) {
-            if (!ctx_->capture_stream) SGN_HIP(hipStreamCreate(&ctx_->capture_stream));
-            hipStream_t cs = ctx_->capture_stream;
-            hipGraph_t g = nullptr;
-            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int it = 0; it < count; ++it) launch_step(cs);
-            } catch (...) {
-                (void)hipStreamEndCapture(cs, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            SGN_HIP(hipStreamEndCapture(cs, &g));
-            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            SGN_HIP(e);
-        }
-        SGN_HIP(hipGraphLaunch(gexec_, s_));
-    } else {
-        for (int it = 0; it < count; ++it) launch_step(s_);
-    }
+    replay_or_capture(*ctx_, gexec_, true, s_, [&](hipStream_t strm) {
+        for (int it = 0; it < count; ++it) launch_step(strm);
+    });
 }
 
 sgn_status QmrBatch::run(sgn_stats *st)

@@ -952,30 +952,9 @@ void MultishiftBatch::rebuild()
 
 void MultishiftBatch::iterate(int count)
 {
-    if (use_graph_ && !ctx_->prof) {
-        if (!gexec_) {
-            // the launches only read device-side state, so one capture serves every chunk until the
-            // descriptors, lists or stencil batches change
-            if (!ctx_->capture_stream) SGN_HIP(hipStreamCreate(&ctx_->capture_stream));
-            hipStream_t cs = ctx_->capture_stream;
-            hipGraph_t g = nullptr;
-            SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            try {
-                launch_iterations(count, cs);
-            } catch (...) {
-                (void)hipStreamEndCapture(cs, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            SGN_HIP(hipStreamEndCapture(cs, &g));
-            const hipError_t e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            SGN_HIP(e);
-        }
-        SGN_HIP(hipGraphLaunch(gexec_, s_));
-    } else {
-        launch_iterations(count, s_);
-    }
+    // the launches only read device-side state, so one capture serves every chunk until the
+    // descriptors, lists or stencil batches change
+    replay_or_capture(*ctx_, gexec_, use_graph_, s_, [&](hipStream_t strm) { launch_iterations(count, strm); });
     for (int it = 0; it < count; ++it)
         for (auto &p : pr_) {
             if (!p.active) continue;

@@ -276,4 +276,34 @@ void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_pr
 
 inline Lattice *as_lattice(sgn_lattice l) { return reinterpret_cast<Lattice *>(l); }
 
+// Run launch(stream) from a HIP graph: captured once on the context's capture stream into exec
+// (which the caller keeps, and destroys when its launches change), then launched on s.  Without
+// use_graph, or with launch profiling on (its events are not captured), launch runs on s directly.
+template <typename F>
+void replay_or_capture(Context &ctx, hipGraphExec_t &exec, bool use_graph, hipStream_t s, F &&launch)
+{
+    if (!use_graph || ctx.prof) {
+        launch(s);
+        return;
+    }
+    if (!exec) {
+        if (!ctx.capture_stream) SGN_HIP(hipStreamCreate(&ctx.capture_stream));
+        hipStream_t cs = ctx.capture_stream;
+        hipGraph_t g = nullptr;
+        SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            launch(cs);
+        } catch (...) {
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        SGN_HIP(hipStreamEndCapture(cs, &g));
+        const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        SGN_HIP(e);
+    }
+    SGN_HIP(hipGraphLaunch(exec, s));
+}
+
 }  // namespace sgn
