@@ -66,7 +66,8 @@ C4_MIXED = dict(theta32=1e-3, theta16=1e-6, delta=0.05)
 C4_BICG_MIXED = dict(theta32=1e-2, theta16=1e-5, delta=0.05)
 DEFL = dict(dims=(8, 8, 8, 8), m=4, nev=24, kmax=64, eig_tol=1e-10, max_restarts=400, tol=1e-9)
 BW_DIMS = (32, 32, 32, 64)
-PROFILE_EVERY = 7   # prime, so the sampled stencils cycle through the four per iteration
+PROFILE_EVERY = 1   # every launch: the dispatch stamps its own events, so sampling costs no time
+MARKER = "bitwise_not"  # name part of the torch kernel that brackets the profiled pass in a kernel trace
 # algorithmic bytes per site of one H_W application: two spinors and four links of nine
 # complex entries (FP64 960, FP32 480, FP32 spinors with FP16 links 336); 1368 flop per site
 SITE_BYTES = {"f64": 960, "f32": 480, "h16": 336}
@@ -87,22 +88,26 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """{kernel class: HBM bytes per launch} from the committed rocprofv3 summary, or {} if
-    the kernels changed since it was taken."""
+def profile_summary():
+    """From the committed rocprofv3 summary: ({kernel class: HBM bytes per launch}, {kernel class:
+    mean kernel-trace duration in us over the profiled pass}), or two empty dicts if the kernels
+    changed since it was taken."""
     try:
         lines = open(PROFILE).read().splitlines()
     except OSError:
-        return {}
+        return {}, {}
     digest = [l.split()[1] for l in lines if l.startswith("source_sha256 ")]
     if not digest or digest[0] != source_digest():
-        return {}
-    out = {}
+        return {}, {}
+    traffic, trace_us = {}, {}
     for l in lines:
         if l.startswith("traffic "):
             _, name, val = l.split()[:3]
-            out[name] = float(val)
-    return out
+            traffic[name] = float(val)
+        elif l.startswith("trace_us "):
+            _, name, val = l.split()[:3]
+            trace_us[name] = float(val)
+    return traffic, trace_us
 
 
 def kernel_class(name):
@@ -149,6 +154,22 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
     for f in files(trace_dir, "kernel_stats.csv"):
         stats += list(csv.DictReader(open(f)))
     stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    # the profiled pass: the dispatches between the two marker kernels the bench launches around it
+    trace = []
+    for f in files(trace_dir, "kernel_trace.csv"):
+        trace += list(csv.DictReader(open(f)))
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    marks = [i for i, r in enumerate(trace) if MARKER in r["Kernel_Name"]]
+    if len(marks) < 2:
+        raise SystemExit(f"the kernel trace holds {len(marks)} marker dispatches, not the two around the profiled pass")
+    pass_cls = collections.defaultdict(list)
+    pass_kernel = collections.defaultdict(list)
+    for r in trace[marks[0] + 1:marks[1]]:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        pass_kernel[r["Kernel_Name"]].append(d)
+        c = kernel_class(r["Kernel_Name"])
+        if c is not None:
+            pass_cls[c].append(d)
     ctr = {}
     for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = collections.defaultdict(list)
@@ -173,6 +194,12 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
     for r in stats[:30]:
         L.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                  f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    L += ["", "## The profiled pass (kernel trace between the bench's two marker kernels)", "",
+          "The bench's roofline times these launches with HIP events that each kernel's dispatch stamps itself "
+          "(every launch of the pass); its `avg_launch_us` per class is to be compared with `trace_us` below.", "",
+          "| kernel | calls | avg us |", "|---|---|---|"]
+    for k, v in sorted(pass_kernel.items(), key=lambda kv: -sum(kv[1]))[:16]:
+        L.append(f"| {_short(k)} | {len(v)} | {sum(v) / len(v):.1f} |")
     L += ["", "## HBM traffic per dispatch (PMC)", "",
           f"Calibration: the bench's plain 512 MiB device copies (`__amd_rocclr_copyBuffer`, {len(copies_f)} dispatches) "
           f"read FETCH_SIZE = {524288.0 / ff:.0f} KiB and WRITE_SIZE = {524288.0 / fw:.0f} KiB on average, so FETCH "
@@ -205,6 +232,9 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
     for c in sorted(cls):
         tot, n = cls[c]
         L.append(f"traffic {c} {tot / n:.0f} bytes_per_launch over {n} dispatches")
+    for c in sorted(pass_cls):
+        v = pass_cls[c]
+        L.append(f"trace_us {c} {sum(v) / len(v):.2f} mean_duration_in_the_profiled_pass over {len(v)} dispatches")
     L += [f"source_sha256 {source_digest()}", "```", ""]
     open(out, "w").write("\n".join(L))
     print(f"wrote {out}")
@@ -393,12 +423,18 @@ def main():
     log(f"[bench] fp64: {t64 * 1e3:.1f} ms/solve, {st64['iterations']} iterations, err {err64:.2e}")
 
     # ---- profiled pass (separate, untimed): per-kernel launch times from HIP events on the
-    #      launch stream (graph replay is off while profiling)
+    #      launch stream (graph replay is off while profiling), bracketed by two marker kernels
+    #      for a kernel trace of this command
+    marker = torch.zeros(64, dtype=torch.int32, device="cuda")
+    torch.bitwise_not(marker)
+    sync()
     sgn.sgn_profile_enable(ctx, True, every=PROFILE_EVERY)
     nprof = 2
     tprof, _ = timed(lambda: solve(sgn.F32_H16, W["tol"]), nprof)
     prof = sgn.sgn_profile_read(ctx)
     sgn.sgn_profile_enable(ctx, False)
+    torch.bitwise_not(marker)
+    sync()
 
     # ---- the exact sign: direct two-sided Lanczos (and the accuracy measure)
     lanczos = None
@@ -660,7 +696,7 @@ def main():
         latb.close()
 
     # ---- roofline of the dominant kernel class and of the whole solve, from the profiled pass
-    traffic = measured_traffic()
+    traffic, trace_us = profile_summary()
 
     def roof(name):
         p = prof[name]
@@ -673,6 +709,7 @@ def main():
                 "achieved_stored_format": round(ach_st, 1),
                 "frac_stored_format": round(ach_st / HBM_PEAK_GBS, 4),
                 "launches": p["calls"], "launches_timed": p["launches"], "avg_launch_us": round(avg_s * 1e6, 2),
+                "trace_avg_launch_us": trace_us.get(name),
                 "bytes_per_launch": p["bytes"] / nl, "stored_bytes_per_launch": p["bytes_stored"] / nl,
                 "tflops": round(p["flops"] / nl / avg_s / 1e12, 2) if avg_s > 0 else 0.0}
     active = [k for k in prof if prof[k]["launches"]]

@@ -516,11 +516,16 @@ sgn_status sgn_accuracy_measure(sgn_lattice lat, const void *b, const void *ssb,
 
 /* ------------------------------------------------------------------ profiling */
 /* Per-kernel-class timing of the library's own launches, measured with HIP
- * events recorded on the launch stream around each launch, together with the
- * algorithmic HBM bytes (every input read once, every output written once;
- * a link counts as its nine complex entries even where only two rows are
- * stored) and flops of each launch, and the bytes of the stored format.  Meant for roofline reporting; adds one event
- * pair per profiled launch. */
+ * events on the launch stream, together with the algorithmic HBM bytes (every
+ * input read once, every output written once; a link counts as its nine
+ * complex entries even where only two rows are stored) and flops of each
+ * launch, and the bytes of the stored format.  Meant for roofline reporting.
+ * Where a profiled launch is one kernel (the stencil, the BiCGStab and Lanczos
+ * vector updates) the kernel's dispatch stamps the event pair with its own
+ * start and end (hipExtLaunchKernel), so the time is the kernel's execution;
+ * the other classes (multishift updates and lifts, which may span several
+ * kernels) are bracketed by event markers, which add a few microseconds of
+ * queue latency per launch.  HIP-graph replay is off while profiling. */
 typedef enum {
     SGN_K_STENCIL_F64 = 0,
     SGN_K_STENCIL_F32 = 1,
@@ -545,8 +550,8 @@ typedef struct {
 
 /* enable != 0 starts (and resets) profiling on this context; 0 stops it.
  * enable = N > 1 records only every N-th launch of each kernel class (the
- * per-launch averages stay representative while the event pairs, which
- * insert markers into the stream, cost 1/N as much). */
+ * per-launch averages stay representative while the event markers of the
+ * marker-bracketed classes cost 1/N as much). */
 sgn_status sgn_profile_enable(sgn_handle h, int enable);
 /* Waits for the recorded launches and fills out[SGN_K_COUNT]. */
 sgn_status sgn_profile_read(sgn_handle h, sgn_kernel_profile *out);

@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "field_io.h"
+#include "launch.h"
 #include "vec.h"
 
 namespace sgn {
@@ -1061,12 +1062,12 @@ void BsStored::launch_iteration(hipStream_t strm)
     e2.partials = spart_;
     const int nb = dslash_launch(lat_, sp, op, tmp, v, e2, strm);
     hipLaunchKernelGGL(bs_alpha_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)spart_, nb);
-    const int pr = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
+    const int pr = ctx_.prof_start(strm, SGN_K_SEED_UPDATE, true);
     if (f)
-        hipLaunchKernelGGL(bs_sub_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+        launch_k(ctx_.prof_stamp(pr), bs_sub_stored<float>, dim3(nvb_), dim3(256), 0u, strm, (const BsState *)S_,
                            (void *const *)rtab_, (const float2 *)v, (float2 *)sv, (void *const *)stab_, n_);
     else
-        hipLaunchKernelGGL(bs_sub_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+        launch_k(ctx_.prof_stamp(pr), bs_sub_stored<double>, dim3(nvb_), dim3(256), 0u, strm, (const BsState *)S_,
                            (void *const *)rtab_, (const double2 *)v, (double2 *)sv, (void *const *)stab_, n_);
     ctx_.prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * (f ? 8.0 : 16.0) * n_, 8.0 * n_);
     dslash_launch(lat_, sp, op, sv, tmp, Epilogue{}, strm);
@@ -1081,23 +1082,23 @@ void BsStored::launch_iteration(hipStream_t strm)
     const double eb = f ? 8.0 : 16.0;
     int pr2 = -1;
     hipLaunchKernelGGL(bs_omega_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nb4);
-    pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE);
+    pr2 = ctx_.prof_start(strm, SGN_K_SEED_UPDATE, true);
     if (f)
-        hipLaunchKernelGGL(bs_res_stored<float>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+        launch_k(ctx_.prof_stamp(pr2), bs_res_stored<float>, dim3(nvb_), dim3(256), 0u, strm, (const BsState *)S_,
                            (const float2 *)sv, (const float2 *)t, (const float2 *)rh, (void *const *)rtab_, n_,
                            vpart_);
     else
-        hipLaunchKernelGGL(bs_res_stored<double>, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_,
+        launch_k(ctx_.prof_stamp(pr2), bs_res_stored<double>, dim3(nvb_), dim3(256), 0u, strm, (const BsState *)S_,
                            (const double2 *)sv, (const double2 *)t, (const double2 *)rh, (void *const *)rtab_, n_,
                            vpart_);
     ctx_.prof_stop(pr2, strm, SGN_K_SEED_UPDATE, 4.0 * eb * n_, 12.0 * n_);
     hipLaunchKernelGGL(bs_beta_kernel, dim3(1), dim3(256), 0, strm, S_, (const z64 *)vpart_, nvb_, hist_, maxiter_);
-    const int pr3 = ctx_.prof_start(strm, SGN_K_SHIFT_UPDATE);
+    const int pr3 = ctx_.prof_start(strm, SGN_K_SHIFT_UPDATE, true);
     if (f)
-        hipLaunchKernelGGL(bs_xp32, dim3(vec_blocks(6 * Sst_)), dim3(256), 0, strm, (const BsState *)S_, (float4 *)p,
+        launch_k(ctx_.prof_stamp(pr3), bs_xp32, dim3(vec_blocks(6 * Sst_)), dim3(256), 0u, strm, (const BsState *)S_, (float4 *)p,
                            (const float4 *)v, (void *const *)rtab_, (const float4 *)sv, (double2 *)x64_, (int)Sst_);
     else
-        hipLaunchKernelGGL(bs_xp64, dim3(nvb_), dim3(256), 0, strm, (const BsState *)S_, (double2 *)p,
+        launch_k(ctx_.prof_stamp(pr3), bs_xp64, dim3(nvb_), dim3(256), 0u, strm, (const BsState *)S_, (double2 *)p,
                            (const double2 *)v, (void *const *)rtab_, (const double2 *)sv, (double2 *)x64_, n_);
     ctx_.prof_stop(pr3, strm, SGN_K_SHIFT_UPDATE, (5.0 * eb + 32.0) * n_, 28.0 * n_);
     SGN_HIP(hipGetLastError());
@@ -1724,27 +1725,27 @@ void BsBatch::launch_iteration(hipStream_t strm)
         stb_[ph][0].launch(strm);
         stb_[ph][1].launch(strm);
         hipLaunchKernelGGL(bs_alpha_batch, dim3(np), dim3(256), 0, strm, d);
-        int pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE);
+        int pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE, true);
         if (f)
-            hipLaunchKernelGGL(bs_sub_batch<float>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+            launch_k(ctx_->prof_stamp(pr), bs_sub_batch<float>, dim3(nvb_max_[ph], np), dim3(256), 0u, strm, d);
         else
-            hipLaunchKernelGGL(bs_sub_batch<double>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+            launch_k(ctx_->prof_stamp(pr), bs_sub_batch<double>, dim3(nvb_max_[ph], np), dim3(256), 0u, strm, d);
         ctx_->prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * vbytes_[ph], 8.0 * nvec);
         stb_[ph][2].launch(strm);
         stb_[ph][3].launch(strm);
         hipLaunchKernelGGL(bs_omega_batch, dim3(np), dim3(256), 0, strm, d);
-        pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE);
+        pr = ctx_->prof_start(strm, SGN_K_SEED_UPDATE, true);
         if (f)
-            hipLaunchKernelGGL(bs_res_batch<float>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+            launch_k(ctx_->prof_stamp(pr), bs_res_batch<float>, dim3(nvb_max_[ph], np), dim3(256), 0u, strm, d);
         else
-            hipLaunchKernelGGL(bs_res_batch<double>, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+            launch_k(ctx_->prof_stamp(pr), bs_res_batch<double>, dim3(nvb_max_[ph], np), dim3(256), 0u, strm, d);
         ctx_->prof_stop(pr, strm, SGN_K_SEED_UPDATE, 4.0 * vbytes_[ph], 12.0 * nvec);
         hipLaunchKernelGGL(bs_beta_batch, dim3(np), dim3(256), 0, strm, d, nvb_max_[ph]);
-        pr = ctx_->prof_start(strm, SGN_K_SHIFT_UPDATE);
+        pr = ctx_->prof_start(strm, SGN_K_SHIFT_UPDATE, true);
         if (f)
-            hipLaunchKernelGGL(bs_xp32_batch, dim3(nxp_max_[ph], np), dim3(256), 0, strm, d);
+            launch_k(ctx_->prof_stamp(pr), bs_xp32_batch, dim3(nxp_max_[ph], np), dim3(256), 0u, strm, d);
         else
-            hipLaunchKernelGGL(bs_xp64_batch, dim3(nvb_max_[ph], np), dim3(256), 0, strm, d);
+            launch_k(ctx_->prof_stamp(pr), bs_xp64_batch, dim3(nvb_max_[ph], np), dim3(256), 0u, strm, d);
         ctx_->prof_stop(pr, strm, SGN_K_SHIFT_UPDATE, 5.0 * vbytes_[ph] + 32.0 * nvec, 28.0 * nvec);
     }
     SGN_HIP(hipGetLastError());

@@ -9,6 +9,7 @@
 // hop); the adjoint H_W(mu)^H = H_W(-mu) is the same kernel with mu -> -mu.
 // Single-RHS stencil: HBM-bound, 1368 flop per site.
 #include "field_io.h"
+#include "launch.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -700,42 +701,44 @@ __global__ void __launch_bounds__(kRegs ? kRegsMaxThreads : kStagedMaxThreads<R>
 }
 
 template <typename R, typename LT>
-void launch_staged(const StencilParams &P, int nblk, int threads, size_t lds, bool epi, bool dot, hipStream_t s)
+void launch_staged(const StencilParams &P, int nblk, int threads, size_t lds, bool epi, bool dot, hipStream_t s,
+                   const LaunchStamp &ev)
 {
     dim3 g(nblk), b(threads);
     if (dot)
-        hipLaunchKernelGGL((stencil_staged_kernel<R, LT, true, true>), g, b, lds, s, P);
+        launch_k(ev, stencil_staged_kernel<R, LT, true, true>, g, b, (uint32_t)lds, s, P);
     else if (epi)
-        hipLaunchKernelGGL((stencil_staged_kernel<R, LT, true, false>), g, b, lds, s, P);
+        launch_k(ev, stencil_staged_kernel<R, LT, true, false>, g, b, (uint32_t)lds, s, P);
     else
-        hipLaunchKernelGGL((stencil_staged_kernel<R, LT, false, false>), g, b, lds, s, P);
+        launch_k(ev, stencil_staged_kernel<R, LT, false, false>, g, b, (uint32_t)lds, s, P);
 }
 
 template <typename R, typename LT, int NR>
-void launch_typed(const StencilParams &P, int nblk, bool epi, bool dot, hipStream_t s)
+void launch_typed(const StencilParams &P, int nblk, bool epi, bool dot, hipStream_t s, const LaunchStamp &ev)
 {
     dim3 g(nblk), b(SGN_STENCIL_THREADS);
     if (dot)
-        hipLaunchKernelGGL((stencil_kernel<R, LT, NR, true, true>), g, b, 0, s, P);
+        launch_k(ev, stencil_kernel<R, LT, NR, true, true>, g, b, 0u, s, P);
     else if (epi)
-        hipLaunchKernelGGL((stencil_kernel<R, LT, NR, true, false>), g, b, 0, s, P);
+        launch_k(ev, stencil_kernel<R, LT, NR, true, false>, g, b, 0u, s, P);
     else
-        hipLaunchKernelGGL((stencil_kernel<R, LT, NR, false, false>), g, b, 0, s, P);
+        launch_k(ev, stencil_kernel<R, LT, NR, false, false>, g, b, 0u, s, P);
 }
 
-// unstaged kernel (lattices too small for a staged block shape): one launch per right-hand side
+// unstaged kernel (lattices too small for a staged block shape): one launch per right-hand side;
+// a stamp is only taken for one right-hand side (one launch)
 template <typename R, typename LT>
-void launch_nr(const StencilParams &P, int nr, int nblk, bool epi, bool dot, hipStream_t s)
+void launch_nr(const StencilParams &P, int nr, int nblk, bool epi, bool dot, hipStream_t s, const LaunchStamp &ev)
 {
     if (nr == 1) {
-        launch_typed<R, LT, 1>(P, nblk, epi, dot, s);
+        launch_typed<R, LT, 1>(P, nblk, epi, dot, s, ev);
         return;
     }
     for (int r = 0; r < nr; ++r) {
         StencilParams Q = P;
         Q.rhs[0] = P.rhs[r];
         Q.nrhs = 1;
-        launch_typed<R, LT, 1>(Q, nblk, epi, dot, s);
+        launch_typed<R, LT, 1>(Q, nblk, epi, dot, s, LaunchStamp{});
     }
 }
 
@@ -923,28 +926,28 @@ int kclass(sgn_prec p)
 
 template <typename R, typename LT, bool kRegs>
 void launch_staged_batch_r(const StencilParams *dev, int count, int gx, int threads, size_t lds, bool epi, bool dot,
-                           hipStream_t s)
+                           hipStream_t s, const LaunchStamp &ev)
 {
     dim3 g(gx, count), b(threads);
     if (dot)
-        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, true, kRegs>), g, b, lds, s, dev);
+        launch_k(ev, stencil_staged_batch<R, LT, true, true, kRegs>, g, b, (uint32_t)lds, s, dev);
     else if (epi)
-        hipLaunchKernelGGL((stencil_staged_batch<R, LT, true, false, kRegs>), g, b, lds, s, dev);
+        launch_k(ev, stencil_staged_batch<R, LT, true, false, kRegs>, g, b, (uint32_t)lds, s, dev);
     else
-        hipLaunchKernelGGL((stencil_staged_batch<R, LT, false, false, kRegs>), g, b, lds, s, dev);
+        launch_k(ev, stencil_staged_batch<R, LT, false, false, kRegs>, g, b, (uint32_t)lds, s, dev);
 }
 
 template <typename R, typename LT>
 void launch_staged_batch(const StencilParams *dev, int count, int gx, int threads, size_t lds, bool epi, bool dot,
-                         bool regs, hipStream_t s)
+                         bool regs, hipStream_t s, const LaunchStamp &ev)
 {
     if constexpr (std::is_same<LT, __half2>::value) {
         if (regs) {
-            launch_staged_batch_r<R, LT, true>(dev, count, gx, threads, lds, epi, dot, s);
+            launch_staged_batch_r<R, LT, true>(dev, count, gx, threads, lds, epi, dot, s, ev);
             return;
         }
     }
-    launch_staged_batch_r<R, LT, false>(dev, count, gx, threads, lds, epi, dot, s);
+    launch_staged_batch_r<R, LT, false>(dev, count, gx, threads, lds, epi, dot, s, ev);
 }
 
 }  // namespace
@@ -964,25 +967,27 @@ int dslash_launch_multi(const Lattice &lat, sgn_prec p, int nr, const OpSpec *op
         lat.multi->launch(s);
         return ps.nblk;
     }
-    const int prof = lat.ctx->prof_start(s, kclass(p));
+    // one launch unless the unstaged kernel runs several right-hand sides
+    const int prof = lat.ctx->prof_start(s, kclass(p), ps.pl.ok || nr == 1);
+    const LaunchStamp ev = lat.ctx->prof_stamp(prof);
     switch (p) {
     case SGN_PREC_F64:
         if (ps.pl.ok)
-            launch_staged<double, double2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s);
+            launch_staged<double, double2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s, ev);
         else
-            launch_nr<double, double2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s);
+            launch_nr<double, double2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s, ev);
         break;
     case SGN_PREC_F32:
         if (ps.pl.ok)
-            launch_staged<float, float2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s);
+            launch_staged<float, float2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s, ev);
         else
-            launch_nr<float, float2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s);
+            launch_nr<float, float2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s, ev);
         break;
     default:
         if (ps.pl.ok)
-            launch_staged<float, __half2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s);
+            launch_staged<float, __half2>(ps.P, ps.nblk, ps.pl.threads, ps.pl.lds, ps.epi, ps.dot, s, ev);
         else
-            launch_nr<float, __half2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s);
+            launch_nr<float, __half2>(ps.P, nr, ps.nblk, ps.epi, ps.dot, s, ev);
         break;
     }
     SGN_HIP(hipGetLastError());
@@ -1110,13 +1115,18 @@ void StencilBatch::launch(hipStream_t s) const
         return;
     }
     Context *ctx = jobs_[0].lat->ctx;
-    const int prof = ctx->prof_start(s, kclass(prec_));
+    const int prof = ctx->prof_start(s, kclass(prec_), true);
+    const LaunchStamp ev = ctx->prof_stamp(prof);
     const StencilParams *d = static_cast<const StencilParams *>(dev_);
     const int cnt = ngroups_;
     switch (prec_) {
-    case SGN_PREC_F64: launch_staged_batch<double, double2>(d, cnt, gx_, threads_, lds_, epi_, dot_, false, s); break;
-    case SGN_PREC_F32: launch_staged_batch<float, float2>(d, cnt, gx_, threads_, lds_, epi_, dot_, regs_, s); break;
-    default: launch_staged_batch<float, __half2>(d, cnt, gx_, threads_, lds_, epi_, dot_, regs_, s); break;
+    case SGN_PREC_F64:
+        launch_staged_batch<double, double2>(d, cnt, gx_, threads_, lds_, epi_, dot_, false, s, ev);
+        break;
+    case SGN_PREC_F32:
+        launch_staged_batch<float, float2>(d, cnt, gx_, threads_, lds_, epi_, dot_, regs_, s, ev);
+        break;
+    default: launch_staged_batch<float, __half2>(d, cnt, gx_, threads_, lds_, epi_, dot_, regs_, s, ev); break;
     }
     SGN_HIP(hipGetLastError());
     ctx->prof_stop(prof, s, kclass(prec_), bytes_, flops_, false, bytes_stored_);

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "field_io.h"
+#include "launch.h"
 #include "small_sign.h"
 #include "vec.h"
 
@@ -833,14 +834,14 @@ void QmrSolve::step(int j)
     dslash_launch(lat_, sp_, opAh_, f32 ? t32_->p : tmp, f32 ? z32_->p : z, ez, s_);
     const double2 *vjm = j > 0 ? static_cast<const double2 *>(basis[j - 1]) : nullptr;
     const double2 *wjm = j > 0 ? reinterpret_cast<const double2 *>(Wj(j - 1)) : nullptr;
-    const int pr = ctx_.prof_start(s_, SGN_K_SEED_UPDATE);
+    const int pr = ctx_.prof_start(s_, SGN_K_SEED_UPDATE, true);
     if (f32)
-        hipLaunchKernelGGL(lz_update_kernel<true>, dim3(nvb_), dim3(256), 0, s_, u32_->p, z32_->p,
+        launch_k(ctx_.prof_stamp(pr), lz_update_kernel<true>, dim3(nvb_), dim3(256), 0u, s_, u32_->p, z32_->p,
                            (const double2 *)basis[j], vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1],
                            (double2 *)Wj(j + 1), (float4 *)v32_->p, (float4 *)w32_->p, (double2 *)nullptr,
                            (double2 *)nullptr, S_, j, (int)Sst_, part_);
     else
-        hipLaunchKernelGGL(lz_update_kernel<false>, dim3(nvb_), dim3(256), 0, s_, u, z, (const double2 *)basis[j],
+        launch_k(ctx_.prof_stamp(pr), lz_update_kernel<false>, dim3(nvb_), dim3(256), 0u, s_, u, z, (const double2 *)basis[j],
                            vjm, (const double2 *)Wj(j), wjm, (double2 *)basis[j + 1], (double2 *)Wj(j + 1),
                            (float4 *)nullptr, (float4 *)nullptr, (double2 *)nullptr, (double2 *)nullptr, S_, j,
                            (int)Sst_, part_);

@@ -387,7 +387,7 @@ extern "C" sgn_status sgn_spinor_unpack(sgn_lattice l, const void *internal, voi
 // ----------------------------------------------------------------------------- profiling
 namespace sgn {
 
-int Context::prof_start(hipStream_t s, int cls)
+int Context::prof_start(hipStream_t s, int cls, bool stamped)
 {
     if (!prof) return -1;
     if (prof_calls[cls]++ % prof_every != 0) return -1;
@@ -400,9 +400,20 @@ int Context::prof_start(hipStream_t s, int cls)
             SGN_HIP(hipEventCreate(e));
         }
     }
-    SGN_HIP(hipEventRecord(r.start, s));
+    r.stamped = stamped;
+    if (!stamped) SGN_HIP(hipEventRecord(r.start, s));
     prof_recs.push_back(r);
     return (int)prof_recs.size() - 1;
+}
+
+LaunchStamp Context::prof_stamp(int rec) const
+{
+    LaunchStamp ev;
+    if (rec >= 0 && prof_recs[rec].stamped) {
+        ev.start = prof_recs[rec].start;
+        ev.stop = prof_recs[rec].stop;
+    }
+    return ev;
 }
 
 void Context::prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes,
@@ -415,7 +426,7 @@ void Context::prof_stop(int rec, hipStream_t s, int cls, double bytes, double fl
     r.bytes_stored = bytes_stored < 0.0 ? bytes : bytes_stored;
     r.flops = flops;
     r.device_bytes = device_bytes;
-    SGN_HIP(hipEventRecord(r.stop, s));
+    if (!r.stamped) SGN_HIP(hipEventRecord(r.stop, s));
 }
 
 void Context::prof_collect()

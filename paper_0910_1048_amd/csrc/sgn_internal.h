@@ -92,6 +92,12 @@ struct ProfRec {
     hipEvent_t start, stop;
     double bytes, flops, bytes_stored;
     bool device_bytes;  // bytes accumulated by the kernel itself into byte_counter
+    bool stamped;       // the events are stamped by the dispatch of one kernel (launch_k)
+};
+
+// Events that the dispatch of one kernel stamps with the kernel's own start and end.
+struct LaunchStamp {
+    hipEvent_t start = nullptr, stop = nullptr;
 };
 
 struct Context {
@@ -110,7 +116,10 @@ struct Context {
     // returns -1 when profiling is off or this launch of class cls is not sampled
     int prof_every = 1;
     long long prof_calls[SGN_K_COUNT] = {};
-    int prof_start(hipStream_t s, int cls);
+    // stamped: the caller launches exactly one kernel with prof_stamp(rec) (launch_k); otherwise
+    // event markers are recorded on s around whatever the caller launches
+    int prof_start(hipStream_t s, int cls, bool stamped = false);
+    LaunchStamp prof_stamp(int rec) const;
     // bytes: algorithmic bytes (links as nine entries); bytes_stored: in the stored format (< 0: = bytes)
     void prof_stop(int rec, hipStream_t s, int cls, double bytes, double flops, bool device_bytes = false,
                    double bytes_stored = -1.0);
