@@ -47,8 +47,6 @@ FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32 (counts packed FMAs)
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.4, seed=0, kappa=0.2, mu=0.2, poles=16,
                 alpha=0.12, beta=2.6, tol=1e-9)
 ERR_TARGET = 1e-8
-# precision schedule of the mixed BiCGStab solve: FP32 below 1e-2 ||y||, FP16 links below
-# 1e-5 ||y||, reliable update whenever the seed residual drops by 0.05
 # the headline BiCGStab's schedule: FP32 after the first polling chunk, FP16 links below 1e-5 ||y||,
 # a reliable update whenever the residual has dropped tenfold (best mean over four sources)
 MIXED = dict(theta32=1.0, theta16=1e-5, delta=0.1)

@@ -493,6 +493,23 @@ __device__ __forceinline__ void stz(float2 *p, int64_t e, z64 v)
 {
     ((SGN_GLOBAL float2 *)p)[e] = make_float2((float)v.r, (float)v.i);
 }
+// Non-temporal forms, for data that the iteration touches once: the seed's FP64 x (read and
+// written once per iteration) and the stored s_k slots (read again only by the final lift).
+// They keep such streams from evicting the links and the vectors the next kernels read.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ z64 ldz_nt(const double2 *p, int64_t e)
+{
+    const nt_d2 v = __builtin_nontemporal_load((const SGN_GLOBAL nt_d2 *)p + e);
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void stz_nt(double2 *p, int64_t e, z64 v)
+{
+    __builtin_nontemporal_store(nt_d2{v.r, v.i}, (SGN_GLOBAL nt_d2 *)p + e);
+}
+__device__ __forceinline__ void stz_nt(float2 *p, int64_t e, z64 v)
+{
+    __builtin_nontemporal_store(nt_f2{(float)v.r, (float)v.i}, (SGN_GLOBAL nt_f2 *)p + e);
+}
 
 // alpha = rho / r^^H v from the dotting stencil's partials; the BiCG factors zeta_next
 __device__ __forceinline__ void bs_alpha_kernel_body(BsState *S, const z64 *part, int nb)
@@ -550,7 +567,7 @@ __device__ __forceinline__ void bs_sub_stored_body(const BsState *S, void *const
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 sv = ldz(r, e) - al * ldz(v, e);
         stz(s, e, sv);
-        stz(slot, e, sv);
+        stz_nt(slot, e, sv);
     }
 }
 template <typename R>
@@ -703,7 +720,7 @@ __device__ __forceinline__ void bs_xp64_body(const BsState *S, double2 *p, const
     const double2 *r = static_cast<const double2 *>(rslots[S->h.iter]);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 pv = ldz(p, e), sv = ldz(s, e);
-        stz(x, e, ldz(x, e) + al * pv + om * sv);
+        stz_nt(x, e, ldz_nt(x, e) + al * pv + om * sv);
         stz(p, e, ldz(r, e) + be * (pv - om * ldz(v, e)));
     }
 }
@@ -731,8 +748,8 @@ __device__ __forceinline__ void bs_xp32_body(const BsState *S, float4 *p, const 
         const float4 p4 = p[f], s4 = s[f], v4 = v[f], r4 = r[f];
         const z64 p0 = {p4.x, p4.y}, p1 = {p4.z, p4.w}, s0 = {s4.x, s4.y}, s1 = {s4.z, s4.w};
         const int64_t e0 = (int64_t)(2 * c2) * Sst + st, e1 = e0 + Sst;
-        stz(x, e0, ldz(x, e0) + al * p0 + om * s0);
-        stz(x, e1, ldz(x, e1) + al * p1 + om * s1);
+        stz_nt(x, e0, ldz_nt(x, e0) + al * p0 + om * s0);
+        stz_nt(x, e1, ldz_nt(x, e1) + al * p1 + om * s1);
         const z64 q0 = z64{r4.x, r4.y} + be * (p0 - om * z64{v4.x, v4.y});
         const z64 q1 = z64{r4.z, r4.w} + be * (p1 - om * z64{v4.z, v4.w});
         p[f] = make_float4((float)q0.r, (float)q0.i, (float)q1.r, (float)q1.i);

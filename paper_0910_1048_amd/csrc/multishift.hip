@@ -260,6 +260,27 @@ __device__ __forceinline__ void stz(float2 *p, int64_t i, z64 v)
 {
     ((SGN_GLOBAL float2 *)p)[i] = make_float2((float)v.r, (float)v.i);
 }
+// Non-temporal forms for the solutions x, read and written once per iteration: they keep this
+// stream from evicting the links and the vectors the next kernels read.
+typedef float ms_nt_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ z64 ldz_nt(const double2 *p, int64_t i)
+{
+    const nt_d2 v = __builtin_nontemporal_load((const SGN_GLOBAL nt_d2 *)p + i);
+    return {v.x, v.y};
+}
+__device__ __forceinline__ z64 ldz_nt(const float2 *p, int64_t i)
+{
+    const ms_nt_f2 v = __builtin_nontemporal_load((const SGN_GLOBAL ms_nt_f2 *)p + i);
+    return {(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void stz_nt(double2 *p, int64_t i, z64 v)
+{
+    __builtin_nontemporal_store(nt_d2{v.r, v.i}, (SGN_GLOBAL nt_d2 *)p + i);
+}
+__device__ __forceinline__ void stz_nt(float2 *p, int64_t i, z64 v)
+{
+    __builtin_nontemporal_store(ms_nt_f2{(float)v.r, (float)v.i}, (SGN_GLOBAL ms_nt_f2 *)p + i);
+}
 
 // r_{k+1} = r_k - alpha q, r~ -= conj(alpha) q~, with partials of r~^H r_{k+1}
 // and ||r_{k+1}||^2.  Per-shift form: in place.  Stored-basis form: from slot k
@@ -347,7 +368,7 @@ __global__ void __launch_bounds__(256) ms_shift_update(const MsVec *vl, const in
             T *Pi = P + (int64_t)i * n;
             XT *Xi = X + (int64_t)i * n;
             const z64 p = ldz(Pi, e);
-            stz(Xi, e, ldz(Xi, e) + al_s[i] * p);
+            stz_nt(Xi, e, ldz_nt(Xi, e) + al_s[i] * p);
             stz(Pi, e, ze_s[i] * rv + be_s[i] * p);
         }
         stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
@@ -376,7 +397,7 @@ __global__ void __launch_bounds__(256) ms_seed_xp_update(const MsVec *vl, const 
     const T *r = static_cast<const T *>(d.slots[S->h.iter]), *rt = static_cast<const T *>(d.rt);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const z64 p = ldz(P, e);
-        stz(X, e, ldz(X, e) + al * p);
+        stz_nt(X, e, ldz_nt(X, e) + al * p);
         stz(P, e, ze * ldz(r, e) + be * p);
         stz(pt, e, ldz(rt, e) + bc * ldz(pt, e));
     }
