@@ -73,6 +73,9 @@ FLOP_PER_SITE = 1368
 # PMC byte counts of the solver kernels, taken with rocprofv3 on this benchmark; valid only
 # while the kernel sources are the ones they were measured on
 PROFILE = os.path.join(ROOT, "profiles", "bench_24x24x24x48_multishift.md")
+COUNTERS = os.path.join(ROOT, "profiles", "stencil_24x24x24x48_counters.md")
+# one PMC pass of the stencil-variant counters (7 SQ counters and GRBM_GUI_ACTIVE)
+COUNTER_SET = "VALUBusy OccupancyPercent LDSBankConflict SQ_WAVES SQ_INSTS_VALU SQ_BUSY_CYCLES SQ_WAIT_INST_ANY"
 KERNEL_SOURCES = os.path.join(ROOT, "paper_0910_1048_amd", "csrc")
 
 
@@ -177,11 +180,7 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
                     per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         ctr[cname] = per
     # calibration: the 512 MiB device copies (WRITE_SIZE = 524288 KiB)
-    copies_w = [v for k, vs in ctr["WRITE_SIZE"].items() if "copyBuffer" in k for v in vs if abs(v - 524288) < 5243]
-    copies_f = [v for k, vs in ctr["FETCH_SIZE"].items() if "copyBuffer" in k for v in vs
-                if abs(2 * v - 524288) < 0.05 * 524288 or abs(v - 524288) < 0.05 * 524288]
-    fw = 524288.0 / (sum(copies_w) / len(copies_w)) if copies_w else 1.0
-    ff = 524288.0 / (sum(copies_f) / len(copies_f)) if copies_f else 1.0
+    ff, fw, ncopies = _copy_calibration(ctr["FETCH_SIZE"], ctr["WRITE_SIZE"])
     L = [f"# rocprofv3 summary: sign(H_W)b bench, 24^3x48, 16-pole multishift BiCGStab (mixed + FP64 legs)", "",
          "Commands (from the repository root, one MI355X; each writes CSV under its own directory):", ""]
     for flag in ("--kernel-trace --stats", "--pmc FETCH_SIZE", "--pmc WRITE_SIZE"):
@@ -199,7 +198,7 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
     for k, v in sorted(pass_kernel.items(), key=lambda kv: -sum(kv[1]))[:16]:
         L.append(f"| {_short(k)} | {len(v)} | {sum(v) / len(v):.1f} |")
     L += ["", "## HBM traffic per dispatch (PMC)", "",
-          f"Calibration: the bench's plain 512 MiB device copies (`__amd_rocclr_copyBuffer`, {len(copies_f)} dispatches) "
+          f"Calibration: the bench's plain 512 MiB device copies (`__amd_rocclr_copyBuffer`, {ncopies} dispatches) "
           f"read FETCH_SIZE = {524288.0 / ff:.0f} KiB and WRITE_SIZE = {524288.0 / fw:.0f} KiB on average, so FETCH "
           f"is scaled by {ff:.3f} and WRITE by {fw:.3f} (bytes = KiB x 1024; one 128-byte read request counts as "
           "64 B in FETCH_SIZE on this GPU).", "",
@@ -236,6 +235,170 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
     L += [f"source_sha256 {source_digest()}", "```", ""]
     open(out, "w").write("\n".join(L))
     print(f"wrote {out}")
+
+
+def _copy_calibration(fetch, write):
+    """FETCH_SIZE and WRITE_SIZE scale factors from the plain 512 MiB device copies of a run
+    ({kernel: [KiB per dispatch]} per counter): one 128-byte read request counts as 64 B in
+    FETCH_SIZE on this GPU, so a copy reads half its bytes there."""
+    cw = [v for k, vs in write.items() if "copyBuffer" in k for v in vs if abs(v - 524288) < 5243]
+    cf = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs
+          if abs(2 * v - 524288) < 0.05 * 524288 or abs(v - 524288) < 0.05 * 524288]
+    fw = 524288.0 / (sum(cw) / len(cw)) if cw else 1.0
+    ff = 524288.0 / (sum(cf) / len(cf)) if cf else 1.0
+    return ff, fw, len(cf)
+
+
+def summarize_counters(trace_dir, pmc_dir, fetch_dir, write_dir, variants_json, out, command):
+    """Per stencil variant of the --stencil-variants run (between its two marker kernels, each
+    variant is one consecutive run of 23 stencil dispatches, labelled in the order of the run's
+    JSON line; the last 20 are used): kernel-trace time, the counter set's values and the HBM bytes
+    per dispatch (FETCH/WRITE scaled by the run's copies)."""
+    import collections
+    import csv
+    import glob
+
+    def rows(d, suffix):
+        f = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+        if not f:
+            raise SystemExit(f"no *{suffix} under {d}")
+        r = []
+        for x in f:
+            r += list(csv.DictReader(open(x)))
+        return r
+
+    def window(rs, key_start):
+        rs = sorted(rs, key=lambda r: int(r[key_start]))
+        marks = [i for i, r in enumerate(rs) if MARKER in r["Kernel_Name"]]
+        if len(marks) < 2:
+            raise SystemExit("the run holds no pair of marker kernels around the stencil variants")
+        return rs[marks[0] + 1:marks[-1]]
+
+    variants = json.loads([l for l in open(variants_json).read().splitlines() if l.startswith("{")][-1])
+    variants = variants["stencil_variants"]
+
+    def runs(rs):
+        """[(kernel name, workgroup size, [dispatch rows])] per consecutive run of stencil dispatches"""
+        out_, cur = [], None
+        for r in rs:
+            if "stencil" not in r["Kernel_Name"]:
+                cur = None
+                continue
+            wg = r.get("Workgroup_Size") or r["Workgroup_Size_X"]
+            if cur is None:
+                cur = (r["Kernel_Name"], wg, [])
+                out_.append(cur)
+            cur[2].append(r)
+        if len(out_) != len(variants):
+            raise SystemExit(f"{len(out_)} stencil runs, {len(variants)} variants")
+        return out_
+
+    trace = runs(window(rows(trace_dir, "kernel_trace.csv"), "Start_Timestamp"))
+
+    def counters(d):
+        all_rows = rows(d, "counter_collection.csv")
+        disp = collections.OrderedDict()  # one entry per dispatch, counters gathered
+        for r in all_rows:
+            disp.setdefault(r["Dispatch_Id"], dict(r, _c={}))["_c"][r["Counter_Name"]] = float(r["Counter_Value"])
+        per = runs(window(list(disp.values()), "Start_Timestamp"))
+        whole = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in disp.values():
+            for c, v in r["_c"].items():
+                whole[r["Kernel_Name"]][c].append(v)
+        return per, whole
+    pmc, _ = counters(pmc_dir)
+    fe, fe_all = counters(fetch_dir)
+    wr, wr_all = counters(write_dir)
+    ff, fw, ncopies = _copy_calibration({k: v["FETCH_SIZE"] for k, v in fe_all.items()},
+                                        {k: v["WRITE_SIZE"] for k, v in wr_all.items()})
+    names = COUNTER_SET.split()
+    L = ["# Stencil variants at 24^3x48: time, VALU use, occupancy and memory bytes (rocprofv3)", "",
+         "Commands (from the repository root, one MI355X; each writes CSV under its own directory):", ""]
+    for flag in ("--kernel-trace --stats", f"--pmc {COUNTER_SET}", "--pmc FETCH_SIZE", "--pmc WRITE_SIZE"):
+        L.append(f"    rocprofv3 {flag} --output-format csv -d <dir> -o run -- {command}")
+    L += ["", "Summarised by `python bench.py --summarize-counters <trace dir> <counter dir> <FETCH dir> <WRITE dir> "
+          "<JSON line of a plain run> --out <this file>`. The run pins each shape with `sgn_tune_set` and applies the "
+          "stencil 3 + 20 times (one right-hand side, internal layout, random source) between two marker kernels; a "
+          "row is one shape, its values the means over the 20 timed dispatches. The first shape of each precision is "
+          "the one the autotuner picks at this size. Memory bytes: what the L2 caches fetch from and write to memory "
+          "(part of it served by the 256 MB Infinity Cache), FETCH_SIZE x "
+          f"{ff:.3f} + WRITE_SIZE x {fw:.3f} (KiB x 1024), the factors from the run's {ncopies} plain 512 MiB copies. "
+          "Stored bytes per site: 768 / 384 / 288 (FP64 / FP32 / FP16 links, two-row links); the byte model of the "
+          "roofline counts 960 / 480 / 336.", "",
+          "| precision | sites per block x t-slices | kernel | threads | us | memory MB | MB / stored MB | "
+          + " | ".join(names) + " |",
+          "|---|---|---|---|---|---|---|" + "---|" * len(names)]
+    V = 24 * 24 * 24 * 48
+    stored = {"f64": 768, "f32": 384, "h16": 288}
+
+    def mean(v):
+        v = v[-20:]
+        return sum(v) / len(v) if v else float("nan")
+    for i, var in enumerate(variants):
+        kname, wg, tr = trace[i]
+        us = mean([(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr])
+        f = mean([r["_c"].get("FETCH_SIZE", float("nan")) for r in fe[i][2]])
+        w = mean([r["_c"].get("WRITE_SIZE", float("nan")) for r in wr[i][2]])
+        mb = (f * ff + w * fw) * 1024 / 1e6
+        vals = [f"{mean([r['_c'][c] for r in pmc[i][2] if c in r['_c']]):.3g}" for c in names]
+        shape = f"{var['block_sites']} x {var['t_slices']}" if var["block_sites"] else "unstaged"
+        L.append(f"| {var['prec']} | {shape} | {_short(kname)} | {wg} | {us:.1f} | {mb:.1f} | "
+                 f"{mb / (stored[var['prec']] * V / 1e6):.2f} | " + " | ".join(vals) + " |")
+    L += ["", "VALUBusy: percent of the kernel's GPU time the vector ALUs issue; OccupancyPercent: resident waves as a "
+          "percent of the maximum; SQ_WAVES: waves launched; SQ_WAIT_INST_ANY: wave-cycles waiting for any "
+          "instruction's data (summed over the GPU, in the counter's units).", ""]
+    open(out, "w").write("\n".join(L))
+    print(f"wrote {out}")
+
+
+# launch shapes of the stencil-variant run, (sites per block over all t-slices, t-slices); 0 is the
+# kernel without LDS staging.  The first of each is the shape the autotuner picks at 24^3x48.
+STENCIL_VARIANTS = {"f64": [(96, 1), (96, 2), (288, 1), (0, 1)],
+                    "f32": [(576, 2), (576, 1), (96, 1), (0, 1)],
+                    "h16": [(384, 2), (384, 1), (576, 1), (0, 1)]}
+
+
+def run_stencil_variants(sgn, torch, synth):
+    """Fixed launch shapes per precision (STENCIL_VARIANTS), each applied 3 + 20 times between
+    two marker kernels (for a kernel trace or counter run of this command). One JSON line."""
+    W = WORKLOAD
+    dims = W["dims"]
+    U = synth.gauge_field(dims, W["eps"], W["seed"])
+    ctx = sgn.Context(0)
+    lat = sgn.Lattice(ctx, torch.from_numpy(U).cuda(), dims, W["kappa"])
+    res = []
+    marker = torch.zeros(64, dtype=torch.int32, device="cuda")
+    plans = []
+    for name, prec in (("f64", sgn.F64), ("f32", sgn.F32), ("h16", sgn.F32_H16)):
+        for sites, T in STENCIL_VARIANTS[name]:
+            plans.append((name, prec, "staged" if sites else "unstaged", {"block_sites": sites, "t_slices": T}))
+    nb_max = max(lat.spinor_bytes(p) for p in (sgn.F64, sgn.F32))
+    xi = torch.zeros(nb_max, dtype=torch.uint8, device="cuda")
+    yi = torch.empty_like(xi)
+    torch.bitwise_not(marker)
+    torch.cuda.synchronize()
+    for name, prec, label, c in plans:
+        cap = -1 if c["block_sites"] == 0 else c["block_sites"]
+        sgn.sgn_tune_set(lat, prec, False, cap, c["t_slices"])
+        canon = torch.randn(12 * lat.V, dtype=torch.complex128 if prec == sgn.F64 else torch.complex64, device="cuda")
+        sgn.sgn_spinor_pack(lat, canon, xi, prec)
+        for _ in range(3):
+            sgn.wilson_apply(lat, W["mu"], xi, yi, prec, sgn.INTERNAL_LAYOUT)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            sgn.wilson_apply(lat, W["mu"], xi, yi, prec, sgn.INTERNAL_LAYOUT)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        res.append({"prec": name, "kernel": label, "block_sites": c["block_sites"], "t_slices": c["t_slices"],
+                    "us": round(us, 2), "frac": round(SITE_BYTES[name] * lat.V / us / 1e3 / HBM_PEAK_GBS, 4)})
+        log(f"[bench] stencil {name} {label}: {c['block_sites']} sites x {c['t_slices']} slices, {us:.1f} us")
+    torch.bitwise_not(marker)
+    torch.cuda.synchronize()
+    for prec in (sgn.F64, sgn.F32, sgn.F32_H16):
+        sgn.sgn_tune_set(lat, prec, False, 0, 1)
+    print(json.dumps({"stencil_variants": res, "dims": list(dims)}), flush=True)
 
 
 def summarize_autotune(bench_json, out, command):
@@ -286,6 +449,12 @@ def main():
                     help="run a plain 512 MiB device-to-device copy first (reference for PMC byte counters)")
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summary from three rocprofv3 CSV runs of the bench command and exit")
+    ap.add_argument("--stencil-variants", action="store_true",
+                    help="apply each stencil launch shape 20 times between two marker kernels (for rocprofv3) and exit")
+    ap.add_argument("--summarize-counters", nargs=5,
+                    metavar=("TRACE_DIR", "COUNTER_DIR", "FETCH_DIR", "WRITE_DIR", "VARIANTS_JSON"),
+                    help="write the stencil-variant counter summary from four rocprofv3 CSV runs of "
+                         "'bench.py --stencil-variants' (and the JSON line of a plain run) and exit")
     ap.add_argument("--summarize-autotune", metavar="BENCH_JSON",
                     help="write the autotuning summary from a bench JSON line and exit")
     ap.add_argument("--out", default=None, help="output file of the --summarize-* modes")
@@ -294,6 +463,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof, args.out or PROFILE, args.profiled_command)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.out or COUNTERS, "python3 bench.py --stencil-variants")
         return
     if args.summarize_autotune:
         summarize_autotune(args.summarize_autotune, args.out or os.path.join(ROOT, "profiles", "autotune_24x24x24x48.md"),
@@ -334,6 +506,9 @@ def main():
     copy_tbs = 2 * a.numel() * 4 / tc / 1e12
     del a, c
     log(f"[bench] device copy 512 MiB: {tc * 1e6:.0f} us, {copy_tbs:.2f} TB/s (read + write)")
+    if args.stencil_variants:
+        run_stencil_variants(sgn, torch, synth)
+        return
 
     W = WORKLOAD
     dims = W["dims"]
