@@ -94,6 +94,40 @@ __global__ void eig_combine_kernel(const double2 *V, int64_t n, int kin, const z
     }
 }
 
+// Arnoldi column j on the device: h_i = c1_i + c2_i (the two Gram-Schmidt passes) into column j
+// of the Hessenberg matrix hd (column-major, leading dimension ld), beta = ||w|| from the norm
+// partials pn[0..nb) (summed in a fixed order), and step[j] = {1 / beta, 0}, or {0, 1} when
+// beta <= 1e-13 ||h|| (an invariant subspace: the host restarts from that column).
+__global__ void __launch_bounds__(256) eig_hcol_kernel(const z64 *c1, const z64 *c2, int j, int ld, const z64 *pn,
+                                                       int nb, z64 *hd, z64 *step)
+{
+    __shared__ double lds[8];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += pn[b].r;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        const z64 h = c1[i] + c2[i];
+        hd[(size_t)j * ld + i] = h;
+        v[1] += norm2(h);
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const double beta = sqrt(v[0]);
+        const bool ok = beta > 1e-13 * sqrt(v[1]);
+        hd[(size_t)j * ld + j + 1] = {ok ? beta : 0.0, 0.0};
+        step[j] = ok ? z64{1.0 / beta, 0.0} : z64{0.0, 1.0};
+    }
+}
+
+// v = step->r * w (zero after a breakdown)
+__global__ void __launch_bounds__(256) eig_scale_kernel(const double2 *w, double2 *v, int64_t n, const z64 *step)
+{
+    const double a = step->r;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 x = w[e];
+        v[e] = make_double2(a * x.x, a * x.y);
+    }
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -165,6 +199,10 @@ struct EigSolver {
     char *w, *t;
     z64 *cd;        // device coefficients (k + 1) * (k + 1)
     z64 *c1, *c2;   // device Gram-Schmidt coefficients (k + 1 each)
+    z64 *hd;        // device Hessenberg matrix of extend, (k + 1) x k column-major
+    z64 *pn;        // device norm partials (kMaxBlocks)
+    z64 *dstep;     // device per column: {1 / beta, breakdown}
+
     int nvb;
     // statistics
     int steps = 0, matvecs = 0, restarts = 0;
@@ -203,33 +241,52 @@ struct EigSolver {
 
     char *vec(char *V, int i) const { return V + (size_t)i * b64; }
 
-    // Arnoldi steps j0 .. k-1 on A = H(mu)^2; H column-major, ld = k + 1
+    // Arnoldi steps j0 .. k-1 on A = H(mu)^2; H column-major, ld = k + 1.  The steps run without
+    // host synchronisation: the Gram-Schmidt coefficients, the Hessenberg column, the norm and the
+    // normalisation stay on the device, and H and the breakdown flags are read once at the end.
     void extend(char *V, const OpSpec &op, std::vector<zc> &H, int j0)
     {
         const int ld = k + 1;
-        std::vector<zc> h;
-        for (int j = j0; j < k; ++j) {
-            dslash_launch(lat, SGN_PREC_F64, op, vec(V, j), t, Epilogue{}, s);
-            dslash_launch(lat, SGN_PREC_F64, op, t, w, Epilogue{}, s);
-            matvecs += 2;
-            ++steps;
-            cgs2(V, j + 1, w, h);
-            for (int i = 0; i <= j; ++i) H[(size_t)j * ld + i] = h[i];
-            double beta = norm_sync(ctx, w, n, false, s);
-            double hn = 0.0;
-            for (int i = 0; i <= j; ++i) hn += std::norm(h[i]);
-            if (!(beta > 1e-13 * std::sqrt(hn))) {
-                // invariant subspace found: continue from a fresh vector orthogonal to the basis
-                fill_random(w, seed + 0x1000 + (unsigned long long)steps);
-                std::vector<zc> dummy;
-                cgs2(V, j + 1, w, dummy);
-                const double r = norm_sync(ctx, w, n, false, s);
-                scale64({1.0 / r, 0.0}, w, vec(V, j + 1), n, s);
-                H[(size_t)j * ld + j + 1] = 0.0;
-            } else {
-                scale64({1.0 / beta, 0.0}, w, vec(V, j + 1), n, s);
-                H[(size_t)j * ld + j + 1] = beta;
+        std::vector<zc> hcol((size_t)ld * k);
+        std::vector<z64> stp(k);
+        // the partials of the largest basis, so that the buffer does not grow (and wait for the
+        // device) between the steps
+        ctx.ensure_partials(deflate_partials_bytes(ld, n));
+        while (j0 < k) {
+            for (int j = j0; j < k; ++j) {
+                dslash_launch(lat, SGN_PREC_F64, op, vec(V, j), t, Epilogue{}, s);
+                dslash_launch(lat, SGN_PREC_F64, op, t, w, Epilogue{}, s);
+                deflate_dots(V, j + 1, w, n, c1, ctx, s);
+                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, V, j + 1, c1, nullptr, n, s);
+                deflate_dots(V, j + 1, w, n, c2, ctx, s);
+                deflate_combine(w, {1.0, 0.0}, {-1.0, 0.0}, V, j + 1, c2, nullptr, n, s);
+                const int nb = norm2_partials(w, n, false, pn, s);
+                hipLaunchKernelGGL(eig_hcol_kernel, dim3(1), dim3(256), 0, s, (const z64 *)c1, (const z64 *)c2, j, ld,
+                                   (const z64 *)pn, nb, hd, dstep);
+                hipLaunchKernelGGL(eig_scale_kernel, dim3(nvb), dim3(256), 0, s, (const double2 *)w,
+                                   (double2 *)vec(V, j + 1), n, (const z64 *)(dstep + j));
+                SGN_HIP(hipGetLastError());
             }
+            matvecs += 2 * (k - j0);
+            steps += k - j0;
+            SGN_HIP(hipMemcpyAsync(hcol.data(), hd, sizeof(z64) * hcol.size(), hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipMemcpyAsync(stp.data(), dstep, sizeof(z64) * k, hipMemcpyDeviceToHost, s));
+            SGN_HIP(hipStreamSynchronize(s));
+            int jb = k;  // the first column whose residual vanished
+            for (int j = j0; j < k && jb == k; ++j)
+                if (stp[j].i != 0.0) jb = j;
+            for (int j = j0; j < std::min(jb + 1, k); ++j)
+                for (int i = 0; i <= j + 1; ++i) H[(size_t)j * ld + i] = hcol[(size_t)j * ld + i];
+            if (jb == k) break;
+            // invariant subspace found at column jb: continue from a fresh vector orthogonal to the
+            // basis (the columns after jb are recomputed)
+            fill_random(w, seed + 0x1000 + (unsigned long long)steps);
+            std::vector<zc> dummy;
+            cgs2(V, jb + 1, w, dummy);
+            const double r = norm_sync(ctx, w, n, false, s);
+            scale64({1.0 / r, 0.0}, w, vec(V, jb + 1), n, s);
+            H[(size_t)jb * ld + jb + 1] = 0.0;
+            j0 = jb + 1;
         }
     }
 
@@ -462,7 +519,8 @@ extern "C" sgn_status sgn_critical_eigenpairs(sgn_lattice l, double mu, const sg
         const size_t b64 = (size_t)n * 16;
         // workspace: 2 bases of k + 1 vectors, w, t, 2p (Ritz block), Q_R, Q_L, H Q_R (m each), coefficients
         const size_t nvec = 2 * (size_t)(k + 1) + 2 + 2 * (size_t)p + 3 * (size_t)m;
-        const size_t cbytes = sizeof(z64) * ((size_t)(k + 1) * (k + 1) + 2 * (size_t)(k + 1));
+        const size_t cbytes =
+            sizeof(z64) * ((size_t)(k + 1) * (k + 1) + 2 * (size_t)(k + 1) + (size_t)(k + 1) * k + kMaxBlocks + k);
         char *arena = static_cast<char *>(ctx.ensure_arena(nvec * b64 + cbytes));
         EigSolver E{lat, ctx, s, m, p, k, o->tol > 0 ? o->tol : 1e-10, o->max_restarts > 0 ? o->max_restarts : 1000,
                     (unsigned long long)o->seed, n, b64};
@@ -477,6 +535,9 @@ extern "C" sgn_status sgn_critical_eigenpairs(sgn_lattice l, double mu, const sg
         E.cd = reinterpret_cast<z64 *>(HQ + (size_t)m * b64);
         E.c1 = E.cd + (size_t)(k + 1) * (k + 1);
         E.c2 = E.c1 + (k + 1);
+        E.hd = E.c2 + (k + 1);
+        E.pn = E.hd + (size_t)(k + 1) * k;
+        E.dstep = E.pn + kMaxBlocks;
         E.nvb = vec_blocks(n);
         const double mus[2] = {mu, -mu};
         char *Qs[2] = {QR, QL};

@@ -44,6 +44,8 @@ void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s);
 // f32: X and y hold complex64 entries (the coefficients and sums stay FP64).
 void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s,
                   bool f32 = false);
+// bytes of the context's partials buffer that deflate_dots uses for m vectors of length n
+size_t deflate_partials_bytes(int m, int64_t n);
 void deflate_combine(void *y, z64 alpha, z64 beta, const void *X, int m, const z64 *c_dev, const z64 *d_dev,
                      int64_t n, hipStream_t s, bool f32 = false);
 // out[i] = {||X_i||^2, 0} for the m complex128 vectors X_i (device)

@@ -426,12 +426,18 @@ void convert_32_to_64(const void *x32, void *x64, int64_t S, hipStream_t s)
     SGN_HIP(hipGetLastError());
 }
 
+size_t deflate_partials_bytes(int m, int64_t n)
+{
+    const int nbx = std::max(1, std::min(kDotBlocks, (int)((n + 255) / 256)));
+    return (size_t)std::max(m, 0) * nbx * sizeof(z64);
+}
+
 void deflate_dots(const void *X, int m, const void *y, int64_t n, z64 *c_dev, Context &ctx, hipStream_t s, bool f32)
 {
     if (m <= 0) return;
     const int nbx = std::max(1, std::min(kDotBlocks, (int)((n + 255) / 256)));
     const int ng = (m + kDotGroup - 1) / kDotGroup;
-    z64 *part = static_cast<z64 *>(ctx.ensure_partials((size_t)m * nbx * sizeof(z64)));
+    z64 *part = static_cast<z64 *>(ctx.ensure_partials(deflate_partials_bytes(m, n)));
     if (f32)
         hipLaunchKernelGGL(mdot_kernel<float2>, dim3(nbx, ng), dim3(256), 0, s, (const float2 *)X, (const float2 *)y, n,
                            m, part);
