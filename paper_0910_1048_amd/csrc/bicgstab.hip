@@ -493,14 +493,20 @@ __device__ __forceinline__ void stz(float2 *p, int64_t e, z64 v)
 {
     ((SGN_GLOBAL float2 *)p)[e] = make_float2((float)v.r, (float)v.i);
 }
-// Non-temporal forms, for data that the iteration touches once: the seed's FP64 x (read and
-// written once per iteration) and the stored s_k slots (read again only by the final lift).
-// They keep such streams from evicting the links and the vectors the next kernels read.
+// Non-temporal forms, for data that the iteration touches once or for the last time: the seed's
+// FP64 x (read and written once per iteration), the stored s_k slots (read again only by the
+// final lift), t in the r' update and s, v in the x, p update.  They keep such streams from
+// evicting the links and the vectors the next kernels read.
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ z64 ldz_nt(const double2 *p, int64_t e)
 {
     const nt_d2 v = __builtin_nontemporal_load((const SGN_GLOBAL nt_d2 *)p + e);
     return {v.x, v.y};
+}
+__device__ __forceinline__ z64 ldz_nt(const float2 *p, int64_t e)
+{
+    const nt_f2 v = __builtin_nontemporal_load((const SGN_GLOBAL nt_f2 *)p + e);
+    return {(double)v.x, (double)v.y};
 }
 __device__ __forceinline__ void stz_nt(double2 *p, int64_t e, z64 v)
 {
@@ -610,9 +616,9 @@ __device__ __forceinline__ void bs_res_stored_body(const BsState *S, const typen
     T *r = static_cast<T *>(rslots[S->h.iter + 1]);
     double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        z64 rv = ldz(s, e) - om * ldz(t, e);
+        z64 rv = ldz(s, e) - om * ldz_nt(t, e);
+        if constexpr (sizeof(R) == 4) rv = {(double)(float)rv.r, (double)(float)rv.i};  // as stored
         stz(r, e, rv);
-        if constexpr (sizeof(R) == 4) rv = ldz(r, e);
         const z64 d = cmulc(ldz(rh, e), rv);
         a += d.r;
         b += d.i;
@@ -719,9 +725,9 @@ __device__ __forceinline__ void bs_xp64_body(const BsState *S, double2 *p, const
     const z64 al = S->h.alpha, om = S->h.omega, be = S->h.beta;
     const double2 *r = static_cast<const double2 *>(rslots[S->h.iter]);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const z64 pv = ldz(p, e), sv = ldz(s, e);
+        const z64 pv = ldz(p, e), sv = ldz_nt(s, e);
         stz_nt(x, e, ldz_nt(x, e) + al * pv + om * sv);
-        stz(p, e, ldz(r, e) + be * (pv - om * ldz(v, e)));
+        stz(p, e, ldz(r, e) + be * (pv - om * ldz_nt(v, e)));
     }
 }
 __global__ void __launch_bounds__(256) bs_xp64(const BsState *S, double2 *p, const double2 *v, void *const *rslots, const double2 *s,
@@ -745,7 +751,9 @@ __device__ __forceinline__ void bs_xp32_body(const BsState *S, float4 *p, const 
     const int64_t np = (int64_t)6 * Sst;
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < np; f += (int64_t)gridDim.x * blockDim.x) {
         const int c2 = (int)(f / Sst), st = (int)(f - (int64_t)c2 * Sst);
-        const float4 p4 = p[f], s4 = s[f], v4 = v[f], r4 = r[f];
+        const float4 p4 = p[f], r4 = r[f];
+        const nt_f4 s4 = __builtin_nontemporal_load((const SGN_GLOBAL nt_f4 *)s + f);
+        const nt_f4 v4 = __builtin_nontemporal_load((const SGN_GLOBAL nt_f4 *)v + f);
         const z64 p0 = {p4.x, p4.y}, p1 = {p4.z, p4.w}, s0 = {s4.x, s4.y}, s1 = {s4.z, s4.w};
         const int64_t e0 = (int64_t)(2 * c2) * Sst + st, e1 = e0 + Sst;
         stz_nt(x, e0, ldz_nt(x, e0) + al * p0 + om * s0);
