@@ -358,6 +358,82 @@ STENCIL_VARIANTS = {"f64": [(96, 1), (96, 2), (288, 1), (0, 1)],
                     "h16": [(384, 2), (384, 1), (576, 1), (0, 1)]}
 
 
+def summarize_legs(trace_dir, fetch_dir, write_dir, out, command):
+    """Kernel time and memory traffic per dispatch of the bench's legs on the 24^3x48 problem (the
+    dispatches between its third and fourth marker kernels) from a kernel trace and two PMC runs."""
+    import collections
+    import csv
+    import glob
+
+    def rows(d, suffix):
+        f = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+        if not f:
+            raise SystemExit(f"no *{suffix} under {d}")
+        r = []
+        for x in f:
+            r += list(csv.DictReader(open(x)))
+        return r
+
+    def window(rs):
+        rs = sorted(rs, key=lambda r: int(r["Start_Timestamp"]))
+        marks = [i for i, r in enumerate(rs) if MARKER in r["Kernel_Name"]]
+        if len(marks) < 4:
+            raise SystemExit(f"{len(marks)} marker dispatches: the legs' pair (third and fourth) is missing")
+        return rs[marks[2] + 1:marks[3]]
+
+    dur = collections.defaultdict(list)
+    for r in window(rows(trace_dir, "kernel_trace.csv")):
+        dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in dur.values())
+    ctr, whole = {}, {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        all_rows = [r for r in rows(d, "counter_collection.csv") if r["Counter_Name"] == cname]
+        per = collections.defaultdict(list)
+        for r in window(all_rows):
+            per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        allk = collections.defaultdict(list)
+        for r in all_rows:
+            allk[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        ctr[cname], whole[cname] = per, allk
+    ff, fw, ncopies = _copy_calibration(whole["FETCH_SIZE"], whole["WRITE_SIZE"])
+    vec_mib = 12 * 24 ** 3 * 48 * 16 / 2 ** 20  # one FP64 vector of the 24^3x48 problem
+    L = ["# rocprofv3 summary: the bench's legs on the 24^3x48 problem", "",
+         "Commands (from the repository root, one MI355X; each writes CSV under its own directory):", ""]
+    for flag in ("--kernel-trace --stats", "--pmc FETCH_SIZE", "--pmc WRITE_SIZE"):
+        L.append(f"    rocprofv3 {flag} --output-format csv -d <dir> -o run -- {command}")
+    L += ["", "Summarised by `python bench.py --summarize-legs <trace dir> <FETCH dir> <WRITE dir> --out <this file>`. "
+          "The window is the dispatches between the bench's third and fourth marker kernels: the direct two-sided "
+          "Lanczos method (stored basis, its accuracy measure, two-pass), the 22-pole solve, the standalone and "
+          "multi-RHS stencil timings, multishift BiCG and QMR, restarted FOM-LR and GMRES-LR (mixed and FP64). "
+          "Times are those of the traced run (tracing adds little per kernel; the bench's own figures are on its "
+          "JSON line).", "",
+          f"Total kernel time {total / 1e3:.0f} ms over {sum(len(v) for v in dur.values())} dispatches.", "",
+          "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:30]:
+        L.append(f"| {_short(k)} | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "
+                 f"{100 * sum(v) / total:.1f} |")
+    L += ["", "## Memory traffic per dispatch (PMC)", "",
+          f"FETCH_SIZE x {ff:.3f} and WRITE_SIZE x {fw:.3f} (the factors from the run's {ncopies} plain 512 MiB "
+          "copies), averaged over each kernel's dispatches in the window; the last two columns give the same in "
+          f"FP64 vectors of this problem ({vec_mib:.1f} MiB each), to compare with the kernel's algorithmic reads "
+          "and writes (an FP32 vector counts one half; the stencil's two-row links count 2, 1 and 0.5 with FP64, FP32 and FP16 links).", "",
+          "| kernel | dispatches | fetched MiB | written MiB | fetched vectors | written vectors |",
+          "|---|---|---|---|---|---|"]
+    rowsl = []
+    for k, fv in ctr["FETCH_SIZE"].items():
+        wv = ctr["WRITE_SIZE"].get(k, [])
+        if not wv:
+            continue
+        fm = sum(fv) / len(fv) * ff / 1024
+        wm = sum(wv) / len(wv) * fw / 1024
+        rowsl.append((len(fv) * (fm + wm), k, len(fv), fm, wm))
+    for _, k, n, fm, wm in sorted(rowsl, reverse=True)[:24]:
+        L.append(f"| {_short(k)} | {n} | {fm:.0f} | {wm:.0f} | {fm / vec_mib:.2f} | {wm / vec_mib:.2f} |")
+    L.append("")
+    open(out, "w").write("\n".join(L))
+    print(f"wrote {out}")
+
+
 def run_stencil_variants(sgn, torch, synth):
     """Fixed launch shapes per precision (STENCIL_VARIANTS), each applied 3 + 20 times between
     two marker kernels (for a kernel trace or counter run of this command). One JSON line."""
@@ -455,6 +531,9 @@ def main():
                     metavar=("TRACE_DIR", "COUNTER_DIR", "FETCH_DIR", "WRITE_DIR", "VARIANTS_JSON"),
                     help="write the stencil-variant counter summary from four rocprofv3 CSV runs of "
                          "'bench.py --stencil-variants' (and the JSON line of a plain run) and exit")
+    ap.add_argument("--summarize-legs", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the summary of the legs on the 24^3x48 problem from three rocprofv3 CSV runs of "
+                         "'bench.py --steps 1 --warmup 1 --no-cpu-baseline' and exit")
     ap.add_argument("--summarize-autotune", metavar="BENCH_JSON",
                     help="write the autotuning summary from a bench JSON line and exit")
     ap.add_argument("--out", default=None, help="output file of the --summarize-* modes")
@@ -463,6 +542,10 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof, args.out or PROFILE, args.profiled_command)
+        return
+    if args.summarize_legs:
+        summarize_legs(*args.summarize_legs, args.out or os.path.join(ROOT, "profiles", "bench_24x24x24x48_all_legs.md"),
+                       "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline")
         return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, args.out or COUNTERS, "python3 bench.py --stencil-variants")
@@ -608,6 +691,9 @@ def main():
     sgn.sgn_profile_enable(ctx, False)
     torch.bitwise_not(marker)
     sync()
+    if not quick:  # two more markers bracket the legs on the 24^3 x 48 problem (--summarize-legs)
+        torch.bitwise_not(marker)
+        sync()
 
     # ---- the exact sign: direct two-sided Lanczos (and the accuracy measure)
     lanczos = None
@@ -752,6 +838,8 @@ def main():
                     "diff_vs_stored_basis": d2}
         log(f"[bench] two-pass direct Lanczos: {t2 * 1e3:.1f} ms/solve, k = {s2['iterations']}, "
             f"vs stored basis {d2:.1e}")
+        torch.bitwise_not(marker)
+        sync()
 
         # ---- restart-size study of restarted FOM-LR on 16^4, FP64 and mixed
         d3 = C3["dims"]
