@@ -518,21 +518,37 @@ __device__ __forceinline__ void stz_nt(float2 *p, int64_t e, z64 v)
 }
 
 // alpha = rho / r^^H v from the dotting stencil's partials; the BiCG factors zeta_next
+// The one-block scalar steps are bound by memory latency: each issues all its loads (the flags,
+// the partials and, in the thread of each shift, that shift's state) before the first use.
+static_assert(kBsShifts <= 256, "one thread per shift in the 256-thread scalar kernels");
+
 __device__ __forceinline__ void bs_alpha_kernel_body(BsState *S, const z64 *part, int nb)
 {
-    if (S->h.done) return;
+    const int done = S->h.done, ns = S->h.ns, i = threadIdx.x;
+    const z64 rho = S->h.rho, ap = S->h.alpha_prev, bp = S->h.beta_prev;
     double re = 0.0, im = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        re += part[i].r;
-        im += part[i].i;
+    for (int b = i; b < nb; b += blockDim.x) {
+        re += part[b].r;
+        im += part[b].i;
     }
+    int act = 0;
+    z64 z = {0.0, 0.0}, zp = {0.0, 0.0};
+    double tau = 0.0;
+    if (i < ns) {
+        act = S->act[i];
+        z = S->zeta[i];
+        zp = S->zeta_prev[i];
+        tau = S->tau[i];
+    }
+    if (done) return;
     __shared__ double lds[8];
     __shared__ int bad;
+    __shared__ z64 al_sh;
     double v[2] = {re, im};
     block_sum<2>(v, lds);
-    if (threadIdx.x == 0) {
+    if (i == 0) {
         const z64 den = {v[0], v[1]};
-        z64 a = bs_div(S->h.rho, den);
+        z64 a = bs_div(rho, den);
         bad = 0;
         if (!(den.r * den.r + den.i * den.i > 0.0) || !bs_finite(a)) {
             S->h.breakdown = 1;
@@ -541,19 +557,17 @@ __device__ __forceinline__ void bs_alpha_kernel_body(BsState *S, const z64 *part
             bad = 1;
         }
         S->h.alpha = a;
+        al_sh = a;
     }
     __syncthreads();
-    if (bad) return;
-    const z64 al = S->h.alpha, ap = S->h.alpha_prev, bp = S->h.beta_prev;
-    for (int i = threadIdx.x; i < S->h.ns; i += blockDim.x) {
-        if (!S->act[i]) {
-            S->zeta_next[i] = S->zeta[i];
-            continue;
-        }
-        const z64 z = S->zeta[i], zp = S->zeta_prev[i];
-        const z64 one_tau = {1.0 + S->tau[i] * al.r, S->tau[i] * al.i};
-        S->zeta_next[i] = bs_div(z * zp * ap, ap * one_tau * zp + al * bp * (zp - z));
+    if (bad || i >= ns) return;
+    if (!act) {
+        S->zeta_next[i] = z;
+        return;
     }
+    const z64 al = al_sh;
+    const z64 one_tau = {1.0 + tau * al.r, tau * al.i};
+    S->zeta_next[i] = bs_div(z * zp * ap, ap * one_tau * zp + al * bp * (zp - z));
 }
 __global__ void __launch_bounds__(256) bs_alpha_kernel(BsState *S, const z64 *part, int nb)
 {
@@ -587,13 +601,14 @@ __global__ void __launch_bounds__(256) bs_sub_stored(const BsState *S, void *con
 // {s^H t, ||t||^2} per block of the stencil that produced t
 __device__ __forceinline__ void bs_omega_kernel_body(BsState *S, const z64 *part, int nb)
 {
-    if (S->h.done) return;
+    const int done = S->h.done;
     double a = 0.0, b = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         a += part[2 * i].r;
         b += part[2 * i].i;
         c += part[2 * i + 1].r;
     }
+    if (done) return;
     __shared__ double lds[12];
     double v[3] = {a, b, c};
     block_sum<3>(v, lds);
@@ -642,22 +657,34 @@ __global__ void __launch_bounds__(256) bs_res_stored(const BsState *S, const typ
 // beta, the history entry, the shifted residual estimates and the control flags
 __device__ __forceinline__ void bs_beta_kernel_body(BsState *S, const z64 *part, int nb, BsHist *hist, int cap)
 {
-    if (S->h.done) {
-        if (threadIdx.x == 0) S->h.go = 0;
-        return;
-    }
+    const int done = S->h.done, ns = S->h.ns, i = threadIdx.x;
+    const z64 om = S->h.omega;
+    const double lim = S->h.tol * S->h.ynorm;
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        a += part[2 * i].r;
-        b += part[2 * i].i;
-        c += part[2 * i + 1].r;
+    for (int bk = i; bk < nb; bk += blockDim.x) {
+        a += part[2 * bk].r;
+        b += part[2 * bk].i;
+        c += part[2 * bk + 1].r;
+    }
+    int act = 0;
+    z64 z = {0.0, 0.0}, zn = {0.0, 0.0}, pi = {0.0, 0.0};
+    double tau = 0.0;
+    if (i < ns) {
+        act = S->act[i];
+        z = S->zeta[i];
+        zn = S->zeta_next[i];
+        pi = S->pi[i];
+        tau = S->tau[i];
+    }
+    if (done) {
+        if (i == 0) S->h.go = 0;
+        return;
     }
     __shared__ double lds[12];
     __shared__ int any, bad;
     __shared__ double rn_sh;
     double v[3] = {a, b, c};
     block_sum<3>(v, lds);
-    const z64 om = S->h.omega;
     if (threadIdx.x == 0) {
         const z64 rho_new = {v[0], v[1]};
         const double rn = sqrt(v[2]);
@@ -690,14 +717,14 @@ __device__ __forceinline__ void bs_beta_kernel_body(BsState *S, const z64 *part,
     }
     __syncthreads();
     if (bad) return;
-    const double lim = S->h.tol * S->h.ynorm, rn = rn_sh;
-    for (int i = threadIdx.x; i < S->h.ns; i += blockDim.x) {
-        if (!S->act[i]) continue;
-        S->zeta_prev[i] = S->zeta[i];
-        S->zeta[i] = S->zeta_next[i];
-        const z64 f = {1.0 + om.r * S->tau[i], om.i * S->tau[i]};
-        S->pi[i] = S->pi[i] * f;
-        const double ri = sqrt(norm2(S->zeta[i]) / norm2(S->pi[i])) * rn;
+    const double rn = rn_sh;
+    if (i < ns && act) {
+        S->zeta_prev[i] = z;
+        S->zeta[i] = zn;
+        const z64 f = {1.0 + om.r * tau, om.i * tau};
+        const z64 pn = pi * f;
+        S->pi[i] = pn;
+        const double ri = sqrt(norm2(zn) / norm2(pn)) * rn;
         if (ri <= lim) {
             S->act[i] = 0;
         } else {
