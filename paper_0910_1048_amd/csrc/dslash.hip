@@ -30,9 +30,6 @@
 #ifndef SGN_T_MINOR
 #define SGN_T_MINOR 1   // t-fastest block order inside each XCD's t-slab when the shape allows
 #endif
-#ifndef SGN_STENCIL_LDS_PAD
-#define SGN_STENCIL_LDS_PAD 0
-#endif
 #ifndef SGN_PIN_PAIR
 #define SGN_PIN_PAIR 0   // 1: both hops of a direction in flight together
 #endif
@@ -41,9 +38,6 @@
 #endif
 #ifndef SGN_STAGED_STRIP
 #define SGN_STAGED_STRIP 1   // staged kernel block order: 0 = z-fastest XCD t-slabs, W > 0 = t-fastest strips of W blocks
-#endif
-#ifndef SGN_ZT_FIRST
-#define SGN_ZT_FIRST 0   // staged stencil: z and t hops (from memory) before the barrier, x and y after
 #endif
 #ifndef SGN_NT_OUT
 #define SGN_NT_OUT 1     // non-temporal stores of the stencil output
