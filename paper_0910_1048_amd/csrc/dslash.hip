@@ -675,8 +675,15 @@ __device__ __forceinline__ void staged_body(const StencilParams &P, const int bx
     }
 }
 
+// Waves per SIMD the compiler must allow the single-RHS staged kernel: with FP16 links 5 (at most 96
+// VGPRs; the epilogue form spills a few bytes and still gains 3% inside the solves); otherwise what
+// the largest block already implies (FP32 and FP64 lost time to spills when pushed further).
+template <typename R, typename LT>
+constexpr int kStagedWaves = std::is_same<LT, __half2>::value ? 5 : (sizeof(R) == 8 ? 2 : 3);
+
 template <typename R, typename LT, bool kEpi, bool kDot>
-__global__ void __launch_bounds__(kStagedMaxThreads<R>) stencil_staged_kernel(StencilParams P)
+__global__ void __launch_bounds__(kStagedMaxThreads<R>) __attribute__((amdgpu_waves_per_eu(kStagedWaves<R, LT>)))
+    stencil_staged_kernel(StencilParams P)
 {
     staged_body<R, LT, kEpi, kDot, false, false>(P, (int)blockIdx.x);
 }
