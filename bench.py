@@ -171,14 +171,27 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
         c = kernel_class(r["Kernel_Name"])
         if c is not None:
             pass_cls[c].append(d)
-    ctr = {}
+    ctr, pass_ctr = {}, {}
     for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = collections.defaultdict(list)
+        rows_c = []
         for f in files(d, "counter_collection.csv"):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] == cname:
                     per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+                    rows_c.append(r)
         ctr[cname] = per
+        # the same profiled pass in the counter run: per class, the values of its dispatches
+        rows_c.sort(key=lambda r: int(r["Start_Timestamp"]))
+        mk = [i for i, r in enumerate(rows_c) if MARKER in r["Kernel_Name"]]
+        if len(mk) < 2:
+            raise SystemExit(f"the {cname} run holds {len(mk)} marker dispatches, not the two around the profiled pass")
+        pc = collections.defaultdict(list)
+        for r in rows_c[mk[0] + 1:mk[1]]:
+            c = kernel_class(r["Kernel_Name"])
+            if c is not None:
+                pc[c].append(float(r["Counter_Value"]))
+        pass_ctr[cname] = pc
     # calibration: the 512 MiB device copies (WRITE_SIZE = 524288 KiB)
     ff, fw, ncopies = _copy_calibration(ctr["FETCH_SIZE"], ctr["WRITE_SIZE"])
     L = [f"# rocprofv3 summary: sign(H_W)b bench, 24^3x48, 16-pole multishift BiCGStab (mixed + FP64 legs)", "",
@@ -213,22 +226,17 @@ def summarize_rocprof(trace_dir, fetch_dir, write_dir, out, command):
     rows.sort(reverse=True)
     for _, k, n, fa, wa in rows[:24]:
         L.append(f"| {_short(k)} | {n} | {fa:.0f} | {wa:.0f} | {(fa * ff + wa * fw) * 1024 / 1e6:.1f} |")
-    # per class: each kernel's mean FETCH and WRITE (the two runs can differ by a few dispatches:
-    # the autotuner's timing may pick another shape), weighted by its dispatches in the FETCH run
-    cls = collections.defaultdict(lambda: [0.0, 0])
-    for k, fv in ctr["FETCH_SIZE"].items():
-        c = kernel_class(k)
-        wv = ctr["WRITE_SIZE"].get(k, [])
-        if c is None or not wv:
+    # per class: the mean FETCH and WRITE of the profiled pass's dispatches (the launches the bench's
+    # roofline times), scaled as above
+    L += ["", "## Per class (the library's profiling classes of the headline solver's kernels, over the dispatches "
+          "of the profiled pass; bench.py reads these lines while the kernel sources still hash to the value below)",
+          "", "```"]
+    for c in sorted(pass_ctr["FETCH_SIZE"]):
+        fv, wv = pass_ctr["FETCH_SIZE"][c], pass_ctr["WRITE_SIZE"].get(c, [])
+        if not wv:
             continue
         per = (sum(fv) / len(fv) * ff + sum(wv) / len(wv) * fw) * 1024
-        cls[c][0] += per * len(fv)
-        cls[c][1] += len(fv)
-    L += ["", "## Per class (the library's profiling classes of the headline solver's kernels; bench.py reads "
-          "these lines while the kernel sources still hash to the value below)", "", "```"]
-    for c in sorted(cls):
-        tot, n = cls[c]
-        L.append(f"traffic {c} {tot / n:.0f} bytes_per_launch over {n} dispatches")
+        L.append(f"traffic {c} {per:.0f} bytes_per_launch over {len(fv)} dispatches of the profiled pass")
     for c in sorted(pass_cls):
         v = pass_cls[c]
         L.append(f"trace_us {c} {sum(v) / len(v):.2f} mean_duration_in_the_profiled_pass over {len(v)} dispatches")

@@ -71,9 +71,9 @@ def test_headline_summary_windows_and_calibration(tmp_path, monkeypatch):
     trace_us = {l.split()[1]: float(l.split()[2]) for l in lines if l.startswith("trace_us ")}
     traffic = {l.split()[1]: float(l.split()[2]) for l in lines if l.startswith("traffic ")}
     assert trace_us == {"stencil_f32": pytest.approx(80.0, abs=0.01)}  # (70 + 90) / 2 inside the window only
-    # per class, over the whole run: each kernel's (FETCH x 2 + WRITE) KiB x 1024 weighted by its
-    # dispatches (6 plain, 4 with the epilogue)
-    want = (6 * (100000.0 * 2 + 60000.0) + 4 * (150000.0 * 2 + 60000.0)) / 10 * 1024
+    # per class, over the profiled pass's dispatches only: (FETCH x 2 + WRITE) KiB x 1024 of the
+    # four plain and four epilogue launches (the two outside the window do not count)
+    want = (4 * (100000.0 * 2 + 60000.0) + 4 * (150000.0 * 2 + 60000.0)) / 8 * 1024
     assert traffic["stencil_f32"] == pytest.approx(want, rel=1e-6)
     assert "source_sha256 feedface" in lines
     # and profile_summary reads both back while the sources hash to the recorded value
