@@ -66,6 +66,8 @@ DEFL = dict(dims=(8, 8, 8, 8), m=4, nev=24, kmax=64, eig_tol=1e-10, max_restarts
 BW_DIMS = (32, 32, 32, 64)
 PROFILE_EVERY = 1   # every launch: the dispatch stamps its own events, so sampling costs no time
 MARKER = "bitwise_not"  # name part of the torch kernel that brackets the profiled pass in a kernel trace
+# the shapes the autotuner picks at 24^3x48, pinned in the profiled runs of the summaries
+PROFILED_SHAPES = "f64:96x1,f32:576x2,h16:384x2"
 # algorithmic bytes per site of one H_W application: two spinors and four links of nine
 # complex entries (FP64 960, FP32 480, FP32 spinors with FP16 links 336); 1368 flop per site
 SITE_BYTES = {"f64": 960, "f32": 480, "h16": 336}
@@ -545,7 +547,12 @@ def main():
     ap.add_argument("--summarize-autotune", metavar="BENCH_JSON",
                     help="write the autotuning summary from a bench JSON line and exit")
     ap.add_argument("--out", default=None, help="output file of the --summarize-* modes")
-    ap.add_argument("--profiled-command", default="python3 bench.py --quick --steps 2 --warmup 1 --no-cpu-baseline",
+    ap.add_argument("--shapes", default=None,
+                    help="after autotuning, pin the single-RHS stencil shapes, e.g. f64:96x1,f32:576x2,h16:384x2 "
+                         "(sites per block over all t-slices x t-slices; 0 = without LDS staging), so that profiled "
+                         "runs launch the same shapes")
+    ap.add_argument("--profiled-command", default="python3 bench.py --quick --steps 2 --warmup 1 --no-cpu-baseline "
+                                                  "--shapes " + PROFILED_SHAPES,
                     help="the command the summarised runs profiled (recorded in the summary)")
     args = ap.parse_args()
     if args.summarize_rocprof:
@@ -626,6 +633,13 @@ def main():
         best = [c for c in cands if c["chosen"]][0]
         log(f"[bench] autotune {name}: {len(cands)} shapes, chosen {best['block_sites']} sites/block"
             f"{' (links in registers)' if best['links_in_registers'] else ''}, {best['us']:.1f} us")
+    if args.shapes:  # the same launch shapes in every profiled run (timing under counters can tip the choice)
+        for item in args.shapes.split(","):
+            name, shp = item.split(":")
+            sites, T = (int(v) for v in shp.split("x"))
+            sgn.sgn_tune_set(lat, {"f64": sgn.F64, "f32": sgn.F32, "h16": sgn.F32_H16}[name], False,
+                             sites if sites > 0 else -1, T)
+        log(f"[bench] stencil shapes pinned: {args.shapes}")
 
     def solve(prec, tol, p=prob, r=rf):
         kw = MIXED if prec != sgn.F64 else {}
@@ -1060,7 +1074,8 @@ def main():
                    "solver": "multishift_bicgstab", "graph_replay": True,
                    "lattice": list(dims), "kappa": W["kappa"], "mu": W["mu"], "link_eps": W["eps"],
                    "poles": W["poles"], "alpha": W["alpha"], "beta": W["beta"], "tol": W["tol"],
-                   "mixed_schedule": MIXED, "deflation_m": 0, "rhs": 1},
+                   "mixed_schedule": MIXED, "deflation_m": 0, "rhs": 1,
+                   "stencil_shapes": args.shapes or "autotuned"},
         "accuracy": {
             "err_vs_g16_reference": err_mixed,
             "err_vs_sign": err_mixed_sign,
