@@ -543,7 +543,7 @@ def main():
                          "'bench.py --stencil-variants' (and the JSON line of a plain run) and exit")
     ap.add_argument("--summarize-legs", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the summary of the legs on the 24^3x48 problem from three rocprofv3 CSV runs of "
-                         "'bench.py --steps 1 --warmup 1 --no-cpu-baseline' and exit")
+                         "'bench.py --steps 1 --warmup 1 --no-cpu-baseline --shapes ...' and exit")
     ap.add_argument("--summarize-autotune", metavar="BENCH_JSON",
                     help="write the autotuning summary from a bench JSON line and exit")
     ap.add_argument("--out", default=None, help="output file of the --summarize-* modes")
@@ -560,7 +560,7 @@ def main():
         return
     if args.summarize_legs:
         summarize_legs(*args.summarize_legs, args.out or os.path.join(ROOT, "profiles", "bench_24x24x24x48_all_legs.md"),
-                       "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline")
+                       "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --shapes " + PROFILED_SHAPES)
         return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, args.out or COUNTERS, "python3 bench.py --stencil-variants")
