@@ -660,7 +660,7 @@ def main():
     xref = om @ xs_ref
     ref_info = {"solver": "multishift_solve FP64, tol 1e-12, per-shift solutions",
                 "oracle_residuals": None, "oracle_residual_max": None}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline:  # part of the CPU leg: the oracle checks the reference, never feeds the GPU path
         from oracle import WilsonRef, rational as orat
         Wr = WilsonRef(U, dims, W["kappa"])
         omo, sgo, co = orat.coefficients(W["poles"], W["alpha"], W["beta"])
