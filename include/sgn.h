@@ -92,6 +92,14 @@ const char *sgn_last_error(void);
  * fix it); otherwise, or with SGN_LINKS_FULL, all nine entries are stored.  The
  * caller may free `links` once the call returns (the call synchronises `stream`). */
 #define SGN_LINKS_FULL 0x100u
+/* SGN_LINKS_TEMPORAL_GAUGE (or-ed into prec_mask; SU(3) links only, else SGN_ERR_INVALID): the
+ * lattice stores the field after the colour rotation G(x) in SU(3) with G(x, t=0) = 1 and
+ * G(x, t+1) = G(x, t) U_t(x, t), so that every time link off the last time slice is the unit matrix
+ * and the stencil skips its load and product.  The operator becomes G H_W G^H and sign(H_W) b =
+ * G^H sign(G H_W G^H) G b; sgn_spinor_pack applies G and sgn_spinor_unpack G^H (in FP64), so every
+ * result in the canonical layout is that of the field as given, up to rounding, and internal-layout
+ * fields hold rotated spinors.  Costs one [V][3][3] complex128 array for G. */
+#define SGN_LINKS_TEMPORAL_GAUGE 0x200u
 sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d, const void *links,
                               unsigned prec_mask, void *stream, sgn_lattice *out);
 sgn_status sgn_lattice_destroy(sgn_lattice lat);

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "sgn.h")
 F64, F32, F32_H16 = 0, 1, 2
 NO_GAMMA5, INTERNAL_LAYOUT = 1, 2
 LINKS_FULL = 0x100
+LINKS_TEMPORAL_GAUGE = 0x200
 
 STATUS = {0: "SGN_OK", 1: "SGN_ERR_INVALID", 2: "SGN_ERR_HIP", 3: "SGN_ERR_NOMEM",
           4: "SGN_ERR_BREAKDOWN", 5: "SGN_ERR_NOT_CONVERGED", 6: "SGN_ERR_IMAG_AXIS",

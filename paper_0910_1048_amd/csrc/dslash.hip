@@ -89,6 +89,7 @@ struct StencilParams {
     int tslices;     // staged kernel: t-slices per block (1, or 2: a brick of the same B sites at t and t + 1)
     int nblk_total;  // blocks of this application (sites + padding); batched launches skip the rest
     int link_ne;     // complex entries stored per link (6 or 9)
+    int tgauge;      // temporal gauge: U_t = 1 off the last time slice (the staged kernel skips those links)
     int nrhs;        // right-hand sides of this application (staged kernel; the unstaged one uses NR)
     RhsParams rhs[kMaxRhs];
 };
@@ -505,10 +506,12 @@ struct SiteLinks {
                 const int L = P.L[nu], st = P.stride[nu];
                 const int nb = c[nu] == 0 ? s + (L - 1) * st : s - st;
                 const LT *b = U + (size_t)nu * 6 * P.S;
+                // temporal gauge: the unit time links are neither loaded nor used
+                const bool fwd = !(nu == 3 && P.tgauge && c[3] != L - 1), bwd = !(nu == 3 && P.tgauge && c[3] != 0);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
-                    e[2 * nu][k] = ld_off(b + (size_t)k * P.S, (uint32_t)s * (uint32_t)sizeof(LT));
-                    e[2 * nu + 1][k] = ld_off(b + (size_t)k * P.S, (uint32_t)nb * (uint32_t)sizeof(LT));
+                    if (fwd) e[2 * nu][k] = ld_off(b + (size_t)k * P.S, (uint32_t)s * (uint32_t)sizeof(LT));
+                    if (bwd) e[2 * nu + 1][k] = ld_off(b + (size_t)k * P.S, (uint32_t)nb * (uint32_t)sizeof(LT));
                 }
             }
         }
@@ -541,10 +544,16 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const int n = wrap ? s - (L - 1) * st : s + st;
         const R bcf = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
-        lk.template get<2 * NU>(P, s, u);
+        const bool unit = NU == 3 && P.tgauge && !wrap;  // temporal gauge: U_t(x) = 1
+        if (!unit) lk.template get<2 * NU>(P, s, u);
         const R s5 = fetch_neighbour<R>(Q, P, lds, base, n, p);
         project<NU, true>(p, h, s5);
-        link_mul<false>(u, h, chi);
+        if (unit) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) chi[k] = h[k];
+        } else {
+            link_mul<false>(u, h, chi);
+        }
         const R w = NU == 3 ? static_cast<R>(Q.wf_t) : R(1);
         accumulate<NU, true>(acc, chi, -kap * w * bcf);
     }
@@ -554,10 +563,16 @@ __device__ __forceinline__ void hop_pair_staged(cpx<R> (&acc)[12], const Stencil
         const int n = wrap ? s + (L - 1) * st : s - st;
         const R bcb = wrap ? static_cast<R>(P.bcf[NU]) : R(1);
         cpx<R> p[12], h[6], chi[6];
-        lk.template get<2 * NU + 1>(P, n, u);
+        const bool unit = NU == 3 && P.tgauge && !wrap;  // temporal gauge: U_t(x - t) = 1
+        if (!unit) lk.template get<2 * NU + 1>(P, n, u);
         const R s5 = fetch_neighbour<R>(Q, P, lds, base, n, p);
         project<NU, false>(p, h, s5);
-        link_mul<true>(u, h, chi);
+        if (unit) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) chi[k] = h[k];
+        } else {
+            link_mul<true>(u, h, chi);
+        }
         const R w = NU == 3 ? static_cast<R>(Q.wb_t) : R(1);
         accumulate<NU, false>(acc, chi, -kap * w * bcb);
     }
@@ -880,6 +895,7 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
     // site once (shared by the right-hand sides) as nine complex entries, plus the
     // epilogue operands; 1368 flop per site and right-hand side for the stencil itself
     P.link_ne = lat.link_ne;
+    P.tgauge = 0;
     const double eb = (p == SGN_PREC_F64) ? 16.0 : (p == SGN_PREC_F32 ? 8.0 : 4.0);
     ps.bytes = (2 * sb * nr + 4 * 9 * eb + extra_bytes) * lat.V;
     ps.bytes_stored = (2 * sb * nr + 4 * lat.link_ne * eb + extra_bytes) * lat.V;
@@ -907,6 +923,10 @@ PreparedStencil prepare_stencil(const Lattice &lat, sgn_prec p, int nr, const Op
         }
     }
     P.nblk_total = ps.nblk;
+    if (lat.gauge && ps.pl.ok) {  // the staged kernel reads the time links of the last slice only
+        P.tgauge = 1;
+        ps.bytes_stored -= (1.0 - 1.0 / lat.L[3]) * lat.link_ne * ((p == SGN_PREC_F64) ? 16.0 : (p == SGN_PREC_F32 ? 8.0 : 4.0)) * lat.V;
+    }
     switch (p) {
     case SGN_PREC_F64: P.links = lat.links64; break;
     case SGN_PREC_F32: P.links = lat.links32; break;

@@ -178,13 +178,151 @@ __global__ void unpack32(const float4 *__restrict__ o, float2 *__restrict__ c, i
     }
 }
 
+// ---------------------------------------------------------------- temporal gauge
+// A site-local colour rotation G(x) in SU(3) maps the field to U'_nu(x) = G(x) U_nu(x) G(x + nu)^H and
+// a spinor to psi'(x) = G(x) psi(x); the operator becomes G D_W G^H (the hops are covariant, gamma5
+// and the weights act on spin only), so sign(H'_W) = G sign(H_W) G^H.  With G(x, 0) = 1 and
+// G(x, t + 1) = G(x, t) U_t(x, t) along each time line every time link off the last slice is the unit
+// matrix, which the stencil then neither loads nor multiplies; the last slice keeps the ordered
+// product of the line's time links.
+
+__device__ inline z64 ldc(const double2 *p) { const double2 v = *p; return {v.x, v.y}; }
+__device__ inline void stc(double2 *p, z64 v) { *p = make_double2(v.r, v.i); }
+
+// G[s][3][3] (row-major, complex128) for every site; one thread walks one time line
+__global__ void tg_gauge_kernel(const double2 *__restrict__ canon, double2 *__restrict__ G, int vs, int lt)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= vs) return;
+    z64 g[9];
+    for (int e = 0; e < 9; ++e) g[e] = {e % 4 == 0 ? 1.0 : 0.0, 0.0};
+    for (int t = 0; t < lt; ++t) {
+        const size_t s = (size_t)t * vs + x;
+        for (int e = 0; e < 9; ++e) stc(G + s * 9 + e, g[e]);
+        if (t + 1 == lt) break;
+        z64 u[9], h[9];
+        for (int e = 0; e < 9; ++e) u[e] = ldc(canon + (s * 4 + 3) * 9 + e);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                z64 acc = {0.0, 0.0};
+                for (int k = 0; k < 3; ++k) acc = acc + g[3 * i + k] * u[3 * k + j];
+                h[3 * i + j] = acc;
+            }
+        for (int e = 0; e < 9; ++e) g[e] = h[e];
+    }
+}
+
+// U'_nu(x) = G(x) U_nu(x) G(x + nu)^H in the canonical layout; time links off the last slice are
+// written as the exact unit matrix
+__global__ void tg_links_kernel(const double2 *__restrict__ canon, const double2 *__restrict__ G,
+                                double2 *__restrict__ out, int V, int L0, int L1, int L2, int L3)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * V) return;
+    const int s = t / 4, nu = t % 4;
+    const int L[4] = {L0, L1, L2, L3}, st[4] = {1, L0, L0 * L1, L0 * L1 * L2};
+    const int c[4] = {s % L0, (s / L0) % L1, (s / (L0 * L1)) % L2, s / (L0 * L1 * L2)};
+    double2 *o = out + (size_t)t * 9;
+    if (nu == 3 && c[3] < L3 - 1) {
+        for (int e = 0; e < 9; ++e) stc(o + e, {e % 4 == 0 ? 1.0 : 0.0, 0.0});
+        return;
+    }
+    const int n = c[nu] == L[nu] - 1 ? s - (L[nu] - 1) * st[nu] : s + st[nu];
+    z64 a[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            z64 acc = {0.0, 0.0};
+            for (int k = 0; k < 3; ++k) acc = acc + ldc(G + (size_t)s * 9 + 3 * i + k) * ldc(canon + (size_t)t * 9 + 3 * k + j);
+            a[3 * i + j] = acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            z64 acc = {0.0, 0.0};
+            for (int k = 0; k < 3; ++k) acc = acc + a[3 * i + k] * conj(ldc(G + (size_t)n * 9 + 3 * j + k));
+            stc(o + 3 * i + j, acc);
+        }
+}
+
+// spinor components (spin 4 x colour 3) rotated in colour: G psi (kAdj false) or G^H psi
+template <bool kAdj>
+__device__ inline void rotate12(const double2 *__restrict__ G, int s, z64 v[12])
+{
+    z64 g[9];
+    for (int e = 0; e < 9; ++e) g[e] = ldc(G + (size_t)s * 9 + e);
+    for (int sp = 0; sp < 4; ++sp) {
+        const z64 a0 = v[3 * sp], a1 = v[3 * sp + 1], a2 = v[3 * sp + 2];
+        for (int i = 0; i < 3; ++i)
+            v[3 * sp + i] = kAdj ? cmulc(g[i], a0) + cmulc(g[3 + i], a1) + cmulc(g[6 + i], a2)
+                                 : g[3 * i] * a0 + g[3 * i + 1] * a1 + g[3 * i + 2] * a2;
+    }
+}
+
+// the internal layouts of a temporal-gauge lattice hold G psi; the rotation is done in FP64
+__global__ void pack64g(const double2 *__restrict__ c, const double2 *__restrict__ G, double2 *__restrict__ o, int V,
+                        int S)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    z64 v[12];
+    for (int k = 0; k < 12; ++k) v[k] = s < V ? ldc(c + (size_t)s * 12 + k) : z64{0.0, 0.0};
+    if (s < V) rotate12<false>(G, s, v);
+    for (int k = 0; k < 12; ++k) stc(o + (size_t)k * S + s, v[k]);
+}
+
+__global__ void unpack64g(const double2 *__restrict__ o, const double2 *__restrict__ G, double2 *__restrict__ c, int V,
+                          int S)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    z64 v[12];
+    for (int k = 0; k < 12; ++k) v[k] = ldc(o + (size_t)k * S + s);
+    rotate12<true>(G, s, v);
+    for (int k = 0; k < 12; ++k) stc(c + (size_t)s * 12 + k, v[k]);
+}
+
+__global__ void pack32g(const float2 *__restrict__ c, const double2 *__restrict__ G, float4 *__restrict__ o, int V,
+                        int S)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    z64 v[12];
+    for (int k = 0; k < 12; ++k) {
+        const float2 a = s < V ? c[(size_t)s * 12 + k] : make_float2(0.f, 0.f);
+        v[k] = {(double)a.x, (double)a.y};
+    }
+    if (s < V) rotate12<false>(G, s, v);
+    for (int k = 0; k < 6; ++k)
+        o[(size_t)k * S + s] = make_float4((float)v[2 * k].r, (float)v[2 * k].i, (float)v[2 * k + 1].r,
+                                           (float)v[2 * k + 1].i);
+}
+
+__global__ void unpack32g(const float4 *__restrict__ o, const double2 *__restrict__ G, float2 *__restrict__ c, int V,
+                          int S)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    z64 v[12];
+    for (int k = 0; k < 6; ++k) {
+        const float4 t = o[(size_t)k * S + s];
+        v[2 * k] = {(double)t.x, (double)t.y};
+        v[2 * k + 1] = {(double)t.z, (double)t.w};
+    }
+    rotate12<true>(G, s, v);
+    for (int k = 0; k < 12; ++k) c[(size_t)s * 12 + k] = make_float2((float)v[k].r, (float)v[k].i);
+}
+
 }  // namespace
 
 void pack_spinor(const Lattice &lat, const void *canon, void *internal, sgn_prec p, hipStream_t s)
 {
     const int V = (int)lat.V, S = (int)lat.S;
     dim3 g((S + 255) / 256), b(256);
-    if (p == SGN_PREC_F64)
+    const double2 *G = static_cast<const double2 *>(lat.gauge);
+    if (p == SGN_PREC_F64 && G)
+        hipLaunchKernelGGL(pack64g, g, b, 0, s, (const double2 *)canon, G, (double2 *)internal, V, S);
+    else if (G)
+        hipLaunchKernelGGL(pack32g, g, b, 0, s, (const float2 *)canon, G, (float4 *)internal, V, S);
+    else if (p == SGN_PREC_F64)
         hipLaunchKernelGGL(pack64, g, b, 0, s, (const double2 *)canon, (double2 *)internal, V, S);
     else
         hipLaunchKernelGGL(pack32, g, b, 0, s, (const float2 *)canon, (float4 *)internal, V, S);
@@ -195,7 +333,12 @@ void unpack_spinor(const Lattice &lat, const void *internal, void *canon, sgn_pr
 {
     const int V = (int)lat.V, S = (int)lat.S;
     dim3 g((V + 255) / 256), b(256);
-    if (p == SGN_PREC_F64)
+    const double2 *G = static_cast<const double2 *>(lat.gauge);
+    if (p == SGN_PREC_F64 && G)
+        hipLaunchKernelGGL(unpack64g, g, b, 0, s, (const double2 *)internal, G, (double2 *)canon, V, S);
+    else if (G)
+        hipLaunchKernelGGL(unpack32g, g, b, 0, s, (const float4 *)internal, G, (float2 *)canon, V, S);
+    else if (p == SGN_PREC_F64)
         hipLaunchKernelGGL(unpack64, g, b, 0, s, (const double2 *)internal, (double2 *)canon, V, S);
     else
         hipLaunchKernelGGL(unpack32, g, b, 0, s, (const float4 *)internal, (float2 *)canon, V, S);
@@ -302,7 +445,9 @@ extern "C" sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d
         dim3 g((nthr + 255) / 256), b(256);
         // two-row storage when every link is SU(3) to 1e-12
         lat->link_ne = 9;
-        if (!(prec_mask & SGN_LINKS_FULL)) {
+        const bool temporal = (prec_mask & SGN_LINKS_TEMPORAL_GAUGE) != 0;
+        bool su3 = false;
+        if (!(prec_mask & SGN_LINKS_FULL) || temporal) {
             std::vector<double> bm(g.x);
             double *dbm = nullptr;
             if (hipMalloc(&dbm, sizeof(double) * g.x) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "su3 check"};
@@ -316,7 +461,25 @@ extern "C" sgn_status sgn_lattice_create(sgn_handle h, const sgn_lattice_desc *d
             SGN_HIP(e3);
             double dev = 0.0;
             for (double v : bm) dev = std::max(dev, v);
-            if (dev <= 1e-12) lat->link_ne = 6;
+            su3 = dev <= 1e-12;
+            if (su3 && !(prec_mask & SGN_LINKS_FULL)) lat->link_ne = 6;
+        }
+        SGN_REQUIRE(su3 || !temporal, "sgn_lattice_create: the temporal gauge needs SU(3) links (to 1e-12)");
+        void *fixed = nullptr;  // the links in the temporal gauge, canonical layout (freed on return)
+        struct FreeOnExit {
+            void *&p;
+            ~FreeOnExit() { if (p) (void)hipFree(p); }
+        } free_fixed{fixed};
+        if (temporal) {
+            const int vs = lat->L[0] * lat->L[1] * lat->L[2];
+            if (hipMalloc(&lat->gauge, (size_t)V * 9 * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "gauge rotation"};
+            if (hipMalloc(&fixed, (size_t)V * 36 * 16) != hipSuccess) throw Failure{SGN_ERR_NOMEM, "gauge-fixed links"};
+            hipLaunchKernelGGL(tg_gauge_kernel, dim3((vs + 63) / 64), dim3(64), 0, s, (const double2 *)links,
+                               (double2 *)lat->gauge, vs, lat->L[3]);
+            hipLaunchKernelGGL(tg_links_kernel, g, b, 0, s, (const double2 *)links, (const double2 *)lat->gauge,
+                               static_cast<double2 *>(fixed), (int)V, lat->L[0], lat->L[1], lat->L[2], lat->L[3]);
+            SGN_HIP(hipGetLastError());
+            links = fixed;
         }
         const size_t nel = (size_t)S * 4 * lat->link_ne;
         const int ne = lat->link_ne;
@@ -352,7 +515,7 @@ extern "C" sgn_status sgn_lattice_destroy(sgn_lattice l)
         if (!l) return;
         Lattice *lat = as_lattice(l);
         SGN_HIP(hipSetDevice(lat->ctx->device));
-        for (void *p : {lat->links64, lat->links32, lat->links16, lat->stage_in, lat->stage_out})
+        for (void *p : {lat->links64, lat->links32, lat->links16, lat->gauge, lat->stage_in, lat->stage_out})
             if (p) SGN_HIP(hipFree(p));
         delete lat;
     });

@@ -177,6 +177,9 @@ struct Lattice {
     void *links64 = nullptr;  // [4][link_ne][S] double2
     void *links32 = nullptr;  // [4][link_ne][S] float2
     void *links16 = nullptr;  // [4][link_ne][S] __half2
+    // temporal gauge (SGN_LINKS_TEMPORAL_GAUGE): the colour rotation G(x), [V][3][3] double2, that the
+    // stored links and every internal field are expressed in; null otherwise
+    void *gauge = nullptr;
     // canonical <-> internal staging for wilson_apply in canonical layout
     void *stage_in = nullptr, *stage_out = nullptr;
     size_t stage_bytes = 0;
