@@ -88,6 +88,15 @@ COUNTER_SET = "VALUBusy OccupancyPercent LDSBankConflict SQ_WAVES SQ_INSTS_VALU 
 KERNEL_SOURCES = os.path.join(ROOT, "paper_0910_1048_amd", "csrc")
 
 
+def stored_site_bytes(prec_name, link_elements, temporal_gauge, lt, staged=True):
+    """Bytes per site one staged application moves in the stored format: two spinors and the links as
+    kept (two rows of SU(3) links), without the unit time links a temporal-gauge lattice skips off its
+    last slice (the unstaged kernel reads them)."""
+    eb, sb = {"f64": (16, 192), "f32": (8, 96), "h16": (4, 96)}[prec_name]
+    links = 4.0 - ((1.0 - 1.0 / lt) if temporal_gauge and staged else 0.0)
+    return 2 * sb + links * link_elements * eb
+
+
 def source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -291,8 +300,10 @@ def summarize_counters(trace_dir, pmc_dir, fetch_dir, write_dir, variants_json, 
             raise SystemExit("the run holds no pair of marker kernels around the stencil variants")
         return rs[marks[0] + 1:marks[-1]]
 
-    variants = json.loads([l for l in open(variants_json).read().splitlines() if l.startswith("{")][-1])
-    variants = variants["stencil_variants"]
+    vline = json.loads([l for l in open(variants_json).read().splitlines() if l.startswith("{")][-1])
+    variants = vline["stencil_variants"]
+    tgauge, ne = bool(vline.get("temporal_gauge", False)), int(vline.get("link_elements", 6))
+    lt = int(vline.get("dims", [24, 24, 24, 48])[3])
 
     def runs(rs):
         """[(kernel name, workgroup size, [dispatch rows])] per consecutive run of stencil dispatches"""
@@ -340,13 +351,15 @@ def summarize_counters(trace_dir, pmc_dir, fetch_dir, write_dir, variants_json, 
           "the one the autotuner picks at this size. Memory bytes: what the L2 caches fetch from and write to memory "
           "(part of it served by the 256 MB Infinity Cache), FETCH_SIZE x "
           f"{ff:.3f} + WRITE_SIZE x {fw:.3f} (KiB x 1024), the factors from the run's {ncopies} plain 512 MiB copies. "
-          "Stored bytes per site: 768 / 384 / 288 (FP64 / FP32 / FP16 links, two-row links); the byte model of the "
-          "roofline counts 960 / 480 / 336.", "",
+          "Stored bytes per site (staged kernels): "
+          + " / ".join(f"{stored_site_bytes(k, ne, tgauge, lt):.0f}" for k in ("f64", "f32", "h16"))
+          + f" (FP64 / FP32 / FP16 links, {'two-row' if ne == 6 else 'nine-entry'} links"
+          + (", a temporal-gauge lattice whose unit time links off the last slice are skipped; the unstaged kernel "
+             "reads them" if tgauge else "") + "); the byte model of the roofline counts 960 / 480 / 336.", "",
           "| precision | sites per block x t-slices | kernel | threads | us | memory MB | MB / stored MB | "
           + " | ".join(names) + " |",
           "|---|---|---|---|---|---|---|" + "---|" * len(names)]
     V = 24 * 24 * 24 * 48
-    stored = {"f64": 768, "f32": 384, "h16": 288}
 
     def mean(v):
         v = v[-20:]
@@ -360,7 +373,8 @@ def summarize_counters(trace_dir, pmc_dir, fetch_dir, write_dir, variants_json, 
         vals = [f"{mean([r['_c'][c] for r in pmc[i][2] if c in r['_c']]):.3g}" for c in names]
         shape = f"{var['block_sites']} x {var['t_slices']}" if var["block_sites"] else "unstaged"
         L.append(f"| {var['prec']} | {shape} | {_short(kname)} | {wg} | {us:.1f} | {mb:.1f} | "
-                 f"{mb / (stored[var['prec']] * V / 1e6):.2f} | " + " | ".join(vals) + " |")
+                 f"{mb / (stored_site_bytes(var['prec'], ne, tgauge, lt, var['block_sites'] > 0) * V / 1e6):.2f} | "
+                 + " | ".join(vals) + " |")
     L += ["", "VALUBusy: percent of the kernel's GPU time the vector ALUs issue; OccupancyPercent: resident waves as a "
           "percent of the maximum; SQ_WAVES: waves launched; SQ_WAIT_INST_ANY: wave-cycles waiting for any "
           "instruction's data (summed over the GPU, in the counter's units).", ""]
@@ -492,7 +506,8 @@ def run_stencil_variants(sgn, torch, synth):
     torch.cuda.synchronize()
     for prec in (sgn.F64, sgn.F32, sgn.F32_H16):
         sgn.sgn_tune_set(lat, prec, False, 0, 1)
-    print(json.dumps({"stencil_variants": res, "dims": list(dims)}), flush=True)
+    print(json.dumps({"stencil_variants": res, "dims": list(dims), "temporal_gauge": lat.temporal_gauge,
+                      "link_elements": lat.link_elements}), flush=True)
 
 
 def summarize_autotune(bench_json, out, command):
@@ -789,11 +804,12 @@ def main():
             sync()
             us = e0.elapsed_time(e1) * 1e3 / reps
             alg = SITE_BYTES[name] * nsites
-            fmt = (2 * sb + 4 * ne * eb) * nsites
+            sbs = stored_site_bytes(name, ne, L_.temporal_gauge, L_.dims[3])
+            fmt = sbs * nsites
             out[name] = {"us": round(us, 2), "GBs": round(alg / us / 1e3, 1),
                          "frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4),
                          "GBs_stored_format": round(fmt / us / 1e3, 1), "bytes_per_site": SITE_BYTES[name],
-                         "stored_bytes_per_site": 2 * sb + 4 * ne * eb,
+                         "stored_bytes_per_site": round(sbs, 1),
                          "TFLOPs": round(FLOP_PER_SITE * nsites / us / 1e6, 2)}
             del xi, yi, canon
         return out
@@ -986,7 +1002,8 @@ def main():
 
         # ---- the stencil on 32^3 x 64 (2.1 M sites, beyond the 256 MB Infinity Cache in every precision)
         Ub = synth.gauge_field(BW_DIMS, W["eps"], W["seed"])
-        latb = sgn.Lattice(ctx, torch.from_numpy(Ub).cuda(), BW_DIMS, W["kappa"])
+        latb = sgn.Lattice(ctx, torch.from_numpy(Ub).cuda(), BW_DIMS, W["kappa"],
+                           prec_mask=sgn.LINKS_TEMPORAL_GAUGE if TEMPORAL_GAUGE else 0)
         del Ub
         dslash["32x32x32x64"] = dslash_rates(latb, 50)
         for k, v in dslash["32x32x32x64"].items():

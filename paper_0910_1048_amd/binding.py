@@ -173,6 +173,7 @@ class Lattice:
         self.kappa = float(kappa)
         self.V = int(lib.sgn_lattice_volume(h))
         self.link_elements = int(lib.sgn_lattice_link_elements(h))
+        self.temporal_gauge = bool(prec_mask & LINKS_TEMPORAL_GAUGE)
 
     def spinor_bytes(self, prec):
         return int(lib.sgn_spinor_bytes(self.h, int(prec)))
