@@ -110,7 +110,10 @@ int sgn_lattice_link_elements(sgn_lattice lat);
 size_t sgn_spinor_bytes(sgn_lattice lat, sgn_prec p);
 
 /* Canonical <-> internal layout.  `canon` is complex128 for SGN_PREC_F64 and
- * complex64 otherwise; `internal` holds sgn_spinor_bytes(lat, p) bytes. */
+ * complex64 otherwise; `internal` holds sgn_spinor_bytes(lat, p) bytes.  On a
+ * temporal-gauge lattice (SGN_LINKS_TEMPORAL_GAUGE) pack stores G(x) psi(x) and unpack
+ * returns G(x)^H of what it reads, each site's colour rotation done in FP64 (a round
+ * trip is then exact only up to rounding). */
 sgn_status sgn_spinor_pack(sgn_lattice lat, const void *canon, void *internal, sgn_prec p, void *stream);
 sgn_status sgn_spinor_unpack(sgn_lattice lat, const void *internal, void *canon, sgn_prec p, void *stream);
 
