@@ -298,3 +298,52 @@ def test_lockstep_batch_mixing_gauges_against_oracle():
         e = _rel(host(outs[k]), ref)
         print(f"  problem {k} (temporal gauge {lat.temporal_gauge}): vs oracle {e:.2e}", flush=True)
         assert e < 1e-9
+
+
+def test_every_solver_on_the_c1_lattice_against_dense_references():
+    """4^4 (eps 0.5, seed 0, kappa 0.2, mu 0.3) stored in the temporal gauge: the direct two-sided
+    Lanczos against the dense sign(H) b, restarted FOM-LR and GMRES-LR and the three multishift
+    solvers against the dense 16-pole g(cH) b, and the critical eigenpairs with the deflated sign
+    against the stored dense eigenvalues, projections and sign (all written by the oracle)."""
+    import os
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g = np.load(os.path.join(gold, "c1_dense.npz"))
+    d = np.load(os.path.join(gold, "c1_deflation.npz"))
+    dims, mu = (4, 4, 4, 4), 0.3
+    lat = _lat(synth.gauge_field(dims, 0.5, 0), dims)
+    b = synth.gaussian_source(dims, 0).ravel()
+    bd = dev(b)
+    x = torch.empty_like(bd)
+    sgn.sign_lanczos_2sided(lat, mu, bd, x, k=320)
+    e = _rel(host(x), g["sign_b"])
+    print(f"C1 temporal gauge: direct Lanczos k=320 vs dense sign {e:.1e}", flush=True)
+    assert e < 1e-8
+    rf = sgn.sgn_rational_neuberger(16, float(g["alpha"]), float(g["beta"]))
+    for fn in (sgn.sign_arnoldi_rational, sgn.sign_gmres_rational):
+        fn(lat, mu, bd, x, rf, kmax=30, tol=1e-11)
+        e = _rel(host(x), g["g16_b"])
+        print(f"  {fn.__name__}: vs dense g16 {e:.1e}", flush=True)
+        assert e < 1e-8
+    for fn in (sgn.multishift_solve, sgn.multishift_bicgstab, sgn.multishift_qmr):
+        fn(sgn.Problem(lat, mu, bd, x), rf, tol=1e-11)
+        e = _rel(host(x), g["g16_b"])
+        print(f"  {fn.__name__}: vs dense g16 {e:.1e}", flush=True)
+        assert e < 1e-8
+    m = 15
+    L = torch.empty((m, 12 * lat.V), dtype=torch.complex128, device="cuda")
+    R = torch.empty_like(L)
+    lam, alpha, _ = sgn.sgn_critical_eigenpairs(lat, mu, m, L, R, tol=1e-12)
+    lam = np.array(lam)
+    Lh, Rh = host(L), host(R)
+    c = Lh.conj() @ b
+    print(f"  eigenpairs: eigenvalue error {np.abs(lam - d['lam']).max():.1e}", flush=True)
+    assert np.abs(lam - d["lam"]).max() < 1e-10
+    assert np.abs(Lh.conj() @ Rh.T - np.eye(m)).max() < 1e-10
+    assert _rel(Rh.T @ c, d["Pb"]) < 1e-9
+    assert _rel(Rh.T @ (np.sign(lam.real) * c), d["xP"]) < 1e-9
+    s = sgn.sgn_poles_needed(alpha, float(g["beta"]), 1e-11)
+    rfd = sgn.sgn_rational_neuberger(s, alpha, float(g["beta"]))
+    sgn.multishift_bicgstab(sgn.Problem(lat, mu, bd, x, sgn.Deflation(L, R, lam)), rfd, tol=1e-11)
+    e = _rel(host(x), g["sign_b"])
+    print(f"  deflated BiCGStab ({s} poles): vs dense sign {e:.1e}", flush=True)
+    assert e < 1e-9
