@@ -51,9 +51,15 @@ ERR_TARGET = 1e-8
 # a reliable update whenever the residual has dropped twentyfold (best mean over eight sources on
 # the temporal-gauge lattice)
 MIXED = dict(theta32=1.0, theta16=1e-6, delta=0.05)
-# the 24^3x48 lattice is stored in the temporal gauge (unit time links off the last slice, which
-# the stencil skips); --plain-gauge keeps the field as generated
+# every lattice of the bench is stored in the temporal gauge (unit time links off the last slice,
+# which the stencil skips); --plain-gauge keeps the fields as generated
 TEMPORAL_GAUGE = True
+
+
+def link_flags():
+    """prec_mask of the bench's lattices"""
+    import paper_0910_1048_amd as sgn
+    return sgn.LINKS_TEMPORAL_GAUGE if TEMPORAL_GAUGE else 0
 BICG_TOL = 1e-8
 BICG_MIXED = dict(theta32=1e-1, theta16=1e-3, delta=0.05)
 QMR_MIXED = dict(theta32=1e-3, theta16=1e-6)
@@ -473,7 +479,7 @@ def run_stencil_variants(sgn, torch, synth):
     U = synth.gauge_field(dims, W["eps"], W["seed"])
     ctx = sgn.Context(0)
     lat = sgn.Lattice(ctx, torch.from_numpy(U).cuda(), dims, W["kappa"],
-                      prec_mask=sgn.LINKS_TEMPORAL_GAUGE if TEMPORAL_GAUGE else 0)
+                      prec_mask=link_flags())
     res = []
     marker = torch.zeros(64, dtype=torch.int32, device="cuda")
     plans = []
@@ -642,7 +648,7 @@ def main():
     b = synth.gaussian_source(dims, W["seed"])
     ctx = sgn.Context(0)
     lat = sgn.Lattice(ctx, torch.from_numpy(U).cuda(), dims, W["kappa"],
-                      prec_mask=sgn.LINKS_TEMPORAL_GAUGE if TEMPORAL_GAUGE else 0)
+                      prec_mask=link_flags())
     V = lat.V
     bd = torch.from_numpy(b.ravel()).cuda()
     x = torch.empty_like(bd)
@@ -897,7 +903,7 @@ def main():
         # ---- restart-size study of restarted FOM-LR on 16^4, FP64 and mixed
         d3 = C3["dims"]
         U3 = synth.gauge_field(d3, W["eps"], W["seed"])
-        lat3 = sgn.Lattice(ctx, torch.from_numpy(U3).cuda(), d3, W["kappa"])
+        lat3 = sgn.Lattice(ctx, torch.from_numpy(U3).cuda(), d3, W["kappa"], prec_mask=link_flags())
         b3 = torch.from_numpy(synth.gaussian_source(d3, W["seed"]).ravel()).cuda()
         x3 = torch.empty_like(b3)
         x3ref = torch.empty_like(b3)
@@ -921,7 +927,8 @@ def main():
 
         # ---- the mixed batch of 32 right-hand sides over 8^4, 12^4, 16^4
         fields, plist = synth.mixed_batch_recipe(C4["nrhs"])
-        lats4 = [sgn.Lattice(ctx, torch.from_numpy(Uf).cuda(), df, W["kappa"]) for df, Uf in fields]
+        lats4 = [sgn.Lattice(ctx, torch.from_numpy(Uf).cuda(), df, W["kappa"], prec_mask=link_flags())
+                 for df, Uf in fields]
         rf4 = sgn.sgn_rational_neuberger(16, C4["alpha"], C4["beta"])
         pb4, refs4 = [], []
         for fi, mu, bj in plist:
@@ -973,7 +980,7 @@ def main():
         # ---- LR deflation on 8^4: critical eigenpairs, then the deflated mixed BiCGStab solve
         d8 = DEFL["dims"]
         U8 = synth.gauge_field(d8, W["eps"], W["seed"])
-        lat8 = sgn.Lattice(ctx, torch.from_numpy(U8).cuda(), d8, W["kappa"])
+        lat8 = sgn.Lattice(ctx, torch.from_numpy(U8).cuda(), d8, W["kappa"], prec_mask=link_flags())
         b8 = torch.from_numpy(synth.gaussian_source(d8, W["seed"]).ravel()).cuda()
         x8, x8ref = torch.empty_like(b8), torch.empty_like(b8)
         sgn.multishift_solve(sgn.Problem(lat8, W["mu"], b8, x8ref), rf, tol=1e-12, prec=sgn.F64)
@@ -1003,7 +1010,7 @@ def main():
         # ---- the stencil on 32^3 x 64 (2.1 M sites, beyond the 256 MB Infinity Cache in every precision)
         Ub = synth.gauge_field(BW_DIMS, W["eps"], W["seed"])
         latb = sgn.Lattice(ctx, torch.from_numpy(Ub).cuda(), BW_DIMS, W["kappa"],
-                           prec_mask=sgn.LINKS_TEMPORAL_GAUGE if TEMPORAL_GAUGE else 0)
+                           prec_mask=link_flags())
         del Ub
         dslash["32x32x32x64"] = dslash_rates(latb, 50)
         for k, v in dslash["32x32x32x64"].items():
