@@ -584,8 +584,10 @@ __device__ __forceinline__ void bs_sub_stored_body(const BsState *S, void *const
     const z64 al = S->h.alpha;
     const T *r = static_cast<const T *>(rslots[S->h.iter]);
     T *slot = static_cast<T *>(sslots[S->h.iter]);
+    // r_k is next read by the lift, v only after two stencils: non-temporal reads keep them from
+    // displacing the links in the Infinity Cache before the stencil that follows
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const z64 sv = ldz(r, e) - al * ldz(v, e);
+        const z64 sv = ldz_nt(r, e) - al * ldz_nt(v, e);
         stz(s, e, sv);
         stz_nt(slot, e, sv);
     }
