@@ -136,3 +136,14 @@ def test_legs_summary_uses_the_second_marker_pair(tmp_path):
     assert "over 10 dispatches" in text  # only the second pair's window
     assert "| lz_update_kernel<false> | 10 | 1.80 | 180.0 | 100.0 |" in text
     assert "| 6.00 | 2.00 |" in text
+
+
+def test_stored_site_bytes_of_the_byte_model():
+    # two spinors and four two-row links per site; a temporal-gauge lattice skips the time link off
+    # its last slice in the staged kernels only
+    assert bench.stored_site_bytes("f64", 6, False, 48) == 2 * 192 + 4 * 6 * 16
+    assert bench.stored_site_bytes("f32", 6, False, 48) == 384
+    assert bench.stored_site_bytes("h16", 6, False, 48) == 288
+    assert bench.stored_site_bytes("f32", 6, True, 48) == pytest.approx(192 + (3 + 1 / 48) * 48)
+    assert bench.stored_site_bytes("f32", 6, True, 48, staged=False) == 384
+    assert bench.stored_site_bytes("f64", 9, True, 24) == pytest.approx(384 + (3 + 1 / 24) * 144)
